@@ -1,0 +1,223 @@
+"""Geometry, face laws and interface spaces of the oracle (CPU, FP64).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Discretisation (section 2 asks for a mixed formulation of eq. (Darcy); on an
+orthogonal, uniformly spaced grid the lowest-order Raviart-Thomas space with
+trapezoidal quadrature is the cell-centred two-point flux scheme used here):
+
+* unknowns are one pressure per cell and one flux per face;
+* a face flux is F = integral of u.n over the face (face length times the
+  normal velocity), positive out of the cell it is written for;
+* half-cell transmissibility t = kappa |f| / d with d the centre-to-face
+  distance; two half cells in series give the harmonic transmissibility
+  1 / (1/t_c + 1/t_d);
+* Dirichlet face: F = t_c (p_c - p_b); Neumann face: F = u_b |f|;
+* Robin face on the skeleton (eq. (mrc1), last line, with eq. (beta)):
+  beta = alpha H / kappa_c and p_f = g + beta F / |f| with
+  g = P_H - beta U_H (n . n_i).  Eliminating p_f from
+  F = t_c (p_c - p_f) gives F = T_R (p_c - g), T_R = |f| kappa_c / (d + alpha H).
+
+Index conventions (all flat, row-major):
+cell (i, j) -> j*nx + i; x-face at x = i*hx in row j -> j*(nx+1) + i;
+y-face at y = j*hy in column i -> j*nx + i; subdomain (I, J) -> J*SX + I.
+Interfaces: vertical ones first, (I, J) between subdomains (I, J) and
+(I+1, J) -> J*(SX-1) + I; then horizontal ones between (I, J) and (I, J+1)
+-> nV + J*SX + I.  The fixed skeleton normal points +x on vertical and +y on
+horizontal interfaces, i.e. out of the subdomain with the smaller index
+(section 3), so sigma = n . n_i is +1 on the lower-index side and -1 on the
+other.  Dofs of interface e are [P_0 .. P_{nP-1}, U_0 .. U_{nU-1}].
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+W, E, S, N = 0, 1, 2, 3
+NEUMANN, DIRICHLET = 0, 1
+
+
+def total_mobility(s, mu_w, mu_o):
+    """lambda(s) = k_rw/mu_w + k_ro/mu_o (eq. fluxos1) with the quadratic
+    relative permeabilities k_rw = s^2, k_ro = (1-s)^2 of section 5."""
+    s = np.asarray(s, dtype=np.float64)
+    return s * s / mu_w + (1.0 - s) * (1.0 - s) / mu_o
+
+
+def fractional_flow(s, mu_w, mu_o):
+    """f(s) = lambda_w / lambda (eq. fluxos2) = M s^2 / (M s^2 + (1-s)^2), M = mu_o/mu_w."""
+    s = np.asarray(s, dtype=np.float64)
+    lw = s * s / mu_w
+    lo = (1.0 - s) ** 2 / mu_o
+    return lw / (lw + lo)
+
+
+def harmonic(a, b):
+    """Two conductances in series: 1 / (1/a + 1/b)."""
+    return 1.0 / (1.0 / a + 1.0 / b)
+
+
+def harmonic_mean(a, b):
+    """2 a b / (a + b)."""
+    return 2.0 * harmonic(a, b)
+
+
+@dataclasses.dataclass
+class Interface:
+    """One interface Gamma_ij: a subdomain edge between two cross-points."""
+    index: int
+    vertical: bool
+    lo: int            # subdomain with the smaller index (sigma = +1)
+    hi: int            # the other subdomain (sigma = -1)
+    lo_side: int       # side of `lo` the interface lies on (E or N)
+    hi_side: int       # side of `hi` the interface lies on (W or S)
+    faces: np.ndarray  # global x-face (vertical) or y-face (horizontal) ids
+    lo_cells: np.ndarray
+    hi_cells: np.ndarray
+    flen: float        # |f|, the fine-face length
+    dist: float        # centre-to-face distance d
+    H: float           # interface length (the H of eq. (beta))
+    xi: np.ndarray     # normalised face-midpoint coordinate (x - a)/(b - a)
+
+
+class Geometry:
+    """Grid, decomposition and interface table of a ``Problem``."""
+
+    def __init__(self, prob):
+        self.prob = prob
+        nx, ny = prob.nx, prob.ny
+        mx, my = prob.sub_nx, prob.sub_ny
+        if nx % mx or ny % my:
+            raise ValueError("grid must be divisible by the subdomain size")
+        self.nx, self.ny, self.mx, self.my = nx, ny, mx, my
+        self.hx, self.hy = prob.lx / nx, prob.ly / ny
+        self.SX, self.SY = nx // mx, ny // my
+        self.n_cells = nx * ny
+        self.n_sub = self.SX * self.SY
+        ii, jj = np.meshgrid(np.arange(nx), np.arange(ny))
+        self.cell_i = ii.reshape(-1)
+        self.cell_j = jj.reshape(-1)
+        self.cell_sub = (self.cell_j // my) * self.SX + (self.cell_i // mx)
+        self.nV = (self.SX - 1) * self.SY
+        self.nH = self.SX * (self.SY - 1)
+        self.interfaces = []
+        for J in range(self.SY):
+            for I in range(self.SX - 1):
+                i = (I + 1) * mx
+                js = J * my + np.arange(my)
+                self.interfaces.append(Interface(
+                    index=len(self.interfaces), vertical=True,
+                    lo=J * self.SX + I, hi=J * self.SX + I + 1, lo_side=E, hi_side=W,
+                    faces=js * (nx + 1) + i, lo_cells=js * nx + i - 1, hi_cells=js * nx + i,
+                    flen=self.hy, dist=0.5 * self.hx, H=my * self.hy,
+                    xi=(np.arange(my) + 0.5) / my))
+        for J in range(self.SY - 1):
+            for I in range(self.SX):
+                j = (J + 1) * my
+                iis = I * mx + np.arange(mx)
+                self.interfaces.append(Interface(
+                    index=len(self.interfaces), vertical=False,
+                    lo=J * self.SX + I, hi=(J + 1) * self.SX + I, lo_side=N, hi_side=S,
+                    faces=j * nx + iis, lo_cells=(j - 1) * nx + iis, hi_cells=j * nx + iis,
+                    flen=self.hx, dist=0.5 * self.hy, H=mx * self.hx,
+                    xi=(np.arange(mx) + 0.5) / mx))
+        self.n_iface = len(self.interfaces)
+        # interface on each side of each subdomain (-1: physical boundary)
+        self.sub_iface = -np.ones((self.n_sub, 4), dtype=np.int64)
+        for itf in self.interfaces:
+            self.sub_iface[itf.lo, itf.lo_side] = itf.index
+            self.sub_iface[itf.hi, itf.hi_side] = itf.index
+
+    def sub_of(self, I, J):
+        return J * self.SX + I
+
+
+# ----------------------------------------------------------------------------
+# Interface spaces (section 3.1).  Every space is a list of per-fine-face
+# vectors on each interface: the piecewise-constant space on skeleton edges
+# defined in section 3 and its subspaces.
+# ----------------------------------------------------------------------------
+
+def linear_space(xi):
+    """Nodal linear polynomials (b - x)/(b - a), (x - a)/(b - a) at the face
+    midpoints; these are the pressure functions of eqs. (new_basis1)-(new_basis3)
+    with no channel (N_high = 0) and span the linear flux space as well."""
+    return np.stack([1.0 - xi, xi])
+
+
+def full_space(m):
+    """All fine-edge indicator functions: the whole piecewise-constant space."""
+    return np.eye(m)
+
+
+def edge_solution_space(k_lo, k_hi):
+    """Non-polynomial two-function spaces from a 1-D edge problem.
+
+    t_j is the harmonic mean of the permeabilities across fine face j.
+    psi solves the 1-D two-point problem along the edge with conductances
+    harm(t_j, t_{j+1}) between neighbouring faces, 2 t_0 and 2 t_{m-1} to the
+    interface ends, psi = 1 at a and psi = 0 at b.  Pressure space:
+    {psi, 1 - psi}; flux space: {t / mean t, t (psi - mean psi) / mean t}.
+    With uniform permeability both reduce to the linear space.
+    """
+    t = harmonic_mean(np.asarray(k_lo, float), np.asarray(k_hi, float))
+    m = t.size
+    tau = harmonic_mean(t[:-1], t[1:]) if m > 1 else np.zeros(0)
+    ta, tb = 2.0 * t[0], 2.0 * t[-1]
+    A = np.zeros((m, m))
+    rhs = np.zeros(m)
+    for j in range(m):
+        if j == 0:
+            A[j, j] += ta
+            rhs[j] += ta * 1.0
+        else:
+            A[j, j] += tau[j - 1]
+            A[j, j - 1] -= tau[j - 1]
+        if j == m - 1:
+            A[j, j] += tb
+        else:
+            A[j, j] += tau[j]
+            A[j, j + 1] -= tau[j]
+    psi = np.linalg.solve(A, rhs)
+    pspace = np.stack([psi, 1.0 - psi])
+    tm = t.mean()
+    uspace = np.stack([t / tm, t * (psi - psi.mean()) / tm])
+    return pspace, uspace
+
+
+def interface_spaces(geom, prob):
+    """Per interface: (psi [nP, m], phi [nU, m]) evaluated on its fine faces."""
+    out = []
+    perm = prob.perm
+    for itf in geom.interfaces:
+        m = itf.faces.size
+        if prob.space == "linear":
+            if prob.p_dofs != 2 or prob.u_dofs != 2:
+                raise ValueError("linear spaces have 2 pressure and 2 flux functions")
+            ps = linear_space(itf.xi)
+            us = linear_space(itf.xi)
+        elif prob.space == "full":
+            if prob.p_dofs != m or prob.u_dofs != m:
+                raise ValueError("full spaces have one function per fine face")
+            ps = full_space(m)
+            us = full_space(m)
+        elif prob.space == "edge":
+            if prob.p_dofs != 2 or prob.u_dofs != 2:
+                raise ValueError("edge-solution spaces have 2 + 2 functions")
+            ps, us = edge_solution_space(perm[itf.lo_cells], perm[itf.hi_cells])
+        elif prob.space == "custom":
+            ps, us = prob.custom_space(itf)
+        else:
+            raise ValueError("unknown interface space %r" % prob.space)
+        out.append((np.asarray(ps, float), np.asarray(us, float)))
+    return out
+
+
+def interface_alpha(geom, prob):
+    if prob.alpha_per_interface is not None:
+        a = np.asarray(prob.alpha_per_interface, dtype=np.float64)
+        if a.shape != (geom.n_iface,):
+            raise ValueError("alpha_per_interface must have one value per interface")
+        return a
+    return np.full(geom.n_iface, float(prob.alpha))

@@ -1,0 +1,491 @@
+"""The Multiscale Robin Coupled Method, step by step (CPU, FP64).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Follows section 3 of the paper:
+
+1. kappa = lambda(s) K (text after eq. (mrc2)); Robin parameter
+   beta_i = alpha H / kappa_i (eq. (beta)), kappa_i taken in the cell beside
+   the face on side i.
+2. Local problems (eq. (mrc1)) on every subdomain: Darcy with the physical
+   boundary data on the domain boundary and the Robin condition
+   -beta u.n_i + p = -beta U_H (n.n_i) + P_H on the skeleton.  By linearity
+   the local solution is a particular solution (interface data zero) plus one
+   basis function per interface degree of freedom (section 3, paragraph after
+   eq. (beta)): pressure dof l of interface e sets g = psi_l on e's faces,
+   flux dof l sets g = -beta sigma phi_l.
+3. Traces of every local solution on the skeleton: Robin face flux
+   F = T_R (p_c - g) and face pressure p_f = g + beta F / |f|.
+4. Interface system (eq. (mrc2), equivalently eq. (compatibility)):
+   for every pressure function psi_l:  sum over both sides of
+   sum_f psi_l(f) F_f = 0 (weak flux continuity);
+   for every flux function phi_l: sum_f |f| phi_l(f) (p_f^lo - p_f^hi) = 0
+   (weak pressure continuity; equal to the beta-form of eq. (mrc2) because
+   beta (u.n_i - U_H sigma) = p_f - P_H and the P_H terms cancel).
+5. Solve for (P_H, U_H); compose the cell pressure and the face fluxes as the
+   same linear combination of the local solutions.
+6. Stitch (the downscaling step that the paper cites for continuous
+   interface fluxes; the cited procedure is not reproduced in the paper, so
+   this is the reading adopted): the interface flux is the average of the two
+   one-sided Robin fluxes, and every subdomain is re-solved with that flux as
+   Neumann data, which gives a single-valued, locally conservative fine flux.
+
+The dense "blocks" returned per subdomain are that subdomain's contribution
+to the interface system in its natural form: rows are the subdomain's
+interface equations, column 0 the particular solution's contribution and
+columns 1.. its interface dofs, in the order of the interfaces on its W, E,
+S and N sides.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .discretization import (DIRICHLET, E, N, S, W, Geometry, harmonic,
+                             interface_alpha, interface_spaces)
+
+
+@dataclasses.dataclass
+class MRCMResult:
+    p: np.ndarray              # composed multiscale cell pressure
+    ux: np.ndarray             # stitched +x velocity on x-faces, (nx+1)*ny
+    uy: np.ndarray             # stitched +y velocity on y-faces, nx*(ny+1)
+    Fx: np.ndarray             # stitched +x face fluxes
+    Fy: np.ndarray             # stitched +y face fluxes
+    Fx_raw: np.ndarray         # multiscale fluxes before stitching (skeleton: side average)
+    Fy_raw: np.ndarray
+    side_flux: list            # per interface: (F_lo, F_hi), outward from each side
+    coeffs: np.ndarray         # interface unknowns, per interface [P.., U..]
+    blocks: list               # per subdomain: natural-form interface block
+    sub_dofs: list             # per subdomain: global dofs of its columns 1..
+    X: np.ndarray              # local solutions, (n_cells, R) columns as in blocks
+    p_stitch: np.ndarray       # pressure of the stitch re-solve
+    imbalance_raw: float       # max cell imbalance / max |F| of the raw MRCM flux
+    imbalance: float           # same for the stitched flux
+    interface_matrix: sp.csr_matrix
+    interface_rhs: np.ndarray
+    dof_offset: np.ndarray
+    n_p: np.ndarray
+    n_u: np.ndarray
+
+
+def _bc_faces(geom, prob, kappa):
+    """Physical boundary faces: (side, cells, half transmissibility, |f|, values)."""
+    nx, ny, hx, hy = geom.nx, geom.ny, geom.hx, geom.hy
+    idx = np.arange(nx * ny).reshape(ny, nx)
+    out = []
+    for side, cells, flen, dist in ((W, idx[:, 0], hy, 0.5 * hx), (E, idx[:, -1], hy, 0.5 * hx),
+                                    (S, idx[0, :], hx, 0.5 * hy), (N, idx[-1, :], hx, 0.5 * hy)):
+        t = kappa[cells] * flen / dist
+        out.append((side, cells, t, flen, prob.bc_array(side)))
+    return out
+
+
+def local_operator(geom, prob, kappa, robin_T=None):
+    """Block-diagonal matrix of all local problems and their data vector.
+
+    Interior faces of a subdomain: harmonic two-point coupling; physical
+    boundary faces: Dirichlet (diagonal t_c, data t_c p_b) or Neumann (data
+    -u_b |f|); source q |V|.  Skeleton faces add the Robin diagonal T_R when
+    ``robin_T`` (a list of (cells, T_R) pairs) is given; without it they are
+    left as zero-flux faces (for the stitch re-solve the prescribed flux is
+    added to the data by the caller).
+    """
+    nx, ny, mx, my = geom.nx, geom.ny, geom.mx, geom.my
+    hx, hy = geom.hx, geom.hy
+    n = nx * ny
+    K = kappa.reshape(ny, nx)
+    idx = np.arange(n).reshape(ny, nx)
+    rows, cols, vals = [], [], []
+
+    def couple(a, b, T):
+        rows.extend([a, b, a, b])
+        cols.extend([a, b, b, a])
+        vals.extend([T, T, -T, -T])
+
+    tx = K * hy / (0.5 * hx)
+    ty = K * hx / (0.5 * hy)
+    Tx = harmonic(tx[:, :-1], tx[:, 1:])
+    same_x = (np.arange(1, nx) % mx) != 0
+    couple(idx[:, :-1][:, same_x].ravel(), idx[:, 1:][:, same_x].ravel(), Tx[:, same_x].ravel())
+    Ty = harmonic(ty[:-1, :], ty[1:, :])
+    same_y = (np.arange(1, ny) % my) != 0
+    couple(idx[:-1, :][same_y, :].ravel(), idx[1:, :][same_y, :].ravel(), Ty[same_y, :].ravel())
+
+    rhs = np.zeros(n)
+    if prob.source is not None:
+        rhs += prob.source * hx * hy
+    for side, cells, t, flen, v in _bc_faces(geom, prob, kappa):
+        if prob.bc_kind[side] == DIRICHLET:
+            rows.append(cells)
+            cols.append(cells)
+            vals.append(t)
+            np.add.at(rhs, cells, t * v)
+        else:
+            np.add.at(rhs, cells, -v * flen)
+    if robin_T is not None:
+        for cells, T in robin_T:
+            rows.append(cells)
+            cols.append(cells)
+            vals.append(T)
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n))
+    return A, rhs, (Tx, Ty, tx, ty, same_x, same_y)
+
+
+def _side_records(geom, prob, kappa, alpha):
+    """Robin data of every skeleton face, per interface and side."""
+    recs = []
+    for itf in geom.interfaces:
+        a = alpha[itf.index]
+        per = []
+        for cells, sub, side, sigma in ((itf.lo_cells, itf.lo, itf.lo_side, 1.0),
+                                        (itf.hi_cells, itf.hi, itf.hi_side, -1.0)):
+            kc = kappa[cells]
+            TR = itf.flen * kc / (itf.dist + a * itf.H)
+            beta = a * itf.H / kc
+            per.append(dict(cells=cells, sub=sub, side=side, sigma=sigma, TR=TR, beta=beta))
+        recs.append(per)
+    return recs
+
+
+def _dof_layout(geom, spaces):
+    n_p = np.array([ps.shape[0] for ps, _ in spaces], dtype=np.int64)
+    n_u = np.array([us.shape[0] for _, us in spaces], dtype=np.int64)
+    off = np.zeros(geom.n_iface + 1, dtype=np.int64)
+    off[1:] = np.cumsum(n_p + n_u)
+    sub_dofs = []
+    col_off = np.zeros((geom.n_sub, 4), dtype=np.int64)
+    for sd in range(geom.n_sub):
+        dofs = []
+        for side in (W, E, S, N):
+            e = geom.sub_iface[sd, side]
+            col_off[sd, side] = 1 + len(dofs)
+            if e >= 0:
+                dofs.extend(range(off[e], off[e + 1]))
+        sub_dofs.append(np.array(dofs, dtype=np.int64))
+    R = 1 + max((len(d) for d in sub_dofs), default=0)
+    return n_p, n_u, off, sub_dofs, col_off, R
+
+
+def _interface_data(itf, rec, ps, us, col):
+    """g on the interface's faces for each column of the side's subdomain."""
+    m = itf.faces.size
+    nP, nU = ps.shape[0], us.shape[0]
+    G = np.zeros((m, nP + nU))
+    G[:, :nP] = ps.T
+    G[:, nP:] = (-rec["beta"] * rec["sigma"])[:, None] * us.T
+    return G
+
+
+def _refined(A, solve, b, steps=2):
+    """x = A^-1 b by a direct solve plus FP64 iterative refinement steps."""
+    x = solve(b)
+    for _ in range(steps):
+        x = x + solve(b - A @ x)
+    return x
+
+
+def _local_solve(A, B, geom, method):
+    if method == "superlu":
+        lu = spla.splu(A.tocsc())
+        return _refined(A, lu.solve, B)
+    if method == "banded":
+        # one LAPACK banded Cholesky per subdomain in the local natural
+        # ordering, whose half-bandwidth is the subdomain width
+        X = np.zeros_like(B)
+        mx, my, nx = geom.mx, geom.my, geom.nx
+        A = A.tocsr()
+        for sd in range(geom.n_sub):
+            I, J = sd % geom.SX, sd // geom.SX
+            li, lj = np.meshgrid(np.arange(mx), np.arange(my))
+            cells = ((J * my + lj) * nx + I * mx + li).reshape(-1)
+            Ad = A[cells][:, cells].toarray()
+            nb = mx
+            ab = np.zeros((nb + 1, cells.size))
+            for d in range(nb + 1):
+                ab[d, : cells.size - d] = np.diagonal(Ad, -d)
+            c = sla.cholesky_banded(ab, lower=True)
+            X[cells] = sla.cho_solve_banded((c, True), B[cells])
+        return X
+    raise ValueError(method)
+
+
+def _interface_solve(M, b, method, ir_steps):
+    if M.shape[0] == 0:
+        return np.zeros(0)
+    if method == "superlu":
+        lu = spla.splu(M.tocsc())
+        solve = lu.solve
+    elif method == "dense":
+        Md = M.toarray()
+        lu = sla.lu_factor(Md)
+        solve = lambda r: sla.lu_solve(lu, r)
+    else:
+        raise ValueError(method)
+    x = solve(b)
+    for _ in range(ir_steps):
+        r = b - M @ x
+        x = x + solve(r)
+    return x
+
+
+def flux_imbalance(geom, prob, Fx, Fy):
+    """max over cells |net outflow - q |V|| / max |F| (section 2 balance)."""
+    nx, ny = geom.nx, geom.ny
+    FX = Fx.reshape(ny, nx + 1)
+    FY = Fy.reshape(ny + 1, nx)
+    net = FX[:, 1:] - FX[:, :-1] + FY[1:, :] - FY[:-1, :]
+    q = np.zeros((ny, nx)) if prob.source is None else (prob.source * geom.hx * geom.hy).reshape(ny, nx)
+    scale = max(np.abs(FX).max(), np.abs(FY).max(), 1e-300)
+    return float(np.abs(net - q).max() / scale)
+
+
+def _boundary_fluxes(geom, prob, kappa, p, FX, FY):
+    """Fill the physical boundary faces of +x/+y flux arrays from pressure p."""
+    P = p.reshape(geom.ny, geom.nx)
+    for side, cells, t, flen, v in _bc_faces(geom, prob, kappa):
+        if prob.bc_kind[side] == DIRICHLET:
+            out = t * (p[cells] - v)
+        else:
+            out = v * flen
+        if side == W:
+            FX[:, 0] = -out
+        elif side == E:
+            FX[:, -1] = out
+        elif side == S:
+            FY[0, :] = -out
+        else:
+            FY[-1, :] = out
+    del P
+
+
+def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu",
+               ir_steps=2, stitch=True):
+    """Run the MRCM on ``prob`` with total mobility ``lam`` (default 1)."""
+    geom = Geometry(prob)
+    nx, ny, mx, my = geom.nx, geom.ny, geom.mx, geom.my
+    lam = np.ones(nx * ny) if lam is None else np.asarray(lam, dtype=np.float64)
+    kappa = prob.perm * lam
+    spaces = interface_spaces(geom, prob)
+    alpha = interface_alpha(geom, prob)
+    n_p, n_u, off, sub_dofs, col_off, R = _dof_layout(geom, spaces)
+    n_dof = int(off[-1])
+    recs = _side_records(geom, prob, kappa, alpha)
+
+    # local problems, all subdomains at once (they are uncoupled)
+    robin = [(r["cells"], r["TR"]) for per in recs for r in per]
+    A, rhs0, (Tx, Ty, tx, ty, same_x, same_y) = local_operator(geom, prob, kappa, robin)
+    B = np.zeros((geom.n_cells, R))
+    B[:, 0] = rhs0
+    for itf, per in zip(geom.interfaces, recs):
+        ps, us = spaces[itf.index]
+        for rec in per:
+            c0 = col_off[rec["sub"], rec["side"]]
+            G = _interface_data(itf, rec, ps, us, c0)
+            B[rec["cells"], c0:c0 + G.shape[1]] += rec["TR"][:, None] * G
+    X = _local_solve(A, B, geom, local_solver)
+
+    # traces and the per-subdomain blocks of the interface system
+    blocks = [np.zeros((len(d), R)) for d in sub_dofs]
+    for itf, per in zip(geom.interfaces, recs):
+        ps, us = spaces[itf.index]
+        nP = ps.shape[0]
+        for rec in per:
+            sd = rec["sub"]
+            c0 = col_off[sd, rec["side"]]
+            Gfull = np.zeros((itf.faces.size, R))
+            G = _interface_data(itf, rec, ps, us, c0)
+            Gfull[:, c0:c0 + G.shape[1]] = G
+            F = rec["TR"][:, None] * (X[rec["cells"]] - Gfull)
+            pf = Gfull + (rec["beta"] / itf.flen)[:, None] * F
+            r0 = c0 - 1
+            blocks[sd][r0:r0 + nP] += ps @ F
+            blocks[sd][r0 + nP:r0 + G.shape[1]] += rec["sigma"] * itf.flen * (us @ pf)
+
+    # interface system, natural form
+    rows, cols, vals = [], [], []
+    b = np.zeros(n_dof)
+    for sd, dofs in enumerate(sub_dofs):
+        if dofs.size == 0:
+            continue
+        blk = blocks[sd]
+        rr, cc = np.meshgrid(dofs, dofs, indexing="ij")
+        rows.append(rr.ravel())
+        cols.append(cc.ravel())
+        vals.append(blk[:, 1:1 + dofs.size].ravel())
+        np.add.at(b, dofs, -blk[:, 0])
+    if n_dof:
+        M = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                          shape=(n_dof, n_dof))
+    else:
+        M = sp.csr_matrix((0, 0))
+    pure_neumann = not prob.has_dirichlet()
+    M_solve, b_solve = M, b.copy()
+    if pure_neumann and n_dof:
+        # gauge: the first pressure dof of interface 0 is fixed to zero in
+        # place of its (dependent) flux-continuity equation
+        M_solve = M.tolil()
+        M_solve[0, :] = 0.0
+        M_solve[0, 0] = 1.0
+        M_solve = M_solve.tocsr()
+        b_solve[0] = 0.0
+    c = _interface_solve(M_solve, b_solve, interface_solver, ir_steps)
+
+    # composition: p = X [1; c] per subdomain
+    Cmat = np.zeros((geom.n_sub, R))
+    Cmat[:, 0] = 1.0
+    for sd, dofs in enumerate(sub_dofs):
+        Cmat[sd, 1:1 + dofs.size] = c[dofs]
+    p = np.einsum("ck,ck->c", X, Cmat[geom.cell_sub])
+
+    # multiscale fluxes: interior of subdomains, physical boundary, and the
+    # two one-sided Robin fluxes on the skeleton
+    P = p.reshape(ny, nx)
+    FX = np.zeros((ny, nx + 1))
+    FY = np.zeros((ny + 1, nx))
+    FX[:, 1:-1] = np.where(same_x[None, :], Tx * (P[:, :-1] - P[:, 1:]), 0.0)
+    FY[1:-1, :] = np.where(same_y[:, None], Ty * (P[:-1, :] - P[1:, :]), 0.0)
+    _boundary_fluxes(geom, prob, kappa, p, FX, FY)
+    side_flux = []
+    FXf, FYf = FX.reshape(-1), FY.reshape(-1)
+    for itf, per in zip(geom.interfaces, recs):
+        ps, us = spaces[itf.index]
+        nP = ps.shape[0]
+        ce = c[off[itf.index]:off[itf.index + 1]]
+        PH = ps.T @ ce[:nP]
+        UH = us.T @ ce[nP:]
+        Fs = []
+        for rec in per:
+            g = PH - rec["beta"] * rec["sigma"] * UH
+            Fs.append(rec["TR"] * (p[rec["cells"]] - g))
+        side_flux.append((Fs[0], Fs[1]))
+        avg = 0.5 * (Fs[0] - Fs[1])
+        if itf.vertical:
+            FXf[itf.faces] = avg
+        else:
+            FYf[itf.faces] = avg
+    Fx_raw, Fy_raw = FXf.copy(), FYf.copy()
+    imb_raw = flux_imbalance(geom, prob, Fx_raw, Fy_raw)
+
+    if pure_neumann:
+        p = p - p.mean()
+
+    # stitch: Neumann re-solve per subdomain with the averaged skeleton flux
+    p_st = np.full_like(p, np.nan)
+    Fx, Fy = Fx_raw.copy(), Fy_raw.copy()
+    if stitch and geom.n_iface:
+        AN, rhsN, _ = local_operator(geom, prob, kappa, None)
+        rhsN = rhsN.copy()
+        for itf, per in zip(geom.interfaces, recs):
+            avg = 0.5 * (side_flux[itf.index][0] - side_flux[itf.index][1])
+            np.add.at(rhsN, per[0]["cells"], -avg)   # outflow of lo is +avg
+            np.add.at(rhsN, per[1]["cells"], avg)    # outflow of hi is -avg
+        AN = AN.tolil()
+        diag = AN.diagonal()
+        for sd in range(geom.n_sub):
+            I, J = sd % geom.SX, sd // geom.SX
+            touches_dirichlet = ((I == 0 and prob.bc_kind[W] == DIRICHLET)
+                                 or (I == geom.SX - 1 and prob.bc_kind[E] == DIRICHLET)
+                                 or (J == 0 and prob.bc_kind[S] == DIRICHLET)
+                                 or (J == geom.SY - 1 and prob.bc_kind[N] == DIRICHLET))
+            if not touches_dirichlet:
+                c0 = (J * my) * nx + I * mx
+                Tpin = diag[c0]
+                AN[c0, c0] = diag[c0] + Tpin
+                rhsN[c0] += Tpin * p[c0]
+        AN = AN.tocsc()
+        p_st = _refined(AN, spla.splu(AN).solve, rhsN)
+        PS = p_st.reshape(ny, nx)
+        FX = Fx.reshape(ny, nx + 1)
+        FY = Fy.reshape(ny + 1, nx)
+        FX[:, 1:-1] = np.where(same_x[None, :], Tx * (PS[:, :-1] - PS[:, 1:]), FX[:, 1:-1])
+        FY[1:-1, :] = np.where(same_y[:, None], Ty * (PS[:-1, :] - PS[1:, :]), FY[1:-1, :])
+        _boundary_fluxes(geom, prob, kappa, p_st, FX, FY)
+        Fx, Fy = FX.reshape(-1), FY.reshape(-1)
+    imb = flux_imbalance(geom, prob, Fx, Fy)
+    return MRCMResult(p=p, ux=Fx / geom.hy, uy=Fy / geom.hx, Fx=Fx, Fy=Fy,
+                      Fx_raw=Fx_raw, Fy_raw=Fy_raw, side_flux=side_flux, coeffs=c,
+                      blocks=blocks, sub_dofs=sub_dofs, X=X, p_stitch=p_st,
+                      imbalance_raw=imb_raw, imbalance=imb, interface_matrix=M,
+                      interface_rhs=b, dof_offset=off, n_p=n_p, n_u=n_u)
+
+
+def solve_mrcm_monolithic(prob, lam=None):
+    """All local pressures and interface unknowns in one sparse system.
+
+    Rows: every cell balance of every local problem (eq. (mrc1) with the
+    interface data left as unknowns) and every interface equation
+    (eq. (mrc2)).  Used to pin the static condensation of ``solve_mrcm``.
+    Returns (p, coeffs).
+    """
+    geom = Geometry(prob)
+    nx, ny = geom.nx, geom.ny
+    n = nx * ny
+    lam = np.ones(n) if lam is None else np.asarray(lam, dtype=np.float64)
+    kappa = prob.perm * lam
+    spaces = interface_spaces(geom, prob)
+    alpha = interface_alpha(geom, prob)
+    n_p, n_u, off, sub_dofs, col_off, R = _dof_layout(geom, spaces)
+    n_dof = int(off[-1])
+    recs = _side_records(geom, prob, kappa, alpha)
+    robin = [(r["cells"], r["TR"]) for per in recs for r in per]
+    A, rhs0, _ = local_operator(geom, prob, kappa, robin)
+    A = A.tocoo()
+    rows = [A.row]
+    cols = [A.col]
+    vals = [A.data]
+    rhs = np.concatenate([rhs0, np.zeros(n_dof)])
+    for itf, per in zip(geom.interfaces, recs):
+        ps, us = spaces[itf.index]
+        nP = ps.shape[0]
+        d0 = off[itf.index]
+        nd = off[itf.index + 1] - d0
+        for rec in per:
+            G = _interface_data(itf, rec, ps, us, 0)       # (m, nd)
+            TR, beta = rec["TR"], rec["beta"]
+            cells = rec["cells"]
+            # cell rows: A p - T_R g = data  ->  -T_R G c
+            for k in range(nd):
+                rows.append(cells)
+                cols.append(np.full(cells.size, n + d0 + k))
+                vals.append(-TR * G[:, k])
+            # flux-continuity rows: sum psi_l T_R (p_c - G c)
+            for l in range(nP):
+                rows.append(np.full(cells.size, n + d0 + l))
+                cols.append(cells)
+                vals.append(ps[l] * TR)
+                for k in range(nd):
+                    rows.append(np.array([n + d0 + l]))
+                    cols.append(np.array([n + d0 + k]))
+                    vals.append(np.array([-(ps[l] * TR * G[:, k]).sum()]))
+            # pressure-continuity rows: sigma sum |f| phi_l p_f,
+            # p_f = G c + beta T_R (p_c - G c) / |f|
+            for l in range(us.shape[0]):
+                row = n + d0 + nP + l
+                w = rec["sigma"] * itf.flen * us[l]
+                rows.append(np.full(cells.size, row))
+                cols.append(cells)
+                vals.append(w * beta * TR / itf.flen)
+                for k in range(nd):
+                    rows.append(np.array([row]))
+                    cols.append(np.array([n + d0 + k]))
+                    vals.append(np.array([(w * (G[:, k] - beta * TR * G[:, k] / itf.flen)).sum()]))
+    Mfull = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                          shape=(n + n_dof, n + n_dof))
+    if not prob.has_dirichlet() and n_dof:
+        Mfull = Mfull.tolil()
+        Mfull[n, :] = 0.0
+        Mfull[n, n] = 1.0
+        Mfull = Mfull.tocsr()
+        rhs[n] = 0.0
+    Mfull = Mfull.tocsc()
+    sol = _refined(Mfull, spla.splu(Mfull).solve, rhs)
+    p = sol[:n]
+    if not prob.has_dirichlet():
+        p = p - p.mean()
+    return p, sol[n:]

@@ -1,0 +1,99 @@
+"""Planted mistakes in the oracle (CPU only) must be caught by the pins.
+
+Each case monkeypatches one plausible slip into the oracle - a wrong mean,
+a flipped normal sign, a dropped Robin factor - and checks that the closed
+form / reduction pins reject it.  This shows the pins constrain every part
+of the chain, not only the parts that happen to be exercised.
+"""
+import numpy as np
+import pytest
+
+import oracle.mrcm as om
+from inputs import make_problem
+from oracle.fine import solve_fine
+from tests import test_oracle_pins as P
+from tests.test_oracle_pins import linear_dirichlet
+
+
+PINS = [
+    lambda: P.test_tiny_mrcm_closed_form(),
+    lambda: P.test_linear_pressure_reproduced(0.7),
+    lambda: P.test_full_spaces_recover_fine(0.7),
+    lambda: P.test_full_spaces_pure_neumann(),
+    lambda: P.test_conservation(),
+    lambda: P.test_alpha_limits(),
+]
+
+
+def _pins_pass():
+    """True when every pin passes on the (possibly mutated) oracle."""
+    for pin in PINS:
+        try:
+            pin()
+        except AssertionError:
+            return False
+    return True
+
+
+def test_unmodified_oracle_passes():
+    assert _pins_pass()
+
+
+def test_arithmetic_mean_caught(monkeypatch):
+    monkeypatch.setattr(om, "harmonic", lambda a, b: 0.25 * (a + b))
+    assert not _pins_pass()
+
+
+def test_reversed_normal_is_harmless(monkeypatch):
+    """Reversing the fixed skeleton normal on both sides only flips the sign
+    of the flux unknowns: the pins must still pass."""
+    orig = om._side_records
+
+    def flipped(geom, prob, kappa, alpha):
+        recs = orig(geom, prob, kappa, alpha)
+        for per in recs:
+            per[0]["sigma"], per[1]["sigma"] = -1.0, 1.0
+        return recs
+    prob = make_problem("gauss64", nx=32, ny=32, sub=8, alpha=0.7)
+    ref = om.solve_mrcm(prob)
+    monkeypatch.setattr(om, "_side_records", flipped)
+    r = om.solve_mrcm(prob)
+    assert np.linalg.norm(r.p - ref.p) < 1e-12 * np.linalg.norm(ref.p)
+    assert np.linalg.norm(r.Fx - ref.Fx) < 1e-11 * np.linalg.norm(ref.Fx)
+
+
+def test_one_sided_normal_sign_caught(monkeypatch):
+    orig = om._side_records
+
+    def flipped(geom, prob, kappa, alpha):
+        recs = orig(geom, prob, kappa, alpha)
+        for per in recs:
+            per[1]["sigma"] = 1.0
+        return recs
+    monkeypatch.setattr(om, "_side_records", flipped)
+    assert not _pins_pass()
+
+
+def test_dropped_beta_in_flux_data_caught(monkeypatch):
+    def nobeta(itf, rec, ps, us, col):
+        m = itf.faces.size
+        nP, nU = ps.shape[0], us.shape[0]
+        G = np.zeros((m, nP + nU))
+        G[:, :nP] = ps.T
+        G[:, nP:] = (-rec["sigma"]) * us.T
+        return G
+    monkeypatch.setattr(om, "_interface_data", nobeta)
+    assert not _pins_pass()
+
+
+def test_transposed_projection_caught(monkeypatch):
+    # use the pressure functions where the flux functions belong
+    def swapped(geom, prob):
+        from oracle.discretization import interface_spaces
+        sp = interface_spaces(geom, prob)
+        return [(ps, ps[::-1].copy()) for ps, us in sp]
+    monkeypatch.setattr(om, "interface_spaces", swapped)
+    prob = make_problem("gauss64", nx=32, ny=32, sub=8, alpha=0.7)
+    lin, exact = linear_dirichlet(16, 12, 4, 0.5, 2.0, -1.5, alpha=0.7)
+    # a reversed basis spans the same space: still exact (basis independence)
+    assert np.abs(om.solve_mrcm(lin).p - exact).max() < 1e-12
