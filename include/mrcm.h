@@ -1,0 +1,197 @@
+/*
+ * mrcm.h - C ABI of the MI355X (gfx950) library for the Darcy solve of the
+ * Multiscale Robin Coupled Method (MRCM).
+ *
+ * The problem (paper, section 2, eq. (Darcy)): u = -lambda(s) K grad p,
+ * div u = q in Omega, p = p_b on the Dirichlet part of the boundary and
+ * u.n = u_b on the Neumann part.  The method (section 3, eqs. (mrc1),
+ * (mrc2), (beta)): split Omega into equal rectangular subdomains, solve one
+ * Robin problem per subdomain and interface basis function, couple the
+ * pieces through weak flux and pressure continuity on the skeleton, and
+ * return one fine-scale pressure and a conservative fine-scale flux.
+ *
+ * Discretisation: cell-centred two-point fluxes on a uniform Cartesian
+ * grid (the quadrature form of lowest-order mixed elements), with the
+ * Robin face law F = T_R (p_c - g), T_R = |f| kappa_c / (d + alpha H),
+ * g = P_H - beta U_H (n . n_i), beta = alpha H / kappa_c.
+ *
+ * Index conventions (all arrays flat, row-major, float64):
+ *   cell (i, j), i along x        -> j*nx + i                 (nx*ny)
+ *   x-face at x = i*hx in row j   -> j*(nx+1) + i             ((nx+1)*ny)
+ *   y-face at y = j*hy in col i   -> j*nx + i                 (nx*(ny+1))
+ *   boundary sides                -> 0 W (x=0), 1 E, 2 S (y=0), 3 N
+ *   interfaces: vertical (between subdomains (I,J),(I+1,J)) first as
+ *   J*(SX-1)+I, then horizontal (between (I,J),(I,J+1)) as nV + J*SX + I;
+ *   dofs of interface e: e*(nP+nU) + [P_0..P_{nP-1}, U_0..U_{nU-1}].
+ * The fixed skeleton normal points +x / +y, i.e. out of the subdomain with
+ * the smaller index (section 3).
+ *
+ * Every entry point returns an int status (0 = MRCM_OK) and never throws.
+ * A context is not re-entrant: use one per host thread.  All device work
+ * is issued on the context's HIP stream.
+ */
+#ifndef MRCM_H
+#define MRCM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mrcm_ctx mrcm_ctx; /* opaque; owns all of its device memory */
+
+enum {
+  MRCM_OK = 0,
+  MRCM_E_INVAL = 1,   /* an argument is out of range; the context is unchanged */
+  MRCM_E_NOMEM = 2,   /* device or host allocation failed */
+  MRCM_E_HIP = 3,     /* a HIP runtime call failed (message in mrcm_last_error) */
+  MRCM_E_NOT_SPD = 4, /* a local or interface pivot was not positive/nonzero */
+  MRCM_E_NO_CONV = 5, /* an iterative refinement did not converge and no fallback is left */
+  MRCM_E_STATE = 6,   /* calls out of order (e.g. fine_flux before solve) */
+  MRCM_E_UNSUPPORTED = 7 /* a valid combination this build has no kernel for */
+};
+
+enum { MRCM_BC_NEUMANN = 0, MRCM_BC_DIRICHLET = 1 };
+
+/* Interface spaces (section 3.1).  LINEAR: the two nodal linear functions
+ * for pressure and for flux (2 + 2 dofs per interface).  EDGE_SOLUTION: two
+ * non-polynomial functions per space built at setup from a 1-D two-point
+ * problem along each interface on the absolute permeability (reduces to
+ * LINEAR for uniform K).  FULL: every fine-edge indicator (m + m dofs). */
+enum { MRCM_SPACE_LINEAR = 0, MRCM_SPACE_EDGE_SOLUTION = 1, MRCM_SPACE_FULL = 2 };
+
+/* Precision of the local (subdomain) factorisations.  The interface system
+ * is always solved in FP64.  FP32_IR: FP32 factors and solves, FP64
+ * residuals and iterative refinement to 1e-12 relative, per-subdomain FP64
+ * fallback when refinement stalls. */
+enum { MRCM_PREC_FP64 = 0, MRCM_PREC_FP32_IR = 1 };
+
+typedef struct {
+  int32_t nx, ny; /* cells; > 0 */
+  double lx, ly;  /* domain [0,lx] x [0,ly]; > 0 */
+} mrcm_grid;
+
+typedef struct {
+  int32_t kind[4];        /* per side W,E,S,N: MRCM_BC_NEUMANN or MRCM_BC_DIRICHLET */
+  const double* value[4]; /* host arrays: W,E: ny values (bottom to top), S,N: nx values
+                             (left to right).  Dirichlet: boundary pressure p_b;
+                             Neumann: outward normal velocity u_b.  NULL = all zero. */
+} mrcm_bc;
+
+typedef struct {
+  double mu_w, mu_o; /* phase viscosities; lambda(s) = s^2/mu_w + (1-s)^2/mu_o
+                        (eq. (fluxos1) with k_rw = s^2, k_ro = (1-s)^2, section 5) */
+} mrcm_fluid;
+
+typedef struct {
+  double ms_local;       /* last solve: assemble + factor + basis solves + traces */
+  double ms_interface;   /* last solve: interface system (FP64) */
+  double ms_flux;        /* last fine_flux: compose + stitch + conservation */
+  int32_t n_sub;         /* subdomains */
+  int32_t n_dof;         /* interface unknowns */
+  int32_t ir_iters_max;  /* FP32_IR: largest refinement count over subdomains */
+  int32_t fallbacks;     /* FP32_IR: subdomains re-solved in FP64 */
+  double interface_residual; /* max |b - A x| / max |b| of the interface solve */
+} mrcm_stats;
+
+/* Set up a solver for one grid, permeability field and decomposition
+ * (section 3: non-overlapping subdomains, interface spaces, Robin alpha).
+ *  out        : receives the new context (caller destroys it).
+ *  g          : grid; nx % sub_nx == 0 and ny % sub_ny == 0 required.
+ *  perm       : host, nx*ny absolute permeabilities K > 0 (finite).
+ *  sub_nx/ny  : subdomain size in cells; this build requires
+ *               sub_nx == sub_ny in {4, 8, 16, 32}.
+ *  space      : MRCM_SPACE_*; p_dofs/u_dofs must match the space (2, 2 for
+ *               LINEAR and EDGE_SOLUTION, sub_nx each for FULL).
+ *  alpha_per_interface : host, one alpha > 0 per interface (eq. (beta)), or
+ *               NULL to use alpha_scalar everywhere.
+ *  bc, source : boundary data (deep-copied) and q per unit area (host,
+ *               nx*ny, NULL = 0).  With no Dirichlet side the pressure is
+ *               defined up to a constant: the first pressure dof of
+ *               interface 0 is fixed to zero in place of its (dependent)
+ *               flux-continuity equation and the returned cell pressure is
+ *               shifted to zero mean.
+ *  fluid      : viscosities for mrcm_update_mobility from saturation.
+ *  precision  : MRCM_PREC_*.
+ *  hip_stream : hipStream_t to issue work on, or NULL for a library-owned
+ *               stream.
+ * Host inputs are copied before return.  Errors: MRCM_E_INVAL (bad sizes,
+ * non-positive or non-finite K or alpha, bad space/dof combination),
+ * MRCM_E_UNSUPPORTED, MRCM_E_NOMEM, MRCM_E_HIP.  The default mobility is
+ * lambda = 1 (single phase). */
+int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t sub_nx,
+               int32_t sub_ny, int32_t space, int32_t p_dofs, int32_t u_dofs,
+               const double* alpha_per_interface, double alpha_scalar, const mrcm_bc* bc,
+               const double* source, const mrcm_fluid* fluid, int32_t precision,
+               void* hip_stream);
+
+/* Set the total mobility used by the next mrcm_solve: kappa = lambda K
+ * (section 3).  values: nx*ny saturations in [0,1] (values_are_lambda = 0;
+ * lambda is evaluated on the GPU with eq. (fluxos1)) or mobilities > 0
+ * (values_are_lambda = 1).  on_device = 1: values is a device pointer that
+ * must stay valid until this call returns (it is consumed on the context's
+ * stream before return of the next solve; the library copies it).
+ * on_device = 0: host array, copied before return.  Values are validated on
+ * the GPU during the next solve: a non-finite or non-positive lambda makes
+ * that solve fail with MRCM_E_INVAL. */
+int mrcm_update_mobility(mrcm_ctx* ctx, const double* values, int32_t values_are_lambda,
+                         int32_t on_device);
+
+/* Solve the MRCM system for the current mobility (eqs. (mrc1), (mrc2)):
+ * local Robin problems and basis functions for all subdomains, then the
+ * FP64 interface system.  Asynchronous except for a final status read. */
+int mrcm_solve(mrcm_ctx* ctx);
+
+/* Reconstruct fine-scale output from the last solve:
+ *  p  : nx*ny composed multiscale cell pressure (basis functions combined
+ *       with the interface solution, section 3);
+ *  ux : (nx+1)*ny normal velocity in +x on x-faces;
+ *  uy : nx*(ny+1) normal velocity in +y on y-faces.
+ * Velocities are the stitched field: on skeleton faces the average of the
+ * two one-sided Robin fluxes, inside every subdomain the fluxes of a
+ * Neumann re-solve with that interface flux, so that every cell balances.
+ *  on_device : 1 if p/ux/uy are device pointers, 0 for host arrays (any of
+ *              them may be NULL to skip it).
+ *  max_cell_imbalance : if not NULL receives max over cells of
+ *              |net outflow - q|V|| / max |face flux|.
+ * Synchronous: outputs are valid on return.  MRCM_E_STATE before the first
+ * successful solve. */
+int mrcm_fine_flux(mrcm_ctx* ctx, double* p, double* ux, double* uy, int32_t on_device,
+                   double* max_cell_imbalance);
+
+/* Statistics of the last solve / fine_flux. */
+int mrcm_get_stats(const mrcm_ctx* ctx, mrcm_stats* stats);
+
+/* Number of interface unknowns and of subdomains, and the column count R
+ * (1 + 4*(nP+nU)) of the per-subdomain basis-function block. */
+int mrcm_get_sizes(const mrcm_ctx* ctx, int32_t* n_dof, int32_t* n_sub, int32_t* n_cols);
+
+/* Inspection of intermediate results of the last solve (host outputs,
+ * synchronous).  Used by parity tests of the individual steps.
+ *  mrcm_get_interface_solution : n_dof values (P_H, U_H coefficients).
+ *  mrcm_get_local_blocks : n_sub * (R-1) * R values.  Block of subdomain
+ *     sd, row r, column c at [sd*(R-1)*R + r*R + c]: rows and the first R-1
+ *     columns follow the subdomain's W, E, S, N interfaces (nP+nU each,
+ *     zero for sides on the domain boundary); column R-1 holds the
+ *     right-hand side.  Rows of flux (U) dofs are the negated
+ *     pressure-continuity equations, which makes every block symmetric.
+ *  mrcm_get_basis : n_sub * sub_nx*sub_ny * R values: for subdomain sd and
+ *     local cell l = ly*sub_nx + lx, column 0 = particular solution,
+ *     column 1 + side*(nP+nU) + k = basis function of that dof.
+ * MRCM_E_STATE before the first successful solve. */
+int mrcm_get_interface_solution(mrcm_ctx* ctx, double* coeffs);
+int mrcm_get_local_blocks(mrcm_ctx* ctx, double* blocks);
+int mrcm_get_basis(mrcm_ctx* ctx, double* basis);
+
+/* Text of the last error on this context (never NULL). */
+const char* mrcm_last_error(const mrcm_ctx* ctx);
+
+/* Release the context and all its device memory.  NULL is ignored. */
+void mrcm_destroy(mrcm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRCM_H */

@@ -1,0 +1,710 @@
+// C ABI of the MRCM library: context, validation, set-up of the interface
+// spaces and of the nested-dissection plan for the interface system, and
+// the orchestration of the per-step kernels.  Declarations and the contract
+// of every entry point are in include/mrcm.h.
+#include "../../include/mrcm.h"
+#include "mrcm_internal.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+using namespace mrcm;
+
+namespace {
+
+struct PanelLaunch {
+  int k0;
+  int panel_off, panel_count;
+  int update_off, update_count;
+};
+
+struct LevelPlan {
+  bool small;
+  int max_n, max_s;
+  int ids_off, count;
+  int gather_off, gather_count;
+  std::vector<PanelLaunch> panels;
+};
+
+}  // namespace
+
+struct mrcm_ctx {
+  std::string err;
+  Geo g{};
+  int precision = 0;
+  int space = 0;
+  double mu_w = 1.0, mu_o = 1.0;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  int n_dof = 0;
+  int R = 0;
+  bool solved = false;
+  mrcm_stats stats{};
+
+  // device buffers
+  double *K = nullptr, *lam = nullptr, *stage = nullptr, *src = nullptr;
+  double* bcv[4] = {nullptr, nullptr, nullptr, nullptr};
+  double *alpha = nullptr, *basis = nullptr, *X = nullptr, *coef = nullptr;
+  double *p = nullptr, *ux = nullptr, *uy = nullptr, *sub_stats = nullptr, *result = nullptr;
+  double* tree = nullptr;
+  int* status = nullptr;
+  NodeDesc* d_nodes = nullptr;
+  int2* d_maps = nullptr;
+  int* d_dofs = nullptr;
+  int* d_ids = nullptr;
+  int2* d_gather = nullptr;
+  PanelItem* d_items = nullptr;
+  std::vector<void*> allocs;
+
+  // interface plan
+  std::vector<LevelPlan> levels;
+  long long leaf_block = 0;  // doubles per subdomain block
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+int fail(mrcm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, MRCM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+int dev_alloc(mrcm_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return fail(c, MRCM_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return MRCM_OK;
+}
+
+#define ALLOC(ctx, ptr, n)                          \
+  do {                                              \
+    int r_ = dev_alloc(ctx, &(ptr), (size_t)(n));   \
+    if (r_ != MRCM_OK) return r_;                   \
+  } while (0)
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+// ---------------------------------------------------------------------------
+// interface spaces (section 3.1), tabulated per interface on its fine faces
+// ---------------------------------------------------------------------------
+
+double hmean(double a, double b) { return 2.0 * a * b / (a + b); }
+
+// Edge-solution functions on one interface: t_j = harmonic mean of K across
+// face j; psi solves the 1-D two-point problem along the edge (conductance
+// hmean(t_j, t_{j+1}) between neighbours, 2 t at the two ends) with psi = 1
+// at the first end and 0 at the other.  Pressure functions {psi, 1 - psi},
+// flux functions {t / mean t, t (psi - mean psi) / mean t}.
+void edge_solution(const std::vector<double>& klo, const std::vector<double>& khi, double* out,
+                   int M) {
+  std::vector<double> t(M), lo(M), di(M), up(M), rhs(M), psi(M);
+  for (int j = 0; j < M; ++j) t[j] = hmean(klo[j], khi[j]);
+  for (int j = 0; j < M; ++j) {
+    double d = 0.0;
+    lo[j] = up[j] = 0.0;
+    rhs[j] = 0.0;
+    if (j == 0) {
+      d += 2.0 * t[0];
+      rhs[j] = 2.0 * t[0];
+    } else {
+      const double c = hmean(t[j - 1], t[j]);
+      d += c;
+      lo[j] = -c;
+    }
+    if (j == M - 1) {
+      d += 2.0 * t[M - 1];
+    } else {
+      const double c = hmean(t[j], t[j + 1]);
+      d += c;
+      up[j] = -c;
+    }
+    di[j] = d;
+  }
+  // tridiagonal elimination (the matrix is an M-matrix, no pivoting needed)
+  for (int j = 1; j < M; ++j) {
+    const double f = lo[j] / di[j - 1];
+    di[j] -= f * up[j - 1];
+    rhs[j] -= f * rhs[j - 1];
+  }
+  psi[M - 1] = rhs[M - 1] / di[M - 1];
+  for (int j = M - 2; j >= 0; --j) psi[j] = (rhs[j] - up[j] * psi[j + 1]) / di[j];
+  double tm = 0.0, pm = 0.0;
+  for (int j = 0; j < M; ++j) { tm += t[j]; pm += psi[j]; }
+  tm /= M;
+  pm /= M;
+  for (int j = 0; j < M; ++j) {
+    out[0 * M + j] = psi[j];
+    out[1 * M + j] = 1.0 - psi[j];
+    out[2 * M + j] = t[j] / tm;
+    out[3 * M + j] = t[j] * (psi[j] - pm) / tm;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// nested-dissection plan of the interface system
+// ---------------------------------------------------------------------------
+
+struct HNode {
+  bool leaf = false;
+  int sd = -1;
+  int child[2] = {-1, -1};
+  std::vector<int> dofs;   // frontal ordering: shared (eliminated) first
+  int s = 0;
+  int level = 0;
+  long long f_off = 0;
+};
+
+struct TreeBuilder {
+  int SX, SY, nV, D;
+  std::vector<HNode> nodes;
+  int viface(int I, int J) const { return J * (SX - 1) + I; }
+  int hiface(int I, int J) const { return nV + J * SX + I; }
+  void add_dofs(std::vector<int>& out, int e) const {
+    for (int k = 0; k < D; ++k) out.push_back(e * D + k);
+  }
+  int rec(int I0, int I1, int J0, int J1) {
+    if ((I1 - I0) * (J1 - J0) == 1) {
+      HNode n;
+      n.leaf = true;
+      n.sd = J0 * SX + I0;
+      nodes.push_back(n);
+      return (int)nodes.size() - 1;
+    }
+    int a, b;
+    std::vector<int> shared;
+    if (I1 - I0 >= J1 - J0) {
+      const int Im = (I0 + I1) / 2;
+      a = rec(I0, Im, J0, J1);
+      b = rec(Im, I1, J0, J1);
+      for (int J = J0; J < J1; ++J) add_dofs(shared, viface(Im - 1, J));
+    } else {
+      const int Jm = (J0 + J1) / 2;
+      a = rec(I0, I1, J0, Jm);
+      b = rec(I0, I1, Jm, J1);
+      for (int I = I0; I < I1; ++I) add_dofs(shared, hiface(I, Jm - 1));
+    }
+    HNode n;
+    n.child[0] = a;
+    n.child[1] = b;
+    n.dofs = shared;
+    n.s = (int)shared.size();
+    if (I0 > 0) for (int J = J0; J < J1; ++J) add_dofs(n.dofs, viface(I0 - 1, J));
+    if (I1 < SX) for (int J = J0; J < J1; ++J) add_dofs(n.dofs, viface(I1 - 1, J));
+    if (J0 > 0) for (int I = I0; I < I1; ++I) add_dofs(n.dofs, hiface(I, J0 - 1));
+    if (J1 < SY) for (int I = I0; I < I1; ++I) add_dofs(n.dofs, hiface(I, J1 - 1));
+    n.level = 1 + std::max(nodes[a].level, nodes[b].level);
+    nodes.push_back(n);
+    return (int)nodes.size() - 1;
+  }
+  // position of global dof in the Schur block a child hands to its parent
+  int schur_index(int node, int dof, const std::vector<std::unordered_map<int, int>>& pos) const {
+    const HNode& n = nodes[node];
+    if (n.leaf) {
+      const int I = n.sd % SX, J = n.sd / SX;
+      const int e = dof / D, k = dof % D;
+      int side = -1;
+      if (I > 0 && e == viface(I - 1, J)) side = 0;
+      else if (I < SX - 1 && e == viface(I, J)) side = 1;
+      else if (J > 0 && e == hiface(I, J - 1)) side = 2;
+      else if (J < SY - 1 && e == hiface(I, J)) side = 3;
+      return side < 0 ? -1 : side * D + k;
+    }
+    auto it = pos[node].find(dof);
+    if (it == pos[node].end() || it->second < n.s) return -1;
+    return it->second - n.s;
+  }
+};
+
+int build_plan(mrcm_ctx* c) {
+  const Geo& g = c->g;
+  c->leaf_block = (long long)(4 * g.D) * (4 * g.D + 1);
+  long long total = c->leaf_block * g.n_sub;
+  if (c->n_dof == 0) {
+    ALLOC(c, c->tree, total);
+    return MRCM_OK;
+  }
+  TreeBuilder tb{g.SX, g.SY, g.nV, g.D, {}};
+  tb.nodes.reserve(2 * g.n_sub);
+  const int root = tb.rec(0, g.SX, 0, g.SY);
+  (void)root;
+  std::vector<std::unordered_map<int, int>> pos(tb.nodes.size());
+  for (size_t i = 0; i < tb.nodes.size(); ++i) {
+    HNode& n = tb.nodes[i];
+    if (n.leaf) continue;
+    for (size_t k = 0; k < n.dofs.size(); ++k) pos[i][n.dofs[k]] = (int)k;
+    n.f_off = total;
+    total += (long long)n.dofs.size() * (n.dofs.size() + 1);
+  }
+  // descriptors, maps, dofs; non-leaf nodes grouped by level
+  int max_level = 0;
+  for (auto& n : tb.nodes) max_level = std::max(max_level, n.level);
+  std::vector<NodeDesc> desc;
+  std::vector<int2> maps;
+  std::vector<int> dofs, ids;
+  std::vector<int2> gather;
+  std::vector<PanelItem> items;
+  std::vector<int> node_desc(tb.nodes.size(), -1);
+  for (size_t i = 0; i < tb.nodes.size(); ++i) {
+    const HNode& n = tb.nodes[i];
+    if (n.leaf) continue;
+    NodeDesc d{};
+    d.f_off = n.f_off;
+    d.n = (int)n.dofs.size();
+    d.s = n.s;
+    d.map_off = (long long)maps.size();
+    d.dof_off = (long long)dofs.size();
+    for (int q = 0; q < 2; ++q) {
+      const HNode& ch = tb.nodes[n.child[q]];
+      if (ch.leaf) {
+        d.c_off[q] = (long long)ch.sd * c->leaf_block;
+        d.c_ld[q] = 4 * g.D + 1;
+        d.c_rhs[q] = 4 * g.D;
+      } else {
+        const int cn = (int)ch.dofs.size();
+        d.c_off[q] = ch.f_off + (long long)ch.s * (cn + 1) + ch.s;
+        d.c_ld[q] = cn + 1;
+        d.c_rhs[q] = cn - ch.s;
+      }
+    }
+    for (int dof : n.dofs) {
+      const int ia = tb.schur_index(n.child[0], dof, pos);
+      const int ib = tb.schur_index(n.child[1], dof, pos);
+      if (ia < 0 && ib < 0) return fail(c, MRCM_E_INVAL, "internal: interface plan is inconsistent");
+      maps.push_back(make_int2(ia, ib));
+      dofs.push_back(dof);
+    }
+    node_desc[i] = (int)desc.size();
+    desc.push_back(d);
+  }
+  for (int lv = 1; lv <= max_level; ++lv) {
+    LevelPlan lp{};
+    lp.ids_off = (int)ids.size();
+    for (size_t i = 0; i < tb.nodes.size(); ++i) {
+      const HNode& n = tb.nodes[i];
+      if (n.leaf || n.level != lv) continue;
+      ids.push_back(node_desc[i]);
+      lp.max_n = std::max(lp.max_n, (int)n.dofs.size());
+      lp.max_s = std::max(lp.max_s, n.s);
+    }
+    lp.count = (int)ids.size() - lp.ids_off;
+    if (lp.count == 0) continue;
+    if (lp.max_s > 2048) return fail(c, MRCM_E_UNSUPPORTED, "interface separator too large");
+    lp.small = lp.max_n <= SMALL_FRONT;
+    if (!lp.small) {
+      lp.gather_off = (int)gather.size();
+      for (int q = 0; q < lp.count; ++q) {
+        const NodeDesc& d = desc[ids[lp.ids_off + q]];
+        for (int r = 0; r < d.n; r += 16) gather.push_back(make_int2(ids[lp.ids_off + q], r));
+      }
+      lp.gather_count = (int)gather.size() - lp.gather_off;
+      for (int k0 = 0; k0 < lp.max_s; k0 += PANEL_NB) {
+        PanelLaunch pl{};
+        pl.k0 = k0;
+        pl.panel_off = (int)items.size();
+        for (int q = 0; q < lp.count; ++q) {
+          const int id = ids[lp.ids_off + q];
+          const NodeDesc& d = desc[id];
+          if (d.s <= k0) continue;
+          const int nb = std::min(PANEL_NB, d.s - k0);
+          for (int r = k0 + nb; r < d.n; r += 256) items.push_back(PanelItem{id, 0, r, 0});
+          for (int cc = k0 + nb; cc <= d.n; cc += 256) items.push_back(PanelItem{id, 1, 0, cc});
+        }
+        pl.panel_count = (int)items.size() - pl.panel_off;
+        pl.update_off = (int)items.size();
+        for (int q = 0; q < lp.count; ++q) {
+          const int id = ids[lp.ids_off + q];
+          const NodeDesc& d = desc[id];
+          if (d.s <= k0) continue;
+          const int nb = std::min(PANEL_NB, d.s - k0);
+          items.push_back(PanelItem{id, 3, k0, k0});
+          for (int r = k0 + nb; r < d.n; r += TILE)
+            for (int cc = k0 + nb; cc <= d.n; cc += TILE) items.push_back(PanelItem{id, 2, r, cc});
+        }
+        pl.update_count = (int)items.size() - pl.update_off;
+        lp.panels.push_back(pl);
+      }
+    }
+    c->levels.push_back(lp);
+  }
+  ALLOC(c, c->tree, total);
+  ALLOC(c, c->d_nodes, desc.size());
+  ALLOC(c, c->d_maps, maps.size());
+  ALLOC(c, c->d_dofs, dofs.size());
+  ALLOC(c, c->d_ids, ids.size());
+  ALLOC(c, c->d_gather, gather.size());
+  ALLOC(c, c->d_items, items.size());
+  HIPCHK(c, hipMemcpy(c->d_nodes, desc.data(), desc.size() * sizeof(NodeDesc), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_maps, maps.data(), maps.size() * sizeof(int2), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_dofs, dofs.data(), dofs.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_ids, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice));
+  if (!gather.empty())
+    HIPCHK(c, hipMemcpy(c->d_gather, gather.data(), gather.size() * sizeof(int2), hipMemcpyHostToDevice));
+  if (!items.empty())
+    HIPCHK(c, hipMemcpy(c->d_items, items.data(), items.size() * sizeof(PanelItem), hipMemcpyHostToDevice));
+  return MRCM_OK;
+}
+
+SubArgs sub_args(const mrcm_ctx* c) {
+  SubArgs a{};
+  a.g = c->g;
+  a.K = c->K;
+  a.lam = c->lam;
+  a.src = c->src;
+  for (int s = 0; s < 4; ++s) a.bcv[s] = c->bcv[s];
+  a.alpha = c->alpha;
+  a.basis = c->basis;
+  a.X = c->X;
+  a.blocks = c->tree;  // the subdomain blocks are the leaves of the interface tree
+  a.coef = c->coef;
+  a.p_out = c->p;
+  a.ux = c->ux;
+  a.uy = c->uy;
+  a.sub_stats = c->sub_stats;
+  a.status = c->status;
+  return a;
+}
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
+int run_interface(mrcm_ctx* c) {
+  hipStream_t st = c->st;
+  for (const LevelPlan& lp : c->levels) {
+    if (lp.small) {
+      HIPCHK(c, launch_front_small(c->d_nodes, c->d_ids + lp.ids_off, lp.count, lp.max_n, c->tree,
+                                   c->d_maps, c->status, st));
+      continue;
+    }
+    HIPCHK(c, launch_front_gather(c->d_nodes, c->d_gather + lp.gather_off, lp.gather_count, c->tree,
+                                  c->d_maps, st));
+    for (const PanelLaunch& pl : lp.panels) {
+      HIPCHK(c, launch_front_panel(c->d_nodes, c->d_items + pl.panel_off, pl.panel_count, pl.k0,
+                                   c->tree, c->status, st));
+      HIPCHK(c, launch_front_update(c->d_nodes, c->d_items + pl.update_off, pl.update_count, pl.k0,
+                                    c->tree, c->status, st));
+    }
+  }
+  for (auto it = c->levels.rbegin(); it != c->levels.rend(); ++it)
+    HIPCHK(c, launch_front_back(c->d_nodes, c->d_ids + it->ids_off, it->count, c->tree, c->d_dofs,
+                                c->coef, st));
+  HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->result + 2, st));
+  return MRCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t sub_nx,
+               int32_t sub_ny, int32_t space, int32_t p_dofs, int32_t u_dofs,
+               const double* alpha_per_interface, double alpha_scalar, const mrcm_bc* bc,
+               const double* source, const mrcm_fluid* fluid, int32_t precision,
+               void* hip_stream) {
+  if (!out) return MRCM_E_INVAL;
+  *out = nullptr;
+  if (!g || !perm || !bc || !fluid) return MRCM_E_INVAL;
+  if (g->nx <= 0 || g->ny <= 0 || !finite_pos(g->lx) || !finite_pos(g->ly)) return MRCM_E_INVAL;
+  if (sub_nx != sub_ny) return MRCM_E_UNSUPPORTED;
+  const int M = sub_nx;
+  if (!(M == 4 || M == 8 || M == 16 || M == 32)) return MRCM_E_UNSUPPORTED;
+  if (g->nx % M || g->ny % M) return MRCM_E_INVAL;
+  if (space == MRCM_SPACE_LINEAR || space == MRCM_SPACE_EDGE_SOLUTION) {
+    if (p_dofs != 2 || u_dofs != 2) return MRCM_E_INVAL;
+  } else if (space == MRCM_SPACE_FULL) {
+    if (p_dofs != M || u_dofs != M) return MRCM_E_INVAL;
+  } else {
+    return MRCM_E_INVAL;
+  }
+  if (precision != MRCM_PREC_FP64 && precision != MRCM_PREC_FP32_IR) return MRCM_E_INVAL;
+  if (precision != MRCM_PREC_FP64) return MRCM_E_UNSUPPORTED;
+  if (!finite_pos(fluid->mu_w) || !finite_pos(fluid->mu_o)) return MRCM_E_INVAL;
+  for (int s = 0; s < 4; ++s)
+    if (bc->kind[s] != MRCM_BC_NEUMANN && bc->kind[s] != MRCM_BC_DIRICHLET) return MRCM_E_INVAL;
+  const size_t ncell = (size_t)g->nx * g->ny;
+  for (size_t i = 0; i < ncell; ++i)
+    if (!finite_pos(perm[i])) return MRCM_E_INVAL;
+  const int SX = g->nx / M, SY = g->ny / M;
+  const int n_iface = (SX - 1) * SY + SX * (SY - 1);
+  if (alpha_per_interface) {
+    for (int e = 0; e < n_iface; ++e)
+      if (!finite_pos(alpha_per_interface[e])) return MRCM_E_INVAL;
+  } else if (!finite_pos(alpha_scalar)) {
+    return MRCM_E_INVAL;
+  }
+  if (!local_supported(M, p_dofs + u_dofs)) return MRCM_E_UNSUPPORTED;
+  for (int s = 0; s < 4; ++s) {
+    const int n = s < 2 ? g->ny : g->nx;
+    if (bc->value[s])
+      for (int i = 0; i < n; ++i)
+        if (!isfinite(bc->value[s][i])) return MRCM_E_INVAL;
+  }
+  if (source)
+    for (size_t i = 0; i < ncell; ++i)
+      if (!isfinite(source[i])) return MRCM_E_INVAL;
+
+  mrcm_ctx* c = new (std::nothrow) mrcm_ctx();
+  if (!c) return MRCM_E_NOMEM;
+  Geo& G = c->g;
+  G.nx = g->nx; G.ny = g->ny; G.M = M; G.SX = SX; G.SY = SY;
+  G.nV = (SX - 1) * SY; G.n_sub = SX * SY;
+  G.nP = p_dofs; G.nU = u_dofs; G.D = p_dofs + u_dofs;
+  G.hx = g->lx / g->nx; G.hy = g->ly / g->ny;
+  bool any_dir = false;
+  for (int s = 0; s < 4; ++s) { G.kind[s] = bc->kind[s]; any_dir |= bc->kind[s] == MRCM_BC_DIRICHLET; }
+  G.gauge = any_dir ? 0 : 1;
+  c->precision = precision;
+  c->space = space;
+  c->mu_w = fluid->mu_w;
+  c->mu_o = fluid->mu_o;
+  c->n_dof = n_iface * G.D;
+  c->R = 1 + 4 * G.D;
+
+  int rc = MRCM_OK;
+  auto setup_body = [&]() -> int {
+    if (hip_stream) {
+      c->st = (hipStream_t)hip_stream;
+    } else {
+      HIPCHK(c, hipStreamCreate(&c->st));
+      c->own_stream = true;
+    }
+    for (int i = 0; i < 4; ++i) HIPCHK(c, hipEventCreate(&c->ev[i]));
+    HIPCHK(c, prepare_interface_kernels());
+    ALLOC(c, c->K, ncell);
+    ALLOC(c, c->lam, ncell);
+    ALLOC(c, c->stage, ncell);
+    if (source) ALLOC(c, c->src, ncell);
+    for (int s = 0; s < 4; ++s) ALLOC(c, c->bcv[s], s < 2 ? G.ny : G.nx);
+    ALLOC(c, c->alpha, n_iface);
+    ALLOC(c, c->basis, (size_t)std::max(n_iface, 1) * G.D * M);
+    ALLOC(c, c->X, (size_t)G.n_sub * M * M * c->R);
+    ALLOC(c, c->coef, std::max(c->n_dof, 1));
+    ALLOC(c, c->p, ncell);
+    ALLOC(c, c->ux, (size_t)(G.nx + 1) * G.ny);
+    ALLOC(c, c->uy, (size_t)G.nx * (G.ny + 1));
+    ALLOC(c, c->sub_stats, 3 * G.n_sub);
+    ALLOC(c, c->result, 8);
+    ALLOC(c, c->status, 1);
+    HIPCHK(c, hipMemcpy(c->K, perm, ncell * sizeof(double), hipMemcpyHostToDevice));
+    {
+      std::vector<double> ones(ncell, 1.0);
+      HIPCHK(c, hipMemcpy(c->lam, ones.data(), ncell * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (source) HIPCHK(c, hipMemcpy(c->src, source, ncell * sizeof(double), hipMemcpyHostToDevice));
+    for (int s = 0; s < 4; ++s) {
+      const int n = s < 2 ? G.ny : G.nx;
+      std::vector<double> v(n, 0.0);
+      if (bc->value[s]) std::copy(bc->value[s], bc->value[s] + n, v.begin());
+      HIPCHK(c, hipMemcpy(c->bcv[s], v.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    }
+    std::vector<double> al(std::max(n_iface, 1), alpha_scalar);
+    if (alpha_per_interface) std::copy(alpha_per_interface, alpha_per_interface + n_iface, al.begin());
+    HIPCHK(c, hipMemcpy(c->alpha, al.data(), al.size() * sizeof(double), hipMemcpyHostToDevice));
+    // interface functions, rows [psi_0.., phi_0..] per interface
+    std::vector<double> bs((size_t)std::max(n_iface, 1) * G.D * M, 0.0);
+    std::vector<double> klo(M), khi(M);
+    for (int e = 0; e < n_iface; ++e) {
+      double* b = bs.data() + (size_t)e * G.D * M;
+      if (space == MRCM_SPACE_LINEAR) {
+        for (int t = 0; t < M; ++t) {
+          const double xi = (t + 0.5) / M;
+          b[0 * M + t] = 1.0 - xi;
+          b[1 * M + t] = xi;
+          b[2 * M + t] = 1.0 - xi;
+          b[3 * M + t] = xi;
+        }
+      } else if (space == MRCM_SPACE_FULL) {
+        for (int k = 0; k < M; ++k) {
+          b[k * M + k] = 1.0;
+          b[(M + k) * M + k] = 1.0;
+        }
+      } else {
+        for (int t = 0; t < M; ++t) {
+          size_t cl, ch;
+          if (e < G.nV) {
+            const int J = e / (SX - 1), I = e % (SX - 1);
+            const int i = (I + 1) * M, j = J * M + t;
+            cl = (size_t)j * G.nx + i - 1;
+            ch = (size_t)j * G.nx + i;
+          } else {
+            const int h = e - G.nV, J = h / SX, I = h % SX;
+            const int j = (J + 1) * M, i = I * M + t;
+            cl = (size_t)(j - 1) * G.nx + i;
+            ch = (size_t)j * G.nx + i;
+          }
+          klo[t] = perm[cl];
+          khi[t] = perm[ch];
+        }
+        edge_solution(klo, khi, b, M);
+      }
+    }
+    HIPCHK(c, hipMemcpy(c->basis, bs.data(), bs.size() * sizeof(double), hipMemcpyHostToDevice));
+    int r = build_plan(c);
+    if (r != MRCM_OK) return r;
+    HIPCHK(c, hipDeviceSynchronize());
+    return MRCM_OK;
+  };
+  rc = setup_body();
+  if (rc != MRCM_OK) {
+    fprintf(stderr, "mrcm_setup: %s\n", c->err.c_str());
+    mrcm_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return MRCM_OK;
+}
+
+int mrcm_update_mobility(mrcm_ctx* c, const double* values, int32_t values_are_lambda,
+                         int32_t on_device) {
+  if (!c) return MRCM_E_INVAL;
+  if (!values) return fail(c, MRCM_E_INVAL, "values is NULL");
+  const size_t n = (size_t)c->g.nx * c->g.ny;
+  const double* src = values;
+  if (!on_device) {
+    HIPCHK(c, hipMemcpyAsync(c->stage, values, n * sizeof(double), hipMemcpyHostToDevice, c->st));
+    src = c->stage;
+  }
+  HIPCHK(c, launch_mobility(src, c->lam, n, values_are_lambda ? 0 : 1, c->mu_w, c->mu_o, c->st));
+  if (!on_device) HIPCHK(c, hipStreamSynchronize(c->st));  // host buffer may be reused on return
+  c->solved = false;
+  return MRCM_OK;
+}
+
+int mrcm_solve(mrcm_ctx* c) {
+  if (!c) return MRCM_E_INVAL;
+  hipStream_t st = c->st;
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, c->status);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipEventRecord(c->ev[0], st));
+  SubArgs a = sub_args(c);
+  HIPCHK(c, launch_local_basis(a, st));
+  HIPCHK(c, hipEventRecord(c->ev[1], st));
+  if (c->n_dof > 0) {
+    int r = run_interface(c);
+    if (r != MRCM_OK) return r;
+  }
+  HIPCHK(c, hipEventRecord(c->ev[2], st));
+  int status = 0;
+  double res[2] = {0.0, 0.0};
+  HIPCHK(c, hipMemcpyAsync(&status, c->status, sizeof(int), hipMemcpyDeviceToHost, st));
+  if (c->n_dof > 0)
+    HIPCHK(c, hipMemcpyAsync(res, c->result + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  float t1 = 0.f, t2 = 0.f;
+  (void)hipEventElapsedTime(&t1, c->ev[0], c->ev[1]);
+  (void)hipEventElapsedTime(&t2, c->ev[1], c->ev[2]);
+  c->stats.ms_local = t1;
+  c->stats.ms_interface = t2;
+  c->stats.interface_residual = res[1] > 0.0 ? res[0] / res[1] : 0.0;
+  if (status & ST_BAD_LAMBDA) return fail(c, MRCM_E_INVAL, "mobility not finite and positive");
+  if (status & (ST_LOCAL_PIVOT | ST_IFACE_PIVOT))
+    return fail(c, MRCM_E_NOT_SPD, "non-positive or zero pivot in the elimination");
+  c->solved = true;
+  return MRCM_OK;
+}
+
+int mrcm_fine_flux(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_device,
+                   double* max_cell_imbalance) {
+  if (!c) return MRCM_E_INVAL;
+  if (!c->solved) return fail(c, MRCM_E_STATE, "fine_flux called before a successful solve");
+  hipStream_t st = c->st;
+  const Geo& G = c->g;
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, c->status);
+  HIPCHK(c, hipEventRecord(c->ev[2], st));
+  SubArgs a = sub_args(c);
+  HIPCHK(c, launch_stitch(a, st));
+  HIPCHK(c, launch_finish_flux(a, c->result, st));
+  HIPCHK(c, hipEventRecord(c->ev[3], st));
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  const size_t ncell = (size_t)G.nx * G.ny;
+  if (p) HIPCHK(c, hipMemcpyAsync(p, c->p, ncell * sizeof(double), kind, st));
+  if (ux) HIPCHK(c, hipMemcpyAsync(ux, c->ux, (size_t)(G.nx + 1) * G.ny * sizeof(double), kind, st));
+  if (uy) HIPCHK(c, hipMemcpyAsync(uy, c->uy, (size_t)G.nx * (G.ny + 1) * sizeof(double), kind, st));
+  double imb = 0.0;
+  int status = 0;
+  HIPCHK(c, hipMemcpyAsync(&imb, c->result, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(&status, c->status, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  float t = 0.f;
+  (void)hipEventElapsedTime(&t, c->ev[2], c->ev[3]);
+  c->stats.ms_flux = t;
+  if (max_cell_imbalance) *max_cell_imbalance = imb;
+  if (status & ST_STITCH_PIVOT) return fail(c, MRCM_E_NOT_SPD, "non-positive pivot in the stitch re-solve");
+  return MRCM_OK;
+}
+
+int mrcm_get_stats(const mrcm_ctx* c, mrcm_stats* s) {
+  if (!c || !s) return MRCM_E_INVAL;
+  *s = c->stats;
+  s->n_sub = c->g.n_sub;
+  s->n_dof = c->n_dof;
+  return MRCM_OK;
+}
+
+int mrcm_get_sizes(const mrcm_ctx* c, int32_t* n_dof, int32_t* n_sub, int32_t* n_cols) {
+  if (!c) return MRCM_E_INVAL;
+  if (n_dof) *n_dof = c->n_dof;
+  if (n_sub) *n_sub = c->g.n_sub;
+  if (n_cols) *n_cols = c->R;
+  return MRCM_OK;
+}
+
+int mrcm_get_interface_solution(mrcm_ctx* c, double* coeffs) {
+  if (!c || !coeffs) return MRCM_E_INVAL;
+  if (!c->solved) return fail(c, MRCM_E_STATE, "no solve yet");
+  if (c->n_dof == 0) return MRCM_OK;
+  HIPCHK(c, hipMemcpyAsync(coeffs, c->coef, c->n_dof * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return MRCM_OK;
+}
+
+int mrcm_get_local_blocks(mrcm_ctx* c, double* blocks) {
+  if (!c || !blocks) return MRCM_E_INVAL;
+  if (!c->solved) return fail(c, MRCM_E_STATE, "no solve yet");
+  HIPCHK(c, hipMemcpyAsync(blocks, c->tree, (size_t)c->g.n_sub * c->leaf_block * sizeof(double),
+                           hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return MRCM_OK;
+}
+
+int mrcm_get_basis(mrcm_ctx* c, double* basis) {
+  if (!c || !basis) return MRCM_E_INVAL;
+  if (!c->solved) return fail(c, MRCM_E_STATE, "no solve yet");
+  const size_t n = (size_t)c->g.n_sub * c->g.M * c->g.M * c->R;
+  HIPCHK(c, hipMemcpyAsync(basis, c->X, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return MRCM_OK;
+}
+
+const char* mrcm_last_error(const mrcm_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+void mrcm_destroy(mrcm_ctx* c) {
+  if (!c) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  for (void* q : c->allocs) (void)hipFree(q);
+  for (int i = 0; i < 4; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
+  delete c;
+}
+
+}  // extern "C"

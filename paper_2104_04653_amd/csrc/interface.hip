@@ -1,0 +1,353 @@
+// FP64 solve of the MRCM interface system (paper, section 3, eq. (mrc2))
+// on gfx950.
+//
+// The interface system is the sum over subdomains of the symmetric
+// per-subdomain blocks written by the local kernel (rows of the
+// pressure-continuity equations negated).  The sum is symmetric
+// quasi-definite: its pressure-pressure part is negative semidefinite and
+// its flux-flux part positive definite, so an elimination without pivoting
+// exists for any ordering.  It is eliminated with a nested-dissection tree
+// over the subdomain grid: boxes of subdomains are split in two along their
+// longer side; a node gathers its two children's Schur complements
+// ("extend-add", a deterministic gather), eliminates the interface unknowns
+// on the line that separates the children, and passes the Schur complement
+// on the box boundary to its parent.  The leaves are the subdomain blocks
+// themselves, so the global matrix is never formed.
+//
+// Fronts of up to SMALL_FRONT unknowns are gathered and eliminated by one
+// work-group in LDS.  Larger fronts (the few nodes near the root) are
+// gathered in global memory and eliminated by a right-looking blocked LU:
+// per panel of PANEL_NB columns, one launch computes the L21 rows and U12
+// columns (every work-group factors the small diagonal block redundantly in
+// LDS) and one launch applies the trailing update A22 -= L21 U12 in 64x64
+// tiles and writes the factored diagonal block.  Back substitution runs top
+// down, one work-group per node.
+#include "mrcm_internal.h"
+
+#include <math.h>
+
+namespace mrcm {
+
+namespace {
+
+constexpr int NT = 256;
+
+__device__ inline double gather_entry(const NodeDesc& nd, const double* tree, int2 ma, int2 mb,
+                                      bool rhs) {
+  double v = 0.0;
+  if (!rhs) {
+    if (ma.x >= 0 && mb.x >= 0) v += tree[nd.c_off[0] + (long long)ma.x * nd.c_ld[0] + mb.x];
+    if (ma.y >= 0 && mb.y >= 0) v += tree[nd.c_off[1] + (long long)ma.y * nd.c_ld[1] + mb.y];
+  } else {
+    if (ma.x >= 0) v += tree[nd.c_off[0] + (long long)ma.x * nd.c_ld[0] + nd.c_rhs[0]];
+    if (ma.y >= 0) v += tree[nd.c_off[1] + (long long)ma.y * nd.c_ld[1] + nd.c_rhs[1]];
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(NT) front_small_kernel(const NodeDesc* nodes, const int* ids,
+                                                         double* tree, const int2* maps,
+                                                         int* status) {
+  extern __shared__ double F[];
+  const NodeDesc nd = nodes[ids[blockIdx.x]];
+  const int n = nd.n, s = nd.s, ld = n + 1;
+  const int tid = threadIdx.x;
+  const int2* mp = maps + nd.map_off;
+  for (int e = tid; e < n * ld; e += NT) {
+    const int a = e / ld, b = e % ld;
+    const int2 ma = mp[a];
+    F[e] = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int k = 0; k < s; ++k) {
+    const double piv = F[k * ld + k];
+    if (piv == 0.0 || !isfinite(piv)) bad = true;
+    const double ip = 1.0 / piv;
+    for (int a = k + 1 + tid; a < n; a += NT) F[a * ld + k] *= ip;
+    __syncthreads();
+    const int w = ld - (k + 1), h = n - (k + 1);
+    for (int e = tid; e < h * w; e += NT) {
+      const int a = k + 1 + e / w, b = k + 1 + e % w;
+      F[a * ld + b] -= F[a * ld + k] * F[k * ld + b];
+    }
+    __syncthreads();
+  }
+  double* out = tree + nd.f_off;
+  for (int e = tid; e < n * ld; e += NT) out[e] = F[e];
+  if (bad && tid == 0) atomicOr(status, ST_IFACE_PIVOT);
+}
+
+// items: (node index, first row); each work-group gathers 16 rows of a front
+__global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes, const int2* items,
+                                                          double* tree, const int2* maps) {
+  const int2 it = items[blockIdx.x];
+  const NodeDesc nd = nodes[it.x];
+  const int n = nd.n, ld = n + 1;
+  const int2* mp = maps + nd.map_off;
+  const int r0 = it.y, r1 = min(n, r0 + 16);
+  double* F = tree + nd.f_off;
+  for (int e = threadIdx.x; e < (r1 - r0) * ld; e += NT) {
+    const int a = r0 + e / ld, b = e % ld;
+    const int2 ma = mp[a];
+    F[(long long)a * ld + b] = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
+  }
+}
+
+// LU (no pivoting) of the nb x nb diagonal block at (k0, k0) into LDS A[nb][PANEL_NB+1]
+__device__ void factor_diag(const double* F, int ld, int k0, int nb, double (*A)[PANEL_NB + 1],
+                            bool& bad) {
+  for (int e = threadIdx.x; e < nb * nb; e += NT) {
+    const int i = e / nb, j = e % nb;
+    A[i][j] = F[(long long)(k0 + i) * ld + k0 + j];
+  }
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    const double piv = A[k][k];
+    if (piv == 0.0 || !isfinite(piv)) bad = true;
+    for (int i = k + 1 + threadIdx.x; i < nb; i += NT) A[i][k] /= piv;
+    __syncthreads();
+    const int w = nb - k - 1;
+    for (int e = threadIdx.x; e < w * w; e += NT) {
+      const int i = k + 1 + e / w, j = k + 1 + e % w;
+      A[i][j] -= A[i][k] * A[k][j];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(NT) front_panel_kernel(const NodeDesc* nodes,
+                                                         const PanelItem* items, int k0,
+                                                         double* tree, int* status) {
+  __shared__ double A[PANEL_NB][PANEL_NB + 1];
+  const PanelItem it = items[blockIdx.x];
+  const NodeDesc nd = nodes[it.node];
+  const int n = nd.n, ld = n + 1;
+  const int nb = min(PANEL_NB, nd.s - k0);
+  double* F = tree + nd.f_off;
+  bool bad = false;
+  factor_diag(F, ld, k0, nb, A, bad);
+  const int t = threadIdx.x;
+  if (it.kind == 0) {
+    // L21 row r: solve x U11 = a
+    const int r = it.i0 + t;
+    if (r < n) {
+      double x[PANEL_NB] = {};
+      double* row = F + (long long)r * ld + k0;
+      for (int k = 0; k < nb; ++k) x[k] = row[k];
+      for (int k = 0; k < nb; ++k) {
+        double v = x[k];
+        for (int m = 0; m < k; ++m) v -= x[m] * A[m][k];
+        x[k] = v / A[k][k];
+      }
+      for (int k = 0; k < nb; ++k) row[k] = x[k];
+    }
+  } else {
+    // U12 column c: solve L11 y = a (unit lower)
+    const int c = it.j0 + t;
+    if (c <= n) {
+      double y[PANEL_NB];
+      for (int k = 0; k < nb; ++k) y[k] = F[(long long)(k0 + k) * ld + c];
+      for (int k = 0; k < nb; ++k) {
+        double v = y[k];
+        for (int m = 0; m < k; ++m) v -= A[k][m] * y[m];
+        y[k] = v;
+      }
+      for (int k = 0; k < nb; ++k) F[(long long)(k0 + k) * ld + c] = y[k];
+    }
+  }
+  if (bad && t == 0) atomicOr(status, ST_IFACE_PIVOT);
+}
+
+__global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
+                                                          const PanelItem* items, int k0,
+                                                          double* tree, int* status) {
+  __shared__ double Ls[TILE][PANEL_NB + 1];
+  __shared__ double Us[PANEL_NB][TILE + 1];
+  __shared__ double A[PANEL_NB][PANEL_NB + 1];
+  const PanelItem it = items[blockIdx.x];
+  const NodeDesc nd = nodes[it.node];
+  const int n = nd.n, ld = n + 1;
+  const int nb = min(PANEL_NB, nd.s - k0);
+  double* F = tree + nd.f_off;
+  const int t = threadIdx.x;
+  if (it.kind == 3) {
+    bool bad = false;
+    factor_diag(F, ld, k0, nb, A, bad);
+    for (int e = t; e < nb * nb; e += NT) {
+      const int i = e / nb, j = e % nb;
+      F[(long long)(k0 + i) * ld + k0 + j] = A[i][j];
+    }
+    if (bad && t == 0) atomicOr(status, ST_IFACE_PIVOT);
+    return;
+  }
+  const int r0 = it.i0, c0 = it.j0;
+  const int rows = min(TILE, n - r0), cols = min(TILE, ld - c0);
+  for (int e = t; e < TILE * PANEL_NB; e += NT) {
+    const int i = e / PANEL_NB, k = e % PANEL_NB;
+    Ls[i][k] = (i < rows && k < nb) ? F[(long long)(r0 + i) * ld + k0 + k] : 0.0;
+  }
+  for (int e = t; e < PANEL_NB * TILE; e += NT) {
+    const int k = e / TILE, j = e % TILE;
+    Us[k][j] = (k < nb && j < cols) ? F[(long long)(k0 + k) * ld + c0 + j] : 0.0;
+  }
+  __syncthreads();
+  // 4x4 outputs per thread: rows ty*4.., cols tx*4..  (16 x 16 threads)
+  const int tx = t % 16, ty = t / 16;
+  double acc[4][4] = {};
+#pragma unroll 2
+  for (int k = 0; k < PANEL_NB; ++k) {
+    double lv[4], uv[4];
+    for (int u = 0; u < 4; ++u) lv[u] = Ls[ty * 4 + u][k];
+    for (int v = 0; v < 4; ++v) uv[v] = Us[k][tx * 4 + v];
+    for (int u = 0; u < 4; ++u)
+      for (int v = 0; v < 4; ++v) acc[u][v] += lv[u] * uv[v];
+  }
+  for (int u = 0; u < 4; ++u) {
+    const int i = ty * 4 + u;
+    if (i >= rows) continue;
+    for (int v = 0; v < 4; ++v) {
+      const int j = tx * 4 + v;
+      if (j < cols) F[(long long)(r0 + i) * ld + c0 + j] -= acc[u][v];
+    }
+  }
+}
+
+// x_s = U_ss^{-1} (y_s - U_sr x_r) for one node; x_r from ancestors
+__global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, const int* ids,
+                                                        const double* tree, const int* dofs,
+                                                        double* x) {
+  extern __shared__ double y[];
+  const NodeDesc nd = nodes[ids[blockIdx.x]];
+  const int n = nd.n, s = nd.s, ld = n + 1;
+  const double* F = tree + nd.f_off;
+  const int* dof = dofs + nd.dof_off;
+  const int t = threadIdx.x;
+  for (int k = t; k < s; k += NT) {
+    const double* row = F + (long long)k * ld;
+    double v = row[n];
+    for (int m = s; m < n; ++m) v -= row[m] * x[dof[m]];
+    y[k] = v;
+  }
+  __syncthreads();
+  for (int k = s - 1; k >= 0; --k) {
+    const double xk = y[k] / F[(long long)k * ld + k];
+    __syncthreads();
+    for (int i = t; i < k; i += NT) y[i] -= F[(long long)i * ld + k] * xk;
+    if (t == 0) y[k] = xk;
+    __syncthreads();
+  }
+  for (int k = t; k < s; k += NT) x[dof[k]] = y[k];
+}
+
+// r = b - A x gathered from the subdomain blocks (each interface row has
+// two owners: its lower- and higher-index subdomain).  out2[0] = max |r|,
+// out2[1] = max |b| over rows, reduced by one work-group.
+__global__ void __launch_bounds__(NT) iface_residual_kernel(Geo g, const double* blocks,
+                                                            const double* x, double* out2) {
+  __shared__ double red[2][NT];
+  const int D = g.D, NBR = 4 * D, NBC = NBR + 1;
+  const int n_iface = g.nV + g.SX * (g.SY - 1);
+  const int ndof = n_iface * D;
+  double rmax = 0.0, bmax = 0.0;
+  for (int row = threadIdx.x; row < ndof; row += NT) {
+    const int e = row / D, k = row % D;
+    int sub[2], side[2];
+    if (e < g.nV) {
+      const int J = e / (g.SX - 1), I = e % (g.SX - 1);
+      sub[0] = J * g.SX + I; side[0] = 1;
+      sub[1] = sub[0] + 1; side[1] = 0;
+    } else {
+      const int h = e - g.nV;
+      const int J = h / g.SX, I = h % g.SX;
+      sub[0] = J * g.SX + I; side[0] = 3;
+      sub[1] = sub[0] + g.SX; side[1] = 2;
+    }
+    double ax = 0.0, b = 0.0;
+    for (int o = 0; o < 2; ++o) {
+      const int sd = sub[o];
+      const int I = sd % g.SX, J = sd / g.SX;
+      const double* blk = blocks + (size_t)sd * NBR * NBC + (size_t)(side[o] * D + k) * NBC;
+      b += blk[NBR];
+      for (int sd_side = 0; sd_side < 4; ++sd_side) {
+        int ee;
+        switch (sd_side) {
+          case 0: ee = I > 0 ? J * (g.SX - 1) + I - 1 : -1; break;
+          case 1: ee = I < g.SX - 1 ? J * (g.SX - 1) + I : -1; break;
+          case 2: ee = J > 0 ? g.nV + (J - 1) * g.SX + I : -1; break;
+          default: ee = J < g.SY - 1 ? g.nV + J * g.SX + I : -1;
+        }
+        if (ee < 0) continue;
+        for (int kk = 0; kk < D; ++kk) ax += blk[sd_side * D + kk] * x[(size_t)ee * D + kk];
+      }
+    }
+    rmax = fmax(rmax, fabs(b - ax));
+    bmax = fmax(bmax, fabs(b));
+  }
+  red[0][threadIdx.x] = rmax;
+  red[1][threadIdx.x] = bmax;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out2[0] = red[0][0];
+    out2[1] = red[1][0];
+  }
+}
+
+}  // namespace
+
+hipError_t prepare_interface_kernels() {
+  return hipFuncSetAttribute((const void*)front_small_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             SMALL_FRONT * (SMALL_FRONT + 1) * (int)sizeof(double));
+}
+
+hipError_t launch_front_small(const NodeDesc* nodes, const int* ids, int count, int max_n,
+                              double* tree, const int2* maps, int* status, hipStream_t st) {
+  const size_t lds = (size_t)max_n * (max_n + 1) * sizeof(double);
+  hipLaunchKernelGGL(front_small_kernel, dim3(count), dim3(NT), lds, st, nodes, ids, tree, maps,
+                     status);
+  return hipGetLastError();
+}
+
+hipError_t launch_front_gather(const NodeDesc* nodes, const int2* items, int count, double* tree,
+                               const int2* maps, hipStream_t st) {
+  hipLaunchKernelGGL(front_gather_kernel, dim3(count), dim3(NT), 0, st, nodes, items, tree, maps);
+  return hipGetLastError();
+}
+
+hipError_t launch_front_panel(const NodeDesc* nodes, const PanelItem* items, int count, int k0,
+                              double* tree, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(front_panel_kernel, dim3(count), dim3(NT), 0, st, nodes, items, k0, tree,
+                     status);
+  return hipGetLastError();
+}
+
+hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count, int k0,
+                               double* tree, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(front_update_kernel, dim3(count), dim3(NT), 0, st, nodes, items, k0, tree,
+                     status);
+  return hipGetLastError();
+}
+
+hipError_t launch_front_back(const NodeDesc* nodes, const int* ids, int count, const double* tree,
+                             const int* dofs, double* x, hipStream_t st) {
+  // callers guarantee s <= 2048 (16 KiB of LDS)
+  hipLaunchKernelGGL(front_back_kernel, dim3(count), dim3(NT), 2048 * sizeof(double), st, nodes,
+                     ids, tree, dofs, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_iface_residual(const Geo& g, const double* blocks, const double* x,
+                                 double* out2, hipStream_t st) {
+  hipLaunchKernelGGL(iface_residual_kernel, dim3(1), dim3(NT), 0, st, g, blocks, x, out2);
+  return hipGetLastError();
+}
+
+}  // namespace mrcm

@@ -1,0 +1,634 @@
+// Per-subdomain kernels of the MRCM Darcy solve (gfx950).
+//
+//  * local_basis_kernel: one work-group per subdomain assembles the local
+//    Robin problem (paper, section 3, eq. (mrc1) with the Robin parameter of
+//    eq. (beta)) from the current mobility, factors it and solves it for the
+//    particular solution and one basis function per interface dof (the
+//    multiscale basis of section 3), then projects the traces of every
+//    column on the interface functions, which gives the subdomain's block of
+//    the interface system (eq. (mrc2)).
+//  * stitch_kernel: composes the cell pressure from the basis functions and
+//    the interface solution, averages the two one-sided Robin fluxes on the
+//    skeleton and re-solves each subdomain with that flux as Neumann data
+//    (the flux downscaling step the paper cites for continuous interface
+//    fluxes), writes the fine fluxes and the per-cell mass balance.
+//
+// Local matrix: cell-centred two-point scheme in the natural row-major
+// ordering of the subdomain, i.e. block tridiagonal with M x M blocks:
+// tridiagonal diagonal blocks D_j (couplings along x inside row j) and
+// diagonal off-diagonal blocks C_j (couplings along y between rows j and
+// j+1).  It is solved by block elimination along the rows with explicit
+// inverses of the Schur-complemented diagonal blocks:
+//     S_0 = D_0,  S_j = D_j - C_{j-1} S_{j-1}^{-1} C_{j-1},
+//     Z_j = S_j^{-1} (B_j - C_{j-1} Z_{j-1}),
+//     X_{M-1} = Z_{M-1},  X_j = Z_j - S_j^{-1} C_j X_{j+1}.
+// Because C_j is diagonal, the Schur update is an element-wise scaling and
+// every other step is a small dense product.  The inverses come from
+// Gauss-Jordan sweeps on the symmetric positive definite S_j (no pivoting
+// needed); each thread keeps one element of S_j in a register and only the
+// pivot row and column go through LDS.
+#include "mrcm_internal.h"
+
+#include <math.h>
+
+namespace mrcm {
+
+namespace {
+
+constexpr int NT = 256;
+
+__device__ inline double series2(double a, double b) { return 1.0 / (1.0 / a + 1.0 / b); }
+
+struct SideGeo {
+  double flen, dist, H;
+};
+
+__device__ inline SideGeo side_geo(const Geo& g, int side) {
+  SideGeo s;
+  if (side < 2) {
+    s.flen = g.hy; s.dist = 0.5 * g.hx; s.H = g.M * g.hy;
+  } else {
+    s.flen = g.hx; s.dist = 0.5 * g.hy; s.H = g.M * g.hx;
+  }
+  return s;
+}
+
+// interface on side (W,E,S,N) of subdomain (I,J), -1 on the domain boundary
+__device__ inline int side_iface(const Geo& g, int I, int J, int side) {
+  switch (side) {
+    case 0: return I > 0 ? J * (g.SX - 1) + I - 1 : -1;
+    case 1: return I < g.SX - 1 ? J * (g.SX - 1) + I : -1;
+    case 2: return J > 0 ? g.nV + (J - 1) * g.SX + I : -1;
+    default: return J < g.SY - 1 ? g.nV + J * g.SX + I : -1;
+  }
+}
+
+// n . n_i: +1 where the subdomain is the lower-index side (E and N sides)
+__device__ inline double side_sigma(int side) { return (side == 1 || side == 3) ? 1.0 : -1.0; }
+
+// local cell index of face t on a side
+template <int M>
+__device__ inline int side_cell(int side, int t) {
+  switch (side) {
+    case 0: return t * M;
+    case 1: return t * M + (M - 1);
+    case 2: return t;
+    default: return (M - 1) * M + t;
+  }
+}
+
+// Assemble one cell of the local two-point system: diagonal, coupling to the
+// +x neighbour (ex) and to the +y neighbour (cy), and the cell's row of the
+// right-hand sides.  robin != 0: skeleton faces carry the Robin law (the
+// basis-function problems); robin == 0: skeleton faces carry the prescribed
+// outflow Fout[side][t] (the stitch re-solve).
+template <int M, int R>
+__device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const double* kap,
+                              double* dg, double* ex, double* cy, double* xrow, int robin,
+                              const double (*Fout)[M]) {
+  const Geo& g = a.g;
+  const int li = l % M, lj = l / M;
+  const int i = I * M + li, j = J * M + lj;
+  const size_t c = (size_t)j * g.nx + i;
+  const double kc = kap[l];
+  const double txc = kc * g.hy / (0.5 * g.hx);
+  const double tyc = kc * g.hx / (0.5 * g.hy);
+  double diag = 0.0, cx = 0.0, cn = 0.0;
+  for (int q = 0; q < R; ++q) xrow[q] = 0.0;
+  double rhs0 = 0.0;
+  if (a.src) rhs0 += a.src[c] * g.hx * g.hy;
+  // face loop: side 0 W, 1 E, 2 S, 3 N
+  for (int side = 0; side < 4; ++side) {
+    const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
+    if (inner) {
+      int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
+      double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
+      double T = series2(side < 2 ? txc : tyc, tn);
+      diag += T;
+      if (side == 1) cx = -T;
+      if (side == 3) cn = -T;
+      continue;
+    }
+    const int e = side_iface(g, I, J, side);
+    const int t = (side < 2) ? lj : li;
+    const double th = (side < 2) ? txc : tyc;
+    if (e < 0) {  // physical boundary
+      const double flen = (side < 2) ? g.hy : g.hx;
+      const double v = a.bcv[side][(side < 2) ? j : i];
+      if (g.kind[side] == 1) {
+        diag += th;
+        rhs0 += th * v;
+      } else {
+        rhs0 -= v * flen;
+      }
+      continue;
+    }
+    if (robin) {
+      SideGeo sg = side_geo(g, side);
+      const double al = a.alpha[e];
+      const double TR = sg.flen * kc / (sg.dist + al * sg.H);
+      const double beta = al * sg.H / kc;
+      const double sig = side_sigma(side);
+      diag += TR;
+      const int D = g.D;
+      const double* bs = a.basis + (size_t)e * D * M;
+      for (int k = 0; k < D; ++k) {
+        double gv = bs[k * M + t];
+        if (k >= g.nP) gv = -beta * sig * gv;
+        xrow[1 + side * D + k] += TR * gv;
+      }
+    } else {
+      rhs0 -= Fout[side][t];
+    }
+  }
+  dg[l] = diag;
+  ex[l] = cx;
+  cy[l] = cn;
+  xrow[0] += rhs0;
+}
+
+// Block elimination of the local system for NR right-hand sides held in
+// Xs[MM][NR]; leaves the solution in Xs and the inverse Schur blocks in
+// Sinv[M][MM].  Requires M*M <= blockDim.x.
+template <int M, int NR>
+__device__ void thomas_solve(double* Xs, double* Sinv, const double* dg, const double* ex,
+                             const double* cy, double* pivbuf /*[2][2][M]*/, int* status,
+                             int flag) {
+  constexpr int MM = M * M;
+  constexpr int NQ = (M * NR + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  const bool own = tid < MM;
+  const int ta = tid / M, tb = tid % M;
+  double s = 0.0;
+  int par = 0;
+  bool bad = false;
+  double acc[NQ];
+  for (int j = 0; j < M; ++j) {
+    if (own) {
+      double dv = (ta == tb) ? dg[j * M + ta]
+                : (tb == ta + 1) ? ex[j * M + ta]
+                : (ta == tb + 1) ? ex[j * M + tb] : 0.0;
+      if (j > 0) dv -= cy[(j - 1) * M + ta] * s * cy[(j - 1) * M + tb];
+      s = dv;
+    }
+    for (int k = 0; k < M; ++k) {
+      if (own && tb == k) pivbuf[(par * 2 + 0) * M + ta] = s;
+      if (own && ta == k) pivbuf[(par * 2 + 1) * M + tb] = s;
+      __syncthreads();
+      if (own) {
+        const double p = pivbuf[(par * 2 + 1) * M + k];
+        if (!(p > 0.0)) bad = true;
+        const double ip = 1.0 / p;
+        const double sak = pivbuf[(par * 2 + 0) * M + ta];
+        const double skb = pivbuf[(par * 2 + 1) * M + tb];
+        if (ta == k && tb == k) s = ip;
+        else if (ta == k) s = s * ip;
+        else if (tb == k) s = -sak * ip;
+        else s = s - sak * skb * ip;
+      }
+      par ^= 1;
+    }
+    if (own) Sinv[j * MM + tid] = s;
+    __syncthreads();
+    // Z_j = S_j^{-1} (B_j - C_{j-1} Z_{j-1})
+    {
+      int q = 0;
+      for (int o = tid; o < M * NR; o += NT, ++q) {
+        const int ra = o / NR, col = o % NR;
+        double sum = 0.0;
+        for (int b = 0; b < M; ++b) {
+          double r = Xs[(j * M + b) * NR + col];
+          if (j > 0) r -= cy[(j - 1) * M + b] * Xs[((j - 1) * M + b) * NR + col];
+          sum += Sinv[j * MM + ra * M + b] * r;
+        }
+        acc[q] = sum;
+      }
+      __syncthreads();
+      q = 0;
+      for (int o = tid; o < M * NR; o += NT, ++q) {
+        const int ra = o / NR, col = o % NR;
+        Xs[(j * M + ra) * NR + col] = acc[q];
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = M - 2; j >= 0; --j) {
+    int q = 0;
+    for (int o = tid; o < M * NR; o += NT, ++q) {
+      const int ra = o / NR, col = o % NR;
+      double sum = Xs[(j * M + ra) * NR + col];
+      for (int b = 0; b < M; ++b)
+        sum -= Sinv[j * MM + ra * M + b] * cy[j * M + b] * Xs[((j + 1) * M + b) * NR + col];
+      acc[q] = sum;
+    }
+    q = 0;
+    for (int o = tid; o < M * NR; o += NT, ++q) {
+      const int ra = o / NR, col = o % NR;
+      Xs[(j * M + ra) * NR + col] = acc[q];
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(status, flag);
+}
+
+// Solve again with the inverse Schur blocks already in Sinv (no factoring):
+// the forward and backward block sweeps of thomas_solve on NR new columns.
+template <int M, int NR>
+__device__ void thomas_resolve(double* Xs, const double* Sinv, const double* cy) {
+  constexpr int MM = M * M;
+  constexpr int NQ = (M * NR + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  double acc[NQ];
+  __syncthreads();
+  for (int j = 0; j < M; ++j) {
+    int q = 0;
+    for (int o = tid; o < M * NR; o += NT, ++q) {
+      const int ra = o / NR, col = o % NR;
+      double sum = 0.0;
+      for (int b = 0; b < M; ++b) {
+        double r = Xs[(j * M + b) * NR + col];
+        if (j > 0) r -= cy[(j - 1) * M + b] * Xs[((j - 1) * M + b) * NR + col];
+        sum += Sinv[j * MM + ra * M + b] * r;
+      }
+      acc[q] = sum;
+    }
+    __syncthreads();
+    q = 0;
+    for (int o = tid; o < M * NR; o += NT, ++q) {
+      const int ra = o / NR, col = o % NR;
+      Xs[(j * M + ra) * NR + col] = acc[q];
+    }
+    __syncthreads();
+  }
+  for (int j = M - 2; j >= 0; --j) {
+    int q = 0;
+    for (int o = tid; o < M * NR; o += NT, ++q) {
+      const int ra = o / NR, col = o % NR;
+      double sum = Xs[(j * M + ra) * NR + col];
+      for (int b = 0; b < M; ++b)
+        sum -= Sinv[j * MM + ra * M + b] * cy[j * M + b] * Xs[((j + 1) * M + b) * NR + col];
+      acc[q] = sum;
+    }
+    q = 0;
+    for (int o = tid; o < M * NR; o += NT, ++q) {
+      const int ra = o / NR, col = o % NR;
+      Xs[(j * M + ra) * NR + col] = acc[q];
+    }
+    __syncthreads();
+  }
+}
+
+// r = b - A x for the local five-point matrix (diagonal dg, +x coupling ex,
+// +y coupling cy), NR columns.
+template <int M, int NR>
+__device__ void local_residual(const double* b, const double* x, double* r, const double* dg,
+                               const double* ex, const double* cy) {
+  for (int o = threadIdx.x; o < M * M * NR; o += NT) {
+    const int l = o / NR, col = o % NR;
+    const int li = l % M, lj = l / M;
+    double ax = dg[l] * x[o];
+    if (li < M - 1) ax += ex[l] * x[(l + 1) * NR + col];
+    if (li > 0) ax += ex[l - 1] * x[(l - 1) * NR + col];
+    if (lj < M - 1) ax += cy[l] * x[(l + M) * NR + col];
+    if (lj > 0) ax += cy[l - M] * x[(l - M) * NR + col];
+    r[o] = b[o] - ax;
+  }
+}
+
+template <int M>
+__device__ void load_kappa(const SubArgs& a, int I, int J, double* kap) {
+  const Geo& g = a.g;
+  for (int l = threadIdx.x; l < M * M; l += NT) {
+    const int li = l % M, lj = l / M;
+    const size_t c = (size_t)(J * M + lj) * g.nx + I * M + li;
+    const double lam = a.lam[c];
+    if (!(lam > 0.0) || !isfinite(lam)) atomicOr(a.status, ST_BAD_LAMBDA);
+    kap[l] = a.K[c] * lam;
+  }
+}
+
+template <int M, int D>
+__global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
+  constexpr int R = 1 + 4 * D;
+  constexpr int MM = M * M;
+  constexpr int NBR = 4 * D, NBC = 4 * D + 1;
+  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
+  __shared__ double Xs[MM * R];
+  __shared__ double Sinv[M * MM];
+  __shared__ double pivbuf[4 * M];
+  const Geo& g = a.g;
+  const int tid = threadIdx.x;
+  const int sd = blockIdx.x;
+  const int I = sd % g.SX, J = sd / g.SX;
+
+  load_kappa<M>(a, I, J, kap);
+  __syncthreads();
+  for (int l = tid; l < MM; l += NT)
+    assemble_cell<M, R>(a, I, J, l, kap, dg, ex, cy, Xs + l * R, 1, nullptr);
+  __syncthreads();
+
+  thomas_solve<M, R>(Xs, Sinv, dg, ex, cy, pivbuf, a.status, ST_LOCAL_PIVOT);
+
+  double* Xg = a.X + (size_t)sd * MM * R;
+  for (int o = tid; o < MM * R; o += NT) Xg[o] = Xs[o];
+
+  // traces and projection: this subdomain's block of the interface system
+  double* blk = a.blocks + (size_t)sd * NBR * NBC;
+  const int nP = g.nP;
+  int e0side = -1;      // side holding global dof 0 (gauge), if any
+  bool e0lo = false;
+  if (g.gauge) {
+    for (int side = 0; side < 4; ++side)
+      if (side_iface(g, I, J, side) == 0) { e0side = side; e0lo = side_sigma(side) > 0; }
+  }
+  for (int o = tid; o < NBR * NBC; o += NT) {
+    const int r = o / NBC, qc = o % NBC;
+    const int side = r / D, k = r % D;
+    const int e = side_iface(g, I, J, side);
+    double val = 0.0;
+    if (e >= 0) {
+      const int col = (qc < NBR) ? 1 + qc : 0;
+      const SideGeo sg = side_geo(g, side);
+      const double al = a.alpha[e];
+      const double sig = side_sigma(side);
+      const double* bs = a.basis + (size_t)e * D * M;
+      const bool colside = col >= 1 + side * D && col < 1 + side * D + D;
+      const int kc = col - 1 - side * D;
+      double sum = 0.0;
+      for (int t = 0; t < M; ++t) {
+        const int l = side_cell<M>(side, t);
+        const double kk = kap[l];
+        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
+        const double beta = al * sg.H / kk;
+        double gv = 0.0;
+        if (colside) gv = (kc < nP) ? bs[kc * M + t] : -beta * sig * bs[kc * M + t];
+        const double F = TR * (Xs[l * R + col] - gv);
+        if (k < nP) sum += bs[k * M + t] * F;
+        else sum += bs[k * M + t] * (gv + beta * F / sg.flen);
+      }
+      const double natural = (k < nP) ? sum : sig * sg.flen * sum;
+      const double sgn = (k < nP) ? 1.0 : -1.0;
+      val = (qc < NBR) ? sgn * natural : -sgn * natural;
+      if (e0side >= 0) {
+        const int r0 = e0side * D;   // local position of global dof 0
+        if (r == r0) val = (qc == r0 && e0lo) ? 1.0 : 0.0;
+        else if (qc == r0) val = 0.0;
+      }
+    }
+    blk[o] = val;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stitch re-solve, composition and fine fluxes
+// ---------------------------------------------------------------------------
+
+template <int M, int D>
+__device__ double compose_at(const SubArgs& a, int sd, int l) {
+  // p at local cell l of subdomain sd = X[sd][l] . [1; coefficients]
+  constexpr int R = 1 + 4 * D;
+  const Geo& g = a.g;
+  const int I = sd % g.SX, J = sd / g.SX;
+  const double* xr = a.X + ((size_t)sd * M * M + l) * R;
+  double p = xr[0];
+  for (int side = 0; side < 4; ++side) {
+    const int e = side_iface(g, I, J, side);
+    if (e < 0) continue;
+    for (int k = 0; k < D; ++k) p += xr[1 + side * D + k] * a.coef[(size_t)e * D + k];
+  }
+  return p;
+}
+
+template <int M, int D>
+__global__ void __launch_bounds__(NT) stitch_kernel(SubArgs a) {
+  constexpr int MM = M * M;
+  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
+  __shared__ double pm[MM];          // composed multiscale pressure
+  __shared__ double Xs[MM];          // stitch right-hand side / pressure
+  __shared__ double Bs[MM];          // saved right-hand side
+  __shared__ double Rs[MM];          // residual / correction
+  __shared__ double Sinv[M * MM];
+  __shared__ double pivbuf[4 * M];
+  __shared__ double Fout[4][M];      // outflow of this subdomain on its skeleton faces
+  __shared__ double red[3][NT];
+  const Geo& g = a.g;
+  const int tid = threadIdx.x;
+  const int sd = blockIdx.x;
+  const int I = sd % g.SX, J = sd / g.SX;
+  const int nP = g.nP;
+
+  load_kappa<M>(a, I, J, kap);
+  for (int l = tid; l < MM; l += NT) pm[l] = compose_at<M, D>(a, sd, l);
+  __syncthreads();
+
+  // one-sided Robin fluxes on both sides of every skeleton face of this
+  // subdomain, and their average
+  for (int o = tid; o < 4 * M; o += NT) {
+    const int side = o / M, t = o % M;
+    const int e = side_iface(g, I, J, side);
+    double fo = 0.0;
+    if (e >= 0) {
+      const SideGeo sg = side_geo(g, side);
+      const double al = a.alpha[e];
+      const double* bs = a.basis + (size_t)e * D * M;
+      const double* ce = a.coef + (size_t)e * D;
+      double PH = 0.0, UH = 0.0;
+      for (int k = 0; k < nP; ++k) PH += ce[k] * bs[k * M + t];
+      for (int k = nP; k < D; ++k) UH += ce[k] * bs[k * M + t];
+      const int l = side_cell<M>(side, t);
+      const double sig = side_sigma(side);
+      const double ko = kap[l];
+      const double Fown = sg.flen * ko / (sg.dist + al * sg.H) *
+                          (pm[l] - (PH - al * sg.H / ko * sig * UH));
+      // neighbour across the face
+      const int nside = side ^ 1;
+      const int nsd = (side == 0) ? sd - 1 : (side == 1) ? sd + 1 : (side == 2) ? sd - g.SX : sd + g.SX;
+      const int nI = nsd % g.SX, nJ = nsd / g.SX;
+      const int nl = side_cell<M>(nside, t);
+      const size_t nc = (size_t)(nJ * M + nl / M) * g.nx + nI * M + nl % M;
+      const double kn = a.K[nc] * a.lam[nc];
+      const double pn = compose_at<M, D>(a, nsd, nl);
+      const double Fnb = sg.flen * kn / (sg.dist + al * sg.H) *
+                         (pn - (PH - al * sg.H / kn * (-sig) * UH));
+      fo = 0.5 * (Fown - Fnb);
+    }
+    Fout[side][t] = fo;
+  }
+  __syncthreads();
+  for (int l = tid; l < MM; l += NT)
+    assemble_cell<M, 1>(a, I, J, l, kap, dg, ex, cy, Xs + l, 0, Fout);
+  __syncthreads();
+  // a subdomain with no Dirichlet face has a Neumann problem defined up to a
+  // constant: fix it at cell 0 to the composed multiscale pressure
+  const bool dir = (I == 0 && g.kind[0] == 1) || (I == g.SX - 1 && g.kind[1] == 1) ||
+                   (J == 0 && g.kind[2] == 1) || (J == g.SY - 1 && g.kind[3] == 1);
+  if (!dir && tid == 0) {
+    const double tp = dg[0];
+    dg[0] += tp;
+    Xs[0] += tp * pm[0];
+  }
+  __syncthreads();
+  for (int l = tid; l < MM; l += NT) Bs[l] = Xs[l];
+  thomas_solve<M, 1>(Xs, Sinv, dg, ex, cy, pivbuf, a.status, ST_STITCH_PIVOT);
+  // two steps of FP64 iterative refinement with the stored inverse blocks
+  for (int it = 0; it < 2; ++it) {
+    local_residual<M, 1>(Bs, Xs, Rs, dg, ex, cy);
+    thomas_resolve<M, 1>(Rs, Sinv, cy);
+    for (int l = tid; l < MM; l += NT) Xs[l] += Rs[l];
+    __syncthreads();
+  }
+
+  // fine fluxes (+x / +y) from the stitched pressure; skeleton faces carry
+  // the averaged flux.  Each subdomain writes the W and S faces of its cells
+  // (and the E / N boundary faces of the last column / row).
+  double imb = 0.0, fmx = 0.0, psum = 0.0;
+  for (int l = tid; l < MM; l += NT) {
+    const int li = l % M, lj = l / M;
+    const int i = I * M + li, j = J * M + lj;
+    const double kc = kap[l];
+    const double txc = kc * g.hy / (0.5 * g.hx), tyc = kc * g.hx / (0.5 * g.hy);
+    const double ps = Xs[l];
+    double F[4];  // W, E, S, N in +x / +y direction
+    for (int side = 0; side < 4; ++side) {
+      const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
+      double f;
+      if (inner) {
+        const int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
+        const double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
+        const double T = series2(side < 2 ? txc : tyc, tn);
+        const double out = T * (ps - Xs[nb]);
+        f = (side == 0 || side == 2) ? -out : out;
+      } else {
+        const int e = side_iface(g, I, J, side);
+        const int t = (side < 2) ? lj : li;
+        double out;
+        if (e >= 0) {
+          out = Fout[side][t];
+        } else {
+          const double flen = (side < 2) ? g.hy : g.hx;
+          const double v = a.bcv[side][(side < 2) ? j : i];
+          out = (g.kind[side] == 1) ? ((side < 2) ? txc : tyc) * (ps - v) : v * flen;
+        }
+        f = (side == 0 || side == 2) ? -out : out;
+      }
+      F[side] = f;
+    }
+    a.ux[(size_t)j * (g.nx + 1) + i] = F[0] / g.hy;
+    if (li == M - 1 && I == g.SX - 1) a.ux[(size_t)j * (g.nx + 1) + i + 1] = F[1] / g.hy;
+    a.uy[(size_t)j * g.nx + i] = F[2] / g.hx;
+    if (lj == M - 1 && J == g.SY - 1) a.uy[(size_t)(j + 1) * g.nx + i] = F[3] / g.hx;
+    double q = a.src ? a.src[(size_t)j * g.nx + i] * g.hx * g.hy : 0.0;
+    const double net = F[1] - F[0] + F[3] - F[2];
+    imb = fmax(imb, fabs(net - q));
+    fmx = fmax(fmx, fmax(fmax(fabs(F[0]), fabs(F[1])), fmax(fabs(F[2]), fabs(F[3]))));
+    a.p_out[(size_t)j * g.nx + i] = pm[l];
+    psum += pm[l];
+  }
+  red[0][tid] = imb;
+  red[1][tid] = fmx;
+  red[2][tid] = psum;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[0][tid] = fmax(red[0][tid], red[0][tid + w]);
+      red[1][tid] = fmax(red[1][tid], red[1][tid + w]);
+      red[2][tid] = red[2][tid] + red[2][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.sub_stats[3 * sd + 0] = red[0][0];
+    a.sub_stats[3 * sd + 1] = red[1][0];
+    a.sub_stats[3 * sd + 2] = red[2][0];
+  }
+}
+
+// max imbalance, max |F| and the pressure mean over subdomains (fixed order,
+// so the result does not depend on scheduling), then the zero-mean shift of
+// the pressure when the problem has no Dirichlet side.
+__global__ void __launch_bounds__(NT) finish_reduce_kernel(SubArgs a, double* result) {
+  __shared__ double red[3][NT];
+  const int tid = threadIdx.x;
+  double imb = 0.0, fmx = 0.0, ps = 0.0;
+  for (int s = tid; s < a.g.n_sub; s += NT) {
+    imb = fmax(imb, a.sub_stats[3 * s]);
+    fmx = fmax(fmx, a.sub_stats[3 * s + 1]);
+    ps += a.sub_stats[3 * s + 2];
+  }
+  red[0][tid] = imb; red[1][tid] = fmx; red[2][tid] = ps;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[0][tid] = fmax(red[0][tid], red[0][tid + w]);
+      red[1][tid] = fmax(red[1][tid], red[1][tid + w]);
+      red[2][tid] += red[2][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    result[0] = red[0][0] / fmax(red[1][0], 1e-300);
+    result[1] = red[2][0] / ((double)a.g.nx * a.g.ny);
+  }
+}
+
+__global__ void shift_kernel(double* p, size_t n, const double* mean) {
+  const double m = *mean;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] -= m;
+}
+
+__global__ void mobility_kernel(const double* in, double* lam, size_t n, int from_s, double mw,
+                                double mo) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double v = in[i];
+    lam[i] = from_s ? v * v / mw + (1.0 - v) * (1.0 - v) / mo : v;
+  }
+}
+
+template <int M, int D>
+hipError_t launch_pair(const SubArgs& a, hipStream_t st, bool stitch) {
+  if (stitch)
+    hipLaunchKernelGGL((stitch_kernel<M, D>), dim3(a.g.n_sub), dim3(NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((local_basis_kernel<M, D>), dim3(a.g.n_sub), dim3(NT), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t dispatch(const SubArgs& a, hipStream_t st, bool stitch) {
+  const int M = a.g.M, D = a.g.D;
+  if (M == 16 && D == 4) return launch_pair<16, 4>(a, st, stitch);
+  if (M == 8 && D == 4) return launch_pair<8, 4>(a, st, stitch);
+  if (M == 4 && D == 4) return launch_pair<4, 4>(a, st, stitch);
+  if (M == 8 && D == 16) return launch_pair<8, 16>(a, st, stitch);
+  if (M == 4 && D == 8) return launch_pair<4, 8>(a, st, stitch);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool local_supported(int M, int D) {
+  return (M == 16 && D == 4) || (M == 8 && D == 4) || (M == 4 && D == 4) || (M == 8 && D == 16) ||
+         (M == 4 && D == 8);
+}
+
+hipError_t launch_local_basis(const SubArgs& a, hipStream_t st) { return dispatch(a, st, false); }
+
+hipError_t launch_stitch(const SubArgs& a, hipStream_t st) { return dispatch(a, st, true); }
+
+hipError_t launch_finish_flux(const SubArgs& a, double* result, hipStream_t st) {
+  hipLaunchKernelGGL(finish_reduce_kernel, dim3(1), dim3(NT), 0, st, a, result);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !a.g.gauge) return e;
+  const size_t n = (size_t)a.g.nx * a.g.ny;
+  hipLaunchKernelGGL(shift_kernel, dim3(1024), dim3(256), 0, st, a.p_out, n, result + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_mobility(const double* in, double* lam, size_t n, int from_saturation,
+                           double mu_w, double mu_o, hipStream_t st) {
+  hipLaunchKernelGGL(mobility_kernel, dim3(1024), dim3(256), 0, st, in, lam, n, from_saturation,
+                     mu_w, mu_o);
+  return hipGetLastError();
+}
+
+}  // namespace mrcm

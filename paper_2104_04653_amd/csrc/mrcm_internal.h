@@ -1,0 +1,96 @@
+// Internal declarations of the MRCM library: device argument blocks, tree
+// node descriptors and kernel launchers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrcm {
+
+// status bits raised by kernels (device int, read back after a solve)
+enum : int {
+  ST_BAD_LAMBDA = 1,    // a mobility was not finite and positive
+  ST_LOCAL_PIVOT = 2,   // a Gauss-Jordan pivot of a local Schur block was not positive
+  ST_IFACE_PIVOT = 4,   // a pivot of the interface elimination was zero or not finite
+  ST_STITCH_PIVOT = 8,  // a pivot of the stitch re-solve was not positive
+};
+
+// Problem geometry shared by the per-subdomain kernels.
+struct Geo {
+  int nx, ny;       // cells
+  int M;            // subdomain edge in cells (square subdomains)
+  int SX, SY;       // subdomains per direction
+  int nV;           // number of vertical interfaces
+  int n_sub;
+  int nP, nU, D;    // interface dofs per interface (D = nP + nU)
+  int kind[4];      // boundary kind per side W E S N (1 = Dirichlet)
+  int gauge;        // 1: no Dirichlet side, first pressure dof pinned
+  double hx, hy;
+};
+
+// Device data of a context used by the subdomain kernels.
+struct SubArgs {
+  Geo g;
+  const double* K;        // nx*ny absolute permeability
+  const double* lam;      // nx*ny total mobility
+  const double* src;      // nx*ny source per unit area, or nullptr
+  const double* bcv[4];   // boundary values per side (ny, ny, nx, nx)
+  const double* alpha;    // per interface
+  const double* basis;    // [iface][D][M]: rows 0..nP-1 pressure, nP..D-1 flux functions
+  double* X;              // [sub][M*M][R] local solutions (R = 1 + 4D)
+  double* blocks;         // [sub][4D][4D+1] symmetric local interface blocks
+  const double* coef;     // interface solution (stitch kernel)
+  double* p_out;          // nx*ny composed pressure (stitch kernel)
+  double* ux;             // (nx+1)*ny
+  double* uy;             // nx*(ny+1)
+  double* sub_stats;      // [sub][3]: max cell imbalance, max |F|, sum of p
+  int* status;
+};
+
+// Frontal-matrix node of the nested-dissection elimination of the
+// interface system.  Front F is n x (n+1), row-major, last column = rhs;
+// the first s unknowns are eliminated at this node.
+struct NodeDesc {
+  long long f_off;      // offset of F in the tree buffer (doubles)
+  long long map_off;    // offset into the map array (n int2: child A index, child B index)
+  long long dof_off;    // offset into the dof array (n ints: global dof per position)
+  long long c_off[2];   // offset of each child's Schur block (top-left)
+  int n, s;
+  int c_ld[2];          // row stride of each child's Schur block
+  int c_rhs[2];         // rhs column of each child's Schur block (relative to c_off)
+};
+
+struct PanelItem {      // one work-group of a blocked elimination step
+  int node;             // index into the node descriptor array
+  int kind;             // 0: rows of L21, 1: columns of U12, 2: trailing tile, 3: diagonal block
+  int i0, j0;           // first row / column handled
+};
+
+// ---- launchers (local.hip) ----
+hipError_t launch_local_basis(const SubArgs& a, hipStream_t st);
+hipError_t launch_stitch(const SubArgs& a, hipStream_t st);
+hipError_t launch_mobility(const double* in, double* lam, size_t n, int from_saturation,
+                           double mu_w, double mu_o, hipStream_t st);
+hipError_t launch_finish_flux(const SubArgs& a, double* result, hipStream_t st);
+bool local_supported(int M, int D);
+
+// ---- launchers (interface.hip) ----
+hipError_t launch_front_small(const NodeDesc* nodes, const int* ids, int count, int max_n,
+                              double* tree, const int2* maps, int* status, hipStream_t st);
+hipError_t launch_front_gather(const NodeDesc* nodes, const int2* items, int count,
+                               double* tree, const int2* maps, hipStream_t st);
+hipError_t launch_front_panel(const NodeDesc* nodes, const PanelItem* items, int count, int k0,
+                              double* tree, int* status, hipStream_t st);
+hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count,
+                               int k0, double* tree, int* status, hipStream_t st);
+hipError_t launch_front_back(const NodeDesc* nodes, const int* ids, int count, const double* tree,
+                             const int* dofs, double* x, hipStream_t st);
+hipError_t launch_iface_residual(const Geo& g, const double* blocks, const double* x,
+                                 double* out2, hipStream_t st);
+hipError_t prepare_interface_kernels();
+
+constexpr int PANEL_NB = 32;      // panel width of the blocked elimination
+constexpr int TILE = 64;          // trailing-update tile
+constexpr int SMALL_FRONT = 128;  // fronts up to this size are eliminated in LDS
+
+}  // namespace mrcm

@@ -1,0 +1,177 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every case runs the same seeded inputs through both and compares element by
+element: local basis functions and interface blocks (steps a1-a5), the
+interface solution (a6-a7), the composed pressure and the stitched fluxes
+(a8-a9).  Floating-point tolerance: relative L2 1e-10 in pressure and flux
+(FP64 path); local basis functions per column and interface blocks at 1e-10.
+"""
+import numpy as np
+import pytest
+
+import inputs
+from oracle.discretization import total_mobility
+from oracle.fine import solve_fine
+from tests.gpu_util import (flux_floor, oracle_basis_padded, oracle_blocks_padded, rel,
+                            run_gpu, run_oracle, say)
+from tests.test_oracle_pins import box, linear_dirichlet
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def check_end_to_end(prob, s=None, lam=None, local=True, tol=TOL, label=""):
+    say("case:", label or prob.name, prob.nx, prob.ny, "sub", prob.sub_nx, "space", prob.space)
+    if s is not None:
+        lam = total_mobility(s, prob.mu_w, prob.mu_o)
+    g = run_gpu(prob, lam=lam, extras=local)
+    ref = run_oracle(prob, lam=lam)
+    ep = rel(g["p"], ref.p)
+    ef = rel(np.r_[g["ux"], g["uy"]], np.r_[ref.ux, ref.uy])
+    say("  rel L2: p %.2e  flux %.2e  imbalance gpu %.2e oracle %.2e  iface res %.2e"
+        % (ep, ef, g["imbalance"], ref.imbalance, g["stats"]["interface_residual"]))
+    assert ep < tol and ef < tol
+    floor = flux_floor(prob, lam, ref.p) / np.abs(np.r_[ref.Fx, ref.Fy]).max()
+    assert g["imbalance"] < max(1e-12, 64 * floor)
+    if local:
+        B = oracle_basis_padded(prob, ref)
+        X = g["basis"]
+        num = np.linalg.norm(X - B, axis=1)
+        den = np.maximum(np.linalg.norm(B, axis=1), 1e-300)
+        used = np.linalg.norm(B, axis=1) > 0
+        eb = float((num[used] / den[used]).max())
+        Bl = oracle_blocks_padded(prob, ref)
+        scale = np.abs(Bl).max(axis=(1, 2), keepdims=True)
+        ebl = float((np.abs(g["blocks"] - Bl) / scale).max())
+        ec = rel(g["coef"], ref.coeffs) if ref.coeffs.size else 0.0
+        say("  basis max col rel %.2e  blocks %.2e  interface coeffs %.2e" % (eb, ebl, ec))
+        assert eb < tol and ebl < tol and ec < tol
+    return g, ref
+
+
+def test_gauss64_single_phase():
+    check_end_to_end(inputs.make_problem("gauss64"))
+
+
+def test_gauss64_two_phase_saturation():
+    prob = inputs.make_problem("gauss64", seed=2)
+    check_end_to_end(prob, s=inputs.synthetic_saturation(prob, 3, 10))
+
+
+def test_sub8_rectangular_grid():
+    prob = inputs.make_problem("gauss64", nx=64, ny=40, ly=0.5, sub=8, alpha=0.3, seed=3)
+    check_end_to_end(prob)
+
+
+def test_channel_quarter_five_spot_small():
+    """All-Neumann boundary with wells: gauge path."""
+    prob = inputs.make_problem("channel256_q5", nx=64, ny=64)
+    check_end_to_end(prob, s=inputs.synthetic_saturation(prob, 5, 20))
+
+
+def test_channel_quarter_five_spot_256():
+    """The 256^2 channelized quarter-five-spot workload, one step."""
+    prob = inputs.make_problem("channel256_q5")
+    check_end_to_end(prob, s=inputs.synthetic_saturation(prob, 7, 20), local=False)
+
+
+def test_linear_pressure_exact_on_gpu():
+    """T-LIN through the GPU path."""
+    prob, exact = linear_dirichlet(32, 16, 8, 0.5, 2.0, -1.5, alpha=0.4)
+    say("case: linear pressure 32x16 sub 8")
+    g = run_gpu(prob, extras=False)
+    assert np.abs(g["p"] - exact).max() < 1e-12
+    assert np.allclose(g["ux"], -3.0 * 2.0, rtol=1e-11)
+    assert np.allclose(g["uy"], 3.0 * 1.5, rtol=1e-11)
+
+
+def test_full_spaces_recover_fine_on_gpu():
+    """T-FULL through the GPU path (4x4 subdomains, every fine-edge indicator)."""
+    prob = inputs.make_problem("gauss64", nx=32, ny=32, sub=4, space="full", alpha=2.0)
+    say("case: full spaces 32x32 sub 4")
+    g = run_gpu(prob, extras=False)
+    f = solve_fine(prob)
+    assert rel(g["p"], f["p"]) < 1e-10
+    assert rel(np.r_[g["ux"], g["uy"]], np.r_[f["ux"], f["uy"]]) < 1e-10
+
+
+def test_one_subdomain_is_fine_on_gpu():
+    """T-ONE through the GPU path: no skeleton, the local problem is the fine one."""
+    prob = inputs.make_problem("gauss64", nx=16, ny=16, sub=16)
+    say("case: one subdomain 16x16")
+    g = run_gpu(prob, extras=False)
+    f = solve_fine(prob)
+    assert rel(g["p"], f["p"]) < 1e-12
+    assert rel(np.r_[g["ux"], g["uy"]], np.r_[f["ux"], f["uy"]]) < 1e-11
+
+
+def test_gauss1024_full_size_step():
+    """The 1024^2 two-phase workload (4096 subdomains), one step, against the
+    full oracle solve."""
+    prob = inputs.make_problem("gauss1024")
+    check_end_to_end(prob, s=inputs.synthetic_saturation(prob, 3), local=False)
+
+
+def test_bad_mobility_rejected():
+    from paper_2104_04653_amd import MRCMSolver, MRCMError
+    from paper_2104_04653_amd.mrcm import E_INVAL, E_STATE
+    prob = inputs.make_problem("gauss64")
+    say("case: error paths")
+    with MRCMSolver(prob) as sol:
+        with pytest.raises(MRCMError) as ei:
+            sol.fine_flux()
+        assert ei.value.code == E_STATE
+        lam = np.ones(prob.nx * prob.ny)
+        lam[100] = np.nan
+        sol.update_mobility(lam, is_lambda=True)
+        with pytest.raises(MRCMError) as ei:
+            sol.solve()
+        assert ei.value.code == E_INVAL
+        lam[100] = -1.0
+        sol.update_mobility(lam, is_lambda=True)
+        with pytest.raises(MRCMError) as ei:
+            sol.solve()
+        assert ei.value.code == E_INVAL
+        # a good mobility afterwards works again
+        sol.update_mobility(np.ones(prob.nx * prob.ny), is_lambda=True)
+        sol.solve()
+        p, ux, uy, imb = sol.fine_flux()
+        assert np.isfinite(p).all() and imb < 1e-10
+
+
+def test_device_inputs_and_outputs():
+    """Mobility from a device tensor, outputs into device tensors."""
+    import torch
+    from paper_2104_04653_amd import MRCMSolver
+    prob = inputs.make_problem("gauss64", seed=4)
+    s = inputs.synthetic_saturation(prob, 1, 4)
+    say("case: device pointers")
+    ref = run_gpu(prob, s=s, extras=False)
+    with MRCMSolver(prob) as sol:
+        sol.update_mobility(torch.from_numpy(s).cuda())
+        sol.solve()
+        p, ux, uy, imb = sol.fine_flux(device=True)
+        torch.cuda.synchronize()
+    assert np.array_equal(p.cpu().numpy(), ref["p"])
+    assert np.array_equal(ux.cpu().numpy(), ref["ux"])
+    assert np.array_equal(uy.cpu().numpy(), ref["uy"])
+
+
+def test_repeat_solves_are_bitwise_identical():
+    """Deterministic gathers, no atomics in the arithmetic: two solves of the
+    same input give identical bits, and a different mobility in between does
+    not leak into the next step."""
+    from paper_2104_04653_amd import MRCMSolver
+    prob = inputs.make_problem("channel256_q5", nx=64, ny=64)
+    s1 = inputs.synthetic_saturation(prob, 2, 10)
+    s2 = inputs.synthetic_saturation(prob, 6, 10)
+    say("case: repeat solves")
+    with MRCMSolver(prob) as sol:
+        outs = []
+        for s in (s1, s2, s1):
+            sol.update_mobility(s)
+            sol.solve()
+            outs.append(sol.fine_flux())
+    for a, b in zip(outs[0][:3], outs[2][:3]):
+        assert np.array_equal(a, b)

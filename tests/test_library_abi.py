@@ -1,0 +1,80 @@
+"""The C-ABI library loads and exports every entry point include/mrcm.h
+declares (CPU only: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mrcm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mrcm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_call_set():
+    names = declared_symbols()
+    for required in ("mrcm_setup", "mrcm_update_mobility", "mrcm_solve", "mrcm_fine_flux",
+                     "mrcm_destroy", "mrcm_last_error", "mrcm_get_stats"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2104_04653_amd import mrcm as binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libmrcm.so not built")
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(binding.EXPORTED) <= set(declared_symbols())
+
+
+def test_null_arguments_rejected_without_gpu():
+    """Argument validation happens before any device call."""
+    from paper_2104_04653_amd import mrcm as binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libmrcm.so not built")
+    lib = binding.load_library()
+    ctx = ctypes.c_void_p()
+    rc = lib.mrcm_setup(ctypes.byref(ctx), None, None, 16, 16, 0, 2, 2, None, 1.0, None, None,
+                        None, 0, None)
+    assert rc == binding.E_INVAL
+    assert lib.mrcm_solve(None) == binding.E_INVAL
+    assert lib.mrcm_fine_flux(None, None, None, None, 0, None) == binding.E_INVAL
+    lib.mrcm_destroy(None)
+
+
+def test_bad_sizes_rejected_without_gpu():
+    from paper_2104_04653_amd import mrcm as binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libmrcm.so not built")
+    import numpy as np
+    lib = binding.load_library()
+    grid = binding.Grid(60, 64, 1.0, 1.0)    # 60 is not a multiple of 16
+    perm = np.ones(60 * 64)
+    bc = binding.BC()
+    for s in range(4):
+        bc.kind[s] = 0
+    fl = binding.Fluid(1.0, 10.0)
+    ctx = ctypes.c_void_p()
+    dp = perm.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rc = lib.mrcm_setup(ctypes.byref(ctx), ctypes.byref(grid), dp, 16, 16, 0, 2, 2, None, 1.0,
+                        ctypes.byref(bc), None, ctypes.byref(fl), 0, None)
+    assert rc == binding.E_INVAL
+    grid = binding.Grid(64, 64, 1.0, 1.0)
+    perm = np.ones(64 * 64)
+    perm[5] = -1.0
+    dp = perm.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rc = lib.mrcm_setup(ctypes.byref(ctx), ctypes.byref(grid), dp, 16, 16, 0, 2, 2, None, 1.0,
+                        ctypes.byref(bc), None, ctypes.byref(fl), 0, None)
+    assert rc == binding.E_INVAL
+    perm[5] = 1.0
+    rc = lib.mrcm_setup(ctypes.byref(ctx), ctypes.byref(grid), dp, 16, 16, 0, 3, 2, None, 1.0,
+                        ctypes.byref(bc), None, ctypes.byref(fl), 0, None)
+    assert rc == binding.E_INVAL            # linear spaces have 2 + 2 dofs
+    rc = lib.mrcm_setup(ctypes.byref(ctx), ctypes.byref(grid), dp, 16, 16, 0, 2, 2, None, -1.0,
+                        ctypes.byref(bc), None, ctypes.byref(fl), 0, None)
+    assert rc == binding.E_INVAL            # alpha must be positive
