@@ -129,10 +129,11 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
 /* Set the total mobility used by the next mrcm_solve: kappa = lambda K
  * (section 3).  values: nx*ny saturations in [0,1] (values_are_lambda = 0;
  * lambda is evaluated on the GPU with eq. (fluxos1)) or mobilities > 0
- * (values_are_lambda = 1).  on_device = 1: values is a device pointer that
- * must stay valid until this call returns (it is consumed on the context's
- * stream before return of the next solve; the library copies it).
- * on_device = 0: host array, copied before return.  Values are validated on
+ * (values_are_lambda = 1).  on_device = 1: values is a device pointer read
+ * by a kernel on the context's stream; it must stay valid and unchanged
+ * until the next mrcm_solve returns (work that produced it on another
+ * stream must be complete).  on_device = 0: host array, copied before
+ * return.  Values are validated on
  * the GPU during the next solve: a non-finite or non-positive lambda makes
  * that solve fail with MRCM_E_INVAL. */
 int mrcm_update_mobility(mrcm_ctx* ctx, const double* values, int32_t values_are_lambda,
@@ -176,9 +177,10 @@ int mrcm_get_sizes(const mrcm_ctx* ctx, int32_t* n_dof, int32_t* n_sub, int32_t*
  *     zero for sides on the domain boundary); column R-1 holds the
  *     right-hand side.  Rows of flux (U) dofs are the negated
  *     pressure-continuity equations, which makes every block symmetric.
- *  mrcm_get_basis : n_sub * sub_nx*sub_ny * R values: for subdomain sd and
- *     local cell l = ly*sub_nx + lx, column 0 = particular solution,
- *     column 1 + side*(nP+nU) + k = basis function of that dof.
+ *  mrcm_get_basis : n_sub * R * sub_nx*sub_ny values, column-major per
+ *     subdomain: [sd][col][l] with local cell l = ly*sub_nx + lx; column 0
+ *     is the particular solution, column 1 + side*(nP+nU) + k the basis
+ *     function of that dof.
  * MRCM_E_STATE before the first successful solve. */
 int mrcm_get_interface_solution(mrcm_ctx* ctx, double* coeffs);
 int mrcm_get_local_blocks(mrcm_ctx* ctx, double* blocks);

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrcm.so")
-SOURCES = ["api.hip", "local.hip", "interface.hip"]
+SOURCES = ["api.hip", "local.hip", "local_mfma.hip", "interface.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -21,6 +21,9 @@ FLAGS = [
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # the one-wavefront kernels keep their tiles in registers only when their
+    # block loops are fully unrolled
+    "-mllvm", "-pragma-unroll-threshold=60000",
 ]
 
 

@@ -7,6 +7,7 @@
 
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -21,8 +22,8 @@ namespace {
 
 struct PanelLaunch {
   int k0;
-  int panel_off, panel_count;
-  int update_off, update_count;
+  int diag_off, diag_count;     // fronts with a panel at k0 (into the id array)
+  int update_off, update_count; // trailing tiles (into the item array)
 };
 
 struct LevelPlan {
@@ -61,6 +62,8 @@ struct mrcm_ctx {
   int* d_ids = nullptr;
   int2* d_gather = nullptr;
   PanelItem* d_items = nullptr;
+  double* inv = nullptr;        // per-panel triangular inverses of blocked fronts
+  double* partials = nullptr;   // residual partial maxima
   std::vector<void*> allocs;
 
   // interface plan
@@ -261,7 +264,13 @@ int build_plan(mrcm_ctx* c) {
   std::vector<int> dofs, ids;
   std::vector<int2> gather;
   std::vector<PanelItem> items;
+  std::vector<std::vector<int>> panel_ids;
   std::vector<int> node_desc(tb.nodes.size(), -1);
+  // a level is eliminated in LDS when all its fronts fit, else by panels
+  std::vector<int> level_max_n(max_level + 1, 0);
+  for (auto& n : tb.nodes)
+    if (!n.leaf) level_max_n[n.level] = std::max(level_max_n[n.level], (int)n.dofs.size());
+  long long inv_total = 0;
   for (size_t i = 0; i < tb.nodes.size(); ++i) {
     const HNode& n = tb.nodes[i];
     if (n.leaf) continue;
@@ -269,6 +278,11 @@ int build_plan(mrcm_ctx* c) {
     d.f_off = n.f_off;
     d.n = (int)n.dofs.size();
     d.s = n.s;
+    d.blocked = level_max_n[n.level] > SMALL_FRONT ? 1 : 0;
+    d.inv_off = inv_total;
+    if (d.blocked)
+      inv_total += (long long)((n.s + PANEL_NB - 1) / PANEL_NB) * 2 * PANEL_NB * PANEL_NB;
+    if (d.n > 4096) return fail(c, MRCM_E_UNSUPPORTED, "interface front too large");
     d.map_off = (long long)maps.size();
     d.dof_off = (long long)dofs.size();
     for (int q = 0; q < 2; ++q) {
@@ -318,33 +332,39 @@ int build_plan(mrcm_ctx* c) {
       for (int k0 = 0; k0 < lp.max_s; k0 += PANEL_NB) {
         PanelLaunch pl{};
         pl.k0 = k0;
-        pl.panel_off = (int)items.size();
-        for (int q = 0; q < lp.count; ++q) {
-          const int id = ids[lp.ids_off + q];
-          const NodeDesc& d = desc[id];
-          if (d.s <= k0) continue;
-          const int nb = std::min(PANEL_NB, d.s - k0);
-          for (int r = k0 + nb; r < d.n; r += 256) items.push_back(PanelItem{id, 0, r, 0});
-          for (int cc = k0 + nb; cc <= d.n; cc += 256) items.push_back(PanelItem{id, 1, 0, cc});
-        }
-        pl.panel_count = (int)items.size() - pl.panel_off;
+        std::vector<int> diag;
         pl.update_off = (int)items.size();
         for (int q = 0; q < lp.count; ++q) {
           const int id = ids[lp.ids_off + q];
           const NodeDesc& d = desc[id];
           if (d.s <= k0) continue;
+          diag.push_back(id);
           const int nb = std::min(PANEL_NB, d.s - k0);
-          items.push_back(PanelItem{id, 3, k0, k0});
           for (int r = k0 + nb; r < d.n; r += TILE)
-            for (int cc = k0 + nb; cc <= d.n; cc += TILE) items.push_back(PanelItem{id, 2, r, cc});
+            for (int cc = k0 + nb; cc <= d.n; cc += TILE) items.push_back(PanelItem{id, r, cc, 0});
         }
         pl.update_count = (int)items.size() - pl.update_off;
+        pl.diag_count = (int)diag.size();
+        panel_ids.push_back(diag);
+        pl.diag_off = -1;  // resolved after all level ids are known
         lp.panels.push_back(pl);
       }
     }
     c->levels.push_back(lp);
   }
+  // append the per-panel front lists after the per-level lists
+  {
+    size_t q = 0;
+    for (LevelPlan& lp : c->levels)
+      for (PanelLaunch& pl : lp.panels) {
+        pl.diag_off = (int)ids.size();
+        ids.insert(ids.end(), panel_ids[q].begin(), panel_ids[q].end());
+        ++q;
+      }
+  }
   ALLOC(c, c->tree, total);
+  ALLOC(c, c->inv, inv_total);
+  ALLOC(c, c->partials, 2 * RESID_WG);
   ALLOC(c, c->d_nodes, desc.size());
   ALLOC(c, c->d_maps, maps.size());
   ALLOC(c, c->d_dofs, dofs.size());
@@ -395,16 +415,17 @@ int run_interface(mrcm_ctx* c) {
     HIPCHK(c, launch_front_gather(c->d_nodes, c->d_gather + lp.gather_off, lp.gather_count, c->tree,
                                   c->d_maps, st));
     for (const PanelLaunch& pl : lp.panels) {
-      HIPCHK(c, launch_front_panel(c->d_nodes, c->d_items + pl.panel_off, pl.panel_count, pl.k0,
-                                   c->tree, c->status, st));
-      HIPCHK(c, launch_front_update(c->d_nodes, c->d_items + pl.update_off, pl.update_count, pl.k0,
-                                    c->tree, c->status, st));
+      HIPCHK(c, launch_front_diag(c->d_nodes, c->d_ids + pl.diag_off, pl.diag_count, pl.k0, c->tree,
+                                  c->inv, c->status, st));
+      if (pl.update_count > 0)
+        HIPCHK(c, launch_front_update(c->d_nodes, c->d_items + pl.update_off, pl.update_count,
+                                      pl.k0, c->tree, c->inv, st));
     }
   }
   for (auto it = c->levels.rbegin(); it != c->levels.rend(); ++it)
-    HIPCHK(c, launch_front_back(c->d_nodes, c->d_ids + it->ids_off, it->count, c->tree, c->d_dofs,
-                                c->coef, st));
-  HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->result + 2, st));
+    HIPCHK(c, launch_front_back(c->d_nodes, c->d_ids + it->ids_off, it->count, c->tree, c->inv,
+                                c->d_dofs, c->coef, st));
+  HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->partials, c->result + 2, st));
   return MRCM_OK;
 }
 
@@ -469,6 +490,10 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
   bool any_dir = false;
   for (int s = 0; s < 4; ++s) { G.kind[s] = bc->kind[s]; any_dir |= bc->kind[s] == MRCM_BC_DIRICHLET; }
   G.gauge = any_dir ? 0 : 1;
+  {
+    const char* gen = getenv("MRCM_GENERIC_KERNELS");
+    G.generic = (gen && gen[0] == '1') ? 1 : 0;
+  }
   c->precision = precision;
   c->space = space;
   c->mu_w = fluid->mu_w;

@@ -17,11 +17,10 @@
 // Fronts of up to SMALL_FRONT unknowns are gathered and eliminated by one
 // work-group in LDS.  Larger fronts (the few nodes near the root) are
 // gathered in global memory and eliminated by a right-looking blocked LU:
-// per panel of PANEL_NB columns, one launch computes the L21 rows and U12
-// columns (every work-group factors the small diagonal block redundantly in
-// LDS) and one launch applies the trailing update A22 -= L21 U12 in 64x64
-// tiles and writes the factored diagonal block.  Back substitution runs top
-// down, one work-group per node.
+// per panel of PANEL_NB columns, one launch factors the diagonal block and
+// stores the inverses of its two triangular factors, and one launch applies
+// the trailing update A22 -= (A21 U11^-1)(L11^-1 A12) in 64x64 tiles.  Back
+// substitution runs top down, one work-group per node.
 #include "mrcm_internal.h"
 
 #include <math.h>
@@ -94,105 +93,115 @@ __global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes,
   }
 }
 
-// LU (no pivoting) of the nb x nb diagonal block at (k0, k0) into LDS A[nb][PANEL_NB+1]
-__device__ void factor_diag(const double* F, int ld, int k0, int nb, double (*A)[PANEL_NB + 1],
-                            bool& bad) {
-  for (int e = threadIdx.x; e < nb * nb; e += NT) {
-    const int i = e / nb, j = e % nb;
-    A[i][j] = F[(long long)(k0 + i) * ld + k0 + j];
-  }
+// Diagonal block of panel k0 of a blocked front: LU without pivoting in
+// LDS, written back in place, plus the explicit inverses of its unit lower
+// factor L11 and its upper factor U11 (stored per panel in `inv`).  One
+// work-group per front.
+__global__ void __launch_bounds__(NT) front_diag_kernel(const NodeDesc* nodes, const int* ids,
+                                                        int k0, double* tree, double* inv,
+                                                        int* status) {
+  __shared__ double A[PANEL_NB][PANEL_NB + 1];
+  __shared__ double Li[PANEL_NB][PANEL_NB + 1];
+  __shared__ double Ui[PANEL_NB][PANEL_NB + 1];
+  const NodeDesc nd = nodes[ids[blockIdx.x]];
+  const int ld = nd.n + 1;
+  const int nb = min(PANEL_NB, nd.s - k0);
+  double* F = tree + nd.f_off;
+  const int t = threadIdx.x;
+  for (int e = t; e < nb * nb; e += NT) A[e / nb][e % nb] = F[(long long)(k0 + e / nb) * ld + k0 + e % nb];
   __syncthreads();
+  bool bad = false;
   for (int k = 0; k < nb; ++k) {
     const double piv = A[k][k];
     if (piv == 0.0 || !isfinite(piv)) bad = true;
-    for (int i = k + 1 + threadIdx.x; i < nb; i += NT) A[i][k] /= piv;
+    for (int i = k + 1 + t; i < nb; i += NT) A[i][k] /= piv;
     __syncthreads();
     const int w = nb - k - 1;
-    for (int e = threadIdx.x; e < w * w; e += NT) {
+    for (int e = t; e < w * w; e += NT) {
       const int i = k + 1 + e / w, j = k + 1 + e % w;
       A[i][j] -= A[i][k] * A[k][j];
     }
     __syncthreads();
   }
-}
-
-__global__ void __launch_bounds__(NT) front_panel_kernel(const NodeDesc* nodes,
-                                                         const PanelItem* items, int k0,
-                                                         double* tree, int* status) {
-  __shared__ double A[PANEL_NB][PANEL_NB + 1];
-  const PanelItem it = items[blockIdx.x];
-  const NodeDesc nd = nodes[it.node];
-  const int n = nd.n, ld = n + 1;
-  const int nb = min(PANEL_NB, nd.s - k0);
-  double* F = tree + nd.f_off;
-  bool bad = false;
-  factor_diag(F, ld, k0, nb, A, bad);
-  const int t = threadIdx.x;
-  if (it.kind == 0) {
-    // L21 row r: solve x U11 = a
-    const int r = it.i0 + t;
-    if (r < n) {
-      double x[PANEL_NB] = {};
-      double* row = F + (long long)r * ld + k0;
-      for (int k = 0; k < nb; ++k) x[k] = row[k];
-      for (int k = 0; k < nb; ++k) {
-        double v = x[k];
-        for (int m = 0; m < k; ++m) v -= x[m] * A[m][k];
-        x[k] = v / A[k][k];
-      }
-      for (int k = 0; k < nb; ++k) row[k] = x[k];
+  for (int e = t; e < nb * nb; e += NT) F[(long long)(k0 + e / nb) * ld + k0 + e % nb] = A[e / nb][e % nb];
+  // column j of L11^{-1} (unit lower) and of U11^{-1} (upper), one thread each
+  if (t < nb) {
+    const int j = t;
+    for (int i = 0; i < nb; ++i) Li[i][j] = 0.0, Ui[i][j] = 0.0;
+    Li[j][j] = 1.0;
+    for (int i = j + 1; i < nb; ++i) {
+      double v = 0.0;
+      for (int m = j; m < i; ++m) v -= A[i][m] * Li[m][j];
+      Li[i][j] = v;
     }
-  } else {
-    // U12 column c: solve L11 y = a (unit lower)
-    const int c = it.j0 + t;
-    if (c <= n) {
-      double y[PANEL_NB];
-      for (int k = 0; k < nb; ++k) y[k] = F[(long long)(k0 + k) * ld + c];
-      for (int k = 0; k < nb; ++k) {
-        double v = y[k];
-        for (int m = 0; m < k; ++m) v -= A[k][m] * y[m];
-        y[k] = v;
-      }
-      for (int k = 0; k < nb; ++k) F[(long long)(k0 + k) * ld + c] = y[k];
+    Ui[j][j] = 1.0 / A[j][j];
+    for (int i = j - 1; i >= 0; --i) {
+      double v = 0.0;
+      for (int m = i + 1; m <= j; ++m) v -= A[i][m] * Ui[m][j];
+      Ui[i][j] = v / A[i][i];
     }
+  }
+  __syncthreads();
+  double* out = inv + nd.inv_off + (long long)(k0 / PANEL_NB) * 2 * PANEL_NB * PANEL_NB;
+  for (int e = t; e < PANEL_NB * PANEL_NB; e += NT) {
+    const int i = e / PANEL_NB, j = e % PANEL_NB;
+    out[e] = (i < nb && j < nb) ? Li[i][j] : 0.0;
+    out[PANEL_NB * PANEL_NB + e] = (i < nb && j < nb) ? Ui[i][j] : 0.0;
   }
   if (bad && t == 0) atomicOr(status, ST_IFACE_PIVOT);
 }
 
+// Trailing update of panel k0 for one 64 x 64 tile of a blocked front:
+// L21 = A21 U11^{-1} and U12 = L11^{-1} A12 are formed on the fly for the
+// tile's rows and columns, then A22 -= L21 U12.  The panel rows and columns
+// themselves are left as they were at the start of the panel (back
+// substitution applies L11^{-1} and U11^{-1} to them), so tiles never write
+// what other tiles read.
 __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
                                                           const PanelItem* items, int k0,
-                                                          double* tree, int* status) {
+                                                          double* tree, const double* inv) {
+  __shared__ double Li[PANEL_NB][PANEL_NB + 1];
+  __shared__ double Ui[PANEL_NB][PANEL_NB + 1];
+  __shared__ double As[TILE][PANEL_NB + 1];   // A21 tile, then L21
+  __shared__ double Bs[PANEL_NB][TILE + 1];   // A12 tile, then U12
   __shared__ double Ls[TILE][PANEL_NB + 1];
   __shared__ double Us[PANEL_NB][TILE + 1];
-  __shared__ double A[PANEL_NB][PANEL_NB + 1];
   const PanelItem it = items[blockIdx.x];
   const NodeDesc nd = nodes[it.node];
   const int n = nd.n, ld = n + 1;
   const int nb = min(PANEL_NB, nd.s - k0);
   double* F = tree + nd.f_off;
+  const double* iv = inv + nd.inv_off + (long long)(k0 / PANEL_NB) * 2 * PANEL_NB * PANEL_NB;
   const int t = threadIdx.x;
-  if (it.kind == 3) {
-    bool bad = false;
-    factor_diag(F, ld, k0, nb, A, bad);
-    for (int e = t; e < nb * nb; e += NT) {
-      const int i = e / nb, j = e % nb;
-      F[(long long)(k0 + i) * ld + k0 + j] = A[i][j];
-    }
-    if (bad && t == 0) atomicOr(status, ST_IFACE_PIVOT);
-    return;
-  }
   const int r0 = it.i0, c0 = it.j0;
   const int rows = min(TILE, n - r0), cols = min(TILE, ld - c0);
+  for (int e = t; e < PANEL_NB * PANEL_NB; e += NT) {
+    Li[e / PANEL_NB][e % PANEL_NB] = iv[e];
+    Ui[e / PANEL_NB][e % PANEL_NB] = iv[PANEL_NB * PANEL_NB + e];
+  }
   for (int e = t; e < TILE * PANEL_NB; e += NT) {
     const int i = e / PANEL_NB, k = e % PANEL_NB;
-    Ls[i][k] = (i < rows && k < nb) ? F[(long long)(r0 + i) * ld + k0 + k] : 0.0;
+    As[i][k] = (i < rows && k < nb) ? F[(long long)(r0 + i) * ld + k0 + k] : 0.0;
   }
   for (int e = t; e < PANEL_NB * TILE; e += NT) {
     const int k = e / TILE, j = e % TILE;
-    Us[k][j] = (k < nb && j < cols) ? F[(long long)(k0 + k) * ld + c0 + j] : 0.0;
+    Bs[k][j] = (k < nb && j < cols) ? F[(long long)(k0 + k) * ld + c0 + j] : 0.0;
   }
   __syncthreads();
-  // 4x4 outputs per thread: rows ty*4.., cols tx*4..  (16 x 16 threads)
+  // L21 = A21 Ui (upper), U12 = Li (unit lower) A12
+  for (int e = t; e < TILE * PANEL_NB; e += NT) {
+    const int i = e / PANEL_NB, k = e % PANEL_NB;
+    double v = 0.0;
+    for (int m = 0; m <= k; ++m) v += As[i][m] * Ui[m][k];
+    Ls[i][k] = v;
+  }
+  for (int e = t; e < PANEL_NB * TILE; e += NT) {
+    const int k = e / TILE, j = e % TILE;
+    double v = 0.0;
+    for (int m = 0; m <= k; ++m) v += Li[k][m] * Bs[m][j];
+    Us[k][j] = v;
+  }
+  __syncthreads();
   const int tx = t % 16, ty = t / 16;
   double acc[4][4] = {};
 #pragma unroll 2
@@ -213,44 +222,85 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
   }
 }
 
-// x_s = U_ss^{-1} (y_s - U_sr x_r) for one node; x_r from ancestors
+// Back substitution of one front, top down in the tree: x_s from the
+// front's eliminated rows and the x_r of its ancestors.
+//  classic fronts: row k holds U (upper part) at elimination time k;
+//  blocked fronts: the rows of panel p hold L11\U11 on the diagonal block and
+//  the panel-time A12 to the right, so x_1 = U11^{-1} L11^{-1} (b_1 - A12 x_2).
 __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, const int* ids,
-                                                        const double* tree, const int* dofs,
-                                                        double* x) {
-  extern __shared__ double y[];
+                                                        const double* tree, const double* inv,
+                                                        const int* dofs, double* x) {
+  extern __shared__ double xl[];   // n values: front-local unknowns
+  __shared__ double y[PANEL_NB], z[PANEL_NB];
   const NodeDesc nd = nodes[ids[blockIdx.x]];
   const int n = nd.n, s = nd.s, ld = n + 1;
   const double* F = tree + nd.f_off;
   const int* dof = dofs + nd.dof_off;
   const int t = threadIdx.x;
-  for (int k = t; k < s; k += NT) {
-    const double* row = F + (long long)k * ld;
-    double v = row[n];
-    for (int m = s; m < n; ++m) v -= row[m] * x[dof[m]];
-    y[k] = v;
-  }
+  for (int m = s + t; m < n; m += NT) xl[m] = x[dof[m]];
   __syncthreads();
-  for (int k = s - 1; k >= 0; --k) {
-    const double xk = y[k] / F[(long long)k * ld + k];
+  if (!nd.blocked) {
+    for (int k = t; k < s; k += NT) {
+      const double* row = F + (long long)k * ld;
+      double v = row[n];
+      for (int m = s; m < n; ++m) v -= row[m] * xl[m];
+      xl[k] = v;
+    }
     __syncthreads();
-    for (int i = t; i < k; i += NT) y[i] -= F[(long long)i * ld + k] * xk;
-    if (t == 0) y[k] = xk;
-    __syncthreads();
+    for (int k = s - 1; k >= 0; --k) {
+      const double xk = xl[k] / F[(long long)k * ld + k];
+      __syncthreads();
+      for (int i = t; i < k; i += NT) xl[i] -= F[(long long)i * ld + k] * xk;
+      if (t == 0) xl[k] = xk;
+      __syncthreads();
+    }
+  } else {
+    const int np = (s + PANEL_NB - 1) / PANEL_NB;
+    for (int p = np - 1; p >= 0; --p) {
+      const int k0 = p * PANEL_NB, nb = min(PANEL_NB, s - k0);
+      // y = b_1 - A12 x_2: 8 lanes per row, then a reduction across them
+      {
+        const int row = t / 8, lane = t % 8;
+        double v = 0.0;
+        if (row < nb) {
+          const double* fr = F + (long long)(k0 + row) * ld;
+          for (int m = k0 + nb + lane; m < n; m += 8) v -= fr[m] * xl[m];
+          if (lane == 0) v += fr[n];
+        }
+        for (int off = 4; off > 0; off >>= 1) v += __shfl_down(v, off, 8);
+        if (row < nb && lane == 0) y[row] = v;
+      }
+      __syncthreads();
+      const double* Li = inv + nd.inv_off + (long long)p * 2 * PANEL_NB * PANEL_NB;
+      const double* Ui = Li + PANEL_NB * PANEL_NB;
+      if (t < nb) {
+        double v = 0.0;
+        for (int m = 0; m <= t; ++m) v += Li[t * PANEL_NB + m] * y[m];
+        z[t] = v;
+      }
+      __syncthreads();
+      if (t < nb) {
+        double v = 0.0;
+        for (int m = t; m < nb; ++m) v += Ui[t * PANEL_NB + m] * z[m];
+        xl[k0 + t] = v;
+      }
+      __syncthreads();
+    }
   }
-  for (int k = t; k < s; k += NT) x[dof[k]] = y[k];
+  for (int k = t; k < s; k += NT) x[dof[k]] = xl[k];
 }
 
 // r = b - A x gathered from the subdomain blocks (each interface row has
-// two owners: its lower- and higher-index subdomain).  out2[0] = max |r|,
-// out2[1] = max |b| over rows, reduced by one work-group.
+// two owners: its lower- and higher-index subdomain).  Stage 1: per
+// work-group maxima of |r| and |b|; stage 2: one work-group reduces them.
 __global__ void __launch_bounds__(NT) iface_residual_kernel(Geo g, const double* blocks,
-                                                            const double* x, double* out2) {
+                                                            const double* x, double* partials) {
   __shared__ double red[2][NT];
   const int D = g.D, NBR = 4 * D, NBC = NBR + 1;
   const int n_iface = g.nV + g.SX * (g.SY - 1);
   const int ndof = n_iface * D;
   double rmax = 0.0, bmax = 0.0;
-  for (int row = threadIdx.x; row < ndof; row += NT) {
+  for (int row = blockIdx.x * NT + threadIdx.x; row < ndof; row += gridDim.x * NT) {
     const int e = row / D, k = row % D;
     int sub[2], side[2];
     if (e < g.nV) {
@@ -295,6 +345,30 @@ __global__ void __launch_bounds__(NT) iface_residual_kernel(Geo g, const double*
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = red[0][0];
+    partials[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+__global__ void __launch_bounds__(NT) max_pairs_kernel(const double* partials, int count,
+                                                       double* out2) {
+  __shared__ double red[2][NT];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < count; i += NT) {
+    a = fmax(a, partials[2 * i]);
+    b = fmax(b, partials[2 * i + 1]);
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
     out2[0] = red[0][0];
     out2[1] = red[1][0];
   }
@@ -322,31 +396,35 @@ hipError_t launch_front_gather(const NodeDesc* nodes, const int2* items, int cou
   return hipGetLastError();
 }
 
-hipError_t launch_front_panel(const NodeDesc* nodes, const PanelItem* items, int count, int k0,
-                              double* tree, int* status, hipStream_t st) {
-  hipLaunchKernelGGL(front_panel_kernel, dim3(count), dim3(NT), 0, st, nodes, items, k0, tree,
+hipError_t launch_front_diag(const NodeDesc* nodes, const int* ids, int count, int k0,
+                             double* tree, double* inv, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(front_diag_kernel, dim3(count), dim3(NT), 0, st, nodes, ids, k0, tree, inv,
                      status);
   return hipGetLastError();
 }
 
 hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count, int k0,
-                               double* tree, int* status, hipStream_t st) {
+                               double* tree, const double* inv, hipStream_t st) {
   hipLaunchKernelGGL(front_update_kernel, dim3(count), dim3(NT), 0, st, nodes, items, k0, tree,
-                     status);
+                     inv);
   return hipGetLastError();
 }
 
 hipError_t launch_front_back(const NodeDesc* nodes, const int* ids, int count, const double* tree,
-                             const int* dofs, double* x, hipStream_t st) {
-  // callers guarantee s <= 2048 (16 KiB of LDS)
-  hipLaunchKernelGGL(front_back_kernel, dim3(count), dim3(NT), 2048 * sizeof(double), st, nodes,
-                     ids, tree, dofs, x);
+                             const double* inv, const int* dofs, double* x, hipStream_t st) {
+  // callers guarantee n <= 4096 (32 KiB of LDS)
+  hipLaunchKernelGGL(front_back_kernel, dim3(count), dim3(NT), 4096 * sizeof(double), st, nodes,
+                     ids, tree, inv, dofs, x);
   return hipGetLastError();
 }
 
 hipError_t launch_iface_residual(const Geo& g, const double* blocks, const double* x,
-                                 double* out2, hipStream_t st) {
-  hipLaunchKernelGGL(iface_residual_kernel, dim3(1), dim3(NT), 0, st, g, blocks, x, out2);
+                                 double* partials, double* out2, hipStream_t st) {
+  hipLaunchKernelGGL(iface_residual_kernel, dim3(RESID_WG), dim3(NT), 0, st, g, blocks, x,
+                     partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(max_pairs_kernel, dim3(1), dim3(NT), 0, st, partials, RESID_WG, out2);
   return hipGetLastError();
 }
 

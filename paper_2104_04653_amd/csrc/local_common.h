@@ -1,0 +1,140 @@
+// Device helpers shared by the per-subdomain kernels: geometry of the
+// subdomain sides and the assembly of one cell of the local two-point
+// system (paper, section 3: eq. (mrc1) with the Robin parameter of eq.
+// (beta); physical Dirichlet/Neumann data of eq. (Darcy)).
+#pragma once
+
+#include "mrcm_internal.h"
+
+#include <math.h>
+
+namespace mrcm {
+namespace local {
+
+__device__ inline double series2(double a, double b) { return 1.0 / (1.0 / a + 1.0 / b); }
+
+struct SideGeo {
+  double flen, dist, H;
+};
+
+__device__ inline SideGeo side_geo(const Geo& g, int side) {
+  SideGeo s;
+  if (side < 2) {
+    s.flen = g.hy; s.dist = 0.5 * g.hx; s.H = g.M * g.hy;
+  } else {
+    s.flen = g.hx; s.dist = 0.5 * g.hy; s.H = g.M * g.hx;
+  }
+  return s;
+}
+
+// interface on side (W,E,S,N) of subdomain (I,J), -1 on the domain boundary
+__device__ inline int side_iface(const Geo& g, int I, int J, int side) {
+  switch (side) {
+    case 0: return I > 0 ? J * (g.SX - 1) + I - 1 : -1;
+    case 1: return I < g.SX - 1 ? J * (g.SX - 1) + I : -1;
+    case 2: return J > 0 ? g.nV + (J - 1) * g.SX + I : -1;
+    default: return J < g.SY - 1 ? g.nV + J * g.SX + I : -1;
+  }
+}
+
+// n . n_i: +1 where the subdomain is the lower-index side (E and N sides)
+__device__ inline double side_sigma(int side) { return (side == 1 || side == 3) ? 1.0 : -1.0; }
+
+// local cell index of face t on a side
+template <int M>
+__device__ inline int side_cell(int side, int t) {
+  switch (side) {
+    case 0: return t * M;
+    case 1: return t * M + (M - 1);
+    case 2: return t;
+    default: return (M - 1) * M + t;
+  }
+}
+
+// Assemble one cell of the local two-point system: diagonal, coupling to the
+// +x neighbour (ex) and to the +y neighbour (cy), and the cell's row of the
+// right-hand sides.  robin != 0: skeleton faces carry the Robin law (the
+// basis-function problems); robin == 0: skeleton faces carry the prescribed
+// outflow Fout[side][t] (the stitch re-solve).
+template <int M, int R, bool SIDES = true>
+__device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const double* kap,
+                              double* dg, double* ex, double* cy, double* xrow, int robin,
+                              const double (*Fout)[M]) {
+  const Geo& g = a.g;
+  const int li = l % M, lj = l / M;
+  const int i = I * M + li, j = J * M + lj;
+  const size_t c = (size_t)j * g.nx + i;
+  const double kc = kap[l];
+  const double txc = kc * g.hy / (0.5 * g.hx);
+  const double tyc = kc * g.hx / (0.5 * g.hy);
+  double diag = 0.0, cx = 0.0, cn = 0.0;
+  for (int q = 0; q < R; ++q) xrow[q] = 0.0;
+  double rhs0 = 0.0;
+  if (a.src) rhs0 += a.src[c] * g.hx * g.hy;
+  // face loop: side 0 W, 1 E, 2 S, 3 N
+  for (int side = 0; side < 4; ++side) {
+    const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
+    if (inner) {
+      int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
+      double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
+      double T = series2(side < 2 ? txc : tyc, tn);
+      diag += T;
+      if (side == 1) cx = -T;
+      if (side == 3) cn = -T;
+      continue;
+    }
+    const int e = side_iface(g, I, J, side);
+    const int t = (side < 2) ? lj : li;
+    const double th = (side < 2) ? txc : tyc;
+    if (e < 0) {  // physical boundary
+      const double flen = (side < 2) ? g.hy : g.hx;
+      const double v = a.bcv[side][(side < 2) ? j : i];
+      if (g.kind[side] == 1) {
+        diag += th;
+        rhs0 += th * v;
+      } else {
+        rhs0 -= v * flen;
+      }
+      continue;
+    }
+    if (robin) {
+      SideGeo sg = side_geo(g, side);
+      const double al = a.alpha[e];
+      const double TR = sg.flen * kc / (sg.dist + al * sg.H);
+      const double beta = al * sg.H / kc;
+      const double sig = side_sigma(side);
+      diag += TR;
+      if (SIDES) {
+        const int D = g.D;
+        const double* bs = a.basis + (size_t)e * D * M;
+        for (int k = 0; k < D; ++k) {
+          double gv = bs[k * M + t];
+          if (k >= g.nP) gv = -beta * sig * gv;
+          xrow[1 + side * D + k] += TR * gv;
+        }
+      }
+    } else {
+      rhs0 -= Fout[side][t];
+    }
+  }
+  dg[l] = diag;
+  ex[l] = cx;
+  cy[l] = cn;
+  xrow[0] += rhs0;
+}
+
+
+template <int M>
+__device__ void load_kappa(const SubArgs& a, int I, int J, double* kap) {
+  const Geo& g = a.g;
+  for (int l = threadIdx.x; l < M * M; l += blockDim.x) {
+    const int li = l % M, lj = l / M;
+    const size_t c = (size_t)(J * M + lj) * g.nx + I * M + li;
+    const double lam = a.lam[c];
+    if (!(lam > 0.0) || !isfinite(lam)) atomicOr(a.status, ST_BAD_LAMBDA);
+    kap[l] = a.K[c] * lam;
+  }
+}
+
+}  // namespace local
+}  // namespace mrcm

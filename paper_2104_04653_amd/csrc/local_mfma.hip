@@ -1,0 +1,502 @@
+// One-wavefront-per-subdomain kernels for 16 x 16 subdomains with two
+// pressure and two flux functions per interface (gfx950, FP64 MFMA).
+//
+// Same method as the generic kernels in local.hip (paper, section 3: local
+// Robin problems of eq. (mrc1), basis functions, traces projected on the
+// interface spaces of eq. (mrc2); and the stitch re-solve), laid out for the
+// matrix cores:
+//
+//  * Every 16 x 16 tile is held in the output layout of
+//    v_mfma_f64_16x16x4f64: lane l = c + 16 g (c = l & 15, g = l >> 4) holds
+//    rows g, g+4, g+8, g+12 of column c in its four registers (row 4v + g in
+//    register v).
+//  * Block row j of the local matrix is inverted by Gauss-Jordan sweeps on
+//    that register tile; the pivot row, pivot column and pivot element are
+//    broadcast with lane shuffles, so no work-group barrier is needed.
+//  * The products S_j^{-1} R and S_j^{-1} (C_j X_{j+1}) run on the matrix
+//    cores.  The K index of the four K=4 steps is assigned as k = 4 kk + g
+//    (step kk, lane group g), so the B operand of step kk is element kk of
+//    the lane's own output-layout registers and the A operand is element kk
+//    of the (symmetric) inverse in the same layout: no data moves between
+//    lanes.  The 16 basis columns fill one MFMA tile; the particular
+//    solution is a second tile with the right-hand side replicated over its
+//    16 columns.
+//  * The 16 inverse blocks and the 16 solution tiles stay in registers for
+//    the backward sweep.
+#include "local_common.h"
+
+namespace mrcm {
+
+namespace {
+
+using namespace local;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int M = 16;
+constexpr int MM = 256;
+constexpr int D = 4;
+constexpr int R = 17;
+constexpr int WAVE = 64;
+
+__device__ inline double readlane_d(double x, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffu), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ inline d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// In-place inverse of the SPD tile s (output layout) by Gauss-Jordan sweeps.
+__device__ inline d4 gauss_jordan16(d4 s, int c, int g, bool& bad) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const int kv = k >> 2, kg = k & 3;                       // row k: register kv, group kg
+    const double p = readlane_d(s[kv], k + 16 * kg);       // S[k][k]
+    const double prow = __shfl(s[kv], c + 16 * kg);         // S[k][c]
+    double pcol[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pcol[v] = __shfl(s[v], k + 16 * g);   // S[4v+g][k]
+    if (!(p > 0.0)) bad = true;
+    const double ip = 1.0 / p;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * v + g;
+      double nv;
+      if (row == k) nv = (c == k) ? ip : s[v] * ip;
+      else nv = (c == k) ? -pcol[v] * ip : fma(-pcol[v] * ip, prow, s[v]);
+      s[v] = nv;
+    }
+  }
+  return s;
+}
+
+// Schur-complemented diagonal block S_j = D_j - C_{j-1} S_{j-1}^{-1} C_{j-1}
+// in output layout (prev = S_{j-1}^{-1}).
+__device__ inline d4 schur_block(int j, const d4& prev, int c, int g, const double* dg,
+                                 const double* ex, const double* cy) {
+  d4 s;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = 4 * v + g;
+    double d = (row == c) ? dg[j * M + row]
+             : (row == c + 1) ? ex[j * M + c]
+             : (c == row + 1) ? ex[j * M + row] : 0.0;
+    if (j > 0) d -= cy[(j - 1) * M + row] * prev[v] * cy[(j - 1) * M + c];
+    s[v] = d;
+  }
+  return s;
+}
+
+// right-hand side of basis column c (dof c of the W, E, S, N interfaces) at
+// local cell (li, lj): non-zero only next to the face of its side
+__device__ inline double side_rhs(const double (*bside)[M][D], int lj, int li, int c) {
+  const int side = c >> 2, k = c & 3;
+  switch (side) {
+    case 0: return li == 0 ? bside[0][lj][k] : 0.0;
+    case 1: return li == M - 1 ? bside[1][lj][k] : 0.0;
+    case 2: return lj == 0 ? bside[2][li][k] : 0.0;
+    default: return lj == M - 1 ? bside[3][li][k] : 0.0;
+  }
+}
+
+// One column solve with the stored inverse blocks Sv (rhs and result in
+// LDS, cell-major).  Forward Z_j = S_j^{-1}(B_j - C_{j-1} Z_{j-1}), backward
+// X_j = Z_j - S_j^{-1} C_j X_{j+1}; the column is replicated over the 16
+// MFMA columns.
+__device__ inline void solve_column(const d4* Sv, const double* rhs, double* out, int c, int g,
+                                    const double* cy) {
+  d4 z;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    d4 r;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * v + g;
+      double b = rhs[j * M + row];
+      if (j > 0) b -= cy[(j - 1) * M + row] * z[v];
+      r[v] = b;
+    }
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mfma(Sv[j][kk], r[kk], acc);
+    z = acc;
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = z[v];
+    }
+  }
+  __syncthreads();
+  d4 xn = z;
+#pragma unroll
+  for (int j = M - 2; j >= 0; --j) {
+    d4 t, x;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * v + g;
+      t[v] = -cy[j * M + row] * xn[v];
+      x[v] = out[j * M + row];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) x = mfma(Sv[j][kk], t[kk], x);
+    xn = x;
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = x[v];
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(WAVE) basis_m16d4_kernel(SubArgs a) {
+  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM], pz[MM];
+  __shared__ double bside[4][M][D];
+  __shared__ double xb[4][M][R];      // solution next to each side's faces, all columns
+  const Geo& g = a.g;
+  const int lane = threadIdx.x, c = lane & 15, gq = lane >> 4;
+  const int sd = blockIdx.x;
+  const int I = sd % g.SX, J = sd / g.SX;
+
+  load_kappa<M>(a, I, J, kap);
+  __syncthreads();
+  for (int l = lane; l < MM; l += WAVE)
+    assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, b0 + l, 1, nullptr);
+  {
+    // Robin data of the basis columns: bside[side][t][k] = T_R g_k(t)
+    const int side = lane >> 4, t = lane & 15;
+    const int e = side_iface(g, I, J, side);
+    for (int k = 0; k < D; ++k) {
+      double v = 0.0;
+      if (e >= 0) {
+        const SideGeo sg = side_geo(g, side);
+        const double al = a.alpha[e];
+        const double kk = kap[side_cell<M>(side, t)];
+        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
+        const double beta = al * sg.H / kk;
+        double gv = a.basis[((size_t)e * D + k) * M + t];
+        if (k >= g.nP) gv = -beta * side_sigma(side) * gv;
+        v = TR * gv;
+      }
+      bside[side][t][k] = v;
+    }
+  }
+  __syncthreads();
+
+  d4 Sv[M], Xv[M];
+  bool bad = false;
+  d4 zp = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    d4 s = schur_block(j, j > 0 ? Sv[j > 0 ? j - 1 : 0] : zp, c, gq, dg, ex, cy);
+    s = gauss_jordan16(s, c, gq, bad);
+    Sv[j] = s;
+    d4 r, rp;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * v + gq;
+      double b = side_rhs(bside, j, row, c);
+      double bp = b0[j * M + row];
+      if (j > 0) {
+        const double cc = cy[(j - 1) * M + row];
+        b -= cc * Xv[j > 0 ? j - 1 : 0][v];
+        bp -= cc * zp[v];
+      }
+      r[v] = b;
+      rp[v] = bp;
+    }
+    d4 z = {0.0, 0.0, 0.0, 0.0}, zz = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      z = mfma(s[kk], r[kk], z);
+      zz = mfma(s[kk], rp[kk], zz);
+    }
+    Xv[j] = z;
+    zp = zz;
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = zz[v];
+    }
+  }
+  __syncthreads();
+  d4 xpn = zp;
+#pragma unroll
+  for (int j = M - 2; j >= 0; --j) {
+    d4 t, tp, xp;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * v + gq;
+      const double cc = -cy[j * M + row];
+      t[v] = cc * Xv[j + 1][v];
+      tp[v] = cc * xpn[v];
+      xp[v] = pz[j * M + row];
+    }
+    d4 x = Xv[j];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      x = mfma(Sv[j][kk], t[kk], x);
+      xp = mfma(Sv[j][kk], tp[kk], xp);
+    }
+    Xv[j] = x;
+    xpn = xp;
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = xp[v];
+    }
+  }
+  if (bad) atomicOr(a.status, ST_LOCAL_PIVOT);
+
+  // basis functions to global memory, column-major per subdomain
+  double* Xg = a.X + (size_t)sd * R * MM;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Xg[(size_t)(1 + c) * MM + j * M + 4 * v + gq] = Xv[j][v];
+  }
+  // cells next to the skeleton faces, for the traces
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    if (gq == 0) xb[0][j][1 + c] = Xv[j][0];
+    if (gq == 3) xb[1][j][1 + c] = Xv[j][3];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    xb[2][4 * v + gq][1 + c] = Xv[0][v];
+    xb[3][4 * v + gq][1 + c] = Xv[M - 1][v];
+  }
+  __syncthreads();
+  for (int l = lane; l < MM; l += WAVE) Xg[l] = pz[l];
+  if (lane < M) {
+    xb[0][lane][0] = pz[lane * M];
+    xb[1][lane][0] = pz[lane * M + M - 1];
+    xb[2][lane][0] = pz[lane];
+    xb[3][lane][0] = pz[(M - 1) * M + lane];
+  }
+  __syncthreads();
+
+  // traces projected on the interface functions: the subdomain's block of
+  // the interface system (rows of flux dofs negated: symmetric form)
+  constexpr int NBR = 4 * D, NBC = 4 * D + 1;
+  double* blk = a.blocks + (size_t)sd * NBR * NBC;
+  const int nP = g.nP;
+  int e0side = -1;
+  bool e0lo = false;
+  if (g.gauge) {
+    for (int side = 0; side < 4; ++side)
+      if (side_iface(g, I, J, side) == 0) { e0side = side; e0lo = side_sigma(side) > 0; }
+  }
+  for (int o = lane; o < NBR * NBC; o += WAVE) {
+    const int r = o / NBC, qc = o % NBC;
+    const int side = r / D, k = r % D;
+    const int e = side_iface(g, I, J, side);
+    double val = 0.0;
+    if (e >= 0) {
+      const int col = (qc < NBR) ? 1 + qc : 0;
+      const SideGeo sg = side_geo(g, side);
+      const double al = a.alpha[e];
+      const double sig = side_sigma(side);
+      const double* bs = a.basis + (size_t)e * D * M;
+      const bool colside = col >= 1 + side * D && col < 1 + side * D + D;
+      const int kc = col - 1 - side * D;
+      double sum = 0.0;
+      for (int t = 0; t < M; ++t) {
+        const double kk = kap[side_cell<M>(side, t)];
+        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
+        const double beta = al * sg.H / kk;
+        double gv = 0.0;
+        if (colside) gv = (kc < nP) ? bs[kc * M + t] : -beta * sig * bs[kc * M + t];
+        const double F = TR * (xb[side][t][col] - gv);
+        if (k < nP) sum += bs[k * M + t] * F;
+        else sum += bs[k * M + t] * (gv + beta * F / sg.flen);
+      }
+      const double natural = (k < nP) ? sum : sig * sg.flen * sum;
+      const double sgn = (k < nP) ? 1.0 : -1.0;
+      val = (qc < NBR) ? sgn * natural : -sgn * natural;
+      if (e0side >= 0) {
+        const int r0 = e0side * D;
+        if (r == r0) val = (qc == r0 && e0lo) ? 1.0 : 0.0;
+        else if (qc == r0) val = 0.0;
+      }
+    }
+    blk[o] = val;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stitch re-solve for 16 x 16 subdomains (one wavefront per subdomain)
+// ---------------------------------------------------------------------------
+
+__device__ inline double compose16(const SubArgs& a, int sd, int l) {
+  const Geo& g = a.g;
+  const int I = sd % g.SX, J = sd / g.SX;
+  const double* xr = a.X + (size_t)sd * R * MM + l;
+  double p = xr[0];
+  for (int side = 0; side < 4; ++side) {
+    const int e = side_iface(g, I, J, side);
+    if (e < 0) continue;
+    for (int k = 0; k < D; ++k) p += xr[(size_t)(1 + side * D + k) * MM] * a.coef[(size_t)e * D + k];
+  }
+  return p;
+}
+
+__global__ void __launch_bounds__(WAVE) stitch_m16d4_kernel(SubArgs a) {
+  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
+  __shared__ double pm[MM], bs_[MM], ps[MM], rs[MM], dx[MM];
+  __shared__ double Fout[4][M];
+  __shared__ double red[3][WAVE];
+  const Geo& g = a.g;
+  const int lane = threadIdx.x, c = lane & 15, gq = lane >> 4;
+  const int sd = blockIdx.x;
+  const int I = sd % g.SX, J = sd / g.SX;
+  const int nP = g.nP;
+
+  load_kappa<M>(a, I, J, kap);
+  for (int l = lane; l < MM; l += WAVE) pm[l] = compose16(a, sd, l);
+  __syncthreads();
+  {
+    // one-sided Robin fluxes on both sides of each skeleton face; outflow
+    // of this subdomain = their average
+    const int side = lane >> 4, t = lane & 15;
+    const int e = side_iface(g, I, J, side);
+    double fo = 0.0;
+    if (e >= 0) {
+      const SideGeo sg = side_geo(g, side);
+      const double al = a.alpha[e];
+      const double* bsf = a.basis + (size_t)e * D * M;
+      const double* ce = a.coef + (size_t)e * D;
+      double PH = 0.0, UH = 0.0;
+      for (int k = 0; k < nP; ++k) PH += ce[k] * bsf[k * M + t];
+      for (int k = nP; k < D; ++k) UH += ce[k] * bsf[k * M + t];
+      const int l = side_cell<M>(side, t);
+      const double sig = side_sigma(side);
+      const double ko = kap[l];
+      const double Fown = sg.flen * ko / (sg.dist + al * sg.H) *
+                          (pm[l] - (PH - al * sg.H / ko * sig * UH));
+      const int nside = side ^ 1;
+      const int nsd = (side == 0) ? sd - 1 : (side == 1) ? sd + 1 : (side == 2) ? sd - g.SX : sd + g.SX;
+      const int nI = nsd % g.SX, nJ = nsd / g.SX;
+      const int nl = side_cell<M>(nside, t);
+      const size_t nc = (size_t)(nJ * M + nl / M) * g.nx + nI * M + nl % M;
+      const double kn = a.K[nc] * a.lam[nc];
+      const double pn = compose16(a, nsd, nl);
+      const double Fnb = sg.flen * kn / (sg.dist + al * sg.H) *
+                         (pn - (PH - al * sg.H / kn * (-sig) * UH));
+      fo = 0.5 * (Fown - Fnb);
+    }
+    Fout[side][t] = fo;
+  }
+  __syncthreads();
+  for (int l = lane; l < MM; l += WAVE)
+    assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, bs_ + l, 0, Fout);
+  __syncthreads();
+  const bool dir = (I == 0 && g.kind[0] == 1) || (I == g.SX - 1 && g.kind[1] == 1) ||
+                   (J == 0 && g.kind[2] == 1) || (J == g.SY - 1 && g.kind[3] == 1);
+  if (!dir && lane == 0) {
+    const double tp = dg[0];
+    dg[0] += tp;
+    bs_[0] += tp * pm[0];
+  }
+  __syncthreads();
+
+  d4 Sv[M];
+  bool bad = false;
+  d4 prev = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    d4 s = schur_block(j, prev, c, gq, dg, ex, cy);
+    s = gauss_jordan16(s, c, gq, bad);
+    Sv[j] = s;
+    prev = s;
+  }
+  if (bad) atomicOr(a.status, ST_STITCH_PIVOT);
+  solve_column(Sv, bs_, ps, c, gq, cy);
+  // two steps of FP64 iterative refinement with the stored inverse blocks
+  for (int it = 0; it < 2; ++it) {
+    for (int l = lane; l < MM; l += WAVE) {
+      const int li = l % M, lj = l / M;
+      double ax = dg[l] * ps[l];
+      if (li < M - 1) ax += ex[l] * ps[l + 1];
+      if (li > 0) ax += ex[l - 1] * ps[l - 1];
+      if (lj < M - 1) ax += cy[l] * ps[l + M];
+      if (lj > 0) ax += cy[l - M] * ps[l - M];
+      rs[l] = bs_[l] - ax;
+    }
+    __syncthreads();
+    solve_column(Sv, rs, dx, c, gq, cy);
+    for (int l = lane; l < MM; l += WAVE) ps[l] += dx[l];
+    __syncthreads();
+  }
+
+  double imb = 0.0, fmx = 0.0, psum = 0.0;
+  for (int l = lane; l < MM; l += WAVE) {
+    const int li = l % M, lj = l / M;
+    const int i = I * M + li, j = J * M + lj;
+    const double kc = kap[l];
+    const double txc = kc * g.hy / (0.5 * g.hx), tyc = kc * g.hx / (0.5 * g.hy);
+    const double pv = ps[l];
+    double F[4];
+    for (int side = 0; side < 4; ++side) {
+      const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
+      double out;
+      if (inner) {
+        const int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
+        const double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
+        out = series2(side < 2 ? txc : tyc, tn) * (pv - ps[nb]);
+      } else {
+        const int e = side_iface(g, I, J, side);
+        const int t = (side < 2) ? lj : li;
+        if (e >= 0) {
+          out = Fout[side][t];
+        } else {
+          const double flen = (side < 2) ? g.hy : g.hx;
+          const double v = a.bcv[side][(side < 2) ? j : i];
+          out = (g.kind[side] == 1) ? ((side < 2) ? txc : tyc) * (pv - v) : v * flen;
+        }
+      }
+      F[side] = (side == 0 || side == 2) ? -out : out;
+    }
+    a.ux[(size_t)j * (g.nx + 1) + i] = F[0] / g.hy;
+    if (li == M - 1 && I == g.SX - 1) a.ux[(size_t)j * (g.nx + 1) + i + 1] = F[1] / g.hy;
+    a.uy[(size_t)j * g.nx + i] = F[2] / g.hx;
+    if (lj == M - 1 && J == g.SY - 1) a.uy[(size_t)(j + 1) * g.nx + i] = F[3] / g.hx;
+    const double q = a.src ? a.src[(size_t)j * g.nx + i] * g.hx * g.hy : 0.0;
+    const double net = F[1] - F[0] + F[3] - F[2];
+    imb = fmax(imb, fabs(net - q));
+    fmx = fmax(fmx, fmax(fmax(fabs(F[0]), fabs(F[1])), fmax(fabs(F[2]), fabs(F[3]))));
+    a.p_out[(size_t)j * g.nx + i] = pm[l];
+    psum += pm[l];
+  }
+  red[0][lane] = imb;
+  red[1][lane] = fmx;
+  red[2][lane] = psum;
+  __syncthreads();
+  for (int w = WAVE / 2; w > 0; w >>= 1) {
+    if (lane < w) {
+      red[0][lane] = fmax(red[0][lane], red[0][lane + w]);
+      red[1][lane] = fmax(red[1][lane], red[1][lane + w]);
+      red[2][lane] = red[2][lane] + red[2][lane + w];
+    }
+    __syncthreads();
+  }
+  if (lane == 0) {
+    a.sub_stats[3 * sd + 0] = red[0][0];
+    a.sub_stats[3 * sd + 1] = red[1][0];
+    a.sub_stats[3 * sd + 2] = red[2][0];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_basis_m16d4(const SubArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(basis_m16d4_kernel, dim3(a.g.n_sub), dim3(WAVE), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(stitch_m16d4_kernel, dim3(a.g.n_sub), dim3(WAVE), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace mrcm

@@ -25,6 +25,8 @@ struct Geo {
   int nP, nU, D;    // interface dofs per interface (D = nP + nU)
   int kind[4];      // boundary kind per side W E S N (1 = Dirichlet)
   int gauge;        // 1: no Dirichlet side, first pressure dof pinned
+  int generic;      // 1: use the generic per-subdomain kernels even where a
+                    //    specialised one exists (host-side switch)
   double hx, hy;
 };
 
@@ -37,7 +39,7 @@ struct SubArgs {
   const double* bcv[4];   // boundary values per side (ny, ny, nx, nx)
   const double* alpha;    // per interface
   const double* basis;    // [iface][D][M]: rows 0..nP-1 pressure, nP..D-1 flux functions
-  double* X;              // [sub][M*M][R] local solutions (R = 1 + 4D)
+  double* X;              // [sub][R][M*M] local solutions (R = 1 + 4D), column-major per subdomain
   double* blocks;         // [sub][4D][4D+1] symmetric local interface blocks
   const double* coef;     // interface solution (stitch kernel)
   double* p_out;          // nx*ny composed pressure (stitch kernel)
@@ -55,15 +57,18 @@ struct NodeDesc {
   long long map_off;    // offset into the map array (n int2: child A index, child B index)
   long long dof_off;    // offset into the dof array (n ints: global dof per position)
   long long c_off[2];   // offset of each child's Schur block (top-left)
+  long long inv_off;    // blocked fronts: offset of the per-panel triangular inverses
   int n, s;
   int c_ld[2];          // row stride of each child's Schur block
   int c_rhs[2];         // rhs column of each child's Schur block (relative to c_off)
+  int blocked;          // 0: eliminated pivot by pivot (classic in-place LU);
+                        // 1: eliminated by panels of PANEL_NB columns
 };
 
-struct PanelItem {      // one work-group of a blocked elimination step
+struct PanelItem {      // one work-group of a blocked trailing update
   int node;             // index into the node descriptor array
-  int kind;             // 0: rows of L21, 1: columns of U12, 2: trailing tile, 3: diagonal block
-  int i0, j0;           // first row / column handled
+  int i0, j0;           // first row / column of the 64 x 64 tile
+  int pad;
 };
 
 // ---- launchers (local.hip) ----
@@ -72,6 +77,9 @@ hipError_t launch_stitch(const SubArgs& a, hipStream_t st);
 hipError_t launch_mobility(const double* in, double* lam, size_t n, int from_saturation,
                            double mu_w, double mu_o, hipStream_t st);
 hipError_t launch_finish_flux(const SubArgs& a, double* result, hipStream_t st);
+// (local_mfma.hip) one wavefront per 16 x 16 subdomain, 2 + 2 interface dofs
+hipError_t launch_basis_m16d4(const SubArgs& a, hipStream_t st);
+hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st);
 bool local_supported(int M, int D);
 
 // ---- launchers (interface.hip) ----
@@ -79,14 +87,17 @@ hipError_t launch_front_small(const NodeDesc* nodes, const int* ids, int count, 
                               double* tree, const int2* maps, int* status, hipStream_t st);
 hipError_t launch_front_gather(const NodeDesc* nodes, const int2* items, int count,
                                double* tree, const int2* maps, hipStream_t st);
-hipError_t launch_front_panel(const NodeDesc* nodes, const PanelItem* items, int count, int k0,
-                              double* tree, int* status, hipStream_t st);
+hipError_t launch_front_diag(const NodeDesc* nodes, const int* ids, int count, int k0,
+                             double* tree, double* inv, int* status, hipStream_t st);
 hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count,
-                               int k0, double* tree, int* status, hipStream_t st);
+                               int k0, double* tree, const double* inv, hipStream_t st);
 hipError_t launch_front_back(const NodeDesc* nodes, const int* ids, int count, const double* tree,
-                             const int* dofs, double* x, hipStream_t st);
+                             const double* inv, const int* dofs, double* x, hipStream_t st);
+// r = b - A x of the assembled interface system; partials: 2 doubles per
+// work-group (RESID_WG of them), reduced into out2[0] = max|r|, out2[1] = max|b|
 hipError_t launch_iface_residual(const Geo& g, const double* blocks, const double* x,
-                                 double* out2, hipStream_t st);
+                                 double* partials, double* out2, hipStream_t st);
+constexpr int RESID_WG = 128;
 hipError_t prepare_interface_kernels();
 
 constexpr int PANEL_NB = 32;      // panel width of the blocked elimination

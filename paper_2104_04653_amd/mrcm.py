@@ -256,4 +256,5 @@ class MRCMSolver:
         m = int(self.prob.sub_nx)
         out = np.empty(self.n_sub * m * m * self.n_cols)
         self._check(self.lib.mrcm_get_basis(self.ctx, _dptr(out)), "mrcm_get_basis")
-        return out.reshape(self.n_sub, m * m, self.n_cols)
+        # stored column-major per subdomain; returned as [sub][cell][col]
+        return out.reshape(self.n_sub, self.n_cols, m * m).transpose(0, 2, 1).copy()
