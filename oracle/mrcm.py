@@ -182,11 +182,26 @@ def _interface_data(itf, rec, ps, us, col):
     return G
 
 
-def _refined(A, solve, b, steps=2):
-    """x = A^-1 b by a direct solve plus FP64 iterative refinement steps."""
+RESIDUAL = "extended"   # or "fp64"
+
+
+def _residual(A, x, b):
+    """b - A x.  With RESIDUAL == "extended" the products and sums are taken
+    in the x87 extended format (64-bit mantissa) and rounded once, so that
+    refinement converges to the FP64 solution of the FP64 data instead of
+    stalling at condition-number times FP64 rounding."""
+    if RESIDUAL == "extended":
+        ld = np.longdouble
+        return (np.asarray(b, dtype=ld) - A.astype(ld) @ np.asarray(x, dtype=ld)).astype(np.float64)
+    return b - A @ x
+
+
+def _refined(A, solve, b, steps=3):
+    """x = A^-1 b by a direct solve plus iterative refinement steps."""
     x = solve(b)
+    A = A.tocsr()
     for _ in range(steps):
-        x = x + solve(b - A @ x)
+        x = x + solve(_residual(A, x, b))
     return x
 
 
@@ -212,6 +227,9 @@ def _local_solve(A, B, geom, method):
             c = sla.cholesky_banded(ab, lower=True)
             X[cells] = sla.cho_solve_banded((c, True), B[cells])
         return X
+
+    if method == "banded_refined":
+        return _refined(A, lambda r: _local_solve(A, r, geom, "banded"), B)
     raise ValueError(method)
 
 
@@ -228,9 +246,9 @@ def _interface_solve(M, b, method, ir_steps):
     else:
         raise ValueError(method)
     x = solve(b)
+    Mc = M.tocsr()
     for _ in range(ir_steps):
-        r = b - M @ x
-        x = x + solve(r)
+        x = x + solve(_residual(Mc, x, b))
     return x
 
 
@@ -265,7 +283,7 @@ def _boundary_fluxes(geom, prob, kappa, p, FX, FY):
 
 
 def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu",
-               ir_steps=2, stitch=True):
+               ir_steps=3, stitch=True):
     """Run the MRCM on ``prob`` with total mobility ``lam`` (default 1)."""
     geom = Geometry(prob)
     nx, ny, mx, my = geom.nx, geom.ny, geom.mx, geom.my

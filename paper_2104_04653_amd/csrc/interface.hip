@@ -44,18 +44,21 @@ __device__ inline double gather_entry(const NodeDesc& nd, const double* tree, in
   return v;
 }
 
+// 2-D thread map used by the element loops below (no integer division):
+// 32 columns x 8 rows per pass.
+constexpr int TXN = 32, TYN = NT / TXN;
+
 __global__ void __launch_bounds__(NT) front_small_kernel(const NodeDesc* nodes, const int* ids,
                                                          double* tree, const int2* maps,
                                                          int* status) {
   extern __shared__ double F[];
   const NodeDesc nd = nodes[ids[blockIdx.x]];
   const int n = nd.n, s = nd.s, ld = n + 1;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, tx = tid % TXN, ty = tid / TXN;
   const int2* mp = maps + nd.map_off;
-  for (int e = tid; e < n * ld; e += NT) {
-    const int a = e / ld, b = e % ld;
+  for (int a = ty; a < n; a += TYN) {
     const int2 ma = mp[a];
-    F[e] = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
+    for (int b = tx; b <= n; b += TXN) F[a * ld + b] = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
   }
   __syncthreads();
   bool bad = false;
@@ -65,15 +68,15 @@ __global__ void __launch_bounds__(NT) front_small_kernel(const NodeDesc* nodes, 
     const double ip = 1.0 / piv;
     for (int a = k + 1 + tid; a < n; a += NT) F[a * ld + k] *= ip;
     __syncthreads();
-    const int w = ld - (k + 1), h = n - (k + 1);
-    for (int e = tid; e < h * w; e += NT) {
-      const int a = k + 1 + e / w, b = k + 1 + e % w;
-      F[a * ld + b] -= F[a * ld + k] * F[k * ld + b];
+    for (int a = k + 1 + ty; a < n; a += TYN) {
+      const double f = F[a * ld + k];
+      for (int b = k + 1 + tx; b <= n; b += TXN) F[a * ld + b] -= f * F[k * ld + b];
     }
     __syncthreads();
   }
   double* out = tree + nd.f_off;
-  for (int e = tid; e < n * ld; e += NT) out[e] = F[e];
+  for (int a = ty; a < n; a += TYN)
+    for (int b = tx; b <= n; b += TXN) out[(long long)a * ld + b] = F[a * ld + b];
   if (bad && tid == 0) atomicOr(status, ST_IFACE_PIVOT);
 }
 
@@ -85,68 +88,72 @@ __global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes,
   const int n = nd.n, ld = n + 1;
   const int2* mp = maps + nd.map_off;
   const int r0 = it.y, r1 = min(n, r0 + 16);
+  const int tx = threadIdx.x % TXN, ty = threadIdx.x / TXN;
   double* F = tree + nd.f_off;
-  for (int e = threadIdx.x; e < (r1 - r0) * ld; e += NT) {
-    const int a = r0 + e / ld, b = e % ld;
+  for (int a = r0 + ty; a < r1; a += TYN) {
     const int2 ma = mp[a];
-    F[(long long)a * ld + b] = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
+    for (int b = tx; b <= n; b += TXN)
+      F[(long long)a * ld + b] = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
   }
 }
 
 // Diagonal block of panel k0 of a blocked front: LU without pivoting in
 // LDS, written back in place, plus the explicit inverses of its unit lower
 // factor L11 and its upper factor U11 (stored per panel in `inv`).  One
-// work-group per front.
+// work-group per front; each inverse column is built in registers by one
+// thread.
 __global__ void __launch_bounds__(NT) front_diag_kernel(const NodeDesc* nodes, const int* ids,
                                                         int k0, double* tree, double* inv,
                                                         int* status) {
   __shared__ double A[PANEL_NB][PANEL_NB + 1];
-  __shared__ double Li[PANEL_NB][PANEL_NB + 1];
-  __shared__ double Ui[PANEL_NB][PANEL_NB + 1];
   const NodeDesc nd = nodes[ids[blockIdx.x]];
   const int ld = nd.n + 1;
   const int nb = min(PANEL_NB, nd.s - k0);
   double* F = tree + nd.f_off;
-  const int t = threadIdx.x;
-  for (int e = t; e < nb * nb; e += NT) A[e / nb][e % nb] = F[(long long)(k0 + e / nb) * ld + k0 + e % nb];
+  const int t = threadIdx.x, tx = t % TXN, ty = t / TXN;
+  for (int i = ty; i < PANEL_NB; i += TYN)
+    A[i][tx] = (i < nb && tx < nb) ? F[(long long)(k0 + i) * ld + k0 + tx]
+             : (i == tx ? 1.0 : 0.0);   // identity padding of a partial panel
   __syncthreads();
   bool bad = false;
   for (int k = 0; k < nb; ++k) {
     const double piv = A[k][k];
     if (piv == 0.0 || !isfinite(piv)) bad = true;
-    for (int i = k + 1 + t; i < nb; i += NT) A[i][k] /= piv;
+    if (t > k && t < PANEL_NB) A[t][k] /= piv;
     __syncthreads();
-    const int w = nb - k - 1;
-    for (int e = t; e < w * w; e += NT) {
-      const int i = k + 1 + e / w, j = k + 1 + e % w;
-      A[i][j] -= A[i][k] * A[k][j];
-    }
+    for (int i = k + 1 + ty; i < PANEL_NB; i += TYN)
+      if (tx > k) A[i][tx] -= A[i][k] * A[k][tx];
     __syncthreads();
   }
-  for (int e = t; e < nb * nb; e += NT) F[(long long)(k0 + e / nb) * ld + k0 + e % nb] = A[e / nb][e % nb];
-  // column j of L11^{-1} (unit lower) and of U11^{-1} (upper), one thread each
-  if (t < nb) {
-    const int j = t;
-    for (int i = 0; i < nb; ++i) Li[i][j] = 0.0, Ui[i][j] = 0.0;
-    Li[j][j] = 1.0;
-    for (int i = j + 1; i < nb; ++i) {
-      double v = 0.0;
-      for (int m = j; m < i; ++m) v -= A[i][m] * Li[m][j];
-      Li[i][j] = v;
-    }
-    Ui[j][j] = 1.0 / A[j][j];
-    for (int i = j - 1; i >= 0; --i) {
-      double v = 0.0;
-      for (int m = i + 1; m <= j; ++m) v -= A[i][m] * Ui[m][j];
-      Ui[i][j] = v / A[i][i];
-    }
-  }
-  __syncthreads();
+  for (int i = ty; i < nb; i += TYN)
+    if (tx < nb) F[(long long)(k0 + i) * ld + k0 + tx] = A[i][tx];
   double* out = inv + nd.inv_off + (long long)(k0 / PANEL_NB) * 2 * PANEL_NB * PANEL_NB;
-  for (int e = t; e < PANEL_NB * PANEL_NB; e += NT) {
-    const int i = e / PANEL_NB, j = e % PANEL_NB;
-    out[e] = (i < nb && j < nb) ? Li[i][j] : 0.0;
-    out[PANEL_NB * PANEL_NB + e] = (i < nb && j < nb) ? Ui[i][j] : 0.0;
+  if (t < PANEL_NB) {
+    // column j = t of L11^{-1} (unit lower): forward substitution of e_j
+    const int j = t;
+    double x[PANEL_NB];
+#pragma unroll
+    for (int i = 0; i < PANEL_NB; ++i) {
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int m = 0; m < i; ++m) v -= A[i][m] * x[m];
+      x[i] = (i < j) ? 0.0 : v;
+    }
+#pragma unroll
+    for (int i = 0; i < PANEL_NB; ++i) out[i * PANEL_NB + j] = x[i];
+  } else if (t >= 64 && t < 64 + PANEL_NB) {
+    // column j of U11^{-1} (upper): back substitution of e_j
+    const int j = t - 64;
+    double x[PANEL_NB];
+#pragma unroll
+    for (int i = PANEL_NB - 1; i >= 0; --i) {
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int m = i + 1; m < PANEL_NB; ++m) v -= A[i][m] * x[m];
+      x[i] = (i > j) ? 0.0 : v / A[i][i];
+    }
+#pragma unroll
+    for (int i = 0; i < PANEL_NB; ++i) out[PANEL_NB * PANEL_NB + i * PANEL_NB + j] = x[i];
   }
   if (bad && t == 0) atomicOr(status, ST_IFACE_PIVOT);
 }
@@ -192,13 +199,15 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
   for (int e = t; e < TILE * PANEL_NB; e += NT) {
     const int i = e / PANEL_NB, k = e % PANEL_NB;
     double v = 0.0;
-    for (int m = 0; m <= k; ++m) v += As[i][m] * Ui[m][k];
+#pragma unroll 8
+    for (int m = 0; m < PANEL_NB; ++m) v += As[i][m] * Ui[m][k];
     Ls[i][k] = v;
   }
   for (int e = t; e < PANEL_NB * TILE; e += NT) {
     const int k = e / TILE, j = e % TILE;
     double v = 0.0;
-    for (int m = 0; m <= k; ++m) v += Li[k][m] * Bs[m][j];
+#pragma unroll 8
+    for (int m = 0; m < PANEL_NB; ++m) v += Li[k][m] * Bs[m][j];
     Us[k][j] = v;
   }
   __syncthreads();
@@ -240,11 +249,16 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
   for (int m = s + t; m < n; m += NT) xl[m] = x[dof[m]];
   __syncthreads();
   if (!nd.blocked) {
-    for (int k = t; k < s; k += NT) {
-      const double* row = F + (long long)k * ld;
-      double v = row[n];
-      for (int m = s; m < n; ++m) v -= row[m] * xl[m];
-      xl[k] = v;
+    for (int k0 = 0; k0 < s; k0 += NT / 8) {
+      const int k = k0 + t / 8, lane = t % 8;
+      double v = 0.0;
+      if (k < s) {
+        const double* row = F + (long long)k * ld;
+        for (int m = s + lane; m < n; m += 8) v -= row[m] * xl[m];
+        if (lane == 0) v += row[n];
+      }
+      for (int off = 4; off > 0; off >>= 1) v += __shfl_down(v, off, 8);
+      if (k < s && lane == 0) xl[k] = v;
     }
     __syncthreads();
     for (int k = s - 1; k >= 0; --k) {

@@ -124,6 +124,21 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
 }
 
 
+// (hi, lo) += a * b in double-double arithmetic: the product is split
+// exactly with an FMA and added with an error-free two-sum, so a residual
+// b - A x accumulated this way carries about twice the FP64 precision
+// (used by the iterative refinement of the local solves).
+__device__ inline void dd_fma(double& hi, double& lo, double a, double b) {
+#pragma clang fp contract(off)
+  const double p = a * b;
+  const double pe = fma(a, b, -p);
+  const double s = hi + p;
+  const double bb = s - hi;
+  const double se = (hi - (s - bb)) + (p - bb);
+  hi = s;
+  lo += pe + se;
+}
+
 template <int M>
 __device__ void load_kappa(const SubArgs& a, int I, int J, double* kap) {
   const Geo& g = a.g;

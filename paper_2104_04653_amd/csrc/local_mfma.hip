@@ -248,6 +248,93 @@ __global__ void __launch_bounds__(WAVE) basis_m16d4_kernel(SubArgs a) {
   }
   if (bad) atomicOr(a.status, ST_LOCAL_PIVOT);
 
+  // one step of iterative refinement of all 17 columns: residual
+  // R = B - A X in double-double (tile by tile, the in-row neighbours through
+  // an LDS staging tile), correction by the same block sweeps with the
+  // stored inverse blocks
+  {
+    __shared__ double T[M][M + 1];
+    __shared__ double zc[MM];
+    d4 Zc[M];
+    d4 zq = {0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[4 * v + gq][c] = Xv[j][v];
+      __syncthreads();
+      d4 r, rp;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * v + gq, l = j * M + i;
+        double hi = side_rhs(bside, j, i, c), lo = 0.0;
+        double ph = b0[l], pl = 0.0;
+        dd_fma(hi, lo, -dg[l], Xv[j][v]);
+        dd_fma(ph, pl, -dg[l], pz[l]);
+        if (i < M - 1) { dd_fma(hi, lo, -ex[l], T[i + 1][c]); dd_fma(ph, pl, -ex[l], pz[l + 1]); }
+        if (i > 0) { dd_fma(hi, lo, -ex[l - 1], T[i - 1][c]); dd_fma(ph, pl, -ex[l - 1], pz[l - 1]); }
+        if (j < M - 1) { dd_fma(hi, lo, -cy[l], Xv[j < M - 1 ? j + 1 : j][v]); dd_fma(ph, pl, -cy[l], pz[l + M]); }
+        if (j > 0) {
+          dd_fma(hi, lo, -cy[l - M], Xv[j > 0 ? j - 1 : 0][v]);
+          dd_fma(ph, pl, -cy[l - M], pz[l - M]);
+        }
+        double rr = hi + lo, rq = ph + pl;
+        if (j > 0) {
+          rr -= cy[(j - 1) * M + i] * Zc[j > 0 ? j - 1 : 0][v];
+          rq -= cy[(j - 1) * M + i] * zq[v];
+        }
+        r[v] = rr;
+        rp[v] = rq;
+      }
+      __syncthreads();
+      d4 z = {0.0, 0.0, 0.0, 0.0}, zz = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        z = mfma(Sv[j][kk], r[kk], z);
+        zz = mfma(Sv[j][kk], rp[kk], zz);
+      }
+      Zc[j] = z;
+      zq = zz;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) zc[j * M + 4 * v + gq] = zz[v];
+      }
+    }
+    __syncthreads();
+    d4 cn = Zc[M - 1], cq = zq;
+    Xv[M - 1] += cn;
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pz[(M - 1) * M + 4 * v + gq] += cq[v];
+    }
+#pragma unroll
+    for (int j = M - 2; j >= 0; --j) {
+      d4 t, tq, xq;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * v + gq;
+        const double cc = -cy[j * M + i];
+        t[v] = cc * cn[v];
+        tq[v] = cc * cq[v];
+        xq[v] = zc[j * M + i];
+      }
+      d4 x = Zc[j];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        x = mfma(Sv[j][kk], t[kk], x);
+        xq = mfma(Sv[j][kk], tq[kk], xq);
+      }
+      cn = x;
+      cq = xq;
+      Xv[j] += x;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] += xq[v];
+      }
+    }
+    __syncthreads();
+  }
+
   // basis functions to global memory, column-major per subdomain
   double* Xg = a.X + (size_t)sd * R * MM;
 #pragma unroll
@@ -412,16 +499,18 @@ __global__ void __launch_bounds__(WAVE) stitch_m16d4_kernel(SubArgs a) {
   }
   if (bad) atomicOr(a.status, ST_STITCH_PIVOT);
   solve_column(Sv, bs_, ps, c, gq, cy);
-  // two steps of FP64 iterative refinement with the stored inverse blocks
-  for (int it = 0; it < 2; ++it) {
+  // iterative refinement with the stored inverse blocks, residual in
+  // double-double
+  for (int it = 0; it < 3; ++it) {
     for (int l = lane; l < MM; l += WAVE) {
       const int li = l % M, lj = l / M;
-      double ax = dg[l] * ps[l];
-      if (li < M - 1) ax += ex[l] * ps[l + 1];
-      if (li > 0) ax += ex[l - 1] * ps[l - 1];
-      if (lj < M - 1) ax += cy[l] * ps[l + M];
-      if (lj > 0) ax += cy[l - M] * ps[l - M];
-      rs[l] = bs_[l] - ax;
+      double hi = bs_[l], lo = 0.0;
+      dd_fma(hi, lo, -dg[l], ps[l]);
+      if (li < M - 1) dd_fma(hi, lo, -ex[l], ps[l + 1]);
+      if (li > 0) dd_fma(hi, lo, -ex[l - 1], ps[l - 1]);
+      if (lj < M - 1) dd_fma(hi, lo, -cy[l], ps[l + M]);
+      if (lj > 0) dd_fma(hi, lo, -cy[l - M], ps[l - M]);
+      rs[l] = hi + lo;
     }
     __syncthreads();
     solve_column(Sv, rs, dx, c, gq, cy);

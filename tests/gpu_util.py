@@ -32,6 +32,7 @@ def run_gpu(prob, s=None, lam=None, precision="fp64", extras=True):
         out["stats"] = sol.stats()
         if extras:
             out["coef"] = sol.interface_solution() if sol.n_dof else np.zeros(0)
+        if extras == True:  # noqa: E712 - "coef" asks for the coefficients only
             out["blocks"] = sol.local_blocks()
             out["basis"] = sol.basis()
     return out
