@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="gauss1024")
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--forms", default="fp64,fp32_ir",
+                    help="comma list of forms to time; the first one is the headline value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
     return ap.parse_args()
@@ -80,36 +81,52 @@ def main():
     uy = torch.empty(prob.nx * (prob.ny + 1), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
 
-    sol = MRCMSolver(prob, precision=args.precision)
     import ctypes
-    outs = [ctypes.c_void_p(t.data_ptr()) for t in (p, ux, uy)]
-    imb = ctypes.c_double()
 
-    def step(k):
-        sol.update_mobility(sats[k])
-        sol.solve()
-        rc = sol.lib.mrcm_fine_flux(sol.ctx, *outs, 1, ctypes.byref(imb))
-        sol._check(rc, "mrcm_fine_flux")
-        return sol.stats()
+    def run_form(precision):
+        sol = MRCMSolver(prob, precision=precision)
+        outs = [ctypes.c_void_p(t.data_ptr()) for t in (p, ux, uy)]
+        imb = ctypes.c_double()
 
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-    phase = {"local": [], "interface": [], "flux": []}
-    t0 = time.perf_counter()
-    for k in range(args.warmup, n_steps_total):
-        st = step(k)
-        phase["local"].append(st["ms_local"])
-        phase["interface"].append(st["ms_interface"])
-        phase["flux"].append(st["ms_flux"])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = 1e3 * dt / args.steps
-    value = prob.n_sub / (dt / args.steps)
-    avg = {k: float(np.mean(v)) for k, v in phase.items()}
+        def step(k):
+            sol.update_mobility(sats[k])
+            sol.solve()
+            rc = sol.lib.mrcm_fine_flux(sol.ctx, *outs, 1, ctypes.byref(imb))
+            sol._check(rc, "mrcm_fine_flux")
+            return sol.stats()
+
+        for k in range(args.warmup):
+            step(k)
+        torch.cuda.synchronize()
+        phase = {"local": [], "interface": [], "flux": []}
+        iters, fallbacks = 0, 0
+        t0 = time.perf_counter()
+        for k in range(args.warmup, n_steps_total):
+            st = step(k)
+            phase["local"].append(st["ms_local"])
+            phase["interface"].append(st["ms_interface"])
+            phase["flux"].append(st["ms_flux"])
+            iters = max(iters, st["ir_iters_max"])
+            fallbacks = max(fallbacks, st["fallbacks"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        n_dof = sol.n_dof
+        sol.close()
+        ms_step = 1e3 * dt / args.steps
+        return {"ms_per_step": ms_step, "subdomain_solves_per_s": prob.n_sub / (dt / args.steps),
+                "phases_ms": {k: float(np.mean(v)) for k, v in phase.items()},
+                "max_cell_imbalance": imb.value, "ir_iters_max": iters,
+                "fp64_fallbacks_max": fallbacks, "n_dof": n_dof}
+
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    results = {f: run_form(f) for f in forms}
+    head = results[forms[0]]
+    ms_step = head["ms_per_step"]
+    value = head["subdomain_solves_per_s"]
+    avg = head["phases_ms"]
     # roofline kernel: the per-subdomain basis kernel (assembly + factor +
-    # 17-column solve + traces, FP64 MFMA), timed by the library's HIP events
-    # on its stream
+    # 17-column solve + refinement + traces, FP64 MFMA), timed by the
+    # library's HIP events on its stream
     alg_flop = prob.n_sub * (FLOP_FACTOR_SD + FLOP_SOLVE17_SD)
     achieved = alg_flop / (avg["local"] * 1e-3) / 1e12
     out = {
@@ -131,11 +148,11 @@ def main():
                         "from synthetic front saturations, linear interface spaces (2+2 dofs), "
                         "alpha 1, %d interface unknowns"
                         % (args.workload, prob.nx, prob.ny, prob.n_sub, prob.sub_nx, prob.sub_ny,
-                           args.seed, sol.n_dof),
-            "precision": args.precision,
+                           args.seed, head["n_dof"]),
+            "headline_form": forms[0],
         },
         "phases_ms": avg,
-        "max_cell_imbalance": imb.value,
+        "max_cell_imbalance": head["max_cell_imbalance"],
         "roofline": {
             "kernel": "basis_m16d4_kernel",
             "bound": "mfma",
@@ -145,10 +162,9 @@ def main():
             "frac": achieved / PEAK_FP64_TFLOPS,
             "traffic": None,
         },
-        "forms": {"fp64": {"ms_per_step": ms_step, "subdomain_solves_per_s": value},
-                  "fp32_ir": None, "surrogate": None},
+        "forms": {"fp64": results.get("fp64"), "fp32_ir": results.get("fp32_ir"),
+                  "surrogate": None},
     }
-    sol.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, sats[0].cpu().numpy())
     print(json.dumps(out), flush=True)

@@ -56,6 +56,8 @@ struct mrcm_ctx {
   double *p = nullptr, *ux = nullptr, *uy = nullptr, *sub_stats = nullptr, *result = nullptr;
   double* tree = nullptr;
   int* status = nullptr;
+  int* fallback = nullptr;     // FP32 refinement: count + list of subdomains
+  int* ir_iters = nullptr;
   NodeDesc* d_nodes = nullptr;
   int2* d_maps = nullptr;
   int* d_dofs = nullptr;
@@ -399,10 +401,14 @@ SubArgs sub_args(const mrcm_ctx* c) {
   a.uy = c->uy;
   a.sub_stats = c->sub_stats;
   a.status = c->status;
+  a.fallback = c->fallback;
+  a.ir_iters = c->ir_iters;
   return a;
 }
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
+
+__global__ void zero_ints_kernel(int* a, int* b, int* c) { *a = 0; *b = 0; *c = 0; }
 
 int run_interface(mrcm_ctx* c) {
   hipStream_t st = c->st;
@@ -454,7 +460,8 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
     return MRCM_E_INVAL;
   }
   if (precision != MRCM_PREC_FP64 && precision != MRCM_PREC_FP32_IR) return MRCM_E_INVAL;
-  if (precision != MRCM_PREC_FP64) return MRCM_E_UNSUPPORTED;
+  if (precision == MRCM_PREC_FP32_IR && !(M == 16 && p_dofs == 2 && u_dofs == 2))
+    return MRCM_E_UNSUPPORTED;
   if (!finite_pos(fluid->mu_w) || !finite_pos(fluid->mu_o)) return MRCM_E_INVAL;
   for (int s = 0; s < 4; ++s)
     if (bc->kind[s] != MRCM_BC_NEUMANN && bc->kind[s] != MRCM_BC_DIRICHLET) return MRCM_E_INVAL;
@@ -490,6 +497,7 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
   bool any_dir = false;
   for (int s = 0; s < 4; ++s) { G.kind[s] = bc->kind[s]; any_dir |= bc->kind[s] == MRCM_BC_DIRICHLET; }
   G.gauge = any_dir ? 0 : 1;
+  G.prec = precision == MRCM_PREC_FP32_IR ? 1 : 0;
   {
     const char* gen = getenv("MRCM_GENERIC_KERNELS");
     G.generic = (gen && gen[0] == '1') ? 1 : 0;
@@ -526,6 +534,8 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
     ALLOC(c, c->sub_stats, 3 * G.n_sub);
     ALLOC(c, c->result, 8);
     ALLOC(c, c->status, 1);
+    ALLOC(c, c->fallback, G.n_sub + 1);
+    ALLOC(c, c->ir_iters, 1);
     HIPCHK(c, hipMemcpy(c->K, perm, ncell * sizeof(double), hipMemcpyHostToDevice));
     {
       std::vector<double> ones(ncell, 1.0);
@@ -614,7 +624,7 @@ int mrcm_update_mobility(mrcm_ctx* c, const double* values, int32_t values_are_l
 int mrcm_solve(mrcm_ctx* c) {
   if (!c) return MRCM_E_INVAL;
   hipStream_t st = c->st;
-  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, c->status);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(1), 0, st, c->status, c->fallback, c->ir_iters);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(c->ev[0], st));
   SubArgs a = sub_args(c);
@@ -625,9 +635,13 @@ int mrcm_solve(mrcm_ctx* c) {
     if (r != MRCM_OK) return r;
   }
   HIPCHK(c, hipEventRecord(c->ev[2], st));
-  int status = 0;
+  int status = 0, nfb = 0, iters = 0;
   double res[2] = {0.0, 0.0};
   HIPCHK(c, hipMemcpyAsync(&status, c->status, sizeof(int), hipMemcpyDeviceToHost, st));
+  if (c->g.prec == 1) {
+    HIPCHK(c, hipMemcpyAsync(&nfb, c->fallback, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(&iters, c->ir_iters, sizeof(int), hipMemcpyDeviceToHost, st));
+  }
   if (c->n_dof > 0)
     HIPCHK(c, hipMemcpyAsync(res, c->result + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(c, hipStreamSynchronize(st));
@@ -637,6 +651,8 @@ int mrcm_solve(mrcm_ctx* c) {
   c->stats.ms_local = t1;
   c->stats.ms_interface = t2;
   c->stats.interface_residual = res[1] > 0.0 ? res[0] / res[1] : 0.0;
+  c->stats.fallbacks = nfb;
+  c->stats.ir_iters_max = iters;
   if (status & ST_BAD_LAMBDA) return fail(c, MRCM_E_INVAL, "mobility not finite and positive");
   if (status & (ST_LOCAL_PIVOT | ST_IFACE_PIVOT))
     return fail(c, MRCM_E_NOT_SPD, "non-positive or zero pivot in the elimination");

@@ -473,8 +473,15 @@ hipError_t launch_pair(const SubArgs& a, hipStream_t st, bool stitch) {
 
 hipError_t dispatch(const SubArgs& a, hipStream_t st, bool stitch) {
   const int M = a.g.M, D = a.g.D;
-  if (M == 16 && D == 4 && a.g.nP == 2 && !a.g.generic)
-    return stitch ? launch_stitch_m16d4(a, st) : launch_basis_m16d4(a, st);
+  if (M == 16 && D == 4 && a.g.nP == 2 && !a.g.generic) {
+    if (stitch) return launch_stitch_m16d4(a, st);
+    if (a.g.prec == 1) {
+      hipError_t e = launch_basis32_m16d4(a, st);
+      if (e != hipSuccess) return e;
+      return launch_basis_m16d4_list(a, st);   // FP64 re-solve of the listed subdomains
+    }
+    return launch_basis_m16d4(a, st);
+  }
   if (M == 16 && D == 4) return launch_pair<16, 4>(a, st, stitch);
   if (M == 8 && D == 4) return launch_pair<8, 4>(a, st, stitch);
   if (M == 4 && D == 4) return launch_pair<4, 4>(a, st, stitch);

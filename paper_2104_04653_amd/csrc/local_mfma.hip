@@ -151,13 +151,72 @@ __device__ inline void solve_column(const d4* Sv, const double* rhs, double* out
   __syncthreads();
 }
 
+// Traces of every column on the skeleton faces (xb: solution in the cells
+// next to each side's faces) projected on the interface functions: the
+// subdomain's block of the interface system, rows of flux dofs negated
+// (symmetric form), last column = right-hand side.
+__device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const double* kap,
+                                   const double (*xb)[M][R]) {
+  const Geo& g = a.g;
+  const int lane = threadIdx.x;
+  constexpr int NBR = 4 * D, NBC = 4 * D + 1;
+  double* blk = a.blocks + (size_t)sd * NBR * NBC;
+  const int nP = g.nP;
+  int e0side = -1;
+  bool e0lo = false;
+  if (g.gauge) {
+    for (int side = 0; side < 4; ++side)
+      if (side_iface(g, I, J, side) == 0) { e0side = side; e0lo = side_sigma(side) > 0; }
+  }
+  for (int o = lane; o < NBR * NBC; o += WAVE) {
+    const int r = o / NBC, qc = o % NBC;
+    const int side = r / D, k = r % D;
+    const int e = side_iface(g, I, J, side);
+    double val = 0.0;
+    if (e >= 0) {
+      const int col = (qc < NBR) ? 1 + qc : 0;
+      const SideGeo sg = side_geo(g, side);
+      const double al = a.alpha[e];
+      const double sig = side_sigma(side);
+      const double* bs = a.basis + (size_t)e * D * M;
+      const bool colside = col >= 1 + side * D && col < 1 + side * D + D;
+      const int kc = col - 1 - side * D;
+      double sum = 0.0;
+      for (int t = 0; t < M; ++t) {
+        const double kk = kap[side_cell<M>(side, t)];
+        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
+        const double beta = al * sg.H / kk;
+        double gv = 0.0;
+        if (colside) gv = (kc < nP) ? bs[kc * M + t] : -beta * sig * bs[kc * M + t];
+        const double F = TR * (xb[side][t][col] - gv);
+        if (k < nP) sum += bs[k * M + t] * F;
+        else sum += bs[k * M + t] * (gv + beta * F / sg.flen);
+      }
+      const double natural = (k < nP) ? sum : sig * sg.flen * sum;
+      const double sgn = (k < nP) ? 1.0 : -1.0;
+      val = (qc < NBR) ? sgn * natural : -sgn * natural;
+      if (e0side >= 0) {
+        const int r0 = e0side * D;
+        if (r == r0) val = (qc == r0 && e0lo) ? 1.0 : 0.0;
+        else if (qc == r0) val = 0.0;
+      }
+    }
+    blk[o] = val;
+  }
+}
+
+template <bool LIST>
 __global__ void __launch_bounds__(WAVE) basis_m16d4_kernel(SubArgs a) {
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM], pz[MM];
   __shared__ double bside[4][M][D];
   __shared__ double xb[4][M][R];      // solution next to each side's faces, all columns
   const Geo& g = a.g;
   const int lane = threadIdx.x, c = lane & 15, gq = lane >> 4;
-  const int sd = blockIdx.x;
+  int sd = blockIdx.x;
+  if (LIST) {   // re-solve only the subdomains listed by the FP32 kernel
+    if ((int)blockIdx.x >= a.fallback[0]) return;
+    sd = a.fallback[1 + blockIdx.x];
+  }
   const int I = sd % g.SX, J = sd / g.SX;
 
   load_kappa<M>(a, I, J, kap);
@@ -363,52 +422,323 @@ __global__ void __launch_bounds__(WAVE) basis_m16d4_kernel(SubArgs a) {
   }
   __syncthreads();
 
-  // traces projected on the interface functions: the subdomain's block of
-  // the interface system (rows of flux dofs negated: symmetric form)
-  constexpr int NBR = 4 * D, NBC = 4 * D + 1;
-  double* blk = a.blocks + (size_t)sd * NBR * NBC;
-  const int nP = g.nP;
-  int e0side = -1;
-  bool e0lo = false;
-  if (g.gauge) {
-    for (int side = 0; side < 4; ++side)
-      if (side_iface(g, I, J, side) == 0) { e0side = side; e0lo = side_sigma(side) > 0; }
+  write_block(a, sd, I, J, kap, xb);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 factors and solves with FP64 iterative refinement (16 x 16, 2 + 2 dofs)
+// ---------------------------------------------------------------------------
+//
+// The local matrix is scaled symmetrically, A^ = Ds A Ds with Ds = diag(A)^-1/2,
+// which removes the permeability scale from the FP32 factorisation.  The
+// Schur blocks of A^ are inverted in FP32 (Gauss-Jordan in registers), and
+// both block sweeps run on v_mfma_f32_16x16x4f32, whose output layout puts
+// rows 4g .. 4g+3 of column c in lane c + 16 g (measured on the device).  The
+// solution is kept in FP64; every refinement step forms R = B - A X in FP64,
+// solves A^ y = Ds R in FP32 and adds Ds y.  A subdomain whose correction does
+// not fall below 1e-10 of its solution within IR_MAX steps, or whose FP32
+// pivots fail, is appended to a.fallback and re-solved in FP64.
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int IR_MAX = 8;
+constexpr double IR_DONE = 1e-12;     // relative size of the last correction: converged
+constexpr double IR_ACCEPT = 1e-10;   // ... accepted without the FP64 fallback
+
+__device__ inline float readlane_f(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+
+__device__ inline f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ inline f4 gauss_jordan16_f32(f4 s, int c, int g, bool& bad) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const int kg = k >> 2, kv = k & 3;                       // row k: group kg, register kv
+    const float p = readlane_f(s[kv], k + 16 * kg);
+    const float prow = __shfl(s[kv], c + 16 * kg);
+    float pcol[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pcol[v] = __shfl(s[v], k + 16 * g);   // S[4g+v][k]
+    if (!(p > 0.0f)) bad = true;
+    const float ip = 1.0f / p;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * g + v;
+      float nv;
+      if (row == k) nv = (c == k) ? ip : s[v] * ip;
+      else nv = (c == k) ? -pcol[v] * ip : fmaf(-pcol[v] * ip, prow, s[v]);
+      s[v] = nv;
+    }
   }
-  for (int o = lane; o < NBR * NBC; o += WAVE) {
-    const int r = o / NBC, qc = o % NBC;
-    const int side = r / D, k = r % D;
+  return s;
+}
+
+// scaled coupling between block rows j and j+1 at cell row i
+__device__ inline double chat(const double* cy, const double* dsc, int j, int i) {
+  return cy[j * M + i] * dsc[j * M + i] * dsc[(j + 1) * M + i];
+}
+
+// In-place solve of A^ W = W for the 16 basis columns (FP32, f32 output layout)
+__device__ inline void solve32_tiles(const f4* Sv, f4* W, int gq, const double* cy,
+                                     const double* dsc) {
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    f4 r = W[j];
+    if (j > 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) r[v] -= (float)chat(cy, dsc, j - 1, 4 * gq + v) * W[j > 0 ? j - 1 : 0][v];
+    }
+    f4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) z = mfma32(Sv[j][kk], r[kk], z);
+    W[j] = z;
+  }
+#pragma unroll
+  for (int j = M - 2; j >= 0; --j) {
+    f4 t;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] = -(float)chat(cy, dsc, j, 4 * gq + v) * W[j + 1][v];
+    f4 x = W[j];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) x = mfma32(Sv[j][kk], t[kk], x);
+    W[j] = x;
+  }
+}
+
+// the same for one column held in LDS (cell-major), replicated over the
+// 16 MFMA columns; `zs` is an LDS work array
+__device__ inline void solve32_col(const f4* Sv, float* col, float* zs, int c, int gq,
+                                   const double* cy, const double* dsc) {
+  f4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    f4 r;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * gq + v;
+      r[v] = col[j * M + i];
+      if (j > 0) r[v] -= (float)chat(cy, dsc, j - 1, i) * z[v];
+    }
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mfma32(Sv[j][kk], r[kk], acc);
+    z = acc;
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) zs[j * M + 4 * gq + v] = z[v];
+    }
+  }
+  __syncthreads();
+  f4 xn = z;
+  if (c == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) col[(M - 1) * M + 4 * gq + v] = xn[v];
+  }
+#pragma unroll
+  for (int j = M - 2; j >= 0; --j) {
+    f4 t, x;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * gq + v;
+      t[v] = -(float)chat(cy, dsc, j, i) * xn[v];
+      x[v] = zs[j * M + i];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) x = mfma32(Sv[j][kk], t[kk], x);
+    xn = x;
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) col[j * M + 4 * gq + v] = x[v];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+__global__ void __launch_bounds__(WAVE) basis32_m16d4_kernel(SubArgs a) {
+  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM], dsc[MM], px[MM];
+  __shared__ double bside[4][M][D];
+  __shared__ double T[M][M + 1];
+  __shared__ float pcol[MM], pzs[MM];
+  __shared__ double xb[4][M][R];
+  const Geo& g = a.g;
+  const int lane = threadIdx.x, c = lane & 15, gq = lane >> 4;
+  const int sd = blockIdx.x;
+  const int I = sd % g.SX, J = sd / g.SX;
+
+  load_kappa<M>(a, I, J, kap);
+  __syncthreads();
+  for (int l = lane; l < MM; l += WAVE)
+    assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, b0 + l, 1, nullptr);
+  {
+    const int side = lane >> 4, t = lane & 15;
     const int e = side_iface(g, I, J, side);
-    double val = 0.0;
-    if (e >= 0) {
-      const int col = (qc < NBR) ? 1 + qc : 0;
-      const SideGeo sg = side_geo(g, side);
-      const double al = a.alpha[e];
-      const double sig = side_sigma(side);
-      const double* bs = a.basis + (size_t)e * D * M;
-      const bool colside = col >= 1 + side * D && col < 1 + side * D + D;
-      const int kc = col - 1 - side * D;
-      double sum = 0.0;
-      for (int t = 0; t < M; ++t) {
+    for (int k = 0; k < D; ++k) {
+      double v = 0.0;
+      if (e >= 0) {
+        const SideGeo sg = side_geo(g, side);
+        const double al = a.alpha[e];
         const double kk = kap[side_cell<M>(side, t)];
         const double TR = sg.flen * kk / (sg.dist + al * sg.H);
         const double beta = al * sg.H / kk;
-        double gv = 0.0;
-        if (colside) gv = (kc < nP) ? bs[kc * M + t] : -beta * sig * bs[kc * M + t];
-        const double F = TR * (xb[side][t][col] - gv);
-        if (k < nP) sum += bs[k * M + t] * F;
-        else sum += bs[k * M + t] * (gv + beta * F / sg.flen);
+        double gv = a.basis[((size_t)e * D + k) * M + t];
+        if (k >= g.nP) gv = -beta * side_sigma(side) * gv;
+        v = TR * gv;
       }
-      const double natural = (k < nP) ? sum : sig * sg.flen * sum;
-      const double sgn = (k < nP) ? 1.0 : -1.0;
-      val = (qc < NBR) ? sgn * natural : -sgn * natural;
-      if (e0side >= 0) {
-        const int r0 = e0side * D;
-        if (r == r0) val = (qc == r0 && e0lo) ? 1.0 : 0.0;
-        else if (qc == r0) val = 0.0;
+      bside[side][t][k] = v;
+    }
+  }
+  __syncthreads();
+  for (int l = lane; l < MM; l += WAVE) dsc[l] = 1.0 / sqrt(dg[l]);
+  __syncthreads();
+
+  // FP32 inverse Schur blocks of the scaled matrix
+  f4 Sv[M];
+  bool bad = false;
+  {
+    f4 prev = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      f4 s;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * gq + v, l = j * M + row;
+        const double d = (row == c) ? 1.0
+                       : (row == c + 1) ? ex[j * M + c] * dsc[j * M + c] * dsc[l]
+                       : (c == row + 1) ? ex[l] * dsc[l] * dsc[j * M + c] : 0.0;
+        float sv = (float)d;
+        if (j > 0) sv -= (float)chat(cy, dsc, j - 1, row) * prev[v] * (float)chat(cy, dsc, j - 1, c);
+        s[v] = sv;
+      }
+      s = gauss_jordan16_f32(s, c, gq, bad);
+      Sv[j] = s;
+      prev = s;
+    }
+  }
+
+  // first solve: X = Ds A^-1 Ds B
+  d4 Xv[M];
+  f4 W[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * gq + v;
+      W[j][v] = (float)(dsc[j * M + row] * side_rhs(bside, j, row, c));
+    }
+  }
+  for (int l = lane; l < MM; l += WAVE) pcol[l] = (float)(dsc[l] * b0[l]);
+  __syncthreads();
+  solve32_tiles(Sv, W, gq, cy, dsc);
+  solve32_col(Sv, pcol, pzs, c, gq, cy, dsc);
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Xv[j][v] = dsc[j * M + 4 * gq + v] * (double)W[j][v];
+  }
+  for (int l = lane; l < MM; l += WAVE) px[l] = dsc[l] * (double)pcol[l];
+  __syncthreads();
+
+  // refinement: FP64 residual, FP32 correction
+  int used = 0;
+  double rel = 1.0;
+  for (int it = 0; it < IR_MAX; ++it) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[4 * gq + v][c] = Xv[j][v];
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * gq + v, l = j * M + i;
+        double r = side_rhs(bside, j, i, c);
+        r = fma(-dg[l], Xv[j][v], r);
+        if (i < M - 1) r = fma(-ex[l], T[i + 1][c], r);
+        if (i > 0) r = fma(-ex[l - 1], T[i - 1][c], r);
+        if (j < M - 1) r = fma(-cy[l], Xv[j < M - 1 ? j + 1 : j][v], r);
+        if (j > 0) r = fma(-cy[l - M], Xv[j > 0 ? j - 1 : 0][v], r);
+        W[j][v] = (float)(dsc[l] * r);
+      }
+      __syncthreads();
+    }
+    for (int l = lane; l < MM; l += WAVE) {
+      const int li = l % M, lj = l / M;
+      double r = fma(-dg[l], px[l], b0[l]);
+      if (li < M - 1) r = fma(-ex[l], px[l + 1], r);
+      if (li > 0) r = fma(-ex[l - 1], px[l - 1], r);
+      if (lj < M - 1) r = fma(-cy[l], px[l + M], r);
+      if (lj > 0) r = fma(-cy[l - M], px[l - M], r);
+      pcol[l] = (float)(dsc[l] * r);
+    }
+    __syncthreads();
+    solve32_tiles(Sv, W, gq, cy, dsc);
+    solve32_col(Sv, pcol, pzs, c, gq, cy, dsc);
+    double cmax = 0.0, xmax = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double dx = dsc[j * M + 4 * gq + v] * (double)W[j][v];
+        Xv[j][v] += dx;
+        cmax = fmax(cmax, fabs(dx));
+        xmax = fmax(xmax, fabs(Xv[j][v]));
       }
     }
-    blk[o] = val;
+    for (int l = lane; l < MM; l += WAVE) {
+      const double dx = dsc[l] * (double)pcol[l];
+      px[l] += dx;
+      cmax = fmax(cmax, fabs(dx));
+      xmax = fmax(xmax, fabs(px[l]));
+    }
+    __syncthreads();
+    cmax = wave_max(cmax);
+    xmax = wave_max(xmax);
+    used = it + 1;
+    rel = cmax / fmax(xmax, 1e-300);
+    if (rel <= IR_DONE) break;
   }
+  if (lane == 0) {
+    atomicMax(a.ir_iters, used);
+    if (bad || !(rel <= IR_ACCEPT)) {
+      const int q = atomicAdd(a.fallback, 1);
+      a.fallback[1 + q] = sd;
+    }
+  }
+
+  // basis functions to global memory (f32 layout: rows 4gq .. 4gq+3 of column c)
+  double* Xg = a.X + (size_t)sd * R * MM;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Xg[(size_t)(1 + c) * MM + j * M + 4 * gq + v] = Xv[j][v];
+  }
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    if (gq == 0) xb[0][j][1 + c] = Xv[j][0];
+    if (gq == 3) xb[1][j][1 + c] = Xv[j][3];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    xb[2][4 * gq + v][1 + c] = Xv[0][v];
+    xb[3][4 * gq + v][1 + c] = Xv[M - 1][v];
+  }
+  __syncthreads();
+  for (int l = lane; l < MM; l += WAVE) Xg[l] = px[l];
+  if (lane < M) {
+    xb[0][lane][0] = px[lane * M];
+    xb[1][lane][0] = px[lane * M + M - 1];
+    xb[2][lane][0] = px[lane];
+    xb[3][lane][0] = px[(M - 1) * M + lane];
+  }
+  __syncthreads();
+  write_block(a, sd, I, J, kap, xb);
 }
 
 // ---------------------------------------------------------------------------
@@ -579,7 +909,17 @@ __global__ void __launch_bounds__(WAVE) stitch_m16d4_kernel(SubArgs a) {
 }  // namespace
 
 hipError_t launch_basis_m16d4(const SubArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(basis_m16d4_kernel, dim3(a.g.n_sub), dim3(WAVE), 0, st, a);
+  hipLaunchKernelGGL(basis_m16d4_kernel<false>, dim3(a.g.n_sub), dim3(WAVE), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_basis_m16d4_list(const SubArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(basis_m16d4_kernel<true>, dim3(a.g.n_sub), dim3(WAVE), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_basis32_m16d4(const SubArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(basis32_m16d4_kernel, dim3(a.g.n_sub), dim3(WAVE), 0, st, a);
   return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ struct Geo {
   int gauge;        // 1: no Dirichlet side, first pressure dof pinned
   int generic;      // 1: use the generic per-subdomain kernels even where a
                     //    specialised one exists (host-side switch)
+  int prec;         // 0: FP64 local solves, 1: FP32 + FP64 iterative refinement
   double hx, hy;
 };
 
@@ -47,6 +48,8 @@ struct SubArgs {
   double* uy;             // nx*(ny+1)
   double* sub_stats;      // [sub][3]: max cell imbalance, max |F|, sum of p
   int* status;
+  int* fallback;          // FP32 refinement: [0] = count, [1..] = subdomains to redo in FP64
+  int* ir_iters;          // FP32 refinement: [0] = largest refinement count used
 };
 
 // Frontal-matrix node of the nested-dissection elimination of the
@@ -79,6 +82,10 @@ hipError_t launch_mobility(const double* in, double* lam, size_t n, int from_sat
 hipError_t launch_finish_flux(const SubArgs& a, double* result, hipStream_t st);
 // (local_mfma.hip) one wavefront per 16 x 16 subdomain, 2 + 2 interface dofs
 hipError_t launch_basis_m16d4(const SubArgs& a, hipStream_t st);
+// FP32 factors and solves with FP64 iterative refinement; subdomains that do
+// not converge are listed in a.fallback and re-solved by the FP64 kernel
+hipError_t launch_basis32_m16d4(const SubArgs& a, hipStream_t st);
+hipError_t launch_basis_m16d4_list(const SubArgs& a, hipStream_t st);
 hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st);
 bool local_supported(int M, int D);
 
