@@ -328,7 +328,7 @@ int build_plan(mrcm_ctx* c) {
       lp.gather_off = (int)gather.size();
       for (int q = 0; q < lp.count; ++q) {
         const NodeDesc& d = desc[ids[lp.ids_off + q]];
-        for (int r = 0; r < d.n; r += 16) gather.push_back(make_int2(ids[lp.ids_off + q], r));
+        for (int r = 0; r < d.n; r += PANEL_NB) gather.push_back(make_int2(ids[lp.ids_off + q], r));
       }
       lp.gather_count = (int)gather.size() - lp.gather_off;
       for (int k0 = 0; k0 < lp.max_s; k0 += PANEL_NB) {
@@ -343,7 +343,8 @@ int build_plan(mrcm_ctx* c) {
           diag.push_back(id);
           const int nb = std::min(PANEL_NB, d.s - k0);
           for (int r = k0 + nb; r < d.n; r += TILE)
-            for (int cc = k0 + nb; cc <= d.n; cc += TILE) items.push_back(PanelItem{id, r, cc, 0});
+            for (int cc = k0 + nb; cc <= d.n; cc += TILE)
+              items.push_back(PanelItem{id, r, cc, (r == k0 + nb && cc == k0 + nb && d.s > k0 + nb) ? 1 : 0});
         }
         pl.update_count = (int)items.size() - pl.update_off;
         pl.diag_count = (int)diag.size();
@@ -418,15 +419,13 @@ int run_interface(mrcm_ctx* c) {
                                    c->d_maps, c->status, st));
       continue;
     }
+    // the gather factors the first panel's diagonal block, each update the next one
     HIPCHK(c, launch_front_gather(c->d_nodes, c->d_gather + lp.gather_off, lp.gather_count, c->tree,
-                                  c->d_maps, st));
-    for (const PanelLaunch& pl : lp.panels) {
-      HIPCHK(c, launch_front_diag(c->d_nodes, c->d_ids + pl.diag_off, pl.diag_count, pl.k0, c->tree,
-                                  c->inv, c->status, st));
-      if (pl.update_count > 0)
+                                  c->d_maps, c->inv, c->status, st));
+    for (const PanelLaunch& pl : lp.panels)
+      if (pl.update_count > 0)   // the root's last panel has no trailing rows
         HIPCHK(c, launch_front_update(c->d_nodes, c->d_items + pl.update_off, pl.update_count,
-                                      pl.k0, c->tree, c->inv, st));
-    }
+                                      pl.k0, c->tree, c->inv, c->status, st));
   }
   for (auto it = c->levels.rbegin(); it != c->levels.rend(); ++it)
     HIPCHK(c, launch_front_back(c->d_nodes, c->d_ids + it->ids_off, it->count, c->tree, c->inv,

@@ -17,10 +17,12 @@
 // Fronts of up to SMALL_FRONT unknowns are gathered and eliminated by one
 // work-group in LDS.  Larger fronts (the few nodes near the root) are
 // gathered in global memory and eliminated by a right-looking blocked LU:
-// per panel of PANEL_NB columns, one launch factors the diagonal block and
-// stores the inverses of its two triangular factors, and one launch applies
-// the trailing update A22 -= (A21 U11^-1)(L11^-1 A12) in 64x64 tiles.  Back
-// substitution runs top down, one work-group per node.
+// the gather factors the first panel's diagonal block; then one launch per
+// panel of PANEL_NB columns applies the trailing update
+// A22 -= (A21 U11^-1)(L11^-1 A12) in 64x64 tiles, and the work-group whose
+// tile starts with the next panel's diagonal block factors it and stores the
+// inverses of its two triangular factors.  Back substitution runs top down,
+// one work-group per node.
 #include "mrcm_internal.h"
 
 #include <math.h>
@@ -80,42 +82,16 @@ __global__ void __launch_bounds__(NT) front_small_kernel(const NodeDesc* nodes, 
   if (bad && tid == 0) atomicOr(status, ST_IFACE_PIVOT);
 }
 
-// items: (node index, first row); each work-group gathers 16 rows of a front
-__global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes, const int2* items,
-                                                          double* tree, const int2* maps) {
-  const int2 it = items[blockIdx.x];
-  const NodeDesc nd = nodes[it.x];
-  const int n = nd.n, ld = n + 1;
-  const int2* mp = maps + nd.map_off;
-  const int r0 = it.y, r1 = min(n, r0 + 16);
-  const int tx = threadIdx.x % TXN, ty = threadIdx.x / TXN;
-  double* F = tree + nd.f_off;
-  for (int a = r0 + ty; a < r1; a += TYN) {
-    const int2 ma = mp[a];
-    for (int b = tx; b <= n; b += TXN)
-      F[(long long)a * ld + b] = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
-  }
-}
-
-// Diagonal block of panel k0 of a blocked front: LU without pivoting in
-// LDS, written back in place, plus the explicit inverses of its unit lower
-// factor L11 and its upper factor U11 (stored per panel in `inv`).  One
-// work-group per front; each inverse column is built in registers by one
-// thread.
-__global__ void __launch_bounds__(NT) front_diag_kernel(const NodeDesc* nodes, const int* ids,
-                                                        int k0, double* tree, double* inv,
-                                                        int* status) {
-  __shared__ double A[PANEL_NB][PANEL_NB + 1];
-  const NodeDesc nd = nodes[ids[blockIdx.x]];
-  const int ld = nd.n + 1;
-  const int nb = min(PANEL_NB, nd.s - k0);
-  double* F = tree + nd.f_off;
+// LU without pivoting of the diagonal block of a panel held in LDS
+// (identity-padded beyond nb), written back to F at (k0, k0), and the
+// explicit inverses of its unit lower factor L11 and upper factor U11,
+// stored for the panel in `out` (2 * PANEL_NB^2 doubles).  Every thread of
+// the work-group must call it; each inverse column is built in registers by
+// one thread.
+__device__ void factor_store_diag(double (*A)[PANEL_NB + 1], int nb, double* F, int ld, int k0,
+                                  double* out, bool& bad) {
   const int t = threadIdx.x, tx = t % TXN, ty = t / TXN;
-  for (int i = ty; i < PANEL_NB; i += TYN)
-    A[i][tx] = (i < nb && tx < nb) ? F[(long long)(k0 + i) * ld + k0 + tx]
-             : (i == tx ? 1.0 : 0.0);   // identity padding of a partial panel
   __syncthreads();
-  bool bad = false;
   for (int k = 0; k < nb; ++k) {
     const double piv = A[k][k];
     if (piv == 0.0 || !isfinite(piv)) bad = true;
@@ -127,10 +103,8 @@ __global__ void __launch_bounds__(NT) front_diag_kernel(const NodeDesc* nodes, c
   }
   for (int i = ty; i < nb; i += TYN)
     if (tx < nb) F[(long long)(k0 + i) * ld + k0 + tx] = A[i][tx];
-  double* out = inv + nd.inv_off + (long long)(k0 / PANEL_NB) * 2 * PANEL_NB * PANEL_NB;
   if (t < PANEL_NB) {
-    // column j = t of L11^{-1} (unit lower): forward substitution of e_j
-    const int j = t;
+    const int j = t;      // column j of L11^{-1} (unit lower): forward substitution of e_j
     double x[PANEL_NB];
 #pragma unroll
     for (int i = 0; i < PANEL_NB; ++i) {
@@ -142,8 +116,7 @@ __global__ void __launch_bounds__(NT) front_diag_kernel(const NodeDesc* nodes, c
 #pragma unroll
     for (int i = 0; i < PANEL_NB; ++i) out[i * PANEL_NB + j] = x[i];
   } else if (t >= 64 && t < 64 + PANEL_NB) {
-    // column j of U11^{-1} (upper): back substitution of e_j
-    const int j = t - 64;
+    const int j = t - 64; // column j of U11^{-1} (upper): back substitution of e_j
     double x[PANEL_NB];
 #pragma unroll
     for (int i = PANEL_NB - 1; i >= 0; --i) {
@@ -155,6 +128,62 @@ __global__ void __launch_bounds__(NT) front_diag_kernel(const NodeDesc* nodes, c
 #pragma unroll
     for (int i = 0; i < PANEL_NB; ++i) out[PANEL_NB * PANEL_NB + i * PANEL_NB + j] = x[i];
   }
+}
+
+__device__ inline double* panel_inv(double* inv, const NodeDesc& nd, int k0) {
+  return inv + nd.inv_off + (long long)(k0 / PANEL_NB) * 2 * PANEL_NB * PANEL_NB;
+}
+
+// items: (node index, first row); each work-group gathers PANEL_NB rows of
+// a blocked front.  The work-group of rows 0 .. PANEL_NB-1 also factors the
+// diagonal block of the first panel.
+__global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes, const int2* items,
+                                                          double* tree, const int2* maps,
+                                                          double* inv, int* status) {
+  __shared__ double A[PANEL_NB][PANEL_NB + 1];
+  const int2 it = items[blockIdx.x];
+  const NodeDesc nd = nodes[it.x];
+  const int n = nd.n, ld = n + 1;
+  const int2* mp = maps + nd.map_off;
+  const int r0 = it.y, r1 = min(n, r0 + PANEL_NB);
+  const int tx = threadIdx.x % TXN, ty = threadIdx.x / TXN;
+  double* F = tree + nd.f_off;
+  const bool first = (r0 == 0);
+  const int nb = min(PANEL_NB, nd.s);
+  for (int a = r0 + ty; a < r0 + PANEL_NB; a += TYN) {
+    if (a < r1) {
+      const int2 ma = mp[a];
+      for (int b = tx; b <= n; b += TXN) {
+        const double v = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
+        F[(long long)a * ld + b] = v;
+        if (first && b < PANEL_NB) A[a][b] = (a < nb && b < nb) ? v : (a == b ? 1.0 : 0.0);
+      }
+    } else if (first) {
+      A[a][tx] = (a == tx) ? 1.0 : 0.0;
+    }
+  }
+  if (first) {
+    bool bad = false;
+    factor_store_diag(A, nb, F, ld, 0, panel_inv(inv, nd, 0), bad);
+    if (bad && threadIdx.x == 0) atomicOr(status, ST_IFACE_PIVOT);
+  }
+}
+
+// Diagonal block of the first panel of blocked fronts (used when a front
+// is not gathered by front_gather_kernel).  One work-group per front.
+__global__ void __launch_bounds__(NT) front_diag_kernel(const NodeDesc* nodes, const int* ids,
+                                                        int k0, double* tree, double* inv,
+                                                        int* status) {
+  __shared__ double A[PANEL_NB][PANEL_NB + 1];
+  const NodeDesc nd = nodes[ids[blockIdx.x]];
+  const int ld = nd.n + 1;
+  const int nb = min(PANEL_NB, nd.s - k0);
+  double* F = tree + nd.f_off;
+  const int t = threadIdx.x, tx = t % TXN, ty = t / TXN;
+  for (int i = ty; i < PANEL_NB; i += TYN)
+    A[i][tx] = (i < nb && tx < nb) ? F[(long long)(k0 + i) * ld + k0 + tx] : (i == tx ? 1.0 : 0.0);
+  bool bad = false;
+  factor_store_diag(A, nb, F, ld, k0, panel_inv(inv, nd, k0), bad);
   if (bad && t == 0) atomicOr(status, ST_IFACE_PIVOT);
 }
 
@@ -166,7 +195,8 @@ __global__ void __launch_bounds__(NT) front_diag_kernel(const NodeDesc* nodes, c
 // what other tiles read.
 __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
                                                           const PanelItem* items, int k0,
-                                                          double* tree, const double* inv) {
+                                                          double* tree, double* inv,
+                                                          int* status) {
   __shared__ double Li[PANEL_NB][PANEL_NB + 1];
   __shared__ double Ui[PANEL_NB][PANEL_NB + 1];
   __shared__ double As[TILE][PANEL_NB + 1];   // A21 tile, then L21
@@ -178,7 +208,7 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
   const int n = nd.n, ld = n + 1;
   const int nb = min(PANEL_NB, nd.s - k0);
   double* F = tree + nd.f_off;
-  const double* iv = inv + nd.inv_off + (long long)(k0 / PANEL_NB) * 2 * PANEL_NB * PANEL_NB;
+  const double* iv = panel_inv(inv, nd, k0);
   const int t = threadIdx.x;
   const int r0 = it.i0, c0 = it.j0;
   const int rows = min(TILE, n - r0), cols = min(TILE, ld - c0);
@@ -221,13 +251,30 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
     for (int u = 0; u < 4; ++u)
       for (int v = 0; v < 4; ++v) acc[u][v] += lv[u] * uv[v];
   }
+  const bool next_diag = it.pad != 0;   // this tile starts with the next panel's diagonal block
+  __syncthreads();
   for (int u = 0; u < 4; ++u) {
     const int i = ty * 4 + u;
-    if (i >= rows) continue;
     for (int v = 0; v < 4; ++v) {
       const int j = tx * 4 + v;
-      if (j < cols) F[(long long)(r0 + i) * ld + c0 + j] -= acc[u][v];
+      double val = 0.0;
+      if (i < rows && j < cols) {
+        val = F[(long long)(r0 + i) * ld + c0 + j] - acc[u][v];
+        F[(long long)(r0 + i) * ld + c0 + j] = val;
+      }
+      if (next_diag && i < PANEL_NB && j < PANEL_NB) Li[i][j] = val;   // reuse as staging
     }
+  }
+  if (next_diag) {
+    const int k1 = k0 + nb, nb1 = min(PANEL_NB, nd.s - k1);
+    __syncthreads();
+    for (int e = t; e < PANEL_NB * PANEL_NB; e += NT) {
+      const int i = e / PANEL_NB, j = e % PANEL_NB;
+      if (!(i < nb1 && j < nb1)) Li[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    bool bad = false;
+    factor_store_diag(Li, nb1, F, ld, k1, panel_inv(inv, nd, k1), bad);
+    if (bad && t == 0) atomicOr(status, ST_IFACE_PIVOT);
   }
 }
 
@@ -405,8 +452,9 @@ hipError_t launch_front_small(const NodeDesc* nodes, const int* ids, int count, 
 }
 
 hipError_t launch_front_gather(const NodeDesc* nodes, const int2* items, int count, double* tree,
-                               const int2* maps, hipStream_t st) {
-  hipLaunchKernelGGL(front_gather_kernel, dim3(count), dim3(NT), 0, st, nodes, items, tree, maps);
+                               const int2* maps, double* inv, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(front_gather_kernel, dim3(count), dim3(NT), 0, st, nodes, items, tree, maps,
+                     inv, status);
   return hipGetLastError();
 }
 
@@ -418,9 +466,9 @@ hipError_t launch_front_diag(const NodeDesc* nodes, const int* ids, int count, i
 }
 
 hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count, int k0,
-                               double* tree, const double* inv, hipStream_t st) {
+                               double* tree, double* inv, int* status, hipStream_t st) {
   hipLaunchKernelGGL(front_update_kernel, dim3(count), dim3(NT), 0, st, nodes, items, k0, tree,
-                     inv);
+                     inv, status);
   return hipGetLastError();
 }
 

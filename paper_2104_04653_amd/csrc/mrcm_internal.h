@@ -71,7 +71,7 @@ struct NodeDesc {
 struct PanelItem {      // one work-group of a blocked trailing update
   int node;             // index into the node descriptor array
   int i0, j0;           // first row / column of the 64 x 64 tile
-  int pad;
+  int pad;              // 1: the tile starts with the next panel's diagonal block
 };
 
 // ---- launchers (local.hip) ----
@@ -93,11 +93,12 @@ bool local_supported(int M, int D);
 hipError_t launch_front_small(const NodeDesc* nodes, const int* ids, int count, int max_n,
                               double* tree, const int2* maps, int* status, hipStream_t st);
 hipError_t launch_front_gather(const NodeDesc* nodes, const int2* items, int count,
-                               double* tree, const int2* maps, hipStream_t st);
+                               double* tree, const int2* maps, double* inv, int* status,
+                               hipStream_t st);
 hipError_t launch_front_diag(const NodeDesc* nodes, const int* ids, int count, int k0,
                              double* tree, double* inv, int* status, hipStream_t st);
 hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count,
-                               int k0, double* tree, const double* inv, hipStream_t st);
+                               int k0, double* tree, double* inv, int* status, hipStream_t st);
 hipError_t launch_front_back(const NodeDesc* nodes, const int* ids, int count, const double* tree,
                              const double* inv, const int* dofs, double* x, hipStream_t st);
 // r = b - A x of the assembled interface system; partials: 2 doubles per
