@@ -29,6 +29,10 @@ METRIC = "MRCM Darcy ms/step, subdomain solves/s @1024²: FP64 vs FP32+IR vs sur
 FLOP_FACTOR_SD = 0.179e6
 FLOP_SOLVE17_SD = 0.418e6
 PEAK_FP64_TFLOPS = 78.6
+# BF16 network: 3x3 convolutions 5->32->32->32->16 on 256 cells, 2 FLOP per
+# multiply-add over the real (unpadded) channels
+CNN_FLOP_PATCH = 2 * 256 * 9 * (5 * 32 + 32 * 32 + 32 * 32 + 32 * 16)
+PEAK_BF16_TFLOPS = 2500.0
 
 
 def parse():
@@ -37,10 +41,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="gauss1024")
-    ap.add_argument("--forms", default="fp64,fp32_ir",
+    ap.add_argument("--forms", default="fp64,fp32_ir,surrogate",
                     help="comma list of forms to time; the first one is the headline value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--train-seconds", type=float, default=30.0,
+                    help="surrogate form: training time budget before the timed steps")
+    ap.add_argument("--train-fields", type=int, default=8,
+                    help="surrogate form: fields (half log-normal, half channelized) whose "
+                         "FP64 solves give the training patches")
+    ap.add_argument("--train-snapshots", type=int, default=3,
+                    help="surrogate form: saturation snapshots per training field")
     return ap.parse_args()
 
 
@@ -83,8 +94,47 @@ def main():
 
     import ctypes
 
+    surrogate_info = {}
+
+    def trained_surrogate():
+        """Network trained on patches of FP64 solves of other fields of the
+        same family (log-normal and channelized), outside the timed region."""
+        from paper_2104_04653_amd import SurrogateNet, surrogate
+        t0 = time.perf_counter()
+        cases = []
+        for k in range(args.train_fields):
+            if k % 2 == 0:
+                q = inputs.make_problem(args.workload, seed=1000 + k)
+            else:
+                q = inputs.make_problem("channel256_q5", seed=1000 + k, nx=prob.nx, ny=prob.ny)
+            for j in range(args.train_snapshots):
+                step = (k + 3 * j) % q.steps
+                cases.append((q, inputs.synthetic_saturation(q, step, q.steps)))
+        x, y = surrogate.method_patches(cases)
+        t_data = time.perf_counter() - t0
+        net = SurrogateNet(max(512, prob.n_sub), seed=args.seed)
+        n_hold = 512
+        t1 = time.perf_counter()
+        losses = surrogate.train(net, x[n_hold:], y[n_hold:], steps=100000, batch=256, lr=2e-3,
+                                 time_limit=args.train_seconds)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t1
+        surrogate_info.update({
+            "training_patches": int(x.shape[0] - n_hold), "data_s": t_data,
+            "train_steps": int(len(losses)), "train_s": t_train, "batch": 256,
+            "heldout_mse": surrogate.evaluate(net, x[:n_hold], y[:n_hold]),
+            "train_loss_first_last": [float(losses[0]), float(losses[-1])]})
+        del x, y
+        return net
+
+    last_p = {}
+
     def run_form(precision):
         sol = MRCMSolver(prob, precision=precision)
+        net = None
+        if precision == "surrogate":
+            net = trained_surrogate()
+            sol.set_surrogate(net)
         outs = [ctypes.c_void_p(t.data_ptr()) for t in (p, ux, uy)]
         imb = ctypes.c_double()
 
@@ -98,7 +148,7 @@ def main():
         for k in range(args.warmup):
             step(k)
         torch.cuda.synchronize()
-        phase = {"local": [], "interface": [], "flux": []}
+        phase = {"local": [], "interface": [], "flux": [], "surrogate_inference_gate": []}
         iters, fallbacks = 0, 0
         t0 = time.perf_counter()
         for k in range(args.warmup, n_steps_total):
@@ -106,17 +156,44 @@ def main():
             phase["local"].append(st["ms_local"])
             phase["interface"].append(st["ms_interface"])
             phase["flux"].append(st["ms_flux"])
+            phase["surrogate_inference_gate"].append(st["ms_surrogate"])
             iters = max(iters, st["ir_iters_max"])
             fallbacks = max(fallbacks, st["fallbacks"])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         n_dof = sol.n_dof
+        last_p[precision] = (p.clone(), torch.cat([ux, uy]))
+        extra = {}
+        if net is not None:
+            extra["training"] = dict(surrogate_info)
+            extra["cnn_forward"] = cnn_forward_rate(net, sol)
+            net.close()
         sol.close()
         ms_step = 1e3 * dt / args.steps
         return {"ms_per_step": ms_step, "subdomain_solves_per_s": prob.n_sub / (dt / args.steps),
                 "phases_ms": {k: float(np.mean(v)) for k, v in phase.items()},
                 "max_cell_imbalance": imb.value, "ir_iters_max": iters,
-                "fp64_fallbacks_max": fallbacks, "n_dof": n_dof}
+                "fp64_fallbacks_max": fallbacks, "fallback_rate": fallbacks / prob.n_sub,
+                "n_dof": n_dof, **extra}
+
+    def cnn_forward_rate(net, sol):
+        """BF16 network forward on all subdomains of the last step, timed
+        with events on the stream the network runs on."""
+        x = sol.surrogate_inputs()
+        net.forward(x)
+        times = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            net.forward(x)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.mean(times))
+        flop = prob.n_sub * CNN_FLOP_PATCH
+        return {"ms": ms, "tflops": flop / (ms * 1e-3) / 1e12, "peak_bf16_tflops": PEAK_BF16_TFLOPS,
+                "frac": flop / (ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
+                "flop_per_patch": CNN_FLOP_PATCH}
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     results = {f: run_form(f) for f in forms}
@@ -163,8 +240,15 @@ def main():
             "traffic": None,
         },
         "forms": {"fp64": results.get("fp64"), "fp32_ir": results.get("fp32_ir"),
-                  "surrogate": None},
+                  "surrogate": results.get("surrogate")},
     }
+    if "fp64" in last_p:
+        rp, rf = last_p["fp64"]
+        for f in forms:
+            if f != "fp64":
+                fp, ff = last_p[f]
+                out["forms"][f]["rel_l2_vs_fp64_last_step"] = {
+                    "p": float((fp - rp).norm() / rp.norm()), "flux": float((ff - rf).norm() / rf.norm())}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, sats[0].cpu().numpy())
     print(json.dumps(out), flush=True)

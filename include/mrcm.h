@@ -64,8 +64,12 @@ enum { MRCM_SPACE_LINEAR = 0, MRCM_SPACE_EDGE_SOLUTION = 1, MRCM_SPACE_FULL = 2 
 /* Precision of the local (subdomain) factorisations.  The interface system
  * is always solved in FP64.  FP32_IR: FP32 factors and solves, FP64
  * residuals and iterative refinement to 1e-12 relative, per-subdomain FP64
- * fallback when refinement stalls. */
-enum { MRCM_PREC_FP64 = 0, MRCM_PREC_FP32_IR = 1 };
+ * fallback when refinement stalls.  SURROGATE: the basis functions of each
+ * subdomain are predicted by the convolutional network set with
+ * mrcm_set_surrogate and accepted only if every column's FP64 residual in
+ * the local problem is below 1e-6 of its right-hand side; every other
+ * subdomain is solved by the FP64 path. */
+enum { MRCM_PREC_FP64 = 0, MRCM_PREC_FP32_IR = 1, MRCM_PREC_SURROGATE = 2 };
 
 typedef struct {
   int32_t nx, ny; /* cells; > 0 */
@@ -91,8 +95,9 @@ typedef struct {
   int32_t n_sub;         /* subdomains */
   int32_t n_dof;         /* interface unknowns */
   int32_t ir_iters_max;  /* FP32_IR: largest refinement count over subdomains */
-  int32_t fallbacks;     /* FP32_IR: subdomains re-solved in FP64 */
+  int32_t fallbacks;     /* FP32_IR / SURROGATE: subdomains re-solved in FP64 */
   double interface_residual; /* max |b - A x| / max |b| of the interface solve */
+  double ms_surrogate;   /* SURROGATE: network inference + residual gate */
 } mrcm_stats;
 
 /* Set up a solver for one grid, permeability field and decomposition
@@ -185,6 +190,66 @@ int mrcm_get_sizes(const mrcm_ctx* ctx, int32_t* n_dof, int32_t* n_sub, int32_t*
 int mrcm_get_interface_solution(mrcm_ctx* ctx, double* coeffs);
 int mrcm_get_local_blocks(mrcm_ctx* ctx, double* blocks);
 int mrcm_get_basis(mrcm_ctx* ctx, double* basis);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the local basis functions (not part of the paper's
+ * method; an approximation that the residual gate of MRCM_PREC_SURROGATE
+ * checks against the local problems of eq. (mrc1)).
+ *
+ * Network: four 3x3 convolutions, 5 -> 32 -> 32 -> 32 -> 16 channels on the
+ * 16 x 16 cells of a subdomain, ReLU after the first three; BF16 weights and
+ * activations, FP32 accumulation and FP32 master weights (Adam).  Tensors
+ * are channels-last: inputs BF16 [batch][256][8] (channels 5..7 zero),
+ * outputs and targets FP32 [batch][256][16].  Only 16 x 16 subdomains with
+ * 2 + 2 interface dofs are supported.
+ * Parameters (FP32, n = mrcm_cnn_num_params): for each layer l = 1..4 the
+ * weights [Cout][9 taps][Cin padded] (layer 1: Cin padded to 8 and taps
+ * padded to 10) followed by the Cout biases.
+ * ------------------------------------------------------------------------ */
+typedef struct mrcm_cnn mrcm_cnn;
+
+/* New network with He-normal weights from `seed`, zero biases, zero Adam
+ * state; workspace for batches up to max_batch.  hip_stream: NULL = own. */
+int mrcm_cnn_create(mrcm_cnn** out, int32_t max_batch, uint64_t seed, void* hip_stream);
+int mrcm_cnn_num_params(const mrcm_cnn* net, int32_t* n);
+/* Copy the FP32 parameters out of / into the network (host arrays). */
+int mrcm_cnn_get_params(mrcm_cnn* net, float* params);
+int mrcm_cnn_set_params(mrcm_cnn* net, const float* params);
+/* Forward pass (device pointers); synchronous. */
+int mrcm_cnn_forward(mrcm_cnn* net, const void* inputs, float* outputs, int32_t batch);
+/* Mean squared error against targets and its gradient with respect to the
+ * parameters (device inputs, host results; grads may be NULL). */
+int mrcm_cnn_loss_grad(mrcm_cnn* net, const void* inputs, const float* targets, int32_t batch,
+                       float* loss, float* grads);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on one batch; *loss
+ * (may be NULL) receives the batch loss before the step. */
+int mrcm_cnn_train_step(mrcm_cnn* net, const void* inputs, const float* targets, int32_t batch,
+                        float lr, float* loss);
+void mrcm_cnn_destroy(mrcm_cnn* net);
+
+/* Network inputs of every subdomain for the context's current mobility
+ * (device BF16 [n_sub][256][8]); synchronous. */
+int mrcm_surrogate_inputs(mrcm_ctx* ctx, void* inputs);
+/* Training targets from the last successful solve (device FP32
+ * [n_sub][256][16]); synchronous.  MRCM_E_STATE before a solve. */
+int mrcm_surrogate_targets(mrcm_ctx* ctx, float* targets);
+/* Copy the network's current parameters into a context set up with
+ * MRCM_PREC_SURROGATE (required before its first solve). */
+int mrcm_set_surrogate(mrcm_ctx* ctx, mrcm_cnn* net);
+
+/* Residual gate of a MRCM_PREC_SURROGATE context: a predicted subdomain is
+ * accepted only if every basis column x satisfies ||b - A x||_2 <= tol ||b||_2
+ * in its local problem (FP64 residual; default tol = 1e-6).  Note that the
+ * FP32 rounding of an exact basis function alone leaves a relative residual
+ * of order 1e-6 on 16 x 16 subdomains.  MRCM_E_INVAL unless 0 < tol < inf. */
+int mrcm_set_gate_tolerance(mrcm_ctx* ctx, double tol);
+
+/* mrcm_solve of a MRCM_PREC_SURROGATE context with the basis functions
+ * predicted elsewhere: predictions is a device array FP32 [n_sub][256][16]
+ * in the network's output form (mrcm_surrogate_targets) that must stay
+ * valid until the call returns.  The same residual gate and FP64 fallback
+ * apply; no network needs to be set. */
+int mrcm_solve_with_predictions(mrcm_ctx* ctx, const float* predictions);
 
 /* Text of the last error on this context (never NULL). */
 const char* mrcm_last_error(const mrcm_ctx* ctx);

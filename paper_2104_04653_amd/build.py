@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrcm.so")
-SOURCES = ["api.hip", "local.hip", "local_mfma.hip", "interface.hip"]
+SOURCES = ["api.hip", "local.hip", "local_mfma.hip", "interface.hip", "surrogate.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

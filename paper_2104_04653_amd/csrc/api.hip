@@ -66,12 +66,19 @@ struct mrcm_ctx {
   PanelItem* d_items = nullptr;
   double* inv = nullptr;        // per-panel triangular inverses of blocked fronts
   double* partials = nullptr;   // residual partial maxima
+  // surrogate precision: network parameters and per-subdomain activations
+  float* s_p32 = nullptr;
+  short* s_wb = nullptr;
+  short *s_in = nullptr, *s_a1 = nullptr, *s_a2 = nullptr, *s_a3 = nullptr;
+  float* s_pred = nullptr;
+  bool s_ready = false;
+  double gate_tol = 1e-6;
   std::vector<void*> allocs;
 
   // interface plan
   std::vector<LevelPlan> levels;
   long long leaf_block = 0;  // doubles per subdomain block
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -404,6 +411,7 @@ SubArgs sub_args(const mrcm_ctx* c) {
   a.status = c->status;
   a.fallback = c->fallback;
   a.ir_iters = c->ir_iters;
+  a.gate_tol = c->gate_tol;
   return a;
 }
 
@@ -458,8 +466,10 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
   } else {
     return MRCM_E_INVAL;
   }
-  if (precision != MRCM_PREC_FP64 && precision != MRCM_PREC_FP32_IR) return MRCM_E_INVAL;
-  if (precision == MRCM_PREC_FP32_IR && !(M == 16 && p_dofs == 2 && u_dofs == 2))
+  if (precision != MRCM_PREC_FP64 && precision != MRCM_PREC_FP32_IR &&
+      precision != MRCM_PREC_SURROGATE)
+    return MRCM_E_INVAL;
+  if (precision != MRCM_PREC_FP64 && !(M == 16 && p_dofs == 2 && u_dofs == 2))
     return MRCM_E_UNSUPPORTED;
   if (!finite_pos(fluid->mu_w) || !finite_pos(fluid->mu_o)) return MRCM_E_INVAL;
   for (int s = 0; s < 4; ++s)
@@ -496,7 +506,7 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
   bool any_dir = false;
   for (int s = 0; s < 4; ++s) { G.kind[s] = bc->kind[s]; any_dir |= bc->kind[s] == MRCM_BC_DIRICHLET; }
   G.gauge = any_dir ? 0 : 1;
-  G.prec = precision == MRCM_PREC_FP32_IR ? 1 : 0;
+  G.prec = precision;
   {
     const char* gen = getenv("MRCM_GENERIC_KERNELS");
     G.generic = (gen && gen[0] == '1') ? 1 : 0;
@@ -516,7 +526,7 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
       HIPCHK(c, hipStreamCreate(&c->st));
       c->own_stream = true;
     }
-    for (int i = 0; i < 4; ++i) HIPCHK(c, hipEventCreate(&c->ev[i]));
+    for (int i = 0; i < 5; ++i) HIPCHK(c, hipEventCreate(&c->ev[i]));
     HIPCHK(c, prepare_interface_kernels());
     ALLOC(c, c->K, ncell);
     ALLOC(c, c->lam, ncell);
@@ -535,6 +545,16 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
     ALLOC(c, c->status, 1);
     ALLOC(c, c->fallback, G.n_sub + 1);
     ALLOC(c, c->ir_iters, 1);
+    if (precision == MRCM_PREC_SURROGATE) {
+      const size_t pix = (size_t)G.n_sub * M * M;
+      ALLOC(c, c->s_p32, cnn::n_params());
+      ALLOC(c, c->s_wb, cnn::n_params());
+      ALLOC(c, c->s_in, pix * 8);
+      ALLOC(c, c->s_a1, pix * 32);
+      ALLOC(c, c->s_a2, pix * 32);
+      ALLOC(c, c->s_a3, pix * 32);
+      ALLOC(c, c->s_pred, pix * 16);
+    }
     HIPCHK(c, hipMemcpy(c->K, perm, ncell * sizeof(double), hipMemcpyHostToDevice));
     {
       std::vector<double> ones(ncell, 1.0);
@@ -620,14 +640,31 @@ int mrcm_update_mobility(mrcm_ctx* c, const double* values, int32_t values_are_l
   return MRCM_OK;
 }
 
-int mrcm_solve(mrcm_ctx* c) {
-  if (!c) return MRCM_E_INVAL;
+namespace {
+
+// one solve; with the surrogate precision `pred` (device, may be NULL)
+// replaces the network's output
+int solve_impl(mrcm_ctx* c, const float* pred) {
   hipStream_t st = c->st;
   hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(1), 0, st, c->status, c->fallback, c->ir_iters);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(c->ev[0], st));
   SubArgs a = sub_args(c);
-  HIPCHK(c, launch_local_basis(a, st));
+  if (c->precision == MRCM_PREC_SURROGATE) {
+    // network inference and residual gate, then the FP64 kernel on the
+    // subdomains the gate rejected
+    const int n = c->g.n_sub;
+    if (!pred) {
+      HIPCHK(c, launch_surrogate_inputs(a, c->s_in, st));
+      HIPCHK(c, cnn::forward(c->s_in, c->s_wb, c->s_p32, c->s_a1, c->s_a2, c->s_a3, c->s_pred, n, st));
+      pred = c->s_pred;
+    }
+    HIPCHK(c, launch_surrogate_gate(a, pred, st));
+    HIPCHK(c, hipEventRecord(c->ev[4], st));
+    HIPCHK(c, launch_basis_m16d4_list(a, st));
+  } else {
+    HIPCHK(c, launch_local_basis(a, st));
+  }
   HIPCHK(c, hipEventRecord(c->ev[1], st));
   if (c->n_dof > 0) {
     int r = run_interface(c);
@@ -637,7 +674,7 @@ int mrcm_solve(mrcm_ctx* c) {
   int status = 0, nfb = 0, iters = 0;
   double res[2] = {0.0, 0.0};
   HIPCHK(c, hipMemcpyAsync(&status, c->status, sizeof(int), hipMemcpyDeviceToHost, st));
-  if (c->g.prec == 1) {
+  if (c->g.prec != 0) {
     HIPCHK(c, hipMemcpyAsync(&nfb, c->fallback, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipMemcpyAsync(&iters, c->ir_iters, sizeof(int), hipMemcpyDeviceToHost, st));
   }
@@ -649,6 +686,12 @@ int mrcm_solve(mrcm_ctx* c) {
   (void)hipEventElapsedTime(&t2, c->ev[1], c->ev[2]);
   c->stats.ms_local = t1;
   c->stats.ms_interface = t2;
+  c->stats.ms_surrogate = 0.0;
+  if (c->precision == MRCM_PREC_SURROGATE) {
+    float ts = 0.f;
+    (void)hipEventElapsedTime(&ts, c->ev[0], c->ev[4]);
+    c->stats.ms_surrogate = ts;
+  }
   c->stats.interface_residual = res[1] > 0.0 ? res[0] / res[1] : 0.0;
   c->stats.fallbacks = nfb;
   c->stats.ir_iters_max = iters;
@@ -657,6 +700,23 @@ int mrcm_solve(mrcm_ctx* c) {
     return fail(c, MRCM_E_NOT_SPD, "non-positive or zero pivot in the elimination");
   c->solved = true;
   return MRCM_OK;
+}
+
+}  // namespace
+
+int mrcm_solve(mrcm_ctx* c) {
+  if (!c) return MRCM_E_INVAL;
+  if (c->precision == MRCM_PREC_SURROGATE && !c->s_ready)
+    return fail(c, MRCM_E_STATE, "surrogate precision: mrcm_set_surrogate was not called");
+  return solve_impl(c, nullptr);
+}
+
+int mrcm_solve_with_predictions(mrcm_ctx* c, const float* predictions) {
+  if (!c) return MRCM_E_INVAL;
+  if (!predictions) return fail(c, MRCM_E_INVAL, "predictions is NULL");
+  if (c->precision != MRCM_PREC_SURROGATE)
+    return fail(c, MRCM_E_STATE, "context was not set up with MRCM_PREC_SURROGATE");
+  return solve_impl(c, predictions);
 }
 
 int mrcm_fine_flux(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_device,
@@ -732,6 +792,52 @@ int mrcm_get_basis(mrcm_ctx* c, double* basis) {
   return MRCM_OK;
 }
 
+static bool surrogate_shape(const mrcm_ctx* c) {
+  return c->g.M == 16 && c->g.nP == 2 && c->g.nU == 2;
+}
+
+int mrcm_surrogate_inputs(mrcm_ctx* c, void* inputs) {
+  if (!c) return MRCM_E_INVAL;
+  if (!inputs) return fail(c, MRCM_E_INVAL, "inputs is NULL");
+  if (!surrogate_shape(c)) return fail(c, MRCM_E_UNSUPPORTED, "surrogate needs 16x16 subdomains, 2+2 dofs");
+  HIPCHK(c, launch_surrogate_inputs(sub_args(c), (short*)inputs, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return MRCM_OK;
+}
+
+int mrcm_surrogate_targets(mrcm_ctx* c, float* targets) {
+  if (!c) return MRCM_E_INVAL;
+  if (!targets) return fail(c, MRCM_E_INVAL, "targets is NULL");
+  if (!surrogate_shape(c)) return fail(c, MRCM_E_UNSUPPORTED, "surrogate needs 16x16 subdomains, 2+2 dofs");
+  if (!c->solved) return fail(c, MRCM_E_STATE, "no solve yet");
+  HIPCHK(c, launch_surrogate_targets(sub_args(c), targets, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return MRCM_OK;
+}
+
+int mrcm_set_gate_tolerance(mrcm_ctx* c, double tol) {
+  if (!c) return MRCM_E_INVAL;
+  if (!(tol > 0.0) || !isfinite(tol)) return fail(c, MRCM_E_INVAL, "gate tolerance must be finite and > 0");
+  if (c->precision != MRCM_PREC_SURROGATE)
+    return fail(c, MRCM_E_STATE, "context was not set up with MRCM_PREC_SURROGATE");
+  c->gate_tol = tol;
+  return MRCM_OK;
+}
+
+int mrcm_set_surrogate(mrcm_ctx* c, mrcm_cnn* net) {
+  if (!c) return MRCM_E_INVAL;
+  if (!net) return fail(c, MRCM_E_INVAL, "net is NULL");
+  if (c->precision != MRCM_PREC_SURROGATE)
+    return fail(c, MRCM_E_STATE, "context was not set up with MRCM_PREC_SURROGATE");
+  HIPCHK(c, hipStreamSynchronize(cnn::stream_of(net)));
+  HIPCHK(c, hipMemcpyAsync(c->s_p32, cnn::params_of(net), cnn::n_params() * sizeof(float),
+                           hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, cnn::cast(c->s_p32, c->s_wb, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->s_ready = true;
+  return MRCM_OK;
+}
+
 const char* mrcm_last_error(const mrcm_ctx* c) {
   if (!c) return "null context";
   return c->err.c_str();
@@ -741,7 +847,7 @@ void mrcm_destroy(mrcm_ctx* c) {
   if (!c) return;
   if (c->st) (void)hipStreamSynchronize(c->st);
   for (void* q : c->allocs) (void)hipFree(q);
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 5; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
   delete c;

@@ -906,6 +906,181 @@ __global__ void __launch_bounds__(WAVE) stitch_m16d4_kernel(SubArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// learned surrogate of the 16 basis functions: network inputs, training
+// targets and the FP64 residual gate (the network itself is in surrogate.hip)
+// ---------------------------------------------------------------------------
+
+__device__ inline short to_bf16(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// mean of ln kappa over the subdomain (every lane gets it)
+__device__ inline double mean_log_kappa(const double* kap) {
+  double s = 0.0;
+  for (int l = threadIdx.x; l < MM; l += WAVE) s += log(kap[l]);
+  return wave_sum(s) / MM;
+}
+
+// normalisation of network output column q (dof k of side q/4): 1 for
+// pressure dofs, kappa_g / (alpha H) for flux dofs, 0 where the side lies on
+// the domain boundary (that column is identically zero)
+__device__ inline double column_scale(const SubArgs& a, int I, int J, int q, double kgeo) {
+  const int side = q / D, k = q % D;
+  const int e = side_iface(a.g, I, J, side);
+  if (e < 0) return 0.0;
+  if (k < a.g.nP) return 1.0;
+  return kgeo / (a.alpha[e] * side_geo(a.g, side).H);
+}
+
+__global__ void __launch_bounds__(WAVE) surrogate_inputs_kernel(SubArgs a, short* inputs) {
+  __shared__ double kap[MM];
+  const Geo& g = a.g;
+  const int sd = blockIdx.x, I = sd % g.SX, J = sd / g.SX;
+  load_kappa<M>(a, I, J, kap);
+  __syncthreads();
+  const double mean = mean_log_kappa(kap);
+  bool has[4];
+  for (int side = 0; side < 4; ++side) has[side] = side_iface(g, I, J, side) >= 0;
+  short* out = inputs + (size_t)sd * MM * 8;
+  for (int l = threadIdx.x; l < MM; l += WAVE) {
+    const int li = l % M, lj = l / M;
+    typedef short s8 __attribute__((ext_vector_type(8)));
+    s8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+    const short one = to_bf16(1.f);
+    v[0] = to_bf16((float)((log(kap[l]) - mean) * 0.25));
+    if (has[0] && li == 0) v[1] = one;
+    if (has[1] && li == M - 1) v[2] = one;
+    if (has[2] && lj == 0) v[3] = one;
+    if (has[3] && lj == M - 1) v[4] = one;
+    *reinterpret_cast<s8*>(out + (size_t)l * 8) = v;
+  }
+}
+
+__global__ void __launch_bounds__(WAVE) surrogate_targets_kernel(SubArgs a, float* targets) {
+  __shared__ double kap[MM];
+  __shared__ double scale[4 * D];
+  const Geo& g = a.g;
+  const int sd = blockIdx.x, I = sd % g.SX, J = sd / g.SX;
+  load_kappa<M>(a, I, J, kap);
+  __syncthreads();
+  const double kgeo = exp(mean_log_kappa(kap));
+  if (threadIdx.x < 4 * D) scale[threadIdx.x] = column_scale(a, I, J, threadIdx.x, kgeo);
+  __syncthreads();
+  const double* Xg = a.X + (size_t)sd * R * MM;
+  float* out = targets + (size_t)sd * MM * 4 * D;
+  for (int o = threadIdx.x; o < MM * 4 * D; o += WAVE) {
+    const int l = o / (4 * D), q = o % (4 * D);
+    out[o] = (float)(Xg[(size_t)(1 + q) * MM + l] * scale[q]);
+  }
+}
+
+// Decode the network's prediction of the 16 basis functions, form each
+// column's FP64 residual in the local Robin problem and accept the subdomain
+// only if every column passes; an accepted subdomain gets its basis block
+// and its block of the interface system written exactly as the FP64 kernel
+// would, a rejected one (or one with source or physical boundary data,
+// whose particular solution the network does not predict) is appended to
+// a.fallback for the FP64 kernel.
+__global__ void __launch_bounds__(WAVE) surrogate_gate_kernel(SubArgs a, const float* pred) {
+  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM];
+  __shared__ double bside[4][M][D];
+  __shared__ double xb[4][M][R];
+  __shared__ double Xs[4 * D][MM];
+  __shared__ double scale[4 * D];
+  const Geo& g = a.g;
+  const int lane = threadIdx.x, c = lane & 15, gq = lane >> 4;
+  const int sd = blockIdx.x, I = sd % g.SX, J = sd / g.SX;
+
+  load_kappa<M>(a, I, J, kap);
+  __syncthreads();
+  for (int l = lane; l < MM; l += WAVE)
+    assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, b0 + l, 1, nullptr);
+  const double kgeo = exp(mean_log_kappa(kap));
+  if (lane < 4 * D) scale[lane] = column_scale(a, I, J, lane, kgeo);
+  {
+    const int side = lane >> 4, t = lane & 15;
+    const int e = side_iface(g, I, J, side);
+    for (int k = 0; k < D; ++k) {
+      double v = 0.0;
+      if (e >= 0) {
+        const SideGeo sg = side_geo(g, side);
+        const double al = a.alpha[e];
+        const double kk = kap[side_cell<M>(side, t)];
+        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
+        const double beta = al * sg.H / kk;
+        double gv = a.basis[((size_t)e * D + k) * M + t];
+        if (k >= g.nP) gv = -beta * side_sigma(side) * gv;
+        v = TR * gv;
+      }
+      bside[side][t][k] = v;
+    }
+  }
+  __syncthreads();
+  bool particular = false;
+  for (int l = lane; l < MM; l += WAVE) particular |= b0[l] != 0.0;
+  const float* pr = pred + (size_t)sd * MM * 4 * D;
+  for (int o = lane; o < MM * 4 * D; o += WAVE) {
+    const int l = o / (4 * D), q = o % (4 * D);
+    const double s = scale[q];
+    Xs[q][l] = s != 0.0 ? (double)pr[o] / s : 0.0;
+  }
+  __syncthreads();
+
+  // residual of column c over the rows gq*4 .. gq*4+3 of the subdomain
+  double r2 = 0.0, b2 = 0.0;
+  for (int j = 4 * gq; j < 4 * gq + 4; ++j) {
+    for (int i = 0; i < M; ++i) {
+      const int l = j * M + i;
+      const double b = side_rhs(bside, j, i, c);
+      double ax = dg[l] * Xs[c][l];
+      if (i < M - 1) ax += ex[l] * Xs[c][l + 1];
+      if (i > 0) ax += ex[l - 1] * Xs[c][l - 1];
+      if (j < M - 1) ax += cy[l] * Xs[c][l + M];
+      if (j > 0) ax += cy[l - M] * Xs[c][l - M];
+      const double r = b - ax;
+      r2 += r * r;
+      b2 += b * b;
+    }
+  }
+  r2 += __shfl_xor(r2, 16);
+  r2 += __shfl_xor(r2, 32);
+  b2 += __shfl_xor(b2, 16);
+  b2 += __shfl_xor(b2, 32);
+  const bool ok = isfinite(r2) && r2 <= a.gate_tol * a.gate_tol * b2;
+  const bool accept = __all(ok) && !__any(particular);
+  if (!accept) {
+    if (lane == 0) {
+      const int q = atomicAdd(a.fallback, 1);
+      a.fallback[1 + q] = sd;
+    }
+    return;
+  }
+
+  double* Xg = a.X + (size_t)sd * R * MM;
+  for (int l = lane; l < MM; l += WAVE) Xg[l] = 0.0;   // no particular data
+  for (int o = lane; o < 4 * D * MM; o += WAVE) Xg[MM + o] = Xs[o / MM][o % MM];
+  for (int o = lane; o < 4 * M * R; o += WAVE) {
+    const int side = o / (M * R), t = (o / R) % M, col = o % R;
+    double v = 0.0;
+    if (col > 0) {
+      const int l = side_cell<M>(side, t);
+      v = Xs[col - 1][l];
+    }
+    xb[side][t][col] = v;
+  }
+  __syncthreads();
+  write_block(a, sd, I, J, kap, xb);
+}
+
 }  // namespace
 
 hipError_t launch_basis_m16d4(const SubArgs& a, hipStream_t st) {
@@ -925,6 +1100,21 @@ hipError_t launch_basis32_m16d4(const SubArgs& a, hipStream_t st) {
 
 hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(stitch_m16d4_kernel, dim3(a.g.n_sub), dim3(WAVE), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_surrogate_inputs(const SubArgs& a, short* inputs, hipStream_t st) {
+  hipLaunchKernelGGL(surrogate_inputs_kernel, dim3(a.g.n_sub), dim3(WAVE), 0, st, a, inputs);
+  return hipGetLastError();
+}
+
+hipError_t launch_surrogate_targets(const SubArgs& a, float* targets, hipStream_t st) {
+  hipLaunchKernelGGL(surrogate_targets_kernel, dim3(a.g.n_sub), dim3(WAVE), 0, st, a, targets);
+  return hipGetLastError();
+}
+
+hipError_t launch_surrogate_gate(const SubArgs& a, const float* pred, hipStream_t st) {
+  hipLaunchKernelGGL(surrogate_gate_kernel, dim3(a.g.n_sub), dim3(WAVE), 0, st, a, pred);
   return hipGetLastError();
 }
 

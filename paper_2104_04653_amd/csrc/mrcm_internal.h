@@ -27,7 +27,8 @@ struct Geo {
   int gauge;        // 1: no Dirichlet side, first pressure dof pinned
   int generic;      // 1: use the generic per-subdomain kernels even where a
                     //    specialised one exists (host-side switch)
-  int prec;         // 0: FP64 local solves, 1: FP32 + FP64 iterative refinement
+  int prec;         // 0: FP64 local solves, 1: FP32 + FP64 iterative refinement,
+                    // 2: surrogate + residual gate + FP64 re-solve
   double hx, hy;
 };
 
@@ -50,6 +51,7 @@ struct SubArgs {
   int* status;
   int* fallback;          // FP32 refinement: [0] = count, [1..] = subdomains to redo in FP64
   int* ir_iters;          // FP32 refinement: [0] = largest refinement count used
+  double gate_tol;        // surrogate: accepted if ||b - A x|| <= gate_tol ||b|| per column
 };
 
 // Frontal-matrix node of the nested-dissection elimination of the
@@ -107,6 +109,27 @@ hipError_t launch_iface_residual(const Geo& g, const double* blocks, const doubl
                                  double* partials, double* out2, hipStream_t st);
 constexpr int RESID_WG = 128;
 hipError_t prepare_interface_kernels();
+
+// ---- surrogate network (surrogate.hip) ----
+}  // namespace mrcm
+struct mrcm_cnn;
+namespace mrcm {
+namespace cnn {
+int n_params();
+int off_w(int l);
+int off_b(int l);
+// forward pass of the network: in BF16 [batch][256][8] -> out FP32 [batch][256][16]
+hipError_t forward(const short* in, const short* wb, const float* p32, short* a1, short* a2,
+                   short* a3, float* out, int batch, hipStream_t st);
+hipError_t cast(const float* p32, short* wb, hipStream_t st);
+const float* params_of(const mrcm_cnn* net);
+hipStream_t stream_of(const mrcm_cnn* net);
+}  // namespace cnn
+// (local_mfma.hip) surrogate inputs / training targets / residual gate for
+// 16 x 16 subdomains with 2 + 2 dofs
+hipError_t launch_surrogate_inputs(const SubArgs& a, short* inputs, hipStream_t st);
+hipError_t launch_surrogate_targets(const SubArgs& a, float* targets, hipStream_t st);
+hipError_t launch_surrogate_gate(const SubArgs& a, const float* pred, hipStream_t st);
 
 constexpr int PANEL_NB = 32;      // panel width of the blocked elimination
 constexpr int TILE = 64;          // trailing-update tile

@@ -20,12 +20,15 @@ ERROR_NAMES = {0: "MRCM_OK", 1: "MRCM_E_INVAL", 2: "MRCM_E_NOMEM", 3: "MRCM_E_HI
                4: "MRCM_E_NOT_SPD", 5: "MRCM_E_NO_CONV", 6: "MRCM_E_STATE",
                7: "MRCM_E_UNSUPPORTED"}
 SPACES = {"linear": 0, "edge": 1, "full": 2}
-PRECISIONS = {"fp64": 0, "fp32_ir": 1}
+PRECISIONS = {"fp64": 0, "fp32_ir": 1, "surrogate": 2}
 
 EXPORTED = [
     "mrcm_setup", "mrcm_update_mobility", "mrcm_solve", "mrcm_fine_flux", "mrcm_get_stats",
     "mrcm_get_sizes", "mrcm_get_interface_solution", "mrcm_get_local_blocks",
-    "mrcm_get_basis", "mrcm_last_error", "mrcm_destroy",
+    "mrcm_get_basis", "mrcm_surrogate_inputs", "mrcm_surrogate_targets", "mrcm_set_surrogate",
+    "mrcm_solve_with_predictions", "mrcm_set_gate_tolerance", "mrcm_cnn_create", "mrcm_cnn_num_params",
+    "mrcm_cnn_get_params", "mrcm_cnn_set_params", "mrcm_cnn_forward", "mrcm_cnn_loss_grad",
+    "mrcm_cnn_train_step", "mrcm_cnn_destroy", "mrcm_last_error", "mrcm_destroy",
 ]
 
 
@@ -52,7 +55,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("ms_local", ctypes.c_double), ("ms_interface", ctypes.c_double),
                 ("ms_flux", ctypes.c_double), ("n_sub", ctypes.c_int32),
                 ("n_dof", ctypes.c_int32), ("ir_iters_max", ctypes.c_int32),
-                ("fallbacks", ctypes.c_int32), ("interface_residual", ctypes.c_double)]
+                ("fallbacks", ctypes.c_int32), ("interface_residual", ctypes.c_double),
+                ("ms_surrogate", ctypes.c_double)]
 
 
 _lib = None
@@ -89,12 +93,29 @@ def load_library(path: str = LIB_PATH):
     lib.mrcm_get_interface_solution.argtypes = [P, dp]
     lib.mrcm_get_local_blocks.argtypes = [P, dp]
     lib.mrcm_get_basis.argtypes = [P, dp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    i32 = ctypes.c_int32
+    lib.mrcm_surrogate_inputs.argtypes = [P, P]
+    lib.mrcm_surrogate_targets.argtypes = [P, P]
+    lib.mrcm_set_surrogate.argtypes = [P, P]
+    lib.mrcm_solve_with_predictions.argtypes = [P, P]
+    lib.mrcm_set_gate_tolerance.argtypes = [P, ctypes.c_double]
+    lib.mrcm_cnn_create.argtypes = [ctypes.POINTER(P), i32, ctypes.c_uint64, P]
+    lib.mrcm_cnn_num_params.argtypes = [P, ctypes.POINTER(i32)]
+    lib.mrcm_cnn_get_params.argtypes = [P, fp]
+    lib.mrcm_cnn_set_params.argtypes = [P, fp]
+    lib.mrcm_cnn_forward.argtypes = [P, P, P, i32]
+    lib.mrcm_cnn_loss_grad.argtypes = [P, P, P, i32, fp, fp]
+    lib.mrcm_cnn_train_step.argtypes = [P, P, P, i32, ctypes.c_float, fp]
+    lib.mrcm_cnn_destroy.argtypes = [P]
+    lib.mrcm_cnn_destroy.restype = None
     lib.mrcm_last_error.argtypes = [P]
     lib.mrcm_last_error.restype = ctypes.c_char_p
     lib.mrcm_destroy.argtypes = [P]
     lib.mrcm_destroy.restype = None
-    for name in EXPORTED[:-2]:
-        getattr(lib, name).restype = ctypes.c_int
+    for name in EXPORTED:
+        if name not in ("mrcm_last_error", "mrcm_destroy", "mrcm_cnn_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -252,9 +273,135 @@ class MRCMSolver:
         self._check(self.lib.mrcm_get_local_blocks(self.ctx, _dptr(out)), "mrcm_get_local_blocks")
         return out.reshape(self.n_sub, R - 1, R)
 
+    # -- learned surrogate (16 x 16 subdomains, 2 + 2 dofs) -----------------
+    def surrogate_inputs(self):
+        """Network inputs of every subdomain for the current mobility: a torch
+        bfloat16 device tensor [n_sub, 256, 8]."""
+        import torch
+        out = torch.empty((self.n_sub, 256, 8), dtype=torch.bfloat16, device="cuda")
+        torch.cuda.current_stream().synchronize()
+        self._check(self.lib.mrcm_surrogate_inputs(self.ctx, ctypes.c_void_p(out.data_ptr())),
+                    "mrcm_surrogate_inputs")
+        return out
+
+    def surrogate_targets(self):
+        """Normalised basis functions of the last solve: a torch float32 device
+        tensor [n_sub, 256, 16] (the network's training targets)."""
+        import torch
+        out = torch.empty((self.n_sub, 256, 16), dtype=torch.float32, device="cuda")
+        torch.cuda.current_stream().synchronize()
+        self._check(self.lib.mrcm_surrogate_targets(self.ctx, ctypes.c_void_p(out.data_ptr())),
+                    "mrcm_surrogate_targets")
+        return out
+
+    def solve_with_predictions(self, pred):
+        """Surrogate-precision solve with given predictions (float32 device
+        tensor [n_sub, 256, 16]) in place of the network's."""
+        import torch
+        if not _is_device(pred) or pred.dtype != torch.float32 or not pred.is_contiguous() or \
+                tuple(pred.shape) != (self.n_sub, 256, 16):
+            raise ValueError("predictions must be a contiguous float32 device tensor [n_sub, 256, 16]")
+        torch.cuda.current_stream().synchronize()
+        self._check(self.lib.mrcm_solve_with_predictions(self.ctx, ctypes.c_void_p(pred.data_ptr())),
+                    "mrcm_solve_with_predictions")
+
+    def set_gate_tolerance(self, tol: float):
+        self._check(self.lib.mrcm_set_gate_tolerance(self.ctx, float(tol)), "mrcm_set_gate_tolerance")
+
+    def set_surrogate(self, net: "SurrogateNet"):
+        self._check(self.lib.mrcm_set_surrogate(self.ctx, net.net), "mrcm_set_surrogate")
+
     def basis(self) -> np.ndarray:
         m = int(self.prob.sub_nx)
         out = np.empty(self.n_sub * m * m * self.n_cols)
         self._check(self.lib.mrcm_get_basis(self.ctx, _dptr(out)), "mrcm_get_basis")
         # stored column-major per subdomain; returned as [sub][cell][col]
         return out.reshape(self.n_sub, self.n_cols, m * m).transpose(0, 2, 1).copy()
+
+
+class SurrogateNet:
+    """The convolutional surrogate of the basis functions (mrcm_cnn_*): BF16
+    forward/backward kernels, FP32 master parameters, Adam.  Inputs are torch
+    bfloat16 device tensors [B, 256, 8], outputs and targets float32
+    [B, 256, 16]."""
+
+    def __init__(self, max_batch: int, seed: int = 0, stream=None):
+        self.lib = load_library()
+        self.max_batch = int(max_batch)
+        net = ctypes.c_void_p()
+        st = _current_stream() if stream is None else ctypes.c_void_p(stream)
+        rc = self.lib.mrcm_cnn_create(ctypes.byref(net), self.max_batch, int(seed), st)
+        if rc != OK:
+            raise MRCMError(rc, "mrcm_cnn_create failed")
+        self.net = net
+        n = ctypes.c_int32()
+        self._check(self.lib.mrcm_cnn_num_params(self.net, ctypes.byref(n)), "num_params")
+        self.n_params = n.value
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise MRCMError(rc, what)
+
+    @staticmethod
+    def _dev(t, dtype, shape_tail):
+        import torch
+        if not _is_device(t) or t.dtype != dtype or not t.is_contiguous() or \
+                tuple(t.shape[1:]) != shape_tail:
+            raise ValueError("expected a contiguous %s device tensor [B, %s]"
+                             % (dtype, ", ".join(map(str, shape_tail))))
+        torch.cuda.current_stream().synchronize()
+        return ctypes.c_void_p(t.data_ptr())
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._check(self.lib.mrcm_cnn_get_params(
+            self.net, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), "get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != self.n_params:
+            raise ValueError("expected %d parameters" % self.n_params)
+        self._check(self.lib.mrcm_cnn_set_params(
+            self.net, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), "set_params")
+
+    def forward(self, x):
+        import torch
+        xp = self._dev(x, torch.bfloat16, (256, 8))
+        out = torch.empty((x.shape[0], 256, 16), dtype=torch.float32, device="cuda")
+        torch.cuda.current_stream().synchronize()
+        self._check(self.lib.mrcm_cnn_forward(self.net, xp, ctypes.c_void_p(out.data_ptr()),
+                                              int(x.shape[0])), "forward")
+        return out
+
+    def loss_grad(self, x, y):
+        """(mean squared error, gradient w.r.t. the parameters as numpy)."""
+        import torch
+        xp = self._dev(x, torch.bfloat16, (256, 8))
+        yp = self._dev(y, torch.float32, (256, 16))
+        loss = ctypes.c_float()
+        g = np.empty(self.n_params, dtype=np.float32)
+        self._check(self.lib.mrcm_cnn_loss_grad(
+            self.net, xp, yp, int(x.shape[0]), ctypes.byref(loss),
+            g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), "loss_grad")
+        return float(loss.value), g
+
+    def train_step(self, x, y, lr: float) -> float:
+        import torch
+        xp = self._dev(x, torch.bfloat16, (256, 8))
+        yp = self._dev(y, torch.float32, (256, 16))
+        loss = ctypes.c_float()
+        self._check(self.lib.mrcm_cnn_train_step(self.net, xp, yp, int(x.shape[0]), float(lr),
+                                                 ctypes.byref(loss)), "train_step")
+        return float(loss.value)
+
+    def close(self):
+        if getattr(self, "net", None):
+            self.lib.mrcm_cnn_destroy(self.net)
+            self.net = None
+
+    def __del__(self):  # pragma: no cover - best effort
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -78,3 +78,24 @@ def test_bad_sizes_rejected_without_gpu():
     rc = lib.mrcm_setup(ctypes.byref(ctx), ctypes.byref(grid), dp, 16, 16, 0, 2, 2, None, -1.0,
                         ctypes.byref(bc), None, ctypes.byref(fl), 0, None)
     assert rc == binding.E_INVAL            # alpha must be positive
+
+
+def test_surrogate_entry_points_reject_null_without_gpu():
+    from paper_2104_04653_amd import mrcm as binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libmrcm.so not built")
+    lib = binding.load_library()
+    assert set(binding.EXPORTED) == set(declared_symbols())
+    net = ctypes.c_void_p()
+    assert lib.mrcm_cnn_create(None, 4, 0, None) == binding.E_INVAL
+    assert lib.mrcm_cnn_create(ctypes.byref(net), 0, 0, None) == binding.E_INVAL
+    assert lib.mrcm_cnn_num_params(None, None) == binding.E_INVAL
+    assert lib.mrcm_cnn_forward(None, None, None, 1) == binding.E_INVAL
+    assert lib.mrcm_cnn_loss_grad(None, None, None, 1, None, None) == binding.E_INVAL
+    assert lib.mrcm_cnn_train_step(None, None, None, 1, 1e-3, None) == binding.E_INVAL
+    assert lib.mrcm_set_surrogate(None, None) == binding.E_INVAL
+    assert lib.mrcm_surrogate_inputs(None, None) == binding.E_INVAL
+    assert lib.mrcm_surrogate_targets(None, None) == binding.E_INVAL
+    assert lib.mrcm_solve_with_predictions(None, None) == binding.E_INVAL
+    assert lib.mrcm_set_gate_tolerance(None, 1e-6) == binding.E_INVAL
+    lib.mrcm_cnn_destroy(None)
