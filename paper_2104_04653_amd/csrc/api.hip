@@ -64,7 +64,7 @@ struct mrcm_ctx {
   int* d_ids = nullptr;
   int2* d_gather = nullptr;
   PanelItem* d_items = nullptr;
-  double* inv = nullptr;        // per-panel triangular inverses of blocked fronts
+  double* inv = nullptr;        // per-panel diagonal-block inverses of blocked fronts
   double* partials = nullptr;   // residual partial maxima
   // surrogate precision: network parameters and per-subdomain activations
   float* s_p32 = nullptr;
@@ -290,7 +290,7 @@ int build_plan(mrcm_ctx* c) {
     d.blocked = level_max_n[n.level] > SMALL_FRONT ? 1 : 0;
     d.inv_off = inv_total;
     if (d.blocked)
-      inv_total += (long long)((n.s + PANEL_NB - 1) / PANEL_NB) * 2 * PANEL_NB * PANEL_NB;
+      inv_total += (long long)((n.s + PANEL_NB - 1) / PANEL_NB) * PANEL_NB * PANEL_NB;
     if (d.n > 4096) return fail(c, MRCM_E_UNSUPPORTED, "interface front too large");
     d.map_off = (long long)maps.size();
     d.dof_off = (long long)dofs.size();
@@ -427,7 +427,7 @@ int run_interface(mrcm_ctx* c) {
                                    c->d_maps, c->status, st));
       continue;
     }
-    // the gather factors the first panel's diagonal block, each update the next one
+    // the gather inverts the first panel's diagonal block, each update the next one
     HIPCHK(c, launch_front_gather(c->d_nodes, c->d_gather + lp.gather_off, lp.gather_count, c->tree,
                                   c->d_maps, c->inv, c->status, st));
     for (const PanelLaunch& pl : lp.panels)

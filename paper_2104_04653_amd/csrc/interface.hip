@@ -17,12 +17,13 @@
 // Fronts of up to SMALL_FRONT unknowns are gathered and eliminated by one
 // work-group in LDS.  Larger fronts (the few nodes near the root) are
 // gathered in global memory and eliminated by a right-looking blocked LU:
-// the gather factors the first panel's diagonal block; then one launch per
-// panel of PANEL_NB columns applies the trailing update
-// A22 -= (A21 U11^-1)(L11^-1 A12) in 64x64 tiles, and the work-group whose
-// tile starts with the next panel's diagonal block factors it and stores the
-// inverses of its two triangular factors.  Back substitution runs top down,
-// one work-group per node.
+// the gather inverts the first panel's diagonal block A11; then one launch
+// per panel of PANEL_NB columns applies the trailing update
+// A22 -= A21 (A11^-1 A12) in 64 x 64 tiles on the FP64 matrix cores, and the
+// work-group whose tile starts with the next panel's diagonal block inverts
+// it (Gauss-Jordan without pivoting, which the quasi-definite structure
+// allows) and stores the inverse.  Back substitution runs top down, one
+// work-group per node.
 #include "mrcm_internal.h"
 
 #include <math.h>
@@ -82,60 +83,50 @@ __global__ void __launch_bounds__(NT) front_small_kernel(const NodeDesc* nodes, 
   if (bad && tid == 0) atomicOr(status, ST_IFACE_PIVOT);
 }
 
-// LU without pivoting of the diagonal block of a panel held in LDS
-// (identity-padded beyond nb), written back to F at (k0, k0), and the
-// explicit inverses of its unit lower factor L11 and upper factor U11,
-// stored for the panel in `out` (2 * PANEL_NB^2 doubles).  Every thread of
-// the work-group must call it; each inverse column is built in registers by
-// one thread.
-__device__ void factor_store_diag(double (*A)[PANEL_NB + 1], int nb, double* F, int ld, int k0,
-                                  double* out, bool& bad) {
-  const int t = threadIdx.x, tx = t % TXN, ty = t / TXN;
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// In-place inverse of the PANEL_NB x PANEL_NB block S (LDS; identity-padded
+// beyond the panel width) by Gauss-Jordan elimination without pivoting,
+// written to `out` row-major.  Every thread of the work-group must call it:
+// thread t updates row t / 8, columns 4 (t % 8) .. 4 (t % 8) + 3.
+__device__ void gj_inverse(double (*S)[PANEL_NB + 1], double* out, bool& bad) {
+  static_assert(NT == 8 * PANEL_NB, "one thread per four entries");
+  const int t = threadIdx.x, i = t >> 3, j0 = (t & 7) * 4;
+  double v[4];
   __syncthreads();
-  for (int k = 0; k < nb; ++k) {
-    const double piv = A[k][k];
-    if (piv == 0.0 || !isfinite(piv)) bad = true;
-    if (t > k && t < PANEL_NB) A[t][k] /= piv;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = S[i][j0 + q];
+  for (int k = 0; k < PANEL_NB; ++k) {
+    const double p = S[k][k], aik = S[i][k];
+    double akj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) akj[q] = S[k][j0 + q];
+    if (p == 0.0 || !isfinite(p)) bad = true;
+    const double ip = 1.0 / p;
     __syncthreads();
-    for (int i = k + 1 + ty; i < PANEL_NB; i += TYN)
-      if (tx > k) A[i][tx] -= A[i][k] * A[k][tx];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + q;
+      if (i == k) v[q] = (j == k) ? ip : akj[q] * ip;
+      else v[q] = (j == k) ? -aik * ip : v[q] - aik * (akj[q] * ip);
+      S[i][j] = v[q];
+    }
     __syncthreads();
   }
-  for (int i = ty; i < nb; i += TYN)
-    if (tx < nb) F[(long long)(k0 + i) * ld + k0 + tx] = A[i][tx];
-  if (t < PANEL_NB) {
-    const int j = t;      // column j of L11^{-1} (unit lower): forward substitution of e_j
-    double x[PANEL_NB];
 #pragma unroll
-    for (int i = 0; i < PANEL_NB; ++i) {
-      double v = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-      for (int m = 0; m < i; ++m) v -= A[i][m] * x[m];
-      x[i] = (i < j) ? 0.0 : v;
-    }
-#pragma unroll
-    for (int i = 0; i < PANEL_NB; ++i) out[i * PANEL_NB + j] = x[i];
-  } else if (t >= 64 && t < 64 + PANEL_NB) {
-    const int j = t - 64; // column j of U11^{-1} (upper): back substitution of e_j
-    double x[PANEL_NB];
-#pragma unroll
-    for (int i = PANEL_NB - 1; i >= 0; --i) {
-      double v = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-      for (int m = i + 1; m < PANEL_NB; ++m) v -= A[i][m] * x[m];
-      x[i] = (i > j) ? 0.0 : v / A[i][i];
-    }
-#pragma unroll
-    for (int i = 0; i < PANEL_NB; ++i) out[PANEL_NB * PANEL_NB + i * PANEL_NB + j] = x[i];
-  }
+  for (int q = 0; q < 4; ++q) out[i * PANEL_NB + j0 + q] = v[q];
 }
 
 __device__ inline double* panel_inv(double* inv, const NodeDesc& nd, int k0) {
-  return inv + nd.inv_off + (long long)(k0 / PANEL_NB) * 2 * PANEL_NB * PANEL_NB;
+  return inv + nd.inv_off + (long long)(k0 / PANEL_NB) * PANEL_NB * PANEL_NB;
 }
 
 // items: (node index, first row); each work-group gathers PANEL_NB rows of
-// a blocked front.  The work-group of rows 0 .. PANEL_NB-1 also factors the
+// a blocked front.  The work-group of rows 0 .. PANEL_NB-1 also inverts the
 // diagonal block of the first panel.
 __global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes, const int2* items,
                                                           double* tree, const int2* maps,
@@ -164,45 +155,27 @@ __global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes,
   }
   if (first) {
     bool bad = false;
-    factor_store_diag(A, nb, F, ld, 0, panel_inv(inv, nd, 0), bad);
-    if (bad && threadIdx.x == 0) atomicOr(status, ST_IFACE_PIVOT);
+    gj_inverse(A, panel_inv(inv, nd, 0), bad);
+    if (bad) atomicOr(status, ST_IFACE_PIVOT);
   }
 }
 
-// Diagonal block of the first panel of blocked fronts (used when a front
-// is not gathered by front_gather_kernel).  One work-group per front.
-__global__ void __launch_bounds__(NT) front_diag_kernel(const NodeDesc* nodes, const int* ids,
-                                                        int k0, double* tree, double* inv,
-                                                        int* status) {
-  __shared__ double A[PANEL_NB][PANEL_NB + 1];
-  const NodeDesc nd = nodes[ids[blockIdx.x]];
-  const int ld = nd.n + 1;
-  const int nb = min(PANEL_NB, nd.s - k0);
-  double* F = tree + nd.f_off;
-  const int t = threadIdx.x, tx = t % TXN, ty = t / TXN;
-  for (int i = ty; i < PANEL_NB; i += TYN)
-    A[i][tx] = (i < nb && tx < nb) ? F[(long long)(k0 + i) * ld + k0 + tx] : (i == tx ? 1.0 : 0.0);
-  bool bad = false;
-  factor_store_diag(A, nb, F, ld, k0, panel_inv(inv, nd, k0), bad);
-  if (bad && t == 0) atomicOr(status, ST_IFACE_PIVOT);
-}
-
-// Trailing update of panel k0 for one 64 x 64 tile of a blocked front:
-// L21 = A21 U11^{-1} and U12 = L11^{-1} A12 are formed on the fly for the
-// tile's rows and columns, then A22 -= L21 U12.  The panel rows and columns
-// themselves are left as they were at the start of the panel (back
-// substitution applies L11^{-1} and U11^{-1} to them), so tiles never write
-// what other tiles read.
+// Trailing update of panel k0 for one 64 x 64 tile of a blocked front,
+// A22 -= A21 W with W = A11^-1 A12 formed for the tile's columns, both
+// products on v_mfma_f64_16x16x4f64 (lane c + 16 g holds rows 4 v + g of
+// column c of a 16 x 16 result; operand A[i][k] from lane i + 16 k, B[k][j]
+// from lane j + 16 k).  The panel rows and columns themselves are left as
+// they were at the start of the panel (back substitution applies A11^-1 to
+// them), so tiles never write what other tiles read.
 __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
                                                           const PanelItem* items, int k0,
                                                           double* tree, double* inv,
                                                           int* status) {
-  __shared__ double Li[PANEL_NB][PANEL_NB + 1];
-  __shared__ double Ui[PANEL_NB][PANEL_NB + 1];
-  __shared__ double As[TILE][PANEL_NB + 1];   // A21 tile, then L21
-  __shared__ double Bs[PANEL_NB][TILE + 1];   // A12 tile, then U12
-  __shared__ double Ls[TILE][PANEL_NB + 1];
-  __shared__ double Us[PANEL_NB][TILE + 1];
+  __shared__ double Dv[PANEL_NB][PANEL_NB + 1];   // A11^-1; then the next diagonal block
+  __shared__ double As[TILE][PANEL_NB + 1];       // A21 rows of the tile
+  __shared__ double Bs[PANEL_NB][TILE + 1];       // A12 columns of the tile
+  __shared__ double Ws[PANEL_NB][TILE + 1];       // W = A11^-1 A12
+  static_assert(TILE == 64 && PANEL_NB == 32 && NT == 256, "tile shape of the MFMA mapping");
   const PanelItem it = items[blockIdx.x];
   const NodeDesc nd = nodes[it.node];
   const int n = nd.n, ld = n + 1;
@@ -213,8 +186,8 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
   const int r0 = it.i0, c0 = it.j0;
   const int rows = min(TILE, n - r0), cols = min(TILE, ld - c0);
   for (int e = t; e < PANEL_NB * PANEL_NB; e += NT) {
-    Li[e / PANEL_NB][e % PANEL_NB] = iv[e];
-    Ui[e / PANEL_NB][e % PANEL_NB] = iv[PANEL_NB * PANEL_NB + e];
+    const int i = e / PANEL_NB, k = e % PANEL_NB;
+    Dv[i][k] = (i < nb && k < nb) ? iv[e] : 0.0;
   }
   for (int e = t; e < TILE * PANEL_NB; e += NT) {
     const int i = e / PANEL_NB, k = e % PANEL_NB;
@@ -225,44 +198,48 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
     Bs[k][j] = (k < nb && j < cols) ? F[(long long)(k0 + k) * ld + c0 + j] : 0.0;
   }
   __syncthreads();
-  // L21 = A21 Ui (upper), U12 = Li (unit lower) A12
-  for (int e = t; e < TILE * PANEL_NB; e += NT) {
-    const int i = e / PANEL_NB, k = e % PANEL_NB;
-    double v = 0.0;
-#pragma unroll 8
-    for (int m = 0; m < PANEL_NB; ++m) v += As[i][m] * Ui[m][k];
-    Ls[i][k] = v;
-  }
-  for (int e = t; e < PANEL_NB * TILE; e += NT) {
-    const int k = e / TILE, j = e % TILE;
-    double v = 0.0;
-#pragma unroll 8
-    for (int m = 0; m < PANEL_NB; ++m) v += Li[k][m] * Bs[m][j];
-    Us[k][j] = v;
+  const int w = t >> 6, lane = t & 63, c = lane & 15, g = lane >> 4;
+  {
+    // W: 2 x 4 result tiles of 16 x 16, two per wave
+    const int ti = w >> 1, tj = 2 * (w & 1);
+    d4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < PANEL_NB / 4; ++q) {
+      const double av = Dv[16 * ti + c][4 * q + g];
+      a0 = mfma64(av, Bs[4 * q + g][16 * tj + c], a0);
+      a1 = mfma64(av, Bs[4 * q + g][16 * tj + 16 + c], a1);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Ws[16 * ti + 4 * v + g][16 * tj + c] = a0[v];
+      Ws[16 * ti + 4 * v + g][16 * tj + 16 + c] = a1[v];
+    }
   }
   __syncthreads();
-  const int tx = t % 16, ty = t / 16;
-  double acc[4][4] = {};
-#pragma unroll 2
-  for (int k = 0; k < PANEL_NB; ++k) {
-    double lv[4], uv[4];
-    for (int u = 0; u < 4; ++u) lv[u] = Ls[ty * 4 + u][k];
-    for (int v = 0; v < 4; ++v) uv[v] = Us[k][tx * 4 + v];
-    for (int u = 0; u < 4; ++u)
-      for (int v = 0; v < 4; ++v) acc[u][v] += lv[u] * uv[v];
+  // A21 W: wave w owns rows 16 w .. 16 w + 15 and all four column tiles
+  d4 acc[4];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) acc[tj] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < PANEL_NB / 4; ++q) {
+    const double av = As[16 * w + c][4 * q + g];
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[tj] = mfma64(av, Ws[4 * q + g][16 * tj + c], acc[tj]);
   }
   const bool next_diag = it.pad != 0;   // this tile starts with the next panel's diagonal block
-  __syncthreads();
-  for (int u = 0; u < 4; ++u) {
-    const int i = ty * 4 + u;
+  __syncthreads();                      // Dv is reused below
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) {
+#pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int j = tx * 4 + v;
+      const int i = 16 * w + 4 * v + g, j = 16 * tj + c;
       double val = 0.0;
       if (i < rows && j < cols) {
-        val = F[(long long)(r0 + i) * ld + c0 + j] - acc[u][v];
-        F[(long long)(r0 + i) * ld + c0 + j] = val;
+        double* f = F + (long long)(r0 + i) * ld + c0 + j;
+        val = *f - acc[tj][v];
+        *f = val;
       }
-      if (next_diag && i < PANEL_NB && j < PANEL_NB) Li[i][j] = val;   // reuse as staging
+      if (next_diag && i < PANEL_NB && j < PANEL_NB) Dv[i][j] = val;
     }
   }
   if (next_diag) {
@@ -270,24 +247,24 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
     __syncthreads();
     for (int e = t; e < PANEL_NB * PANEL_NB; e += NT) {
       const int i = e / PANEL_NB, j = e % PANEL_NB;
-      if (!(i < nb1 && j < nb1)) Li[i][j] = (i == j) ? 1.0 : 0.0;
+      if (!(i < nb1 && j < nb1)) Dv[i][j] = (i == j) ? 1.0 : 0.0;
     }
     bool bad = false;
-    factor_store_diag(Li, nb1, F, ld, k1, panel_inv(inv, nd, k1), bad);
-    if (bad && t == 0) atomicOr(status, ST_IFACE_PIVOT);
+    gj_inverse(Dv, panel_inv(inv, nd, k1), bad);
+    if (bad) atomicOr(status, ST_IFACE_PIVOT);
   }
 }
 
 // Back substitution of one front, top down in the tree: x_s from the
 // front's eliminated rows and the x_r of its ancestors.
 //  classic fronts: row k holds U (upper part) at elimination time k;
-//  blocked fronts: the rows of panel p hold L11\U11 on the diagonal block and
-//  the panel-time A12 to the right, so x_1 = U11^{-1} L11^{-1} (b_1 - A12 x_2).
+//  blocked fronts: the rows of panel p hold the panel-time A12 to the right
+//  of the diagonal block, so x_1 = A11^{-1} (b_1 - A12 x_2).
 __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, const int* ids,
                                                         const double* tree, const double* inv,
                                                         const int* dofs, double* x) {
   extern __shared__ double xl[];   // n values: front-local unknowns
-  __shared__ double y[PANEL_NB], z[PANEL_NB];
+  __shared__ double y[PANEL_NB];
   const NodeDesc nd = nodes[ids[blockIdx.x]];
   const int n = nd.n, s = nd.s, ld = n + 1;
   const double* F = tree + nd.f_off;
@@ -332,17 +309,10 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
         if (row < nb && lane == 0) y[row] = v;
       }
       __syncthreads();
-      const double* Li = inv + nd.inv_off + (long long)p * 2 * PANEL_NB * PANEL_NB;
-      const double* Ui = Li + PANEL_NB * PANEL_NB;
+      const double* Di = inv + nd.inv_off + (long long)p * PANEL_NB * PANEL_NB;
       if (t < nb) {
         double v = 0.0;
-        for (int m = 0; m <= t; ++m) v += Li[t * PANEL_NB + m] * y[m];
-        z[t] = v;
-      }
-      __syncthreads();
-      if (t < nb) {
-        double v = 0.0;
-        for (int m = t; m < nb; ++m) v += Ui[t * PANEL_NB + m] * z[m];
+        for (int m = 0; m < nb; ++m) v += Di[t * PANEL_NB + m] * y[m];
         xl[k0 + t] = v;
       }
       __syncthreads();
@@ -455,13 +425,6 @@ hipError_t launch_front_gather(const NodeDesc* nodes, const int2* items, int cou
                                const int2* maps, double* inv, int* status, hipStream_t st) {
   hipLaunchKernelGGL(front_gather_kernel, dim3(count), dim3(NT), 0, st, nodes, items, tree, maps,
                      inv, status);
-  return hipGetLastError();
-}
-
-hipError_t launch_front_diag(const NodeDesc* nodes, const int* ids, int count, int k0,
-                             double* tree, double* inv, int* status, hipStream_t st) {
-  hipLaunchKernelGGL(front_diag_kernel, dim3(count), dim3(NT), 0, st, nodes, ids, k0, tree, inv,
-                     status);
   return hipGetLastError();
 }
 

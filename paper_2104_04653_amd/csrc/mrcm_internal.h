@@ -62,7 +62,7 @@ struct NodeDesc {
   long long map_off;    // offset into the map array (n int2: child A index, child B index)
   long long dof_off;    // offset into the dof array (n ints: global dof per position)
   long long c_off[2];   // offset of each child's Schur block (top-left)
-  long long inv_off;    // blocked fronts: offset of the per-panel triangular inverses
+  long long inv_off;    // blocked fronts: offset of the per-panel diagonal-block inverses
   int n, s;
   int c_ld[2];          // row stride of each child's Schur block
   int c_rhs[2];         // rhs column of each child's Schur block (relative to c_off)
@@ -97,8 +97,6 @@ hipError_t launch_front_small(const NodeDesc* nodes, const int* ids, int count, 
 hipError_t launch_front_gather(const NodeDesc* nodes, const int2* items, int count,
                                double* tree, const int2* maps, double* inv, int* status,
                                hipStream_t st);
-hipError_t launch_front_diag(const NodeDesc* nodes, const int* ids, int count, int k0,
-                             double* tree, double* inv, int* status, hipStream_t st);
 hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count,
                                int k0, double* tree, double* inv, int* status, hipStream_t st);
 hipError_t launch_front_back(const NodeDesc* nodes, const int* ids, int count, const double* tree,
