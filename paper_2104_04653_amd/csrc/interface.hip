@@ -21,8 +21,9 @@
 // per panel of PANEL_NB columns applies the trailing update
 // A22 -= A21 (A11^-1 A12) in 64 x 64 tiles on the FP64 matrix cores, and the
 // work-group whose tile starts with the next panel's diagonal block inverts
-// it (Gauss-Jordan without pivoting, which the quasi-definite structure
-// allows) and stores the inverse.  Back substitution runs top down, one
+// it (two 16 x 16 Gauss-Jordan inversions without pivoting, which the
+// quasi-definite structure allows, joined by a Schur complement) and stores
+// the inverse.  Back substitution runs top down, one
 // work-group per node.
 #include "mrcm_internal.h"
 
@@ -61,6 +62,7 @@ __global__ void __launch_bounds__(NT) front_small_kernel(const NodeDesc* nodes, 
   const int2* mp = maps + nd.map_off;
   for (int a = ty; a < n; a += TYN) {
     const int2 ma = mp[a];
+#pragma unroll 4
     for (int b = tx; b <= n; b += TXN) F[a * ld + b] = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
   }
   __syncthreads();
@@ -89,36 +91,91 @@ __device__ inline d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// In-place inverse of the PANEL_NB x PANEL_NB block S (LDS; identity-padded
-// beyond the panel width) by Gauss-Jordan elimination without pivoting,
-// written to `out` row-major.  Every thread of the work-group must call it:
-// thread t updates row t / 8, columns 4 (t % 8) .. 4 (t % 8) + 3.
-__device__ void gj_inverse(double (*S)[PANEL_NB + 1], double* out, bool& bad) {
-  static_assert(NT == 8 * PANEL_NB, "one thread per four entries");
-  const int t = threadIdx.x, i = t >> 3, j0 = (t & 7) * 4;
-  double v[4];
-  __syncthreads();
+__device__ inline double readlane_d(double x, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffu), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// In-place inverse of a 16 x 16 tile held by one wavefront in the MFMA
+// output layout (lane c + 16 g holds rows 4 v + g of column c in s[v]) by
+// Gauss-Jordan sweeps without pivoting; the pivot row and column are
+// broadcast with lane shuffles.
+__device__ inline d4 gj16(d4 s, int c, int g, bool& bad) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) v[q] = S[i][j0 + q];
-  for (int k = 0; k < PANEL_NB; ++k) {
-    const double p = S[k][k], aik = S[i][k];
-    double akj[4];
+  for (int k = 0; k < 16; ++k) {
+    const int kv = k >> 2, kg = k & 3;
+    const double p = readlane_d(s[kv], k + 16 * kg);
+    const double prow = __shfl(s[kv], c + 16 * kg);
+    double pcol[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) akj[q] = S[k][j0 + q];
+    for (int v = 0; v < 4; ++v) pcol[v] = __shfl(s[v], k + 16 * g);
     if (p == 0.0 || !isfinite(p)) bad = true;
     const double ip = 1.0 / p;
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = j0 + q;
-      if (i == k) v[q] = (j == k) ? ip : akj[q] * ip;
-      else v[q] = (j == k) ? -aik * ip : v[q] - aik * (akj[q] * ip);
-      S[i][j] = v[q];
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * v + g;
+      double nv;
+      if (row == k) nv = (c == k) ? ip : s[v] * ip;
+      else nv = (c == k) ? -pcol[v] * ip : fma(-pcol[v] * ip, prow, s[v]);
+      s[v] = nv;
     }
-    __syncthreads();
   }
+  return s;
+}
+
+// Inverse of the symmetric PANEL_NB x PANEL_NB diagonal block in S (LDS;
+// identity-padded beyond the panel width; only its upper triangle of 16 x 16
+// tiles is read), by one wavefront, written to `out` row-major.  With
+// A = [P Q; Q^T B]:  X = P^-1 Q,  C = B - Q^T X,  and
+// A^-1 = [P^-1 + X C^-1 X^T, -X C^-1; -C^-1 X^T, C^-1].
+// The products run on the matrix cores with the K index of step kk taken as
+// 4 kk + g, so that a symmetric left factor and any right factor in the
+// output layout are read from the lane's own registers; X^T as a left
+// factor comes from one transpose through `T`.  The pivots of the two 16 x 16
+// inversions are the pivots of an LU factorisation of A.
+__device__ void inv32_wave(const double (*S)[PANEL_NB + 1], double (*T)[17], double* out,
+                           bool& bad) {
+  static_assert(PANEL_NB == 32, "two 16 x 16 tiles per side");
+  const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+  d4 P, Q, B;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) out[i * PANEL_NB + j0 + q] = v[q];
+  for (int v = 0; v < 4; ++v) {
+    const int r = 4 * v + g;
+    P[v] = S[r][c];
+    Q[v] = S[r][16 + c];
+    B[v] = S[16 + r][16 + c];
+  }
+  const d4 z = {0.0, 0.0, 0.0, 0.0};
+  const d4 Pi = gj16(P, c, g, bad);
+  d4 X = z;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) X = mfma64(Pi[kk], Q[kk], X);          // P^-1 Q
+  d4 QX = z;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) QX = mfma64(Q[kk], X[kk], QX);         // Q^T X
+  const d4 Ci = gj16(B - QX, c, g, bad);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) T[4 * v + g][c] = X[v];
+  __builtin_amdgcn_wave_barrier();
+  d4 Xt;                                                                // X[c][4 kk + g]
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) Xt[kk] = T[c][4 * kk + g];
+  d4 L = z;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) L = mfma64(Ci[kk], Xt[kk], L);         // C^-1 X^T
+  d4 U = Pi;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) U = mfma64(Xt[kk], L[kk], U);          // P^-1 + X C^-1 X^T
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = 4 * v + g;
+    out[r * PANEL_NB + c] = U[v];
+    out[(16 + r) * PANEL_NB + c] = -L[v];
+    out[c * PANEL_NB + 16 + r] = -L[v];
+    out[(16 + r) * PANEL_NB + 16 + c] = Ci[v];
+  }
 }
 
 __device__ inline double* panel_inv(double* inv, const NodeDesc& nd, int k0) {
@@ -132,6 +189,7 @@ __global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes,
                                                           double* tree, const int2* maps,
                                                           double* inv, int* status) {
   __shared__ double A[PANEL_NB][PANEL_NB + 1];
+  __shared__ double Tt[16][17];
   const int2 it = items[blockIdx.x];
   const NodeDesc nd = nodes[it.x];
   const int n = nd.n, ld = n + 1;
@@ -144,6 +202,7 @@ __global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes,
   for (int a = r0 + ty; a < r0 + PANEL_NB; a += TYN) {
     if (a < r1) {
       const int2 ma = mp[a];
+#pragma unroll 4
       for (int b = tx; b <= n; b += TXN) {
         const double v = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
         F[(long long)a * ld + b] = v;
@@ -154,9 +213,12 @@ __global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes,
     }
   }
   if (first) {
-    bool bad = false;
-    gj_inverse(A, panel_inv(inv, nd, 0), bad);
-    if (bad) atomicOr(status, ST_IFACE_PIVOT);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      bool bad = false;
+      inv32_wave(A, Tt, panel_inv(inv, nd, 0), bad);
+      if (bad) atomicOr(status, ST_IFACE_PIVOT);
+    }
   }
 }
 
@@ -175,6 +237,7 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
   __shared__ double As[TILE][PANEL_NB + 1];       // A21 rows of the tile
   __shared__ double Bs[PANEL_NB][TILE + 1];       // A12 columns of the tile
   __shared__ double Ws[PANEL_NB][TILE + 1];       // W = A11^-1 A12
+  __shared__ double Tt[16][17];
   static_assert(TILE == 64 && PANEL_NB == 32 && NT == 256, "tile shape of the MFMA mapping");
   const PanelItem it = items[blockIdx.x];
   const NodeDesc nd = nodes[it.node];
@@ -185,14 +248,17 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
   const int t = threadIdx.x;
   const int r0 = it.i0, c0 = it.j0;
   const int rows = min(TILE, n - r0), cols = min(TILE, ld - c0);
+#pragma unroll
   for (int e = t; e < PANEL_NB * PANEL_NB; e += NT) {
     const int i = e / PANEL_NB, k = e % PANEL_NB;
     Dv[i][k] = (i < nb && k < nb) ? iv[e] : 0.0;
   }
+#pragma unroll
   for (int e = t; e < TILE * PANEL_NB; e += NT) {
     const int i = e / PANEL_NB, k = e % PANEL_NB;
     As[i][k] = (i < rows && k < nb) ? F[(long long)(r0 + i) * ld + k0 + k] : 0.0;
   }
+#pragma unroll
   for (int e = t; e < PANEL_NB * TILE; e += NT) {
     const int k = e / TILE, j = e % TILE;
     Bs[k][j] = (k < nb && j < cols) ? F[(long long)(k0 + k) * ld + c0 + j] : 0.0;
@@ -249,9 +315,12 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
       const int i = e / PANEL_NB, j = e % PANEL_NB;
       if (!(i < nb1 && j < nb1)) Dv[i][j] = (i == j) ? 1.0 : 0.0;
     }
-    bool bad = false;
-    gj_inverse(Dv, panel_inv(inv, nd, k1), bad);
-    if (bad) atomicOr(status, ST_IFACE_PIVOT);
+    __syncthreads();
+    if (t < 64) {
+      bool bad = false;
+      inv32_wave(Dv, Tt, panel_inv(inv, nd, k1), bad);
+      if (bad) atomicOr(status, ST_IFACE_PIVOT);
+    }
   }
 }
 
@@ -278,6 +347,7 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
       double v = 0.0;
       if (k < s) {
         const double* row = F + (long long)k * ld;
+#pragma unroll 4
         for (int m = s + lane; m < n; m += 8) v -= row[m] * xl[m];
         if (lane == 0) v += row[n];
       }
@@ -302,6 +372,7 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
         double v = 0.0;
         if (row < nb) {
           const double* fr = F + (long long)(k0 + row) * ld;
+#pragma unroll 4
           for (int m = k0 + nb + lane; m < n; m += 8) v -= fr[m] * xl[m];
           if (lane == 0) v += fr[n];
         }
