@@ -291,7 +291,7 @@ int build_plan(mrcm_ctx* c) {
     d.inv_off = inv_total;
     if (d.blocked)
       inv_total += (long long)((n.s + PANEL_NB - 1) / PANEL_NB) * PANEL_NB * PANEL_NB;
-    if (d.n > 4096) return fail(c, MRCM_E_UNSUPPORTED, "interface front too large");
+    if (d.n > MAX_FRONT) return fail(c, MRCM_E_UNSUPPORTED, "interface front too large");
     d.map_off = (long long)maps.size();
     d.dof_off = (long long)dofs.size();
     for (int q = 0; q < 2; ++q) {
@@ -335,7 +335,8 @@ int build_plan(mrcm_ctx* c) {
       lp.gather_off = (int)gather.size();
       for (int q = 0; q < lp.count; ++q) {
         const NodeDesc& d = desc[ids[lp.ids_off + q]];
-        for (int r = 0; r < d.n; r += PANEL_NB) gather.push_back(make_int2(ids[lp.ids_off + q], r));
+        gather.push_back(make_int2(ids[lp.ids_off + q], -1));   // first diagonal block
+        for (int r = 0; r < d.n; r += GATHER_ROWS) gather.push_back(make_int2(ids[lp.ids_off + q], r));
       }
       lp.gather_count = (int)gather.size() - lp.gather_off;
       for (int k0 = 0; k0 < lp.max_s; k0 += PANEL_NB) {

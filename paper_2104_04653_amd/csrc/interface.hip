@@ -17,7 +17,7 @@
 // Fronts of up to SMALL_FRONT unknowns are gathered and eliminated by one
 // work-group in LDS.  Larger fronts (the few nodes near the root) are
 // gathered in global memory and eliminated by a right-looking blocked LU:
-// the gather inverts the first panel's diagonal block A11; then one launch
+// the gather also inverts the first panel's diagonal block A11; then one launch
 // per panel of PANEL_NB columns applies the trailing update
 // A22 -= A21 (A11^-1 A12) in 64 x 64 tiles on the FP64 matrix cores, and the
 // work-group whose tile starts with the next panel's diagonal block inverts
@@ -56,10 +56,12 @@ __global__ void __launch_bounds__(NT) front_small_kernel(const NodeDesc* nodes, 
                                                          double* tree, const int2* maps,
                                                          int* status) {
   extern __shared__ double F[];
+  __shared__ int2 mp[SMALL_FRONT];
   const NodeDesc nd = nodes[ids[blockIdx.x]];
   const int n = nd.n, s = nd.s, ld = n + 1;
   const int tid = threadIdx.x, tx = tid % TXN, ty = tid / TXN;
-  const int2* mp = maps + nd.map_off;
+  for (int a = tid; a < n; a += NT) mp[a] = maps[nd.map_off + a];
+  __syncthreads();
   for (int a = ty; a < n; a += TYN) {
     const int2 ma = mp[a];
 #pragma unroll 4
@@ -182,44 +184,44 @@ __device__ inline double* panel_inv(double* inv, const NodeDesc& nd, int k0) {
   return inv + nd.inv_off + (long long)(k0 / PANEL_NB) * PANEL_NB * PANEL_NB;
 }
 
-// items: (node index, first row); each work-group gathers PANEL_NB rows of
-// a blocked front.  The work-group of rows 0 .. PANEL_NB-1 also inverts the
-// diagonal block of the first panel.
+// items: (node index, first row); each work-group gathers GATHER_ROWS rows
+// of a blocked front.  An item with first row -1 instead gathers the
+// diagonal block of the front's first panel into LDS and inverts it.
 __global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes, const int2* items,
                                                           double* tree, const int2* maps,
                                                           double* inv, int* status) {
   __shared__ double A[PANEL_NB][PANEL_NB + 1];
   __shared__ double Tt[16][17];
+  static_assert(GATHER_ROWS == NT / TXN, "one row per thread row");
+  __shared__ int2 mp[MAX_FRONT];
   const int2 it = items[blockIdx.x];
   const NodeDesc nd = nodes[it.x];
   const int n = nd.n, ld = n + 1;
-  const int2* mp = maps + nd.map_off;
-  const int r0 = it.y, r1 = min(n, r0 + PANEL_NB);
   const int tx = threadIdx.x % TXN, ty = threadIdx.x / TXN;
-  double* F = tree + nd.f_off;
-  const bool first = (r0 == 0);
-  const int nb = min(PANEL_NB, nd.s);
-  for (int a = r0 + ty; a < r0 + PANEL_NB; a += TYN) {
-    if (a < r1) {
-      const int2 ma = mp[a];
-#pragma unroll 4
-      for (int b = tx; b <= n; b += TXN) {
-        const double v = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
-        F[(long long)a * ld + b] = v;
-        if (first && b < PANEL_NB) A[a][b] = (a < nb && b < nb) ? v : (a == b ? 1.0 : 0.0);
-      }
-    } else if (first) {
-      A[a][tx] = (a == tx) ? 1.0 : 0.0;
+  for (int a = threadIdx.x; a < (it.y < 0 ? min(n, PANEL_NB) : n); a += NT) mp[a] = maps[nd.map_off + a];
+  __syncthreads();
+  if (it.y < 0) {
+    const int nb = min(PANEL_NB, nd.s);
+#pragma unroll
+    for (int a = ty; a < PANEL_NB; a += TYN) {
+      double v = (a == tx) ? 1.0 : 0.0;
+      if (a < nb && tx < nb) v = gather_entry(nd, tree, mp[a], mp[tx], false);
+      A[a][tx] = v;
     }
-  }
-  if (first) {
     __syncthreads();
     if (threadIdx.x < 64) {
       bool bad = false;
       inv32_wave(A, Tt, panel_inv(inv, nd, 0), bad);
       if (bad) atomicOr(status, ST_IFACE_PIVOT);
     }
+    return;
   }
+  const int a = it.y + ty;
+  if (a >= n) return;
+  double* F = tree + nd.f_off + (long long)a * ld;
+  const int2 ma = mp[a];
+#pragma unroll 8
+  for (int b = tx; b <= n; b += TXN) F[b] = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
 }
 
 // Trailing update of panel k0 for one 64 x 64 tile of a blocked front,
@@ -508,8 +510,8 @@ hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, in
 
 hipError_t launch_front_back(const NodeDesc* nodes, const int* ids, int count, const double* tree,
                              const double* inv, const int* dofs, double* x, hipStream_t st) {
-  // callers guarantee n <= 4096 (32 KiB of LDS)
-  hipLaunchKernelGGL(front_back_kernel, dim3(count), dim3(NT), 4096 * sizeof(double), st, nodes,
+  // the plan guarantees n <= MAX_FRONT
+  hipLaunchKernelGGL(front_back_kernel, dim3(count), dim3(NT), MAX_FRONT * sizeof(double), st, nodes,
                      ids, tree, inv, dofs, x);
   return hipGetLastError();
 }
