@@ -132,7 +132,7 @@ hipError_t launch_surrogate_gate(const SubArgs& a, const float* pred, hipStream_
 constexpr int PANEL_NB = 32;      // panel width of the blocked elimination
 constexpr int GATHER_ROWS = 8;    // rows per work-group of the blocked-front gather
 constexpr int TILE = 64;          // trailing-update tile
-constexpr int SMALL_FRONT = 128;  // fronts up to this size are eliminated in LDS
+constexpr int SMALL_FRONT = 64;   // fronts up to this size are eliminated in LDS
 constexpr int MAX_FRONT = 4096;   // largest front the interface plan accepts
 
 }  // namespace mrcm
