@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--train-seconds", type=float, default=30.0,
                     help="surrogate form: training time budget before the timed steps")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="copy 256 MiB device to device once before timing (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
     ap.add_argument("--train-fields", type=int, default=8,
                     help="surrogate form: fields (half log-normal, half channelized) whose "
                          "FP64 solves give the training patches")
@@ -195,6 +198,12 @@ def main():
                 "frac": flop / (ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
                 "flop_per_patch": CNN_FLOP_PATCH}
 
+    if args.copy_probe:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     results = {f: run_form(f) for f in forms}
     head = results[forms[0]]

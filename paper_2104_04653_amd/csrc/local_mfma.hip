@@ -32,12 +32,20 @@ namespace {
 using namespace local;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4z __attribute__((ext_vector_type(4)));
+
+// the forward sweep of a refinement correction is kept in FP32 registers:
+// it only carries the few leading digits of a correction that is itself
+// orders of magnitude below the solution
+__device__ inline f4z tof(d4 x) { return f4z{(float)x[0], (float)x[1], (float)x[2], (float)x[3]}; }
+__device__ inline d4 tod(f4z x) { return d4{(double)x[0], (double)x[1], (double)x[2], (double)x[3]}; }
 
 constexpr int M = 16;
 constexpr int MM = 256;
 constexpr int D = 4;
 constexpr int R = 17;
 constexpr int WAVE = 64;
+constexpr int MID = M / 2;   // joining block row of the two-sided elimination
 
 __device__ inline double readlane_d(double x, int lane) {
   const unsigned long long u = (unsigned long long)__double_as_longlong(x);
@@ -50,6 +58,14 @@ __device__ inline d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// 1/p from the hardware reciprocal estimate and two Newton steps (each
+// squares the relative error), in place of the IEEE division sequence
+__device__ inline double recip(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  r = fma(r, fma(-p, r, 1.0), r);
+  return fma(r, fma(-p, r, 1.0), r);
+}
+
 // In-place inverse of the SPD tile s (output layout) by Gauss-Jordan sweeps.
 __device__ inline d4 gauss_jordan16(d4 s, int c, int g, bool& bad) {
 #pragma unroll
@@ -60,8 +76,8 @@ __device__ inline d4 gauss_jordan16(d4 s, int c, int g, bool& bad) {
     double pcol[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) pcol[v] = __shfl(s[v], k + 16 * g);   // S[4v+g][k]
-    if (!(p > 0.0)) bad = true;
-    const double ip = 1.0 / p;
+    if (!(p > 0.0) || !isfinite(p)) bad = true;
+    const double ip = recip(p);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = 4 * v + g;
@@ -86,6 +102,24 @@ __device__ inline d4 schur_block(int j, const d4& prev, int c, int g, const doub
              : (row == c + 1) ? ex[j * M + c]
              : (c == row + 1) ? ex[j * M + row] : 0.0;
     if (j > 0) d -= cy[(j - 1) * M + row] * prev[v] * cy[(j - 1) * M + c];
+    s[v] = d;
+  }
+  return s;
+}
+
+// D_j - C P C with C = diag(cy of coupling row jc) in output layout (D_j
+// alone for jc < 0): the Schur-complemented diagonal block of row j after
+// eliminating the neighbouring row whose inverse block is P.
+__device__ inline d4 coupled_block(int j, int jc, const d4& P, int c, int g, const double* dg,
+                                   const double* ex, const double* cy) {
+  d4 s;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = 4 * v + g;
+    double d = (row == c) ? dg[j * M + row]
+             : (row == c + 1) ? ex[j * M + c]
+             : (c == row + 1) ? ex[j * M + row] : 0.0;
+    if (jc >= 0) d -= cy[jc * M + row] * P[v] * cy[jc * M + c];
     s[v] = d;
   }
   return s;
@@ -244,85 +278,180 @@ __global__ void __launch_bounds__(WAVE) basis_m16d4_kernel(SubArgs a) {
   }
   __syncthreads();
 
+  // Two-sided ("twisted") block elimination: the upper chain eliminates
+  // block rows 0 .. MID-1 downwards, the lower chain rows M-1 .. MID+1
+  // upwards, both in the same unrolled steps so that their latencies
+  // overlap, and block row MID joins them.  Sv[j] holds the inverse of the
+  // Schur-complemented diagonal block of row j in its chain.
   d4 Sv[M], Xv[M];
   bool bad = false;
-  d4 zp = {0.0, 0.0, 0.0, 0.0};
+  const d4 zero = {0.0, 0.0, 0.0, 0.0};
+  d4 zt = zero, zb = zero;   // particular column carried by each chain
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
-    d4 s = schur_block(j, j > 0 ? Sv[j > 0 ? j - 1 : 0] : zp, c, gq, dg, ex, cy);
+  for (int t = 0; t < MID; ++t) {
+    {
+      const int j = t;   // upper chain
+      d4 s = coupled_block(j, j - 1, j > 0 ? Sv[j > 0 ? j - 1 : 0] : zero, c, gq, dg, ex, cy);
+      s = gauss_jordan16(s, c, gq, bad);
+      Sv[j] = s;
+      d4 r, rp;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * v + gq;
+        double bv = side_rhs(bside, j, row, c), bp = b0[j * M + row];
+        if (j > 0) {
+          const double cc = cy[(j - 1) * M + row];
+          bv -= cc * Xv[j > 0 ? j - 1 : 0][v];
+          bp -= cc * zt[v];
+        }
+        r[v] = bv;
+        rp[v] = bp;
+      }
+      d4 z = zero, zz = zero;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        z = mfma(s[kk], r[kk], z);
+        zz = mfma(s[kk], rp[kk], zz);
+      }
+      Xv[j] = z;
+      zt = zz;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = zz[v];
+      }
+    }
+    if (t < M - 1 - MID) {
+      const int j = M - 1 - t;   // lower chain
+      d4 s = coupled_block(j, j < M - 1 ? j : -1, j < M - 1 ? Sv[j < M - 1 ? j + 1 : j] : zero, c,
+                           gq, dg, ex, cy);
+      s = gauss_jordan16(s, c, gq, bad);
+      Sv[j] = s;
+      d4 r, rp;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * v + gq;
+        double bv = side_rhs(bside, j, row, c), bp = b0[j * M + row];
+        if (j < M - 1) {
+          const double cc = cy[j * M + row];
+          bv -= cc * Xv[j < M - 1 ? j + 1 : j][v];
+          bp -= cc * zb[v];
+        }
+        r[v] = bv;
+        rp[v] = bp;
+      }
+      d4 z = zero, zz = zero;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        z = mfma(s[kk], r[kk], z);
+        zz = mfma(s[kk], rp[kk], zz);
+      }
+      Xv[j] = z;
+      zb = zz;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = zz[v];
+      }
+    }
+  }
+  {
+    // joining block row: both neighbours' Schur complements
+    constexpr int j = MID;
+    d4 s = coupled_block(j, j - 1, Sv[j - 1], c, gq, dg, ex, cy);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s[v] -= cy[j * M + 4 * v + gq] * Sv[j + 1][v] * cy[j * M + c];
     s = gauss_jordan16(s, c, gq, bad);
     Sv[j] = s;
     d4 r, rp;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = 4 * v + gq;
-      double b = side_rhs(bside, j, row, c);
-      double bp = b0[j * M + row];
-      if (j > 0) {
-        const double cc = cy[(j - 1) * M + row];
-        b -= cc * Xv[j > 0 ? j - 1 : 0][v];
-        bp -= cc * zp[v];
-      }
-      r[v] = b;
-      rp[v] = bp;
+      const double cu = cy[(j - 1) * M + row], cl = cy[j * M + row];
+      r[v] = side_rhs(bside, j, row, c) - cu * Xv[j - 1][v] - cl * Xv[j + 1][v];
+      rp[v] = b0[j * M + row] - cu * zt[v] - cl * zb[v];
     }
-    d4 z = {0.0, 0.0, 0.0, 0.0}, zz = {0.0, 0.0, 0.0, 0.0};
+    d4 z = zero, zz = zero;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       z = mfma(s[kk], r[kk], z);
       zz = mfma(s[kk], rp[kk], zz);
     }
     Xv[j] = z;
-    zp = zz;
+    zt = zz;
+    zb = zz;
     if (c == 0) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = zz[v];
     }
   }
   __syncthreads();
-  d4 xpn = zp;
+  // back substitution outwards from the joining row
 #pragma unroll
-  for (int j = M - 2; j >= 0; --j) {
-    d4 t, tp, xp;
+  for (int t = 0; t < MID; ++t) {
+    {
+      const int j = MID - 1 - t;   // upper chain: X_j = Z_j - S_j^-1 C_j X_{j+1}
+      d4 tt, tp, xp;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 4 * v + gq;
-      const double cc = -cy[j * M + row];
-      t[v] = cc * Xv[j + 1][v];
-      tp[v] = cc * xpn[v];
-      xp[v] = pz[j * M + row];
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * v + gq;
+        const double cc = -cy[j * M + row];
+        tt[v] = cc * Xv[j + 1][v];
+        tp[v] = cc * zt[v];
+        xp[v] = pz[j * M + row];
+      }
+      d4 x = Xv[j];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        x = mfma(Sv[j][kk], tt[kk], x);
+        xp = mfma(Sv[j][kk], tp[kk], xp);
+      }
+      Xv[j] = x;
+      zt = xp;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = xp[v];
+      }
     }
-    d4 x = Xv[j];
+    if (t < M - 1 - MID) {
+      const int j = MID + 1 + t;   // lower chain: X_j = W_j - T_j^-1 C_{j-1} X_{j-1}
+      d4 tt, tp, xp;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      x = mfma(Sv[j][kk], t[kk], x);
-      xp = mfma(Sv[j][kk], tp[kk], xp);
-    }
-    Xv[j] = x;
-    xpn = xp;
-    if (c == 0) {
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * v + gq;
+        const double cc = -cy[(j - 1) * M + row];
+        tt[v] = cc * Xv[j - 1][v];
+        tp[v] = cc * zb[v];
+        xp[v] = pz[j * M + row];
+      }
+      d4 x = Xv[j];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = xp[v];
+      for (int kk = 0; kk < 4; ++kk) {
+        x = mfma(Sv[j][kk], tt[kk], x);
+        xp = mfma(Sv[j][kk], tp[kk], xp);
+      }
+      Xv[j] = x;
+      zb = xp;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = xp[v];
+      }
     }
   }
   if (bad) atomicOr(a.status, ST_LOCAL_PIVOT);
 
   // one step of iterative refinement of all 17 columns: residual
-  // R = B - A X in double-double (tile by tile, the in-row neighbours through
-  // an LDS staging tile), correction by the same block sweeps with the
-  // stored inverse blocks
+  // R = B - A X in double-double (block row by block row, the in-row
+  // neighbours through an LDS staging tile), correction by the same
+  // two-sided sweeps with the stored inverse blocks
   {
-    __shared__ double T[M][M + 1];
+    __shared__ double T[2][M][M + 1];
     __shared__ double zc[MM];
-    d4 Zc[M];
-    d4 zq = {0.0, 0.0, 0.0, 0.0};
+    f4z Zc[M];
+    d4 qt = zero, qb = zero;
     __syncthreads();
+    auto residual = [&](int j, int h, d4& r, d4& rp) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) T[4 * v + gq][c] = Xv[j][v];
+      for (int v = 0; v < 4; ++v) T[h][4 * v + gq][c] = Xv[j][v];
       __syncthreads();
-      d4 r, rp;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = 4 * v + gq, l = j * M + i;
@@ -330,65 +459,154 @@ __global__ void __launch_bounds__(WAVE) basis_m16d4_kernel(SubArgs a) {
         double ph = b0[l], pl = 0.0;
         dd_fma(hi, lo, -dg[l], Xv[j][v]);
         dd_fma(ph, pl, -dg[l], pz[l]);
-        if (i < M - 1) { dd_fma(hi, lo, -ex[l], T[i + 1][c]); dd_fma(ph, pl, -ex[l], pz[l + 1]); }
-        if (i > 0) { dd_fma(hi, lo, -ex[l - 1], T[i - 1][c]); dd_fma(ph, pl, -ex[l - 1], pz[l - 1]); }
-        if (j < M - 1) { dd_fma(hi, lo, -cy[l], Xv[j < M - 1 ? j + 1 : j][v]); dd_fma(ph, pl, -cy[l], pz[l + M]); }
+        if (i < M - 1) { dd_fma(hi, lo, -ex[l], T[h][i + 1][c]); dd_fma(ph, pl, -ex[l], pz[l + 1]); }
+        if (i > 0) { dd_fma(hi, lo, -ex[l - 1], T[h][i - 1][c]); dd_fma(ph, pl, -ex[l - 1], pz[l - 1]); }
+        if (j < M - 1) {
+          dd_fma(hi, lo, -cy[l], Xv[j < M - 1 ? j + 1 : j][v]);
+          dd_fma(ph, pl, -cy[l], pz[l + M]);
+        }
         if (j > 0) {
           dd_fma(hi, lo, -cy[l - M], Xv[j > 0 ? j - 1 : 0][v]);
           dd_fma(ph, pl, -cy[l - M], pz[l - M]);
         }
-        double rr = hi + lo, rq = ph + pl;
-        if (j > 0) {
-          rr -= cy[(j - 1) * M + i] * Zc[j > 0 ? j - 1 : 0][v];
-          rq -= cy[(j - 1) * M + i] * zq[v];
-        }
-        r[v] = rr;
-        rp[v] = rq;
+        r[v] = hi + lo;
+        rp[v] = ph + pl;
       }
+    };
+#pragma unroll
+    for (int ju = 0; ju < MID; ++ju) {
+      d4 ru, rpu;
+      residual(ju, 0, ru, rpu);
       __syncthreads();
-      d4 z = {0.0, 0.0, 0.0, 0.0}, zz = {0.0, 0.0, 0.0, 0.0};
+      if (ju > 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double cc = cy[(ju - 1) * M + 4 * v + gq];
+          ru[v] -= cc * (double)Zc[ju > 0 ? ju - 1 : 0][v];
+          rpu[v] -= cc * qt[v];
+        }
+      }
+      d4 z = zero, zz = zero;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        z = mfma(Sv[ju][kk], ru[kk], z);
+        zz = mfma(Sv[ju][kk], rpu[kk], zz);
+      }
+      Zc[ju] = tof(z);
+      qt = zz;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) zc[ju * M + 4 * v + gq] = zz[v];
+      }
+    }
+#pragma unroll
+    for (int jl = M - 1; jl > MID; --jl) {
+      d4 rl, rpl;
+      residual(jl, 1, rl, rpl);
+      __syncthreads();
+      if (jl < M - 1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double cc = cy[jl * M + 4 * v + gq];
+          rl[v] -= cc * (double)Zc[jl < M - 1 ? jl + 1 : jl][v];
+          rpl[v] -= cc * qb[v];
+        }
+      }
+      d4 z = zero, zz = zero;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        z = mfma(Sv[jl][kk], rl[kk], z);
+        zz = mfma(Sv[jl][kk], rpl[kk], zz);
+      }
+      Zc[jl] = tof(z);
+      qb = zz;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) zc[jl * M + 4 * v + gq] = zz[v];
+      }
+    }
+    {
+      constexpr int j = MID;
+      d4 r, rp;
+      residual(j, 0, r, rp);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double cu = cy[(j - 1) * M + 4 * v + gq], cl = cy[j * M + 4 * v + gq];
+        r[v] -= cu * (double)Zc[j - 1][v] + cl * (double)Zc[j + 1][v];
+        rp[v] -= cu * qt[v] + cl * qb[v];
+      }
+      d4 z = zero, zz = zero;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         z = mfma(Sv[j][kk], r[kk], z);
         zz = mfma(Sv[j][kk], rp[kk], zz);
       }
-      Zc[j] = z;
-      zq = zz;
+      Zc[j] = tof(z);
+      qt = zz;
+      qb = zz;
       if (c == 0) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) zc[j * M + 4 * v + gq] = zz[v];
       }
     }
     __syncthreads();
-    d4 cn = Zc[M - 1], cq = zq;
-    Xv[M - 1] += cn;
+    Xv[MID] += tod(Zc[MID]);
     if (c == 0) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) pz[(M - 1) * M + 4 * v + gq] += cq[v];
+      for (int v = 0; v < 4; ++v) pz[MID * M + 4 * v + gq] += qt[v];
     }
+    d4 cu = tod(Zc[MID]), cl = tod(Zc[MID]);
 #pragma unroll
-    for (int j = M - 2; j >= 0; --j) {
-      d4 t, tq, xq;
+    for (int t = 0; t < MID; ++t) {
+      {
+        const int j = MID - 1 - t;
+        d4 tt, tq, xq;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 4 * v + gq;
-        const double cc = -cy[j * M + i];
-        t[v] = cc * cn[v];
-        tq[v] = cc * cq[v];
-        xq[v] = zc[j * M + i];
+        for (int v = 0; v < 4; ++v) {
+          const int i = 4 * v + gq;
+          const double cc = -cy[j * M + i];
+          tt[v] = cc * cu[v];
+          tq[v] = cc * qt[v];
+          xq[v] = zc[j * M + i];
+        }
+        d4 x = tod(Zc[j]);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          x = mfma(Sv[j][kk], tt[kk], x);
+          xq = mfma(Sv[j][kk], tq[kk], xq);
+        }
+        cu = x;
+        qt = xq;
+        Xv[j] += x;
+        if (c == 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] += xq[v];
+        }
       }
-      d4 x = Zc[j];
+      if (t < M - 1 - MID) {
+        const int j = MID + 1 + t;
+        d4 tt, tq, xq;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        x = mfma(Sv[j][kk], t[kk], x);
-        xq = mfma(Sv[j][kk], tq[kk], xq);
-      }
-      cn = x;
-      cq = xq;
-      Xv[j] += x;
-      if (c == 0) {
+        for (int v = 0; v < 4; ++v) {
+          const int i = 4 * v + gq;
+          const double cc = -cy[(j - 1) * M + i];
+          tt[v] = cc * cl[v];
+          tq[v] = cc * qb[v];
+          xq[v] = zc[j * M + i];
+        }
+        d4 x = tod(Zc[j]);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] += xq[v];
+        for (int kk = 0; kk < 4; ++kk) {
+          x = mfma(Sv[j][kk], tt[kk], x);
+          xq = mfma(Sv[j][kk], tq[kk], xq);
+        }
+        cl = x;
+        qb = xq;
+        Xv[j] += x;
+        if (c == 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] += xq[v];
+        }
       }
     }
     __syncthreads();
