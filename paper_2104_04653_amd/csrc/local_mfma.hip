@@ -66,44 +66,51 @@ __device__ inline double recip(double p) {
   return fma(r, fma(-p, r, 1.0), r);
 }
 
-// In-place inverse of the SPD tile s (output layout) by Gauss-Jordan sweeps.
-__device__ inline d4 gauss_jordan16(d4 s, int c, int g, bool& bad) {
-#pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const int kv = k >> 2, kg = k & 3;                       // row k: register kv, group kg
-    const double p = readlane_d(s[kv], k + 16 * kg);       // S[k][k]
-    const double prow = __shfl(s[kv], c + 16 * kg);         // S[k][c]
-    double pcol[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) pcol[v] = __shfl(s[v], k + 16 * g);   // S[4v+g][k]
-    if (!(p > 0.0) || !isfinite(p)) bad = true;
-    const double ip = recip(p);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 4 * v + g;
-      double nv;
-      if (row == k) nv = (c == k) ? ip : s[v] * ip;
-      else nv = (c == k) ? -pcol[v] * ip : fma(-pcol[v] * ip, prow, s[v]);
-      s[v] = nv;
-    }
-  }
-  return s;
+// value of lane K of each 16-lane row (DPP row_newbcast, two 32-bit moves)
+template <int K>
+__device__ inline double row_bcast(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(u & 0xffffffffu), 0x150 + K, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x150 + K, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// Schur-complemented diagonal block S_j = D_j - C_{j-1} S_{j-1}^{-1} C_{j-1}
-// in output layout (prev = S_{j-1}^{-1}).
-__device__ inline d4 schur_block(int j, const d4& prev, int c, int g, const double* dg,
-                                 const double* ex, const double* cy) {
-  d4 s;
+// One Gauss-Jordan sweep with pivot K on a tile in the output layout: the
+// pivot column (row 4 v + g, column K) comes from lane K of the lane's own
+// 16-lane row, the pivot row (row K, column c) from lane c + 16 (K % 4).
+template <int K>
+__device__ inline void gj_sweep(d4& s, int c, int g, bool& bad) {
+  constexpr int kv = K >> 2, kg = K & 3;
+  const double p = readlane_d(s[kv], K + 16 * kg);
+  const double prow = __shfl(s[kv], c + 16 * kg);
+  double pcol[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) pcol[v] = row_bcast<K>(s[v]);
+  if (!(p > 0.0) || !isfinite(p)) bad = true;
+  const double ip = recip(p);
+  const double b = (c == K) ? ip : prow * ip;      // new row K
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int row = 4 * v + g;
-    double d = (row == c) ? dg[j * M + row]
-             : (row == c + 1) ? ex[j * M + c]
-             : (c == row + 1) ? ex[j * M + row] : 0.0;
-    if (j > 0) d -= cy[(j - 1) * M + row] * prev[v] * cy[(j - 1) * M + c];
-    s[v] = d;
+    const double nv = fma(-pcol[v], b, (c == K) ? 0.0 : s[v]);
+    s[v] = (v == kv && g == kg) ? b : nv;
   }
+}
+
+template <int K>
+struct GJ16 {
+  static __device__ inline void run(d4& s, int c, int g, bool& bad) {
+    gj_sweep<K>(s, c, g, bad);
+    GJ16<K + 1>::run(s, c, g, bad);
+  }
+};
+template <>
+struct GJ16<M> {
+  static __device__ inline void run(d4&, int, int, bool&) {}
+};
+
+// In-place inverse of the SPD tile s (output layout) by Gauss-Jordan sweeps.
+__device__ inline d4 gauss_jordan16(d4 s, int c, int g, bool& bad) {
+  GJ16<0>::run(s, c, g, bad);
   return s;
 }
 
@@ -129,12 +136,9 @@ __device__ inline d4 coupled_block(int j, int jc, const d4& P, int c, int g, con
 // local cell (li, lj): non-zero only next to the face of its side
 __device__ inline double side_rhs(const double (*bside)[M][D], int lj, int li, int c) {
   const int side = c >> 2, k = c & 3;
-  switch (side) {
-    case 0: return li == 0 ? bside[0][lj][k] : 0.0;
-    case 1: return li == M - 1 ? bside[1][lj][k] : 0.0;
-    case 2: return lj == 0 ? bside[2][li][k] : 0.0;
-    default: return lj == M - 1 ? bside[3][li][k] : 0.0;
-  }
+  const bool on = side == 0 ? li == 0 : side == 1 ? li == M - 1 : side == 2 ? lj == 0 : lj == M - 1;
+  const double v = bside[side][side < 2 ? lj : li][k];
+  return on ? v : 0.0;
 }
 
 // One column solve with the stored inverse blocks Sv (rhs and result in
@@ -444,9 +448,21 @@ __global__ void __launch_bounds__(WAVE) basis_m16d4_kernel(SubArgs a) {
   // two-sided sweeps with the stored inverse blocks
   {
     __shared__ double T[2][M][M + 1];
-    __shared__ double zc[MM];
+    __shared__ double zc[MM], rpz[MM];
     f4z Zc[M];
     d4 qt = zero, qb = zero;
+    __syncthreads();
+    // particular column: residual of all cells first (4 cells per lane)
+    for (int l = lane; l < MM; l += WAVE) {
+      const int i = l % M, j = l / M;
+      double ph = b0[l], pl = 0.0;
+      dd_fma(ph, pl, -dg[l], pz[l]);
+      dd_fma(ph, pl, i < M - 1 ? -ex[l] : 0.0, pz[i < M - 1 ? l + 1 : l]);
+      dd_fma(ph, pl, i > 0 ? -ex[l - 1] : 0.0, pz[i > 0 ? l - 1 : l]);
+      dd_fma(ph, pl, j < M - 1 ? -cy[l] : 0.0, pz[j < M - 1 ? l + M : l]);
+      dd_fma(ph, pl, j > 0 ? -cy[l - M] : 0.0, pz[j > 0 ? l - M : l]);
+      rpz[l] = ph + pl;
+    }
     __syncthreads();
     auto residual = [&](int j, int h, d4& r, d4& rp) {
 #pragma unroll
@@ -456,21 +472,13 @@ __global__ void __launch_bounds__(WAVE) basis_m16d4_kernel(SubArgs a) {
       for (int v = 0; v < 4; ++v) {
         const int i = 4 * v + gq, l = j * M + i;
         double hi = side_rhs(bside, j, i, c), lo = 0.0;
-        double ph = b0[l], pl = 0.0;
         dd_fma(hi, lo, -dg[l], Xv[j][v]);
-        dd_fma(ph, pl, -dg[l], pz[l]);
-        if (i < M - 1) { dd_fma(hi, lo, -ex[l], T[h][i + 1][c]); dd_fma(ph, pl, -ex[l], pz[l + 1]); }
-        if (i > 0) { dd_fma(hi, lo, -ex[l - 1], T[h][i - 1][c]); dd_fma(ph, pl, -ex[l - 1], pz[l - 1]); }
-        if (j < M - 1) {
-          dd_fma(hi, lo, -cy[l], Xv[j < M - 1 ? j + 1 : j][v]);
-          dd_fma(ph, pl, -cy[l], pz[l + M]);
-        }
-        if (j > 0) {
-          dd_fma(hi, lo, -cy[l - M], Xv[j > 0 ? j - 1 : 0][v]);
-          dd_fma(ph, pl, -cy[l - M], pz[l - M]);
-        }
+        dd_fma(hi, lo, i < M - 1 ? -ex[l] : 0.0, T[h][i < M - 1 ? i + 1 : i][c]);
+        dd_fma(hi, lo, i > 0 ? -ex[i > 0 ? l - 1 : l] : 0.0, T[h][i > 0 ? i - 1 : i][c]);
+        if (j < M - 1) dd_fma(hi, lo, -cy[l], Xv[j < M - 1 ? j + 1 : j][v]);
+        if (j > 0) dd_fma(hi, lo, -cy[l - M], Xv[j > 0 ? j - 1 : 0][v]);
         r[v] = hi + lo;
-        rp[v] = ph + pl;
+        rp[v] = rpz[l];
       }
     };
 #pragma unroll
@@ -1040,7 +1048,7 @@ __global__ void __launch_bounds__(WAVE) stitch_m16d4_kernel(SubArgs a) {
   d4 prev = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int j = 0; j < M; ++j) {
-    d4 s = schur_block(j, prev, c, gq, dg, ex, cy);
+    d4 s = coupled_block(j, j - 1, prev, c, gq, dg, ex, cy);
     s = gauss_jordan16(s, c, gq, bad);
     Sv[j] = s;
     prev = s;
