@@ -152,7 +152,7 @@ def full_space(m):
 
 
 def edge_solution_space(k_lo, k_hi):
-    """Non-polynomial two-function spaces from a 1-D edge problem.
+    """Non-polynomial two-function spaces from a 1-D edge problem (§3.1).
 
     t_j is the harmonic mean of the permeabilities across fine face j.
     psi solves the 1-D two-point problem along the edge with conductances
@@ -160,27 +160,23 @@ def edge_solution_space(k_lo, k_hi):
     interface ends, psi = 1 at a and psi = 0 at b.  Pressure space:
     {psi, 1 - psi}; flux space: {t / mean t, t (psi - mean psi) / mean t}.
     With uniform permeability both reduce to the linear space.
+
+    The 1-D problem is a chain of conductances in series, so its solution is
+    the fraction of the total resistance that lies between face j and the
+    b end; 1 - psi is the fraction on the a side, summed directly, so both
+    functions keep their relative accuracy where they are small (high
+    contrast along the edge).
     """
     t = harmonic_mean(np.asarray(k_lo, float), np.asarray(k_hi, float))
     m = t.size
-    tau = harmonic_mean(t[:-1], t[1:]) if m > 1 else np.zeros(0)
-    ta, tb = 2.0 * t[0], 2.0 * t[-1]
-    A = np.zeros((m, m))
-    rhs = np.zeros(m)
-    for j in range(m):
-        if j == 0:
-            A[j, j] += ta
-            rhs[j] += ta * 1.0
-        else:
-            A[j, j] += tau[j - 1]
-            A[j, j - 1] -= tau[j - 1]
-        if j == m - 1:
-            A[j, j] += tb
-        else:
-            A[j, j] += tau[j]
-            A[j, j + 1] -= tau[j]
-    psi = np.linalg.solve(A, rhs)
-    pspace = np.stack([psi, 1.0 - psi])
+    r_in = 1.0 / harmonic_mean(t[:-1], t[1:]) if m > 1 else np.zeros(0)
+    r_a, r_b = 1.0 / (2.0 * t[0]), 1.0 / (2.0 * t[-1])
+    # resistance from the a end to face j, and from face j to the b end
+    up = r_a + np.concatenate([[0.0], np.cumsum(r_in)])
+    down = r_b + np.concatenate([np.cumsum(r_in[::-1])[::-1], [0.0]])
+    total = r_a + r_in.sum() + r_b
+    psi = down / total
+    pspace = np.stack([psi, up / total])
     tm = t.mean()
     uspace = np.stack([t / tm, t * (psi - psi.mean()) / tm])
     return pspace, uspace

@@ -9,7 +9,7 @@ import pytest
 
 from inputs import Problem, make_problem
 from inputs.problems import DIRICHLET, NEUMANN
-from oracle.discretization import (Geometry, edge_solution_space, fractional_flow,
+from oracle.discretization import (Geometry, edge_solution_space, fractional_flow, harmonic_mean,
                                    total_mobility)
 from oracle.fine import solve_fine
 from oracle.mrcm import solve_mrcm, solve_mrcm_monolithic
@@ -259,6 +259,83 @@ def test_edge_solution_space_reduces_to_linear():
     rng = np.random.default_rng(3)
     ps, us = edge_solution_space(np.exp(rng.normal(size=m) * 3), np.exp(rng.normal(size=m) * 3))
     assert np.all(np.diff(ps[0]) < 0) and ps[0].max() < 1 and ps[0].min() > 0
+
+
+def _edge_system(k_lo, k_hi):
+    """The 1-D two-point system of the edge problem, assembled."""
+    t = harmonic_mean(k_lo, k_hi)
+    m = t.size
+    A = np.zeros((m, m))
+    rhs = np.zeros(m)
+    for j in range(m):
+        if j == 0:
+            A[j, j] += 2 * t[0]
+            rhs[j] = 2 * t[0]
+        else:
+            c = harmonic_mean(t[j - 1], t[j])
+            A[j, j] += c
+            A[j, j - 1] -= c
+        if j == m - 1:
+            A[j, j] += 2 * t[-1]
+        else:
+            c = harmonic_mean(t[j], t[j + 1])
+            A[j, j] += c
+            A[j, j + 1] -= c
+    return A, rhs
+
+
+def test_edge_solution_solves_the_edge_problem():
+    """psi is the solution of the assembled 1-D two-point problem."""
+    rng = np.random.default_rng(7)
+    for m in (4, 16, 32):
+        k_lo, k_hi = np.exp(rng.normal(size=m) * 2), np.exp(rng.normal(size=m) * 2)
+        A, rhs = _edge_system(k_lo, k_hi)
+        ps, _ = edge_solution_space(k_lo, k_hi)
+        assert np.allclose(ps[0], np.linalg.solve(A, rhs), rtol=1e-13, atol=0)
+        assert np.allclose(A @ ps[0], rhs, rtol=0, atol=1e-12 * np.abs(A).max())
+
+
+def test_edge_solution_relative_accuracy_at_high_contrast():
+    """Exact rational elimination of the assembled edge system at contrast
+    1e8: psi and 1 - psi hold full relative accuracy in every entry."""
+    from fractions import Fraction
+    k_lo = np.array([1e8, 2e8, 1.0, 3.0, 0.5, 2.0, 1e8, 3e8])
+    k_hi = np.array([3e8, 1e8, 2.0, 1.0, 0.7, 1e8, 1e8, 1e8])
+    m = k_lo.size
+    F = [Fraction(x) for x in k_lo], [Fraction(x) for x in k_hi]
+    h = lambda a, b: 2 * a * b / (a + b)
+    t = [h(F[0][j], F[1][j]) for j in range(m)]
+    A = [[Fraction(0)] * m for _ in range(m)]
+    rhs = [Fraction(0)] * m
+    for j in range(m):
+        if j == 0:
+            A[0][0] += 2 * t[0]
+            rhs[0] = 2 * t[0]
+        else:
+            c = h(t[j - 1], t[j])
+            A[j][j] += c
+            A[j][j - 1] -= c
+        if j == m - 1:
+            A[j][j] += 2 * t[-1]
+        else:
+            c = h(t[j], t[j + 1])
+            A[j][j] += c
+            A[j][j + 1] -= c
+    for j in range(1, m):          # exact elimination
+        f = A[j][j - 1] / A[j - 1][j - 1]
+        A[j][j] -= f * A[j - 1][j]
+        A[j][j - 1] = Fraction(0)
+        rhs[j] -= f * rhs[j - 1]
+    x = [Fraction(0)] * m
+    x[-1] = rhs[-1] / A[-1][-1]
+    for j in range(m - 2, -1, -1):
+        x[j] = (rhs[j] - A[j][j + 1] * x[j + 1]) / A[j][j]
+    ps, _ = edge_solution_space(k_lo, k_hi)
+    exact = np.array([float(v) for v in x])
+    exact_c = np.array([float(1 - v) for v in x])
+    assert exact_c.min() < 1e-7 and exact.min() < 1e-7   # both functions get small
+    assert np.allclose(ps[0], exact, rtol=1e-14, atol=0)
+    assert np.allclose(ps[1], exact_c, rtol=1e-14, atol=0)
 
 
 def test_edge_space_homogeneous_equals_linear_mrcm():
