@@ -66,6 +66,8 @@ struct mrcm_ctx {
   PanelItem* d_items = nullptr;
   double* inv = nullptr;        // per-panel diagonal-block inverses of blocked fronts
   double* partials = nullptr;   // residual partial maxima
+  double* scratch = nullptr;    // generic local kernels: per-subdomain work arrays
+  long long scratch_stride = 0;
   // surrogate precision: network parameters and per-subdomain activations
   float* s_p32 = nullptr;
   short* s_wb = nullptr;
@@ -124,49 +126,33 @@ double hmean(double a, double b) { return 2.0 * a * b / (a + b); }
 // face j; psi solves the 1-D two-point problem along the edge (conductance
 // hmean(t_j, t_{j+1}) between neighbours, 2 t at the two ends) with psi = 1
 // at the first end and 0 at the other.  Pressure functions {psi, 1 - psi},
-// flux functions {t / mean t, t (psi - mean psi) / mean t}.
+// flux functions {t / mean t, t (psi - mean psi) / mean t}.  The conductances
+// are in series, so psi at face j is the share of the total resistance
+// between face j and the far end, and 1 - psi the share on the near side;
+// both are formed as such sums, which keeps each accurate where it is small.
 void edge_solution(const std::vector<double>& klo, const std::vector<double>& khi, double* out,
                    int M) {
-  std::vector<double> t(M), lo(M), di(M), up(M), rhs(M), psi(M);
+  std::vector<double> t(M), near(M), far(M);
   for (int j = 0; j < M; ++j) t[j] = hmean(klo[j], khi[j]);
-  for (int j = 0; j < M; ++j) {
-    double d = 0.0;
-    lo[j] = up[j] = 0.0;
-    rhs[j] = 0.0;
-    if (j == 0) {
-      d += 2.0 * t[0];
-      rhs[j] = 2.0 * t[0];
-    } else {
-      const double c = hmean(t[j - 1], t[j]);
-      d += c;
-      lo[j] = -c;
-    }
-    if (j == M - 1) {
-      d += 2.0 * t[M - 1];
-    } else {
-      const double c = hmean(t[j], t[j + 1]);
-      d += c;
-      up[j] = -c;
-    }
-    di[j] = d;
-  }
-  // tridiagonal elimination (the matrix is an M-matrix, no pivoting needed)
-  for (int j = 1; j < M; ++j) {
-    const double f = lo[j] / di[j - 1];
-    di[j] -= f * up[j - 1];
-    rhs[j] -= f * rhs[j - 1];
-  }
-  psi[M - 1] = rhs[M - 1] / di[M - 1];
-  for (int j = M - 2; j >= 0; --j) psi[j] = (rhs[j] - up[j] * psi[j + 1]) / di[j];
+  const double r_first = 1.0 / (2.0 * t[0]), r_last = 1.0 / (2.0 * t[M - 1]);
+  near[0] = r_first;
+  for (int j = 1; j < M; ++j) near[j] = near[j - 1] + 1.0 / hmean(t[j - 1], t[j]);
+  far[M - 1] = r_last;
+  for (int j = M - 2; j >= 0; --j) far[j] = far[j + 1] + 1.0 / hmean(t[j], t[j + 1]);
+  const double total = near[M - 1] + r_last;
   double tm = 0.0, pm = 0.0;
-  for (int j = 0; j < M; ++j) { tm += t[j]; pm += psi[j]; }
+  for (int j = 0; j < M; ++j) {
+    tm += t[j];
+    pm += far[j] / total;
+  }
   tm /= M;
   pm /= M;
   for (int j = 0; j < M; ++j) {
-    out[0 * M + j] = psi[j];
-    out[1 * M + j] = 1.0 - psi[j];
+    const double psi = far[j] / total;
+    out[0 * M + j] = psi;
+    out[1 * M + j] = near[j] / total;
     out[2 * M + j] = t[j] / tm;
-    out[3 * M + j] = t[j] * (psi[j] - pm) / tm;
+    out[3 * M + j] = t[j] * (psi - pm) / tm;
   }
 }
 
@@ -413,6 +399,8 @@ SubArgs sub_args(const mrcm_ctx* c) {
   a.fallback = c->fallback;
   a.ir_iters = c->ir_iters;
   a.gate_tol = c->gate_tol;
+  a.scratch = c->scratch;
+  a.scratch_stride = c->scratch_stride;
   return a;
 }
 
@@ -546,6 +534,8 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
     ALLOC(c, c->status, 1);
     ALLOC(c, c->fallback, G.n_sub + 1);
     ALLOC(c, c->ir_iters, 1);
+    c->scratch_stride = local_scratch_doubles(G);
+    if (c->scratch_stride > 0) ALLOC(c, c->scratch, (size_t)G.n_sub * c->scratch_stride);
     if (precision == MRCM_PREC_SURROGATE) {
       const size_t pix = (size_t)G.n_sub * M * M;
       ALLOC(c, c->s_p32, cnn::n_params());

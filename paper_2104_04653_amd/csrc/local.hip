@@ -34,50 +34,71 @@ namespace mrcm {
 namespace {
 
 constexpr int NT = 256;
+constexpr int LOCAL_IR_STEPS = 3;   // refinement steps of the local basis solve
 using namespace local;
 
 // Block elimination of the local system for NR right-hand sides held in
 // Xs[MM][NR]; leaves the solution in Xs and the inverse Schur blocks in
-// Sinv[M][MM].  Requires M*M <= blockDim.x.
+// Sinv[M][MM] (LDS, or global scratch for large M).  Each thread keeps
+// EPT elements of S_j in registers.
 template <int M, int NR>
 __device__ void thomas_solve(double* Xs, double* Sinv, const double* dg, const double* ex,
                              const double* cy, double* pivbuf /*[2][2][M]*/, int* status,
                              int flag) {
   constexpr int MM = M * M;
   constexpr int NQ = (M * NR + NT - 1) / NT;
+  constexpr int EPT = (MM + NT - 1) / NT;
   const int tid = threadIdx.x;
-  const bool own = tid < MM;
-  const int ta = tid / M, tb = tid % M;
-  double s = 0.0;
+  double s[EPT];
+  int ta[EPT], tb[EPT];
+  bool own[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = tid + q * NT;
+    own[q] = e < MM;
+    ta[q] = e / M;
+    tb[q] = e % M;
+    s[q] = 0.0;
+  }
   int par = 0;
   bool bad = false;
   double acc[NQ];
   for (int j = 0; j < M; ++j) {
-    if (own) {
-      double dv = (ta == tb) ? dg[j * M + ta]
-                : (tb == ta + 1) ? ex[j * M + ta]
-                : (ta == tb + 1) ? ex[j * M + tb] : 0.0;
-      if (j > 0) dv -= cy[(j - 1) * M + ta] * s * cy[(j - 1) * M + tb];
-      s = dv;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      if (!own[q]) continue;
+      const int a_ = ta[q], b_ = tb[q];
+      double dv = (a_ == b_) ? dg[j * M + a_]
+                : (b_ == a_ + 1) ? ex[j * M + a_]
+                : (a_ == b_ + 1) ? ex[j * M + b_] : 0.0;
+      if (j > 0) dv -= cy[(j - 1) * M + a_] * s[q] * cy[(j - 1) * M + b_];
+      s[q] = dv;
     }
     for (int k = 0; k < M; ++k) {
-      if (own && tb == k) pivbuf[(par * 2 + 0) * M + ta] = s;
-      if (own && ta == k) pivbuf[(par * 2 + 1) * M + tb] = s;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        if (own[q] && tb[q] == k) pivbuf[(par * 2 + 0) * M + ta[q]] = s[q];
+        if (own[q] && ta[q] == k) pivbuf[(par * 2 + 1) * M + tb[q]] = s[q];
+      }
       __syncthreads();
-      if (own) {
-        const double p = pivbuf[(par * 2 + 1) * M + k];
-        if (!(p > 0.0)) bad = true;
-        const double ip = 1.0 / p;
-        const double sak = pivbuf[(par * 2 + 0) * M + ta];
-        const double skb = pivbuf[(par * 2 + 1) * M + tb];
-        if (ta == k && tb == k) s = ip;
-        else if (ta == k) s = s * ip;
-        else if (tb == k) s = -sak * ip;
-        else s = s - sak * skb * ip;
+      const double p = pivbuf[(par * 2 + 1) * M + k];
+      if (!(p > 0.0)) bad = true;
+      const double ip = 1.0 / p;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        if (!own[q]) continue;
+        const double sak = pivbuf[(par * 2 + 0) * M + ta[q]];
+        const double skb = pivbuf[(par * 2 + 1) * M + tb[q]];
+        if (ta[q] == k && tb[q] == k) s[q] = ip;
+        else if (ta[q] == k) s[q] = s[q] * ip;
+        else if (tb[q] == k) s[q] = -sak * ip;
+        else s[q] = s[q] - sak * skb * ip;
       }
       par ^= 1;
     }
-    if (own) Sinv[j * MM + tid] = s;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q)
+      if (own[q]) Sinv[j * MM + tid + q * NT] = s[q];
     __syncthreads();
     // Z_j = S_j^{-1} (B_j - C_{j-1} Z_{j-1})
     {
@@ -184,27 +205,72 @@ __device__ void local_residual(const double* b, const double* x, double* r, cons
   }
 }
 
+// b <- b - A x in double-double for the local five-point matrix, NR columns
+template <int M, int NR>
+__device__ void local_residual_dd(double* b, const double* x, const double* dg, const double* ex,
+                                  const double* cy) {
+  for (int o = threadIdx.x; o < M * M * NR; o += NT) {
+    const int l = o / NR, col = o % NR;
+    const int li = l % M, lj = l / M;
+    double hi = b[o], lo = 0.0;
+    dd_fma(hi, lo, -dg[l], x[o]);
+    if (li < M - 1) dd_fma(hi, lo, -ex[l], x[(l + 1) * NR + col]);
+    if (li > 0) dd_fma(hi, lo, -ex[l - 1], x[(l - 1) * NR + col]);
+    if (lj < M - 1) dd_fma(hi, lo, -cy[l], x[(l + M) * NR + col]);
+    if (lj > 0) dd_fma(hi, lo, -cy[l - M], x[(l - M) * NR + col]);
+    b[o] = hi + lo;
+  }
+}
+
+// LDS holds the basis-function block and the inverse Schur blocks up to
+// 16 x 16 subdomains; larger ones keep them in the per-subdomain scratch
+template <int M>
+struct LocalStore {
+  static constexpr bool big = M > 16;
+};
+
 template <int M, int D>
 __global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
   constexpr int R = 1 + 4 * D;
   constexpr int MM = M * M;
   constexpr int NBR = 4 * D, NBC = 4 * D + 1;
+  constexpr bool BIG = LocalStore<M>::big;
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
-  __shared__ double Xs[MM * R];
-  __shared__ double Sinv[M * MM];
+  __shared__ double Xs_l[BIG ? 1 : MM * R];
+  __shared__ double Sinv_l[BIG ? 1 : M * MM];
   __shared__ double pivbuf[4 * M];
   const Geo& g = a.g;
   const int tid = threadIdx.x;
   const int sd = blockIdx.x;
   const int I = sd % g.SX, J = sd / g.SX;
+  // per-subdomain scratch: [Bs | Rs] (all sizes), then [Xs | Sinv] beyond
+  // 16 x 16; its length is local_scratch_doubles()
+  double* scr = a.scratch + (size_t)sd * a.scratch_stride;
+  double* Rs_l = scr + MM * R;
+  double* Bs = scr;
+  double* Xs = BIG ? scr + 2 * MM * R : Xs_l;
+  double* Sinv = BIG ? scr + 3 * MM * R : Sinv_l;
 
   load_kappa<M>(a, I, J, kap);
   __syncthreads();
   for (int l = tid; l < MM; l += NT)
     assemble_cell<M, R>(a, I, J, l, kap, dg, ex, cy, Xs + l * R, 1, nullptr);
   __syncthreads();
+  for (int o = tid; o < MM * R; o += NT) Bs[o] = Xs[o];
 
   thomas_solve<M, R>(Xs, Sinv, dg, ex, cy, pivbuf, a.status, ST_LOCAL_PIVOT);
+  // iterative refinement, residual in double-double (Bs keeps B; the
+  // correction goes through Rg)
+  double* Rg = Rs_l;
+  for (int it = 0; it < LOCAL_IR_STEPS; ++it) {
+    __syncthreads();
+    for (int o = tid; o < MM * R; o += NT) Rg[o] = Bs[o];
+    __syncthreads();
+    local_residual_dd<M, R>(Rg, Xs, dg, ex, cy);
+    thomas_resolve<M, R>(Rg, Sinv, cy);
+    for (int o = tid; o < MM * R; o += NT) Xs[o] += Rg[o];
+  }
+  __syncthreads();
 
   double* Xg = a.X + (size_t)sd * MM * R;   // column-major per subdomain: [col][cell]
   for (int o = tid; o < MM * R; o += NT) Xg[(o % R) * MM + o / R] = Xs[o];
@@ -284,13 +350,14 @@ __global__ void __launch_bounds__(NT) stitch_kernel(SubArgs a) {
   __shared__ double Xs[MM];          // stitch right-hand side / pressure
   __shared__ double Bs[MM];          // saved right-hand side
   __shared__ double Rs[MM];          // residual / correction
-  __shared__ double Sinv[M * MM];
+  __shared__ double Sinv_l[LocalStore<M>::big ? 1 : M * MM];
   __shared__ double pivbuf[4 * M];
   __shared__ double Fout[4][M];      // outflow of this subdomain on its skeleton faces
   __shared__ double red[3][NT];
   const Geo& g = a.g;
   const int tid = threadIdx.x;
   const int sd = blockIdx.x;
+  double* Sinv = LocalStore<M>::big ? a.scratch + (size_t)sd * a.scratch_stride : Sinv_l;
   const int I = sd % g.SX, J = sd / g.SX;
   const int nP = g.nP;
 
@@ -482,6 +549,7 @@ hipError_t dispatch(const SubArgs& a, hipStream_t st, bool stitch) {
     }
     return launch_basis_m16d4(a, st);
   }
+  if (M == 32 && D == 4) return launch_pair<32, 4>(a, st, stitch);
   if (M == 16 && D == 4) return launch_pair<16, 4>(a, st, stitch);
   if (M == 8 && D == 4) return launch_pair<8, 4>(a, st, stitch);
   if (M == 4 && D == 4) return launch_pair<4, 4>(a, st, stitch);
@@ -493,8 +561,15 @@ hipError_t dispatch(const SubArgs& a, hipStream_t st, bool stitch) {
 }  // namespace
 
 bool local_supported(int M, int D) {
-  return (M == 16 && D == 4) || (M == 8 && D == 4) || (M == 4 && D == 4) || (M == 8 && D == 16) ||
+  return (M == 32 && D == 4) || (M == 16 && D == 4) || (M == 8 && D == 4) || (M == 4 && D == 4) || (M == 8 && D == 16) ||
          (M == 4 && D == 8);
+}
+
+long long local_scratch_doubles(const Geo& g) {
+  const bool fast = g.M == 16 && g.D == 4 && g.nP == 2 && !g.generic;
+  if (fast) return 0;
+  const long long MM = (long long)g.M * g.M, R = 1 + 4 * g.D;
+  return 2 * MM * R + (g.M > 16 ? MM * R + g.M * MM : 0);
 }
 
 hipError_t launch_local_basis(const SubArgs& a, hipStream_t st) { return dispatch(a, st, false); }

@@ -52,6 +52,8 @@ struct SubArgs {
   int* fallback;          // FP32 refinement: [0] = count, [1..] = subdomains to redo in FP64
   int* ir_iters;          // FP32 refinement: [0] = largest refinement count used
   double gate_tol;        // surrogate: accepted if ||b - A x|| <= gate_tol ||b|| per column
+  double* scratch;        // generic kernels: per-subdomain work arrays (global memory)
+  long long scratch_stride;   // doubles per subdomain in scratch
 };
 
 // Frontal-matrix node of the nested-dissection elimination of the
@@ -90,6 +92,8 @@ hipError_t launch_basis32_m16d4(const SubArgs& a, hipStream_t st);
 hipError_t launch_basis_m16d4_list(const SubArgs& a, hipStream_t st);
 hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st);
 bool local_supported(int M, int D);
+// doubles of global scratch per subdomain the generic kernels need (0 if none)
+long long local_scratch_doubles(const Geo& g);
 
 // ---- launchers (interface.hip) ----
 hipError_t launch_front_small(const NodeDesc* nodes, const int* ids, int count, int max_n,

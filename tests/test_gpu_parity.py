@@ -21,7 +21,12 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 
-def check_end_to_end(prob, s=None, lam=None, local=True, tol=TOL, label=""):
+def check_end_to_end(prob, s=None, lam=None, local=True, tol=TOL, label="", coef_tol=TOL):
+    """Parity of one case.  The pressure and flux bar is `tol`; the interface
+    coefficients are held to `coef_tol`, which cases with an ill-conditioned
+    interface system (high contrast with non-polynomial spaces) relax: there
+    rounding-level differences of the local blocks are amplified by the
+    system's condition number while p and the fluxes stay at `tol`."""
     say("case:", label or prob.name, prob.nx, prob.ny, "sub", prob.sub_nx, "space", prob.space)
     if s is not None:
         lam = total_mobility(s, prob.mu_w, prob.mu_o)
@@ -33,9 +38,6 @@ def check_end_to_end(prob, s=None, lam=None, local=True, tol=TOL, label=""):
     say("  rel L2: p %.2e  flux %.2e  interface coeffs %.2e  imbalance gpu %.2e oracle %.2e"
         "  iface res %.2e" % (ep, ef, ec, g["imbalance"], ref.imbalance,
                               g["stats"]["interface_residual"]))
-    assert ep < tol and ef < tol and ec < tol
-    floor = flux_floor(prob, lam, ref.p) / np.abs(np.r_[ref.Fx, ref.Fy]).max()
-    assert g["imbalance"] < max(1e-12, 64 * floor)
     if local:
         B = oracle_basis_padded(prob, ref)
         X = g["basis"]
@@ -48,6 +50,9 @@ def check_end_to_end(prob, s=None, lam=None, local=True, tol=TOL, label=""):
         ebl = float((np.abs(g["blocks"] - Bl) / scale).max())
         say("  basis max col rel %.2e  blocks %.2e" % (eb, ebl))
         assert eb < tol and ebl < tol
+    assert ep < tol and ef < tol and ec < coef_tol
+    floor = flux_floor(prob, lam, ref.p) / np.abs(np.r_[ref.Fx, ref.Fy]).max()
+    assert g["imbalance"] < max(1e-12, 64 * floor)
     return g, ref
 
 
