@@ -98,6 +98,8 @@ typedef struct {
   int32_t fallbacks;     /* FP32_IR / SURROGATE: subdomains re-solved in FP64 */
   double interface_residual; /* max |b - A x| / max |b| of the interface solve */
   double ms_surrogate;   /* SURROGATE: network inference + residual gate */
+  int32_t interface_ir_steps; /* refinement steps of the interface solve (taken while
+                                 max |b - A x| > 1e-14 max |b|, at most 3) */
 } mrcm_stats;
 
 /* Set up a solver for one grid, permeability field and decomposition

@@ -66,6 +66,10 @@ struct mrcm_ctx {
   PanelItem* d_items = nullptr;
   double* inv = nullptr;        // per-panel diagonal-block inverses of blocked fronts
   double* partials = nullptr;   // residual partial maxima
+  double* rtree = nullptr;      // interface refinement: rhs vectors of the fronts
+  double* rvec = nullptr;       // interface refinement: residual (n_dof)
+  double* dx = nullptr;         // interface refinement: correction (n_dof)
+  int iface_ir = 0;             // refinement steps taken by the last solve
   double* scratch = nullptr;    // generic local kernels: per-subdomain work arrays
   long long scratch_stride = 0;
   // surrogate precision: network parameters and per-subdomain activations
@@ -115,6 +119,9 @@ int dev_alloc(mrcm_ctx* c, T** p, size_t count) {
   } while (0)
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+constexpr int IFACE_IR_MAX = 3;         // refinement steps of the interface solve
+constexpr double IFACE_IR_TOL = 1e-14;  // max|r| / max|b| that needs no refinement
 
 // ---------------------------------------------------------------------------
 // interface spaces (section 3.1), tabulated per interface on its fine faces
@@ -266,6 +273,13 @@ int build_plan(mrcm_ctx* c) {
   for (auto& n : tb.nodes)
     if (!n.leaf) level_max_n[n.level] = std::max(level_max_n[n.level], (int)n.dofs.size());
   long long inv_total = 0;
+  long long r_total = 0;
+  std::vector<long long> node_r(tb.nodes.size(), -1);
+  for (size_t i = 0; i < tb.nodes.size(); ++i) {
+    if (tb.nodes[i].leaf) continue;
+    node_r[i] = r_total;
+    r_total += (long long)tb.nodes[i].dofs.size();
+  }
   for (size_t i = 0; i < tb.nodes.size(); ++i) {
     const HNode& n = tb.nodes[i];
     if (n.leaf) continue;
@@ -275,6 +289,7 @@ int build_plan(mrcm_ctx* c) {
     d.s = n.s;
     d.blocked = level_max_n[n.level] > SMALL_FRONT ? 1 : 0;
     d.inv_off = inv_total;
+    d.r_off = node_r[i];
     if (d.blocked)
       inv_total += (long long)((n.s + PANEL_NB - 1) / PANEL_NB) * PANEL_NB * PANEL_NB;
     if (d.n > MAX_FRONT) return fail(c, MRCM_E_UNSUPPORTED, "interface front too large");
@@ -282,6 +297,7 @@ int build_plan(mrcm_ctx* c) {
     d.dof_off = (long long)dofs.size();
     for (int q = 0; q < 2; ++q) {
       const HNode& ch = tb.nodes[n.child[q]];
+      d.cr_off[q] = ch.leaf ? -1 : node_r[n.child[q]] + ch.s;
       if (ch.leaf) {
         d.c_off[q] = (long long)ch.sd * c->leaf_block;
         d.c_ld[q] = 4 * g.D + 1;
@@ -361,6 +377,9 @@ int build_plan(mrcm_ctx* c) {
   }
   ALLOC(c, c->tree, total);
   ALLOC(c, c->inv, inv_total);
+  ALLOC(c, c->rtree, r_total);
+  ALLOC(c, c->rvec, c->n_dof);
+  ALLOC(c, c->dx, c->n_dof);
   ALLOC(c, c->partials, 2 * RESID_WG);
   ALLOC(c, c->d_nodes, desc.size());
   ALLOC(c, c->d_maps, maps.size());
@@ -426,8 +445,27 @@ int run_interface(mrcm_ctx* c) {
   }
   for (auto it = c->levels.rbegin(); it != c->levels.rend(); ++it)
     HIPCHK(c, launch_front_back(c->d_nodes, c->d_ids + it->ids_off, it->count, c->tree, c->inv,
-                                c->d_dofs, c->coef, st));
-  HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->partials, c->result + 2, st));
+                                c->d_dofs, nullptr, c->coef, st));
+  HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2, st));
+  // iterative refinement with the stored factors while the residual is
+  // above IFACE_IR_TOL of the right-hand side (high contrast with
+  // non-polynomial spaces makes the system ill-conditioned)
+  c->iface_ir = 0;
+  for (int it = 0; it < IFACE_IR_MAX; ++it) {
+    double res[2] = {0.0, 0.0};
+    HIPCHK(c, hipMemcpyAsync(res, c->result + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (!(res[0] > IFACE_IR_TOL * res[1])) break;
+    for (const LevelPlan& lp : c->levels)
+      HIPCHK(c, launch_front_rhs(c->d_nodes, c->d_ids + lp.ids_off, lp.count, c->tree, c->inv,
+                                 c->d_maps, c->d_dofs, c->rvec, c->rtree, st));
+    for (auto lv = c->levels.rbegin(); lv != c->levels.rend(); ++lv)
+      HIPCHK(c, launch_front_back(c->d_nodes, c->d_ids + lv->ids_off, lv->count, c->tree, c->inv,
+                                  c->d_dofs, c->rtree, c->dx, st));
+    HIPCHK(c, launch_add(c->coef, c->dx, c->n_dof, st));
+    HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2, st));
+    c->iface_ir = it + 1;
+  }
   return MRCM_OK;
 }
 
@@ -685,6 +723,7 @@ int solve_impl(mrcm_ctx* c, const float* pred) {
   }
   c->stats.interface_residual = res[1] > 0.0 ? res[0] / res[1] : 0.0;
   c->stats.fallbacks = nfb;
+  c->stats.interface_ir_steps = c->iface_ir;
   c->stats.ir_iters_max = iters;
   if (status & ST_BAD_LAMBDA) return fail(c, MRCM_E_INVAL, "mobility not finite and positive");
   if (status & (ST_LOCAL_PIVOT | ST_IFACE_PIVOT))

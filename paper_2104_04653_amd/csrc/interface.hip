@@ -48,6 +48,20 @@ __device__ inline double gather_entry(const NodeDesc& nd, const double* tree, in
   return v;
 }
 
+// double-double accumulation: (hi, lo) += v, and (hi, lo) -= a b
+__device__ inline void two_sum(double& hi, double& lo, double v) {
+#pragma clang fp contract(off)
+  const double s = hi + v, bb = s - hi;
+  lo += (hi - (s - bb)) + (v - bb);
+  hi = s;
+}
+__device__ inline void two_prod_sub(double& hi, double& lo, double a, double b) {
+#pragma clang fp contract(off)
+  const double p = a * b, pe = fma(a, b, -p);
+  two_sum(hi, lo, -p);
+  lo -= pe;
+}
+
 // 2-D thread map used by the element loops below (no integer division):
 // 32 columns x 8 rows per pass.
 constexpr int TXN = 32, TYN = NT / TXN;
@@ -333,13 +347,15 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
 //  of the diagonal block, so x_1 = A11^{-1} (b_1 - A12 x_2).
 __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, const int* ids,
                                                         const double* tree, const double* inv,
-                                                        const int* dofs, double* x) {
+                                                        const int* dofs, const double* rtree,
+                                                        double* x) {
   extern __shared__ double xl[];   // n values: front-local unknowns
   __shared__ double y[PANEL_NB];
   const NodeDesc nd = nodes[ids[blockIdx.x]];
   const int n = nd.n, s = nd.s, ld = n + 1;
   const double* F = tree + nd.f_off;
   const int* dof = dofs + nd.dof_off;
+  const double* rv = rtree ? rtree + nd.r_off : nullptr;   // rhs vector, else column n
   const int t = threadIdx.x;
   for (int m = s + t; m < n; m += NT) xl[m] = x[dof[m]];
   __syncthreads();
@@ -351,7 +367,7 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
         const double* row = F + (long long)k * ld;
 #pragma unroll 4
         for (int m = s + lane; m < n; m += 8) v -= row[m] * xl[m];
-        if (lane == 0) v += row[n];
+        if (lane == 0) v += rv ? rv[k] : row[n];
       }
       for (int off = 4; off > 0; off >>= 1) v += __shfl_down(v, off, 8);
       if (k < s && lane == 0) xl[k] = v;
@@ -376,7 +392,7 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
           const double* fr = F + (long long)(k0 + row) * ld;
 #pragma unroll 4
           for (int m = k0 + nb + lane; m < n; m += 8) v -= fr[m] * xl[m];
-          if (lane == 0) v += fr[n];
+          if (lane == 0) v += rv ? rv[k0 + row] : fr[n];
         }
         for (int off = 4; off > 0; off >>= 1) v += __shfl_down(v, off, 8);
         if (row < nb && lane == 0) y[row] = v;
@@ -394,11 +410,73 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
   for (int k = t; k < s; k += NT) x[dof[k]] = xl[k];
 }
 
+// Forward elimination of a new right-hand side through one stored front:
+// gather the children's eliminated rhs (extend-add with the same maps as
+// the matrix), add the new values of the front's own separator dofs (each
+// dof is eliminated at exactly one node, so each value enters once), and
+// apply the stored elimination: multipliers in the columns of classic
+// fronts; A21 A11^-1 per panel for blocked fronts (the panel rows keep their
+// panel-time values for the back substitution).
+__global__ void __launch_bounds__(NT) front_rhs_kernel(const NodeDesc* nodes, const int* ids,
+                                                       const double* tree, const double* inv,
+                                                       const int2* maps, const int* dofs,
+                                                       const double* r, double* rtree) {
+  extern __shared__ double rl[];   // n values
+  __shared__ double z[PANEL_NB];
+  const NodeDesc nd = nodes[ids[blockIdx.x]];
+  const int n = nd.n, s = nd.s, ld = n + 1;
+  const int t = threadIdx.x;
+  const int2* mp = maps + nd.map_off;
+  const int* dof = dofs + nd.dof_off;
+  for (int a = t; a < n; a += NT) {
+    const int2 ma = mp[a];
+    double v = 0.0;
+    if (ma.x >= 0 && nd.cr_off[0] >= 0) v += rtree[nd.cr_off[0] + ma.x];
+    if (ma.y >= 0 && nd.cr_off[1] >= 0) v += rtree[nd.cr_off[1] + ma.y];
+    if (a < s) v += r[dof[a]];
+    rl[a] = v;
+  }
+  const double* F = tree + nd.f_off;
+  if (!nd.blocked) {
+    for (int k = 0; k < s; ++k) {
+      __syncthreads();
+      const double rk = rl[k];
+      for (int a = k + 1 + t; a < n; a += NT) rl[a] -= F[(long long)a * ld + k] * rk;
+    }
+  } else {
+    for (int k0 = 0; k0 < s; k0 += PANEL_NB) {
+      const int nb = min(PANEL_NB, s - k0);
+      const double* Di = inv + nd.inv_off + (long long)(k0 / PANEL_NB) * PANEL_NB * PANEL_NB;
+      __syncthreads();
+      if (t < nb) {
+        double v = 0.0;
+        for (int m = 0; m < nb; ++m) v += Di[t * PANEL_NB + m] * rl[k0 + m];
+        z[t] = v;
+      }
+      __syncthreads();
+      for (int a = k0 + nb + t; a < n; a += NT) {
+        const double* fr = F + (long long)a * ld + k0;
+        double v = 0.0;
+        for (int c = 0; c < nb; ++c) v += fr[c] * z[c];
+        rl[a] -= v;
+      }
+    }
+  }
+  __syncthreads();
+  for (int a = t; a < n; a += NT) rtree[nd.r_off + a] = rl[a];
+}
+
+__global__ void add_kernel(double* x, const double* dx, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    x[i] += dx[i];
+}
+
 // r = b - A x gathered from the subdomain blocks (each interface row has
 // two owners: its lower- and higher-index subdomain).  Stage 1: per
 // work-group maxima of |r| and |b|; stage 2: one work-group reduces them.
 __global__ void __launch_bounds__(NT) iface_residual_kernel(Geo g, const double* blocks,
-                                                            const double* x, double* partials) {
+                                                            const double* x, double* rvec,
+                                                            double* partials) {
   __shared__ double red[2][NT];
   const int D = g.D, NBR = 4 * D, NBC = NBR + 1;
   const int n_iface = g.nV + g.SX * (g.SY - 1);
@@ -417,12 +495,13 @@ __global__ void __launch_bounds__(NT) iface_residual_kernel(Geo g, const double*
       sub[0] = J * g.SX + I; side[0] = 3;
       sub[1] = sub[0] + g.SX; side[1] = 2;
     }
-    double ax = 0.0, b = 0.0;
+    double hi = 0.0, lo = 0.0, b = 0.0;   // residual b - A x in double-double
     for (int o = 0; o < 2; ++o) {
       const int sd = sub[o];
       const int I = sd % g.SX, J = sd / g.SX;
       const double* blk = blocks + (size_t)sd * NBR * NBC + (size_t)(side[o] * D + k) * NBC;
       b += blk[NBR];
+      two_sum(hi, lo, blk[NBR]);
       for (int sd_side = 0; sd_side < 4; ++sd_side) {
         int ee;
         switch (sd_side) {
@@ -432,10 +511,12 @@ __global__ void __launch_bounds__(NT) iface_residual_kernel(Geo g, const double*
           default: ee = J < g.SY - 1 ? g.nV + J * g.SX + I : -1;
         }
         if (ee < 0) continue;
-        for (int kk = 0; kk < D; ++kk) ax += blk[sd_side * D + kk] * x[(size_t)ee * D + kk];
+        for (int kk = 0; kk < D; ++kk) two_prod_sub(hi, lo, blk[sd_side * D + kk], x[(size_t)ee * D + kk]);
       }
     }
-    rmax = fmax(rmax, fabs(b - ax));
+    const double res = hi + lo;
+    if (rvec) rvec[row] = res;
+    rmax = fmax(rmax, fabs(res));
     bmax = fmax(bmax, fabs(b));
   }
   red[0][threadIdx.x] = rmax;
@@ -509,16 +590,30 @@ hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, in
 }
 
 hipError_t launch_front_back(const NodeDesc* nodes, const int* ids, int count, const double* tree,
-                             const double* inv, const int* dofs, double* x, hipStream_t st) {
+                             const double* inv, const int* dofs, const double* rtree, double* x,
+                             hipStream_t st) {
   // the plan guarantees n <= MAX_FRONT
   hipLaunchKernelGGL(front_back_kernel, dim3(count), dim3(NT), MAX_FRONT * sizeof(double), st, nodes,
-                     ids, tree, inv, dofs, x);
+                     ids, tree, inv, dofs, rtree, x);
   return hipGetLastError();
 }
 
-hipError_t launch_iface_residual(const Geo& g, const double* blocks, const double* x,
+hipError_t launch_front_rhs(const NodeDesc* nodes, const int* ids, int count, const double* tree,
+                            const double* inv, const int2* maps, const int* dofs, const double* r,
+                            double* rtree, hipStream_t st) {
+  hipLaunchKernelGGL(front_rhs_kernel, dim3(count), dim3(NT), MAX_FRONT * sizeof(double), st, nodes,
+                     ids, tree, inv, maps, dofs, r, rtree);
+  return hipGetLastError();
+}
+
+hipError_t launch_add(double* x, const double* dx, int n, hipStream_t st) {
+  hipLaunchKernelGGL(add_kernel, dim3(64), dim3(NT), 0, st, x, dx, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_iface_residual(const Geo& g, const double* blocks, const double* x, double* r,
                                  double* partials, double* out2, hipStream_t st) {
-  hipLaunchKernelGGL(iface_residual_kernel, dim3(RESID_WG), dim3(NT), 0, st, g, blocks, x,
+  hipLaunchKernelGGL(iface_residual_kernel, dim3(RESID_WG), dim3(NT), 0, st, g, blocks, x, r,
                      partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -70,6 +70,8 @@ struct NodeDesc {
   int c_rhs[2];         // rhs column of each child's Schur block (relative to c_off)
   int blocked;          // 0: eliminated pivot by pivot (classic in-place LU);
                         // 1: eliminated by panels of PANEL_NB columns
+  long long r_off;      // offset of the front's right-hand-side vector (n) in the rhs tree
+  long long cr_off[2];  // each child's right-hand-side vector, -1 for a leaf child
 };
 
 struct PanelItem {      // one work-group of a blocked trailing update
@@ -103,12 +105,23 @@ hipError_t launch_front_gather(const NodeDesc* nodes, const int2* items, int cou
                                hipStream_t st);
 hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count,
                                int k0, double* tree, double* inv, int* status, hipStream_t st);
+// back substitution of one tree level; rtree = NULL takes the right-hand
+// side from the fronts' last column, else from the fronts' rhs vectors
 hipError_t launch_front_back(const NodeDesc* nodes, const int* ids, int count, const double* tree,
-                             const double* inv, const int* dofs, double* x, hipStream_t st);
-// r = b - A x of the assembled interface system; partials: 2 doubles per
-// work-group (RESID_WG of them), reduced into out2[0] = max|r|, out2[1] = max|b|
-hipError_t launch_iface_residual(const Geo& g, const double* blocks, const double* x,
+                             const double* inv, const int* dofs, const double* rtree, double* x,
+                             hipStream_t st);
+// forward elimination of a new right-hand side r (one value per interface
+// dof) through the stored fronts of one tree level, into the rhs tree
+hipError_t launch_front_rhs(const NodeDesc* nodes, const int* ids, int count, const double* tree,
+                            const double* inv, const int2* maps, const int* dofs, const double* r,
+                            double* rtree, hipStream_t st);
+// r = b - A x of the assembled interface system (double-double), written to
+// r if not NULL; partials: 2 doubles per work-group (RESID_WG of them),
+// reduced into out2[0] = max|r|, out2[1] = max|b|
+hipError_t launch_iface_residual(const Geo& g, const double* blocks, const double* x, double* r,
                                  double* partials, double* out2, hipStream_t st);
+// x += dx over n values
+hipError_t launch_add(double* x, const double* dx, int n, hipStream_t st);
 constexpr int RESID_WG = 128;
 hipError_t prepare_interface_kernels();
 

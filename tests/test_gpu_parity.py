@@ -36,8 +36,9 @@ def check_end_to_end(prob, s=None, lam=None, local=True, tol=TOL, label="", coef
     ef = rel(np.r_[g["ux"], g["uy"]], np.r_[ref.ux, ref.uy])
     ec = rel(g["coef"], ref.coeffs) if ref.coeffs.size else 0.0
     say("  rel L2: p %.2e  flux %.2e  interface coeffs %.2e  imbalance gpu %.2e oracle %.2e"
-        "  iface res %.2e" % (ep, ef, ec, g["imbalance"], ref.imbalance,
-                              g["stats"]["interface_residual"]))
+        "  iface res %.2e (%d refinement steps)" % (ep, ef, ec, g["imbalance"], ref.imbalance,
+                                                   g["stats"]["interface_residual"],
+                                                   g["stats"]["interface_ir_steps"]))
     if local:
         B = oracle_basis_padded(prob, ref)
         X = g["basis"]
@@ -51,8 +52,11 @@ def check_end_to_end(prob, s=None, lam=None, local=True, tol=TOL, label="", coef
         say("  basis max col rel %.2e  blocks %.2e" % (eb, ebl))
         assert eb < tol and ebl < tol
     assert ep < tol and ef < tol and ec < coef_tol
+    # cell balance: 1e-12, or the FP64 floor of fluxes formed from pressures,
+    # or what the oracle itself reaches on the same case (channelized 1e6
+    # contrast with 32 x 32 subdomains), whichever is largest
     floor = flux_floor(prob, lam, ref.p) / np.abs(np.r_[ref.Fx, ref.Fy]).max()
-    assert g["imbalance"] < max(1e-12, 64 * floor)
+    assert g["imbalance"] < max(1e-12, 64 * floor, 4 * ref.imbalance)
     return g, ref
 
 
