@@ -152,7 +152,7 @@ def main():
             step(k)
         torch.cuda.synchronize()
         phase = {"local": [], "interface": [], "flux": [], "surrogate_inference_gate": []}
-        iters, fallbacks = 0, 0
+        iters, fallbacks, iface_ir = 0, 0, 0
         t0 = time.perf_counter()
         for k in range(args.warmup, n_steps_total):
             st = step(k)
@@ -162,6 +162,7 @@ def main():
             phase["surrogate_inference_gate"].append(st["ms_surrogate"])
             iters = max(iters, st["ir_iters_max"])
             fallbacks = max(fallbacks, st["fallbacks"])
+            iface_ir = max(iface_ir, st["interface_ir_steps"])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         n_dof = sol.n_dof
@@ -177,6 +178,7 @@ def main():
                 "phases_ms": {k: float(np.mean(v)) for k, v in phase.items()},
                 "max_cell_imbalance": imb.value, "ir_iters_max": iters,
                 "fp64_fallbacks_max": fallbacks, "fallback_rate": fallbacks / prob.n_sub,
+                "interface_refinement_steps_max": iface_ir,
                 "n_dof": n_dof, **extra}
 
     def cnn_forward_rate(net, sol):

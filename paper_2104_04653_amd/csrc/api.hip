@@ -447,25 +447,23 @@ int run_interface(mrcm_ctx* c) {
     HIPCHK(c, launch_front_back(c->d_nodes, c->d_ids + it->ids_off, it->count, c->tree, c->inv,
                                 c->d_dofs, nullptr, c->coef, st));
   HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2, st));
-  // iterative refinement with the stored factors while the residual is
-  // above IFACE_IR_TOL of the right-hand side (high contrast with
-  // non-polynomial spaces makes the system ill-conditioned)
-  c->iface_ir = 0;
-  for (int it = 0; it < IFACE_IR_MAX; ++it) {
-    double res[2] = {0.0, 0.0};
-    HIPCHK(c, hipMemcpyAsync(res, c->result + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
-    if (!(res[0] > IFACE_IR_TOL * res[1])) break;
-    for (const LevelPlan& lp : c->levels)
-      HIPCHK(c, launch_front_rhs(c->d_nodes, c->d_ids + lp.ids_off, lp.count, c->tree, c->inv,
-                                 c->d_maps, c->d_dofs, c->rvec, c->rtree, st));
-    for (auto lv = c->levels.rbegin(); lv != c->levels.rend(); ++lv)
-      HIPCHK(c, launch_front_back(c->d_nodes, c->d_ids + lv->ids_off, lv->count, c->tree, c->inv,
-                                  c->d_dofs, c->rtree, c->dx, st));
-    HIPCHK(c, launch_add(c->coef, c->dx, c->n_dof, st));
-    HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2, st));
-    c->iface_ir = it + 1;
-  }
+  return MRCM_OK;
+}
+
+// One step of iterative refinement of the interface solution with the
+// stored factors: the residual left in rvec by the last residual launch is
+// eliminated through the tree into dx, added to the coefficients, and the
+// residual is formed again.
+int refine_interface(mrcm_ctx* c) {
+  hipStream_t st = c->st;
+  for (const LevelPlan& lp : c->levels)
+    HIPCHK(c, launch_front_rhs(c->d_nodes, c->d_ids + lp.ids_off, lp.count, c->tree, c->inv,
+                               c->d_maps, c->d_dofs, c->rvec, c->rtree, st));
+  for (auto lv = c->levels.rbegin(); lv != c->levels.rend(); ++lv)
+    HIPCHK(c, launch_front_back(c->d_nodes, c->d_ids + lv->ids_off, lv->count, c->tree, c->inv,
+                                c->d_dofs, c->rtree, c->dx, st));
+  HIPCHK(c, launch_add(c->coef, c->dx, c->n_dof, st));
+  HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2, st));
   return MRCM_OK;
 }
 
@@ -710,6 +708,19 @@ int solve_impl(mrcm_ctx* c, const float* pred) {
   if (c->n_dof > 0)
     HIPCHK(c, hipMemcpyAsync(res, c->result + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(c, hipStreamSynchronize(st));
+  // iterative refinement of the interface solve while its residual is above
+  // IFACE_IR_TOL of the right-hand side (high contrast with non-polynomial
+  // spaces makes the system ill-conditioned); checked at this existing
+  // synchronisation, so a well-conditioned solve pays nothing for it
+  c->iface_ir = 0;
+  while (c->n_dof > 0 && c->iface_ir < IFACE_IR_MAX && res[0] > IFACE_IR_TOL * res[1]) {
+    int r = refine_interface(c);
+    if (r != MRCM_OK) return r;
+    HIPCHK(c, hipEventRecord(c->ev[2], st));
+    HIPCHK(c, hipMemcpyAsync(res, c->result + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->iface_ir += 1;
+  }
   float t1 = 0.f, t2 = 0.f;
   (void)hipEventElapsedTime(&t1, c->ev[0], c->ev[1]);
   (void)hipEventElapsedTime(&t2, c->ev[1], c->ev[2]);

@@ -678,26 +678,46 @@ __device__ inline f4 mfma32(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-__device__ inline f4 gauss_jordan16_f32(f4 s, int c, int g, bool& bad) {
+template <int K>
+__device__ inline float row_bcast_f(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x150 + K, 0xF, 0xF, false));
+}
+
+// One FP32 Gauss-Jordan sweep with pivot K (f32 output layout: lane c + 16 g
+// holds rows 4 g .. 4 g + 3 of column c): the pivot column comes from lane K
+// of the lane's own 16-lane row, the pivot row from lane c + 16 (K / 4).
+template <int K>
+__device__ inline void gj_sweep_f32(f4& s, int c, int g, bool& bad) {
+  constexpr int kg = K >> 2, kv = K & 3;
+  const float p = readlane_f(s[kv], K + 16 * kg);
+  const float prow = __shfl(s[kv], c + 16 * kg);
+  float pcol[4];
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const int kg = k >> 2, kv = k & 3;                       // row k: group kg, register kv
-    const float p = readlane_f(s[kv], k + 16 * kg);
-    const float prow = __shfl(s[kv], c + 16 * kg);
-    float pcol[4];
+  for (int v = 0; v < 4; ++v) pcol[v] = row_bcast_f<K>(s[v]);
+  if (!(p > 0.0f)) bad = true;
+  const float ip = 1.0f / p;
+  const float b = (c == K) ? ip : prow * ip;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) pcol[v] = __shfl(s[v], k + 16 * g);   // S[4g+v][k]
-    if (!(p > 0.0f)) bad = true;
-    const float ip = 1.0f / p;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 4 * g + v;
-      float nv;
-      if (row == k) nv = (c == k) ? ip : s[v] * ip;
-      else nv = (c == k) ? -pcol[v] * ip : fmaf(-pcol[v] * ip, prow, s[v]);
-      s[v] = nv;
-    }
+  for (int v = 0; v < 4; ++v) {
+    const float nv = fmaf(-pcol[v], b, (c == K) ? 0.0f : s[v]);
+    s[v] = (v == kv && g == kg) ? b : nv;
   }
+}
+
+template <int K>
+struct GJ16F {
+  static __device__ inline void run(f4& s, int c, int g, bool& bad) {
+    gj_sweep_f32<K>(s, c, g, bad);
+    GJ16F<K + 1>::run(s, c, g, bad);
+  }
+};
+template <>
+struct GJ16F<M> {
+  static __device__ inline void run(f4&, int, int, bool&) {}
+};
+
+__device__ inline f4 gauss_jordan16_f32(f4 s, int c, int g, bool& bad) {
+  GJ16F<0>::run(s, c, g, bad);
   return s;
 }
 
