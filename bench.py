@@ -58,6 +58,33 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_basis_m16d4_gauss1024.md")
+KERNEL_SOURCES = ("local_mfma.hip", "local_common.h", "mrcm_internal.h")
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the roofline kernel from the committed counter
+    summary, or None when it is missing, for another workload, or was taken
+    on kernel sources other than the current ones."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith(("#", "|", "`")):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    csrc = os.path.join(ROOT, "paper_2104_04653_amd", "csrc")
+    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                  for f in KERNEL_SOURCES)).hexdigest()
+    if vals.get("source_sha256") != sha or vals.get("workload") != workload:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(prob, sat):
     """Time the CPU oracle (as it stands) on one full step, one thread."""
     from threadpoolctl import threadpool_limits
@@ -217,6 +244,7 @@ def main():
     # library's HIP events on its stream
     alg_flop = prob.n_sub * (FLOP_FACTOR_SD + FLOP_SOLVE17_SD)
     achieved = alg_flop / (avg["local"] * 1e-3) / 1e12
+    traffic = measured_traffic(args.workload)
     out = {
         "metric": METRIC,
         "value": value,
@@ -248,7 +276,8 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_gbs": None if traffic is None else traffic / (avg["local"] * 1e-3) / 1e9,
         },
         "forms": {"fp64": results.get("fp64"), "fp32_ir": results.get("fp32_ir"),
                   "surrogate": results.get("surrogate")},
