@@ -141,49 +141,135 @@ __device__ inline double side_rhs(const double (*bside)[M][D], int lj, int li, i
   return on ? v : 0.0;
 }
 
-// One column solve with the stored inverse blocks Sv (rhs and result in
-// LDS, cell-major).  Forward Z_j = S_j^{-1}(B_j - C_{j-1} Z_{j-1}), backward
-// X_j = Z_j - S_j^{-1} C_j X_{j+1}; the column is replicated over the 16
-// MFMA columns.
-__device__ inline void solve_column(const d4* Sv, const double* rhs, double* out, int c, int g,
-                                    const double* cy) {
-  d4 z;
+// Two-sided elimination of the 16 Schur blocks (upper chain rows 0..MID-1
+// downwards, lower chain rows M-1..MID+1 upwards, joined at row MID):
+// Sv[j] receives the inverse of row j's Schur-complemented block in its chain.
+__device__ inline void factor_two_sided(d4* Sv, int c, int g, const double* dg, const double* ex,
+                                        const double* cy, bool& bad) {
+  const d4 zero = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
+  for (int t = 0; t < MID; ++t) {
+    {
+      const int j = t;
+      d4 s = coupled_block(j, j - 1, j > 0 ? Sv[j > 0 ? j - 1 : 0] : zero, c, g, dg, ex, cy);
+      Sv[j] = gauss_jordan16(s, c, g, bad);
+    }
+    if (t < M - 1 - MID) {
+      const int j = M - 1 - t;
+      d4 s = coupled_block(j, j < M - 1 ? j : -1, j < M - 1 ? Sv[j < M - 1 ? j + 1 : j] : zero, c, g,
+                           dg, ex, cy);
+      Sv[j] = gauss_jordan16(s, c, g, bad);
+    }
+  }
+  constexpr int j = MID;
+  d4 s = coupled_block(j, j - 1, Sv[j - 1], c, g, dg, ex, cy);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) s[v] -= cy[j * M + 4 * v + g] * Sv[j + 1][v] * cy[j * M + c];
+  Sv[j] = gauss_jordan16(s, c, g, bad);
+}
+
+// One column solve with the two-sided inverse blocks of factor_two_sided
+// (rhs and result in LDS, cell-major; the column is replicated over the 16
+// MFMA columns and lanes with c == 0 write the result).
+__device__ inline void solve_column_two_sided(const d4* Sv, const double* rhs, double* out, int c,
+                                              int g, const double* cy) {
+  const d4 zero = {0.0, 0.0, 0.0, 0.0};
+  d4 zu = zero, zl = zero;
+#pragma unroll
+  for (int t = 0; t < MID; ++t) {
+    {
+      const int j = t;
+      d4 r;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * v + g;
+        double b = rhs[j * M + row];
+        if (j > 0) b -= cy[(j - 1) * M + row] * zu[v];
+        r[v] = b;
+      }
+      d4 acc = zero;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = mfma(Sv[j][kk], r[kk], acc);
+      zu = acc;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = acc[v];
+      }
+    }
+    if (t < M - 1 - MID) {
+      const int j = M - 1 - t;
+      d4 r;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * v + g;
+        double b = rhs[j * M + row];
+        if (j < M - 1) b -= cy[j * M + row] * zl[v];
+        r[v] = b;
+      }
+      d4 acc = zero;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = mfma(Sv[j][kk], r[kk], acc);
+      zl = acc;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = acc[v];
+      }
+    }
+  }
+  {
+    constexpr int j = MID;
     d4 r;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = 4 * v + g;
-      double b = rhs[j * M + row];
-      if (j > 0) b -= cy[(j - 1) * M + row] * z[v];
-      r[v] = b;
+      r[v] = rhs[j * M + row] - cy[(j - 1) * M + row] * zu[v] - cy[j * M + row] * zl[v];
     }
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    d4 acc = zero;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) acc = mfma(Sv[j][kk], r[kk], acc);
-    z = acc;
+    zu = acc;
+    zl = acc;
     if (c == 0) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = z[v];
+      for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = acc[v];
     }
   }
   __syncthreads();
-  d4 xn = z;
 #pragma unroll
-  for (int j = M - 2; j >= 0; --j) {
-    d4 t, x;
+  for (int t = 0; t < MID; ++t) {
+    {
+      const int j = MID - 1 - t;
+      d4 tt, x;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 4 * v + g;
-      t[v] = -cy[j * M + row] * xn[v];
-      x[v] = out[j * M + row];
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * v + g;
+        tt[v] = -cy[j * M + row] * zu[v];
+        x[v] = out[j * M + row];
+      }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) x = mfma(Sv[j][kk], tt[kk], x);
+      zu = x;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = x[v];
+      }
     }
+    if (t < M - 1 - MID) {
+      const int j = MID + 1 + t;
+      d4 tt, x;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) x = mfma(Sv[j][kk], t[kk], x);
-    xn = x;
-    if (c == 0) {
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * v + g;
+        tt[v] = -cy[(j - 1) * M + row] * zl[v];
+        x[v] = out[j * M + row];
+      }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = x[v];
+      for (int kk = 0; kk < 4; ++kk) x = mfma(Sv[j][kk], tt[kk], x);
+      zl = x;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = x[v];
+      }
     }
   }
   __syncthreads();
@@ -1065,16 +1151,9 @@ __global__ void __launch_bounds__(WAVE) stitch_m16d4_kernel(SubArgs a) {
 
   d4 Sv[M];
   bool bad = false;
-  d4 prev = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    d4 s = coupled_block(j, j - 1, prev, c, gq, dg, ex, cy);
-    s = gauss_jordan16(s, c, gq, bad);
-    Sv[j] = s;
-    prev = s;
-  }
+  factor_two_sided(Sv, c, gq, dg, ex, cy, bad);
   if (bad) atomicOr(a.status, ST_STITCH_PIVOT);
-  solve_column(Sv, bs_, ps, c, gq, cy);
+  solve_column_two_sided(Sv, bs_, ps, c, gq, cy);
   // iterative refinement with the stored inverse blocks, residual in
   // double-double
   for (int it = 0; it < 3; ++it) {
@@ -1089,7 +1168,7 @@ __global__ void __launch_bounds__(WAVE) stitch_m16d4_kernel(SubArgs a) {
       rs[l] = hi + lo;
     }
     __syncthreads();
-    solve_column(Sv, rs, dx, c, gq, cy);
+    solve_column_two_sided(Sv, rs, dx, c, gq, cy);
     for (int l = lane; l < MM; l += WAVE) ps[l] += dx[l];
     __syncthreads();
   }
