@@ -284,6 +284,28 @@ __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const
   const Geo& g = a.g;
   const int lane = threadIdx.x;
   constexpr int NBR = 4 * D, NBC = 4 * D + 1;
+  // per skeleton face (one lane each): Robin transmissibility T_R, beta and
+  // beta / |f|, and the interface functions of its side
+  __shared__ double trf[4][M], btf[4][M], bfl[4][M], phi[4][D][M];
+  {
+    const int side = lane >> 4, t = lane & 15;
+    const int e = side_iface(g, I, J, side);
+    double tr = 0.0, bt = 0.0, bl = 0.0;
+    if (e >= 0) {
+      const SideGeo sg = side_geo(g, side);
+      const double al = a.alpha[e];
+      const double kk = kap[side_cell<M>(side, t)];
+      tr = sg.flen * kk / (sg.dist + al * sg.H);
+      bt = al * sg.H / kk;
+      bl = bt / sg.flen;
+    }
+    trf[side][t] = tr;
+    btf[side][t] = bt;
+    bfl[side][t] = bl;
+#pragma unroll
+    for (int k = 0; k < D; ++k) phi[side][k][t] = e >= 0 ? a.basis[((size_t)e * D + k) * M + t] : 0.0;
+  }
+  __syncthreads();
   double* blk = a.blocks + (size_t)sd * NBR * NBC;
   const int nP = g.nP;
   int e0side = -1;
@@ -299,23 +321,21 @@ __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const
     double val = 0.0;
     if (e >= 0) {
       const int col = (qc < NBR) ? 1 + qc : 0;
-      const SideGeo sg = side_geo(g, side);
-      const double al = a.alpha[e];
       const double sig = side_sigma(side);
-      const double* bs = a.basis + (size_t)e * D * M;
       const bool colside = col >= 1 + side * D && col < 1 + side * D + D;
-      const int kc = col - 1 - side * D;
+      const int kc = colside ? col - 1 - side * D : 0;
+      const bool flux_col = colside && kc >= nP;
+      const double gscale = colside ? 1.0 : 0.0;
       double sum = 0.0;
+#pragma unroll 4
       for (int t = 0; t < M; ++t) {
-        const double kk = kap[side_cell<M>(side, t)];
-        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
-        const double beta = al * sg.H / kk;
-        double gv = 0.0;
-        if (colside) gv = (kc < nP) ? bs[kc * M + t] : -beta * sig * bs[kc * M + t];
-        const double F = TR * (xb[side][t][col] - gv);
-        if (k < nP) sum += bs[k * M + t] * F;
-        else sum += bs[k * M + t] * (gv + beta * F / sg.flen);
+        const double ph = phi[side][kc][t];
+        const double gv = gscale * (flux_col ? -btf[side][t] * sig * ph : ph);
+        const double F = trf[side][t] * (xb[side][t][col] - gv);
+        const double w = (k < nP) ? F : fma(bfl[side][t], F, gv);
+        sum = fma(phi[side][k][t], w, sum);
       }
+      const SideGeo sg = side_geo(g, side);
       const double natural = (k < nP) ? sum : sig * sg.flen * sum;
       const double sgn = (k < nP) ? 1.0 : -1.0;
       val = (qc < NBR) ? sgn * natural : -sgn * natural;
