@@ -114,30 +114,54 @@ __device__ inline double readlane_d(double x, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// In-place inverse of a 16 x 16 tile held by one wavefront in the MFMA
-// output layout (lane c + 16 g holds rows 4 v + g of column c in s[v]) by
-// Gauss-Jordan sweeps without pivoting; the pivot row and column are
-// broadcast with lane shuffles.
-__device__ inline d4 gj16(d4 s, int c, int g, bool& bad) {
+// value of lane K of each 16-lane row (DPP row_newbcast, two 32-bit moves)
+template <int K>
+__device__ inline double row_bcast(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(u & 0xffffffffu), 0x150 + K, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x150 + K, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// One Gauss-Jordan sweep with pivot K on a 16 x 16 tile held by one
+// wavefront in the MFMA output layout (lane c + 16 g holds rows 4 v + g of
+// column c in s[v]), no pivoting: the pivot column comes from lane K of the
+// lane's own 16-lane row, the pivot row from lane c + 16 (K % 4).
+template <int K>
+__device__ inline void gj16_sweep(d4& s, int c, int g, bool& bad) {
+  constexpr int kv = K >> 2, kg = K & 3;
+  const double p = readlane_d(s[kv], K + 16 * kg);
+  const double prow = __shfl(s[kv], c + 16 * kg);
+  double pcol[4];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int kv = k >> 2, kg = k & 3;
-    const double p = readlane_d(s[kv], k + 16 * kg);
-    const double prow = __shfl(s[kv], c + 16 * kg);
-    double pcol[4];
+  for (int v = 0; v < 4; ++v) pcol[v] = row_bcast<K>(s[v]);
+  if (p == 0.0 || !isfinite(p)) bad = true;
+  double ip = __builtin_amdgcn_rcp(p);              // reciprocal estimate, two Newton steps
+  ip = fma(ip, fma(-p, ip, 1.0), ip);
+  ip = fma(ip, fma(-p, ip, 1.0), ip);
+  const double b = (c == K) ? ip : prow * ip;      // new row K
 #pragma unroll
-    for (int v = 0; v < 4; ++v) pcol[v] = __shfl(s[v], k + 16 * g);
-    if (p == 0.0 || !isfinite(p)) bad = true;
-    const double ip = 1.0 / p;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 4 * v + g;
-      double nv;
-      if (row == k) nv = (c == k) ? ip : s[v] * ip;
-      else nv = (c == k) ? -pcol[v] * ip : fma(-pcol[v] * ip, prow, s[v]);
-      s[v] = nv;
-    }
+  for (int v = 0; v < 4; ++v) {
+    const double nv = fma(-pcol[v], b, (c == K) ? 0.0 : s[v]);
+    s[v] = (v == kv && g == kg) ? b : nv;
   }
+}
+
+template <int K>
+struct GJ16 {
+  static __device__ inline void run(d4& s, int c, int g, bool& bad) {
+    gj16_sweep<K>(s, c, g, bad);
+    GJ16<K + 1>::run(s, c, g, bad);
+  }
+};
+template <>
+struct GJ16<16> {
+  static __device__ inline void run(d4&, int, int, bool&) {}
+};
+
+// In-place inverse of a 16 x 16 tile (output layout) by Gauss-Jordan sweeps.
+__device__ inline d4 gj16(d4 s, int c, int g, bool& bad) {
+  GJ16<0>::run(s, c, g, bad);
   return s;
 }
 
