@@ -284,10 +284,11 @@ __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const
   const Geo& g = a.g;
   const int lane = threadIdx.x;
   constexpr int NBR = 4 * D, NBC = 4 * D + 1;
-  // per skeleton face (one lane each): Robin transmissibility T_R, beta and
-  // beta / |f|, and the interface functions of its side
+  // per skeleton face (one of the first 64 threads each): Robin
+  // transmissibility T_R, beta and beta / |f|, and the interface functions
+  // of its side
   __shared__ double trf[4][M], btf[4][M], bfl[4][M], phi[4][D][M];
-  {
+  if (lane < 4 * M) {
     const int side = lane >> 4, t = lane & 15;
     const int e = side_iface(g, I, J, side);
     double tr = 0.0, bt = 0.0, bl = 0.0;
@@ -314,7 +315,7 @@ __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const
     for (int side = 0; side < 4; ++side)
       if (side_iface(g, I, J, side) == 0) { e0side = side; e0lo = side_sigma(side) > 0; }
   }
-  for (int o = lane; o < NBR * NBC; o += WAVE) {
+  for (int o = lane; o < NBR * NBC; o += blockDim.x) {
     const int r = o / NBC, qc = o % NBC;
     const int side = r / D, k = r % D;
     const int e = side_iface(g, I, J, side);
@@ -754,6 +755,385 @@ __global__ void __launch_bounds__(WAVE) basis_m16d4_kernel(SubArgs a) {
   }
   __syncthreads();
 
+  write_block(a, sd, I, J, kap, xb);
+}
+
+// ---------------------------------------------------------------------------
+// The same solve by two wavefronts per subdomain: wave 0 eliminates block
+// rows 0..MID-1 downwards and solves the joining row MID, wave 1 eliminates
+// rows M-1..MID+1 upwards.  Each wavefront keeps only its own rows' inverse
+// blocks and solution tiles in registers, so two wavefronts fit on a SIMD,
+// and the two chains run on different SIMDs.  The waves exchange the tiles
+// next to the joining row through LDS; everything else of a row is local to
+// the wave that owns it (LDS written and read by the same wavefront needs no
+// barrier: its LDS accesses complete in program order).
+// ---------------------------------------------------------------------------
+constexpr int PAIR = 2 * WAVE;
+constexpr int NU = MID + 1;       // rows of wave 0: 0 .. MID
+constexpr int NL = M - 1 - MID;   // rows of wave 1: M-1 .. MID+1 (index t is row M-1-t)
+
+template <bool LIST>
+__global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
+  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM], pz[MM];
+  __shared__ double bside[4][M][D];
+  __shared__ double xb[4][M][R];
+  __shared__ double xs[2][M][M + 1];   // exchange tiles; per-wave staging
+  __shared__ double zc[MM], rpz[MM];
+  const Geo& g = a.g;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, c = lane & 15, gq = lane >> 4;
+  int sd = blockIdx.x;
+  if (LIST) {   // re-solve only the subdomains on the fallback list
+    if ((int)blockIdx.x >= a.fallback[0]) return;
+    sd = a.fallback[1 + blockIdx.x];
+  }
+  const int I = sd % g.SX, J = sd / g.SX;
+
+  load_kappa<M>(a, I, J, kap);
+  __syncthreads();
+  for (int l = tid; l < MM; l += PAIR)
+    assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, b0 + l, 1, nullptr);
+  if (tid < 4 * M) {
+    // Robin data of the basis columns: bside[side][t][k] = T_R g_k(t)
+    const int side = lane >> 4, t = lane & 15;
+    const int e = side_iface(g, I, J, side);
+    for (int k = 0; k < D; ++k) {
+      double v = 0.0;
+      if (e >= 0) {
+        const SideGeo sg = side_geo(g, side);
+        const double al = a.alpha[e];
+        const double kk = kap[side_cell<M>(side, t)];
+        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
+        const double beta = al * sg.H / kk;
+        double gv = a.basis[((size_t)e * D + k) * M + t];
+        if (k >= g.nP) gv = -beta * side_sigma(side) * gv;
+        v = TR * gv;
+      }
+      bside[side][t][k] = v;
+    }
+  }
+  __syncthreads();
+
+  const d4 zero = {0.0, 0.0, 0.0, 0.0};
+  const int nchain = w ? NL : MID;   // rows eliminated before the join
+  d4 Sv[NU], Xv[NU];
+  bool bad = false;
+  d4 pc = zero;   // particular column carried along the chain
+#pragma unroll
+  for (int t = 0; t < MID; ++t) {
+    if (t < nchain) {
+      const int j = w ? M - 1 - t : t;
+      const int jc = w ? j : j - 1;     // coupling towards the chain's previous row
+      d4 s = coupled_block(j, t > 0 ? jc : -1, t > 0 ? Sv[t > 0 ? t - 1 : 0] : zero, c, gq, dg, ex, cy);
+      s = gauss_jordan16(s, c, gq, bad);
+      Sv[t] = s;
+      d4 r, rp;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * v + gq;
+        double bv = side_rhs(bside, j, row, c), bp = b0[j * M + row];
+        if (t > 0) {
+          const double cc = cy[jc * M + row];
+          bv -= cc * Xv[t > 0 ? t - 1 : 0][v];
+          bp -= cc * pc[v];
+        }
+        r[v] = bv;
+        rp[v] = bp;
+      }
+      d4 z = zero, zz = zero;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        z = mfma(s[kk], r[kk], z);
+        zz = mfma(s[kk], rp[kk], zz);
+      }
+      Xv[t] = z;
+      pc = zz;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = zz[v];
+      }
+    }
+  }
+  // join: wave 1 hands over its last inverse block and forward tile (row
+  // MID+1); wave 0 solves row MID and hands back its solution tile
+  if (w == 1) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      xs[0][4 * v + gq][c] = Sv[NL - 1][v];
+      xs[1][4 * v + gq][c] = Xv[NL - 1][v];
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+    constexpr int j = MID;
+    d4 s = coupled_block(j, j - 1, Sv[MID - 1], c, gq, dg, ex, cy);
+    d4 r, rp;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * v + gq;
+      s[v] -= cy[j * M + row] * xs[0][row][c] * cy[j * M + c];
+      const double cu = cy[(j - 1) * M + row], cl = cy[j * M + row];
+      r[v] = side_rhs(bside, j, row, c) - cu * Xv[MID - 1][v] - cl * xs[1][row][c];
+      rp[v] = b0[j * M + row] - cu * pc[v] - cl * pz[(j + 1) * M + row];
+    }
+    s = gauss_jordan16(s, c, gq, bad);
+    Sv[MID] = s;
+    d4 z = zero, zz = zero;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      z = mfma(s[kk], r[kk], z);
+      zz = mfma(s[kk], rp[kk], zz);
+    }
+    Xv[MID] = z;
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = zz[v];
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xs[0][4 * v + gq][c] = Xv[MID][v];
+  }
+  __syncthreads();
+  d4 xm;      // solution tile of the joining row, in both waves
+#pragma unroll
+  for (int v = 0; v < 4; ++v) xm[v] = (w == 0) ? Xv[MID][v] : xs[0][4 * v + gq][c];
+  // back substitution outwards from the joining row
+  {
+    d4 xp = xm;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pc[v] = pz[MID * M + 4 * v + gq];
+#pragma unroll
+    for (int t = MID - 1; t >= 0; --t) {
+      if (t < nchain) {
+        const int j = w ? M - 1 - t : t;
+        const int jc = w ? j - 1 : j;   // coupling towards the joining side
+        d4 tt, tp, xq;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 4 * v + gq;
+          const double cc = -cy[jc * M + row];
+          tt[v] = cc * xp[v];
+          tp[v] = cc * pc[v];
+          xq[v] = pz[j * M + row];
+        }
+        d4 x = Xv[t];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          x = mfma(Sv[t][kk], tt[kk], x);
+          xq = mfma(Sv[t][kk], tp[kk], xq);
+        }
+        Xv[t] = x;
+        xp = x;
+        pc = xq;
+        if (c == 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = xq[v];
+        }
+      }
+    }
+  }
+  if (bad) atomicOr(a.status, ST_LOCAL_PIVOT);
+
+  // one step of iterative refinement of all 17 columns (residual in
+  // double-double, correction by the same two-chain sweeps)
+  __syncthreads();
+  for (int l = tid; l < MM; l += PAIR) {
+    const int i = l % M, j = l / M;
+    double ph = b0[l], pl = 0.0;
+    dd_fma(ph, pl, -dg[l], pz[l]);
+    dd_fma(ph, pl, i < M - 1 ? -ex[l] : 0.0, pz[i < M - 1 ? l + 1 : l]);
+    dd_fma(ph, pl, i > 0 ? -ex[l - 1] : 0.0, pz[i > 0 ? l - 1 : l]);
+    dd_fma(ph, pl, j < M - 1 ? -cy[l] : 0.0, pz[j < M - 1 ? l + M : l]);
+    dd_fma(ph, pl, j > 0 ? -cy[l - M] : 0.0, pz[j > 0 ? l - M : l]);
+    rpz[l] = ph + pl;
+  }
+  if (w == 1) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xs[1][4 * v + gq][c] = Xv[NL - 1][v];
+  }
+  __syncthreads();
+  d4 xo;      // the other wave's tile next to the join (rows MID+1 / MID)
+#pragma unroll
+  for (int v = 0; v < 4; ++v) xo[v] = (w == 0) ? xs[1][4 * v + gq][c] : xm[v];
+  __syncthreads();
+  double (*T)[M + 1] = xs[w];   // per-wave staging of in-row neighbours
+  // residual of own row index t (row j): neighbours along y from the
+  // chain's tiles, the other wave's tile across the join
+  auto residual = [&](int t, int j, d4& r) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[4 * v + gq][c] = Xv[t][v];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * v + gq, l = j * M + i;
+      double hi = side_rhs(bside, j, i, c), lo = 0.0;
+      dd_fma(hi, lo, -dg[l], Xv[t][v]);
+      dd_fma(hi, lo, i < M - 1 ? -ex[l] : 0.0, T[i < M - 1 ? i + 1 : i][c]);
+      dd_fma(hi, lo, i > 0 ? -ex[i > 0 ? l - 1 : l] : 0.0, T[i > 0 ? i - 1 : i][c]);
+      r[v] = hi + lo;
+    }
+    __builtin_amdgcn_wave_barrier();
+  };
+  f4z Zc[NU];
+  d4 qc = zero;   // particular correction carried along the chain
+#pragma unroll
+  for (int t = 0; t < MID; ++t) {
+    if (t < nchain) {
+      const int j = w ? M - 1 - t : t;
+      const int jc = w ? j : j - 1;
+      d4 r;
+      residual(t, j, r);
+      // y neighbours: the previous row of the chain (t-1) and the next (t+1,
+      // or across the join for the last row before it)
+      const int jcn = w ? j - 1 : j;                // coupling towards the join
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * v + gq;
+        double hi = r[v], lo = 0.0;
+        const double xnext = (t + 1 < nchain) ? Xv[t + 1 < NU ? t + 1 : t][v] : (w ? xm[v] : Xv[MID][v]);
+        dd_fma(hi, lo, -cy[jcn * M + i], xnext);
+        if (t > 0) dd_fma(hi, lo, -cy[jc * M + i], Xv[t > 0 ? t - 1 : 0][v]);
+        r[v] = hi + lo;
+      }
+      d4 rp;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * v + gq;
+        rp[v] = rpz[j * M + i];
+        if (t > 0) {
+          const double cc = cy[jc * M + i];
+          r[v] -= cc * (double)Zc[t > 0 ? t - 1 : 0][v];
+          rp[v] -= cc * qc[v];
+        }
+      }
+      d4 z = zero, zz = zero;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        z = mfma(Sv[t][kk], r[kk], z);
+        zz = mfma(Sv[t][kk], rp[kk], zz);
+      }
+      Zc[t] = tof(z);
+      qc = zz;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) zc[j * M + 4 * v + gq] = zz[v];
+      }
+    }
+  }
+  // join of the correction sweeps
+  if (w == 1) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xs[1][4 * v + gq][c] = (double)Zc[NL - 1][v];
+  }
+  __syncthreads();
+  if (w == 0) {
+    constexpr int j = MID;
+    d4 r;
+    residual(MID, j, r);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * v + gq;
+      double hi = r[v], lo = 0.0;
+      dd_fma(hi, lo, -cy[j * M + i], xo[v]);
+      dd_fma(hi, lo, -cy[(j - 1) * M + i], Xv[MID - 1][v]);
+      r[v] = hi + lo;
+    }
+    d4 rp;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * v + gq;
+      const double cu = cy[(j - 1) * M + i], cl = cy[j * M + i];
+      r[v] -= cu * (double)Zc[MID - 1][v] + cl * xs[1][i][c];
+      rp[v] = rpz[j * M + i] - cu * qc[v] - cl * zc[(j + 1) * M + i];
+    }
+    d4 z = zero, zz = zero;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      z = mfma(Sv[MID][kk], r[kk], z);
+      zz = mfma(Sv[MID][kk], rp[kk], zz);
+    }
+    Zc[MID] = tof(z);
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) zc[j * M + 4 * v + gq] = zz[v];
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xs[0][4 * v + gq][c] = (double)Zc[MID][v];
+  }
+  __syncthreads();
+  {
+    d4 cm;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) cm[v] = xs[0][4 * v + gq][c];
+    if (w == 0) Xv[MID] += cm;
+    if (w == 0 && c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pz[MID * M + 4 * v + gq] += zc[MID * M + 4 * v + gq];
+    }
+    d4 cp = cm, qp;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qp[v] = zc[MID * M + 4 * v + gq];
+#pragma unroll
+    for (int t = MID - 1; t >= 0; --t) {
+      if (t < nchain) {
+        const int j = w ? M - 1 - t : t;
+        const int jc = w ? j - 1 : j;
+        d4 tt, tq, xq;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 4 * v + gq;
+          const double cc = -cy[jc * M + i];
+          tt[v] = cc * cp[v];
+          tq[v] = cc * qp[v];
+          xq[v] = zc[j * M + i];
+        }
+        d4 x = tod(Zc[t]);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          x = mfma(Sv[t][kk], tt[kk], x);
+          xq = mfma(Sv[t][kk], tq[kk], xq);
+        }
+        cp = x;
+        qp = xq;
+        Xv[t] += x;
+        if (c == 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] += xq[v];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // basis functions to global memory, column-major per subdomain
+  double* Xg = a.X + (size_t)sd * R * MM;
+#pragma unroll
+  for (int t = 0; t < NU; ++t) {
+    if (t < nchain || (w == 0 && t == MID)) {
+      const int j = w ? M - 1 - t : t;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Xg[(size_t)(1 + c) * MM + j * M + 4 * v + gq] = Xv[t][v];
+      if (gq == 0) xb[0][j][1 + c] = Xv[t][0];
+      if (gq == 3) xb[1][j][1 + c] = Xv[t][3];
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    if (w == 0) xb[2][4 * v + gq][1 + c] = Xv[0][v];
+    else xb[3][4 * v + gq][1 + c] = Xv[0][v];
+  }
+  for (int l = tid; l < MM; l += PAIR) Xg[l] = pz[l];
+  if (tid < M) {
+    xb[0][tid][0] = pz[tid * M];
+    xb[1][tid][0] = pz[tid * M + M - 1];
+    xb[2][tid][0] = pz[tid];
+    xb[3][tid][0] = pz[(M - 1) * M + tid];
+  }
+  __syncthreads();
   write_block(a, sd, I, J, kap, xb);
 }
 
@@ -1429,12 +1809,12 @@ __global__ void __launch_bounds__(WAVE) surrogate_gate_kernel(SubArgs a, const f
 }  // namespace
 
 hipError_t launch_basis_m16d4(const SubArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(basis_m16d4_kernel<false>, dim3(a.g.n_sub), dim3(WAVE), 0, st, a);
+  hipLaunchKernelGGL(basis_pair_kernel<false>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_basis_m16d4_list(const SubArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(basis_m16d4_kernel<true>, dim3(a.g.n_sub), dim3(WAVE), 0, st, a);
+  hipLaunchKernelGGL(basis_pair_kernel<true>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
   return hipGetLastError();
 }
 
