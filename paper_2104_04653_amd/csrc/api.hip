@@ -354,7 +354,9 @@ int build_plan(mrcm_ctx* c) {
           const int nb = std::min(PANEL_NB, d.s - k0);
           for (int r = k0 + nb; r < d.n; r += TILE)
             for (int cc = k0 + nb; cc <= d.n; cc += TILE)
-              items.push_back(PanelItem{id, r, cc, (r == k0 + nb && cc == k0 + nb && d.s > k0 + nb) ? 1 : 0});
+              items.push_back(PanelItem{id, r, cc,
+                                        (r == k0 + nb && cc == k0 + nb && d.s > k0 + nb) ? 1 : 0,
+                                        d.n, d.s, d.f_off, d.inv_off});
         }
         pl.update_count = (int)items.size() - pl.update_off;
         pl.diag_count = (int)diag.size();

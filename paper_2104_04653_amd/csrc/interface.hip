@@ -279,15 +279,25 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
   __shared__ double Ws[PANEL_NB][TILE + 1];       // W = A11^-1 A12
   __shared__ double Tt[16][17];
   static_assert(TILE == 64 && PANEL_NB == 32 && NT == 256, "tile shape of the MFMA mapping");
-  const PanelItem it = items[blockIdx.x];
-  const NodeDesc nd = nodes[it.node];
-  const int n = nd.n, ld = n + 1;
-  const int nb = min(PANEL_NB, nd.s - k0);
-  double* F = tree + nd.f_off;
-  const double* iv = panel_inv(inv, nd, k0);
+  const PanelItem it = items[blockIdx.x];   // carries the front's fields: one load round
+  const int n = it.n, ld = n + 1;
+  const int nb = min(PANEL_NB, it.s - k0);
+  double* F = tree + it.f_off;
+  const double* iv = inv + it.inv_off + (long long)(k0 / PANEL_NB) * PANEL_NB * PANEL_NB;
   const int t = threadIdx.x;
   const int r0 = it.i0, c0 = it.j0;
   const int rows = min(TILE, n - r0), cols = min(TILE, ld - c0);
+  const int w = t >> 6, lane = t & 63, c = lane & 15, g = lane >> 4;
+  // this thread's entries of the A22 tile, loaded with the operands
+  double a22[4][4];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * w + 4 * v + g, j = 16 * tj + c;
+      a22[tj][v] = (i < rows && j < cols) ? F[(long long)(r0 + i) * ld + c0 + j] : 0.0;
+    }
+  }
 #pragma unroll
   for (int e = t; e < PANEL_NB * PANEL_NB; e += NT) {
     const int i = e / PANEL_NB, k = e % PANEL_NB;
@@ -304,7 +314,6 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
     Bs[k][j] = (k < nb && j < cols) ? F[(long long)(k0 + k) * ld + c0 + j] : 0.0;
   }
   __syncthreads();
-  const int w = t >> 6, lane = t & 63, c = lane & 15, g = lane >> 4;
   {
     // W: 2 x 4 result tiles of 16 x 16, two per wave
     const int ti = w >> 1, tj = 2 * (w & 1);
@@ -341,15 +350,14 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
       const int i = 16 * w + 4 * v + g, j = 16 * tj + c;
       double val = 0.0;
       if (i < rows && j < cols) {
-        double* f = F + (long long)(r0 + i) * ld + c0 + j;
-        val = *f - acc[tj][v];
-        *f = val;
+        val = a22[tj][v] - acc[tj][v];
+        F[(long long)(r0 + i) * ld + c0 + j] = val;
       }
       if (next_diag && i < PANEL_NB && j < PANEL_NB) Dv[i][j] = val;
     }
   }
   if (next_diag) {
-    const int k1 = k0 + nb, nb1 = min(PANEL_NB, nd.s - k1);
+    const int k1 = k0 + nb, nb1 = min(PANEL_NB, it.s - k1);
     __syncthreads();
     for (int e = t; e < PANEL_NB * PANEL_NB; e += NT) {
       const int i = e / PANEL_NB, j = e % PANEL_NB;
@@ -358,7 +366,7 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
     __syncthreads();
     if (t < 64) {
       bool bad = false;
-      inv32_wave(Dv, Tt, panel_inv(inv, nd, k1), bad);
+      inv32_wave(Dv, Tt, inv + it.inv_off + (long long)(k1 / PANEL_NB) * PANEL_NB * PANEL_NB, bad);
       if (bad) atomicOr(status, ST_IFACE_PIVOT);
     }
   }

@@ -78,6 +78,9 @@ struct PanelItem {      // one work-group of a blocked trailing update
   int node;             // index into the node descriptor array
   int i0, j0;           // first row / column of the 64 x 64 tile
   int pad;              // 1: the tile starts with the next panel's diagonal block
+  int n, s;             // the front's size and separator size (copied from its node)
+  long long f_off;      // the front's offset in the tree buffer
+  long long inv_off;    // the front's diagonal-block inverses
 };
 
 // ---- launchers (local.hip) ----
