@@ -62,7 +62,8 @@ struct mrcm_ctx {
   int2* d_maps = nullptr;
   int* d_dofs = nullptr;
   int* d_ids = nullptr;
-  int2* d_gather = nullptr;
+  GatherItem* d_gather = nullptr;
+  NodeDesc* d_lvnodes = nullptr;  // node descriptors in level order (ids order)
   PanelItem* d_items = nullptr;
   double* inv = nullptr;        // per-panel diagonal-block inverses of blocked fronts
   double* partials = nullptr;   // residual partial maxima
@@ -264,7 +265,7 @@ int build_plan(mrcm_ctx* c) {
   std::vector<NodeDesc> desc;
   std::vector<int2> maps;
   std::vector<int> dofs, ids;
-  std::vector<int2> gather;
+  std::vector<GatherItem> gather;
   std::vector<PanelItem> items;
   std::vector<std::vector<int>> panel_ids;
   std::vector<int> node_desc(tb.nodes.size(), -1);
@@ -337,8 +338,8 @@ int build_plan(mrcm_ctx* c) {
       lp.gather_off = (int)gather.size();
       for (int q = 0; q < lp.count; ++q) {
         const NodeDesc& d = desc[ids[lp.ids_off + q]];
-        gather.push_back(make_int2(ids[lp.ids_off + q], -1));   // first diagonal block
-        for (int r = 0; r < d.n; r += GATHER_ROWS) gather.push_back(make_int2(ids[lp.ids_off + q], r));
+        gather.push_back(GatherItem{d, -1, 0});   // first diagonal block
+        for (int r = 0; r < d.n; r += GATHER_ROWS) gather.push_back(GatherItem{d, r, 0});
       }
       lp.gather_count = (int)gather.size() - lp.gather_off;
       for (int k0 = 0; k0 < lp.max_s; k0 += PANEL_NB) {
@@ -387,14 +388,20 @@ int build_plan(mrcm_ctx* c) {
   ALLOC(c, c->d_maps, maps.size());
   ALLOC(c, c->d_dofs, dofs.size());
   ALLOC(c, c->d_ids, ids.size());
+  ALLOC(c, c->d_lvnodes, ids.size());
   ALLOC(c, c->d_gather, gather.size());
   ALLOC(c, c->d_items, items.size());
   HIPCHK(c, hipMemcpy(c->d_nodes, desc.data(), desc.size() * sizeof(NodeDesc), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_maps, maps.data(), maps.size() * sizeof(int2), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_dofs, dofs.data(), dofs.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_ids, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice));
+  {
+    std::vector<NodeDesc> lv(ids.size());
+    for (size_t k = 0; k < ids.size(); ++k) lv[k] = desc[ids[k]];
+    HIPCHK(c, hipMemcpy(c->d_lvnodes, lv.data(), lv.size() * sizeof(NodeDesc), hipMemcpyHostToDevice));
+  }
   if (!gather.empty())
-    HIPCHK(c, hipMemcpy(c->d_gather, gather.data(), gather.size() * sizeof(int2), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_gather, gather.data(), gather.size() * sizeof(GatherItem), hipMemcpyHostToDevice));
   if (!items.empty())
     HIPCHK(c, hipMemcpy(c->d_items, items.data(), items.size() * sizeof(PanelItem), hipMemcpyHostToDevice));
   return MRCM_OK;
@@ -433,21 +440,21 @@ int run_interface(mrcm_ctx* c) {
   hipStream_t st = c->st;
   for (const LevelPlan& lp : c->levels) {
     if (lp.small) {
-      HIPCHK(c, launch_front_small(c->d_nodes, c->d_ids + lp.ids_off, lp.count, lp.max_n, c->tree,
+      HIPCHK(c, launch_front_small(c->d_lvnodes + lp.ids_off, lp.count, lp.max_n, c->tree,
                                    c->d_maps, c->status, st));
       continue;
     }
     // the gather inverts the first panel's diagonal block, each update the next one
-    HIPCHK(c, launch_front_gather(c->d_nodes, c->d_gather + lp.gather_off, lp.gather_count, c->tree,
-                                  c->d_maps, c->inv, c->status, st));
+    HIPCHK(c, launch_front_gather(c->d_gather + lp.gather_off, lp.gather_count, c->tree, c->d_maps,
+                                  c->inv, c->status, st));
     for (const PanelLaunch& pl : lp.panels)
       if (pl.update_count > 0)   // the root's last panel has no trailing rows
         HIPCHK(c, launch_front_update(c->d_nodes, c->d_items + pl.update_off, pl.update_count,
                                       pl.k0, c->tree, c->inv, c->status, st));
   }
   for (auto it = c->levels.rbegin(); it != c->levels.rend(); ++it)
-    HIPCHK(c, launch_front_back(c->d_nodes, c->d_ids + it->ids_off, it->count, c->tree, c->inv,
-                                c->d_dofs, nullptr, c->coef, st));
+    HIPCHK(c, launch_front_back(c->d_lvnodes + it->ids_off, it->count, c->tree, c->inv, c->d_dofs,
+                                nullptr, c->coef, st));
   HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2, st));
   return MRCM_OK;
 }
@@ -459,11 +466,11 @@ int run_interface(mrcm_ctx* c) {
 int refine_interface(mrcm_ctx* c) {
   hipStream_t st = c->st;
   for (const LevelPlan& lp : c->levels)
-    HIPCHK(c, launch_front_rhs(c->d_nodes, c->d_ids + lp.ids_off, lp.count, c->tree, c->inv,
-                               c->d_maps, c->d_dofs, c->rvec, c->rtree, st));
+    HIPCHK(c, launch_front_rhs(c->d_lvnodes + lp.ids_off, lp.count, c->tree, c->inv, c->d_maps,
+                               c->d_dofs, c->rvec, c->rtree, st));
   for (auto lv = c->levels.rbegin(); lv != c->levels.rend(); ++lv)
-    HIPCHK(c, launch_front_back(c->d_nodes, c->d_ids + lv->ids_off, lv->count, c->tree, c->inv,
-                                c->d_dofs, c->rtree, c->dx, st));
+    HIPCHK(c, launch_front_back(c->d_lvnodes + lv->ids_off, lv->count, c->tree, c->inv, c->d_dofs,
+                                c->rtree, c->dx, st));
   HIPCHK(c, launch_add(c->coef, c->dx, c->n_dof, st));
   HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2, st));
   return MRCM_OK;

@@ -66,12 +66,11 @@ __device__ inline void two_prod_sub(double& hi, double& lo, double a, double b) 
 // 32 columns x 8 rows per pass.
 constexpr int TXN = 32, TYN = NT / TXN;
 
-__global__ void __launch_bounds__(NT) front_small_kernel(const NodeDesc* nodes, const int* ids,
-                                                         double* tree, const int2* maps,
-                                                         int* status) {
+__global__ void __launch_bounds__(NT) front_small_kernel(const NodeDesc* nodes, double* tree,
+                                                         const int2* maps, int* status) {
   extern __shared__ double F[];
   __shared__ int2 mp[SMALL_FRONT];
-  const NodeDesc nd = nodes[ids[blockIdx.x]];
+  const NodeDesc nd = nodes[blockIdx.x];   // this level's fronts, one per work-group
   const int n = nd.n, s = nd.s, ld = n + 1;
   const int tid = threadIdx.x, tx = tid % TXN, ty = tid / TXN;
   for (int a = tid; a < n; a += NT) mp[a] = maps[nd.map_off + a];
@@ -225,20 +224,20 @@ __device__ inline double* panel_inv(double* inv, const NodeDesc& nd, int k0) {
 // items: (node index, first row); each work-group gathers GATHER_ROWS rows
 // of a blocked front.  An item with first row -1 instead gathers the
 // diagonal block of the front's first panel into LDS and inverts it.
-__global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes, const int2* items,
-                                                          double* tree, const int2* maps,
-                                                          double* inv, int* status) {
+__global__ void __launch_bounds__(NT) front_gather_kernel(const GatherItem* items, double* tree,
+                                                          const int2* maps, double* inv,
+                                                          int* status) {
   __shared__ double A[PANEL_NB][PANEL_NB + 1];
   __shared__ double Tt[16][17];
   static_assert(GATHER_ROWS == NT / TXN, "one row per thread row");
   __shared__ int2 mp[MAX_FRONT];
-  const int2 it = items[blockIdx.x];
-  const NodeDesc nd = nodes[it.x];
+  const GatherItem gi = items[blockIdx.x];   // carries its front's descriptor
+  const NodeDesc& nd = gi.nd;
   const int n = nd.n, ld = n + 1;
   const int tx = threadIdx.x % TXN, ty = threadIdx.x / TXN;
-  for (int a = threadIdx.x; a < (it.y < 0 ? min(n, PANEL_NB) : n); a += NT) mp[a] = maps[nd.map_off + a];
+  for (int a = threadIdx.x; a < (gi.row < 0 ? min(n, PANEL_NB) : n); a += NT) mp[a] = maps[nd.map_off + a];
   __syncthreads();
-  if (it.y < 0) {
+  if (gi.row < 0) {
     const int nb = min(PANEL_NB, nd.s);
 #pragma unroll
     for (int a = ty; a < PANEL_NB; a += TYN) {
@@ -254,7 +253,7 @@ __global__ void __launch_bounds__(NT) front_gather_kernel(const NodeDesc* nodes,
     }
     return;
   }
-  const int a = it.y + ty;
+  const int a = gi.row + ty;
   if (a >= n) return;
   double* F = tree + nd.f_off + (long long)a * ld;
   const int2 ma = mp[a];
@@ -377,13 +376,12 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
 //  classic fronts: row k holds U (upper part) at elimination time k;
 //  blocked fronts: the rows of panel p hold the panel-time A12 to the right
 //  of the diagonal block, so x_1 = A11^{-1} (b_1 - A12 x_2).
-__global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, const int* ids,
-                                                        const double* tree, const double* inv,
-                                                        const int* dofs, const double* rtree,
-                                                        double* x) {
+__global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, const double* tree,
+                                                        const double* inv, const int* dofs,
+                                                        const double* rtree, double* x) {
   extern __shared__ double xl[];   // n values: front-local unknowns
   __shared__ double y[PANEL_NB];
-  const NodeDesc nd = nodes[ids[blockIdx.x]];
+  const NodeDesc nd = nodes[blockIdx.x];
   const int n = nd.n, s = nd.s, ld = n + 1;
   const double* F = tree + nd.f_off;
   const int* dof = dofs + nd.dof_off;
@@ -449,13 +447,13 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
 // apply the stored elimination: multipliers in the columns of classic
 // fronts; A21 A11^-1 per panel for blocked fronts (the panel rows keep their
 // panel-time values for the back substitution).
-__global__ void __launch_bounds__(NT) front_rhs_kernel(const NodeDesc* nodes, const int* ids,
-                                                       const double* tree, const double* inv,
-                                                       const int2* maps, const int* dofs,
-                                                       const double* r, double* rtree) {
+__global__ void __launch_bounds__(NT) front_rhs_kernel(const NodeDesc* nodes, const double* tree,
+                                                       const double* inv, const int2* maps,
+                                                       const int* dofs, const double* r,
+                                                       double* rtree) {
   extern __shared__ double rl[];   // n values
   __shared__ double z[PANEL_NB];
-  const NodeDesc nd = nodes[ids[blockIdx.x]];
+  const NodeDesc nd = nodes[blockIdx.x];
   const int n = nd.n, s = nd.s, ld = n + 1;
   const int t = threadIdx.x;
   const int2* mp = maps + nd.map_off;
@@ -599,18 +597,17 @@ hipError_t prepare_interface_kernels() {
                              SMALL_FRONT * (SMALL_FRONT + 1) * (int)sizeof(double));
 }
 
-hipError_t launch_front_small(const NodeDesc* nodes, const int* ids, int count, int max_n,
-                              double* tree, const int2* maps, int* status, hipStream_t st) {
+hipError_t launch_front_small(const NodeDesc* nodes, int count, int max_n, double* tree,
+                              const int2* maps, int* status, hipStream_t st) {
   const size_t lds = (size_t)max_n * (max_n + 1) * sizeof(double);
-  hipLaunchKernelGGL(front_small_kernel, dim3(count), dim3(NT), lds, st, nodes, ids, tree, maps,
-                     status);
+  hipLaunchKernelGGL(front_small_kernel, dim3(count), dim3(NT), lds, st, nodes, tree, maps, status);
   return hipGetLastError();
 }
 
-hipError_t launch_front_gather(const NodeDesc* nodes, const int2* items, int count, double* tree,
-                               const int2* maps, double* inv, int* status, hipStream_t st) {
-  hipLaunchKernelGGL(front_gather_kernel, dim3(count), dim3(NT), 0, st, nodes, items, tree, maps,
-                     inv, status);
+hipError_t launch_front_gather(const GatherItem* items, int count, double* tree, const int2* maps,
+                               double* inv, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(front_gather_kernel, dim3(count), dim3(NT), 0, st, items, tree, maps, inv,
+                     status);
   return hipGetLastError();
 }
 
@@ -621,20 +618,19 @@ hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, in
   return hipGetLastError();
 }
 
-hipError_t launch_front_back(const NodeDesc* nodes, const int* ids, int count, const double* tree,
-                             const double* inv, const int* dofs, const double* rtree, double* x,
-                             hipStream_t st) {
+hipError_t launch_front_back(const NodeDesc* nodes, int count, const double* tree, const double* inv,
+                             const int* dofs, const double* rtree, double* x, hipStream_t st) {
   // the plan guarantees n <= MAX_FRONT
   hipLaunchKernelGGL(front_back_kernel, dim3(count), dim3(NT), MAX_FRONT * sizeof(double), st, nodes,
-                     ids, tree, inv, dofs, rtree, x);
+                     tree, inv, dofs, rtree, x);
   return hipGetLastError();
 }
 
-hipError_t launch_front_rhs(const NodeDesc* nodes, const int* ids, int count, const double* tree,
-                            const double* inv, const int2* maps, const int* dofs, const double* r,
-                            double* rtree, hipStream_t st) {
+hipError_t launch_front_rhs(const NodeDesc* nodes, int count, const double* tree, const double* inv,
+                            const int2* maps, const int* dofs, const double* r, double* rtree,
+                            hipStream_t st) {
   hipLaunchKernelGGL(front_rhs_kernel, dim3(count), dim3(NT), MAX_FRONT * sizeof(double), st, nodes,
-                     ids, tree, inv, maps, dofs, r, rtree);
+                     tree, inv, maps, dofs, r, rtree);
   return hipGetLastError();
 }
 

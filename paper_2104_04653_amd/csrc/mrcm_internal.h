@@ -74,6 +74,12 @@ struct NodeDesc {
   long long cr_off[2];  // each child's right-hand-side vector, -1 for a leaf child
 };
 
+struct GatherItem {     // one work-group of a blocked-front gather
+  NodeDesc nd;          // the front
+  int row;              // first of its GATHER_ROWS rows; -1: the first panel's diagonal block
+  int pad_;
+};
+
 struct PanelItem {      // one work-group of a blocked trailing update
   int node;             // index into the node descriptor array
   int i0, j0;           // first row / column of the 64 x 64 tile
@@ -101,23 +107,21 @@ bool local_supported(int M, int D);
 long long local_scratch_doubles(const Geo& g);
 
 // ---- launchers (interface.hip) ----
-hipError_t launch_front_small(const NodeDesc* nodes, const int* ids, int count, int max_n,
-                              double* tree, const int2* maps, int* status, hipStream_t st);
-hipError_t launch_front_gather(const NodeDesc* nodes, const int2* items, int count,
-                               double* tree, const int2* maps, double* inv, int* status,
-                               hipStream_t st);
+hipError_t launch_front_small(const NodeDesc* nodes, int count, int max_n, double* tree,
+                              const int2* maps, int* status, hipStream_t st);
+hipError_t launch_front_gather(const GatherItem* items, int count, double* tree, const int2* maps,
+                               double* inv, int* status, hipStream_t st);
 hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count,
                                int k0, double* tree, double* inv, int* status, hipStream_t st);
 // back substitution of one tree level; rtree = NULL takes the right-hand
 // side from the fronts' last column, else from the fronts' rhs vectors
-hipError_t launch_front_back(const NodeDesc* nodes, const int* ids, int count, const double* tree,
-                             const double* inv, const int* dofs, const double* rtree, double* x,
-                             hipStream_t st);
+hipError_t launch_front_back(const NodeDesc* nodes, int count, const double* tree, const double* inv,
+                             const int* dofs, const double* rtree, double* x, hipStream_t st);
 // forward elimination of a new right-hand side r (one value per interface
 // dof) through the stored fronts of one tree level, into the rhs tree
-hipError_t launch_front_rhs(const NodeDesc* nodes, const int* ids, int count, const double* tree,
-                            const double* inv, const int2* maps, const int* dofs, const double* r,
-                            double* rtree, hipStream_t st);
+hipError_t launch_front_rhs(const NodeDesc* nodes, int count, const double* tree, const double* inv,
+                            const int2* maps, const int* dofs, const double* r, double* rtree,
+                            hipStream_t st);
 // r = b - A x of the assembled interface system (double-double), written to
 // r if not NULL; partials: 2 doubles per work-group (RESID_WG of them),
 // reduced into out2[0] = max|r|, out2[1] = max|b|
