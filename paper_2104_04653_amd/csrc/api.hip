@@ -360,6 +360,10 @@ int build_plan(mrcm_ctx* c) {
                                         d.n, d.s, d.f_off, d.inv_off});
         }
         pl.update_count = (int)items.size() - pl.update_off;
+        // tiles that invert the next diagonal block first: they are the
+        // critical path of the panel
+        std::stable_partition(items.begin() + pl.update_off, items.end(),
+                              [](const PanelItem& q) { return q.pad != 0; });
         pl.diag_count = (int)diag.size();
         panel_ids.push_back(diag);
         pl.diag_off = -1;  // resolved after all level ids are known

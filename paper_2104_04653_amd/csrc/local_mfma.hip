@@ -1137,6 +1137,113 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
   write_block(a, sd, I, J, kap, xb);
 }
 
+// Two-wavefront elimination of the 16 Schur blocks (wave 0: rows 0..MID-1
+// and the joining row MID, wave 1: rows M-1..MID+1, index t = row M-1-t);
+// xch is an LDS tile for the hand-over at the join.  Both waves must call.
+__device__ inline void factor_pair(d4* Sv, int w, int c, int g, const double* dg, const double* ex,
+                                   const double* cy, double (*xch)[M + 1], bool& bad) {
+  const d4 zero = {0.0, 0.0, 0.0, 0.0};
+  const int nchain = w ? NL : MID;
+#pragma unroll
+  for (int t = 0; t < MID; ++t) {
+    if (t < nchain) {
+      const int j = w ? M - 1 - t : t;
+      const int jc = w ? j : j - 1;
+      d4 s = coupled_block(j, t > 0 ? jc : -1, t > 0 ? Sv[t > 0 ? t - 1 : 0] : zero, c, g, dg, ex, cy);
+      Sv[t] = gauss_jordan16(s, c, g, bad);
+    }
+  }
+  if (w == 1) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xch[4 * v + g][c] = Sv[NL - 1][v];
+  }
+  __syncthreads();
+  if (w == 0) {
+    constexpr int j = MID;
+    d4 s = coupled_block(j, j - 1, Sv[MID - 1], c, g, dg, ex, cy);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s[v] -= cy[j * M + 4 * v + g] * xch[4 * v + g][c] * cy[j * M + c];
+    Sv[MID] = gauss_jordan16(s, c, g, bad);
+  }
+  __syncthreads();
+}
+
+// One column solve with the blocks of factor_pair (rhs and result in LDS,
+// cell-major; the column is replicated over the 16 MFMA columns and lanes
+// with c == 0 write the result).  Both waves must call.
+__device__ inline void solve_column_pair(const d4* Sv, int w, const double* rhs, double* out, int c,
+                                         int g, const double* cy) {
+  const d4 zero = {0.0, 0.0, 0.0, 0.0};
+  const int nchain = w ? NL : MID;
+  d4 zc = zero;
+#pragma unroll
+  for (int t = 0; t < MID; ++t) {
+    if (t < nchain) {
+      const int j = w ? M - 1 - t : t;
+      const int jc = w ? j : j - 1;
+      d4 r;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * v + g;
+        double b = rhs[j * M + row];
+        if (t > 0) b -= cy[jc * M + row] * zc[v];
+        r[v] = b;
+      }
+      d4 acc = zero;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = mfma(Sv[t][kk], r[kk], acc);
+      zc = acc;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = acc[v];
+      }
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+    constexpr int j = MID;
+    d4 r;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * v + g;
+      r[v] = rhs[j * M + row] - cy[(j - 1) * M + row] * zc[v] - cy[j * M + row] * out[(j + 1) * M + row];
+    }
+    d4 acc = zero;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mfma(Sv[MID][kk], r[kk], acc);
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = acc[v];
+    }
+  }
+  __syncthreads();
+  d4 xp;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) xp[v] = out[MID * M + 4 * v + g];
+#pragma unroll
+  for (int t = MID - 1; t >= 0; --t) {
+    if (t < nchain) {
+      const int j = w ? M - 1 - t : t;
+      const int jc = w ? j - 1 : j;
+      d4 tt, x;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * v + g;
+        tt[v] = -cy[jc * M + row] * xp[v];
+        x[v] = out[j * M + row];
+      }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) x = mfma(Sv[t][kk], tt[kk], x);
+      xp = x;
+      if (c == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = x[v];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // FP32 factors and solves with FP64 iterative refinement (16 x 16, 2 + 2 dofs)
 // ---------------------------------------------------------------------------
@@ -1631,6 +1738,148 @@ __global__ void __launch_bounds__(WAVE) stitch_m16d4_kernel(SubArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(PAIR) stitch_pair_kernel(SubArgs a) {
+  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
+  __shared__ double pm[MM], bs_[MM], ps[MM], rs[MM], dx[MM];
+  __shared__ double Fout[4][M];
+  __shared__ double red[3][PAIR];
+  __shared__ double xch[M][M + 1];
+  const Geo& g = a.g;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, c = lane & 15, gq = lane >> 4;
+  const int sd = blockIdx.x;
+  const int I = sd % g.SX, J = sd / g.SX;
+  const int nP = g.nP;
+
+  load_kappa<M>(a, I, J, kap);
+  for (int l = tid; l < MM; l += PAIR) pm[l] = compose16(a, sd, l);
+  __syncthreads();
+  if (tid < 4 * M) {
+    // one-sided Robin fluxes on both sides of each skeleton face; outflow
+    // of this subdomain = their average
+    const int side = lane >> 4, t = lane & 15;
+    const int e = side_iface(g, I, J, side);
+    double fo = 0.0;
+    if (e >= 0) {
+      const SideGeo sg = side_geo(g, side);
+      const double al = a.alpha[e];
+      const double* bsf = a.basis + (size_t)e * D * M;
+      const double* ce = a.coef + (size_t)e * D;
+      double PH = 0.0, UH = 0.0;
+      for (int k = 0; k < nP; ++k) PH += ce[k] * bsf[k * M + t];
+      for (int k = nP; k < D; ++k) UH += ce[k] * bsf[k * M + t];
+      const int l = side_cell<M>(side, t);
+      const double sig = side_sigma(side);
+      const double ko = kap[l];
+      const double Fown = sg.flen * ko / (sg.dist + al * sg.H) *
+                          (pm[l] - (PH - al * sg.H / ko * sig * UH));
+      const int nside = side ^ 1;
+      const int nsd = (side == 0) ? sd - 1 : (side == 1) ? sd + 1 : (side == 2) ? sd - g.SX : sd + g.SX;
+      const int nI = nsd % g.SX, nJ = nsd / g.SX;
+      const int nl = side_cell<M>(nside, t);
+      const size_t nc = (size_t)(nJ * M + nl / M) * g.nx + nI * M + nl % M;
+      const double kn = a.K[nc] * a.lam[nc];
+      const double pn = compose16(a, nsd, nl);
+      const double Fnb = sg.flen * kn / (sg.dist + al * sg.H) *
+                         (pn - (PH - al * sg.H / kn * (-sig) * UH));
+      fo = 0.5 * (Fown - Fnb);
+    }
+    Fout[side][t] = fo;
+  }
+  __syncthreads();
+  for (int l = tid; l < MM; l += PAIR)
+    assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, bs_ + l, 0, Fout);
+  __syncthreads();
+  const bool dir = (I == 0 && g.kind[0] == 1) || (I == g.SX - 1 && g.kind[1] == 1) ||
+                   (J == 0 && g.kind[2] == 1) || (J == g.SY - 1 && g.kind[3] == 1);
+  if (!dir && tid == 0) {
+    const double tp = dg[0];
+    dg[0] += tp;
+    bs_[0] += tp * pm[0];
+  }
+  __syncthreads();
+
+  d4 Sv[NU];
+  bool bad = false;
+  factor_pair(Sv, w, c, gq, dg, ex, cy, xch, bad);
+  if (bad) atomicOr(a.status, ST_STITCH_PIVOT);
+  solve_column_pair(Sv, w, bs_, ps, c, gq, cy);
+  // iterative refinement with the stored inverse blocks, residual in
+  // double-double
+  for (int it = 0; it < 3; ++it) {
+    for (int l = tid; l < MM; l += PAIR) {
+      const int li = l % M, lj = l / M;
+      double hi = bs_[l], lo = 0.0;
+      dd_fma(hi, lo, -dg[l], ps[l]);
+      if (li < M - 1) dd_fma(hi, lo, -ex[l], ps[l + 1]);
+      if (li > 0) dd_fma(hi, lo, -ex[l - 1], ps[l - 1]);
+      if (lj < M - 1) dd_fma(hi, lo, -cy[l], ps[l + M]);
+      if (lj > 0) dd_fma(hi, lo, -cy[l - M], ps[l - M]);
+      rs[l] = hi + lo;
+    }
+    __syncthreads();
+    solve_column_pair(Sv, w, rs, dx, c, gq, cy);
+    for (int l = tid; l < MM; l += PAIR) ps[l] += dx[l];
+    __syncthreads();
+  }
+
+  double imb = 0.0, fmx = 0.0, psum = 0.0;
+  for (int l = tid; l < MM; l += PAIR) {
+    const int li = l % M, lj = l / M;
+    const int i = I * M + li, j = J * M + lj;
+    const double kc = kap[l];
+    const double txc = kc * g.hy / (0.5 * g.hx), tyc = kc * g.hx / (0.5 * g.hy);
+    const double pv = ps[l];
+    double F[4];
+    for (int side = 0; side < 4; ++side) {
+      const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
+      double out;
+      if (inner) {
+        const int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
+        const double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
+        out = series2(side < 2 ? txc : tyc, tn) * (pv - ps[nb]);
+      } else {
+        const int e = side_iface(g, I, J, side);
+        const int t = (side < 2) ? lj : li;
+        if (e >= 0) {
+          out = Fout[side][t];
+        } else {
+          const double flen = (side < 2) ? g.hy : g.hx;
+          const double v = a.bcv[side][(side < 2) ? j : i];
+          out = (g.kind[side] == 1) ? ((side < 2) ? txc : tyc) * (pv - v) : v * flen;
+        }
+      }
+      F[side] = (side == 0 || side == 2) ? -out : out;
+    }
+    a.ux[(size_t)j * (g.nx + 1) + i] = F[0] / g.hy;
+    if (li == M - 1 && I == g.SX - 1) a.ux[(size_t)j * (g.nx + 1) + i + 1] = F[1] / g.hy;
+    a.uy[(size_t)j * g.nx + i] = F[2] / g.hx;
+    if (lj == M - 1 && J == g.SY - 1) a.uy[(size_t)(j + 1) * g.nx + i] = F[3] / g.hx;
+    const double q = a.src ? a.src[(size_t)j * g.nx + i] * g.hx * g.hy : 0.0;
+    const double net = F[1] - F[0] + F[3] - F[2];
+    imb = fmax(imb, fabs(net - q));
+    fmx = fmax(fmx, fmax(fmax(fabs(F[0]), fabs(F[1])), fmax(fabs(F[2]), fabs(F[3]))));
+    a.p_out[(size_t)j * g.nx + i] = pm[l];
+    psum += pm[l];
+  }
+  red[0][tid] = imb;
+  red[1][tid] = fmx;
+  red[2][tid] = psum;
+  __syncthreads();
+  for (int h = PAIR / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      red[0][tid] = fmax(red[0][tid], red[0][tid + h]);
+      red[1][tid] = fmax(red[1][tid], red[1][tid + h]);
+      red[2][tid] = red[2][tid] + red[2][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.sub_stats[3 * sd + 0] = red[0][0];
+    a.sub_stats[3 * sd + 1] = red[1][0];
+    a.sub_stats[3 * sd + 2] = red[2][0];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // learned surrogate of the 16 basis functions: network inputs, training
 // targets and the FP64 residual gate (the network itself is in surrogate.hip)
@@ -1824,7 +2073,7 @@ hipError_t launch_basis32_m16d4(const SubArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(stitch_m16d4_kernel, dim3(a.g.n_sub), dim3(WAVE), 0, st, a);
+  hipLaunchKernelGGL(stitch_pair_kernel, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
   return hipGetLastError();
 }
 
