@@ -58,7 +58,7 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_basis_m16d4_gauss1024.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_basis_pair_gauss1024.md")
 KERNEL_SOURCES = ("local_mfma.hip", "local_common.h", "mrcm_internal.h")
 
 
@@ -270,7 +270,7 @@ def main():
         "phases_ms": avg,
         "max_cell_imbalance": head["max_cell_imbalance"],
         "roofline": {
-            "kernel": "basis_m16d4_kernel",
+            "kernel": "basis_pair_kernel",
             "bound": "mfma",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,
