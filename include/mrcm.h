@@ -159,8 +159,10 @@ int mrcm_solve(mrcm_ctx* ctx);
  * Velocities are the stitched field: on skeleton faces the average of the
  * two one-sided Robin fluxes, inside every subdomain the fluxes of a
  * Neumann re-solve with that interface flux, so that every cell balances.
- *  on_device : 1 if p/ux/uy are device pointers, 0 for host arrays (any of
- *              them may be NULL to skip it).
+ *  on_device : 1 if p/ux/uy are device pointers (written in place by the
+ *              kernels; distinct, non-overlapping, 8-byte aligned), 0 for
+ *              host arrays (copied from the context's buffers); any of them
+ *              may be NULL to skip it.
  *  max_cell_imbalance : if not NULL receives max over cells of
  *              |net outflow - q|V|| / max |face flux|.
  * Synchronous: outputs are valid on return.  MRCM_E_STATE before the first

@@ -55,9 +55,13 @@ struct mrcm_ctx {
   double *alpha = nullptr, *basis = nullptr, *X = nullptr, *coef = nullptr;
   double *p = nullptr, *ux = nullptr, *uy = nullptr, *sub_stats = nullptr, *result = nullptr;
   double* tree = nullptr;
+  // report block (one device allocation, read back with one copy):
+  // result[RESULT_N] doubles, status, ir_iters, then the fallback list
+  double* report = nullptr;
   int* status = nullptr;
   int* fallback = nullptr;     // FP32 refinement: count + list of subdomains
   int* ir_iters = nullptr;
+  double* h_report = nullptr;  // pinned host mirror of the report head
   NodeDesc* d_nodes = nullptr;
   int2* d_maps = nullptr;
   int* d_dofs = nullptr;
@@ -120,6 +124,12 @@ int dev_alloc(mrcm_ctx* c, T** p, size_t count) {
   } while (0)
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+// report block: doubles result[0] = max cell imbalance, [1] = pressure sum
+// (gauge shift), [2] = max |r|, [3] = max |b| of the interface residual;
+// then ints status, ir_iters, fallback count, fallback list
+constexpr int RESULT_N = 8;
+constexpr size_t REPORT_HEAD = RESULT_N * sizeof(double) + 3 * sizeof(int);
 
 constexpr int IFACE_IR_MAX = 3;         // refinement steps of the interface solve
 constexpr double IFACE_IR_TOL = 1e-14;  // max|r| / max|b| that needs no refinement
@@ -440,6 +450,13 @@ __global__ void zero_int_kernel(int* p) { *p = 0; }
 
 __global__ void zero_ints_kernel(int* a, int* b, int* c) { *a = 0; *b = 0; *c = 0; }
 
+// copy the head of the report block into the pinned host mirror and wait
+hipError_t read_report(mrcm_ctx* c) {
+  hipError_t e = hipMemcpyAsync(c->h_report, c->report, REPORT_HEAD, hipMemcpyDeviceToHost, c->st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->st);
+}
+
 int run_interface(mrcm_ctx* c) {
   hipStream_t st = c->st;
   for (const LevelPlan& lp : c->levels) {
@@ -579,10 +596,16 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
     ALLOC(c, c->ux, (size_t)(G.nx + 1) * G.ny);
     ALLOC(c, c->uy, (size_t)G.nx * (G.ny + 1));
     ALLOC(c, c->sub_stats, 3 * G.n_sub);
-    ALLOC(c, c->result, 8);
-    ALLOC(c, c->status, 1);
-    ALLOC(c, c->fallback, G.n_sub + 1);
-    ALLOC(c, c->ir_iters, 1);
+    ALLOC(c, c->report, RESULT_N + (G.n_sub + 4 + 1) / 2);
+    c->result = c->report;
+    c->status = reinterpret_cast<int*>(c->report + RESULT_N);
+    c->ir_iters = c->status + 1;
+    c->fallback = c->status + 2;
+    {
+      void* h = nullptr;
+      HIPCHK(c, hipHostMalloc(&h, REPORT_HEAD, hipHostMallocDefault));
+      c->h_report = static_cast<double*>(h);
+    }
     c->scratch_stride = local_scratch_doubles(G);
     if (c->scratch_stride > 0) ALLOC(c, c->scratch, (size_t)G.n_sub * c->scratch_stride);
     if (precision == MRCM_PREC_SURROGATE) {
@@ -711,16 +734,10 @@ int solve_impl(mrcm_ctx* c, const float* pred) {
     if (r != MRCM_OK) return r;
   }
   HIPCHK(c, hipEventRecord(c->ev[2], st));
-  int status = 0, nfb = 0, iters = 0;
-  double res[2] = {0.0, 0.0};
-  HIPCHK(c, hipMemcpyAsync(&status, c->status, sizeof(int), hipMemcpyDeviceToHost, st));
-  if (c->g.prec != 0) {
-    HIPCHK(c, hipMemcpyAsync(&nfb, c->fallback, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipMemcpyAsync(&iters, c->ir_iters, sizeof(int), hipMemcpyDeviceToHost, st));
-  }
-  if (c->n_dof > 0)
-    HIPCHK(c, hipMemcpyAsync(res, c->result + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(c, hipStreamSynchronize(st));
+  HIPCHK(c, read_report(c));
+  const int* hi = reinterpret_cast<const int*>(c->h_report + RESULT_N);
+  const int status = hi[0], iters = hi[1], nfb = hi[2];
+  double res[2] = {c->h_report[2], c->h_report[3]};
   // iterative refinement of the interface solve while its residual is above
   // IFACE_IR_TOL of the right-hand side (high contrast with non-polynomial
   // spaces makes the system ill-conditioned); checked at this existing
@@ -730,8 +747,9 @@ int solve_impl(mrcm_ctx* c, const float* pred) {
     int r = refine_interface(c);
     if (r != MRCM_OK) return r;
     HIPCHK(c, hipEventRecord(c->ev[2], st));
-    HIPCHK(c, hipMemcpyAsync(res, c->result + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
+    HIPCHK(c, read_report(c));
+    res[0] = c->h_report[2];
+    res[1] = c->h_report[3];
     c->iface_ir += 1;
   }
   float t1 = 0.f, t2 = 0.f;
@@ -746,9 +764,9 @@ int solve_impl(mrcm_ctx* c, const float* pred) {
     c->stats.ms_surrogate = ts;
   }
   c->stats.interface_residual = res[1] > 0.0 ? res[0] / res[1] : 0.0;
-  c->stats.fallbacks = nfb;
+  c->stats.fallbacks = c->g.prec != 0 ? nfb : 0;
   c->stats.interface_ir_steps = c->iface_ir;
-  c->stats.ir_iters_max = iters;
+  c->stats.ir_iters_max = c->g.prec != 0 ? iters : 0;
   if (status & ST_BAD_LAMBDA) return fail(c, MRCM_E_INVAL, "mobility not finite and positive");
   if (status & (ST_LOCAL_PIVOT | ST_IFACE_PIVOT))
     return fail(c, MRCM_E_NOT_SPD, "non-positive or zero pivot in the elimination");
@@ -782,19 +800,26 @@ int mrcm_fine_flux(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_de
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, c->status);
   HIPCHK(c, hipEventRecord(c->ev[2], st));
   SubArgs a = sub_args(c);
+  // device outputs are written by the kernels in place; host outputs are
+  // copied from the context's buffers
+  if (on_device) {
+    if (p) a.p_out = p;
+    if (ux) a.ux = ux;
+    if (uy) a.uy = uy;
+  }
   HIPCHK(c, launch_stitch(a, st));
   HIPCHK(c, launch_finish_flux(a, c->result, st));
   HIPCHK(c, hipEventRecord(c->ev[3], st));
-  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   const size_t ncell = (size_t)G.nx * G.ny;
-  if (p) HIPCHK(c, hipMemcpyAsync(p, c->p, ncell * sizeof(double), kind, st));
-  if (ux) HIPCHK(c, hipMemcpyAsync(ux, c->ux, (size_t)(G.nx + 1) * G.ny * sizeof(double), kind, st));
-  if (uy) HIPCHK(c, hipMemcpyAsync(uy, c->uy, (size_t)G.nx * (G.ny + 1) * sizeof(double), kind, st));
-  double imb = 0.0;
-  int status = 0;
-  HIPCHK(c, hipMemcpyAsync(&imb, c->result, sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(c, hipMemcpyAsync(&status, c->status, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(c, hipStreamSynchronize(st));
+  if (!on_device) {
+    const hipMemcpyKind kind = hipMemcpyDeviceToHost;
+    if (p) HIPCHK(c, hipMemcpyAsync(p, c->p, ncell * sizeof(double), kind, st));
+    if (ux) HIPCHK(c, hipMemcpyAsync(ux, c->ux, (size_t)(G.nx + 1) * G.ny * sizeof(double), kind, st));
+    if (uy) HIPCHK(c, hipMemcpyAsync(uy, c->uy, (size_t)G.nx * (G.ny + 1) * sizeof(double), kind, st));
+  }
+  HIPCHK(c, read_report(c));
+  const double imb = c->h_report[0];
+  const int status = reinterpret_cast<const int*>(c->h_report + RESULT_N)[0];
   float t = 0.f;
   (void)hipEventElapsedTime(&t, c->ev[2], c->ev[3]);
   c->stats.ms_flux = t;
@@ -901,6 +926,7 @@ void mrcm_destroy(mrcm_ctx* c) {
   if (!c) return;
   if (c->st) (void)hipStreamSynchronize(c->st);
   for (void* q : c->allocs) (void)hipFree(q);
+  if (c->h_report) (void)hipHostFree(c->h_report);
   for (int i = 0; i < 5; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);

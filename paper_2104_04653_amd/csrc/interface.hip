@@ -115,26 +115,27 @@ __device__ inline double readlane_d(double x, int lane) {
 
 // value of lane K of each 16-lane row (DPP row_newbcast, two 32-bit moves)
 template <int K>
-__device__ inline double row_bcast(double x) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(u & 0xffffffffu), 0x150 + K, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x150 + K, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+__device__ inline double row_bcast(double x) {   // one 64-bit DPP row_newbcast move
+  return __longlong_as_double(
+      __builtin_amdgcn_update_dpp(0LL, __double_as_longlong(x), 0x150 + K, 0xF, 0xF, false));
 }
 
 // One Gauss-Jordan sweep with pivot K on a 16 x 16 tile held by one
 // wavefront in the MFMA output layout (lane c + 16 g holds rows 4 v + g of
 // column c in s[v]), no pivoting: the pivot column comes from lane K of the
 // lane's own 16-lane row, the pivot row from lane c + 16 (K % 4).
+// Pivot health is accumulated without branches: pmin = min |pivot|, pnan =
+// sum of pivot * 0 (NaN once a pivot was not finite).
 template <int K>
-__device__ inline void gj16_sweep(d4& s, int c, int g, bool& bad) {
+__device__ inline void gj16_sweep(d4& s, int c, int g, double& pmin, double& pnan) {
   constexpr int kv = K >> 2, kg = K & 3;
   const double p = readlane_d(s[kv], K + 16 * kg);
   const double prow = __shfl(s[kv], c + 16 * kg);
   double pcol[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) pcol[v] = row_bcast<K>(s[v]);
-  if (p == 0.0 || !isfinite(p)) bad = true;
+  pmin = fmin(pmin, fabs(p));
+  pnan = fma(p, 0.0, pnan);
   double ip = __builtin_amdgcn_rcp(p);              // reciprocal estimate, two Newton steps
   ip = fma(ip, fma(-p, ip, 1.0), ip);
   ip = fma(ip, fma(-p, ip, 1.0), ip);
@@ -148,19 +149,22 @@ __device__ inline void gj16_sweep(d4& s, int c, int g, bool& bad) {
 
 template <int K>
 struct GJ16 {
-  static __device__ inline void run(d4& s, int c, int g, bool& bad) {
-    gj16_sweep<K>(s, c, g, bad);
-    GJ16<K + 1>::run(s, c, g, bad);
+  static __device__ inline void run(d4& s, int c, int g, double& pmin, double& pnan) {
+    gj16_sweep<K>(s, c, g, pmin, pnan);
+    GJ16<K + 1>::run(s, c, g, pmin, pnan);
   }
 };
 template <>
 struct GJ16<16> {
-  static __device__ inline void run(d4&, int, int, bool&) {}
+  static __device__ inline void run(d4&, int, int, double&, double&) {}
 };
 
-// In-place inverse of a 16 x 16 tile (output layout) by Gauss-Jordan sweeps.
+// In-place inverse of a 16 x 16 tile (output layout) by Gauss-Jordan sweeps;
+// bad is set if a pivot was zero or not finite.
 __device__ inline d4 gj16(d4 s, int c, int g, bool& bad) {
-  GJ16<0>::run(s, c, g, bad);
+  double pmin = 1.0, pnan = 0.0;
+  GJ16<0>::run(s, c, g, pmin, pnan);
+  if (!(pmin > 0.0) || pnan != 0.0) bad = true;
   return s;
 }
 

@@ -1,5 +1,5 @@
-// One-wavefront-per-subdomain kernels for 16 x 16 subdomains with two
-// pressure and two flux functions per interface (gfx950, FP64 MFMA).
+// Register-tile kernels for 16 x 16 subdomains with two pressure and two
+// flux functions per interface (gfx950, FP64 MFMA).
 //
 // Same method as the generic kernels in local.hip (paper, section 3: local
 // Robin problems of eq. (mrc1), basis functions, traces projected on the
@@ -21,8 +21,13 @@
 //    lanes.  The 16 basis columns fill one MFMA tile; the particular
 //    solution is a second tile with the right-hand side replicated over its
 //    16 columns.
-//  * The 16 inverse blocks and the 16 solution tiles stay in registers for
-//    the backward sweep.
+//  * Two-sided ("twisted") block elimination: one chain eliminates block
+//    rows 0 .. MID-1 downwards, the other rows M-1 .. MID+1 upwards, and
+//    block row MID joins them, which shortens the dependent chain of
+//    Schur-block inversions from 16 to 9.  The FP64 basis and stitch kernels
+//    give each chain its own wavefront; the inverse blocks and solution
+//    tiles of a chain stay in that wavefront's registers for the backward
+//    sweep.
 #include "local_common.h"
 
 namespace mrcm {
@@ -66,27 +71,28 @@ __device__ inline double recip(double p) {
   return fma(r, fma(-p, r, 1.0), r);
 }
 
-// value of lane K of each 16-lane row (DPP row_newbcast, two 32-bit moves)
+// value of lane K of each 16-lane row (one 64-bit DPP row_newbcast move)
 template <int K>
 __device__ inline double row_bcast(double x) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(u & 0xffffffffu), 0x150 + K, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x150 + K, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+  return __longlong_as_double(
+      __builtin_amdgcn_update_dpp(0LL, __double_as_longlong(x), 0x150 + K, 0xF, 0xF, false));
 }
 
 // One Gauss-Jordan sweep with pivot K on a tile in the output layout: the
 // pivot column (row 4 v + g, column K) comes from lane K of the lane's own
-// 16-lane row, the pivot row (row K, column c) from lane c + 16 (K % 4).
+// 16-lane row, the pivot row (row K, column c) from lane c of row K % 4.
+// Pivot health is accumulated without branches: pmin = min of the pivots,
+// pnan = sum of pivot * 0 (NaN once a pivot was not finite).
 template <int K>
-__device__ inline void gj_sweep(d4& s, int c, int g, bool& bad) {
+__device__ inline void gj_sweep(d4& s, int c, int g, double& pmin, double& pnan) {
   constexpr int kv = K >> 2, kg = K & 3;
   const double p = readlane_d(s[kv], K + 16 * kg);
   const double prow = __shfl(s[kv], c + 16 * kg);
   double pcol[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) pcol[v] = row_bcast<K>(s[v]);
-  if (!(p > 0.0) || !isfinite(p)) bad = true;
+  pmin = fmin(pmin, p);
+  pnan = fma(p, 0.0, pnan);
   const double ip = recip(p);
   const double b = (c == K) ? ip : prow * ip;      // new row K
 #pragma unroll
@@ -98,19 +104,29 @@ __device__ inline void gj_sweep(d4& s, int c, int g, bool& bad) {
 
 template <int K>
 struct GJ16 {
-  static __device__ inline void run(d4& s, int c, int g, bool& bad) {
-    gj_sweep<K>(s, c, g, bad);
-    GJ16<K + 1>::run(s, c, g, bad);
+  static __device__ inline void run(d4& s, int c, int g, double& pmin, double& pnan) {
+    gj_sweep<K>(s, c, g, pmin, pnan);
+    GJ16<K + 1>::run(s, c, g, pmin, pnan);
   }
 };
 template <>
 struct GJ16<M> {
-  static __device__ inline void run(d4&, int, int, bool&) {}
+  static __device__ inline void run(d4&, int, int, double&, double&) {}
+};
+
+// Health of all pivots of a kernel's Gauss-Jordan inversions, accumulated
+// without branches (a per-pivot test would keep every pivot live until the
+// kernel's final status write).
+struct PivotCheck {
+  double pmin = 1.0, pnan = 0.0;
+  __device__ bool bad() const { return !(pmin > 0.0) || pnan != 0.0; }
 };
 
 // In-place inverse of the SPD tile s (output layout) by Gauss-Jordan sweeps.
-__device__ inline d4 gauss_jordan16(d4 s, int c, int g, bool& bad) {
-  GJ16<0>::run(s, c, g, bad);
+__device__ inline d4 gauss_jordan16(d4 s, int c, int g, PivotCheck& pc) {
+  GJ16<0>::run(s, c, g, pc.pmin, pc.pnan);
+  // materialise the accumulators here, so that the pivots die with the sweep
+  asm volatile("" : "+v"(pc.pmin), "+v"(pc.pnan));
   return s;
 }
 
@@ -139,140 +155,6 @@ __device__ inline double side_rhs(const double (*bside)[M][D], int lj, int li, i
   const bool on = side == 0 ? li == 0 : side == 1 ? li == M - 1 : side == 2 ? lj == 0 : lj == M - 1;
   const double v = bside[side][side < 2 ? lj : li][k];
   return on ? v : 0.0;
-}
-
-// Two-sided elimination of the 16 Schur blocks (upper chain rows 0..MID-1
-// downwards, lower chain rows M-1..MID+1 upwards, joined at row MID):
-// Sv[j] receives the inverse of row j's Schur-complemented block in its chain.
-__device__ inline void factor_two_sided(d4* Sv, int c, int g, const double* dg, const double* ex,
-                                        const double* cy, bool& bad) {
-  const d4 zero = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int t = 0; t < MID; ++t) {
-    {
-      const int j = t;
-      d4 s = coupled_block(j, j - 1, j > 0 ? Sv[j > 0 ? j - 1 : 0] : zero, c, g, dg, ex, cy);
-      Sv[j] = gauss_jordan16(s, c, g, bad);
-    }
-    if (t < M - 1 - MID) {
-      const int j = M - 1 - t;
-      d4 s = coupled_block(j, j < M - 1 ? j : -1, j < M - 1 ? Sv[j < M - 1 ? j + 1 : j] : zero, c, g,
-                           dg, ex, cy);
-      Sv[j] = gauss_jordan16(s, c, g, bad);
-    }
-  }
-  constexpr int j = MID;
-  d4 s = coupled_block(j, j - 1, Sv[j - 1], c, g, dg, ex, cy);
-#pragma unroll
-  for (int v = 0; v < 4; ++v) s[v] -= cy[j * M + 4 * v + g] * Sv[j + 1][v] * cy[j * M + c];
-  Sv[j] = gauss_jordan16(s, c, g, bad);
-}
-
-// One column solve with the two-sided inverse blocks of factor_two_sided
-// (rhs and result in LDS, cell-major; the column is replicated over the 16
-// MFMA columns and lanes with c == 0 write the result).
-__device__ inline void solve_column_two_sided(const d4* Sv, const double* rhs, double* out, int c,
-                                              int g, const double* cy) {
-  const d4 zero = {0.0, 0.0, 0.0, 0.0};
-  d4 zu = zero, zl = zero;
-#pragma unroll
-  for (int t = 0; t < MID; ++t) {
-    {
-      const int j = t;
-      d4 r;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 4 * v + g;
-        double b = rhs[j * M + row];
-        if (j > 0) b -= cy[(j - 1) * M + row] * zu[v];
-        r[v] = b;
-      }
-      d4 acc = zero;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) acc = mfma(Sv[j][kk], r[kk], acc);
-      zu = acc;
-      if (c == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = acc[v];
-      }
-    }
-    if (t < M - 1 - MID) {
-      const int j = M - 1 - t;
-      d4 r;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 4 * v + g;
-        double b = rhs[j * M + row];
-        if (j < M - 1) b -= cy[j * M + row] * zl[v];
-        r[v] = b;
-      }
-      d4 acc = zero;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) acc = mfma(Sv[j][kk], r[kk], acc);
-      zl = acc;
-      if (c == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = acc[v];
-      }
-    }
-  }
-  {
-    constexpr int j = MID;
-    d4 r;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 4 * v + g;
-      r[v] = rhs[j * M + row] - cy[(j - 1) * M + row] * zu[v] - cy[j * M + row] * zl[v];
-    }
-    d4 acc = zero;
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mfma(Sv[j][kk], r[kk], acc);
-    zu = acc;
-    zl = acc;
-    if (c == 0) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = acc[v];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < MID; ++t) {
-    {
-      const int j = MID - 1 - t;
-      d4 tt, x;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 4 * v + g;
-        tt[v] = -cy[j * M + row] * zu[v];
-        x[v] = out[j * M + row];
-      }
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) x = mfma(Sv[j][kk], tt[kk], x);
-      zu = x;
-      if (c == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = x[v];
-      }
-    }
-    if (t < M - 1 - MID) {
-      const int j = MID + 1 + t;
-      d4 tt, x;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 4 * v + g;
-        tt[v] = -cy[(j - 1) * M + row] * zl[v];
-        x[v] = out[j * M + row];
-      }
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) x = mfma(Sv[j][kk], tt[kk], x);
-      zl = x;
-      if (c == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) out[j * M + 4 * v + g] = x[v];
-      }
-    }
-  }
-  __syncthreads();
 }
 
 // Traces of every column on the skeleton faces (xb: solution in the cells
@@ -350,416 +232,8 @@ __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const
   }
 }
 
-template <bool LIST>
-__global__ void __launch_bounds__(WAVE) basis_m16d4_kernel(SubArgs a) {
-  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM], pz[MM];
-  __shared__ double bside[4][M][D];
-  __shared__ double xb[4][M][R];      // solution next to each side's faces, all columns
-  const Geo& g = a.g;
-  const int lane = threadIdx.x, c = lane & 15, gq = lane >> 4;
-  int sd = blockIdx.x;
-  if (LIST) {   // re-solve only the subdomains listed by the FP32 kernel
-    if ((int)blockIdx.x >= a.fallback[0]) return;
-    sd = a.fallback[1 + blockIdx.x];
-  }
-  const int I = sd % g.SX, J = sd / g.SX;
-
-  load_kappa<M>(a, I, J, kap);
-  __syncthreads();
-  for (int l = lane; l < MM; l += WAVE)
-    assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, b0 + l, 1, nullptr);
-  {
-    // Robin data of the basis columns: bside[side][t][k] = T_R g_k(t)
-    const int side = lane >> 4, t = lane & 15;
-    const int e = side_iface(g, I, J, side);
-    for (int k = 0; k < D; ++k) {
-      double v = 0.0;
-      if (e >= 0) {
-        const SideGeo sg = side_geo(g, side);
-        const double al = a.alpha[e];
-        const double kk = kap[side_cell<M>(side, t)];
-        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
-        const double beta = al * sg.H / kk;
-        double gv = a.basis[((size_t)e * D + k) * M + t];
-        if (k >= g.nP) gv = -beta * side_sigma(side) * gv;
-        v = TR * gv;
-      }
-      bside[side][t][k] = v;
-    }
-  }
-  __syncthreads();
-
-  // Two-sided ("twisted") block elimination: the upper chain eliminates
-  // block rows 0 .. MID-1 downwards, the lower chain rows M-1 .. MID+1
-  // upwards, both in the same unrolled steps so that their latencies
-  // overlap, and block row MID joins them.  Sv[j] holds the inverse of the
-  // Schur-complemented diagonal block of row j in its chain.
-  d4 Sv[M], Xv[M];
-  bool bad = false;
-  const d4 zero = {0.0, 0.0, 0.0, 0.0};
-  d4 zt = zero, zb = zero;   // particular column carried by each chain
-#pragma unroll
-  for (int t = 0; t < MID; ++t) {
-    {
-      const int j = t;   // upper chain
-      d4 s = coupled_block(j, j - 1, j > 0 ? Sv[j > 0 ? j - 1 : 0] : zero, c, gq, dg, ex, cy);
-      s = gauss_jordan16(s, c, gq, bad);
-      Sv[j] = s;
-      d4 r, rp;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 4 * v + gq;
-        double bv = side_rhs(bside, j, row, c), bp = b0[j * M + row];
-        if (j > 0) {
-          const double cc = cy[(j - 1) * M + row];
-          bv -= cc * Xv[j > 0 ? j - 1 : 0][v];
-          bp -= cc * zt[v];
-        }
-        r[v] = bv;
-        rp[v] = bp;
-      }
-      d4 z = zero, zz = zero;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        z = mfma(s[kk], r[kk], z);
-        zz = mfma(s[kk], rp[kk], zz);
-      }
-      Xv[j] = z;
-      zt = zz;
-      if (c == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = zz[v];
-      }
-    }
-    if (t < M - 1 - MID) {
-      const int j = M - 1 - t;   // lower chain
-      d4 s = coupled_block(j, j < M - 1 ? j : -1, j < M - 1 ? Sv[j < M - 1 ? j + 1 : j] : zero, c,
-                           gq, dg, ex, cy);
-      s = gauss_jordan16(s, c, gq, bad);
-      Sv[j] = s;
-      d4 r, rp;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 4 * v + gq;
-        double bv = side_rhs(bside, j, row, c), bp = b0[j * M + row];
-        if (j < M - 1) {
-          const double cc = cy[j * M + row];
-          bv -= cc * Xv[j < M - 1 ? j + 1 : j][v];
-          bp -= cc * zb[v];
-        }
-        r[v] = bv;
-        rp[v] = bp;
-      }
-      d4 z = zero, zz = zero;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        z = mfma(s[kk], r[kk], z);
-        zz = mfma(s[kk], rp[kk], zz);
-      }
-      Xv[j] = z;
-      zb = zz;
-      if (c == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = zz[v];
-      }
-    }
-  }
-  {
-    // joining block row: both neighbours' Schur complements
-    constexpr int j = MID;
-    d4 s = coupled_block(j, j - 1, Sv[j - 1], c, gq, dg, ex, cy);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) s[v] -= cy[j * M + 4 * v + gq] * Sv[j + 1][v] * cy[j * M + c];
-    s = gauss_jordan16(s, c, gq, bad);
-    Sv[j] = s;
-    d4 r, rp;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 4 * v + gq;
-      const double cu = cy[(j - 1) * M + row], cl = cy[j * M + row];
-      r[v] = side_rhs(bside, j, row, c) - cu * Xv[j - 1][v] - cl * Xv[j + 1][v];
-      rp[v] = b0[j * M + row] - cu * zt[v] - cl * zb[v];
-    }
-    d4 z = zero, zz = zero;
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      z = mfma(s[kk], r[kk], z);
-      zz = mfma(s[kk], rp[kk], zz);
-    }
-    Xv[j] = z;
-    zt = zz;
-    zb = zz;
-    if (c == 0) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = zz[v];
-    }
-  }
-  __syncthreads();
-  // back substitution outwards from the joining row
-#pragma unroll
-  for (int t = 0; t < MID; ++t) {
-    {
-      const int j = MID - 1 - t;   // upper chain: X_j = Z_j - S_j^-1 C_j X_{j+1}
-      d4 tt, tp, xp;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 4 * v + gq;
-        const double cc = -cy[j * M + row];
-        tt[v] = cc * Xv[j + 1][v];
-        tp[v] = cc * zt[v];
-        xp[v] = pz[j * M + row];
-      }
-      d4 x = Xv[j];
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        x = mfma(Sv[j][kk], tt[kk], x);
-        xp = mfma(Sv[j][kk], tp[kk], xp);
-      }
-      Xv[j] = x;
-      zt = xp;
-      if (c == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = xp[v];
-      }
-    }
-    if (t < M - 1 - MID) {
-      const int j = MID + 1 + t;   // lower chain: X_j = W_j - T_j^-1 C_{j-1} X_{j-1}
-      d4 tt, tp, xp;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 4 * v + gq;
-        const double cc = -cy[(j - 1) * M + row];
-        tt[v] = cc * Xv[j - 1][v];
-        tp[v] = cc * zb[v];
-        xp[v] = pz[j * M + row];
-      }
-      d4 x = Xv[j];
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        x = mfma(Sv[j][kk], tt[kk], x);
-        xp = mfma(Sv[j][kk], tp[kk], xp);
-      }
-      Xv[j] = x;
-      zb = xp;
-      if (c == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] = xp[v];
-      }
-    }
-  }
-  if (bad) atomicOr(a.status, ST_LOCAL_PIVOT);
-
-  // one step of iterative refinement of all 17 columns: residual
-  // R = B - A X in double-double (block row by block row, the in-row
-  // neighbours through an LDS staging tile), correction by the same
-  // two-sided sweeps with the stored inverse blocks
-  {
-    __shared__ double T[2][M][M + 1];
-    __shared__ double zc[MM], rpz[MM];
-    f4z Zc[M];
-    d4 qt = zero, qb = zero;
-    __syncthreads();
-    // particular column: residual of all cells first (4 cells per lane)
-    for (int l = lane; l < MM; l += WAVE) {
-      const int i = l % M, j = l / M;
-      double ph = b0[l], pl = 0.0;
-      dd_fma(ph, pl, -dg[l], pz[l]);
-      dd_fma(ph, pl, i < M - 1 ? -ex[l] : 0.0, pz[i < M - 1 ? l + 1 : l]);
-      dd_fma(ph, pl, i > 0 ? -ex[l - 1] : 0.0, pz[i > 0 ? l - 1 : l]);
-      dd_fma(ph, pl, j < M - 1 ? -cy[l] : 0.0, pz[j < M - 1 ? l + M : l]);
-      dd_fma(ph, pl, j > 0 ? -cy[l - M] : 0.0, pz[j > 0 ? l - M : l]);
-      rpz[l] = ph + pl;
-    }
-    __syncthreads();
-    auto residual = [&](int j, int h, d4& r, d4& rp) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) T[h][4 * v + gq][c] = Xv[j][v];
-      __syncthreads();
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 4 * v + gq, l = j * M + i;
-        double hi = side_rhs(bside, j, i, c), lo = 0.0;
-        dd_fma(hi, lo, -dg[l], Xv[j][v]);
-        dd_fma(hi, lo, i < M - 1 ? -ex[l] : 0.0, T[h][i < M - 1 ? i + 1 : i][c]);
-        dd_fma(hi, lo, i > 0 ? -ex[i > 0 ? l - 1 : l] : 0.0, T[h][i > 0 ? i - 1 : i][c]);
-        if (j < M - 1) dd_fma(hi, lo, -cy[l], Xv[j < M - 1 ? j + 1 : j][v]);
-        if (j > 0) dd_fma(hi, lo, -cy[l - M], Xv[j > 0 ? j - 1 : 0][v]);
-        r[v] = hi + lo;
-        rp[v] = rpz[l];
-      }
-    };
-#pragma unroll
-    for (int ju = 0; ju < MID; ++ju) {
-      d4 ru, rpu;
-      residual(ju, 0, ru, rpu);
-      __syncthreads();
-      if (ju > 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double cc = cy[(ju - 1) * M + 4 * v + gq];
-          ru[v] -= cc * (double)Zc[ju > 0 ? ju - 1 : 0][v];
-          rpu[v] -= cc * qt[v];
-        }
-      }
-      d4 z = zero, zz = zero;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        z = mfma(Sv[ju][kk], ru[kk], z);
-        zz = mfma(Sv[ju][kk], rpu[kk], zz);
-      }
-      Zc[ju] = tof(z);
-      qt = zz;
-      if (c == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) zc[ju * M + 4 * v + gq] = zz[v];
-      }
-    }
-#pragma unroll
-    for (int jl = M - 1; jl > MID; --jl) {
-      d4 rl, rpl;
-      residual(jl, 1, rl, rpl);
-      __syncthreads();
-      if (jl < M - 1) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double cc = cy[jl * M + 4 * v + gq];
-          rl[v] -= cc * (double)Zc[jl < M - 1 ? jl + 1 : jl][v];
-          rpl[v] -= cc * qb[v];
-        }
-      }
-      d4 z = zero, zz = zero;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        z = mfma(Sv[jl][kk], rl[kk], z);
-        zz = mfma(Sv[jl][kk], rpl[kk], zz);
-      }
-      Zc[jl] = tof(z);
-      qb = zz;
-      if (c == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) zc[jl * M + 4 * v + gq] = zz[v];
-      }
-    }
-    {
-      constexpr int j = MID;
-      d4 r, rp;
-      residual(j, 0, r, rp);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double cu = cy[(j - 1) * M + 4 * v + gq], cl = cy[j * M + 4 * v + gq];
-        r[v] -= cu * (double)Zc[j - 1][v] + cl * (double)Zc[j + 1][v];
-        rp[v] -= cu * qt[v] + cl * qb[v];
-      }
-      d4 z = zero, zz = zero;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        z = mfma(Sv[j][kk], r[kk], z);
-        zz = mfma(Sv[j][kk], rp[kk], zz);
-      }
-      Zc[j] = tof(z);
-      qt = zz;
-      qb = zz;
-      if (c == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) zc[j * M + 4 * v + gq] = zz[v];
-      }
-    }
-    __syncthreads();
-    Xv[MID] += tod(Zc[MID]);
-    if (c == 0) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) pz[MID * M + 4 * v + gq] += qt[v];
-    }
-    d4 cu = tod(Zc[MID]), cl = tod(Zc[MID]);
-#pragma unroll
-    for (int t = 0; t < MID; ++t) {
-      {
-        const int j = MID - 1 - t;
-        d4 tt, tq, xq;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = 4 * v + gq;
-          const double cc = -cy[j * M + i];
-          tt[v] = cc * cu[v];
-          tq[v] = cc * qt[v];
-          xq[v] = zc[j * M + i];
-        }
-        d4 x = tod(Zc[j]);
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          x = mfma(Sv[j][kk], tt[kk], x);
-          xq = mfma(Sv[j][kk], tq[kk], xq);
-        }
-        cu = x;
-        qt = xq;
-        Xv[j] += x;
-        if (c == 0) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] += xq[v];
-        }
-      }
-      if (t < M - 1 - MID) {
-        const int j = MID + 1 + t;
-        d4 tt, tq, xq;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = 4 * v + gq;
-          const double cc = -cy[(j - 1) * M + i];
-          tt[v] = cc * cl[v];
-          tq[v] = cc * qb[v];
-          xq[v] = zc[j * M + i];
-        }
-        d4 x = tod(Zc[j]);
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          x = mfma(Sv[j][kk], tt[kk], x);
-          xq = mfma(Sv[j][kk], tq[kk], xq);
-        }
-        cl = x;
-        qb = xq;
-        Xv[j] += x;
-        if (c == 0) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) pz[j * M + 4 * v + gq] += xq[v];
-        }
-      }
-    }
-    __syncthreads();
-  }
-
-  // basis functions to global memory, column-major per subdomain
-  double* Xg = a.X + (size_t)sd * R * MM;
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Xg[(size_t)(1 + c) * MM + j * M + 4 * v + gq] = Xv[j][v];
-  }
-  // cells next to the skeleton faces, for the traces
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    if (gq == 0) xb[0][j][1 + c] = Xv[j][0];
-    if (gq == 3) xb[1][j][1 + c] = Xv[j][3];
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    xb[2][4 * v + gq][1 + c] = Xv[0][v];
-    xb[3][4 * v + gq][1 + c] = Xv[M - 1][v];
-  }
-  __syncthreads();
-  for (int l = lane; l < MM; l += WAVE) Xg[l] = pz[l];
-  if (lane < M) {
-    xb[0][lane][0] = pz[lane * M];
-    xb[1][lane][0] = pz[lane * M + M - 1];
-    xb[2][lane][0] = pz[lane];
-    xb[3][lane][0] = pz[(M - 1) * M + lane];
-  }
-  __syncthreads();
-
-  write_block(a, sd, I, J, kap, xb);
-}
-
 // ---------------------------------------------------------------------------
-// The same solve by two wavefronts per subdomain: wave 0 eliminates block
+// Basis functions by two wavefronts per subdomain: wave 0 eliminates block
 // rows 0..MID-1 downwards and solves the joining row MID, wave 1 eliminates
 // rows M-1..MID+1 upwards.  Each wavefront keeps only its own rows' inverse
 // blocks and solution tiles in registers, so two wavefronts fit on a SIMD,
@@ -780,7 +254,10 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
   __shared__ double xs[2][M][M + 1];   // exchange tiles; per-wave staging
   __shared__ double zc[MM], rpz[MM];
   const Geo& g = a.g;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, c = lane & 15, gq = lane >> 4;
+  // the wave index is uniform per wavefront: taken into a scalar register,
+  // so that row offsets that depend on it are scalar too
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63, c = lane & 15, gq = lane >> 4;
   int sd = blockIdx.x;
   if (LIST) {   // re-solve only the subdomains on the fallback list
     if ((int)blockIdx.x >= a.fallback[0]) return;
@@ -816,7 +293,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
   const d4 zero = {0.0, 0.0, 0.0, 0.0};
   const int nchain = w ? NL : MID;   // rows eliminated before the join
   d4 Sv[NU], Xv[NU];
-  bool bad = false;
+  PivotCheck pvc;
   d4 pc = zero;   // particular column carried along the chain
 #pragma unroll
   for (int t = 0; t < MID; ++t) {
@@ -824,7 +301,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
       const int j = w ? M - 1 - t : t;
       const int jc = w ? j : j - 1;     // coupling towards the chain's previous row
       d4 s = coupled_block(j, t > 0 ? jc : -1, t > 0 ? Sv[t > 0 ? t - 1 : 0] : zero, c, gq, dg, ex, cy);
-      s = gauss_jordan16(s, c, gq, bad);
+      s = gauss_jordan16(s, c, gq, pvc);
       Sv[t] = s;
       d4 r, rp;
 #pragma unroll
@@ -875,7 +352,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
       r[v] = side_rhs(bside, j, row, c) - cu * Xv[MID - 1][v] - cl * xs[1][row][c];
       rp[v] = b0[j * M + row] - cu * pc[v] - cl * pz[(j + 1) * M + row];
     }
-    s = gauss_jordan16(s, c, gq, bad);
+    s = gauss_jordan16(s, c, gq, pvc);
     Sv[MID] = s;
     d4 z = zero, zz = zero;
 #pragma unroll
@@ -933,7 +410,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
       }
     }
   }
-  if (bad) atomicOr(a.status, ST_LOCAL_PIVOT);
+  if (pvc.bad()) atomicOr(a.status, ST_LOCAL_PIVOT);
 
   // one step of iterative refinement of all 17 columns (residual in
   // double-double, correction by the same two-chain sweeps)
@@ -1141,7 +618,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
 // and the joining row MID, wave 1: rows M-1..MID+1, index t = row M-1-t);
 // xch is an LDS tile for the hand-over at the join.  Both waves must call.
 __device__ inline void factor_pair(d4* Sv, int w, int c, int g, const double* dg, const double* ex,
-                                   const double* cy, double (*xch)[M + 1], bool& bad) {
+                                   const double* cy, double (*xch)[M + 1], PivotCheck& pvc) {
   const d4 zero = {0.0, 0.0, 0.0, 0.0};
   const int nchain = w ? NL : MID;
 #pragma unroll
@@ -1150,7 +627,7 @@ __device__ inline void factor_pair(d4* Sv, int w, int c, int g, const double* dg
       const int j = w ? M - 1 - t : t;
       const int jc = w ? j : j - 1;
       d4 s = coupled_block(j, t > 0 ? jc : -1, t > 0 ? Sv[t > 0 ? t - 1 : 0] : zero, c, g, dg, ex, cy);
-      Sv[t] = gauss_jordan16(s, c, g, bad);
+      Sv[t] = gauss_jordan16(s, c, g, pvc);
     }
   }
   if (w == 1) {
@@ -1163,7 +640,7 @@ __device__ inline void factor_pair(d4* Sv, int w, int c, int g, const double* dg
     d4 s = coupled_block(j, j - 1, Sv[MID - 1], c, g, dg, ex, cy);
 #pragma unroll
     for (int v = 0; v < 4; ++v) s[v] -= cy[j * M + 4 * v + g] * xch[4 * v + g][c] * cy[j * M + c];
-    Sv[MID] = gauss_jordan16(s, c, g, bad);
+    Sv[MID] = gauss_jordan16(s, c, g, pvc);
   }
   __syncthreads();
 }
@@ -1279,16 +756,20 @@ __device__ inline float row_bcast_f(float x) {
 // One FP32 Gauss-Jordan sweep with pivot K (f32 output layout: lane c + 16 g
 // holds rows 4 g .. 4 g + 3 of column c): the pivot column comes from lane K
 // of the lane's own 16-lane row, the pivot row from lane c + 16 (K / 4).
+// 1/p is the hardware reciprocal (1 ulp in FP32; the refinement in FP64
+// absorbs it).  pmin accumulates the smallest pivot (NaN-free pivots that are
+// all positive leave it positive; a NaN pivot makes it NaN through pnan).
 template <int K>
-__device__ inline void gj_sweep_f32(f4& s, int c, int g, bool& bad) {
+__device__ inline void gj_sweep_f32(f4& s, int c, int g, float& pmin, float& pnan) {
   constexpr int kg = K >> 2, kv = K & 3;
   const float p = readlane_f(s[kv], K + 16 * kg);
   const float prow = __shfl(s[kv], c + 16 * kg);
   float pcol[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) pcol[v] = row_bcast_f<K>(s[v]);
-  if (!(p > 0.0f)) bad = true;
-  const float ip = 1.0f / p;
+  pmin = fminf(pmin, p);
+  pnan = fmaf(p, 0.0f, pnan);
+  const float ip = __builtin_amdgcn_rcpf(p);
   const float b = (c == K) ? ip : prow * ip;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -1299,18 +780,19 @@ __device__ inline void gj_sweep_f32(f4& s, int c, int g, bool& bad) {
 
 template <int K>
 struct GJ16F {
-  static __device__ inline void run(f4& s, int c, int g, bool& bad) {
-    gj_sweep_f32<K>(s, c, g, bad);
-    GJ16F<K + 1>::run(s, c, g, bad);
+  static __device__ inline void run(f4& s, int c, int g, float& pmin, float& pnan) {
+    gj_sweep_f32<K>(s, c, g, pmin, pnan);
+    GJ16F<K + 1>::run(s, c, g, pmin, pnan);
   }
 };
 template <>
 struct GJ16F<M> {
-  static __device__ inline void run(f4&, int, int, bool&) {}
+  static __device__ inline void run(f4&, int, int, float&, float&) {}
 };
 
-__device__ inline f4 gauss_jordan16_f32(f4 s, int c, int g, bool& bad) {
-  GJ16F<0>::run(s, c, g, bad);
+__device__ inline f4 gauss_jordan16_f32(f4 s, int c, int g, float& pmin, float& pnan) {
+  GJ16F<0>::run(s, c, g, pmin, pnan);
+  asm volatile("" : "+v"(pmin), "+v"(pnan));
   return s;
 }
 
@@ -1319,80 +801,22 @@ __device__ inline double chat(const double* cy, const double* dsc, int j, int i)
   return cy[j * M + i] * dsc[j * M + i] * dsc[(j + 1) * M + i];
 }
 
-// In-place solve of A^ W = W for the 16 basis columns (FP32, f32 output layout)
-__device__ inline void solve32_tiles(const f4* Sv, f4* W, int gq, const double* cy,
-                                     const double* dsc) {
+// scaled diagonal block of row j (unit diagonal) minus C P C with C the
+// scaled coupling of row jc (jc < 0: none), f32 output layout
+__device__ inline f4 coupled_block32(int j, int jc, const f4& P, int c, int gq, const double* ex,
+                                     const double* cy, const double* dsc) {
+  f4 s;
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
-    f4 r = W[j];
-    if (j > 0) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) r[v] -= (float)chat(cy, dsc, j - 1, 4 * gq + v) * W[j > 0 ? j - 1 : 0][v];
-    }
-    f4 z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) z = mfma32(Sv[j][kk], r[kk], z);
-    W[j] = z;
+  for (int v = 0; v < 4; ++v) {
+    const int row = 4 * gq + v, l = j * M + row;
+    const double d = (row == c) ? 1.0
+                   : (row == c + 1) ? ex[j * M + c] * dsc[j * M + c] * dsc[l]
+                   : (c == row + 1) ? ex[l] * dsc[l] * dsc[j * M + c] : 0.0;
+    float sv = (float)d;
+    if (jc >= 0) sv -= (float)chat(cy, dsc, jc, row) * P[v] * (float)chat(cy, dsc, jc, c);
+    s[v] = sv;
   }
-#pragma unroll
-  for (int j = M - 2; j >= 0; --j) {
-    f4 t;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) t[v] = -(float)chat(cy, dsc, j, 4 * gq + v) * W[j + 1][v];
-    f4 x = W[j];
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) x = mfma32(Sv[j][kk], t[kk], x);
-    W[j] = x;
-  }
-}
-
-// the same for one column held in LDS (cell-major), replicated over the
-// 16 MFMA columns; `zs` is an LDS work array
-__device__ inline void solve32_col(const f4* Sv, float* col, float* zs, int c, int gq,
-                                   const double* cy, const double* dsc) {
-  f4 z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    f4 r;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = 4 * gq + v;
-      r[v] = col[j * M + i];
-      if (j > 0) r[v] -= (float)chat(cy, dsc, j - 1, i) * z[v];
-    }
-    f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mfma32(Sv[j][kk], r[kk], acc);
-    z = acc;
-    if (c == 0) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) zs[j * M + 4 * gq + v] = z[v];
-    }
-  }
-  __syncthreads();
-  f4 xn = z;
-  if (c == 0) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) col[(M - 1) * M + 4 * gq + v] = xn[v];
-  }
-#pragma unroll
-  for (int j = M - 2; j >= 0; --j) {
-    f4 t, x;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = 4 * gq + v;
-      t[v] = -(float)chat(cy, dsc, j, i) * xn[v];
-      x[v] = zs[j * M + i];
-    }
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) x = mfma32(Sv[j][kk], t[kk], x);
-    xn = x;
-    if (c == 0) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) col[j * M + 4 * gq + v] = x[v];
-    }
-  }
-  __syncthreads();
+  return s;
 }
 
 __device__ inline double wave_max(double v) {
@@ -1401,22 +825,227 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-__global__ void __launch_bounds__(WAVE) basis32_m16d4_kernel(SubArgs a) {
-  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM], dsc[MM], px[MM];
-  __shared__ double bside[4][M][D];
-  __shared__ double T[M][M + 1];
-  __shared__ float pcol[MM], pzs[MM];
-  __shared__ double xb[4][M][R];
+// Rows of the two elimination chains: wave W = 0 owns block rows 0..MID
+// (index t = row) and solves the joining row MID, wave W = 1 owns rows
+// M-1..MID+1 (index t = M-1-row).  Instantiating the per-wave code for each
+// W makes every row index a compile-time constant (LDS offsets fold into the
+// instructions, no per-row branches).
+template <int W>
+struct Chain {
+  static constexpr int NR = W ? NL : NU;   // rows the wave owns
+  static constexpr int NC = W ? NL : MID;  // rows it eliminates before the join
+  static constexpr int row(int t) { return W ? M - 1 - t : t; }
+  // coupling (row of cy) towards the previous row of the chain / the join
+  static constexpr int cprev(int t) { return W ? M - 1 - t : t - 1; }
+  static constexpr int cnext(int t) { return W ? M - 2 - t : t; }
+};
+
+// LDS of the FP32 + refinement kernel
+struct Lds32 {
+  double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM], dsc[MM], px[MM];
+  double bside[4][M][D];
+  double xb[4][M][R];
+  double T[2][M][M + 1];    // per-wave staging of in-row neighbours
+  double xj[2][M][M + 1];   // solution tiles next to the join
+  float xf[M][M + 1];       // FP32 hand-over tile at the join
+  float pcol[MM];           // particular column (FP32 right-hand side / solution)
+  double red[2][2];
+  int bad[2];               // per wave: a pivot of its chain was not positive
+};
+
+// FP32 inverse Schur blocks of the scaled matrix along the wave's chain; the
+// joining row is inverted by wave 0.  Both waves call.
+template <int W>
+__device__ inline void factor32(f4* Sv, Lds32& sh, int c, int gq, float& pmin, float& pnan) {
+  using C = Chain<W>;
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < C::NC; ++t) {
+    const f4 s = coupled_block32(C::row(t), t > 0 ? C::cprev(t) : -1, t > 0 ? Sv[t > 0 ? t - 1 : 0] : zero,
+                                 c, gq, sh.ex, sh.cy, sh.dsc);
+    Sv[t] = gauss_jordan16_f32(s, c, gq, pmin, pnan);
+  }
+  if (W == 1) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sh.xf[4 * gq + v][c] = Sv[NL - 1][v];
+  }
+  __syncthreads();
+  if (W == 0) {
+    constexpr int j = MID;
+    f4 s = coupled_block32(j, j - 1, Sv[MID - 1], c, gq, sh.ex, sh.cy, sh.dsc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * gq + v;
+      s[v] -= (float)chat(sh.cy, sh.dsc, j, row) * sh.xf[row][c] * (float)chat(sh.cy, sh.dsc, j, c);
+    }
+    Sv[MID] = gauss_jordan16_f32(s, c, gq, pmin, pnan);
+  }
+  __syncthreads();
+}
+
+// Two-chain FP32 solve of the scaled system.  rhs(t) gives the 16 basis
+// right-hand-side tile of the wave's row t; it is called in chain order, just
+// before the row is eliminated (so a residual can be formed row by row).
+// Wt[t] receives the solution.  sh.pcol: the particular right-hand side on
+// entry, its solution on return (a second MFMA tile with the column
+// replicated over its 16 columns; lanes with c == 0 write it).  Both waves
+// call.
+template <int W, class Rhs>
+__device__ inline void solve32(const f4* Sv, f4* Wt, Lds32& sh, int c, int gq, Rhs rhs) {
+  using C = Chain<W>;
+  const double* cy = sh.cy;
+  const double* dsc = sh.dsc;
+  float* pcol = sh.pcol;
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+  f4 pc = zero;
+#pragma unroll
+  for (int t = 0; t < C::NC; ++t) {
+    const int j = C::row(t);
+    f4 r = rhs(t), rp;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * gq + v;
+      rp[v] = pcol[j * M + row];
+      if (t > 0) {
+        const float cc = (float)chat(cy, dsc, C::cprev(t), row);
+        r[v] -= cc * Wt[t > 0 ? t - 1 : 0][v];
+        rp[v] -= cc * pc[v];
+      }
+    }
+    f4 z = zero, zz = zero;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      z = mfma32(Sv[t][kk], r[kk], z);
+      zz = mfma32(Sv[t][kk], rp[kk], zz);
+    }
+    Wt[t] = z;
+    pc = zz;
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pcol[j * M + 4 * gq + v] = zz[v];
+    }
+  }
+  if (W == 1) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sh.xf[4 * gq + v][c] = Wt[NL - 1][v];
+  }
+  __syncthreads();
+  if (W == 0) {
+    constexpr int j = MID;
+    f4 r = rhs(MID), rp;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * gq + v;
+      const float cu = (float)chat(cy, dsc, j - 1, row), cl = (float)chat(cy, dsc, j, row);
+      r[v] -= cu * Wt[MID - 1][v] + cl * sh.xf[row][c];
+      rp[v] = pcol[j * M + row] - cu * pc[v] - cl * pcol[(j + 1) * M + row];
+    }
+    f4 z = zero, zz = zero;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      z = mfma32(Sv[MID][kk], r[kk], z);
+      zz = mfma32(Sv[MID][kk], rp[kk], zz);
+    }
+    Wt[MID] = z;
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pcol[j * M + 4 * gq + v] = zz[v];
+    }
+  }
+  __syncthreads();
+  if (W == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sh.xf[4 * gq + v][c] = Wt[MID][v];
+  }
+  __syncthreads();
+  f4 xp;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    xp[v] = W == 0 ? Wt[MID][v] : sh.xf[4 * gq + v][c];
+    pc[v] = pcol[MID * M + 4 * gq + v];
+  }
+#pragma unroll
+  for (int t = C::NC - 1; t >= 0; --t) {
+    const int j = C::row(t);
+    f4 tt, tp, xq;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * gq + v;
+      const float cc = -(float)chat(cy, dsc, C::cnext(t), row);
+      tt[v] = cc * xp[v];
+      tp[v] = cc * pc[v];
+      xq[v] = pcol[j * M + row];
+    }
+    f4 x = Wt[t];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      x = mfma32(Sv[t][kk], tt[kk], x);
+      xq = mfma32(Sv[t][kk], tp[kk], xq);
+    }
+    Wt[t] = x;
+    xp = x;
+    pc = xq;
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pcol[j * M + 4 * gq + v] = xq[v];
+    }
+  }
+  __syncthreads();
+}
+
+// FP64 residual of the basis columns in the wave's row t, scaled and rounded
+// to FP32 (the tile of the other wave next to the join must be in sh.xj).
+template <int W>
+__device__ inline f4 residual32_row(int t, const d4* Xv, Lds32& sh, int c, int gq) {
+  using C = Chain<W>;
+  const int j = C::row(t);
+  double (*T)[M + 1] = sh.T[W];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) T[4 * gq + v][c] = Xv[t][v];
+  __builtin_amdgcn_wave_barrier();
+  f4 w;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    // every load unconditional (indices clamped): the selects stay branch-free
+    const int i = 4 * gq + v, l = j * M + i;
+    const int ir = i < M - 1 ? i + 1 : i, il = i > 0 ? i - 1 : i;
+    const double exr = sh.ex[l], exl = sh.ex[j * M + il];
+    const double xr = T[ir][c], xl = T[il][c];
+    double r = side_rhs(sh.bside, j, i, c);
+    r = fma(-sh.dg[l], Xv[t][v], r);
+    r = fma(i < M - 1 ? -exr : 0.0, xr, r);
+    r = fma(i > 0 ? -exl : 0.0, xl, r);
+    if (t > 0) r = fma(-sh.cy[C::cprev(t) * M + i], Xv[t > 0 ? t - 1 : 0][v], r);
+    const double xn = (t + 1 < C::NR) ? Xv[t + 1 < C::NR ? t + 1 : t][v] : sh.xj[1 - W][i][c];
+    r = fma(-sh.cy[C::cnext(t) * M + i], xn, r);
+    w[v] = (float)(sh.dsc[l] * r);
+  }
+  __builtin_amdgcn_wave_barrier();
+  return w;
+}
+
+// FP32 factorisation + FP64 iterative refinement, two wavefronts per
+// subdomain with the chains of basis_pair_kernel.  The local matrix is scaled
+// symmetrically (Ds A Ds, Ds = diag(A)^-1/2, unit diagonal); the inverse
+// Schur blocks and the correction solves are FP32 (MFMA with FP32
+// accumulation), the solution and the residuals FP64.  Refinement stops when
+// the largest correction is below IR_DONE of the largest solution value; a
+// subdomain that ends above IR_ACCEPT, or met a bad pivot, is listed for the
+// FP64 re-solve.
+template <int W>
+__device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
+  using C = Chain<W>;
   const Geo& g = a.g;
-  const int lane = threadIdx.x, c = lane & 15, gq = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, c = lane & 15, gq = lane >> 4;
   const int sd = blockIdx.x;
   const int I = sd % g.SX, J = sd / g.SX;
 
-  load_kappa<M>(a, I, J, kap);
+  load_kappa<M>(a, I, J, sh.kap);
   __syncthreads();
-  for (int l = lane; l < MM; l += WAVE)
-    assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, b0 + l, 1, nullptr);
-  {
+  for (int l = tid; l < MM; l += PAIR)
+    assemble_cell<M, 1, false>(a, I, J, l, sh.kap, sh.dg, sh.ex, sh.cy, sh.b0 + l, 1, nullptr);
+  if (W == 0) {
+    // Robin data of the basis columns: bside[side][t][k] = T_R g_k(t)
     const int side = lane >> 4, t = lane & 15;
     const int e = side_iface(g, I, J, side);
     for (int k = 0; k < D; ++k) {
@@ -1424,126 +1053,104 @@ __global__ void __launch_bounds__(WAVE) basis32_m16d4_kernel(SubArgs a) {
       if (e >= 0) {
         const SideGeo sg = side_geo(g, side);
         const double al = a.alpha[e];
-        const double kk = kap[side_cell<M>(side, t)];
+        const double kk = sh.kap[side_cell<M>(side, t)];
         const double TR = sg.flen * kk / (sg.dist + al * sg.H);
         const double beta = al * sg.H / kk;
         double gv = a.basis[((size_t)e * D + k) * M + t];
         if (k >= g.nP) gv = -beta * side_sigma(side) * gv;
         v = TR * gv;
       }
-      bside[side][t][k] = v;
+      sh.bside[side][t][k] = v;
     }
   }
   __syncthreads();
-  for (int l = lane; l < MM; l += WAVE) dsc[l] = 1.0 / sqrt(dg[l]);
+  for (int l = tid; l < MM; l += PAIR) sh.dsc[l] = 1.0 / sqrt(sh.dg[l]);
   __syncthreads();
 
-  // FP32 inverse Schur blocks of the scaled matrix
-  f4 Sv[M];
-  bool bad = false;
-  {
-    f4 prev = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      f4 s;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 4 * gq + v, l = j * M + row;
-        const double d = (row == c) ? 1.0
-                       : (row == c + 1) ? ex[j * M + c] * dsc[j * M + c] * dsc[l]
-                       : (c == row + 1) ? ex[l] * dsc[l] * dsc[j * M + c] : 0.0;
-        float sv = (float)d;
-        if (j > 0) sv -= (float)chat(cy, dsc, j - 1, row) * prev[v] * (float)chat(cy, dsc, j - 1, c);
-        s[v] = sv;
-      }
-      s = gauss_jordan16_f32(s, c, gq, bad);
-      Sv[j] = s;
-      prev = s;
-    }
-  }
+  f4 Sv[C::NR];
+  float pmin = 1.0f, pnan = 0.0f;
+  factor32<W>(Sv, sh, c, gq, pmin, pnan);
+  if (lane == 0) sh.bad[W] = !(pmin > 0.0f) || pnan != 0.0f;
 
   // first solve: X = Ds A^-1 Ds B
-  d4 Xv[M];
-  f4 W[M];
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
+  f4 Wt[C::NR];
+  d4 Xv[C::NR];
+  for (int l = tid; l < MM; l += PAIR) sh.pcol[l] = (float)(sh.dsc[l] * sh.b0[l]);
+  __syncthreads();
+  const bool bad = sh.bad[0] || sh.bad[1];
+  solve32<W>(Sv, Wt, sh, c, gq, [&](int t) {
+    const int j = C::row(t);
+    f4 w;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = 4 * gq + v;
-      W[j][v] = (float)(dsc[j * M + row] * side_rhs(bside, j, row, c));
+      w[v] = (float)(sh.dsc[j * M + row] * side_rhs(sh.bside, j, row, c));
     }
-  }
-  for (int l = lane; l < MM; l += WAVE) pcol[l] = (float)(dsc[l] * b0[l]);
-  __syncthreads();
-  solve32_tiles(Sv, W, gq, cy, dsc);
-  solve32_col(Sv, pcol, pzs, c, gq, cy, dsc);
+    return w;
+  });
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
+  for (int t = 0; t < C::NR; ++t) {
+    const int j = C::row(t);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Xv[j][v] = dsc[j * M + 4 * gq + v] * (double)W[j][v];
+    for (int v = 0; v < 4; ++v) Xv[t][v] = sh.dsc[j * M + 4 * gq + v] * (double)Wt[t][v];
   }
-  for (int l = lane; l < MM; l += WAVE) px[l] = dsc[l] * (double)pcol[l];
+  for (int l = tid; l < MM; l += PAIR) sh.px[l] = sh.dsc[l] * (double)sh.pcol[l];
   __syncthreads();
 
   // refinement: FP64 residual, FP32 correction
   int used = 0;
   double rel = 1.0;
+#pragma unroll 1
   for (int it = 0; it < IR_MAX; ++it) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) T[4 * gq + v][c] = Xv[j][v];
-      __syncthreads();
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 4 * gq + v, l = j * M + i;
-        double r = side_rhs(bside, j, i, c);
-        r = fma(-dg[l], Xv[j][v], r);
-        if (i < M - 1) r = fma(-ex[l], T[i + 1][c], r);
-        if (i > 0) r = fma(-ex[l - 1], T[i - 1][c], r);
-        if (j < M - 1) r = fma(-cy[l], Xv[j < M - 1 ? j + 1 : j][v], r);
-        if (j > 0) r = fma(-cy[l - M], Xv[j > 0 ? j - 1 : 0][v], r);
-        W[j][v] = (float)(dsc[l] * r);
-      }
-      __syncthreads();
-    }
-    for (int l = lane; l < MM; l += WAVE) {
+    for (int v = 0; v < 4; ++v) sh.xj[W][4 * gq + v][c] = Xv[C::NR - 1][v];
+    __syncthreads();
+    for (int l = tid; l < MM; l += PAIR) {
       const int li = l % M, lj = l / M;
-      double r = fma(-dg[l], px[l], b0[l]);
-      if (li < M - 1) r = fma(-ex[l], px[l + 1], r);
-      if (li > 0) r = fma(-ex[l - 1], px[l - 1], r);
-      if (lj < M - 1) r = fma(-cy[l], px[l + M], r);
-      if (lj > 0) r = fma(-cy[l - M], px[l - M], r);
-      pcol[l] = (float)(dsc[l] * r);
+      const int le = li < M - 1 ? l + 1 : l, lw = li > 0 ? l - 1 : l;
+      const int ln = lj < M - 1 ? l + M : l, ls = lj > 0 ? l - M : l;
+      double r = fma(-sh.dg[l], sh.px[l], sh.b0[l]);
+      r = fma(li < M - 1 ? -sh.ex[l] : 0.0, sh.px[le], r);
+      r = fma(li > 0 ? -sh.ex[lw] : 0.0, sh.px[lw], r);
+      r = fma(lj < M - 1 ? -sh.cy[l] : 0.0, sh.px[ln], r);
+      r = fma(lj > 0 ? -sh.cy[ls] : 0.0, sh.px[ls], r);
+      sh.pcol[l] = (float)(sh.dsc[l] * r);
     }
     __syncthreads();
-    solve32_tiles(Sv, W, gq, cy, dsc);
-    solve32_col(Sv, pcol, pzs, c, gq, cy, dsc);
+    solve32<W>(Sv, Wt, sh, c, gq, [&](int t) { return residual32_row<W>(t, Xv, sh, c, gq); });
     double cmax = 0.0, xmax = 0.0;
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
+    for (int t = 0; t < C::NR; ++t) {
+      const int j = C::row(t);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const double dx = dsc[j * M + 4 * gq + v] * (double)W[j][v];
-        Xv[j][v] += dx;
+        const double dx = sh.dsc[j * M + 4 * gq + v] * (double)Wt[t][v];
+        Xv[t][v] += dx;
         cmax = fmax(cmax, fabs(dx));
-        xmax = fmax(xmax, fabs(Xv[j][v]));
+        xmax = fmax(xmax, fabs(Xv[t][v]));
       }
     }
-    for (int l = lane; l < MM; l += WAVE) {
-      const double dx = dsc[l] * (double)pcol[l];
-      px[l] += dx;
+    for (int l = tid; l < MM; l += PAIR) {
+      const double dx = sh.dsc[l] * (double)sh.pcol[l];
+      sh.px[l] += dx;
       cmax = fmax(cmax, fabs(dx));
-      xmax = fmax(xmax, fabs(px[l]));
+      xmax = fmax(xmax, fabs(sh.px[l]));
     }
-    __syncthreads();
     cmax = wave_max(cmax);
     xmax = wave_max(xmax);
+    if (lane == 0) {
+      sh.red[W][0] = cmax;
+      sh.red[W][1] = xmax;
+    }
+    __syncthreads();
+    cmax = fmax(sh.red[0][0], sh.red[1][0]);
+    xmax = fmax(sh.red[0][1], sh.red[1][1]);
+    __syncthreads();
     used = it + 1;
     rel = cmax / fmax(xmax, 1e-300);
     if (rel <= IR_DONE) break;
   }
-  if (lane == 0) {
+  if (W == 0 && tid == 0) {
     atomicMax(a.ir_iters, used);
     if (bad || !(rel <= IR_ACCEPT)) {
       const int q = atomicAdd(a.fallback, 1);
@@ -1554,34 +1161,34 @@ __global__ void __launch_bounds__(WAVE) basis32_m16d4_kernel(SubArgs a) {
   // basis functions to global memory (f32 layout: rows 4gq .. 4gq+3 of column c)
   double* Xg = a.X + (size_t)sd * R * MM;
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
+  for (int t = 0; t < C::NR; ++t) {
+    const int j = C::row(t);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Xg[(size_t)(1 + c) * MM + j * M + 4 * gq + v] = Xv[j][v];
+    for (int v = 0; v < 4; ++v) Xg[(size_t)(1 + c) * MM + j * M + 4 * gq + v] = Xv[t][v];
+    if (gq == 0) sh.xb[0][j][1 + c] = Xv[t][0];
+    if (gq == 3) sh.xb[1][j][1 + c] = Xv[t][3];
   }
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
-    if (gq == 0) xb[0][j][1 + c] = Xv[j][0];
-    if (gq == 3) xb[1][j][1 + c] = Xv[j][3];
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    xb[2][4 * gq + v][1 + c] = Xv[0][v];
-    xb[3][4 * gq + v][1 + c] = Xv[M - 1][v];
+  for (int v = 0; v < 4; ++v) sh.xb[W ? 3 : 2][4 * gq + v][1 + c] = Xv[0][v];
+  for (int l = tid; l < MM; l += PAIR) Xg[l] = sh.px[l];
+  if (tid < M) {
+    sh.xb[0][tid][0] = sh.px[tid * M];
+    sh.xb[1][tid][0] = sh.px[tid * M + M - 1];
+    sh.xb[2][tid][0] = sh.px[tid];
+    sh.xb[3][tid][0] = sh.px[(M - 1) * M + tid];
   }
   __syncthreads();
-  for (int l = lane; l < MM; l += WAVE) Xg[l] = px[l];
-  if (lane < M) {
-    xb[0][lane][0] = px[lane * M];
-    xb[1][lane][0] = px[lane * M + M - 1];
-    xb[2][lane][0] = px[lane];
-    xb[3][lane][0] = px[(M - 1) * M + lane];
-  }
-  __syncthreads();
-  write_block(a, sd, I, J, kap, xb);
+  write_block(a, sd, I, J, sh.kap, sh.xb);
+}
+
+__global__ void __launch_bounds__(PAIR, 2) basis32_pair_kernel(SubArgs a) {
+  __shared__ Lds32 sh;
+  if (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0) basis32_body<0>(a, sh);
+  else basis32_body<1>(a, sh);
 }
 
 // ---------------------------------------------------------------------------
-// stitch re-solve for 16 x 16 subdomains (one wavefront per subdomain)
+// stitch re-solve for 16 x 16 subdomains (two wavefronts per subdomain)
 // ---------------------------------------------------------------------------
 
 __device__ inline double compose16(const SubArgs& a, int sd, int l) {
@@ -1597,147 +1204,6 @@ __device__ inline double compose16(const SubArgs& a, int sd, int l) {
   return p;
 }
 
-__global__ void __launch_bounds__(WAVE) stitch_m16d4_kernel(SubArgs a) {
-  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
-  __shared__ double pm[MM], bs_[MM], ps[MM], rs[MM], dx[MM];
-  __shared__ double Fout[4][M];
-  __shared__ double red[3][WAVE];
-  const Geo& g = a.g;
-  const int lane = threadIdx.x, c = lane & 15, gq = lane >> 4;
-  const int sd = blockIdx.x;
-  const int I = sd % g.SX, J = sd / g.SX;
-  const int nP = g.nP;
-
-  load_kappa<M>(a, I, J, kap);
-  for (int l = lane; l < MM; l += WAVE) pm[l] = compose16(a, sd, l);
-  __syncthreads();
-  {
-    // one-sided Robin fluxes on both sides of each skeleton face; outflow
-    // of this subdomain = their average
-    const int side = lane >> 4, t = lane & 15;
-    const int e = side_iface(g, I, J, side);
-    double fo = 0.0;
-    if (e >= 0) {
-      const SideGeo sg = side_geo(g, side);
-      const double al = a.alpha[e];
-      const double* bsf = a.basis + (size_t)e * D * M;
-      const double* ce = a.coef + (size_t)e * D;
-      double PH = 0.0, UH = 0.0;
-      for (int k = 0; k < nP; ++k) PH += ce[k] * bsf[k * M + t];
-      for (int k = nP; k < D; ++k) UH += ce[k] * bsf[k * M + t];
-      const int l = side_cell<M>(side, t);
-      const double sig = side_sigma(side);
-      const double ko = kap[l];
-      const double Fown = sg.flen * ko / (sg.dist + al * sg.H) *
-                          (pm[l] - (PH - al * sg.H / ko * sig * UH));
-      const int nside = side ^ 1;
-      const int nsd = (side == 0) ? sd - 1 : (side == 1) ? sd + 1 : (side == 2) ? sd - g.SX : sd + g.SX;
-      const int nI = nsd % g.SX, nJ = nsd / g.SX;
-      const int nl = side_cell<M>(nside, t);
-      const size_t nc = (size_t)(nJ * M + nl / M) * g.nx + nI * M + nl % M;
-      const double kn = a.K[nc] * a.lam[nc];
-      const double pn = compose16(a, nsd, nl);
-      const double Fnb = sg.flen * kn / (sg.dist + al * sg.H) *
-                         (pn - (PH - al * sg.H / kn * (-sig) * UH));
-      fo = 0.5 * (Fown - Fnb);
-    }
-    Fout[side][t] = fo;
-  }
-  __syncthreads();
-  for (int l = lane; l < MM; l += WAVE)
-    assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, bs_ + l, 0, Fout);
-  __syncthreads();
-  const bool dir = (I == 0 && g.kind[0] == 1) || (I == g.SX - 1 && g.kind[1] == 1) ||
-                   (J == 0 && g.kind[2] == 1) || (J == g.SY - 1 && g.kind[3] == 1);
-  if (!dir && lane == 0) {
-    const double tp = dg[0];
-    dg[0] += tp;
-    bs_[0] += tp * pm[0];
-  }
-  __syncthreads();
-
-  d4 Sv[M];
-  bool bad = false;
-  factor_two_sided(Sv, c, gq, dg, ex, cy, bad);
-  if (bad) atomicOr(a.status, ST_STITCH_PIVOT);
-  solve_column_two_sided(Sv, bs_, ps, c, gq, cy);
-  // iterative refinement with the stored inverse blocks, residual in
-  // double-double
-  for (int it = 0; it < 3; ++it) {
-    for (int l = lane; l < MM; l += WAVE) {
-      const int li = l % M, lj = l / M;
-      double hi = bs_[l], lo = 0.0;
-      dd_fma(hi, lo, -dg[l], ps[l]);
-      if (li < M - 1) dd_fma(hi, lo, -ex[l], ps[l + 1]);
-      if (li > 0) dd_fma(hi, lo, -ex[l - 1], ps[l - 1]);
-      if (lj < M - 1) dd_fma(hi, lo, -cy[l], ps[l + M]);
-      if (lj > 0) dd_fma(hi, lo, -cy[l - M], ps[l - M]);
-      rs[l] = hi + lo;
-    }
-    __syncthreads();
-    solve_column_two_sided(Sv, rs, dx, c, gq, cy);
-    for (int l = lane; l < MM; l += WAVE) ps[l] += dx[l];
-    __syncthreads();
-  }
-
-  double imb = 0.0, fmx = 0.0, psum = 0.0;
-  for (int l = lane; l < MM; l += WAVE) {
-    const int li = l % M, lj = l / M;
-    const int i = I * M + li, j = J * M + lj;
-    const double kc = kap[l];
-    const double txc = kc * g.hy / (0.5 * g.hx), tyc = kc * g.hx / (0.5 * g.hy);
-    const double pv = ps[l];
-    double F[4];
-    for (int side = 0; side < 4; ++side) {
-      const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
-      double out;
-      if (inner) {
-        const int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
-        const double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
-        out = series2(side < 2 ? txc : tyc, tn) * (pv - ps[nb]);
-      } else {
-        const int e = side_iface(g, I, J, side);
-        const int t = (side < 2) ? lj : li;
-        if (e >= 0) {
-          out = Fout[side][t];
-        } else {
-          const double flen = (side < 2) ? g.hy : g.hx;
-          const double v = a.bcv[side][(side < 2) ? j : i];
-          out = (g.kind[side] == 1) ? ((side < 2) ? txc : tyc) * (pv - v) : v * flen;
-        }
-      }
-      F[side] = (side == 0 || side == 2) ? -out : out;
-    }
-    a.ux[(size_t)j * (g.nx + 1) + i] = F[0] / g.hy;
-    if (li == M - 1 && I == g.SX - 1) a.ux[(size_t)j * (g.nx + 1) + i + 1] = F[1] / g.hy;
-    a.uy[(size_t)j * g.nx + i] = F[2] / g.hx;
-    if (lj == M - 1 && J == g.SY - 1) a.uy[(size_t)(j + 1) * g.nx + i] = F[3] / g.hx;
-    const double q = a.src ? a.src[(size_t)j * g.nx + i] * g.hx * g.hy : 0.0;
-    const double net = F[1] - F[0] + F[3] - F[2];
-    imb = fmax(imb, fabs(net - q));
-    fmx = fmax(fmx, fmax(fmax(fabs(F[0]), fabs(F[1])), fmax(fabs(F[2]), fabs(F[3]))));
-    a.p_out[(size_t)j * g.nx + i] = pm[l];
-    psum += pm[l];
-  }
-  red[0][lane] = imb;
-  red[1][lane] = fmx;
-  red[2][lane] = psum;
-  __syncthreads();
-  for (int w = WAVE / 2; w > 0; w >>= 1) {
-    if (lane < w) {
-      red[0][lane] = fmax(red[0][lane], red[0][lane + w]);
-      red[1][lane] = fmax(red[1][lane], red[1][lane + w]);
-      red[2][lane] = red[2][lane] + red[2][lane + w];
-    }
-    __syncthreads();
-  }
-  if (lane == 0) {
-    a.sub_stats[3 * sd + 0] = red[0][0];
-    a.sub_stats[3 * sd + 1] = red[1][0];
-    a.sub_stats[3 * sd + 2] = red[2][0];
-  }
-}
-
 __global__ void __launch_bounds__(PAIR) stitch_pair_kernel(SubArgs a) {
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
   __shared__ double pm[MM], bs_[MM], ps[MM], rs[MM], dx[MM];
@@ -1745,7 +1211,10 @@ __global__ void __launch_bounds__(PAIR) stitch_pair_kernel(SubArgs a) {
   __shared__ double red[3][PAIR];
   __shared__ double xch[M][M + 1];
   const Geo& g = a.g;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, c = lane & 15, gq = lane >> 4;
+  // the wave index is uniform per wavefront: taken into a scalar register,
+  // so that row offsets that depend on it are scalar too
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63, c = lane & 15, gq = lane >> 4;
   const int sd = blockIdx.x;
   const int I = sd % g.SX, J = sd / g.SX;
   const int nP = g.nP;
@@ -1799,9 +1268,9 @@ __global__ void __launch_bounds__(PAIR) stitch_pair_kernel(SubArgs a) {
   __syncthreads();
 
   d4 Sv[NU];
-  bool bad = false;
-  factor_pair(Sv, w, c, gq, dg, ex, cy, xch, bad);
-  if (bad) atomicOr(a.status, ST_STITCH_PIVOT);
+  PivotCheck pvc;
+  factor_pair(Sv, w, c, gq, dg, ex, cy, xch, pvc);
+  if (pvc.bad()) atomicOr(a.status, ST_STITCH_PIVOT);
   solve_column_pair(Sv, w, bs_, ps, c, gq, cy);
   // iterative refinement with the stored inverse blocks, residual in
   // double-double
@@ -2068,7 +1537,7 @@ hipError_t launch_basis_m16d4_list(const SubArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_basis32_m16d4(const SubArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(basis32_m16d4_kernel, dim3(a.g.n_sub), dim3(WAVE), 0, st, a);
+  hipLaunchKernelGGL(basis32_pair_kernel, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
   return hipGetLastError();
 }
 

@@ -95,7 +95,7 @@ hipError_t launch_stitch(const SubArgs& a, hipStream_t st);
 hipError_t launch_mobility(const double* in, double* lam, size_t n, int from_saturation,
                            double mu_w, double mu_o, hipStream_t st);
 hipError_t launch_finish_flux(const SubArgs& a, double* result, hipStream_t st);
-// (local_mfma.hip) one wavefront per 16 x 16 subdomain, 2 + 2 interface dofs
+// (local_mfma.hip) 16 x 16 subdomains, 2 + 2 interface dofs (FP64: two wavefronts per subdomain)
 hipError_t launch_basis_m16d4(const SubArgs& a, hipStream_t st);
 // FP32 factors and solves with FP64 iterative refinement; subdomains that do
 // not converge are listed in a.fallback and re-solved by the FP64 kernel

@@ -174,6 +174,7 @@ class MRCMSolver:
         fluid = Fluid(float(prob.mu_w), float(prob.mu_o))
         ctx = ctypes.c_void_p()
         st = _current_stream() if stream is None else ctypes.c_void_p(stream)
+        self._stream = st.value
         rc = self.lib.mrcm_setup(ctypes.byref(ctx), ctypes.byref(grid), _dptr(perm),
                                  int(prob.sub_nx), int(prob.sub_ny), SPACES[prob.space],
                                  int(prob.p_dofs), int(prob.u_dofs),
@@ -222,7 +223,9 @@ class MRCMSolver:
                 raise ValueError("device mobility must be a contiguous float64 tensor of nx*ny")
             self._dev_in = values   # keep alive until the next solve
             import torch
-            torch.cuda.current_stream().synchronize()   # producer work is complete
+            cur = torch.cuda.current_stream()
+            if cur.cuda_stream != self._stream:
+                cur.synchronize()   # producer work on another stream is complete
             rc = self.lib.mrcm_update_mobility(self.ctx, ctypes.c_void_p(values.data_ptr()),
                                                int(is_lambda), 1)
         else:
