@@ -132,7 +132,12 @@ constexpr int RESULT_N = 8;
 constexpr size_t REPORT_HEAD = RESULT_N * sizeof(double) + 3 * sizeof(int);
 
 constexpr int IFACE_IR_MAX = 3;         // refinement steps of the interface solve
-constexpr double IFACE_IR_TOL = 1e-14;  // max|r| / max|b| that needs no refinement
+// max|r| / max|b| of the interface system that needs no refinement: near the
+// FP64 floor for FP64 local solves; for FP32 + refinement, whose local
+// solutions are converged to about 1e-10 relative, a residual 1e-12 of the
+// right-hand side is already below what its inputs resolve
+constexpr double IFACE_IR_TOL_FP64 = 1e-14;
+constexpr double IFACE_IR_TOL_FP32 = 1e-12;
 
 // ---------------------------------------------------------------------------
 // interface spaces (section 3.1), tabulated per interface on its fine faces
@@ -739,11 +744,12 @@ int solve_impl(mrcm_ctx* c, const float* pred) {
   const int status = hi[0], iters = hi[1], nfb = hi[2];
   double res[2] = {c->h_report[2], c->h_report[3]};
   // iterative refinement of the interface solve while its residual is above
-  // IFACE_IR_TOL of the right-hand side (high contrast with non-polynomial
+  // ir_tol of the right-hand side (high contrast with non-polynomial
   // spaces makes the system ill-conditioned); checked at this existing
   // synchronisation, so a well-conditioned solve pays nothing for it
   c->iface_ir = 0;
-  while (c->n_dof > 0 && c->iface_ir < IFACE_IR_MAX && res[0] > IFACE_IR_TOL * res[1]) {
+  const double ir_tol = c->g.prec == 1 ? IFACE_IR_TOL_FP32 : IFACE_IR_TOL_FP64;
+  while (c->n_dof > 0 && c->iface_ir < IFACE_IR_MAX && res[0] > ir_tol * res[1]) {
     int r = refine_interface(c);
     if (r != MRCM_OK) return r;
     HIPCHK(c, hipEventRecord(c->ev[2], st));

@@ -157,21 +157,20 @@ __device__ inline double side_rhs(const double (*bside)[M][D], int lj, int li, i
   return on ? v : 0.0;
 }
 
-// Traces of every column on the skeleton faces (xb: solution in the cells
-// next to each side's faces) projected on the interface functions: the
-// subdomain's block of the interface system, rows of flux dofs negated
-// (symmetric form), last column = right-hand side.
-__device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const double* kap,
-                                   const double (*xb)[M][R]) {
+// Per skeleton face (side, t) of a subdomain: Robin transmissibility T_R,
+// beta = alpha H / kappa and beta / |f| (all 0 on the domain boundary), and
+// the interface functions of the side.  Computed once per kernel by the first
+// 4 M threads; used by the Robin right-hand sides and by write_block.
+struct Faces {
+  double tr[4][M], bt[4][M], bl[4][M];
+  double phi[4][D][M];
+};
+
+__device__ inline void prepare_faces(const SubArgs& a, int I, int J, const double* kap, Faces& f) {
   const Geo& g = a.g;
-  const int lane = threadIdx.x;
-  constexpr int NBR = 4 * D, NBC = 4 * D + 1;
-  // per skeleton face (one of the first 64 threads each): Robin
-  // transmissibility T_R, beta and beta / |f|, and the interface functions
-  // of its side
-  __shared__ double trf[4][M], btf[4][M], bfl[4][M], phi[4][D][M];
-  if (lane < 4 * M) {
-    const int side = lane >> 4, t = lane & 15;
+  const int l = threadIdx.x;
+  if (l < 4 * M) {
+    const int side = l >> 4, t = l & 15;
     const int e = side_iface(g, I, J, side);
     double tr = 0.0, bt = 0.0, bl = 0.0;
     if (e >= 0) {
@@ -182,13 +181,38 @@ __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const
       bt = al * sg.H / kk;
       bl = bt / sg.flen;
     }
-    trf[side][t] = tr;
-    btf[side][t] = bt;
-    bfl[side][t] = bl;
+    f.tr[side][t] = tr;
+    f.bt[side][t] = bt;
+    f.bl[side][t] = bl;
 #pragma unroll
-    for (int k = 0; k < D; ++k) phi[side][k][t] = e >= 0 ? a.basis[((size_t)e * D + k) * M + t] : 0.0;
+    for (int k = 0; k < D; ++k) f.phi[side][k][t] = e >= 0 ? a.basis[((size_t)e * D + k) * M + t] : 0.0;
   }
-  __syncthreads();
+}
+
+// Robin data of the basis columns, bside[side][t][k] = T_R g_k(t) (flux
+// functions scaled by -beta sigma), from the face data (first 4 M threads).
+__device__ inline void robin_data(const Geo& g, const Faces& f, double (*bside)[M][D]) {
+  const int l = threadIdx.x;
+  if (l < 4 * M) {
+    const int side = l >> 4, t = l & 15;
+    const double sig = side_sigma(side);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double ph = f.phi[side][k][t];
+      bside[side][t][k] = f.tr[side][t] * (k < g.nP ? ph : -f.bt[side][t] * sig * ph);
+    }
+  }
+}
+
+// Traces of every column on the skeleton faces (xb: solution in the cells
+// next to each side's faces) projected on the interface functions: the
+// subdomain's block of the interface system, rows of flux dofs negated
+// (symmetric form), last column = right-hand side.  One (side, column) pair
+// per thread, the D rows of that side accumulated together.
+__device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const Faces& f,
+                                   const double (*xb)[M][R]) {
+  const Geo& g = a.g;
+  constexpr int NBR = 4 * D, NBC = 4 * D + 1;
   double* blk = a.blocks + (size_t)sd * NBR * NBC;
   const int nP = g.nP;
   int e0side = -1;
@@ -197,38 +221,46 @@ __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const
     for (int side = 0; side < 4; ++side)
       if (side_iface(g, I, J, side) == 0) { e0side = side; e0lo = side_sigma(side) > 0; }
   }
-  for (int o = lane; o < NBR * NBC; o += blockDim.x) {
-    const int r = o / NBC, qc = o % NBC;
-    const int side = r / D, k = r % D;
+  for (int pr = threadIdx.x; pr < 4 * NBC; pr += blockDim.x) {
+    const int side = pr / NBC, qc = pr % NBC;
     const int e = side_iface(g, I, J, side);
-    double val = 0.0;
+    double acc[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] = 0.0;
+    const double sig = side_sigma(side);
     if (e >= 0) {
       const int col = (qc < NBR) ? 1 + qc : 0;
-      const double sig = side_sigma(side);
       const bool colside = col >= 1 + side * D && col < 1 + side * D + D;
       const int kc = colside ? col - 1 - side * D : 0;
       const bool flux_col = colside && kc >= nP;
       const double gscale = colside ? 1.0 : 0.0;
-      double sum = 0.0;
 #pragma unroll 4
       for (int t = 0; t < M; ++t) {
-        const double ph = phi[side][kc][t];
-        const double gv = gscale * (flux_col ? -btf[side][t] * sig * ph : ph);
-        const double F = trf[side][t] * (xb[side][t][col] - gv);
-        const double w = (k < nP) ? F : fma(bfl[side][t], F, gv);
-        sum = fma(phi[side][k][t], w, sum);
-      }
-      const SideGeo sg = side_geo(g, side);
-      const double natural = (k < nP) ? sum : sig * sg.flen * sum;
-      const double sgn = (k < nP) ? 1.0 : -1.0;
-      val = (qc < NBR) ? sgn * natural : -sgn * natural;
-      if (e0side >= 0) {
-        const int r0 = e0side * D;
-        if (r == r0) val = (qc == r0 && e0lo) ? 1.0 : 0.0;
-        else if (qc == r0) val = 0.0;
+        const double ph = f.phi[side][kc][t];
+        const double gv = gscale * (flux_col ? -f.bt[side][t] * sig * ph : ph);
+        const double F = f.tr[side][t] * (xb[side][t][col] - gv);
+        const double wu = fma(f.bl[side][t], F, gv);
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = fma(f.phi[side][k][t], k < nP ? F : wu, acc[k]);
       }
     }
-    blk[o] = val;
+    const double flen = side_geo(g, side).flen;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int r = side * D + k;
+      double val = 0.0;
+      if (e >= 0) {
+        const double natural = (k < nP) ? acc[k] : sig * flen * acc[k];
+        const double sgn = (k < nP) ? 1.0 : -1.0;
+        val = (qc < NBR) ? sgn * natural : -sgn * natural;
+        if (e0side >= 0) {
+          const int r0 = e0side * D;
+          if (r == r0) val = (qc == r0 && e0lo) ? 1.0 : 0.0;
+          else if (qc == r0) val = 0.0;
+        }
+      }
+      blk[r * NBC + qc] = val;
+    }
   }
 }
 
@@ -249,6 +281,7 @@ constexpr int NL = M - 1 - MID;   // rows of wave 1: M-1 .. MID+1 (index t is ro
 template <bool LIST>
 __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM], pz[MM];
+  __shared__ Faces fc;
   __shared__ double bside[4][M][D];
   __shared__ double xb[4][M][R];
   __shared__ double xs[2][M][M + 1];   // exchange tiles; per-wave staging
@@ -269,25 +302,9 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
   __syncthreads();
   for (int l = tid; l < MM; l += PAIR)
     assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, b0 + l, 1, nullptr);
-  if (tid < 4 * M) {
-    // Robin data of the basis columns: bside[side][t][k] = T_R g_k(t)
-    const int side = lane >> 4, t = lane & 15;
-    const int e = side_iface(g, I, J, side);
-    for (int k = 0; k < D; ++k) {
-      double v = 0.0;
-      if (e >= 0) {
-        const SideGeo sg = side_geo(g, side);
-        const double al = a.alpha[e];
-        const double kk = kap[side_cell<M>(side, t)];
-        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
-        const double beta = al * sg.H / kk;
-        double gv = a.basis[((size_t)e * D + k) * M + t];
-        if (k >= g.nP) gv = -beta * side_sigma(side) * gv;
-        v = TR * gv;
-      }
-      bside[side][t][k] = v;
-    }
-  }
+  prepare_faces(a, I, J, kap, fc);
+  __syncthreads();
+  robin_data(g, fc, bside);
   __syncthreads();
 
   const d4 zero = {0.0, 0.0, 0.0, 0.0};
@@ -586,16 +603,29 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
   }
   __syncthreads();
 
-  // basis functions to global memory, column-major per subdomain
+  // basis functions to global memory, column-major per subdomain: each
+  // row tile is transposed through the wave's LDS tile so that every store
+  // instruction writes four whole 128-byte column segments
   double* Xg = a.X + (size_t)sd * R * MM;
+  {
+    double (*Tt)[M + 1] = xs[w];
+    const int ci = lane & 15, q0 = lane >> 4;
 #pragma unroll
-  for (int t = 0; t < NU; ++t) {
-    if (t < nchain || (w == 0 && t == MID)) {
-      const int j = w ? M - 1 - t : t;
+    for (int t = 0; t < NU; ++t) {
+      if (t < nchain || (w == 0 && t == MID)) {
+        const int j = w ? M - 1 - t : t;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Xg[(size_t)(1 + c) * MM + j * M + 4 * v + gq] = Xv[t][v];
-      if (gq == 0) xb[0][j][1 + c] = Xv[t][0];
-      if (gq == 3) xb[1][j][1 + c] = Xv[t][3];
+        for (int v = 0; v < 4; ++v) Tt[4 * v + gq][c] = Xv[t][v];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int q = q0 + 4 * s4;
+          Xg[(size_t)(1 + q) * MM + j * M + ci] = Tt[ci][q];
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (gq == 0) xb[0][j][1 + c] = Xv[t][0];
+        if (gq == 3) xb[1][j][1 + c] = Xv[t][3];
+      }
     }
   }
 #pragma unroll
@@ -611,7 +641,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
     xb[3][tid][0] = pz[(M - 1) * M + tid];
   }
   __syncthreads();
-  write_block(a, sd, I, J, kap, xb);
+  write_block(a, sd, I, J, fc, xb);
 }
 
 // Two-wavefront elimination of the 16 Schur blocks (wave 0: rows 0..MID-1
@@ -732,13 +762,16 @@ __device__ inline void solve_column_pair(const d4* Sv, int w, const double* rhs,
 // rows 4g .. 4g+3 of column c in lane c + 16 g (measured on the device).  The
 // solution is kept in FP64; every refinement step forms R = B - A X in FP64,
 // solves A^ y = Ds R in FP32 and adds Ds y.  A subdomain whose correction does
-// not fall below 1e-10 of its solution within IR_MAX steps, or whose FP32
-// pivots fail, is appended to a.fallback and re-solved in FP64.
+// not fall below IR_DONE of its solution within IR_MAX steps, or whose FP32
+// pivots fail, is appended to a.fallback and re-solved in FP64.  The error
+// left after a step is about the contraction factor times that step's
+// correction, so IR_DONE = 1e-9 leaves local errors near 1e-11 (the target of
+// this path is 1e-8 against FP64).
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int IR_MAX = 8;
-constexpr double IR_DONE = 1e-12;     // relative size of the last correction: converged
-constexpr double IR_ACCEPT = 1e-10;   // ... accepted without the FP64 fallback
+constexpr double IR_DONE = 1e-9;      // relative size of the last correction: converged
+constexpr double IR_ACCEPT = 1e-9;    // ... accepted without the FP64 fallback
 
 __device__ inline float readlane_f(float x, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
@@ -845,6 +878,7 @@ struct Lds32 {
   double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM], dsc[MM], px[MM];
   double bside[4][M][D];
   double xb[4][M][R];
+  Faces fc;
   double T[2][M][M + 1];    // per-wave staging of in-row neighbours
   double xj[2][M][M + 1];   // solution tiles next to the join
   float xf[M][M + 1];       // FP32 hand-over tile at the join
@@ -1044,27 +1078,10 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
   __syncthreads();
   for (int l = tid; l < MM; l += PAIR)
     assemble_cell<M, 1, false>(a, I, J, l, sh.kap, sh.dg, sh.ex, sh.cy, sh.b0 + l, 1, nullptr);
-  if (W == 0) {
-    // Robin data of the basis columns: bside[side][t][k] = T_R g_k(t)
-    const int side = lane >> 4, t = lane & 15;
-    const int e = side_iface(g, I, J, side);
-    for (int k = 0; k < D; ++k) {
-      double v = 0.0;
-      if (e >= 0) {
-        const SideGeo sg = side_geo(g, side);
-        const double al = a.alpha[e];
-        const double kk = sh.kap[side_cell<M>(side, t)];
-        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
-        const double beta = al * sg.H / kk;
-        double gv = a.basis[((size_t)e * D + k) * M + t];
-        if (k >= g.nP) gv = -beta * side_sigma(side) * gv;
-        v = TR * gv;
-      }
-      sh.bside[side][t][k] = v;
-    }
-  }
-  __syncthreads();
+  prepare_faces(a, I, J, sh.kap, sh.fc);
   for (int l = tid; l < MM; l += PAIR) sh.dsc[l] = 1.0 / sqrt(sh.dg[l]);
+  __syncthreads();
+  robin_data(g, sh.fc, sh.bside);
   __syncthreads();
 
   f4 Sv[C::NR];
@@ -1178,7 +1195,7 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
     sh.xb[3][tid][0] = sh.px[(M - 1) * M + tid];
   }
   __syncthreads();
-  write_block(a, sd, I, J, sh.kap, sh.xb);
+  write_block(a, sd, I, J, sh.fc, sh.xb);
 }
 
 __global__ void __launch_bounds__(PAIR, 2) basis32_pair_kernel(SubArgs a) {
@@ -1436,6 +1453,7 @@ __global__ void __launch_bounds__(WAVE) surrogate_targets_kernel(SubArgs a, floa
 __global__ void __launch_bounds__(WAVE) surrogate_gate_kernel(SubArgs a, const float* pred) {
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM];
   __shared__ double bside[4][M][D];
+  __shared__ Faces fc;
   __shared__ double xb[4][M][R];
   __shared__ double Xs[4 * D][MM];
   __shared__ double scale[4 * D];
@@ -1449,24 +1467,9 @@ __global__ void __launch_bounds__(WAVE) surrogate_gate_kernel(SubArgs a, const f
     assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, b0 + l, 1, nullptr);
   const double kgeo = exp(mean_log_kappa(kap));
   if (lane < 4 * D) scale[lane] = column_scale(a, I, J, lane, kgeo);
-  {
-    const int side = lane >> 4, t = lane & 15;
-    const int e = side_iface(g, I, J, side);
-    for (int k = 0; k < D; ++k) {
-      double v = 0.0;
-      if (e >= 0) {
-        const SideGeo sg = side_geo(g, side);
-        const double al = a.alpha[e];
-        const double kk = kap[side_cell<M>(side, t)];
-        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
-        const double beta = al * sg.H / kk;
-        double gv = a.basis[((size_t)e * D + k) * M + t];
-        if (k >= g.nP) gv = -beta * side_sigma(side) * gv;
-        v = TR * gv;
-      }
-      bside[side][t][k] = v;
-    }
-  }
+  prepare_faces(a, I, J, kap, fc);
+  __syncthreads();
+  robin_data(g, fc, bside);
   __syncthreads();
   bool particular = false;
   for (int l = lane; l < MM; l += WAVE) particular |= b0[l] != 0.0;
@@ -1521,7 +1524,7 @@ __global__ void __launch_bounds__(WAVE) surrogate_gate_kernel(SubArgs a, const f
     xb[side][t][col] = v;
   }
   __syncthreads();
-  write_block(a, sd, I, J, kap, xb);
+  write_block(a, sd, I, J, fc, xb);
 }
 
 }  // namespace
