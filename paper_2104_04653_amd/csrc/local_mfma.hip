@@ -1208,16 +1208,23 @@ __global__ void __launch_bounds__(PAIR, 2) basis32_pair_kernel(SubArgs a) {
 // stitch re-solve for 16 x 16 subdomains (two wavefronts per subdomain)
 // ---------------------------------------------------------------------------
 
-__device__ inline double compose16(const SubArgs& a, int sd, int l) {
-  const Geo& g = a.g;
-  const int I = sd % g.SX, J = sd / g.SX;
+// interface coefficient of basis column q of subdomain (I, J) (0 for a side
+// on the domain boundary, whose basis columns are zero)
+__device__ inline double column_coef(const SubArgs& a, int I, int J, int q) {
+  const int e = side_iface(a.g, I, J, q / D);
+  return e >= 0 ? a.coef[(size_t)e * D + q % D] : 0.0;
+}
+
+// composed pressure p = X [1; c] at cell l of subdomain sd, coefficients cf
+// of its 4 D basis columns; all loads are issued unconditionally
+__device__ inline double compose16(const SubArgs& a, int sd, int l, const double* cf) {
   const double* xr = a.X + (size_t)sd * R * MM + l;
+  double x[4 * D];
+#pragma unroll
+  for (int q = 0; q < 4 * D; ++q) x[q] = xr[(size_t)(1 + q) * MM];
   double p = xr[0];
-  for (int side = 0; side < 4; ++side) {
-    const int e = side_iface(g, I, J, side);
-    if (e < 0) continue;
-    for (int k = 0; k < D; ++k) p += xr[(size_t)(1 + side * D + k) * MM] * a.coef[(size_t)e * D + k];
-  }
+#pragma unroll
+  for (int q = 0; q < 4 * D; ++q) p = fma(x[q], cf[q], p);
   return p;
 }
 
@@ -1236,35 +1243,48 @@ __global__ void __launch_bounds__(PAIR) stitch_pair_kernel(SubArgs a) {
   const int I = sd % g.SX, J = sd / g.SX;
   const int nP = g.nP;
 
+  __shared__ double cfs[4 * D];
+  if (tid < 4 * D) cfs[tid] = column_coef(a, I, J, tid);
+  // the neighbour's side of each skeleton face (first 4 M threads): its
+  // composed pressure and mobility next to the face, loaded before this
+  // subdomain's own pressure so that both sets of loads are in flight together
+  const int side = lane >> 4, t = lane & 15;
+  const int e = tid < 4 * M ? side_iface(g, I, J, side) : -1;
+  double pn = 0.0, kn = 1.0, al = 0.0, PH = 0.0, UH = 0.0;
+  if (e >= 0) {
+    // interface data of the face: alpha and the interface pressure / flux
+    // P_H, U_H = sum of coefficient times interface function
+    al = a.alpha[e];
+    const double* bsf = a.basis + (size_t)e * D * M;
+    const double* ce = a.coef + (size_t)e * D;
+    for (int k = 0; k < nP; ++k) PH += ce[k] * bsf[k * M + t];
+    for (int k = nP; k < D; ++k) UH += ce[k] * bsf[k * M + t];
+    const int nside = side ^ 1;
+    const int nsd = (side == 0) ? sd - 1 : (side == 1) ? sd + 1 : (side == 2) ? sd - g.SX : sd + g.SX;
+    const int nI = nsd % g.SX, nJ = nsd / g.SX;
+    const int nl = side_cell<M>(nside, t);
+    const size_t nc = (size_t)(nJ * M + nl / M) * g.nx + nI * M + nl % M;
+    kn = a.K[nc] * a.lam[nc];
+    double cfn[4 * D];
+#pragma unroll
+    for (int q = 0; q < 4 * D; ++q) cfn[q] = column_coef(a, nI, nJ, q);
+    pn = compose16(a, nsd, nl, cfn);
+  }
   load_kappa<M>(a, I, J, kap);
-  for (int l = tid; l < MM; l += PAIR) pm[l] = compose16(a, sd, l);
+  __syncthreads();
+  for (int l = tid; l < MM; l += PAIR) pm[l] = compose16(a, sd, l, cfs);
   __syncthreads();
   if (tid < 4 * M) {
     // one-sided Robin fluxes on both sides of each skeleton face; outflow
     // of this subdomain = their average
-    const int side = lane >> 4, t = lane & 15;
-    const int e = side_iface(g, I, J, side);
     double fo = 0.0;
     if (e >= 0) {
       const SideGeo sg = side_geo(g, side);
-      const double al = a.alpha[e];
-      const double* bsf = a.basis + (size_t)e * D * M;
-      const double* ce = a.coef + (size_t)e * D;
-      double PH = 0.0, UH = 0.0;
-      for (int k = 0; k < nP; ++k) PH += ce[k] * bsf[k * M + t];
-      for (int k = nP; k < D; ++k) UH += ce[k] * bsf[k * M + t];
       const int l = side_cell<M>(side, t);
       const double sig = side_sigma(side);
       const double ko = kap[l];
       const double Fown = sg.flen * ko / (sg.dist + al * sg.H) *
                           (pm[l] - (PH - al * sg.H / ko * sig * UH));
-      const int nside = side ^ 1;
-      const int nsd = (side == 0) ? sd - 1 : (side == 1) ? sd + 1 : (side == 2) ? sd - g.SX : sd + g.SX;
-      const int nI = nsd % g.SX, nJ = nsd / g.SX;
-      const int nl = side_cell<M>(nside, t);
-      const size_t nc = (size_t)(nJ * M + nl / M) * g.nx + nI * M + nl % M;
-      const double kn = a.K[nc] * a.lam[nc];
-      const double pn = compose16(a, nsd, nl);
       const double Fnb = sg.flen * kn / (sg.dist + al * sg.H) *
                          (pn - (PH - al * sg.H / kn * (-sig) * UH));
       fo = 0.5 * (Fown - Fnb);
@@ -1290,8 +1310,8 @@ __global__ void __launch_bounds__(PAIR) stitch_pair_kernel(SubArgs a) {
   if (pvc.bad()) atomicOr(a.status, ST_STITCH_PIVOT);
   solve_column_pair(Sv, w, bs_, ps, c, gq, cy);
   // iterative refinement with the stored inverse blocks, residual in
-  // double-double
-  for (int it = 0; it < 3; ++it) {
+  // double-double; two steps bring the per-cell balance to the FP64 floor
+  for (int it = 0; it < 2; ++it) {
     for (int l = tid; l < MM; l += PAIR) {
       const int li = l % M, lj = l / M;
       double hi = bs_[l], lo = 0.0;
