@@ -368,17 +368,19 @@ int build_plan(mrcm_ctx* c) {
           if (d.s <= k0) continue;
           diag.push_back(id);
           const int nb = std::min(PANEL_NB, d.s - k0);
+          const bool next = d.s > k0 + nb;   // a next panel: its diagonal block gets its own item
+          if (next)
+            items.push_back(PanelItem{id, k0 + nb, k0 + nb, 2, d.n, d.s, d.f_off, d.inv_off});
           for (int r = k0 + nb; r < d.n; r += TILE)
             for (int cc = k0 + nb; cc <= d.n; cc += TILE)
-              items.push_back(PanelItem{id, r, cc,
-                                        (r == k0 + nb && cc == k0 + nb && d.s > k0 + nb) ? 1 : 0,
+              items.push_back(PanelItem{id, r, cc, (next && r == k0 + nb && cc == k0 + nb) ? 1 : 0,
                                         d.n, d.s, d.f_off, d.inv_off});
         }
         pl.update_count = (int)items.size() - pl.update_off;
-        // tiles that invert the next diagonal block first: they are the
-        // critical path of the panel
+        // the items that update and invert the next diagonal blocks first:
+        // they are the critical path of the panel
         std::stable_partition(items.begin() + pl.update_off, items.end(),
-                              [](const PanelItem& q) { return q.pad != 0; });
+                              [](const PanelItem& q) { return q.pad == 2; });
         pl.diag_count = (int)diag.size();
         panel_ids.push_back(diag);
         pl.diag_off = -1;  // resolved after all level ids are known

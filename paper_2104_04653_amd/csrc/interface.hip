@@ -272,6 +272,10 @@ __global__ void __launch_bounds__(NT) front_gather_kernel(const GatherItem* item
 // from lane j + 16 k).  The panel rows and columns themselves are left as
 // they were at the start of the panel (back substitution applies A11^-1 to
 // them), so tiles never write what other tiles read.
+// The next panel's diagonal block is the critical path of the elimination:
+// it is updated and inverted by an item of its own (kind 2, a 32 x 32 tile
+// with one 16 x 16 product tile per wavefront, dispatched first), and the
+// 64 x 64 tile that contains it (kind 1) leaves it out.
 __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
                                                           const PanelItem* items, int k0,
                                                           double* tree, double* inv,
@@ -283,22 +287,34 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
   __shared__ double Tt[16][17];
   static_assert(TILE == 64 && PANEL_NB == 32 && NT == 256, "tile shape of the MFMA mapping");
   const PanelItem it = items[blockIdx.x];   // carries the front's fields: one load round
+  const int kind = it.pad;                  // 0: tile, 1: tile without its leading diagonal
+                                            // block, 2: that block alone (then inverted)
   const int n = it.n, ld = n + 1;
   const int nb = min(PANEL_NB, it.s - k0);
+  const int nb1 = min(PANEL_NB, it.s - (k0 + nb));   // next panel's width (kinds 1, 2)
   double* F = tree + it.f_off;
   const double* iv = inv + it.inv_off + (long long)(k0 / PANEL_NB) * PANEL_NB * PANEL_NB;
   const int t = threadIdx.x;
   const int r0 = it.i0, c0 = it.j0;
-  const int rows = min(TILE, n - r0), cols = min(TILE, ld - c0);
+  const int rows = kind == 2 ? nb1 : min(TILE, n - r0), cols = kind == 2 ? nb1 : min(TILE, ld - c0);
   const int w = t >> 6, lane = t & 63, c = lane & 15, g = lane >> 4;
-  // this thread's entries of the A22 tile, loaded with the operands
+  // this thread's entries of the A22 tile, loaded with the operands (kind 2:
+  // wave w owns the 16 x 16 tile (w / 2, w % 2), in a22[0])
   double a22[4][4];
-#pragma unroll
-  for (int tj = 0; tj < 4; ++tj) {
+  if (kind == 2) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = 16 * w + 4 * v + g, j = 16 * tj + c;
-      a22[tj][v] = (i < rows && j < cols) ? F[(long long)(r0 + i) * ld + c0 + j] : 0.0;
+      const int i = 16 * (w >> 1) + 4 * v + g, j = 16 * (w & 1) + c;
+      a22[0][v] = (i < rows && j < cols) ? F[(long long)(r0 + i) * ld + c0 + j] : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + 4 * v + g, j = 16 * tj + c;
+        a22[tj][v] = (i < rows && j < cols) ? F[(long long)(r0 + i) * ld + c0 + j] : 0.0;
+      }
     }
   }
 #pragma unroll
@@ -317,6 +333,37 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
     Bs[k][j] = (k < nb && j < cols) ? F[(long long)(k0 + k) * ld + c0 + j] : 0.0;
   }
   __syncthreads();
+  if (kind == 2) {
+    // the next diagonal block: W and A21 W, one 16 x 16 tile per wave
+    const int ti = w >> 1, tj = w & 1;
+    d4 wv = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < PANEL_NB / 4; ++q) wv = mfma64(Dv[16 * ti + c][4 * q + g], Bs[4 * q + g][16 * tj + c], wv);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ws[16 * ti + 4 * v + g][16 * tj + c] = wv[v];
+    __syncthreads();
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < PANEL_NB / 4; ++q) acc = mfma64(As[16 * ti + c][4 * q + g], Ws[4 * q + g][16 * tj + c], acc);
+    __syncthreads();   // Dv is reused below
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * ti + 4 * v + g, j = 16 * tj + c;
+      double val = (i == j) ? 1.0 : 0.0;   // identity beyond the block's width
+      if (i < rows && j < cols) {
+        val = a22[0][v] - acc[v];
+        F[(long long)(r0 + i) * ld + c0 + j] = val;
+      }
+      Dv[i][j] = val;
+    }
+    __syncthreads();
+    if (t < 64) {
+      bool bad = false;
+      inv32_wave(Dv, Tt, inv + it.inv_off + (long long)((k0 + nb) / PANEL_NB) * PANEL_NB * PANEL_NB, bad);
+      if (bad) atomicOr(status, ST_IFACE_PIVOT);
+    }
+    return;
+  }
   {
     // W: 2 x 4 result tiles of 16 x 16, two per wave
     const int ti = w >> 1, tj = 2 * (w & 1);
@@ -344,33 +391,14 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj) acc[tj] = mfma64(av, Ws[4 * q + g][16 * tj + c], acc[tj]);
   }
-  const bool next_diag = it.pad != 0;   // this tile starts with the next panel's diagonal block
-  __syncthreads();                      // Dv is reused below
+  const int skip = kind == 1 ? nb1 : 0;   // leading diagonal block left to its own item
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = 16 * w + 4 * v + g, j = 16 * tj + c;
-      double val = 0.0;
-      if (i < rows && j < cols) {
-        val = a22[tj][v] - acc[tj][v];
-        F[(long long)(r0 + i) * ld + c0 + j] = val;
-      }
-      if (next_diag && i < PANEL_NB && j < PANEL_NB) Dv[i][j] = val;
-    }
-  }
-  if (next_diag) {
-    const int k1 = k0 + nb, nb1 = min(PANEL_NB, it.s - k1);
-    __syncthreads();
-    for (int e = t; e < PANEL_NB * PANEL_NB; e += NT) {
-      const int i = e / PANEL_NB, j = e % PANEL_NB;
-      if (!(i < nb1 && j < nb1)) Dv[i][j] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    if (t < 64) {
-      bool bad = false;
-      inv32_wave(Dv, Tt, inv + it.inv_off + (long long)(k1 / PANEL_NB) * PANEL_NB * PANEL_NB, bad);
-      if (bad) atomicOr(status, ST_IFACE_PIVOT);
+      if (i < rows && j < cols && !(i < skip && j < skip))
+        F[(long long)(r0 + i) * ld + c0 + j] = a22[tj][v] - acc[tj][v];
     }
   }
 }

@@ -83,7 +83,9 @@ struct GatherItem {     // one work-group of a blocked-front gather
 struct PanelItem {      // one work-group of a blocked trailing update
   int node;             // index into the node descriptor array
   int i0, j0;           // first row / column of the 64 x 64 tile
-  int pad;              // 1: the tile starts with the next panel's diagonal block
+  int pad;              // 0: tile; 1: tile whose leading 32 x 32 block is the next
+                        // panel's diagonal block (left out); 2: that block alone,
+                        // updated and inverted (i0 = j0 = its first row)
   int n, s;             // the front's size and separator size (copied from its node)
   long long f_off;      // the front's offset in the tree buffer
   long long inv_off;    // the front's diagonal-block inverses
