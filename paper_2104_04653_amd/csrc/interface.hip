@@ -443,29 +443,41 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
       __syncthreads();
     }
   } else {
+    // one panel per step, last first; 8 lanes per panel row.  The panel's
+    // A11^-1 is loaded into registers before the A12 products, so that both
+    // loads are in flight together, and applied from LDS.
+    __shared__ double Ds[PANEL_NB][PANEL_NB + 1];
+    static_assert(NT == 8 * PANEL_NB, "8 lanes per panel row");
+    const int row = t / 8, lane = t % 8;
     const int np = (s + PANEL_NB - 1) / PANEL_NB;
     for (int p = np - 1; p >= 0; --p) {
       const int k0 = p * PANEL_NB, nb = min(PANEL_NB, s - k0);
-      // y = b_1 - A12 x_2: 8 lanes per row, then a reduction across them
-      {
-        const int row = t / 8, lane = t % 8;
-        double v = 0.0;
-        if (row < nb) {
-          const double* fr = F + (long long)(k0 + row) * ld;
-#pragma unroll 4
-          for (int m = k0 + nb + lane; m < n; m += 8) v -= fr[m] * xl[m];
-          if (lane == 0) v += rv ? rv[k0 + row] : fr[n];
-        }
-        for (int off = 4; off > 0; off >>= 1) v += __shfl_down(v, off, 8);
-        if (row < nb && lane == 0) y[row] = v;
-      }
-      __syncthreads();
       const double* Di = inv + nd.inv_off + (long long)p * PANEL_NB * PANEL_NB;
-      if (t < nb) {
-        double v = 0.0;
-        for (int m = 0; m < nb; ++m) v += Di[t * PANEL_NB + m] * y[m];
-        xl[k0 + t] = v;
+      double dreg[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dreg[q] = Di[row * PANEL_NB + 4 * lane + q];
+      // y = b_1 - A12 x_2, then a reduction across the row's lanes
+      double v = 0.0;
+      if (row < nb) {
+        const double* fr = F + (long long)(k0 + row) * ld;
+#pragma unroll 4
+        for (int m = k0 + nb + lane; m < n; m += 8) v -= fr[m] * xl[m];
+        if (lane == 0) v += rv ? rv[k0 + row] : fr[n];
       }
+      for (int off = 4; off > 0; off >>= 1) v += __shfl_down(v, off, 8);
+      if (row < nb && lane == 0) y[row] = v;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Ds[row][4 * lane + q] = dreg[q];
+      __syncthreads();
+      // x_1 = A11^-1 y: 4 products per lane, reduced across the row's lanes
+      double u = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = 4 * lane + q;
+        u += m < nb ? Ds[row][m] * y[m] : 0.0;
+      }
+      for (int off = 4; off > 0; off >>= 1) u += __shfl_down(u, off, 8);
+      if (row < nb && lane == 0) xl[k0 + row] = u;
       __syncthreads();
     }
   }
