@@ -62,9 +62,12 @@ enum { MRCM_BC_NEUMANN = 0, MRCM_BC_DIRICHLET = 1 };
 enum { MRCM_SPACE_LINEAR = 0, MRCM_SPACE_EDGE_SOLUTION = 1, MRCM_SPACE_FULL = 2 };
 
 /* Precision of the local (subdomain) factorisations.  The interface system
- * is always solved in FP64.  FP32_IR: FP32 factors and solves, FP64
- * residuals and iterative refinement to 1e-12 relative, per-subdomain FP64
- * fallback when refinement stalls.  SURROGATE: the basis functions of each
+ * is always solved in FP64.  FP32_IR: FP32 factors and solves of the
+ * diagonally scaled local system, FP64 residuals and iterative refinement
+ * until the last correction is below 1e-9 of the solution, per-subdomain
+ * FP64 fallback when refinement stalls (16 x 16 subdomains with 2 + 2 dofs,
+ * 32 x 32 subdomains with 4 dofs; other sizes MRCM_E_UNSUPPORTED).
+ * SURROGATE (16 x 16, 2 + 2 dofs): the basis functions of each
  * subdomain are predicted by the convolutional network set with
  * mrcm_set_surrogate and accepted only if every column's FP64 residual in
  * the local problem is below 1e-6 of its right-hand side; every other

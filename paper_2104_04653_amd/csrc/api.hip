@@ -531,7 +531,9 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
   if (precision != MRCM_PREC_FP64 && precision != MRCM_PREC_FP32_IR &&
       precision != MRCM_PREC_SURROGATE)
     return MRCM_E_INVAL;
-  if (precision != MRCM_PREC_FP64 && !(M == 16 && p_dofs == 2 && u_dofs == 2))
+  if (precision == MRCM_PREC_FP32_IR && !local_fp32_supported(M, p_dofs + u_dofs, p_dofs))
+    return MRCM_E_UNSUPPORTED;
+  if (precision == MRCM_PREC_SURROGATE && !(M == 16 && p_dofs == 2 && u_dofs == 2))
     return MRCM_E_UNSUPPORTED;
   if (!finite_pos(fluid->mu_w) || !finite_pos(fluid->mu_o)) return MRCM_E_INVAL;
   for (int s = 0; s < 4; ++s)

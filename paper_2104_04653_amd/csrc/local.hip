@@ -40,16 +40,17 @@ using namespace local;
 // Block elimination of the local system for NR right-hand sides held in
 // Xs[MM][NR]; leaves the solution in Xs and the inverse Schur blocks in
 // Sinv[M][MM] (LDS, or global scratch for large M).  Each thread keeps
-// EPT elements of S_j in registers.
-template <int M, int NR>
-__device__ void thomas_solve(double* Xs, double* Sinv, const double* dg, const double* ex,
-                             const double* cy, double* pivbuf /*[2][2][M]*/, int* status,
-                             int flag) {
+// EPT elements of S_j in registers.  T is the working precision (double,
+// or float for the FP32 factorisation of a scaled matrix).  Returns true
+// (on every thread) if a pivot was not positive.
+template <int M, int NR, class T>
+__device__ bool thomas_solve(T* Xs, T* Sinv, const T* dg, const T* ex, const T* cy,
+                             T* pivbuf /*[2][2][M]*/) {
   constexpr int MM = M * M;
   constexpr int NQ = (M * NR + NT - 1) / NT;
   constexpr int EPT = (MM + NT - 1) / NT;
   const int tid = threadIdx.x;
-  double s[EPT];
+  T s[EPT];
   int ta[EPT], tb[EPT];
   bool own[EPT];
 #pragma unroll
@@ -58,19 +59,19 @@ __device__ void thomas_solve(double* Xs, double* Sinv, const double* dg, const d
     own[q] = e < MM;
     ta[q] = e / M;
     tb[q] = e % M;
-    s[q] = 0.0;
+    s[q] = T(0);
   }
   int par = 0;
   bool bad = false;
-  double acc[NQ];
+  T acc[NQ];
   for (int j = 0; j < M; ++j) {
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       if (!own[q]) continue;
       const int a_ = ta[q], b_ = tb[q];
-      double dv = (a_ == b_) ? dg[j * M + a_]
-                : (b_ == a_ + 1) ? ex[j * M + a_]
-                : (a_ == b_ + 1) ? ex[j * M + b_] : 0.0;
+      T dv = (a_ == b_) ? dg[j * M + a_]
+           : (b_ == a_ + 1) ? ex[j * M + a_]
+           : (a_ == b_ + 1) ? ex[j * M + b_] : T(0);
       if (j > 0) dv -= cy[(j - 1) * M + a_] * s[q] * cy[(j - 1) * M + b_];
       s[q] = dv;
     }
@@ -81,14 +82,14 @@ __device__ void thomas_solve(double* Xs, double* Sinv, const double* dg, const d
         if (own[q] && ta[q] == k) pivbuf[(par * 2 + 1) * M + tb[q]] = s[q];
       }
       __syncthreads();
-      const double p = pivbuf[(par * 2 + 1) * M + k];
-      if (!(p > 0.0)) bad = true;
-      const double ip = 1.0 / p;
+      const T p = pivbuf[(par * 2 + 1) * M + k];
+      if (!(p > T(0))) bad = true;
+      const T ip = T(1) / p;
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
         if (!own[q]) continue;
-        const double sak = pivbuf[(par * 2 + 0) * M + ta[q]];
-        const double skb = pivbuf[(par * 2 + 1) * M + tb[q]];
+        const T sak = pivbuf[(par * 2 + 0) * M + ta[q]];
+        const T skb = pivbuf[(par * 2 + 1) * M + tb[q]];
         if (ta[q] == k && tb[q] == k) s[q] = ip;
         else if (ta[q] == k) s[q] = s[q] * ip;
         else if (tb[q] == k) s[q] = -sak * ip;
@@ -105,9 +106,9 @@ __device__ void thomas_solve(double* Xs, double* Sinv, const double* dg, const d
       int q = 0;
       for (int o = tid; o < M * NR; o += NT, ++q) {
         const int ra = o / NR, col = o % NR;
-        double sum = 0.0;
+        T sum = T(0);
         for (int b = 0; b < M; ++b) {
-          double r = Xs[(j * M + b) * NR + col];
+          T r = Xs[(j * M + b) * NR + col];
           if (j > 0) r -= cy[(j - 1) * M + b] * Xs[((j - 1) * M + b) * NR + col];
           sum += Sinv[j * MM + ra * M + b] * r;
         }
@@ -126,7 +127,7 @@ __device__ void thomas_solve(double* Xs, double* Sinv, const double* dg, const d
     int q = 0;
     for (int o = tid; o < M * NR; o += NT, ++q) {
       const int ra = o / NR, col = o % NR;
-      double sum = Xs[(j * M + ra) * NR + col];
+      T sum = Xs[(j * M + ra) * NR + col];
       for (int b = 0; b < M; ++b)
         sum -= Sinv[j * MM + ra * M + b] * cy[j * M + b] * Xs[((j + 1) * M + b) * NR + col];
       acc[q] = sum;
@@ -138,25 +139,25 @@ __device__ void thomas_solve(double* Xs, double* Sinv, const double* dg, const d
     }
     __syncthreads();
   }
-  if (bad) atomicOr(status, flag);
+  return bad;
 }
 
 // Solve again with the inverse Schur blocks already in Sinv (no factoring):
 // the forward and backward block sweeps of thomas_solve on NR new columns.
-template <int M, int NR>
-__device__ void thomas_resolve(double* Xs, const double* Sinv, const double* cy) {
+template <int M, int NR, class T>
+__device__ void thomas_resolve(T* Xs, const T* Sinv, const T* cy) {
   constexpr int MM = M * M;
   constexpr int NQ = (M * NR + NT - 1) / NT;
   const int tid = threadIdx.x;
-  double acc[NQ];
+  T acc[NQ];
   __syncthreads();
   for (int j = 0; j < M; ++j) {
     int q = 0;
     for (int o = tid; o < M * NR; o += NT, ++q) {
       const int ra = o / NR, col = o % NR;
-      double sum = 0.0;
+      T sum = T(0);
       for (int b = 0; b < M; ++b) {
-        double r = Xs[(j * M + b) * NR + col];
+        T r = Xs[(j * M + b) * NR + col];
         if (j > 0) r -= cy[(j - 1) * M + b] * Xs[((j - 1) * M + b) * NR + col];
         sum += Sinv[j * MM + ra * M + b] * r;
       }
@@ -174,7 +175,7 @@ __device__ void thomas_resolve(double* Xs, const double* Sinv, const double* cy)
     int q = 0;
     for (int o = tid; o < M * NR; o += NT, ++q) {
       const int ra = o / NR, col = o % NR;
-      double sum = Xs[(j * M + ra) * NR + col];
+      T sum = Xs[(j * M + ra) * NR + col];
       for (int b = 0; b < M; ++b)
         sum -= Sinv[j * MM + ra * M + b] * cy[j * M + b] * Xs[((j + 1) * M + b) * NR + col];
       acc[q] = sum;
@@ -229,53 +230,15 @@ struct LocalStore {
   static constexpr bool big = M > 16;
 };
 
+// Traces of every column (Xs: [cell][column], FP64) projected on the
+// interface functions: the subdomain's block of the interface system, rows
+// of flux dofs negated (symmetric form), last column = right-hand side.
 template <int M, int D>
-__global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
+__device__ void generic_block(const SubArgs& a, int sd, int I, int J, const double* kap,
+                              const double* Xs) {
   constexpr int R = 1 + 4 * D;
-  constexpr int MM = M * M;
   constexpr int NBR = 4 * D, NBC = 4 * D + 1;
-  constexpr bool BIG = LocalStore<M>::big;
-  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
-  __shared__ double Xs_l[BIG ? 1 : MM * R];
-  __shared__ double Sinv_l[BIG ? 1 : M * MM];
-  __shared__ double pivbuf[4 * M];
   const Geo& g = a.g;
-  const int tid = threadIdx.x;
-  const int sd = blockIdx.x;
-  const int I = sd % g.SX, J = sd / g.SX;
-  // per-subdomain scratch: [Bs | Rs] (all sizes), then [Xs | Sinv] beyond
-  // 16 x 16; its length is local_scratch_doubles()
-  double* scr = a.scratch + (size_t)sd * a.scratch_stride;
-  double* Rs_l = scr + MM * R;
-  double* Bs = scr;
-  double* Xs = BIG ? scr + 2 * MM * R : Xs_l;
-  double* Sinv = BIG ? scr + 3 * MM * R : Sinv_l;
-
-  load_kappa<M>(a, I, J, kap);
-  __syncthreads();
-  for (int l = tid; l < MM; l += NT)
-    assemble_cell<M, R>(a, I, J, l, kap, dg, ex, cy, Xs + l * R, 1, nullptr);
-  __syncthreads();
-  for (int o = tid; o < MM * R; o += NT) Bs[o] = Xs[o];
-
-  thomas_solve<M, R>(Xs, Sinv, dg, ex, cy, pivbuf, a.status, ST_LOCAL_PIVOT);
-  // iterative refinement, residual in double-double (Bs keeps B; the
-  // correction goes through Rg)
-  double* Rg = Rs_l;
-  for (int it = 0; it < LOCAL_IR_STEPS; ++it) {
-    __syncthreads();
-    for (int o = tid; o < MM * R; o += NT) Rg[o] = Bs[o];
-    __syncthreads();
-    local_residual_dd<M, R>(Rg, Xs, dg, ex, cy);
-    thomas_resolve<M, R>(Rg, Sinv, cy);
-    for (int o = tid; o < MM * R; o += NT) Xs[o] += Rg[o];
-  }
-  __syncthreads();
-
-  double* Xg = a.X + (size_t)sd * MM * R;   // column-major per subdomain: [col][cell]
-  for (int o = tid; o < MM * R; o += NT) Xg[(o % R) * MM + o / R] = Xs[o];
-
-  // traces and projection: this subdomain's block of the interface system
   double* blk = a.blocks + (size_t)sd * NBR * NBC;
   const int nP = g.nP;
   int e0side = -1;      // side holding global dof 0 (gauge), if any
@@ -284,7 +247,7 @@ __global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
     for (int side = 0; side < 4; ++side)
       if (side_iface(g, I, J, side) == 0) { e0side = side; e0lo = side_sigma(side) > 0; }
   }
-  for (int o = tid; o < NBR * NBC; o += NT) {
+  for (int o = threadIdx.x; o < NBR * NBC; o += NT) {
     const int r = o / NBC, qc = o % NBC;
     const int side = r / D, k = r % D;
     const int e = side_iface(g, I, J, side);
@@ -320,6 +283,161 @@ __global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
     }
     blk[o] = val;
   }
+}
+
+// FP64 local solves (LIST: only the subdomains on the fallback list of the
+// FP32 kernel below)
+template <int M, int D, bool LIST>
+__global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
+  constexpr int R = 1 + 4 * D;
+  constexpr int MM = M * M;
+  constexpr bool BIG = LocalStore<M>::big;
+  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
+  __shared__ double Xs_l[BIG ? 1 : MM * R];
+  __shared__ double Sinv_l[BIG ? 1 : M * MM];
+  __shared__ double pivbuf[4 * M];
+  const Geo& g = a.g;
+  const int tid = threadIdx.x;
+  int sd = blockIdx.x;
+  if (LIST) {
+    if ((int)blockIdx.x >= a.fallback[0]) return;
+    sd = a.fallback[1 + blockIdx.x];
+  }
+  const int I = sd % g.SX, J = sd / g.SX;
+  // per-subdomain scratch: [Bs | Rs] (all sizes), then [Xs | Sinv] beyond
+  // 16 x 16; its length is local_scratch_doubles()
+  double* scr = a.scratch + (size_t)sd * a.scratch_stride;
+  double* Rs_l = scr + MM * R;
+  double* Bs = scr;
+  double* Xs = BIG ? scr + 2 * MM * R : Xs_l;
+  double* Sinv = BIG ? scr + 3 * MM * R : Sinv_l;
+
+  load_kappa<M>(a, I, J, kap);
+  __syncthreads();
+  for (int l = tid; l < MM; l += NT)
+    assemble_cell<M, R>(a, I, J, l, kap, dg, ex, cy, Xs + l * R, 1, nullptr);
+  __syncthreads();
+  for (int o = tid; o < MM * R; o += NT) Bs[o] = Xs[o];
+
+  if (thomas_solve<M, R, double>(Xs, Sinv, dg, ex, cy, pivbuf) && tid == 0)
+    atomicOr(a.status, ST_LOCAL_PIVOT);
+  // iterative refinement, residual in double-double (Bs keeps B; the
+  // correction goes through Rg)
+  double* Rg = Rs_l;
+  for (int it = 0; it < LOCAL_IR_STEPS; ++it) {
+    __syncthreads();
+    for (int o = tid; o < MM * R; o += NT) Rg[o] = Bs[o];
+    __syncthreads();
+    local_residual_dd<M, R>(Rg, Xs, dg, ex, cy);
+    thomas_resolve<M, R, double>(Rg, Sinv, cy);
+    for (int o = tid; o < MM * R; o += NT) Xs[o] += Rg[o];
+  }
+  __syncthreads();
+
+  double* Xg = a.X + (size_t)sd * MM * R;   // column-major per subdomain: [col][cell]
+  for (int o = tid; o < MM * R; o += NT) Xg[(o % R) * MM + o / R] = Xs[o];
+  generic_block<M, D>(a, sd, I, J, kap, Xs);
+}
+
+// FP32 factorisation + FP64 iterative refinement for the generic sizes with
+// their work arrays in the per-subdomain scratch (32 x 32 subdomains): the
+// same method as the 16 x 16 FP32 kernel.  The local matrix is scaled
+// symmetrically (Ds A Ds, Ds = diag(A)^-1/2, unit diagonal); the inverse
+// Schur blocks and the solves of the scaled system are FP32, the solution
+// and the residuals FP64.  Refinement stops when the largest correction is
+// below IR_DONE32 of the largest solution value; a subdomain that ends above
+// it, or met a bad FP32 pivot, is listed for the FP64 re-solve.
+constexpr int IR_MAX32 = 8;
+constexpr double IR_DONE32 = 1e-9;
+
+template <int M, int D>
+__global__ void __launch_bounds__(NT) local_basis32_kernel(SubArgs a) {
+  constexpr int R = 1 + 4 * D;
+  constexpr int MM = M * M;
+  static_assert(LocalStore<M>::big && R <= M, "scratch layout of the large subdomains");
+  __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], dsc[MM];
+  __shared__ float dgs[MM], exs[MM], cys[MM];
+  __shared__ float pivbuf[4 * M];
+  __shared__ double red[2][NT / 64];
+  const Geo& g = a.g;
+  const int tid = threadIdx.x;
+  const int sd = blockIdx.x;
+  const int I = sd % g.SX, J = sd / g.SX;
+  // scratch: Bs | Rg | Xs (FP64, MM R each), then FP32 Sinv (M MM) and the
+  // FP32 work columns Ws (MM R) in the space of the FP64 inverse blocks
+  double* scr = a.scratch + (size_t)sd * a.scratch_stride;
+  double* Bs = scr;
+  double* Rg = scr + MM * R;
+  double* Xs = scr + 2 * MM * R;
+  float* Sinv = reinterpret_cast<float*>(scr + 3 * MM * R);
+  float* Ws = Sinv + M * MM;
+
+  load_kappa<M>(a, I, J, kap);
+  __syncthreads();
+  for (int l = tid; l < MM; l += NT)
+    assemble_cell<M, R>(a, I, J, l, kap, dg, ex, cy, Bs + l * R, 1, nullptr);
+  __syncthreads();
+  for (int l = tid; l < MM; l += NT) dsc[l] = 1.0 / sqrt(dg[l]);
+  __syncthreads();
+  for (int l = tid; l < MM; l += NT) {
+    const int li = l % M, lj = l / M;
+    dgs[l] = 1.0f;
+    exs[l] = li < M - 1 ? (float)(ex[l] * dsc[l] * dsc[l + 1]) : 0.0f;
+    cys[l] = lj < M - 1 ? (float)(cy[l] * dsc[l] * dsc[l + M]) : 0.0f;
+  }
+  for (int o = tid; o < MM * R; o += NT) Ws[o] = (float)(dsc[o / R] * Bs[o]);
+  __syncthreads();
+  const bool bad = thomas_solve<M, R, float>(Ws, Sinv, dgs, exs, cys, pivbuf);
+  __syncthreads();
+  for (int o = tid; o < MM * R; o += NT) Xs[o] = dsc[o / R] * (double)Ws[o];
+
+  int used = 0;
+  double rel = 1.0;
+  for (int it = 0; it < IR_MAX32; ++it) {
+    __syncthreads();
+    local_residual<M, R>(Bs, Xs, Rg, dg, ex, cy);
+    __syncthreads();
+    for (int o = tid; o < MM * R; o += NT) Ws[o] = (float)(dsc[o / R] * Rg[o]);
+    thomas_resolve<M, R, float>(Ws, Sinv, cys);
+    double cmax = 0.0, xmax = 0.0;
+    for (int o = tid; o < MM * R; o += NT) {
+      const double dx = dsc[o / R] * (double)Ws[o];
+      const double x = Xs[o] + dx;
+      Xs[o] = x;
+      cmax = fmax(cmax, fabs(dx));
+      xmax = fmax(xmax, fabs(x));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      cmax = fmax(cmax, __shfl_xor(cmax, off));
+      xmax = fmax(xmax, __shfl_xor(xmax, off));
+    }
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = cmax;
+      red[1][tid >> 6] = xmax;
+    }
+    __syncthreads();
+    cmax = 0.0;
+    xmax = 0.0;
+    for (int w = 0; w < NT / 64; ++w) {
+      cmax = fmax(cmax, red[0][w]);
+      xmax = fmax(xmax, red[1][w]);
+    }
+    used = it + 1;
+    rel = cmax / fmax(xmax, 1e-300);
+    if (rel <= IR_DONE32) break;
+  }
+  if (tid == 0) {
+    atomicMax(a.ir_iters, used);
+    if (bad || !(rel <= IR_DONE32)) {
+      const int q = atomicAdd(a.fallback, 1);
+      a.fallback[1 + q] = sd;
+    }
+  }
+  __syncthreads();
+
+  double* Xg = a.X + (size_t)sd * MM * R;   // column-major per subdomain: [col][cell]
+  for (int o = tid; o < MM * R; o += NT) Xg[(o % R) * MM + o / R] = Xs[o];
+  generic_block<M, D>(a, sd, I, J, kap, Xs);
 }
 
 // ---------------------------------------------------------------------------
@@ -413,11 +531,12 @@ __global__ void __launch_bounds__(NT) stitch_kernel(SubArgs a) {
   }
   __syncthreads();
   for (int l = tid; l < MM; l += NT) Bs[l] = Xs[l];
-  thomas_solve<M, 1>(Xs, Sinv, dg, ex, cy, pivbuf, a.status, ST_STITCH_PIVOT);
+  if (thomas_solve<M, 1, double>(Xs, Sinv, dg, ex, cy, pivbuf) && threadIdx.x == 0)
+    atomicOr(a.status, ST_STITCH_PIVOT);
   // two steps of FP64 iterative refinement with the stored inverse blocks
   for (int it = 0; it < 2; ++it) {
     local_residual<M, 1>(Bs, Xs, Rs, dg, ex, cy);
-    thomas_resolve<M, 1>(Rs, Sinv, cy);
+    thomas_resolve<M, 1, double>(Rs, Sinv, cy);
     for (int l = tid; l < MM; l += NT) Xs[l] += Rs[l];
     __syncthreads();
   }
@@ -534,7 +653,17 @@ hipError_t launch_pair(const SubArgs& a, hipStream_t st, bool stitch) {
   if (stitch)
     hipLaunchKernelGGL((stitch_kernel<M, D>), dim3(a.g.n_sub), dim3(NT), 0, st, a);
   else
-    hipLaunchKernelGGL((local_basis_kernel<M, D>), dim3(a.g.n_sub), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((local_basis_kernel<M, D, false>), dim3(a.g.n_sub), dim3(NT), 0, st, a);
+  return hipGetLastError();
+}
+
+// FP32 + refinement, then the FP64 re-solve of the listed subdomains
+template <int M, int D>
+hipError_t launch_fp32(const SubArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((local_basis32_kernel<M, D>), dim3(a.g.n_sub), dim3(NT), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((local_basis_kernel<M, D, true>), dim3(a.g.n_sub), dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 
@@ -549,7 +678,10 @@ hipError_t dispatch(const SubArgs& a, hipStream_t st, bool stitch) {
     }
     return launch_basis_m16d4(a, st);
   }
-  if (M == 32 && D == 4) return launch_pair<32, 4>(a, st, stitch);
+  if (M == 32 && D == 4) {
+    if (!stitch && a.g.prec == 1) return launch_fp32<32, 4>(a, st);
+    return launch_pair<32, 4>(a, st, stitch);
+  }
   if (M == 16 && D == 4) return launch_pair<16, 4>(a, st, stitch);
   if (M == 8 && D == 4) return launch_pair<8, 4>(a, st, stitch);
   if (M == 4 && D == 4) return launch_pair<4, 4>(a, st, stitch);
@@ -559,6 +691,10 @@ hipError_t dispatch(const SubArgs& a, hipStream_t st, bool stitch) {
 }
 
 }  // namespace
+
+bool local_fp32_supported(int M, int D, int nP) {
+  return (M == 16 && D == 4 && nP == 2) || (M == 32 && D == 4);
+}
 
 bool local_supported(int M, int D) {
   return (M == 32 && D == 4) || (M == 16 && D == 4) || (M == 8 && D == 4) || (M == 4 && D == 4) || (M == 8 && D == 16) ||

@@ -105,6 +105,8 @@ hipError_t launch_basis32_m16d4(const SubArgs& a, hipStream_t st);
 hipError_t launch_basis_m16d4_list(const SubArgs& a, hipStream_t st);
 hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st);
 bool local_supported(int M, int D);
+// sizes with an FP32 + refinement kernel (16 x 16 with 2 + 2 dofs, 32 x 32 with 4 dofs)
+bool local_fp32_supported(int M, int D, int nP);
 // doubles of global scratch per subdomain the generic kernels need (0 if none)
 long long local_scratch_doubles(const Geo& g);
 

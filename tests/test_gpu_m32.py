@@ -1,14 +1,18 @@
 """32 x 32 subdomains on the GPU (the 2048 x 1024 channelized workload with
 edge-solution interface spaces, and smaller cases of the same shape),
-against the oracle at relative L2 1e-10 in pressure and flux."""
+against the oracle at relative L2 1e-10 in pressure and flux (FP64 local
+solves) and 1e-8 (FP32 factorisation + FP64 refinement)."""
 import numpy as np
 import pytest
 
 import inputs
-from tests.gpu_util import say
+from oracle.discretization import total_mobility
+from tests.gpu_util import rel, run_gpu, run_oracle, say
 from tests.test_gpu_parity import check_end_to_end
 
 pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-8   # FP32 factorisation + FP64 refinement against the oracle
 
 
 def test_m32_edge_spaces_channelized_small():
@@ -22,19 +26,39 @@ def test_m32_linear_spaces_all_neumann_wells():
     check_end_to_end(prob, s=inputs.synthetic_saturation(prob, 4, 20), label="m32 q5 256")
 
 
+def check_fp32_ir(prob, lam, ref, label):
+    """FP32 factorisation + FP64 refinement against the oracle at 1e-8."""
+    g = run_gpu(prob, lam=lam, precision="fp32_ir", extras=False)
+    ep = rel(g["p"], ref.p)
+    ef = rel(np.r_[g["ux"], g["uy"]], np.r_[ref.ux, ref.uy])
+    st = g["stats"]
+    say("  %s fp32+ir: rel L2 p %.2e flux %.2e  refinement steps (max) %d  fp64 fallbacks %d of %d"
+        "  ms local %.3f" % (label, ep, ef, st["ir_iters_max"], st["fallbacks"], st["n_sub"],
+                             st["ms_local"]))
+    assert ep < FP32_TOL and ef < FP32_TOL
+    return g
+
+
+def test_m32_fp32_ir_edge_spaces_channelized_small():
+    prob = inputs.make_problem("channel2048x1024", nx=256, ny=128, lx=0.25, ly=0.125, seed=2)
+    lam = total_mobility(inputs.synthetic_saturation(prob, 2, 5), prob.mu_w, prob.mu_o)
+    check_fp32_ir(prob, lam, run_oracle(prob, lam=lam), "m32 edge 256x128")
+
+
 def test_m32_full_size_2048x1024():
+    """FP64 at 1e-10 and FP32 + refinement at 1e-8, against one oracle solve."""
     prob = inputs.make_problem("channel2048x1024", seed=1)
-    g, _ = check_end_to_end(prob, s=inputs.synthetic_saturation(prob, 2, 5), local=False,
-                            label="m32 2048x1024", coef_tol=1e-8)
+    lam = total_mobility(inputs.synthetic_saturation(prob, 2, 5), prob.mu_w, prob.mu_o)
+    g, ref = check_end_to_end(prob, lam=lam, local=False, label="m32 2048x1024", coef_tol=1e-8)
     st = g["stats"]
     say("  ms local %.3f interface %.3f flux %.3f (n_dof %d)"
         % (st["ms_local"], st["ms_interface"], st["ms_flux"], st["n_dof"]))
+    check_fp32_ir(prob, lam, ref, "m32 2048x1024")
 
 
-def test_m32_reduced_precision_paths_are_reported_unsupported():
+def test_m32_surrogate_is_reported_unsupported():
     from paper_2104_04653_amd import MRCMError, MRCMSolver
     prob = inputs.make_problem("channel2048x1024", nx=128, ny=64, lx=0.125, ly=0.0625)
-    for precision in ("fp32_ir", "surrogate"):
-        with pytest.raises(MRCMError) as e:
-            MRCMSolver(prob, precision=precision)
-        assert e.value.code == 7    # MRCM_E_UNSUPPORTED
+    with pytest.raises(MRCMError) as e:
+        MRCMSolver(prob, precision="surrogate")
+    assert e.value.code == 7    # MRCM_E_UNSUPPORTED
