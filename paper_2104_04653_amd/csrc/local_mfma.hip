@@ -429,20 +429,22 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
   }
   if (pvc.bad()) atomicOr(a.status, ST_LOCAL_PIVOT);
 
-  // one step of iterative refinement of all 17 columns (FP64 residual formed
-  // with fused multiply-adds, correction by the same two-chain sweeps): it
-  // removes the growth of the Gauss-Jordan inverses; a double-double residual
-  // gave the same parity with the oracle at 9 times the residual work
+  // one step of iterative refinement of all 17 columns (residual in
+  // double-double, correction by the same two-chain sweeps).  With a plain
+  // FP64 residual the parity with the oracle is the same, but the interface
+  // blocks then keep an asymmetry near 1e-13 of their size, which the
+  // interface elimination (symmetric diagonal-block inverses) turns into a
+  // residual above its refinement threshold on some steps
   __syncthreads();
   for (int l = tid; l < MM; l += PAIR) {
     const int i = l % M, j = l / M;
-    double ph = b0[l];
-    ph = fma(-dg[l], pz[l], ph);
-    ph = fma(i < M - 1 ? -ex[l] : 0.0, pz[i < M - 1 ? l + 1 : l], ph);
-    ph = fma(i > 0 ? -ex[l - 1] : 0.0, pz[i > 0 ? l - 1 : l], ph);
-    ph = fma(j < M - 1 ? -cy[l] : 0.0, pz[j < M - 1 ? l + M : l], ph);
-    ph = fma(j > 0 ? -cy[l - M] : 0.0, pz[j > 0 ? l - M : l], ph);
-    rpz[l] = ph;
+    double ph = b0[l], pl = 0.0;
+    dd_fma(ph, pl, -dg[l], pz[l]);
+    dd_fma(ph, pl, i < M - 1 ? -ex[l] : 0.0, pz[i < M - 1 ? l + 1 : l]);
+    dd_fma(ph, pl, i > 0 ? -ex[l - 1] : 0.0, pz[i > 0 ? l - 1 : l]);
+    dd_fma(ph, pl, j < M - 1 ? -cy[l] : 0.0, pz[j < M - 1 ? l + M : l]);
+    dd_fma(ph, pl, j > 0 ? -cy[l - M] : 0.0, pz[j > 0 ? l - M : l]);
+    rpz[l] = ph + pl;
   }
   if (w == 1) {
 #pragma unroll
@@ -463,11 +465,11 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = 4 * v + gq, l = j * M + i;
-      double hi = side_rhs(bside, j, i, c);
-      hi = fma(-dg[l], Xv[t][v], hi);
-      hi = fma(i < M - 1 ? -ex[l] : 0.0, T[i < M - 1 ? i + 1 : i][c], hi);
-      hi = fma(i > 0 ? -ex[i > 0 ? l - 1 : l] : 0.0, T[i > 0 ? i - 1 : i][c], hi);
-      r[v] = hi;
+      double hi = side_rhs(bside, j, i, c), lo = 0.0;
+      dd_fma(hi, lo, -dg[l], Xv[t][v]);
+      dd_fma(hi, lo, i < M - 1 ? -ex[l] : 0.0, T[i < M - 1 ? i + 1 : i][c]);
+      dd_fma(hi, lo, i > 0 ? -ex[i > 0 ? l - 1 : l] : 0.0, T[i > 0 ? i - 1 : i][c]);
+      r[v] = hi + lo;
     }
     __builtin_amdgcn_wave_barrier();
   };
@@ -486,11 +488,11 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = 4 * v + gq;
-        double hi = r[v];
+        double hi = r[v], lo = 0.0;
         const double xnext = (t + 1 < nchain) ? Xv[t + 1 < NU ? t + 1 : t][v] : (w ? xm[v] : Xv[MID][v]);
-        hi = fma(-cy[jcn * M + i], xnext, hi);
-        if (t > 0) hi = fma(-cy[jc * M + i], Xv[t > 0 ? t - 1 : 0][v], hi);
-        r[v] = hi;
+        dd_fma(hi, lo, -cy[jcn * M + i], xnext);
+        if (t > 0) dd_fma(hi, lo, -cy[jc * M + i], Xv[t > 0 ? t - 1 : 0][v]);
+        r[v] = hi + lo;
       }
       d4 rp;
 #pragma unroll
@@ -530,10 +532,10 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = 4 * v + gq;
-      double hi = r[v];
-      hi = fma(-cy[j * M + i], xo[v], hi);
-      hi = fma(-cy[(j - 1) * M + i], Xv[MID - 1][v], hi);
-      r[v] = hi;
+      double hi = r[v], lo = 0.0;
+      dd_fma(hi, lo, -cy[j * M + i], xo[v]);
+      dd_fma(hi, lo, -cy[(j - 1) * M + i], Xv[MID - 1][v]);
+      r[v] = hi + lo;
     }
     d4 rp;
 #pragma unroll
