@@ -1314,8 +1314,9 @@ __global__ void __launch_bounds__(PAIR) stitch_pair_kernel(SubArgs a) {
   if (pvc.bad()) atomicOr(a.status, ST_STITCH_PIVOT);
   solve_column_pair(Sv, w, bs_, ps, c, gq, cy);
   // iterative refinement with the stored inverse blocks, residual in
-  // double-double; two steps bring the per-cell balance to the FP64 floor
-  for (int it = 0; it < 2; ++it) {
+  // double-double: one step brings the per-cell balance to the FP64 floor
+  // (a second left every balance and parity figure unchanged)
+  for (int it = 0; it < 1; ++it) {
     for (int l = tid; l < MM; l += PAIR) {
       const int li = l % M, lj = l / M;
       double hi = bs_[l], lo = 0.0;
