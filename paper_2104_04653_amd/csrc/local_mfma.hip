@@ -166,26 +166,49 @@ struct Faces {
   double phi[4][D][M];
 };
 
-__device__ inline void prepare_faces(const SubArgs& a, int I, int J, const double* kap, Faces& f) {
+// The global data of a face (its interface's alpha and functions), loaded
+// by the first 4 M threads at the start of a kernel so that the loads are in
+// flight with the mobility loads; prepare_faces completes the face data once
+// the cell mobilities are in LDS.
+struct FaceLoad {
+  int e = -1;
+  double al = 0.0;
+  double phi[D] = {0.0, 0.0, 0.0, 0.0};
+};
+
+__device__ inline FaceLoad load_faces(const SubArgs& a, int I, int J) {
+  FaceLoad fl;
+  const int l = threadIdx.x;
+  if (l < 4 * M) {
+    const int side = l >> 4, t = l & 15;
+    fl.e = side_iface(a.g, I, J, side);
+    if (fl.e >= 0) {
+      fl.al = a.alpha[fl.e];
+#pragma unroll
+      for (int k = 0; k < D; ++k) fl.phi[k] = a.basis[((size_t)fl.e * D + k) * M + t];
+    }
+  }
+  return fl;
+}
+
+__device__ inline void prepare_faces(const SubArgs& a, const FaceLoad& fl, const double* kap, Faces& f) {
   const Geo& g = a.g;
   const int l = threadIdx.x;
   if (l < 4 * M) {
     const int side = l >> 4, t = l & 15;
-    const int e = side_iface(g, I, J, side);
     double tr = 0.0, bt = 0.0, bl = 0.0;
-    if (e >= 0) {
+    if (fl.e >= 0) {
       const SideGeo sg = side_geo(g, side);
-      const double al = a.alpha[e];
       const double kk = kap[side_cell<M>(side, t)];
-      tr = sg.flen * kk / (sg.dist + al * sg.H);
-      bt = al * sg.H / kk;
+      tr = sg.flen * kk / (sg.dist + fl.al * sg.H);
+      bt = fl.al * sg.H / kk;
       bl = bt / sg.flen;
     }
     f.tr[side][t] = tr;
     f.bt[side][t] = bt;
     f.bl[side][t] = bl;
 #pragma unroll
-    for (int k = 0; k < D; ++k) f.phi[side][k][t] = e >= 0 ? a.basis[((size_t)e * D + k) * M + t] : 0.0;
+    for (int k = 0; k < D; ++k) f.phi[side][k][t] = fl.phi[k];
   }
 }
 
@@ -298,11 +321,12 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
   }
   const int I = sd % g.SX, J = sd / g.SX;
 
+  const FaceLoad fl = load_faces(a, I, J);
   load_kappa<M>(a, I, J, kap);
   __syncthreads();
   for (int l = tid; l < MM; l += PAIR)
     assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, b0 + l, 1, nullptr);
-  prepare_faces(a, I, J, kap, fc);
+  prepare_faces(a, fl, kap, fc);
   __syncthreads();
   robin_data(g, fc, bside);
   __syncthreads();
@@ -1078,11 +1102,12 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
   const int sd = blockIdx.x;
   const int I = sd % g.SX, J = sd / g.SX;
 
+  const FaceLoad fl = load_faces(a, I, J);
   load_kappa<M>(a, I, J, sh.kap);
   __syncthreads();
   for (int l = tid; l < MM; l += PAIR)
     assemble_cell<M, 1, false>(a, I, J, l, sh.kap, sh.dg, sh.ex, sh.cy, sh.b0 + l, 1, nullptr);
-  prepare_faces(a, I, J, sh.kap, sh.fc);
+  prepare_faces(a, fl, sh.kap, sh.fc);
   for (int l = tid; l < MM; l += PAIR) sh.dsc[l] = 1.0 / sqrt(sh.dg[l]);
   __syncthreads();
   robin_data(g, sh.fc, sh.bside);
@@ -1232,11 +1257,12 @@ __device__ inline double compose16(const SubArgs& a, int sd, int l, const double
   return p;
 }
 
-__global__ void __launch_bounds__(PAIR) stitch_pair_kernel(SubArgs a) {
+// four wavefronts per SIMD: 128 registers per lane and 19 KB of LDS per pair
+__global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
-  __shared__ double pm[MM], bs_[MM], ps[MM], rs[MM], dx[MM];
+  __shared__ double pm[MM], bs_[MM], ps[MM], rs[MM];
   __shared__ double Fout[4][M];
-  __shared__ double red[3][PAIR];
+  __shared__ double red[3][2];
   __shared__ double xch[M][M + 1];
   const Geo& g = a.g;
   // the wave index is uniform per wavefront: taken into a scalar register,
@@ -1328,8 +1354,8 @@ __global__ void __launch_bounds__(PAIR) stitch_pair_kernel(SubArgs a) {
       rs[l] = hi + lo;
     }
     __syncthreads();
-    solve_column_pair(Sv, w, rs, dx, c, gq, cy);
-    for (int l = tid; l < MM; l += PAIR) ps[l] += dx[l];
+    solve_column_pair(Sv, w, rs, rs, c, gq, cy);   // in place: each row is read before it is written
+    for (int l = tid; l < MM; l += PAIR) ps[l] += rs[l];
     __syncthreads();
   }
 
@@ -1372,22 +1398,23 @@ __global__ void __launch_bounds__(PAIR) stitch_pair_kernel(SubArgs a) {
     a.p_out[(size_t)j * g.nx + i] = pm[l];
     psum += pm[l];
   }
-  red[0][tid] = imb;
-  red[1][tid] = fmx;
-  red[2][tid] = psum;
-  __syncthreads();
-  for (int h = PAIR / 2; h > 0; h >>= 1) {
-    if (tid < h) {
-      red[0][tid] = fmax(red[0][tid], red[0][tid + h]);
-      red[1][tid] = fmax(red[1][tid], red[1][tid + h]);
-      red[2][tid] = red[2][tid] + red[2][tid + h];
-    }
-    __syncthreads();
+  // reductions over the wave (fixed butterfly order), then over the two waves
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    imb = fmax(imb, __shfl_xor(imb, off));
+    fmx = fmax(fmx, __shfl_xor(fmx, off));
+    psum += __shfl_xor(psum, off);
   }
+  if (lane == 0) {
+    red[0][w] = imb;
+    red[1][w] = fmx;
+    red[2][w] = psum;
+  }
+  __syncthreads();
   if (tid == 0) {
-    a.sub_stats[3 * sd + 0] = red[0][0];
-    a.sub_stats[3 * sd + 1] = red[1][0];
-    a.sub_stats[3 * sd + 2] = red[2][0];
+    a.sub_stats[3 * sd + 0] = fmax(red[0][0], red[0][1]);
+    a.sub_stats[3 * sd + 1] = fmax(red[1][0], red[1][1]);
+    a.sub_stats[3 * sd + 2] = red[2][0] + red[2][1];
   }
 }
 
@@ -1486,13 +1513,14 @@ __global__ void __launch_bounds__(WAVE) surrogate_gate_kernel(SubArgs a, const f
   const int lane = threadIdx.x, c = lane & 15, gq = lane >> 4;
   const int sd = blockIdx.x, I = sd % g.SX, J = sd / g.SX;
 
+  const FaceLoad fl = load_faces(a, I, J);
   load_kappa<M>(a, I, J, kap);
   __syncthreads();
   for (int l = lane; l < MM; l += WAVE)
     assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, b0 + l, 1, nullptr);
   const double kgeo = exp(mean_log_kappa(kap));
   if (lane < 4 * D) scale[lane] = column_scale(a, I, J, lane, kgeo);
-  prepare_faces(a, I, J, kap, fc);
+  prepare_faces(a, fl, kap, fc);
   __syncthreads();
   robin_data(g, fc, bside);
   __syncthreads();
