@@ -419,6 +419,14 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
   const int* dof = dofs + nd.dof_off;
   const double* rv = rtree ? rtree + nd.r_off : nullptr;   // rhs vector, else column n
   const int t = threadIdx.x;
+  // the separator's own U block (s x s, classic fronts up to US_MAX) goes to
+  // LDS with the ancestors' unknowns, so that the triangular solve below
+  // reads no global memory
+  constexpr int US_MAX = 32;
+  __shared__ double Us[US_MAX][US_MAX + 1];
+  const bool stage = !nd.blocked && s <= US_MAX;
+  if (stage)
+    for (int e = t; e < s * s; e += NT) Us[e / s][e % s] = F[(long long)(e / s) * ld + e % s];
   for (int m = s + t; m < n; m += NT) xl[m] = x[dof[m]];
   __syncthreads();
   if (!nd.blocked) {
@@ -435,12 +443,26 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
       if (k < s && lane == 0) xl[k] = v;
     }
     __syncthreads();
-    for (int k = s - 1; k >= 0; --k) {
-      const double xk = xl[k] / F[(long long)k * ld + k];
+    if (stage) {
+      // triangular solve by the first wavefront, lane i holding x_i
+      if (t < 64) {
+        double xi = t < s ? xl[t] : 0.0;
+        for (int k = s - 1; k >= 0; --k) {
+          const double xk = __shfl(xi, k) / Us[k][k];
+          if (t < k) xi -= Us[t][k] * xk;
+          if (t == k) xi = xk;
+        }
+        if (t < s) xl[t] = xi;
+      }
       __syncthreads();
-      for (int i = t; i < k; i += NT) xl[i] -= F[(long long)i * ld + k] * xk;
-      if (t == 0) xl[k] = xk;
-      __syncthreads();
+    } else {
+      for (int k = s - 1; k >= 0; --k) {
+        const double xk = xl[k] / F[(long long)k * ld + k];
+        __syncthreads();
+        for (int i = t; i < k; i += NT) xl[i] -= F[(long long)i * ld + k] * xk;
+        if (t == 0) xl[k] = xk;
+        __syncthreads();
+      }
     }
   } else {
     // one panel per step, last first; 8 lanes per panel row.  The panel's
