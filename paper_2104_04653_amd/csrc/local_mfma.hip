@@ -1502,72 +1502,104 @@ __global__ void __launch_bounds__(WAVE) surrogate_targets_kernel(SubArgs a, floa
 // would, a rejected one (or one with source or physical boundary data,
 // whose particular solution the network does not predict) is appended to
 // a.fallback for the FP64 kernel.
-__global__ void __launch_bounds__(WAVE) surrogate_gate_kernel(SubArgs a, const float* pred) {
+constexpr int GATE = 256;   // threads of the gate kernel: one per cell
+
+__global__ void __launch_bounds__(GATE) surrogate_gate_kernel(SubArgs a, const float* pred) {
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM];
   __shared__ double bside[4][M][D];
   __shared__ Faces fc;
   __shared__ double xb[4][M][R];
-  __shared__ double Xs[4 * D][MM];
+  __shared__ double Xs[4 * D][MM];        // decoded basis functions
   __shared__ double scale[4 * D];
+  __shared__ double part[GATE / WAVE][2][4 * D];
+  __shared__ int verdict;
   const Geo& g = a.g;
-  const int lane = threadIdx.x, c = lane & 15, gq = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int sd = blockIdx.x, I = sd % g.SX, J = sd / g.SX;
+  static_assert(GATE == MM, "one thread per cell");
 
   const FaceLoad fl = load_faces(a, I, J);
+  const float* pr = pred + (size_t)sd * MM * 4 * D;
+  // raw predictions, cell-major in memory: 16 per thread, coalesced (entry
+  // tid + k GATE is column tid % 16 of cell tid / 16 + 16 k)
+  float praw[4 * D];
+#pragma unroll
+  for (int k = 0; k < 4 * D; ++k) praw[k] = pr[tid + k * GATE];
   load_kappa<M>(a, I, J, kap);
   __syncthreads();
-  for (int l = lane; l < MM; l += WAVE)
-    assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, b0 + l, 1, nullptr);
-  const double kgeo = exp(mean_log_kappa(kap));
-  if (lane < 4 * D) scale[lane] = column_scale(a, I, J, lane, kgeo);
+  assemble_cell<M, 1, false>(a, I, J, tid, kap, dg, ex, cy, b0 + tid, 1, nullptr);
+  if (wv == 0) {
+    // the same geometric mean (same summation order) as the input and
+    // target builders
+    const double kgeo = exp(mean_log_kappa(kap));
+    if (lane < 4 * D) scale[lane] = column_scale(a, I, J, lane, kgeo);
+  }
   prepare_faces(a, fl, kap, fc);
   __syncthreads();
   robin_data(g, fc, bside);
-  __syncthreads();
-  bool particular = false;
-  for (int l = lane; l < MM; l += WAVE) particular |= b0[l] != 0.0;
-  const float* pr = pred + (size_t)sd * MM * 4 * D;
-  for (int o = lane; o < MM * 4 * D; o += WAVE) {
-    const int l = o / (4 * D), q = o % (4 * D);
-    const double s = scale[q];
-    Xs[q][l] = s != 0.0 ? (double)pr[o] / s : 0.0;
+  {
+    const int q = tid % (4 * D);
+    const double sc = scale[q];
+#pragma unroll
+    for (int k = 0; k < 4 * D; ++k) Xs[q][tid / (4 * D) + k * (GATE / (4 * D))] = sc != 0.0 ? (double)praw[k] / sc : 0.0;
   }
-  __syncthreads();
+  const int particular = __syncthreads_or(b0[tid] != 0.0);
 
-  // residual of column c over the rows gq*4 .. gq*4+3 of the subdomain
-  double r2 = 0.0, b2 = 0.0;
-  for (int j = 4 * gq; j < 4 * gq + 4; ++j) {
-    for (int i = 0; i < M; ++i) {
-      const int l = j * M + i;
-      const double b = side_rhs(bside, j, i, c);
-      double ax = dg[l] * Xs[c][l];
-      if (i < M - 1) ax += ex[l] * Xs[c][l + 1];
-      if (i > 0) ax += ex[l - 1] * Xs[c][l - 1];
-      if (j < M - 1) ax += cy[l] * Xs[c][l + M];
-      if (j > 0) ax += cy[l - M] * Xs[c][l - M];
-      const double r = b - ax;
-      r2 += r * r;
-      b2 += b * b;
+  // residual of every column at cell tid, squared norms per column
+  const int i = tid % M, j = tid / M;
+  const int le = i < M - 1 ? tid + 1 : tid, lw = i > 0 ? tid - 1 : tid;
+  const int ln = j < M - 1 ? tid + M : tid, ls = j > 0 ? tid - M : tid;
+  const double ce = i < M - 1 ? ex[tid] : 0.0, cw = i > 0 ? ex[lw] : 0.0;
+  const double cn = j < M - 1 ? cy[tid] : 0.0, cs = j > 0 ? cy[ls] : 0.0;
+  double r2[4 * D], b2[4 * D];
+#pragma unroll
+  for (int q = 0; q < 4 * D; ++q) {
+    double ax = dg[tid] * Xs[q][tid];
+    ax = fma(ce, Xs[q][le], ax);
+    ax = fma(cw, Xs[q][lw], ax);
+    ax = fma(cn, Xs[q][ln], ax);
+    ax = fma(cs, Xs[q][ls], ax);
+    const double bq = side_rhs(bside, j, i, q);
+    const double r = bq - ax;
+    r2[q] = wave_sum(r * r);
+    b2[q] = wave_sum(bq * bq);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < 4 * D; ++q) {
+      part[wv][0][q] = r2[q];
+      part[wv][1][q] = b2[q];
     }
   }
-  r2 += __shfl_xor(r2, 16);
-  r2 += __shfl_xor(r2, 32);
-  b2 += __shfl_xor(b2, 16);
-  b2 += __shfl_xor(b2, 32);
-  const bool ok = isfinite(r2) && r2 <= a.gate_tol * a.gate_tol * b2;
-  const bool accept = __all(ok) && !__any(particular);
-  if (!accept) {
-    if (lane == 0) {
-      const int q = atomicAdd(a.fallback, 1);
-      a.fallback[1 + q] = sd;
+  __syncthreads();
+  if (tid < WAVE) {
+    bool ok = true;
+    if (tid < 4 * D) {
+      double rr = 0.0, bb = 0.0;
+      for (int w = 0; w < GATE / WAVE; ++w) {
+        rr += part[w][0][tid];
+        bb += part[w][1][tid];
+      }
+      ok = isfinite(rr) && rr <= a.gate_tol * a.gate_tol * bb;
     }
-    return;
+    const bool accept = __all(ok) && !particular;
+    if (tid == 0) {
+      verdict = accept;
+      if (!accept) {
+        const int q = atomicAdd(a.fallback, 1);
+        a.fallback[1 + q] = sd;
+      }
+    }
   }
+  __syncthreads();
+  if (!verdict) return;
 
+  // accepted: the decoded basis block and the interface block
   double* Xg = a.X + (size_t)sd * R * MM;
-  for (int l = lane; l < MM; l += WAVE) Xg[l] = 0.0;   // no particular data
-  for (int o = lane; o < 4 * D * MM; o += WAVE) Xg[MM + o] = Xs[o / MM][o % MM];
-  for (int o = lane; o < 4 * M * R; o += WAVE) {
+  Xg[tid] = 0.0;   // no particular data
+#pragma unroll
+  for (int q = 0; q < 4 * D; ++q) Xg[(size_t)(1 + q) * MM + tid] = Xs[q][tid];
+  for (int o = tid; o < 4 * M * R; o += GATE) {
     const int side = o / (M * R), t = (o / R) % M, col = o % R;
     double v = 0.0;
     if (col > 0) {
@@ -1613,7 +1645,7 @@ hipError_t launch_surrogate_targets(const SubArgs& a, float* targets, hipStream_
 }
 
 hipError_t launch_surrogate_gate(const SubArgs& a, const float* pred, hipStream_t st) {
-  hipLaunchKernelGGL(surrogate_gate_kernel, dim3(a.g.n_sub), dim3(WAVE), 0, st, a, pred);
+  hipLaunchKernelGGL(surrogate_gate_kernel, dim3(a.g.n_sub), dim3(GATE), 0, st, a, pred);
   return hipGetLastError();
 }
 
