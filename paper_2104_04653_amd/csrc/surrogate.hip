@@ -57,11 +57,14 @@ constexpr int kpad() { return (9 * C + 15) / 16 * 16; }
 // load one patch (NPIX x C, channels-last) into an LDS tile with a zero halo
 template <int C>
 __device__ void load_halo(const short* src, short* Xs) {
-  for (int e = threadIdx.x; e < HALO * HALO * C; e += NT) Xs[e] = 0;
+  static_assert(C % 4 == 0, "four channels per 8-byte move");
+  s4* X4 = reinterpret_cast<s4*>(Xs);
+  const s4* S4 = reinterpret_cast<const s4*>(src);
+  for (int e = threadIdx.x; e < HALO * HALO * C / 4; e += NT) X4[e] = s4{0, 0, 0, 0};
   __syncthreads();
-  for (int e = threadIdx.x; e < NPIX * C; e += NT) {
-    const int p = e / C, c = e % C;
-    Xs[((p / HW + 1) * HALO + p % HW + 1) * C + c] = src[e];
+  for (int e = threadIdx.x; e < NPIX * C / 4; e += NT) {
+    const int p = e / (C / 4), c4 = e % (C / 4);
+    X4[((p / HW + 1) * HALO + p % HW + 1) * (C / 4) + c4] = S4[e];
   }
 }
 
@@ -72,38 +75,62 @@ template <int CIN, int COUT, bool RELU, bool OUTF32>
 __global__ void __launch_bounds__(NT) conv_fwd_kernel(const short* in, const short* W,
                                                       const float* bias, short* out_bf,
                                                       float* out_f) {
-  constexpr int KP = kpad<CIN>();
+  // Each wave keeps the weight fragments of all output-channel tiles in
+  // registers (read once from the LDS copy of the weights), reads each
+  // input fragment once from LDS for all of them, and stores four
+  // consecutive channels of a pixel per lane in one write.
+  constexpr int KP = kpad<CIN>(), NK = KP / 16, MT = COUT / 16;
   __shared__ __attribute__((aligned(16))) short Xs[HALO * HALO * CIN];
   __shared__ __attribute__((aligned(16))) short Ws[COUT * KP];
   const int b = blockIdx.x;
-  for (int e = threadIdx.x; e < COUT * KP; e += NT) Ws[e] = W[e];
-  load_halo<CIN>(in + (size_t)b * NPIX * CIN, Xs);
-  __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x = lane & 15, g = lane >> 4;
-  for (int mt = 0; mt < COUT / 16; ++mt) {
-    for (int yy = 0; yy < 4; ++yy) {
-      const int y = wv * 4 + yy;
-      f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-      for (int kk = 0; kk < KP / 16; ++kk) {
-        const int k0 = 16 * kk + 4 * g, tap = k0 / CIN, ci = k0 % CIN;
-        s4 bv = {0, 0, 0, 0};
-        if (tap < 9) {
-          const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-          bv = *reinterpret_cast<const s4*>(&Xs[((y + dy + 1) * HALO + x + dx + 1) * CIN + ci]);
-        }
-        const s4 av = *reinterpret_cast<const s4*>(&Ws[(mt * 16 + x) * KP + k0]);
-        acc = mma(av, bv, acc);
+  for (int e = threadIdx.x; e < COUT * KP / 4; e += NT)   // coalesced 8-byte copies
+    reinterpret_cast<s4*>(Ws)[e] = reinterpret_cast<const s4*>(W)[e];
+  load_halo<CIN>(in + (size_t)b * NPIX * CIN, Xs);
+  float bv4[MT][4];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) bv4[mt][v] = bias[mt * 16 + 4 * g + v];
+  __syncthreads();
+  s4 av[MT][NK];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk)
+      av[mt][kk] = *reinterpret_cast<const s4*>(&Ws[(mt * 16 + x) * KP + 16 * kk + 4 * g]);
+  for (int yy = 0; yy < 4; ++yy) {
+    const int y = wv * 4 + yy;
+    f4 acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const int k0 = 16 * kk + 4 * g, tap = k0 / CIN, ci = k0 % CIN;
+      s4 bv = {0, 0, 0, 0};
+      if (tap < 9) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        bv = *reinterpret_cast<const s4*>(&Xs[((y + dy + 1) * HALO + x + dx + 1) * CIN + ci]);
       }
-      const int p = y * HW + x;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = mma(av[mt][kk], bv, acc[mt]);
+    }
+    const size_t p = (size_t)b * NPIX + y * HW + x;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      float val[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int co = mt * 16 + 4 * g + v;
-        float val = acc[v] + bias[co];
-        if (RELU) val = fmaxf(val, 0.f);
-        if (OUTF32) out_f[((size_t)b * NPIX + p) * COUT + co] = val;
-        else out_bf[((size_t)b * NPIX + p) * COUT + co] = f2bf(val);
+        val[v] = acc[mt][v] + bv4[mt][v];
+        if (RELU) val[v] = fmaxf(val[v], 0.f);
+      }
+      const int co = mt * 16 + 4 * g;
+      if (OUTF32) {
+        *reinterpret_cast<f4*>(&out_f[p * COUT + co]) = f4{val[0], val[1], val[2], val[3]};
+      } else {
+        *reinterpret_cast<s4*>(&out_bf[p * COUT + co]) =
+            s4{f2bf(val[0]), f2bf(val[1]), f2bf(val[2]), f2bf(val[3])};
       }
     }
   }
