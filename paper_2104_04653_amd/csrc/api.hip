@@ -30,7 +30,6 @@ struct LevelPlan {
   bool small;
   int max_n, max_s;
   int ids_off, count;
-  int gather_off, gather_count;
   std::vector<PanelLaunch> panels;
 };
 
@@ -66,7 +65,6 @@ struct mrcm_ctx {
   int2* d_maps = nullptr;
   int* d_dofs = nullptr;
   int* d_ids = nullptr;
-  GatherItem* d_gather = nullptr;
   NodeDesc* d_lvnodes = nullptr;  // node descriptors in level order (ids order)
   PanelItem* d_items = nullptr;
   double* inv = nullptr;        // per-panel diagonal-block inverses of blocked fronts
@@ -280,7 +278,6 @@ int build_plan(mrcm_ctx* c) {
   std::vector<NodeDesc> desc;
   std::vector<int2> maps;
   std::vector<int> dofs, ids;
-  std::vector<GatherItem> gather;
   std::vector<PanelItem> items;
   std::vector<std::vector<int>> panel_ids;
   std::vector<int> node_desc(tb.nodes.size(), -1);
@@ -350,13 +347,6 @@ int build_plan(mrcm_ctx* c) {
     if (lp.max_s > 2048) return fail(c, MRCM_E_UNSUPPORTED, "interface separator too large");
     lp.small = lp.max_n <= SMALL_FRONT;
     if (!lp.small) {
-      lp.gather_off = (int)gather.size();
-      for (int q = 0; q < lp.count; ++q) {
-        const NodeDesc& d = desc[ids[lp.ids_off + q]];
-        gather.push_back(GatherItem{d, -1, 0});   // first diagonal block
-        for (int r = 0; r < d.n; r += GATHER_ROWS) gather.push_back(GatherItem{d, r, 0});
-      }
-      lp.gather_count = (int)gather.size() - lp.gather_off;
       for (int k0 = 0; k0 < lp.max_s; k0 += PANEL_NB) {
         PanelLaunch pl{};
         pl.k0 = k0;
@@ -375,6 +365,13 @@ int build_plan(mrcm_ctx* c) {
             for (int cc = k0 + nb; cc <= d.n; cc += TILE)
               items.push_back(PanelItem{id, r, cc, (next && r == k0 + nb && cc == k0 + nb) ? 1 : 0,
                                         d.n, d.s, d.f_off, d.inv_off});
+          if (k0 == 0 && d.n == nb) {
+            // the first panel assembles the front; without trailing tiles
+            // (which store the panel's rows as they read them) its rows
+            // are stored by items of their own
+            for (int cc = 0; cc <= d.n; cc += TILE)
+              items.push_back(PanelItem{id, 0, cc, 3, d.n, d.s, d.f_off, d.inv_off});
+          }
         }
         pl.update_count = (int)items.size() - pl.update_off;
         // the items that update and invert the next diagonal blocks first:
@@ -410,7 +407,6 @@ int build_plan(mrcm_ctx* c) {
   ALLOC(c, c->d_dofs, dofs.size());
   ALLOC(c, c->d_ids, ids.size());
   ALLOC(c, c->d_lvnodes, ids.size());
-  ALLOC(c, c->d_gather, gather.size());
   ALLOC(c, c->d_items, items.size());
   HIPCHK(c, hipMemcpy(c->d_nodes, desc.data(), desc.size() * sizeof(NodeDesc), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_maps, maps.data(), maps.size() * sizeof(int2), hipMemcpyHostToDevice));
@@ -421,8 +417,6 @@ int build_plan(mrcm_ctx* c) {
     for (size_t k = 0; k < ids.size(); ++k) lv[k] = desc[ids[k]];
     HIPCHK(c, hipMemcpy(c->d_lvnodes, lv.data(), lv.size() * sizeof(NodeDesc), hipMemcpyHostToDevice));
   }
-  if (!gather.empty())
-    HIPCHK(c, hipMemcpy(c->d_gather, gather.data(), gather.size() * sizeof(GatherItem), hipMemcpyHostToDevice));
   if (!items.empty())
     HIPCHK(c, hipMemcpy(c->d_items, items.data(), items.size() * sizeof(PanelItem), hipMemcpyHostToDevice));
   return MRCM_OK;
@@ -472,13 +466,12 @@ int run_interface(mrcm_ctx* c) {
                                    c->d_maps, c->status, st));
       continue;
     }
-    // the gather inverts the first panel's diagonal block, each update the next one
-    HIPCHK(c, launch_front_gather(c->d_gather + lp.gather_off, lp.gather_count, c->tree, c->d_maps,
-                                  c->inv, c->status, st));
+    // the first panel assembles the fronts and inverts its own diagonal
+    // block; each panel inverts the next one
     for (const PanelLaunch& pl : lp.panels)
       if (pl.update_count > 0)   // the root's last panel has no trailing rows
         HIPCHK(c, launch_front_update(c->d_nodes, c->d_items + pl.update_off, pl.update_count,
-                                      pl.k0, c->tree, c->inv, c->status, st));
+                                      pl.k0, c->tree, c->d_maps, c->inv, c->status, st));
   }
   for (auto it = c->levels.rbegin(); it != c->levels.rend(); ++it)
     HIPCHK(c, launch_front_back(c->d_lvnodes + it->ids_off, it->count, c->tree, c->inv, c->d_dofs,

@@ -15,16 +15,16 @@
 // themselves, so the global matrix is never formed.
 //
 // Fronts of up to SMALL_FRONT unknowns are gathered and eliminated by one
-// work-group in LDS.  Larger fronts (the few nodes near the root) are
-// gathered in global memory and eliminated by a right-looking blocked LU:
-// the gather also inverts the first panel's diagonal block A11; then one launch
-// per panel of PANEL_NB columns applies the trailing update
-// A22 -= A21 (A11^-1 A12) in 64 x 64 tiles on the FP64 matrix cores, and the
-// work-group whose tile starts with the next panel's diagonal block inverts
-// it (two 16 x 16 Gauss-Jordan inversions without pivoting, which the
-// quasi-definite structure allows, joined by a Schur complement) and stores
-// the inverse.  Back substitution runs top down, one
-// work-group per node.
+// work-group in LDS.  Larger fronts (the nodes near the root) are
+// eliminated in global memory by a right-looking blocked LU, one launch
+// per panel of PANEL_NB columns: the trailing update A22 -= A21 (A11^-1 A12)
+// in 64 x 64 tiles on the FP64 matrix cores, with the next panel's
+// diagonal block updated and inverted by a work-group of its own (two
+// 16 x 16 Gauss-Jordan inversions without pivoting, which the
+// quasi-definite structure allows, joined by a Schur complement).  The first
+// panel's launch also assembles the fronts: its work-groups read their
+// operands straight from the children and write the assembled front.
+// Back substitution runs top down, one work-group per node.
 #include "mrcm_internal.h"
 
 #include <math.h>
@@ -35,17 +35,19 @@ namespace {
 
 constexpr int NT = 256;
 
+// entry of a front from its two children (extend-add).  Both children's
+// entries are loaded unconditionally (from the start of the tree buffer
+// when the unknown is not the child's) and selected afterwards: a branch
+// around each load would make every load wait for the one before it.
 __device__ inline double gather_entry(const NodeDesc& nd, const double* tree, int2 ma, int2 mb,
                                       bool rhs) {
-  double v = 0.0;
-  if (!rhs) {
-    if (ma.x >= 0 && mb.x >= 0) v += tree[nd.c_off[0] + (long long)ma.x * nd.c_ld[0] + mb.x];
-    if (ma.y >= 0 && mb.y >= 0) v += tree[nd.c_off[1] + (long long)ma.y * nd.c_ld[1] + mb.y];
-  } else {
-    if (ma.x >= 0) v += tree[nd.c_off[0] + (long long)ma.x * nd.c_ld[0] + nd.c_rhs[0]];
-    if (ma.y >= 0) v += tree[nd.c_off[1] + (long long)ma.y * nd.c_ld[1] + nd.c_rhs[1]];
-  }
-  return v;
+  const bool u0 = ma.x >= 0 && (rhs || mb.x >= 0), u1 = ma.y >= 0 && (rhs || mb.y >= 0);
+  const long long i0 =
+      u0 ? nd.c_off[0] + (long long)ma.x * nd.c_ld[0] + (rhs ? nd.c_rhs[0] : mb.x) : 0;
+  const long long i1 =
+      u1 ? nd.c_off[1] + (long long)ma.y * nd.c_ld[1] + (rhs ? nd.c_rhs[1] : mb.y) : 0;
+  const double x0 = tree[i0], x1 = tree[i1];
+  return (u0 ? x0 : 0.0) + (u1 ? x1 : 0.0);
 }
 
 // double-double accumulation: (hi, lo) += v, and (hi, lo) -= a b
@@ -66,37 +68,54 @@ __device__ inline void two_prod_sub(double& hi, double& lo, double a, double b) 
 // 32 columns x 8 rows per pass.
 constexpr int TXN = 32, TYN = NT / TXN;
 
+// entries of a small front (and its rhs column) per thread, at most
+constexpr int SMALL_PER_T = (SMALL_FRONT * (SMALL_FRONT + 1) + NT - 1) / NT;
+
+// PER: entries per thread, enough for the level's largest front
+template <int PER>
 __global__ void __launch_bounds__(NT) front_small_kernel(const NodeDesc* nodes, double* tree,
                                                          const int2* maps, int* status) {
   extern __shared__ double F[];
   __shared__ int2 mp[SMALL_FRONT];
   const NodeDesc nd = nodes[blockIdx.x];   // this level's fronts, one per work-group
-  const int n = nd.n, s = nd.s, ld = n + 1;
+  const int n = nd.n, s = nd.s, ld = n + 1, ne = n * ld;
   const int tid = threadIdx.x, tx = tid % TXN, ty = tid / TXN;
   for (int a = tid; a < n; a += NT) mp[a] = maps[nd.map_off + a];
   __syncthreads();
-  for (int a = ty; a < n; a += TYN) {
-    const int2 ma = mp[a];
-#pragma unroll 4
-    for (int b = tx; b <= n; b += TXN) F[a * ld + b] = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
+  // all of a thread's entries are read before any is stored, so that their
+  // loads are in flight together.  Entry e = a ld + b; a = e / ld is taken in
+  // single precision: e < 2^13 and e / ld is at least 1 / (2 ld) away from
+  // the next integer, far more than the rounding of the product.
+  const float ild = 1.0f / (float)ld;
+  double v[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + NT * i;
+    const int a = min((int)(((float)e + 0.5f) * ild), n - 1), b = min(e - a * ld, n);
+    const double x = gather_entry(nd, tree, mp[a], b < n ? mp[b] : mp[a], b == n);
+    v[i] = e < ne ? x : 0.0;   // beyond the front: a valid entry read and dropped
   }
+#pragma unroll
+  for (int i = 0; i < PER; ++i)
+    if (tid + NT * i < ne) F[tid + NT * i] = v[i];
   __syncthreads();
+  // one barrier per pivot: row a is updated by one half-wavefront (TXN = 32
+  // lanes), whose lanes all read the entry under the pivot before its lane 0
+  // replaces it by the multiplier (program order within the wavefront)
   bool bad = false;
   for (int k = 0; k < s; ++k) {
     const double piv = F[k * ld + k];
     if (piv == 0.0 || !isfinite(piv)) bad = true;
     const double ip = 1.0 / piv;
-    for (int a = k + 1 + tid; a < n; a += NT) F[a * ld + k] *= ip;
-    __syncthreads();
     for (int a = k + 1 + ty; a < n; a += TYN) {
-      const double f = F[a * ld + k];
+      const double f = F[a * ld + k] * ip;
       for (int b = k + 1 + tx; b <= n; b += TXN) F[a * ld + b] -= f * F[k * ld + b];
+      if (tx == 0) F[a * ld + k] = f;
     }
     __syncthreads();
   }
   double* out = tree + nd.f_off;
-  for (int a = ty; a < n; a += TYN)
-    for (int b = tx; b <= n; b += TXN) out[(long long)a * ld + b] = F[a * ld + b];
+  for (int e = tid; e < ne; e += NT) out[e] = F[e];
   if (bad && tid == 0) atomicOr(status, ST_IFACE_PIVOT);
 }
 
@@ -178,6 +197,9 @@ __device__ inline d4 gj16(d4 s, int c, int g, bool& bad) {
 // output layout are read from the lane's own registers; X^T as a left
 // factor comes from one transpose through `T`.  The pivots of the two 16 x 16
 // inversions are the pivots of an LU factorisation of A.
+// The result goes to out with row stride LDO; out may be S itself (stride
+// PANEL_NB + 1): S is read in full before anything is written.
+template <int LDO>
 __device__ void inv32_wave(const double (*S)[PANEL_NB + 1], double (*T)[17], double* out,
                            bool& bad) {
   static_assert(PANEL_NB == 32, "two 16 x 16 tiles per side");
@@ -214,55 +236,15 @@ __device__ void inv32_wave(const double (*S)[PANEL_NB + 1], double (*T)[17], dou
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int r = 4 * v + g;
-    out[r * PANEL_NB + c] = U[v];
-    out[(16 + r) * PANEL_NB + c] = -L[v];
-    out[c * PANEL_NB + 16 + r] = -L[v];
-    out[(16 + r) * PANEL_NB + 16 + c] = Ci[v];
+    out[r * LDO + c] = U[v];
+    out[(16 + r) * LDO + c] = -L[v];
+    out[c * LDO + 16 + r] = -L[v];
+    out[(16 + r) * LDO + 16 + c] = Ci[v];
   }
 }
 
 __device__ inline double* panel_inv(double* inv, const NodeDesc& nd, int k0) {
   return inv + nd.inv_off + (long long)(k0 / PANEL_NB) * PANEL_NB * PANEL_NB;
-}
-
-// items: (node index, first row); each work-group gathers GATHER_ROWS rows
-// of a blocked front.  An item with first row -1 instead gathers the
-// diagonal block of the front's first panel into LDS and inverts it.
-__global__ void __launch_bounds__(NT) front_gather_kernel(const GatherItem* items, double* tree,
-                                                          const int2* maps, double* inv,
-                                                          int* status) {
-  __shared__ double A[PANEL_NB][PANEL_NB + 1];
-  __shared__ double Tt[16][17];
-  static_assert(GATHER_ROWS == NT / TXN, "one row per thread row");
-  __shared__ int2 mp[MAX_FRONT];
-  const GatherItem gi = items[blockIdx.x];   // carries its front's descriptor
-  const NodeDesc& nd = gi.nd;
-  const int n = nd.n, ld = n + 1;
-  const int tx = threadIdx.x % TXN, ty = threadIdx.x / TXN;
-  for (int a = threadIdx.x; a < (gi.row < 0 ? min(n, PANEL_NB) : n); a += NT) mp[a] = maps[nd.map_off + a];
-  __syncthreads();
-  if (gi.row < 0) {
-    const int nb = min(PANEL_NB, nd.s);
-#pragma unroll
-    for (int a = ty; a < PANEL_NB; a += TYN) {
-      double v = (a == tx) ? 1.0 : 0.0;
-      if (a < nb && tx < nb) v = gather_entry(nd, tree, mp[a], mp[tx], false);
-      A[a][tx] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      bool bad = false;
-      inv32_wave(A, Tt, panel_inv(inv, nd, 0), bad);
-      if (bad) atomicOr(status, ST_IFACE_PIVOT);
-    }
-    return;
-  }
-  const int a = gi.row + ty;
-  if (a >= n) return;
-  double* F = tree + nd.f_off + (long long)a * ld;
-  const int2 ma = mp[a];
-#pragma unroll 8
-  for (int b = tx; b <= n; b += TXN) F[b] = gather_entry(nd, tree, ma, b < n ? mp[b] : ma, b == n);
 }
 
 // Trailing update of panel k0 for one 64 x 64 tile of a blocked front,
@@ -276,19 +258,30 @@ __global__ void __launch_bounds__(NT) front_gather_kernel(const GatherItem* item
 // it is updated and inverted by an item of its own (kind 2, a 32 x 32 tile
 // with one 16 x 16 product tile per wavefront, dispatched first), and the
 // 64 x 64 tile that contains it (kind 1) leaves it out.
+// FIRST: the first panel, fused with the assembly of the front from its
+// children (extend-add: a parent's system is the sum of its children's
+// Schur complements over the shared unknowns).  Every item reads the
+// entries it needs straight from the children, inverts the panel's
+// diagonal block itself (one wavefront, in LDS), and writes its tile of the
+// assembled and updated front; the tiles next to the panel also store the
+// panel's rows and columns as assembled.  Kind 3 items do that for a front
+// without trailing rows (a 64-column stretch of the panel rows; the one at
+// (0, 0) also stores the diagonal block's inverse).
+template <bool FIRST>
 __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
                                                           const PanelItem* items, int k0,
-                                                          double* tree, double* inv,
-                                                          int* status) {
+                                                          double* tree, const int2* maps,
+                                                          double* inv, int* status) {
   __shared__ double Dv[PANEL_NB][PANEL_NB + 1];   // A11^-1; then the next diagonal block
   __shared__ double As[TILE][PANEL_NB + 1];       // A21 rows of the tile
-  __shared__ double Bs[PANEL_NB][TILE + 1];       // A12 columns of the tile
-  __shared__ double Ws[PANEL_NB][TILE + 1];       // W = A11^-1 A12
+  __shared__ double Bs[PANEL_NB][TILE + 1];       // A12 columns of the tile; then W = A11^-1 A12
   __shared__ double Tt[16][17];
+  __shared__ int2 mr[TILE], mc[TILE], mk[PANEL_NB];   // FIRST: maps of rows, columns, panel
   static_assert(TILE == 64 && PANEL_NB == 32 && NT == 256, "tile shape of the MFMA mapping");
   const PanelItem it = items[blockIdx.x];   // carries the front's fields: one load round
   const int kind = it.pad;                  // 0: tile, 1: tile without its leading diagonal
-                                            // block, 2: that block alone (then inverted)
+                                            // block, 2: that block alone (then inverted),
+                                            // 3 (FIRST): panel rows or columns, stored
   const int n = it.n, ld = n + 1;
   const int nb = min(PANEL_NB, it.s - k0);
   const int nb1 = min(PANEL_NB, it.s - (k0 + nb));   // next panel's width (kinds 1, 2)
@@ -296,41 +289,157 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
   const double* iv = inv + it.inv_off + (long long)(k0 / PANEL_NB) * PANEL_NB * PANEL_NB;
   const int t = threadIdx.x;
   const int r0 = it.i0, c0 = it.j0;
-  const int rows = kind == 2 ? nb1 : min(TILE, n - r0), cols = kind == 2 ? nb1 : min(TILE, ld - c0);
+  int rows = kind == 2 ? nb1 : min(TILE, n - r0), cols = kind == 2 ? nb1 : min(TILE, ld - c0);
   const int w = t >> 6, lane = t & 63, c = lane & 15, g = lane >> 4;
+  NodeDesc nd;
+  if constexpr (FIRST) {
+    nd = nodes[it.node];
+    const int2* mp = maps + nd.map_off;
+    if (t < TILE) mr[t] = mp[min(r0 + t, n - 1)];
+    else if (t < 2 * TILE) mc[t - TILE] = mp[min(c0 + t - TILE, n - 1)];   // column n: the rhs
+    else if (t < 2 * TILE + PANEL_NB) mk[t - 2 * TILE] = mp[min(t - 2 * TILE, n - 1)];
+    __syncthreads();
+  }
+  // entry (r0 + i, c0 + j) of the front at the start of the panel
+  auto a22_at = [&](int i, int j) -> double {
+    if constexpr (FIRST) return gather_entry(nd, tree, mr[i], mc[j], c0 + j == n);
+    else return F[(long long)(r0 + i) * ld + c0 + j];
+  };
+  if constexpr (FIRST) {
+    if (kind == 3) {
+      if (r0 == 0) rows = nb; else cols = nb;   // panel rows / panel columns
+      constexpr int PER = TILE * TILE / NT;
+      double v[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = t + NT * q, i = e / TILE, j = e % TILE;
+        const double x = a22_at(min(i, rows - 1), min(j, cols - 1));
+        v[q] = (i < rows && j < cols) ? x : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = t + NT * q, i = e / TILE, j = e % TILE;
+        if (i < rows && j < cols) F[(long long)(r0 + i) * ld + c0 + j] = v[q];
+      }
+      if (r0 == 0 && c0 == 0) {
+        constexpr int PD = PANEL_NB * PANEL_NB / NT;
+        double xd[PD];
+#pragma unroll
+        for (int q = 0; q < PD; ++q) {
+          const int e = t + NT * q, i = min(e / PANEL_NB, nb - 1), k = min(e % PANEL_NB, nb - 1);
+          xd[q] = gather_entry(nd, tree, mk[i], mk[k], false);
+        }
+#pragma unroll
+        for (int q = 0; q < PD; ++q) {
+          const int e = t + NT * q, i = e / PANEL_NB, k = e % PANEL_NB;
+          Dv[i][k] = (i < nb && k < nb) ? xd[q] : (i == k ? 1.0 : 0.0);
+        }
+        __syncthreads();
+        if (t < 64) {
+          bool bad = false;
+          inv32_wave<PANEL_NB>(Dv, Tt, inv + it.inv_off, bad);
+          if (bad) atomicOr(status, ST_IFACE_PIVOT);
+        }
+      }
+      return;
+    }
+  }
   // this thread's entries of the A22 tile, loaded with the operands (kind 2:
-  // wave w owns the 16 x 16 tile (w / 2, w % 2), in a22[0])
+  // wave w owns the 16 x 16 tile (w / 2, w % 2), in a22[0]).  Every load
+  // below is issued unconditionally, from an index clamped into the block,
+  // and entries outside it are dropped afterwards: a branch around a load
+  // would make each load wait for the previous one.
   double a22[4][4];
-  if (kind == 2) {
+  const bool k2 = kind == 2;
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = 16 * (w >> 1) + 4 * v + g, j = 16 * (w & 1) + c;
-      a22[0][v] = (i < rows && j < cols) ? F[(long long)(r0 + i) * ld + c0 + j] : 0.0;
+      // kind 2 reads its one tile four times over: the loads stay unconditional
+      const int i = (k2 ? 16 * (w >> 1) : 16 * w) + 4 * v + g, j = (k2 ? 16 * (w & 1) : 16 * tj) + c;
+      const double x = a22_at(min(i, rows - 1), min(j, cols - 1));
+      a22[tj][v] = (i < rows && j < cols) ? x : 0.0;
     }
-  } else {
+  }
+  // the panel operands: A11 (first panel: gathered, identity beyond its
+  // width, and inverted in place below; else its stored inverse), and the
+  // A21 rows and A12 columns of the tile, all loaded before any is stored
+  constexpr int PD = PANEL_NB * PANEL_NB / NT, PA = TILE * PANEL_NB / NT;
+  double xd[PD], xa[PA], xb[PA];
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj) {
+  for (int q = 0; q < PD; ++q) {
+    const int e = t + NT * q, i = min(e / PANEL_NB, nb - 1), k = min(e % PANEL_NB, nb - 1);
+    if constexpr (FIRST) xd[q] = gather_entry(nd, tree, mk[i], mk[k], false);
+    else xd[q] = iv[i * PANEL_NB + k];
+  }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * w + 4 * v + g, j = 16 * tj + c;
-        a22[tj][v] = (i < rows && j < cols) ? F[(long long)(r0 + i) * ld + c0 + j] : 0.0;
+  for (int q = 0; q < PA; ++q) {
+    const int e = t + NT * q, i = min(e / PANEL_NB, rows - 1), k = min(e % PANEL_NB, nb - 1);
+    if constexpr (FIRST) xa[q] = gather_entry(nd, tree, mr[i], mk[k], false);
+    else xa[q] = F[(long long)(r0 + i) * ld + k0 + k];
+  }
+#pragma unroll
+  for (int q = 0; q < PA; ++q) {
+    const int e = t + NT * q, k = min(e / TILE, nb - 1), j = min(e % TILE, cols - 1);
+    if constexpr (FIRST) xb[q] = gather_entry(nd, tree, mk[k], mc[j], c0 + j == n);
+    else xb[q] = F[(long long)(k0 + k) * ld + c0 + j];
+  }
+#pragma unroll
+  for (int q = 0; q < PD; ++q) {
+    const int e = t + NT * q, i = e / PANEL_NB, k = e % PANEL_NB;
+    Dv[i][k] = (i < nb && k < nb) ? xd[q] : ((FIRST && i == k) ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int q = 0; q < PA; ++q) {
+    const int e = t + NT * q, i = e / PANEL_NB, k = e % PANEL_NB;
+    As[i][k] = (i < rows && k < nb) ? xa[q] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < PA; ++q) {
+    const int e = t + NT * q, k = e / TILE, j = e % TILE;
+    Bs[k][j] = (k < nb && j < cols) ? xb[q] : 0.0;
+  }
+  if constexpr (FIRST) {
+    // the panel's own rows and columns, as assembled: the first tile row
+    // stores the A12 columns it read, the first tile column the A21 rows,
+    // the tile at (nb, nb) also A11 and, once inverted, its inverse
+    const bool lead = kind != 2 && r0 == nb && c0 == nb;
+    if (kind != 2 && c0 == nb) {
+#pragma unroll
+      for (int q = 0; q < PA; ++q) {
+        const int e = t + NT * q, i = e / PANEL_NB, k = e % PANEL_NB;
+        if (i < rows && k < nb) F[(long long)(r0 + i) * ld + k] = xa[q];
       }
     }
-  }
+    if (kind != 2 && r0 == nb) {
 #pragma unroll
-  for (int e = t; e < PANEL_NB * PANEL_NB; e += NT) {
-    const int i = e / PANEL_NB, k = e % PANEL_NB;
-    Dv[i][k] = (i < nb && k < nb) ? iv[e] : 0.0;
-  }
+      for (int q = 0; q < PA; ++q) {
+        const int e = t + NT * q, k = e / TILE, j = e % TILE;
+        if (k < nb && j < cols) F[(long long)k * ld + c0 + j] = xb[q];
+      }
+    }
+    if (lead) {
 #pragma unroll
-  for (int e = t; e < TILE * PANEL_NB; e += NT) {
-    const int i = e / PANEL_NB, k = e % PANEL_NB;
-    As[i][k] = (i < rows && k < nb) ? F[(long long)(r0 + i) * ld + k0 + k] : 0.0;
-  }
+      for (int q = 0; q < PD; ++q) {
+        const int e = t + NT * q, i = e / PANEL_NB, k = e % PANEL_NB;
+        if (i < nb && k < nb) F[(long long)i * ld + k] = xd[q];
+      }
+    }
+    __syncthreads();
+    if (t < 64) {
+      bool bad = false;
+      inv32_wave<PANEL_NB + 1>(Dv, Tt, &Dv[0][0], bad);
+      if (lead && bad) atomicOr(status, ST_IFACE_PIVOT);
+    }
+    if (lead) {
+      __syncthreads();
+      double* out = inv + it.inv_off;
 #pragma unroll
-  for (int e = t; e < PANEL_NB * TILE; e += NT) {
-    const int k = e / TILE, j = e % TILE;
-    Bs[k][j] = (k < nb && j < cols) ? F[(long long)(k0 + k) * ld + c0 + j] : 0.0;
+      for (int q = 0; q < PD; ++q) {
+        const int e = t + NT * q;
+        out[e] = Dv[e / PANEL_NB][e % PANEL_NB];
+      }
+    }
   }
   __syncthreads();
   if (kind == 2) {
@@ -339,12 +448,13 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
     d4 wv = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < PANEL_NB / 4; ++q) wv = mfma64(Dv[16 * ti + c][4 * q + g], Bs[4 * q + g][16 * tj + c], wv);
+    __syncthreads();   // W replaces A12
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Ws[16 * ti + 4 * v + g][16 * tj + c] = wv[v];
+    for (int v = 0; v < 4; ++v) Bs[16 * ti + 4 * v + g][16 * tj + c] = wv[v];
     __syncthreads();
     d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < PANEL_NB / 4; ++q) acc = mfma64(As[16 * ti + c][4 * q + g], Ws[4 * q + g][16 * tj + c], acc);
+    for (int q = 0; q < PANEL_NB / 4; ++q) acc = mfma64(As[16 * ti + c][4 * q + g], Bs[4 * q + g][16 * tj + c], acc);
     __syncthreads();   // Dv is reused below
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -359,7 +469,8 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
     __syncthreads();
     if (t < 64) {
       bool bad = false;
-      inv32_wave(Dv, Tt, inv + it.inv_off + (long long)((k0 + nb) / PANEL_NB) * PANEL_NB * PANEL_NB, bad);
+      inv32_wave<PANEL_NB>(Dv, Tt, inv + it.inv_off + (long long)((k0 + nb) / PANEL_NB) * PANEL_NB * PANEL_NB,
+                           bad);
       if (bad) atomicOr(status, ST_IFACE_PIVOT);
     }
     return;
@@ -374,10 +485,11 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
       a0 = mfma64(av, Bs[4 * q + g][16 * tj + c], a0);
       a1 = mfma64(av, Bs[4 * q + g][16 * tj + 16 + c], a1);
     }
+    __syncthreads();   // W replaces A12
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      Ws[16 * ti + 4 * v + g][16 * tj + c] = a0[v];
-      Ws[16 * ti + 4 * v + g][16 * tj + 16 + c] = a1[v];
+      Bs[16 * ti + 4 * v + g][16 * tj + c] = a0[v];
+      Bs[16 * ti + 4 * v + g][16 * tj + 16 + c] = a1[v];
     }
   }
   __syncthreads();
@@ -389,7 +501,7 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
   for (int q = 0; q < PANEL_NB / 4; ++q) {
     const double av = As[16 * w + c][4 * q + g];
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj) acc[tj] = mfma64(av, Ws[4 * q + g][16 * tj + c], acc[tj]);
+    for (int tj = 0; tj < 4; ++tj) acc[tj] = mfma64(av, Bs[4 * q + g][16 * tj + c], acc[tj]);
   }
   const int skip = kind == 1 ? nb1 : 0;   // leading diagonal block left to its own item
 #pragma unroll
@@ -658,29 +770,41 @@ __global__ void __launch_bounds__(NT) max_pairs_kernel(const double* partials, i
 }  // namespace
 
 hipError_t prepare_interface_kernels() {
-  return hipFuncSetAttribute((const void*)front_small_kernel,
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             SMALL_FRONT * (SMALL_FRONT + 1) * (int)sizeof(double));
+  const int lds = SMALL_FRONT * (SMALL_FRONT + 1) * (int)sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)front_small_kernel<4>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)front_small_kernel<8>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)front_small_kernel<SMALL_PER_T>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  return e;
 }
 
 hipError_t launch_front_small(const NodeDesc* nodes, int count, int max_n, double* tree,
                               const int2* maps, int* status, hipStream_t st) {
   const size_t lds = (size_t)max_n * (max_n + 1) * sizeof(double);
-  hipLaunchKernelGGL(front_small_kernel, dim3(count), dim3(NT), lds, st, nodes, tree, maps, status);
-  return hipGetLastError();
-}
-
-hipError_t launch_front_gather(const GatherItem* items, int count, double* tree, const int2* maps,
-                               double* inv, int* status, hipStream_t st) {
-  hipLaunchKernelGGL(front_gather_kernel, dim3(count), dim3(NT), 0, st, items, tree, maps, inv,
-                     status);
+  const int per = (max_n * (max_n + 1) + NT - 1) / NT;   // the plan keeps max_n <= SMALL_FRONT
+  if (per <= 4)
+    hipLaunchKernelGGL(front_small_kernel<4>, dim3(count), dim3(NT), lds, st, nodes, tree, maps, status);
+  else if (per <= 8)
+    hipLaunchKernelGGL(front_small_kernel<8>, dim3(count), dim3(NT), lds, st, nodes, tree, maps, status);
+  else
+    hipLaunchKernelGGL(front_small_kernel<SMALL_PER_T>, dim3(count), dim3(NT), lds, st, nodes, tree,
+                       maps, status);
   return hipGetLastError();
 }
 
 hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count, int k0,
-                               double* tree, double* inv, int* status, hipStream_t st) {
-  hipLaunchKernelGGL(front_update_kernel, dim3(count), dim3(NT), 0, st, nodes, items, k0, tree,
-                     inv, status);
+                               double* tree, const int2* maps, double* inv, int* status,
+                               hipStream_t st) {
+  if (k0 == 0)
+    hipLaunchKernelGGL(front_update_kernel<true>, dim3(count), dim3(NT), 0, st, nodes, items, k0,
+                       tree, maps, inv, status);
+  else
+    hipLaunchKernelGGL(front_update_kernel<false>, dim3(count), dim3(NT), 0, st, nodes, items, k0,
+                       tree, maps, inv, status);
   return hipGetLastError();
 }
 

@@ -74,18 +74,14 @@ struct NodeDesc {
   long long cr_off[2];  // each child's right-hand-side vector, -1 for a leaf child
 };
 
-struct GatherItem {     // one work-group of a blocked-front gather
-  NodeDesc nd;          // the front
-  int row;              // first of its GATHER_ROWS rows; -1: the first panel's diagonal block
-  int pad_;
-};
-
 struct PanelItem {      // one work-group of a blocked trailing update
   int node;             // index into the node descriptor array
   int i0, j0;           // first row / column of the 64 x 64 tile
   int pad;              // 0: tile; 1: tile whose leading 32 x 32 block is the next
                         // panel's diagonal block (left out); 2: that block alone,
-                        // updated and inverted (i0 = j0 = its first row)
+                        // updated and inverted (i0 = j0 = its first row);
+                        // 3 (first panel of a front without trailing rows):
+                        // the panel's rows from column j0, stored as assembled
   int n, s;             // the front's size and separator size (copied from its node)
   long long f_off;      // the front's offset in the tree buffer
   long long inv_off;    // the front's diagonal-block inverses
@@ -113,10 +109,11 @@ long long local_scratch_doubles(const Geo& g);
 // ---- launchers (interface.hip) ----
 hipError_t launch_front_small(const NodeDesc* nodes, int count, int max_n, double* tree,
                               const int2* maps, int* status, hipStream_t st);
-hipError_t launch_front_gather(const GatherItem* items, int count, double* tree, const int2* maps,
-                               double* inv, int* status, hipStream_t st);
-hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count,
-                               int k0, double* tree, double* inv, int* status, hipStream_t st);
+// one panel of the blocked fronts of a level; the first (k0 = 0) also
+// assembles the fronts from their children
+hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count, int k0,
+                               double* tree, const int2* maps, double* inv, int* status,
+                               hipStream_t st);
 // back substitution of one tree level; rtree = NULL takes the right-hand
 // side from the fronts' last column, else from the fronts' rhs vectors
 hipError_t launch_front_back(const NodeDesc* nodes, int count, const double* tree, const double* inv,
@@ -158,7 +155,6 @@ hipError_t launch_surrogate_targets(const SubArgs& a, float* targets, hipStream_
 hipError_t launch_surrogate_gate(const SubArgs& a, const float* pred, hipStream_t st);
 
 constexpr int PANEL_NB = 32;      // panel width of the blocked elimination
-constexpr int GATHER_ROWS = 8;    // rows per work-group of the blocked-front gather
 constexpr int TILE = 64;          // trailing-update tile
 constexpr int SMALL_FRONT = 64;   // fronts up to this size are eliminated in LDS
 constexpr int MAX_FRONT = 4096;   // largest front the interface plan accepts
