@@ -474,7 +474,7 @@ int run_interface(mrcm_ctx* c) {
                                       pl.k0, c->tree, c->d_maps, c->inv, c->status, st));
   }
   for (auto it = c->levels.rbegin(); it != c->levels.rend(); ++it)
-    HIPCHK(c, launch_front_back(c->d_lvnodes + it->ids_off, it->count, c->tree, c->inv, c->d_dofs,
+    HIPCHK(c, launch_front_back(c->d_lvnodes + it->ids_off, it->count, it->max_n, c->tree, c->inv, c->d_dofs,
                                 nullptr, c->coef, st));
   HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2, st));
   return MRCM_OK;
@@ -487,10 +487,10 @@ int run_interface(mrcm_ctx* c) {
 int refine_interface(mrcm_ctx* c) {
   hipStream_t st = c->st;
   for (const LevelPlan& lp : c->levels)
-    HIPCHK(c, launch_front_rhs(c->d_lvnodes + lp.ids_off, lp.count, c->tree, c->inv, c->d_maps,
+    HIPCHK(c, launch_front_rhs(c->d_lvnodes + lp.ids_off, lp.count, lp.max_n, c->tree, c->inv, c->d_maps,
                                c->d_dofs, c->rvec, c->rtree, st));
   for (auto lv = c->levels.rbegin(); lv != c->levels.rend(); ++lv)
-    HIPCHK(c, launch_front_back(c->d_lvnodes + lv->ids_off, lv->count, c->tree, c->inv, c->d_dofs,
+    HIPCHK(c, launch_front_back(c->d_lvnodes + lv->ids_off, lv->count, lv->max_n, c->tree, c->inv, c->d_dofs,
                                 c->rtree, c->dx, st));
   HIPCHK(c, launch_add(c->coef, c->dx, c->n_dof, st));
   HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2, st));
@@ -584,7 +584,6 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
       c->own_stream = true;
     }
     for (int i = 0; i < 5; ++i) HIPCHK(c, hipEventCreate(&c->ev[i]));
-    HIPCHK(c, prepare_interface_kernels());
     ALLOC(c, c->K, ncell);
     ALLOC(c, c->lam, ncell);
     ALLOC(c, c->stage, ncell);

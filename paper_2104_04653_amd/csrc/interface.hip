@@ -15,7 +15,7 @@
 // themselves, so the global matrix is never formed.
 //
 // Fronts of up to SMALL_FRONT unknowns are gathered and eliminated by one
-// work-group in LDS.  Larger fronts (the nodes near the root) are
+// work-group in registers.  Larger fronts (the nodes near the root) are
 // eliminated in global memory by a right-looking blocked LU, one launch
 // per panel of PANEL_NB columns: the trailing update A22 -= A21 (A11^-1 A12)
 // in 64 x 64 tiles on the FP64 matrix cores, with the next panel's
@@ -68,54 +68,92 @@ __device__ inline void two_prod_sub(double& hi, double& lo, double a, double b) 
 // 32 columns x 8 rows per pass.
 constexpr int TXN = 32, TYN = NT / TXN;
 
-// entries of a small front (and its rhs column) per thread, at most
-constexpr int SMALL_PER_T = (SMALL_FRONT * (SMALL_FRONT + 1) + NT - 1) / NT;
-
-// PER: entries per thread, enough for the level's largest front
-template <int PER>
+// A front of up to SMALL_FRONT unknowns, eliminated in registers: thread
+// (tx, ty) holds the entries of rows ty + TYN i and columns tx + TXN j
+// (column n: the rhs), RI x CJ of them, for the whole elimination.  At
+// pivot k the holders of row k and of column k put them in LDS (double
+// buffered, so one barrier per pivot), and every thread updates its own
+// entries: F[a][k] becomes the multiplier F[a][k] / F[k][k], and
+// F[a][b] -= F[a][k] F[k][b] for a, b > k.  The result (U in the
+// eliminated rows, multipliers below them, the Schur complement and its
+// rhs in the trailing block) is stored row-major, n x (n + 1).
+template <int RI, int CJ>
 __global__ void __launch_bounds__(NT) front_small_kernel(const NodeDesc* nodes, double* tree,
                                                          const int2* maps, int* status) {
-  extern __shared__ double F[];
   __shared__ int2 mp[SMALL_FRONT];
+  __shared__ double prow[2][SMALL_FRONT + 1], pcol[2][SMALL_FRONT];
   const NodeDesc nd = nodes[blockIdx.x];   // this level's fronts, one per work-group
-  const int n = nd.n, s = nd.s, ld = n + 1, ne = n * ld;
+  const int n = nd.n, s = nd.s, ld = n + 1;
   const int tid = threadIdx.x, tx = tid % TXN, ty = tid / TXN;
   for (int a = tid; a < n; a += NT) mp[a] = maps[nd.map_off + a];
   __syncthreads();
-  // all of a thread's entries are read before any is stored, so that their
-  // loads are in flight together.  Entry e = a ld + b; a = e / ld is taken in
-  // single precision: e < 2^13 and e / ld is at least 1 / (2 ld) away from
-  // the next integer, far more than the rounding of the product.
-  const float ild = 1.0f / (float)ld;
-  double v[PER];
+  // every entry's loads in flight together: unconditional, from clamped
+  // indices, entries outside the front dropped afterwards
+  double R[RI][CJ];
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = tid + NT * i;
-    const int a = min((int)(((float)e + 0.5f) * ild), n - 1), b = min(e - a * ld, n);
-    const double x = gather_entry(nd, tree, mp[a], b < n ? mp[b] : mp[a], b == n);
-    v[i] = e < ne ? x : 0.0;   // beyond the front: a valid entry read and dropped
+  for (int i = 0; i < RI; ++i) {
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) {
+      const int a = ty + TYN * i, b = tx + TXN * j;
+      const int ac = min(a, n - 1), bc = min(b, n);
+      const double x = gather_entry(nd, tree, mp[ac], bc < n ? mp[bc] : mp[ac], bc == n);
+      R[i][j] = (a < n && b <= n) ? x : 0.0;
+    }
   }
-#pragma unroll
-  for (int i = 0; i < PER; ++i)
-    if (tid + NT * i < ne) F[tid + NT * i] = v[i];
-  __syncthreads();
-  // one barrier per pivot: row a is updated by one half-wavefront (TXN = 32
-  // lanes), whose lanes all read the entry under the pivot before its lane 0
-  // replaces it by the multiplier (program order within the wavefront)
+  // the pivot loop is written with selects, not branches: per-entry
+  // branches compile to hundreds of exec-mask blocks per pivot
   bool bad = false;
   for (int k = 0; k < s; ++k) {
-    const double piv = F[k * ld + k];
-    if (piv == 0.0 || !isfinite(piv)) bad = true;
-    const double ip = 1.0 / piv;
-    for (int a = k + 1 + ty; a < n; a += TYN) {
-      const double f = F[a * ld + k] * ip;
-      for (int b = k + 1 + tx; b <= n; b += TXN) F[a * ld + b] -= f * F[k * ld + b];
-      if (tx == 0) F[a * ld + k] = f;
+    const int bf = k & 1;
+    const int ik = k / TYN, jk = k / TXN;   // register row / column that hold pivot row / column
+    if (ty == k % TYN) {
+#pragma unroll
+      for (int j = 0; j < CJ; ++j) {
+        double v = R[0][j];
+#pragma unroll
+        for (int i = 1; i < RI; ++i) v = i == ik ? R[i][j] : v;
+        if (tx + TXN * j <= n) prow[bf][tx + TXN * j] = v;
+      }
+    }
+    if (tx == k % TXN) {
+#pragma unroll
+      for (int i = 0; i < RI; ++i) {
+        double v = R[i][0];
+#pragma unroll
+        for (int j = 1; j < CJ; ++j) v = j == jk ? R[i][j] : v;
+        if (ty + TYN * i < n) pcol[bf][ty + TYN * i] = v;
+      }
     }
     __syncthreads();
+    const double piv = prow[bf][k];
+    if (piv == 0.0 || !isfinite(piv)) bad = true;
+    const double ip = 1.0 / piv;
+    double pr[CJ];
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) pr[j] = prow[bf][min(tx + TXN * j, n)];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+      const int a = ty + TYN * i;
+      const double f = pcol[bf][min(a, n - 1)] * ip;
+      const bool below = a > k && a < n;
+#pragma unroll
+      for (int j = 0; j < CJ; ++j) {
+        const int b = tx + TXN * j;
+        const double upd = R[i][j] - f * pr[j];
+        const double nv = b == k ? f : ((b > k && b <= n) ? upd : R[i][j]);
+        R[i][j] = below ? nv : R[i][j];
+      }
+    }
   }
   double* out = tree + nd.f_off;
-  for (int e = tid; e < ne; e += NT) out[e] = F[e];
+#pragma unroll
+  for (int i = 0; i < RI; ++i) {
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) {
+      const int a = ty + TYN * i, b = tx + TXN * j;
+      if (a < n && b <= n) out[(long long)a * ld + b] = R[i][j];
+    }
+  }
   if (bad && tid == 0) atomicOr(status, ST_IFACE_PIVOT);
 }
 
@@ -515,11 +553,34 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
   }
 }
 
+// v - sum of row[m] xl[m] over m = m0, m0 + 8, ... below n, in that
+// order.  The row is read CH values at a time, unconditionally from
+// clamped indices, so that each chunk is one round of loads in flight.
+template <int CH>
+__device__ inline double row_dot_sub(double v, const double* row, const double* xl, int m0, int n) {
+  for (int mb = m0; mb < n; mb += 8 * CH) {
+    double f[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) f[j] = row[min(mb + 8 * j, n - 1)];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int m = mb + 8 * j;
+      const double pr = f[j] * xl[min(m, n - 1)];
+      v -= m < n ? pr : 0.0;
+    }
+  }
+  return v;
+}
+
 // Back substitution of one front, top down in the tree: x_s from the
 // front's eliminated rows and the x_r of its ancestors.
 //  classic fronts: row k holds U (upper part) at elimination time k;
 //  blocked fronts: the rows of panel p hold the panel-time A12 to the right
 //  of the diagonal block, so x_1 = A11^{-1} (b_1 - A12 x_2).
+// BLOCKED: the level's fronts are blocked (all of a level's fronts are of
+// one kind), a separate instance so that its load registers do not limit
+// the occupancy of the many small classic fronts.
+template <bool BLOCKED>
 __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, const double* tree,
                                                         const double* inv, const int* dofs,
                                                         const double* rtree, double* x) {
@@ -536,20 +597,20 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
   // reads no global memory
   constexpr int US_MAX = 32;
   __shared__ double Us[US_MAX][US_MAX + 1];
-  const bool stage = !nd.blocked && s <= US_MAX;
+  const bool stage = !BLOCKED && s <= US_MAX;
   if (stage)
     for (int e = t; e < s * s; e += NT) Us[e / s][e % s] = F[(long long)(e / s) * ld + e % s];
   for (int m = s + t; m < n; m += NT) xl[m] = x[dof[m]];
   __syncthreads();
-  if (!nd.blocked) {
+  if constexpr (!BLOCKED) {
     for (int k0 = 0; k0 < s; k0 += NT / 8) {
       const int k = k0 + t / 8, lane = t % 8;
       double v = 0.0;
       if (k < s) {
         const double* row = F + (long long)k * ld;
-#pragma unroll 4
-        for (int m = s + lane; m < n; m += 8) v -= row[m] * xl[m];
-        if (lane == 0) v += rv ? rv[k] : row[n];
+        const double bk = rv ? rv[k] : row[n];   // in flight with the row's loads
+        v = row_dot_sub<8>(v, row, xl, s + lane, n);
+        if (lane == 0) v += bk;
       }
       for (int off = 4; off > 0; off >>= 1) v += __shfl_down(v, off, 8);
       if (k < s && lane == 0) xl[k] = v;
@@ -578,8 +639,8 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
     }
   } else {
     // one panel per step, last first; 8 lanes per panel row.  The panel's
-    // A11^-1 is loaded into registers before the A12 products, so that both
-    // loads are in flight together, and applied from LDS.
+    // A11^-1 is loaded into registers with the A12 rows, so that both loads
+    // are in flight together, and applied from LDS.
     __shared__ double Ds[PANEL_NB][PANEL_NB + 1];
     static_assert(NT == 8 * PANEL_NB, "8 lanes per panel row");
     const int row = t / 8, lane = t % 8;
@@ -594,9 +655,9 @@ __global__ void __launch_bounds__(NT) front_back_kernel(const NodeDesc* nodes, c
       double v = 0.0;
       if (row < nb) {
         const double* fr = F + (long long)(k0 + row) * ld;
-#pragma unroll 4
-        for (int m = k0 + nb + lane; m < n; m += 8) v -= fr[m] * xl[m];
-        if (lane == 0) v += rv ? rv[k0 + row] : fr[n];
+        const double bk = rv ? rv[k0 + row] : fr[n];   // in flight with the row's loads
+        v = row_dot_sub<32>(v, fr, xl, k0 + nb + lane, n);
+        if (lane == 0) v += bk;
       }
       for (int off = 4; off > 0; off >>= 1) v += __shfl_down(v, off, 8);
       if (row < nb && lane == 0) y[row] = v;
@@ -769,30 +830,19 @@ __global__ void __launch_bounds__(NT) max_pairs_kernel(const double* partials, i
 
 }  // namespace
 
-hipError_t prepare_interface_kernels() {
-  const int lds = SMALL_FRONT * (SMALL_FRONT + 1) * (int)sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void*)front_small_kernel<4>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)front_small_kernel<8>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)front_small_kernel<SMALL_PER_T>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  return e;
-}
-
 hipError_t launch_front_small(const NodeDesc* nodes, int count, int max_n, double* tree,
                               const int2* maps, int* status, hipStream_t st) {
-  const size_t lds = (size_t)max_n * (max_n + 1) * sizeof(double);
-  const int per = (max_n * (max_n + 1) + NT - 1) / NT;   // the plan keeps max_n <= SMALL_FRONT
-  if (per <= 4)
-    hipLaunchKernelGGL(front_small_kernel<4>, dim3(count), dim3(NT), lds, st, nodes, tree, maps, status);
-  else if (per <= 8)
-    hipLaunchKernelGGL(front_small_kernel<8>, dim3(count), dim3(NT), lds, st, nodes, tree, maps, status);
-  else
-    hipLaunchKernelGGL(front_small_kernel<SMALL_PER_T>, dim3(count), dim3(NT), lds, st, nodes, tree,
-                       maps, status);
+  // the smallest register tile that holds the level's largest front (the
+  // plan keeps max_n <= SMALL_FRONT): rows TYN RI >= n, columns TXN CJ > n
+  static_assert(TYN * 8 >= SMALL_FRONT && TXN * 3 > SMALL_FRONT, "register tile of the largest front");
+#define SMALL_LAUNCH(RI, CJ) \
+  hipLaunchKernelGGL((front_small_kernel<RI, CJ>), dim3(count), dim3(NT), 0, st, nodes, tree, maps, status)
+  if (max_n <= 31) SMALL_LAUNCH(4, 1);
+  else if (max_n <= 40) SMALL_LAUNCH(5, 2);
+  else if (max_n <= 56) SMALL_LAUNCH(7, 2);
+  else if (max_n <= 63) SMALL_LAUNCH(8, 2);
+  else SMALL_LAUNCH(8, 3);
+#undef SMALL_LAUNCH
   return hipGetLastError();
 }
 
@@ -808,19 +858,25 @@ hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, in
   return hipGetLastError();
 }
 
-hipError_t launch_front_back(const NodeDesc* nodes, int count, const double* tree, const double* inv,
-                             const int* dofs, const double* rtree, double* x, hipStream_t st) {
-  // the plan guarantees n <= MAX_FRONT
-  hipLaunchKernelGGL(front_back_kernel, dim3(count), dim3(NT), MAX_FRONT * sizeof(double), st, nodes,
-                     tree, inv, dofs, rtree, x);
+hipError_t launch_front_back(const NodeDesc* nodes, int count, int max_n, const double* tree,
+                             const double* inv, const int* dofs, const double* rtree, double* x,
+                             hipStream_t st) {
+  // LDS for the level's largest front (the plan guarantees n <= MAX_FRONT)
+  const size_t lds = (size_t)max_n * sizeof(double);
+  if (max_n > SMALL_FRONT)   // the plan's rule for a blocked level
+    hipLaunchKernelGGL(front_back_kernel<true>, dim3(count), dim3(NT), lds, st, nodes, tree, inv, dofs,
+                       rtree, x);
+  else
+    hipLaunchKernelGGL(front_back_kernel<false>, dim3(count), dim3(NT), lds, st, nodes, tree, inv, dofs,
+                       rtree, x);
   return hipGetLastError();
 }
 
-hipError_t launch_front_rhs(const NodeDesc* nodes, int count, const double* tree, const double* inv,
-                            const int2* maps, const int* dofs, const double* r, double* rtree,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(front_rhs_kernel, dim3(count), dim3(NT), MAX_FRONT * sizeof(double), st, nodes,
-                     tree, inv, maps, dofs, r, rtree);
+hipError_t launch_front_rhs(const NodeDesc* nodes, int count, int max_n, const double* tree,
+                            const double* inv, const int2* maps, const int* dofs, const double* r,
+                            double* rtree, hipStream_t st) {
+  hipLaunchKernelGGL(front_rhs_kernel, dim3(count), dim3(NT), (size_t)max_n * sizeof(double), st,
+                     nodes, tree, inv, maps, dofs, r, rtree);
   return hipGetLastError();
 }
 

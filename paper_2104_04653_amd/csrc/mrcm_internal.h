@@ -116,13 +116,14 @@ hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, in
                                hipStream_t st);
 // back substitution of one tree level; rtree = NULL takes the right-hand
 // side from the fronts' last column, else from the fronts' rhs vectors
-hipError_t launch_front_back(const NodeDesc* nodes, int count, const double* tree, const double* inv,
-                             const int* dofs, const double* rtree, double* x, hipStream_t st);
+hipError_t launch_front_back(const NodeDesc* nodes, int count, int max_n, const double* tree,
+                             const double* inv, const int* dofs, const double* rtree, double* x,
+                             hipStream_t st);
 // forward elimination of a new right-hand side r (one value per interface
 // dof) through the stored fronts of one tree level, into the rhs tree
-hipError_t launch_front_rhs(const NodeDesc* nodes, int count, const double* tree, const double* inv,
-                            const int2* maps, const int* dofs, const double* r, double* rtree,
-                            hipStream_t st);
+hipError_t launch_front_rhs(const NodeDesc* nodes, int count, int max_n, const double* tree,
+                            const double* inv, const int2* maps, const int* dofs, const double* r,
+                            double* rtree, hipStream_t st);
 // r = b - A x of the assembled interface system (double-double), written to
 // r if not NULL; partials: 2 doubles per work-group (RESID_WG of them),
 // reduced into out2[0] = max|r|, out2[1] = max|b|
@@ -131,7 +132,6 @@ hipError_t launch_iface_residual(const Geo& g, const double* blocks, const doubl
 // x += dx over n values
 hipError_t launch_add(double* x, const double* dx, int n, hipStream_t st);
 constexpr int RESID_WG = 128;
-hipError_t prepare_interface_kernels();
 
 // ---- surrogate network (surrogate.hip) ----
 }  // namespace mrcm
@@ -156,7 +156,7 @@ hipError_t launch_surrogate_gate(const SubArgs& a, const float* pred, hipStream_
 
 constexpr int PANEL_NB = 32;      // panel width of the blocked elimination
 constexpr int TILE = 64;          // trailing-update tile
-constexpr int SMALL_FRONT = 64;   // fronts up to this size are eliminated in LDS
+constexpr int SMALL_FRONT = 64;   // levels with fronts up to this size are eliminated in registers
 constexpr int MAX_FRONT = 4096;   // largest front the interface plan accepts
 
 }  // namespace mrcm

@@ -123,6 +123,19 @@ def test_gauss1024_full_size_step():
     check_end_to_end(prob, s=inputs.synthetic_saturation(prob, 3), local=False)
 
 
+@pytest.mark.parametrize("grid", [(10, 10), (16, 16), (24, 24), (32, 16)])
+def test_interface_front_sizes(grid):
+    """Subdomain grids whose tree levels take every register tile of the
+    small-front elimination (largest front per level from 28 to 64
+    unknowns, 64 on the 10 x 10 grid) and blocked levels of several shapes
+    (fronts of 72 to 160 unknowns)."""
+    sx, sy = grid
+    prob = inputs.make_problem("gauss1024", nx=16 * sx, ny=16 * sy, lx=sx / 64, ly=sy / 64,
+                               seed=sx + sy)
+    check_end_to_end(prob, s=inputs.synthetic_saturation(prob, 2, 7), local=False,
+                     label="front sizes %dx%d subdomains" % grid)
+
+
 def test_bad_mobility_rejected():
     from paper_2104_04653_amd import MRCMSolver, MRCMError
     from paper_2104_04653_amd.mrcm import E_INVAL, E_STATE
