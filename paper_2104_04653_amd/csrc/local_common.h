@@ -51,27 +51,57 @@ __device__ inline int side_cell(int side, int t) {
   }
 }
 
-// Assemble one cell of the local two-point system: diagonal, coupling to the
-// +x neighbour (ex) and to the +y neighbour (cy), and the cell's row of the
-// right-hand sides.  robin != 0: skeleton faces carry the Robin law (the
-// basis-function problems); robin == 0: skeleton faces carry the prescribed
-// outflow Fout[side][t] (the stitch re-solve).
-template <int M, int R, bool SIDES = true>
-__device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const double* kap,
-                              double* dg, double* ex, double* cy, double* xrow, int robin,
-                              const double (*Fout)[M]) {
+// The global values one cell's assembly reads: the source, and per side the
+// boundary value (domain boundary) and the Robin parameter (skeleton).
+struct CellLoads {
+  double sv, bv[4], av[4];
+};
+
+// Loaded without branches, each from an address selected per side (the
+// cell's own permeability stands in where the value is not needed), so that
+// a thread's loads are all in flight together: loads behind branches wait
+// one by one.
+template <int M>
+__device__ inline CellLoads cell_loads(const SubArgs& a, int I, int J, int l, int robin) {
   const Geo& g = a.g;
   const int li = l % M, lj = l / M;
   const int i = I * M + li, j = J * M + lj;
   const size_t c = (size_t)j * g.nx + i;
+  const double* stand = a.K + c;
+  CellLoads cl;
+  cl.sv = *(a.src ? a.src + c : stand);
+#pragma unroll
+  for (int side = 0; side < 4; ++side) {
+    const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
+    const int e = inner ? 0 : side_iface(g, I, J, side);
+    cl.bv[side] = *((!inner && e < 0) ? a.bcv[side] + ((side < 2) ? j : i) : stand);
+    cl.av[side] = *((!inner && e >= 0 && robin) ? a.alpha + e : stand);
+  }
+  return cl;
+}
+
+// Assemble one cell of the local two-point system: diagonal, coupling to the
+// +x neighbour (ex) and to the +y neighbour (cy), and the cell's row of the
+// right-hand sides.  robin != 0: skeleton faces carry the Robin law (the
+// basis-function problems); robin == 0: skeleton faces carry the prescribed
+// outflow Fout[side][t] (the stitch re-solve).  cl: the cell's values from
+// cell_loads (a kernel may load several cells' values before assembling).
+template <int M, int R, bool SIDES = true>
+__device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const double* kap,
+                              double* dg, double* ex, double* cy, double* xrow, int robin,
+                              const double (*Fout)[M], const CellLoads& cl) {
+  const Geo& g = a.g;
+  const int li = l % M, lj = l / M;
+  const int i = I * M + li, j = J * M + lj;
   const double kc = kap[l];
   const double txc = kc * g.hy / (0.5 * g.hx);
   const double tyc = kc * g.hx / (0.5 * g.hy);
   double diag = 0.0, cx = 0.0, cn = 0.0;
   for (int q = 0; q < R; ++q) xrow[q] = 0.0;
   double rhs0 = 0.0;
-  if (a.src) rhs0 += a.src[c] * g.hx * g.hy;
+  if (a.src) rhs0 += cl.sv * g.hx * g.hy;
   // face loop: side 0 W, 1 E, 2 S, 3 N
+#pragma unroll
   for (int side = 0; side < 4; ++side) {
     const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
     if (inner) {
@@ -88,7 +118,7 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
     const double th = (side < 2) ? txc : tyc;
     if (e < 0) {  // physical boundary
       const double flen = (side < 2) ? g.hy : g.hx;
-      const double v = a.bcv[side][(side < 2) ? j : i];
+      const double v = cl.bv[side];
       if (g.kind[side] == 1) {
         diag += th;
         rhs0 += th * v;
@@ -99,7 +129,7 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
     }
     if (robin) {
       SideGeo sg = side_geo(g, side);
-      const double al = a.alpha[e];
+      const double al = cl.av[side];
       const double TR = sg.flen * kc / (sg.dist + al * sg.H);
       const double beta = al * sg.H / kc;
       const double sig = side_sigma(side);
@@ -123,6 +153,14 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
   xrow[0] += rhs0;
 }
 
+// the same, loading the cell's values itself
+template <int M, int R, bool SIDES = true>
+__device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const double* kap,
+                              double* dg, double* ex, double* cy, double* xrow, int robin,
+                              const double (*Fout)[M]) {
+  assemble_cell<M, R, SIDES>(a, I, J, l, kap, dg, ex, cy, xrow, robin, Fout,
+                             cell_loads<M>(a, I, J, l, robin));
+}
 
 // (hi, lo) += a * b in double-double arithmetic: the product is split
 // exactly with an FMA and added with an error-free two-sum, so a residual

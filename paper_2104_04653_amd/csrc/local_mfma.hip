@@ -182,11 +182,16 @@ __device__ inline FaceLoad load_faces(const SubArgs& a, int I, int J) {
   if (l < 4 * M) {
     const int side = l >> 4, t = l & 15;
     fl.e = side_iface(a.g, I, J, side);
-    if (fl.e >= 0) {
-      fl.al = a.alpha[fl.e];
+    // loaded from selected addresses (the first permeability stands in on
+    // the domain boundary), so that the loads are not behind a branch
+    const bool has = fl.e >= 0;
+    const double al = *(has ? a.alpha + fl.e : a.K);
+    double ph[D];
 #pragma unroll
-      for (int k = 0; k < D; ++k) fl.phi[k] = a.basis[((size_t)fl.e * D + k) * M + t];
-    }
+    for (int k = 0; k < D; ++k) ph[k] = *(has ? a.basis + ((size_t)fl.e * D + k) * M + t : a.K);
+    fl.al = has ? al : 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) fl.phi[k] = has ? ph[k] : 0.0;
   }
   return fl;
 }
@@ -298,6 +303,7 @@ __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const
 // barrier: its LDS accesses complete in program order).
 // ---------------------------------------------------------------------------
 constexpr int PAIR = 2 * WAVE;
+static_assert(MM % PAIR == 0, "whole cells per thread");
 constexpr int NU = MID + 1;       // rows of wave 0: 0 .. MID
 constexpr int NL = M - 1 - MID;   // rows of wave 1: M-1 .. MID+1 (index t is row M-1-t)
 
@@ -322,10 +328,15 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
   const int I = sd % g.SX, J = sd / g.SX;
 
   const FaceLoad fl = load_faces(a, I, J);
+  CellLoads cl[MM / PAIR];   // issued with the permeability loads
+#pragma unroll
+  for (int q = 0; q < MM / PAIR; ++q) cl[q] = cell_loads<M>(a, I, J, tid + PAIR * q, 1);
   load_kappa<M>(a, I, J, kap);
   __syncthreads();
-  for (int l = tid; l < MM; l += PAIR)
-    assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, b0 + l, 1, nullptr);
+#pragma unroll
+  for (int q = 0; q < MM / PAIR; ++q)
+    assemble_cell<M, 1, false>(a, I, J, tid + PAIR * q, kap, dg, ex, cy, b0 + tid + PAIR * q, 1, nullptr,
+                               cl[q]);
   prepare_faces(a, fl, kap, fc);
   __syncthreads();
   robin_data(g, fc, bside);
@@ -1103,10 +1114,15 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
   const int I = sd % g.SX, J = sd / g.SX;
 
   const FaceLoad fl = load_faces(a, I, J);
+  CellLoads cl[MM / PAIR];   // issued with the permeability loads
+#pragma unroll
+  for (int q = 0; q < MM / PAIR; ++q) cl[q] = cell_loads<M>(a, I, J, tid + PAIR * q, 1);
   load_kappa<M>(a, I, J, sh.kap);
   __syncthreads();
-  for (int l = tid; l < MM; l += PAIR)
-    assemble_cell<M, 1, false>(a, I, J, l, sh.kap, sh.dg, sh.ex, sh.cy, sh.b0 + l, 1, nullptr);
+#pragma unroll
+  for (int q = 0; q < MM / PAIR; ++q)
+    assemble_cell<M, 1, false>(a, I, J, tid + PAIR * q, sh.kap, sh.dg, sh.ex, sh.cy,
+                               sh.b0 + tid + PAIR * q, 1, nullptr, cl[q]);
   prepare_faces(a, fl, sh.kap, sh.fc);
   for (int l = tid; l < MM; l += PAIR) sh.dsc[l] = 1.0 / sqrt(sh.dg[l]);
   __syncthreads();
@@ -1300,6 +1316,9 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
     for (int q = 0; q < 4 * D; ++q) cfn[q] = column_coef(a, nI, nJ, q);
     pn = compose16(a, nsd, nl, cfn);
   }
+  CellLoads cl[MM / PAIR];   // issued with the permeability loads
+#pragma unroll
+  for (int q = 0; q < MM / PAIR; ++q) cl[q] = cell_loads<M>(a, I, J, tid + PAIR * q, 0);
   load_kappa<M>(a, I, J, kap);
   __syncthreads();
   for (int l = tid; l < MM; l += PAIR) pm[l] = compose16(a, sd, l, cfs);
@@ -1322,8 +1341,10 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
     Fout[side][t] = fo;
   }
   __syncthreads();
-  for (int l = tid; l < MM; l += PAIR)
-    assemble_cell<M, 1, false>(a, I, J, l, kap, dg, ex, cy, bs_ + l, 0, Fout);
+#pragma unroll
+  for (int q = 0; q < MM / PAIR; ++q)
+    assemble_cell<M, 1, false>(a, I, J, tid + PAIR * q, kap, dg, ex, cy, bs_ + tid + PAIR * q, 0, Fout,
+                               cl[q]);
   __syncthreads();
   const bool dir = (I == 0 && g.kind[0] == 1) || (I == g.SX - 1 && g.kind[1] == 1) ||
                    (J == 0 && g.kind[2] == 1) || (J == g.SY - 1 && g.kind[3] == 1);
@@ -1525,9 +1546,10 @@ __global__ void __launch_bounds__(GATE) surrogate_gate_kernel(SubArgs a, const f
   float praw[4 * D];
 #pragma unroll
   for (int k = 0; k < 4 * D; ++k) praw[k] = pr[tid + k * GATE];
+  const CellLoads cl = cell_loads<M>(a, I, J, tid, 1);   // issued with the permeability loads
   load_kappa<M>(a, I, J, kap);
   __syncthreads();
-  assemble_cell<M, 1, false>(a, I, J, tid, kap, dg, ex, cy, b0 + tid, 1, nullptr);
+  assemble_cell<M, 1, false>(a, I, J, tid, kap, dg, ex, cy, b0 + tid, 1, nullptr, cl);
   if (wv == 0) {
     // the same geometric mean (same summation order) as the input and
     // target builders
