@@ -236,10 +236,12 @@ __device__ inline d4 gj16(d4 s, int c, int g, bool& bad) {
 // factor comes from one transpose through `T`.  The pivots of the two 16 x 16
 // inversions are the pivots of an LU factorisation of A.
 // The result goes to out with row stride LDO; out may be S itself (stride
-// PANEL_NB + 1): S is read in full before anything is written.
+// PANEL_NB + 1): S is read in full before anything is written.  A block
+// of width nb <= 16 is [P 0; 0 I]: its inverse [P^-1 0; 0 I] takes one
+// 16 x 16 inversion.
 template <int LDO>
 __device__ void inv32_wave(const double (*S)[PANEL_NB + 1], double (*T)[17], double* out,
-                           bool& bad) {
+                           bool& bad, int nb) {
   static_assert(PANEL_NB == 32, "two 16 x 16 tiles per side");
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
   d4 P, Q, B;
@@ -252,6 +254,17 @@ __device__ void inv32_wave(const double (*S)[PANEL_NB + 1], double (*T)[17], dou
   }
   const d4 z = {0.0, 0.0, 0.0, 0.0};
   const d4 Pi = gj16(P, c, g, bad);
+  if (nb <= 16) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 4 * v + g;
+      out[r * LDO + c] = Pi[v];
+      out[(16 + r) * LDO + c] = 0.0;
+      out[c * LDO + 16 + r] = 0.0;
+      out[(16 + r) * LDO + 16 + c] = r == c ? 1.0 : 0.0;
+    }
+    return;
+  }
   d4 X = z;
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) X = mfma64(Pi[kk], Q[kk], X);          // P^-1 Q
@@ -375,7 +388,7 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
         __syncthreads();
         if (t < 64) {
           bool bad = false;
-          inv32_wave<PANEL_NB>(Dv, Tt, inv + it.inv_off, bad);
+          inv32_wave<PANEL_NB>(Dv, Tt, inv + it.inv_off, bad, nb);
           if (bad) atomicOr(status, ST_IFACE_PIVOT);
         }
       }
@@ -466,7 +479,7 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
     __syncthreads();
     if (t < 64) {
       bool bad = false;
-      inv32_wave<PANEL_NB + 1>(Dv, Tt, &Dv[0][0], bad);
+      inv32_wave<PANEL_NB + 1>(Dv, Tt, &Dv[0][0], bad, nb);
       if (lead && bad) atomicOr(status, ST_IFACE_PIVOT);
     }
     if (lead) {
@@ -508,7 +521,7 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
     if (t < 64) {
       bool bad = false;
       inv32_wave<PANEL_NB>(Dv, Tt, inv + it.inv_off + (long long)((k0 + nb) / PANEL_NB) * PANEL_NB * PANEL_NB,
-                           bad);
+                           bad, nb1);
       if (bad) atomicOr(status, ST_IFACE_PIVOT);
     }
     return;
@@ -743,11 +756,25 @@ __global__ void add_kernel(double* x, const double* dx, int n) {
 // r = b - A x gathered from the subdomain blocks (each interface row has
 // two owners: its lower- and higher-index subdomain).  Stage 1: per
 // work-group maxima of |r| and |b|; stage 2: one work-group reduces them.
+// interface edge on side (W, E, S, N) of subdomain (I, J), -1 on the
+// domain boundary
+__device__ inline int side_edge(const Geo& g, int I, int J, int side) {
+  switch (side) {
+    case 0: return I > 0 ? J * (g.SX - 1) + I - 1 : -1;
+    case 1: return I < g.SX - 1 ? J * (g.SX - 1) + I : -1;
+    case 2: return J > 0 ? g.nV + (J - 1) * g.SX + I : -1;
+    default: return J < g.SY - 1 ? g.nV + J * g.SX + I : -1;
+  }
+}
+
+// DT: the interface dofs per edge when fixed at compile time (all loads of a
+// row issued together), 0 for any
+template <int DT>
 __global__ void __launch_bounds__(NT) iface_residual_kernel(Geo g, const double* blocks,
                                                             const double* x, double* rvec,
                                                             double* partials) {
   __shared__ double red[2][NT];
-  const int D = g.D, NBR = 4 * D, NBC = NBR + 1;
+  const int D = DT > 0 ? DT : g.D, NBR = 4 * D, NBC = NBR + 1;
   const int n_iface = g.nV + g.SX * (g.SY - 1);
   const int ndof = n_iface * D;
   double rmax = 0.0, bmax = 0.0;
@@ -765,22 +792,50 @@ __global__ void __launch_bounds__(NT) iface_residual_kernel(Geo g, const double*
       sub[1] = sub[0] + g.SX; side[1] = 2;
     }
     double hi = 0.0, lo = 0.0, b = 0.0;   // residual b - A x in double-double
-    for (int o = 0; o < 2; ++o) {
-      const int sd = sub[o];
-      const int I = sd % g.SX, J = sd / g.SX;
-      const double* blk = blocks + (size_t)sd * NBR * NBC + (size_t)(side[o] * D + k) * NBC;
-      b += blk[NBR];
-      two_sum(hi, lo, blk[NBR]);
-      for (int sd_side = 0; sd_side < 4; ++sd_side) {
-        int ee;
-        switch (sd_side) {
-          case 0: ee = I > 0 ? J * (g.SX - 1) + I - 1 : -1; break;
-          case 1: ee = I < g.SX - 1 ? J * (g.SX - 1) + I : -1; break;
-          case 2: ee = J > 0 ? g.nV + (J - 1) * g.SX + I : -1; break;
-          default: ee = J < g.SY - 1 ? g.nV + J * g.SX + I : -1;
+    if constexpr (DT > 0) {
+      // all of the row's loads first, from clamped addresses (a side on the
+      // domain boundary contributes the exact no-op 0 * 0), then the
+      // accumulation in the order of the sides
+      double bb[2], av[2][4][DT], xv[2][4][DT];
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        const int sd = sub[o];
+        const int I = sd % g.SX, J = sd / g.SX;
+        const double* blk = blocks + (size_t)sd * NBR * NBC + (size_t)(side[o] * D + k) * NBC;
+        bb[o] = blk[NBR];
+#pragma unroll
+        for (int sd_side = 0; sd_side < 4; ++sd_side) {
+          const int ee = side_edge(g, I, J, sd_side);
+#pragma unroll
+          for (int kk = 0; kk < DT; ++kk) {
+            const double av_ = blk[sd_side * D + kk];
+            const double xv_ = x[(size_t)max(ee, 0) * D + kk];
+            av[o][sd_side][kk] = ee >= 0 ? av_ : 0.0;
+            xv[o][sd_side][kk] = ee >= 0 ? xv_ : 0.0;
+          }
         }
-        if (ee < 0) continue;
-        for (int kk = 0; kk < D; ++kk) two_prod_sub(hi, lo, blk[sd_side * D + kk], x[(size_t)ee * D + kk]);
+      }
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        b += bb[o];
+        two_sum(hi, lo, bb[o]);
+#pragma unroll
+        for (int sd_side = 0; sd_side < 4; ++sd_side)
+#pragma unroll
+          for (int kk = 0; kk < DT; ++kk) two_prod_sub(hi, lo, av[o][sd_side][kk], xv[o][sd_side][kk]);
+      }
+    } else {
+      for (int o = 0; o < 2; ++o) {
+        const int sd = sub[o];
+        const int I = sd % g.SX, J = sd / g.SX;
+        const double* blk = blocks + (size_t)sd * NBR * NBC + (size_t)(side[o] * D + k) * NBC;
+        b += blk[NBR];
+        two_sum(hi, lo, blk[NBR]);
+        for (int sd_side = 0; sd_side < 4; ++sd_side) {
+          const int ee = side_edge(g, I, J, sd_side);
+          if (ee < 0) continue;
+          for (int kk = 0; kk < D; ++kk) two_prod_sub(hi, lo, blk[sd_side * D + kk], x[(size_t)ee * D + kk]);
+        }
       }
     }
     const double res = hi + lo;
@@ -887,8 +942,12 @@ hipError_t launch_add(double* x, const double* dx, int n, hipStream_t st) {
 
 hipError_t launch_iface_residual(const Geo& g, const double* blocks, const double* x, double* r,
                                  double* partials, double* out2, hipStream_t st) {
-  hipLaunchKernelGGL(iface_residual_kernel, dim3(RESID_WG), dim3(NT), 0, st, g, blocks, x, r,
-                     partials);
+  if (g.D == 4)
+    hipLaunchKernelGGL(iface_residual_kernel<4>, dim3(RESID_WG), dim3(NT), 0, st, g, blocks, x, r,
+                       partials);
+  else
+    hipLaunchKernelGGL(iface_residual_kernel<0>, dim3(RESID_WG), dim3(NT), 0, st, g, blocks, x, r,
+                       partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(max_pairs_kernel, dim3(1), dim3(NT), 0, st, partials, RESID_WG, out2);
