@@ -361,10 +361,12 @@ int build_plan(mrcm_ctx* c) {
           const bool next = d.s > k0 + nb;   // a next panel: its diagonal block gets its own item
           if (next)
             items.push_back(PanelItem{id, k0 + nb, k0 + nb, 2, d.n, d.s, d.f_off, d.inv_off});
+          // a rhs column left alone after whole tiles goes with the tile before it
           for (int r = k0 + nb; r < d.n; r += TILE)
             for (int cc = k0 + nb; cc <= d.n; cc += TILE)
-              items.push_back(PanelItem{id, r, cc, (next && r == k0 + nb && cc == k0 + nb) ? 1 : 0,
-                                        d.n, d.s, d.f_off, d.inv_off});
+              if (cc < d.n || cc == k0 + nb)
+                items.push_back(PanelItem{id, r, cc, (next && r == k0 + nb && cc == k0 + nb) ? 1 : 0,
+                                          d.n, d.s, d.f_off, d.inv_off});
           if (k0 == 0 && d.n == nb) {
             // the first panel assembles the front; without trailing tiles
             // (which store the panel's rows as they read them) its rows

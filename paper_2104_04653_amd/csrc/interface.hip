@@ -341,6 +341,9 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
   const int t = threadIdx.x;
   const int r0 = it.i0, c0 = it.j0;
   int rows = kind == 2 ? nb1 : min(TILE, n - r0), cols = kind == 2 ? nb1 : min(TILE, ld - c0);
+  // a tile followed by the rhs column alone also updates that column (plain
+  // FMAs instead of a work-group of its own)
+  const bool xr = (kind == 0 || kind == 1) && ld - c0 == TILE + 1;
   const int w = t >> 6, lane = t & 63, c = lane & 15, g = lane >> 4;
   NodeDesc nd;
   if constexpr (FIRST) {
@@ -412,6 +415,15 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
       a22[tj][v] = (i < rows && j < cols) ? x : 0.0;
     }
   }
+  // the rhs column after the tile (xr): A22 rows in wave 0, panel rows in
+  // the first half of wave 1 (loaded either way, used only with xr)
+  double xrv;
+  {
+    const int i = min(t < 64 ? t : t - 64, t < 64 ? rows - 1 : nb - 1);
+    const int row = t < 64 ? r0 + i : k0 + i;
+    if constexpr (FIRST) xrv = gather_entry(nd, tree, t < 64 ? mr[i] : mk[i], mk[0], true);
+    else xrv = F[(long long)row * ld + n];
+  }
   // the panel operands: A11 (first panel: gathered, identity beyond its
   // width, and inverted in place below; else its stored inverse), and the
   // A21 rows and A12 columns of the tile, all loaded before any is stored
@@ -450,6 +462,7 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
     const int e = t + NT * q, k = e / TILE, j = e % TILE;
     Bs[k][j] = (k < nb && j < cols) ? xb[q] : 0.0;
   }
+  if (t >= 64 && t < 64 + PANEL_NB) Bs[t - 64][TILE] = (xr && t - 64 < nb) ? xrv : 0.0;
   if constexpr (FIRST) {
     // the panel's own rows and columns, as assembled: the first tile row
     // stores the A12 columns it read, the first tile column the A21 rows,
@@ -468,6 +481,7 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
         const int e = t + NT * q, k = e / TILE, j = e % TILE;
         if (k < nb && j < cols) F[(long long)k * ld + c0 + j] = xb[q];
       }
+      if (xr && t >= 64 && t - 64 < nb) F[(long long)(t - 64) * ld + n] = xrv;
     }
     if (lead) {
 #pragma unroll
@@ -536,12 +550,18 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
       a0 = mfma64(av, Bs[4 * q + g][16 * tj + c], a0);
       a1 = mfma64(av, Bs[4 * q + g][16 * tj + 16 + c], a1);
     }
+    double wr = 0.0;   // xr: W of the rhs column, row t
+    if (xr && t < PANEL_NB) {
+#pragma unroll 8
+      for (int m = 0; m < PANEL_NB; ++m) wr = fma(Dv[t][m], Bs[m][TILE], wr);
+    }
     __syncthreads();   // W replaces A12
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       Bs[16 * ti + 4 * v + g][16 * tj + c] = a0[v];
       Bs[16 * ti + 4 * v + g][16 * tj + 16 + c] = a1[v];
     }
+    if (xr && t < PANEL_NB) Bs[t][TILE] = wr;
   }
   __syncthreads();
   // A21 W: wave w owns rows 16 w .. 16 w + 15 and all four column tiles
@@ -563,6 +583,12 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
       if (i < rows && j < cols && !(i < skip && j < skip))
         F[(long long)(r0 + i) * ld + c0 + j] = a22[tj][v] - acc[tj][v];
     }
+  }
+  if (xr && t < rows) {
+    double ar = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < PANEL_NB; ++k) ar = fma(As[t][k], Bs[k][TILE], ar);
+    F[(long long)(r0 + t) * ld + n] = xrv - ar;
   }
 }
 
