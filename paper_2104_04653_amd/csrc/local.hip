@@ -613,10 +613,26 @@ __global__ void __launch_bounds__(NT) finish_reduce_kernel(SubArgs a, double* re
   __shared__ double red[3][NT];
   const int tid = threadIdx.x;
   double imb = 0.0, fmx = 0.0, ps = 0.0;
-  for (int s = tid; s < a.g.n_sub; s += NT) {
-    imb = fmax(imb, a.sub_stats[3 * s]);
-    fmx = fmax(fmx, a.sub_stats[3 * s + 1]);
-    ps += a.sub_stats[3 * s + 2];
+  // CH subdomains per thread loaded before any is used (clamped, dropped
+  // beyond the end), summed in the order of s
+  constexpr int CH = 16;
+  const int ns = a.g.n_sub;
+  for (int s0 = tid; s0 < ns; s0 += CH * NT) {
+    double v[CH][3];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int s = min(s0 + q * NT, ns - 1);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[q][k] = a.sub_stats[3 * s + k];
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      if (s0 + q * NT < ns) {
+        imb = fmax(imb, v[q][0]);
+        fmx = fmax(fmx, v[q][1]);
+        ps += v[q][2];
+      }
+    }
   }
   red[0][tid] = imb; red[1][tid] = fmx; red[2][tid] = ps;
   __syncthreads();
@@ -642,9 +658,17 @@ __global__ void shift_kernel(double* p, size_t n, const double* mean) {
 
 __global__ void mobility_kernel(const double* in, double* lam, size_t n, int from_s, double mw,
                                 double mo) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const double v = in[i];
-    lam[i] = from_s ? v * v / mw + (1.0 - v) * (1.0 - v) / mo : v;
+  // four grid strides per step, loaded before any is stored
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i0 < n; i0 += 4 * stride) {
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = in[min(i0 + q * stride, n - 1)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const size_t i = i0 + q * stride;
+      if (i < n) lam[i] = from_s ? v[q] * v[q] / mw + (1.0 - v[q]) * (1.0 - v[q]) / mo : v[q];
+    }
   }
 }
 
