@@ -111,6 +111,7 @@ def main():
     import torch
     import inputs
     from paper_2104_04653_amd import MRCMSolver
+    from paper_2104_04653_amd.mrcm import Stats
 
     prob = inputs.make_problem(args.workload, seed=args.seed)
     n_steps_total = args.warmup + args.steps
@@ -166,14 +167,18 @@ def main():
             net = trained_surrogate()
             sol.set_surrogate(net)
         outs = [ctypes.c_void_p(t.data_ptr()) for t in (p, ux, uy)]
+        satp = [ctypes.c_void_p(t.data_ptr()) for t in sats]
         imb = ctypes.c_double()
+        stats = Stats()
 
         def step(k):
-            sol.update_mobility(sats[k])
-            sol.solve()
-            rc = sol.lib.mrcm_fine_flux(sol.ctx, *outs, 1, ctypes.byref(imb))
-            sol._check(rc, "mrcm_fine_flux")
-            return sol.stats()
+            # mobility update, solve and fine-scale reconstruction in one
+            # library call (one synchronisation); the saturations are device
+            # arrays on the solver's stream
+            rc = sol.lib.mrcm_step(sol.ctx, satp[k], 0, 1, *outs, 1, ctypes.byref(imb))
+            sol._check(rc, "mrcm_step")
+            sol._check(sol.lib.mrcm_get_stats(sol.ctx, ctypes.byref(stats)), "mrcm_get_stats")
+            return stats
 
         for k in range(args.warmup):
             step(k)
@@ -183,13 +188,13 @@ def main():
         t0 = time.perf_counter()
         for k in range(args.warmup, n_steps_total):
             st = step(k)
-            phase["local"].append(st["ms_local"])
-            phase["interface"].append(st["ms_interface"])
-            phase["flux"].append(st["ms_flux"])
-            phase["surrogate_inference_gate"].append(st["ms_surrogate"])
-            iters = max(iters, st["ir_iters_max"])
-            fallbacks = max(fallbacks, st["fallbacks"])
-            iface_ir = max(iface_ir, st["interface_ir_steps"])
+            phase["local"].append(st.ms_local)
+            phase["interface"].append(st.ms_interface)
+            phase["flux"].append(st.ms_flux)
+            phase["surrogate_inference_gate"].append(st.ms_surrogate)
+            iters = max(iters, st.ir_iters_max)
+            fallbacks = max(fallbacks, st.fallbacks)
+            iface_ir = max(iface_ir, st.interface_ir_steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         n_dof = sol.n_dof

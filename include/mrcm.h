@@ -173,6 +173,23 @@ int mrcm_solve(mrcm_ctx* ctx);
 int mrcm_fine_flux(mrcm_ctx* ctx, double* p, double* ux, double* uy, int32_t on_device,
                    double* max_cell_imbalance);
 
+/* One step of the pressure solve in one call: the mobility update, the
+ * solve and the fine-scale reconstruction, with one synchronisation where
+ * mrcm_update_mobility + mrcm_solve + mrcm_fine_flux take two or three.
+ *  values, values_are_lambda, values_on_device : as mrcm_update_mobility
+ *              (values = NULL keeps the current mobility; a host array is
+ *              read before the call returns);
+ *  p, ux, uy, outputs_on_device, max_cell_imbalance : as mrcm_fine_flux.
+ * The reconstruction is enqueued before the solve's status is known; if
+ * the interface solve needs refinement it is refined (one synchronisation
+ * per step) and the reconstruction is done again.  Results, statistics and
+ * errors are those of the three calls; on an error the outputs are
+ * unspecified.  MRCM_E_STATE for a MRCM_PREC_SURROGATE context without a
+ * network.  Synchronous: outputs are valid on return. */
+int mrcm_step(mrcm_ctx* ctx, const double* values, int32_t values_are_lambda,
+              int32_t values_on_device, double* p, double* ux, double* uy,
+              int32_t outputs_on_device, double* max_cell_imbalance);
+
 /* Statistics of the last solve / fine_flux. */
 int mrcm_get_stats(const mrcm_ctx* ctx, mrcm_stats* stats);
 

@@ -87,7 +87,7 @@ struct mrcm_ctx {
   // interface plan
   std::vector<LevelPlan> levels;
   long long leaf_block = 0;  // doubles per subdomain block
-  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -585,7 +585,7 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
       HIPCHK(c, hipStreamCreate(&c->st));
       c->own_stream = true;
     }
-    for (int i = 0; i < 5; ++i) HIPCHK(c, hipEventCreate(&c->ev[i]));
+    for (int i = 0; i < 6; ++i) HIPCHK(c, hipEventCreate(&c->ev[i]));
     ALLOC(c, c->K, ncell);
     ALLOC(c, c->lam, ncell);
     ALLOC(c, c->stage, ncell);
@@ -708,9 +708,10 @@ int mrcm_update_mobility(mrcm_ctx* c, const double* values, int32_t values_are_l
 
 namespace {
 
-// one solve; with the surrogate precision `pred` (device, may be NULL)
-// replaces the network's output
-int solve_impl(mrcm_ctx* c, const float* pred) {
+// The work of one solve, enqueued on the context's stream: local solves
+// (with the surrogate precision `pred`, device, may be NULL, replaces the
+// network's output), interface solve and its residual check.
+int solve_enqueue(mrcm_ctx* c, const float* pred) {
   hipStream_t st = c->st;
   hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(1), 0, st, c->status, c->fallback, c->ir_iters);
   HIPCHK(c, hipGetLastError());
@@ -737,25 +738,31 @@ int solve_impl(mrcm_ctx* c, const float* pred) {
     if (r != MRCM_OK) return r;
   }
   HIPCHK(c, hipEventRecord(c->ev[2], st));
-  HIPCHK(c, read_report(c));
-  const int* hi = reinterpret_cast<const int*>(c->h_report + RESULT_N);
-  const int status = hi[0], iters = hi[1], nfb = hi[2];
-  double res[2] = {c->h_report[2], c->h_report[3]};
-  // iterative refinement of the interface solve while its residual is above
-  // ir_tol of the right-hand side (high contrast with non-polynomial
-  // spaces makes the system ill-conditioned); checked at this existing
-  // synchronisation, so a well-conditioned solve pays nothing for it
-  c->iface_ir = 0;
+  return MRCM_OK;
+}
+
+// Residual of the interface solve in the report just read: above ir_tol of
+// the right-hand side (high contrast with non-polynomial spaces makes the
+// system ill-conditioned) the solve is refined, each step checked at a
+// synchronisation of its own; well-conditioned solves pay nothing.
+bool needs_refinement(const mrcm_ctx* c) {
   const double ir_tol = c->g.prec == 1 ? IFACE_IR_TOL_FP32 : IFACE_IR_TOL_FP64;
-  while (c->n_dof > 0 && c->iface_ir < IFACE_IR_MAX && res[0] > ir_tol * res[1]) {
+  return c->n_dof > 0 && c->iface_ir < IFACE_IR_MAX && c->h_report[2] > ir_tol * c->h_report[3];
+}
+
+// Statistics and status of a solve whose report has been read (and
+// refined while needed).
+int solve_finish(mrcm_ctx* c) {
+  while (needs_refinement(c)) {
     int r = refine_interface(c);
     if (r != MRCM_OK) return r;
-    HIPCHK(c, hipEventRecord(c->ev[2], st));
+    HIPCHK(c, hipEventRecord(c->ev[2], c->st));
     HIPCHK(c, read_report(c));
-    res[0] = c->h_report[2];
-    res[1] = c->h_report[3];
     c->iface_ir += 1;
   }
+  const int* hi = reinterpret_cast<const int*>(c->h_report + RESULT_N);
+  const int status = hi[0], iters = hi[1], nfb = hi[2];
+  const double res[2] = {c->h_report[2], c->h_report[3]};
   float t1 = 0.f, t2 = 0.f;
   (void)hipEventElapsedTime(&t1, c->ev[0], c->ev[1]);
   (void)hipEventElapsedTime(&t2, c->ev[1], c->ev[2]);
@@ -775,6 +782,54 @@ int solve_impl(mrcm_ctx* c, const float* pred) {
   if (status & (ST_LOCAL_PIVOT | ST_IFACE_PIVOT))
     return fail(c, MRCM_E_NOT_SPD, "non-positive or zero pivot in the elimination");
   c->solved = true;
+  return MRCM_OK;
+}
+
+int solve_impl(mrcm_ctx* c, const float* pred) {
+  c->solved = false;
+  int r = solve_enqueue(c, pred);
+  if (r != MRCM_OK) return r;
+  HIPCHK(c, read_report(c));
+  c->iface_ir = 0;
+  return solve_finish(c);
+}
+
+// The fine-scale reconstruction, enqueued: stitch and flux statistics, and
+// the copies of host outputs.  The stitch's pivot flag joins the solve's
+// status word (cleared by the solve).
+int flux_enqueue(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_device) {
+  hipStream_t st = c->st;
+  const Geo& G = c->g;
+  HIPCHK(c, hipEventRecord(c->ev[5], st));
+  SubArgs a = sub_args(c);
+  // device outputs are written by the kernels in place; host outputs are
+  // copied from the context's buffers
+  if (on_device) {
+    if (p) a.p_out = p;
+    if (ux) a.ux = ux;
+    if (uy) a.uy = uy;
+  }
+  HIPCHK(c, launch_stitch(a, st));
+  HIPCHK(c, launch_finish_flux(a, c->result, st));
+  HIPCHK(c, hipEventRecord(c->ev[3], st));
+  const size_t ncell = (size_t)G.nx * G.ny;
+  if (!on_device) {
+    const hipMemcpyKind kind = hipMemcpyDeviceToHost;
+    if (p) HIPCHK(c, hipMemcpyAsync(p, c->p, ncell * sizeof(double), kind, st));
+    if (ux) HIPCHK(c, hipMemcpyAsync(ux, c->ux, (size_t)(G.nx + 1) * G.ny * sizeof(double), kind, st));
+    if (uy) HIPCHK(c, hipMemcpyAsync(uy, c->uy, (size_t)G.nx * (G.ny + 1) * sizeof(double), kind, st));
+  }
+  return MRCM_OK;
+}
+
+// after the report of a reconstruction has been read
+int flux_finish(mrcm_ctx* c, double* max_cell_imbalance) {
+  const int status = reinterpret_cast<const int*>(c->h_report + RESULT_N)[0];
+  float t = 0.f;
+  (void)hipEventElapsedTime(&t, c->ev[5], c->ev[3]);
+  c->stats.ms_flux = t;
+  if (max_cell_imbalance) *max_cell_imbalance = c->h_report[0];
+  if (status & ST_STITCH_PIVOT) return fail(c, MRCM_E_NOT_SPD, "non-positive pivot in the stitch re-solve");
   return MRCM_OK;
 }
 
@@ -799,37 +854,51 @@ int mrcm_fine_flux(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_de
                    double* max_cell_imbalance) {
   if (!c) return MRCM_E_INVAL;
   if (!c->solved) return fail(c, MRCM_E_STATE, "fine_flux called before a successful solve");
-  hipStream_t st = c->st;
-  const Geo& G = c->g;
-  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, c->status);
-  HIPCHK(c, hipEventRecord(c->ev[2], st));
-  SubArgs a = sub_args(c);
-  // device outputs are written by the kernels in place; host outputs are
-  // copied from the context's buffers
-  if (on_device) {
-    if (p) a.p_out = p;
-    if (ux) a.ux = ux;
-    if (uy) a.uy = uy;
-  }
-  HIPCHK(c, launch_stitch(a, st));
-  HIPCHK(c, launch_finish_flux(a, c->result, st));
-  HIPCHK(c, hipEventRecord(c->ev[3], st));
-  const size_t ncell = (size_t)G.nx * G.ny;
-  if (!on_device) {
-    const hipMemcpyKind kind = hipMemcpyDeviceToHost;
-    if (p) HIPCHK(c, hipMemcpyAsync(p, c->p, ncell * sizeof(double), kind, st));
-    if (ux) HIPCHK(c, hipMemcpyAsync(ux, c->ux, (size_t)(G.nx + 1) * G.ny * sizeof(double), kind, st));
-    if (uy) HIPCHK(c, hipMemcpyAsync(uy, c->uy, (size_t)G.nx * (G.ny + 1) * sizeof(double), kind, st));
-  }
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c->st, c->status);
+  HIPCHK(c, hipGetLastError());
+  int r = flux_enqueue(c, p, ux, uy, on_device);
+  if (r != MRCM_OK) return r;
   HIPCHK(c, read_report(c));
-  const double imb = c->h_report[0];
-  const int status = reinterpret_cast<const int*>(c->h_report + RESULT_N)[0];
-  float t = 0.f;
-  (void)hipEventElapsedTime(&t, c->ev[2], c->ev[3]);
-  c->stats.ms_flux = t;
-  if (max_cell_imbalance) *max_cell_imbalance = imb;
-  if (status & ST_STITCH_PIVOT) return fail(c, MRCM_E_NOT_SPD, "non-positive pivot in the stitch re-solve");
-  return MRCM_OK;
+  return flux_finish(c, max_cell_imbalance);
+}
+
+int mrcm_step(mrcm_ctx* c, const double* values, int32_t values_are_lambda, int32_t values_on_device,
+              double* p, double* ux, double* uy, int32_t outputs_on_device, double* max_cell_imbalance) {
+  if (!c) return MRCM_E_INVAL;
+  if (c->precision == MRCM_PREC_SURROGATE && !c->s_ready)
+    return fail(c, MRCM_E_STATE, "surrogate precision: mrcm_set_surrogate was not called");
+  if (values) {
+    const size_t n = (size_t)c->g.nx * c->g.ny;
+    const double* src = values;
+    if (!values_on_device) {   // the host array is read before the call returns
+      HIPCHK(c, hipMemcpyAsync(c->stage, values, n * sizeof(double), hipMemcpyHostToDevice, c->st));
+      src = c->stage;
+    }
+    HIPCHK(c, launch_mobility(src, c->lam, n, values_are_lambda ? 0 : 1, c->mu_w, c->mu_o, c->st));
+  }
+  c->solved = false;
+  int r = solve_enqueue(c, nullptr);
+  if (r != MRCM_OK) return r;
+  // the reconstruction is enqueued before the solve's status is known; one
+  // synchronisation reads both reports
+  r = flux_enqueue(c, p, ux, uy, outputs_on_device);
+  if (r != MRCM_OK) return r;
+  HIPCHK(c, read_report(c));
+  c->iface_ir = 0;
+  if (needs_refinement(c)) {
+    // refine (solve_finish synchronises per step), then reconstruct again
+    r = solve_finish(c);
+    if (r != MRCM_OK) return r;
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c->st, c->status);
+    HIPCHK(c, hipGetLastError());
+    r = flux_enqueue(c, p, ux, uy, outputs_on_device);
+    if (r != MRCM_OK) return r;
+    HIPCHK(c, read_report(c));
+    return flux_finish(c, max_cell_imbalance);
+  }
+  r = solve_finish(c);
+  if (r != MRCM_OK) return r;
+  return flux_finish(c, max_cell_imbalance);
 }
 
 int mrcm_get_stats(const mrcm_ctx* c, mrcm_stats* s) {
@@ -931,7 +1000,7 @@ void mrcm_destroy(mrcm_ctx* c) {
   if (c->st) (void)hipStreamSynchronize(c->st);
   for (void* q : c->allocs) (void)hipFree(q);
   if (c->h_report) (void)hipHostFree(c->h_report);
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < 6; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
   delete c;

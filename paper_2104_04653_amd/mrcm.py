@@ -23,7 +23,7 @@ SPACES = {"linear": 0, "edge": 1, "full": 2}
 PRECISIONS = {"fp64": 0, "fp32_ir": 1, "surrogate": 2}
 
 EXPORTED = [
-    "mrcm_setup", "mrcm_update_mobility", "mrcm_solve", "mrcm_fine_flux", "mrcm_get_stats",
+    "mrcm_setup", "mrcm_update_mobility", "mrcm_solve", "mrcm_fine_flux", "mrcm_step", "mrcm_get_stats",
     "mrcm_get_sizes", "mrcm_get_interface_solution", "mrcm_get_local_blocks",
     "mrcm_get_basis", "mrcm_surrogate_inputs", "mrcm_surrogate_targets", "mrcm_set_surrogate",
     "mrcm_solve_with_predictions", "mrcm_set_gate_tolerance", "mrcm_cnn_create", "mrcm_cnn_num_params",
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
     lib.mrcm_update_mobility.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32]
     lib.mrcm_solve.argtypes = [P]
     lib.mrcm_fine_flux.argtypes = [P, P, P, P, ctypes.c_int32, dp]
+    lib.mrcm_step.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int32, dp]
     lib.mrcm_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.mrcm_get_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
@@ -236,6 +237,44 @@ class MRCMSolver:
 
     def solve(self):
         self._check(self.lib.mrcm_solve(self.ctx), "mrcm_solve")
+
+    def step(self, values=None, is_lambda: bool = False, out=None):
+        """update_mobility + solve + fine_flux in one library call with one
+        synchronisation.  values: as update_mobility, or None to keep the
+        mobility.  out: None (host numpy outputs are returned) or a tuple of
+        three contiguous float64 device tensors (p, ux, uy) written in place.
+        Returns (p, ux, uy, max_cell_imbalance)."""
+        n = self.nx * self.ny
+        vptr, von = None, 0
+        if values is not None:
+            if _is_device(values):
+                if values.numel() != n or str(values.dtype) != "torch.float64" or not values.is_contiguous():
+                    raise ValueError("device mobility must be a contiguous float64 tensor of nx*ny")
+                import torch
+                cur = torch.cuda.current_stream()
+                if cur.cuda_stream != self._stream:
+                    cur.synchronize()   # producer work on another stream is complete
+                vptr, von = ctypes.c_void_p(values.data_ptr()), 1
+            else:
+                arr = _host(values, n)
+                vptr = arr.ctypes.data_as(ctypes.c_void_p)
+        imb = ctypes.c_double()
+        sizes = (n, (self.nx + 1) * self.ny, self.nx * (self.ny + 1))
+        if out is not None:
+            for t, m in zip(out, sizes):
+                if not _is_device(t) or t.numel() != m or str(t.dtype) != "torch.float64" \
+                        or not t.is_contiguous():
+                    raise ValueError("out must be three contiguous float64 device tensors")
+            res = tuple(out)
+            ptrs = [ctypes.c_void_p(t.data_ptr()) for t in res]
+            oon = 1
+        else:
+            res = tuple(np.empty(m) for m in sizes)
+            ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in res]
+            oon = 0
+        rc = self.lib.mrcm_step(self.ctx, vptr, int(is_lambda), von, *ptrs, oon, ctypes.byref(imb))
+        self._check(rc, "mrcm_step")
+        return res + (imb.value,)
 
     def fine_flux(self, device: bool = False):
         """Return (p, ux, uy, max_cell_imbalance); numpy, or torch tensors on
