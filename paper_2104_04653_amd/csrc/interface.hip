@@ -398,23 +398,6 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
       return;
     }
   }
-  // this thread's entries of the A22 tile, loaded with the operands (kind 2:
-  // wave w owns the 16 x 16 tile (w / 2, w % 2), in a22[0]).  Every load
-  // below is issued unconditionally, from an index clamped into the block,
-  // and entries outside it are dropped afterwards: a branch around a load
-  // would make each load wait for the previous one.
-  double a22[4][4];
-  const bool k2 = kind == 2;
-#pragma unroll
-  for (int tj = 0; tj < 4; ++tj) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      // kind 2 reads its one tile four times over: the loads stay unconditional
-      const int i = (k2 ? 16 * (w >> 1) : 16 * w) + 4 * v + g, j = (k2 ? 16 * (w & 1) : 16 * tj) + c;
-      const double x = a22_at(min(i, rows - 1), min(j, cols - 1));
-      a22[tj][v] = (i < rows && j < cols) ? x : 0.0;
-    }
-  }
   // the rhs column after the tile (xr): A22 rows in wave 0, panel rows in
   // the first half of wave 1 (loaded either way, used only with xr)
   double xrv;
@@ -446,6 +429,25 @@ __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
     const int e = t + NT * q, k = min(e / TILE, nb - 1), j = min(e % TILE, cols - 1);
     if constexpr (FIRST) xb[q] = gather_entry(nd, tree, mk[k], mc[j], c0 + j == n);
     else xb[q] = F[(long long)(k0 + k) * ld + c0 + j];
+  }
+  // this thread's entries of the A22 tile (kind 2: wave w owns the 16 x 16
+  // tile (w / 2, w % 2), in a22[0]), issued after the panel operands: a
+  // wait for a load waits for every load issued before it, and A22 is used
+  // last, so these stay in flight through the inversion and the products.
+  // Like all loads here they are unconditional, from indices clamped into
+  // the block, and entries outside it are dropped afterwards: a branch
+  // around a load would make each load wait for the previous one.
+  double a22[4][4];
+  const bool k2 = kind == 2;
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      // kind 2 reads its one tile four times over: the loads stay unconditional
+      const int i = (k2 ? 16 * (w >> 1) : 16 * w) + 4 * v + g, j = (k2 ? 16 * (w & 1) : 16 * tj) + c;
+      const double x = a22_at(min(i, rows - 1), min(j, cols - 1));
+      a22[tj][v] = (i < rows && j < cols) ? x : 0.0;
+    }
   }
 #pragma unroll
   for (int q = 0; q < PD; ++q) {
