@@ -205,7 +205,10 @@ int mrcm_get_sizes(const mrcm_ctx* ctx, int32_t* n_dof, int32_t* n_sub, int32_t*
  *     columns follow the subdomain's W, E, S, N interfaces (nP+nU each,
  *     zero for sides on the domain boundary); column R-1 holds the
  *     right-hand side.  Rows of flux (U) dofs are the negated
- *     pressure-continuity equations, which makes every block symmetric.
+ *     pressure-continuity equations: a block is then symmetric except for
+ *     the couplings between the pressure and flux dofs of one edge, which
+ *     are antisymmetric and cancel between the edge's two subdomains, so
+ *     that the assembled interface matrix is symmetric.
  *  mrcm_get_basis : n_sub * R * sub_nx*sub_ny values, column-major per
  *     subdomain: [sd][col][l] with local cell l = ly*sub_nx + lx; column 0
  *     is the particular solution, column 1 + side*(nP+nU) + k the basis
