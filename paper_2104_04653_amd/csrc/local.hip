@@ -232,7 +232,8 @@ struct LocalStore {
 
 // Traces of every column (Xs: [cell][column], FP64) projected on the
 // interface functions: the subdomain's block of the interface system, rows
-// of flux dofs negated (symmetric form), last column = right-hand side.
+// of flux dofs negated (the form in which the assembled interface matrix
+// is symmetric), last column = right-hand side.
 template <int M, int D>
 __device__ void generic_block(const SubArgs& a, int sd, int I, int J, const double* kap,
                               const double* Xs) {

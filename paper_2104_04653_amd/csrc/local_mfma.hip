@@ -235,7 +235,8 @@ __device__ inline void robin_data(const Geo& g, const Faces& f, double (*bside)[
 // Traces of every column on the skeleton faces (xb: solution in the cells
 // next to each side's faces) projected on the interface functions: the
 // subdomain's block of the interface system, rows of flux dofs negated
-// (symmetric form), last column = right-hand side.  One (side, column) pair
+// (the form in which the assembled interface matrix is symmetric), last
+// column = right-hand side.  One (side, column) pair
 // per thread, the D rows of that side accumulated together.
 __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const Faces& f,
                                    const double (*xb)[M][R]) {

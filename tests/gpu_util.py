@@ -56,7 +56,7 @@ def padded_columns(prob, sd):
 
 
 def oracle_blocks_padded(prob, ref):
-    """Oracle blocks in the library's symmetric padded layout."""
+    """Oracle blocks in the library's padded layout and sign convention."""
     g = Geometry(prob)
     D = prob.p_dofs + prob.u_dofs
     NB = 4 * D
