@@ -78,7 +78,7 @@ struct mrcm_ctx {
   // surrogate precision: network parameters and per-subdomain activations
   float* s_p32 = nullptr;
   short* s_wb = nullptr;
-  short *s_in = nullptr, *s_a1 = nullptr, *s_a2 = nullptr, *s_a3 = nullptr;
+  short* s_in = nullptr;
   float* s_pred = nullptr;
   bool s_ready = false;
   double gate_tol = 1e-6;
@@ -616,9 +616,6 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
       ALLOC(c, c->s_p32, cnn::n_params());
       ALLOC(c, c->s_wb, cnn::n_params());
       ALLOC(c, c->s_in, pix * 8);
-      ALLOC(c, c->s_a1, pix * 32);
-      ALLOC(c, c->s_a2, pix * 32);
-      ALLOC(c, c->s_a3, pix * 32);
       ALLOC(c, c->s_pred, pix * 16);
     }
     HIPCHK(c, hipMemcpy(c->K, perm, ncell * sizeof(double), hipMemcpyHostToDevice));
@@ -723,7 +720,7 @@ int solve_enqueue(mrcm_ctx* c, const float* pred) {
     const int n = c->g.n_sub;
     if (!pred) {
       HIPCHK(c, launch_surrogate_inputs(a, c->s_in, st));
-      HIPCHK(c, cnn::forward(c->s_in, c->s_wb, c->s_p32, c->s_a1, c->s_a2, c->s_a3, c->s_pred, n, st));
+      HIPCHK(c, cnn::forward_fused(c->s_in, c->s_wb, c->s_p32, c->s_pred, n, st));
       pred = c->s_pred;
     }
     HIPCHK(c, launch_surrogate_gate(a, pred, st));

@@ -144,6 +144,10 @@ int off_b(int l);
 // forward pass of the network: in BF16 [batch][256][8] -> out FP32 [batch][256][16]
 hipError_t forward(const short* in, const short* wb, const float* p32, short* a1, short* a2,
                    short* a3, float* out, int batch, hipStream_t st);
+// the same outputs from one launch that keeps the activations on chip
+// (inference only: the per-layer form keeps them for the backward pass)
+hipError_t forward_fused(const short* in, const short* wb, const float* p32, float* out, int batch,
+                         hipStream_t st);
 hipError_t cast(const float* p32, short* wb, hipStream_t st);
 const float* params_of(const mrcm_cnn* net);
 hipStream_t stream_of(const mrcm_cnn* net);

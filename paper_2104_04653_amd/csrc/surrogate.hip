@@ -137,6 +137,103 @@ __global__ void __launch_bounds__(NT) conv_fwd_kernel(const short* in, const sho
 }
 
 // ---------------------------------------------------------------------------
+// inference: the four layers of one patch in one work-group, the
+// activations kept in LDS (two 32-channel tiles with a zero halo, used in
+// turn; the 8-channel input has a tile of its own).  The arithmetic is the
+// per-layer kernel's (same K order, same BF16 rounding of the activations),
+// so the outputs are the same bits, without the three activation round
+// trips through HBM and three launches.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, bool RELU, bool OUTF32>
+__device__ void conv_layer_lds(const short* Xin, const short* W, const float* bias, short* Ws,
+                               short* Xout, float* out_f) {
+  constexpr int KP = kpad<CIN>(), NK = KP / 16, MT = COUT / 16;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x = lane & 15, g = lane >> 4;
+  for (int e = threadIdx.x; e < COUT * KP / 4; e += NT)   // coalesced 8-byte copies
+    reinterpret_cast<s4*>(Ws)[e] = reinterpret_cast<const s4*>(W)[e];
+  float bv4[MT][4];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) bv4[mt][v] = bias[mt * 16 + 4 * g + v];
+  __syncthreads();   // weights staged; the input tile is complete
+  s4 av[MT][NK];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk)
+      av[mt][kk] = *reinterpret_cast<const s4*>(&Ws[(mt * 16 + x) * KP + 16 * kk + 4 * g]);
+  // the wave's four image rows at once: eight independent accumulators
+  // keep the matrix cores busy (one row at a time waits on each MFMA)
+  f4 acc[4][MT];
+#pragma unroll
+  for (int yy = 0; yy < 4; ++yy)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[yy][mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk) {
+    const int k0 = 16 * kk + 4 * g, tap = k0 / CIN, ci = k0 % CIN;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    s4 bv[4];
+#pragma unroll
+    for (int yy = 0; yy < 4; ++yy) {
+      const int y = wv * 4 + yy;
+      bv[yy] = s4{0, 0, 0, 0};
+      if (tap < 9) bv[yy] = *reinterpret_cast<const s4*>(&Xin[((y + dy + 1) * HALO + x + dx + 1) * CIN + ci]);
+    }
+#pragma unroll
+    for (int yy = 0; yy < 4; ++yy)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[yy][mt] = mma(av[mt][kk], bv[yy], acc[yy][mt]);
+  }
+#pragma unroll
+  for (int yy = 0; yy < 4; ++yy) {
+    const int y = wv * 4 + yy;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      float val[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        val[v] = acc[yy][mt][v] + bv4[mt][v];
+        if (RELU) val[v] = fmaxf(val[v], 0.f);
+      }
+      const int co = mt * 16 + 4 * g;
+      if (OUTF32) {
+        *reinterpret_cast<f4*>(&out_f[(size_t)(y * HW + x) * COUT + co]) = f4{val[0], val[1], val[2], val[3]};
+      } else {
+        *reinterpret_cast<s4*>(&Xout[((y + 1) * HALO + x + 1) * COUT + co]) =
+            s4{f2bf(val[0]), f2bf(val[1]), f2bf(val[2]), f2bf(val[3])};
+      }
+    }
+  }
+  __syncthreads();   // the output tile is complete and the weights are free
+}
+
+__global__ void __launch_bounds__(NT) forward_fused_kernel(const short* in, const short* wb,
+                                                           const float* p32, int ow0, int ow1,
+                                                           int ow2, int ow3, int ob0, int ob1,
+                                                           int ob2, int ob3, float* out) {
+  constexpr int KPMAX = kpad<32>();
+  __shared__ __attribute__((aligned(16))) short X8[HALO * HALO * 8];
+  __shared__ __attribute__((aligned(16))) short Xa[HALO * HALO * 32];
+  __shared__ __attribute__((aligned(16))) short Xb[HALO * HALO * 32];
+  __shared__ __attribute__((aligned(16))) short Ws[32 * KPMAX];
+  const int b = blockIdx.x;
+  // zero halos of the 32-channel tiles (their interiors are written whole
+  // by every layer), then the input tile
+  for (int e = threadIdx.x; e < HALO * HALO * 32 / 4; e += NT) {
+    reinterpret_cast<s4*>(Xa)[e] = s4{0, 0, 0, 0};
+    reinterpret_cast<s4*>(Xb)[e] = s4{0, 0, 0, 0};
+  }
+  load_halo<8>(in + (size_t)b * NPIX * 8, X8);
+  conv_layer_lds<8, 32, true, false>(X8, wb + ow0, p32 + ob0, Ws, Xa, nullptr);
+  conv_layer_lds<32, 32, true, false>(Xa, wb + ow1, p32 + ob1, Ws, Xb, nullptr);
+  conv_layer_lds<32, 32, true, false>(Xb, wb + ow2, p32 + ob2, Ws, Xa, nullptr);
+  conv_layer_lds<32, 16, false, true>(Xa, wb + ow3, p32 + ob3, Ws, nullptr, out + (size_t)b * NPIX * 16);
+}
+
+// ---------------------------------------------------------------------------
 // backward to the input: dx[q][ci] = sum_{tap,co} W[co][tap][ci] gy[q - off(tap)][co],
 // multiplied by the ReLU mask of the previous layer's output (y_prev > 0)
 // ---------------------------------------------------------------------------
@@ -331,6 +428,14 @@ hipError_t forward(const short* in, const short* wb, const float* p32, short* a1
                      wb + off_w(2), p32 + off_b(2), a3, nullptr);
   hipLaunchKernelGGL((conv_fwd_kernel<32, 16, false, true>), dim3(batch), dim3(NT), 0, st, a3,
                      wb + off_w(3), p32 + off_b(3), nullptr, out);
+  return hipGetLastError();
+}
+
+hipError_t forward_fused(const short* in, const short* wb, const float* p32, float* out, int batch,
+                         hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(forward_fused_kernel, dim3(batch), dim3(NT), 0, st, in, wb, p32, off_w(0), off_w(1),
+                     off_w(2), off_w(3), off_b(0), off_b(1), off_b(2), off_b(3), out);
   return hipGetLastError();
 }
 
@@ -543,8 +648,7 @@ int mrcm_cnn_set_params(mrcm_cnn* net, const float* params) {
 
 int mrcm_cnn_forward(mrcm_cnn* net, const void* inputs, float* outputs, int32_t batch) {
   if (!net || !inputs || !outputs || batch <= 0 || batch > net->max_batch) return MRCM_E_INVAL;
-  CNN_HIP(mrcm::cnn::forward((const short*)inputs, net->wb, net->p32, net->a1, net->a2, net->a3,
-                             outputs, batch, net->st));
+  CNN_HIP(mrcm::cnn::forward_fused((const short*)inputs, net->wb, net->p32, outputs, batch, net->st));
   CNN_HIP(hipStreamSynchronize(net->st));
   return MRCM_OK;
 }
