@@ -91,6 +91,8 @@ typedef struct {
                         (eq. (fluxos1) with k_rw = s^2, k_ro = (1-s)^2, section 5) */
 } mrcm_fluid;
 
+/* Phase times are read from the GPU's constant-rate clock by the kernels that
+   open and close each phase, so timing adds no work to the stream. */
 typedef struct {
   double ms_local;       /* last solve: assemble + factor + basis solves + traces */
   double ms_interface;   /* last solve: interface system (FP64) */

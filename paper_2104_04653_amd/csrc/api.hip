@@ -87,7 +87,9 @@ struct mrcm_ctx {
   // interface plan
   std::vector<LevelPlan> levels;
   long long leaf_block = 0;  // doubles per subdomain block
-  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // solve start, local end, gate end
+  unsigned long long* stamps = nullptr;   // device, inside the report block
+  double clock_khz = 0.0;                 // rate of the clock the kernels read
 };
 
 namespace {
@@ -124,9 +126,12 @@ int dev_alloc(mrcm_ctx* c, T** p, size_t count) {
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
 // report block: doubles result[0] = max cell imbalance, [1] = pressure sum
-// (gauge shift), [2] = max |r|, [3] = max |b| of the interface residual;
-// then ints status, ir_iters, fallback count, fallback list
-constexpr int RESULT_N = 8;
+// (gauge shift), [2] = max |r|, [3] = max |b| of the interface residual,
+// [STAMP_OFF + k] = clock reading of phase boundary k (PhaseStamp), as an
+// unsigned 64-bit integer; then ints status, ir_iters, fallback count,
+// fallback list
+constexpr int STAMP_OFF = 4;
+constexpr int RESULT_N = STAMP_OFF + STAMP_N + 1;
 constexpr size_t REPORT_HEAD = RESULT_N * sizeof(double) + 3 * sizeof(int);
 
 constexpr int IFACE_IR_MAX = 3;         // refinement steps of the interface solve
@@ -446,12 +451,23 @@ SubArgs sub_args(const mrcm_ctx* c) {
   a.gate_tol = c->gate_tol;
   a.scratch = c->scratch;
   a.scratch_stride = c->scratch_stride;
+  a.stamps = c->stamps;
   return a;
 }
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
 
-__global__ void zero_ints_kernel(int* a, int* b, int* c) { *a = 0; *b = 0; *c = 0; }
+// clears the status words of a solve and stamps its start
+__global__ void zero_ints_kernel(int* a, int* b, int* c, unsigned long long* stamps) {
+  *a = 0; *b = 0; *c = 0;
+  stamp_now(stamps + STAMP_SOLVE);
+}
+
+// milliseconds between two phase stamps of the report just read
+double stamp_ms(const mrcm_ctx* c, int from, int to) {
+  const unsigned long long* s = reinterpret_cast<const unsigned long long*>(c->h_report + STAMP_OFF);
+  return s[to] >= s[from] ? (double)(s[to] - s[from]) / c->clock_khz : 0.0;
+}
 
 // copy the head of the report block into the pinned host mirror and wait
 hipError_t read_report(mrcm_ctx* c) {
@@ -462,23 +478,29 @@ hipError_t read_report(mrcm_ctx* c) {
 
 int run_interface(mrcm_ctx* c) {
   hipStream_t st = c->st;
+  // the first launch stamps the start of the interface phase
+  unsigned long long* stamp = c->stamps + STAMP_IFACE;
   for (const LevelPlan& lp : c->levels) {
     if (lp.small) {
       HIPCHK(c, launch_front_small(c->d_lvnodes + lp.ids_off, lp.count, lp.max_n, c->tree,
-                                   c->d_maps, c->status, st));
+                                   c->d_maps, c->status, stamp, st));
+      stamp = nullptr;
       continue;
     }
     // the first panel assembles the fronts and inverts its own diagonal
     // block; each panel inverts the next one
     for (const PanelLaunch& pl : lp.panels)
-      if (pl.update_count > 0)   // the root's last panel has no trailing rows
+      if (pl.update_count > 0) {   // the root's last panel has no trailing rows
         HIPCHK(c, launch_front_update(c->d_nodes, c->d_items + pl.update_off, pl.update_count,
-                                      pl.k0, c->tree, c->d_maps, c->inv, c->status, st));
+                                      pl.k0, c->tree, c->d_maps, c->inv, c->status, stamp, st));
+        stamp = nullptr;
+      }
   }
   for (auto it = c->levels.rbegin(); it != c->levels.rend(); ++it)
     HIPCHK(c, launch_front_back(c->d_lvnodes + it->ids_off, it->count, it->max_n, c->tree, c->inv, c->d_dofs,
                                 nullptr, c->coef, st));
-  HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2, st));
+  HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2,
+                                  c->stamps + STAMP_IFACE_END, st));
   return MRCM_OK;
 }
 
@@ -495,7 +517,8 @@ int refine_interface(mrcm_ctx* c) {
     HIPCHK(c, launch_front_back(c->d_lvnodes + lv->ids_off, lv->count, lv->max_n, c->tree, c->inv, c->d_dofs,
                                 c->rtree, c->dx, st));
   HIPCHK(c, launch_add(c->coef, c->dx, c->n_dof, st));
-  HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2, st));
+  HIPCHK(c, launch_iface_residual(c->g, c->tree, c->coef, c->rvec, c->partials, c->result + 2,
+                                  c->stamps + STAMP_IFACE_END, st));
   return MRCM_OK;
 }
 
@@ -585,7 +608,7 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
       HIPCHK(c, hipStreamCreate(&c->st));
       c->own_stream = true;
     }
-    for (int i = 0; i < 6; ++i) HIPCHK(c, hipEventCreate(&c->ev[i]));
+    for (int i = 0; i < 3; ++i) HIPCHK(c, hipEventCreate(&c->ev[i]));
     ALLOC(c, c->K, ncell);
     ALLOC(c, c->lam, ncell);
     ALLOC(c, c->stage, ncell);
@@ -602,6 +625,14 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
     ALLOC(c, c->report, RESULT_N + (G.n_sub + 4 + 1) / 2);
     c->result = c->report;
     c->status = reinterpret_cast<int*>(c->report + RESULT_N);
+    c->stamps = reinterpret_cast<unsigned long long*>(c->report + STAMP_OFF);
+    {
+      int dev = 0, khz = 0;
+      HIPCHK(c, hipGetDevice(&dev));
+      HIPCHK(c, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+      if (khz <= 0) return fail(c, MRCM_E_HIP, "device reports no wall clock rate");
+      c->clock_khz = khz;
+    }
     c->ir_iters = c->status + 1;
     c->fallback = c->status + 2;
     {
@@ -710,9 +741,15 @@ namespace {
 // network's output), interface solve and its residual check.
 int solve_enqueue(mrcm_ctx* c, const float* pred) {
   hipStream_t st = c->st;
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(1), 0, st, c->status, c->fallback, c->ir_iters);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(1), 0, st, c->status, c->fallback, c->ir_iters,
+                     c->stamps);
   HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipEventRecord(c->ev[0], st));
+  // the phases are timed by the kernels' clock stamps; events (each a packet
+  // that drains the stream) only where no kernel marks the boundary: the
+  // surrogate's gate, and the end of the local phase when there is no
+  // interface system
+  const bool ev_local = c->n_dof == 0, ev_gate = c->precision == MRCM_PREC_SURROGATE;
+  if (ev_local || ev_gate) HIPCHK(c, hipEventRecord(c->ev[0], st));
   SubArgs a = sub_args(c);
   if (c->precision == MRCM_PREC_SURROGATE) {
     // network inference and residual gate, then the FP64 kernel on the
@@ -724,17 +761,16 @@ int solve_enqueue(mrcm_ctx* c, const float* pred) {
       pred = c->s_pred;
     }
     HIPCHK(c, launch_surrogate_gate(a, pred, st));
-    HIPCHK(c, hipEventRecord(c->ev[4], st));
+    HIPCHK(c, hipEventRecord(c->ev[2], st));
     HIPCHK(c, launch_basis_m16d4_list(a, st));
   } else {
     HIPCHK(c, launch_local_basis(a, st));
   }
-  HIPCHK(c, hipEventRecord(c->ev[1], st));
+  if (ev_local) HIPCHK(c, hipEventRecord(c->ev[1], st));
   if (c->n_dof > 0) {
     int r = run_interface(c);
     if (r != MRCM_OK) return r;
   }
-  HIPCHK(c, hipEventRecord(c->ev[2], st));
   return MRCM_OK;
 }
 
@@ -753,22 +789,25 @@ int solve_finish(mrcm_ctx* c) {
   while (needs_refinement(c)) {
     int r = refine_interface(c);
     if (r != MRCM_OK) return r;
-    HIPCHK(c, hipEventRecord(c->ev[2], c->st));
     HIPCHK(c, read_report(c));
     c->iface_ir += 1;
   }
   const int* hi = reinterpret_cast<const int*>(c->h_report + RESULT_N);
   const int status = hi[0], iters = hi[1], nfb = hi[2];
   const double res[2] = {c->h_report[2], c->h_report[3]};
-  float t1 = 0.f, t2 = 0.f;
-  (void)hipEventElapsedTime(&t1, c->ev[0], c->ev[1]);
-  (void)hipEventElapsedTime(&t2, c->ev[1], c->ev[2]);
-  c->stats.ms_local = t1;
-  c->stats.ms_interface = t2;
+  if (c->n_dof > 0) {
+    c->stats.ms_local = stamp_ms(c, STAMP_SOLVE, STAMP_IFACE);
+    c->stats.ms_interface = stamp_ms(c, STAMP_IFACE, STAMP_IFACE_END);
+  } else {
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, c->ev[0], c->ev[1]);
+    c->stats.ms_local = t;
+    c->stats.ms_interface = 0.0;
+  }
   c->stats.ms_surrogate = 0.0;
   if (c->precision == MRCM_PREC_SURROGATE) {
     float ts = 0.f;
-    (void)hipEventElapsedTime(&ts, c->ev[0], c->ev[4]);
+    (void)hipEventElapsedTime(&ts, c->ev[0], c->ev[2]);
     c->stats.ms_surrogate = ts;
   }
   c->stats.interface_residual = res[1] > 0.0 ? res[0] / res[1] : 0.0;
@@ -797,7 +836,6 @@ int solve_impl(mrcm_ctx* c, const float* pred) {
 int flux_enqueue(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_device) {
   hipStream_t st = c->st;
   const Geo& G = c->g;
-  HIPCHK(c, hipEventRecord(c->ev[5], st));
   SubArgs a = sub_args(c);
   // device outputs are written by the kernels in place; host outputs are
   // copied from the context's buffers
@@ -808,7 +846,6 @@ int flux_enqueue(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_devi
   }
   HIPCHK(c, launch_stitch(a, st));
   HIPCHK(c, launch_finish_flux(a, c->result, st));
-  HIPCHK(c, hipEventRecord(c->ev[3], st));
   const size_t ncell = (size_t)G.nx * G.ny;
   if (!on_device) {
     const hipMemcpyKind kind = hipMemcpyDeviceToHost;
@@ -822,9 +859,7 @@ int flux_enqueue(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_devi
 // after the report of a reconstruction has been read
 int flux_finish(mrcm_ctx* c, double* max_cell_imbalance) {
   const int status = reinterpret_cast<const int*>(c->h_report + RESULT_N)[0];
-  float t = 0.f;
-  (void)hipEventElapsedTime(&t, c->ev[5], c->ev[3]);
-  c->stats.ms_flux = t;
+  c->stats.ms_flux = stamp_ms(c, STAMP_FLUX, STAMP_FLUX_END);
   if (max_cell_imbalance) *max_cell_imbalance = c->h_report[0];
   if (status & ST_STITCH_PIVOT) return fail(c, MRCM_E_NOT_SPD, "non-positive pivot in the stitch re-solve");
   return MRCM_OK;
@@ -997,8 +1032,8 @@ void mrcm_destroy(mrcm_ctx* c) {
   if (c->st) (void)hipStreamSynchronize(c->st);
   for (void* q : c->allocs) (void)hipFree(q);
   if (c->h_report) (void)hipHostFree(c->h_report);
-  for (int i = 0; i < 6; ++i)
-    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  for (hipEvent_t e : c->ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
   delete c;
 }

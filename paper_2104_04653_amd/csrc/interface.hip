@@ -79,7 +79,9 @@ constexpr int TXN = 32, TYN = NT / TXN;
 // rhs in the trailing block) is stored row-major, n x (n + 1).
 template <int RI, int CJ>
 __global__ void __launch_bounds__(NT) front_small_kernel(const NodeDesc* nodes, double* tree,
-                                                         const int2* maps, int* status) {
+                                                         const int2* maps, int* status,
+                                                         unsigned long long* stamp) {
+  if (stamp && blockIdx.x == 0 && threadIdx.x == 0) stamp_now(stamp);
   __shared__ int2 mp[SMALL_FRONT];
   __shared__ double prow[2][SMALL_FRONT + 1], pcol[2][SMALL_FRONT];
   const NodeDesc nd = nodes[blockIdx.x];   // this level's fronts, one per work-group
@@ -322,7 +324,9 @@ template <bool FIRST>
 __global__ void __launch_bounds__(NT) front_update_kernel(const NodeDesc* nodes,
                                                           const PanelItem* items, int k0,
                                                           double* tree, const int2* maps,
-                                                          double* inv, int* status) {
+                                                          double* inv, int* status,
+                                                          unsigned long long* stamp) {
+  if (stamp && blockIdx.x == 0 && threadIdx.x == 0) stamp_now(stamp);
   __shared__ double Dv[PANEL_NB][PANEL_NB + 1];   // A11^-1; then the next diagonal block
   __shared__ double As[TILE][PANEL_NB + 1];       // A21 rows of the tile
   __shared__ double Bs[PANEL_NB][TILE + 1];       // A12 columns of the tile; then W = A11^-1 A12
@@ -888,7 +892,7 @@ __global__ void __launch_bounds__(NT) iface_residual_kernel(Geo g, const double*
 }
 
 __global__ void __launch_bounds__(NT) max_pairs_kernel(const double* partials, int count,
-                                                       double* out2) {
+                                                       double* out2, unsigned long long* stamp) {
   __shared__ double red[2][NT];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < count; i += NT) {
@@ -908,18 +912,21 @@ __global__ void __launch_bounds__(NT) max_pairs_kernel(const double* partials, i
   if (threadIdx.x == 0) {
     out2[0] = red[0][0];
     out2[1] = red[1][0];
+    stamp_now(stamp);
   }
 }
 
 }  // namespace
 
 hipError_t launch_front_small(const NodeDesc* nodes, int count, int max_n, double* tree,
-                              const int2* maps, int* status, hipStream_t st) {
+                              const int2* maps, int* status, unsigned long long* stamp,
+                              hipStream_t st) {
   // the smallest register tile that holds the level's largest front (the
   // plan keeps max_n <= SMALL_FRONT): rows TYN RI >= n, columns TXN CJ > n
   static_assert(TYN * 8 >= SMALL_FRONT && TXN * 3 > SMALL_FRONT, "register tile of the largest front");
 #define SMALL_LAUNCH(RI, CJ) \
-  hipLaunchKernelGGL((front_small_kernel<RI, CJ>), dim3(count), dim3(NT), 0, st, nodes, tree, maps, status)
+  hipLaunchKernelGGL((front_small_kernel<RI, CJ>), dim3(count), dim3(NT), 0, st, nodes, tree, maps, status, \
+                     stamp)
   if (max_n <= 31) SMALL_LAUNCH(4, 1);
   else if (max_n <= 40) SMALL_LAUNCH(5, 2);
   else if (max_n <= 56) SMALL_LAUNCH(7, 2);
@@ -931,13 +938,13 @@ hipError_t launch_front_small(const NodeDesc* nodes, int count, int max_n, doubl
 
 hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count, int k0,
                                double* tree, const int2* maps, double* inv, int* status,
-                               hipStream_t st) {
+                               unsigned long long* stamp, hipStream_t st) {
   if (k0 == 0)
     hipLaunchKernelGGL(front_update_kernel<true>, dim3(count), dim3(NT), 0, st, nodes, items, k0,
-                       tree, maps, inv, status);
+                       tree, maps, inv, status, stamp);
   else
     hipLaunchKernelGGL(front_update_kernel<false>, dim3(count), dim3(NT), 0, st, nodes, items, k0,
-                       tree, maps, inv, status);
+                       tree, maps, inv, status, stamp);
   return hipGetLastError();
 }
 
@@ -969,7 +976,8 @@ hipError_t launch_add(double* x, const double* dx, int n, hipStream_t st) {
 }
 
 hipError_t launch_iface_residual(const Geo& g, const double* blocks, const double* x, double* r,
-                                 double* partials, double* out2, hipStream_t st) {
+                                 double* partials, double* out2, unsigned long long* stamp,
+                                 hipStream_t st) {
   if (g.D == 4)
     hipLaunchKernelGGL(iface_residual_kernel<4>, dim3(RESID_WG), dim3(NT), 0, st, g, blocks, x, r,
                        partials);
@@ -978,7 +986,7 @@ hipError_t launch_iface_residual(const Geo& g, const double* blocks, const doubl
                        partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(max_pairs_kernel, dim3(1), dim3(NT), 0, st, partials, RESID_WG, out2);
+  hipLaunchKernelGGL(max_pairs_kernel, dim3(1), dim3(NT), 0, st, partials, RESID_WG, out2, stamp);
   return hipGetLastError();
 }
 

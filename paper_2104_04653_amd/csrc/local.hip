@@ -463,6 +463,7 @@ __device__ double compose_at(const SubArgs& a, int sd, int l) {
 
 template <int M, int D>
 __global__ void __launch_bounds__(NT) stitch_kernel(SubArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) stamp_now(a.stamps + STAMP_FLUX);
   constexpr int MM = M * M;
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
   __shared__ double pm[MM];          // composed multiscale pressure
@@ -648,6 +649,7 @@ __global__ void __launch_bounds__(NT) finish_reduce_kernel(SubArgs a, double* re
   if (tid == 0) {
     result[0] = red[0][0] / fmax(red[1][0], 1e-300);
     result[1] = red[2][0] / ((double)a.g.nx * a.g.ny);
+    stamp_now(a.stamps + STAMP_FLUX_END);
   }
 }
 

@@ -1276,6 +1276,7 @@ __device__ inline double compose16(const SubArgs& a, int sd, int l, const double
 
 // four wavefronts per SIMD: 128 registers per lane and 19 KB of LDS per pair
 __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) stamp_now(a.stamps + STAMP_FLUX);
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
   __shared__ double pm[MM], bs_[MM], ps[MM], rs[MM];
   __shared__ double Fout[4][M];

@@ -54,7 +54,22 @@ struct SubArgs {
   double gate_tol;        // surrogate: accepted if ||b - A x|| <= gate_tol ||b|| per column
   double* scratch;        // generic kernels: per-subdomain work arrays (global memory)
   long long scratch_stride;   // doubles per subdomain in scratch
+  unsigned long long* stamps; // phase clock readings (PhaseStamp slots)
 };
+
+// Phase boundaries, read from the GPU's constant-rate clock by the kernels
+// that open or close a phase (thread 0 of work-group 0 at its start, or the
+// single work-group of a reduction at its end), so that timing the phases
+// adds no packet to the stream.
+enum PhaseStamp {
+  STAMP_SOLVE = 0,       // solve enqueued: the local kernels follow
+  STAMP_IFACE = 1,       // first interface kernel starts
+  STAMP_IFACE_END = 2,   // interface residual reduced (after any refinement)
+  STAMP_FLUX = 3,        // stitch starts
+  STAMP_FLUX_END = 4,    // flux statistics reduced
+  STAMP_N = 5
+};
+__device__ inline void stamp_now(unsigned long long* s) { *s = __builtin_amdgcn_s_memrealtime(); }
 
 // Frontal-matrix node of the nested-dissection elimination of the
 // interface system.  Front F is n x (n+1), row-major, last column = rhs;
@@ -107,13 +122,15 @@ bool local_fp32_supported(int M, int D, int nP);
 long long local_scratch_doubles(const Geo& g);
 
 // ---- launchers (interface.hip) ----
+// stamp: if not NULL, the launch's start is written there
 hipError_t launch_front_small(const NodeDesc* nodes, int count, int max_n, double* tree,
-                              const int2* maps, int* status, hipStream_t st);
+                              const int2* maps, int* status, unsigned long long* stamp,
+                              hipStream_t st);
 // one panel of the blocked fronts of a level; the first (k0 = 0) also
 // assembles the fronts from their children
 hipError_t launch_front_update(const NodeDesc* nodes, const PanelItem* items, int count, int k0,
                                double* tree, const int2* maps, double* inv, int* status,
-                               hipStream_t st);
+                               unsigned long long* stamp, hipStream_t st);
 // back substitution of one tree level; rtree = NULL takes the right-hand
 // side from the fronts' last column, else from the fronts' rhs vectors
 hipError_t launch_front_back(const NodeDesc* nodes, int count, int max_n, const double* tree,
@@ -126,9 +143,11 @@ hipError_t launch_front_rhs(const NodeDesc* nodes, int count, int max_n, const d
                             double* rtree, hipStream_t st);
 // r = b - A x of the assembled interface system (double-double), written to
 // r if not NULL; partials: 2 doubles per work-group (RESID_WG of them),
-// reduced into out2[0] = max|r|, out2[1] = max|b|
+// reduced into out2[0] = max|r|, out2[1] = max|b|; the reduction's end is
+// written to stamp
 hipError_t launch_iface_residual(const Geo& g, const double* blocks, const double* x, double* r,
-                                 double* partials, double* out2, hipStream_t st);
+                                 double* partials, double* out2, unsigned long long* stamp,
+                                 hipStream_t st);
 // x += dx over n values
 hipError_t launch_add(double* x, const double* dx, int n, hipStream_t st);
 constexpr int RESID_WG = 128;

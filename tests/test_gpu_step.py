@@ -46,6 +46,12 @@ def test_step_equals_separate_calls(workload, kw, step):
         sa["interface_ir_steps"], sb["interface_ir_steps"], sb["interface_residual"]))
     assert sa["interface_ir_steps"] == sb["interface_ir_steps"]
     assert sa["interface_residual"] == sb["interface_residual"]
+    # phase times from the kernels' clock stamps: positive and plausible
+    for st in (sa, sb):
+        say("  phases ms: local %.3f interface %.3f flux %.3f" % (
+            st["ms_local"], st["ms_interface"], st["ms_flux"]))
+        for k in ("ms_local", "ms_interface", "ms_flux"):
+            assert 0.0 < st[k] < 1e3
     if workload == "channel256_q5":
         assert sb["interface_ir_steps"] > 0
     # and against the oracle, as the separate calls are
