@@ -114,6 +114,12 @@ def test_one_subdomain_is_fine_on_gpu():
     f = solve_fine(prob)
     assert rel(g["p"], f["p"]) < 1e-12
     assert rel(np.r_[g["ux"], g["uy"]], np.r_[f["ux"], f["uy"]]) < 1e-11
+    # no interface system: the local phase is timed by events, the interface
+    # phase is empty, the flux phase by the kernels' clock stamps
+    st = g["stats"]
+    assert st["n_dof"] == 0
+    assert 0.0 < st["ms_local"] < 1e3 and st["ms_interface"] == 0.0
+    assert 0.0 < st["ms_flux"] < 1e3
 
 
 def test_gauss1024_full_size_step():
