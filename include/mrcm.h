@@ -54,11 +54,15 @@ enum {
 
 enum { MRCM_BC_NEUMANN = 0, MRCM_BC_DIRICHLET = 1 };
 
-/* Interface spaces (section 3.1).  LINEAR: the two nodal linear functions
- * for pressure and for flux (2 + 2 dofs per interface).  EDGE_SOLUTION: two
- * non-polynomial functions per space built at setup from a 1-D two-point
- * problem along each interface on the absolute permeability (reduces to
- * LINEAR for uniform K).  FULL: every fine-edge indicator (m + m dofs). */
+/* Interface spaces: piecewise-constant functions on the fine faces of each
+ * interface (section 3).  LINEAR: the two nodal linear functions for
+ * pressure and for flux (2 + 2 dofs per interface; the polynomial space of
+ * section 3.1 with no channel).  EDGE_SOLUTION: two non-polynomial functions
+ * per space built at setup from a 1-D two-point problem along each interface
+ * on the absolute permeability (reduces to LINEAR for uniform K); the paper
+ * does not define this space (its own physics-based spaces are those of
+ * eqs. (new_basis1)-(new_basis6)), so it is a reading of "spaces built from
+ * local edge solutions".  FULL: every fine-edge indicator (m + m dofs). */
 enum { MRCM_SPACE_LINEAR = 0, MRCM_SPACE_EDGE_SOLUTION = 1, MRCM_SPACE_FULL = 2 };
 
 /* Precision of the local (subdomain) factorisations.  The interface system
@@ -104,7 +108,8 @@ typedef struct {
   double interface_residual; /* max |b - A x| / max |b| of the interface solve */
   double ms_surrogate;   /* SURROGATE: network inference + residual gate */
   int32_t interface_ir_steps; /* refinement steps of the interface solve (taken while
-                                 max |b - A x| > 1e-14 max |b|, at most 3) */
+                                 max |b - A x| > tol max |b|, at most max_steps: see
+                                 mrcm_set_interface_refinement) */
 } mrcm_stats;
 
 /* Set up a solver for one grid, permeability field and decomposition
@@ -153,8 +158,34 @@ int mrcm_update_mobility(mrcm_ctx* ctx, const double* values, int32_t values_are
 
 /* Solve the MRCM system for the current mobility (eqs. (mrc1), (mrc2)):
  * local Robin problems and basis functions for all subdomains, then the
- * FP64 interface system.  Asynchronous except for a final status read. */
+ * FP64 interface system.  Asynchronous except for a final status read.
+ * Errors: MRCM_E_INVAL (a mobility not finite and positive), MRCM_E_NOT_SPD
+ * (a zero, negative or non-finite pivot), MRCM_E_NO_CONV (the interface
+ * residual is still above its tolerance after the allowed refinement steps:
+ * the elimination does not pivot, so a nearly singular pivot shows here);
+ * after any error the context has no solution (mrcm_fine_flux returns
+ * MRCM_E_STATE) until a solve succeeds. */
 int mrcm_solve(mrcm_ctx* ctx);
+
+/* Stopping rule of the FP32 + FP64 refinement of the local solves
+ * (MRCM_PREC_FP32_IR; spec precision extension, local problems of
+ * eq. (mrc1)): refinement stops once the largest correction of a subdomain is
+ * at most tol of its largest solution value, or after max_steps steps; a
+ * subdomain that ends above tol (or met a bad FP32 pivot) is re-solved by the
+ * FP64 path and counted in mrcm_stats.fallbacks.  Defaults: 8 steps, 1e-9.
+ * max_steps = 0 sends every subdomain to the FP64 re-solve.  Takes effect at
+ * the next solve.  Errors: MRCM_E_INVAL unless 0 <= max_steps <= 64 and
+ * 0 < tol < 1; MRCM_E_STATE for another precision. */
+int mrcm_set_refinement(mrcm_ctx* ctx, int32_t max_steps, double tol);
+
+/* Stopping rule of the iterative refinement of the FP64 interface solve
+ * (eq. (mrc2)): after the direct solve, refinement steps are taken while
+ * max |b - A x| > tol max |b|, at most max_steps; if the residual is still
+ * above tol after them the solve fails with MRCM_E_NO_CONV.  Defaults: 3
+ * steps; tol 1e-14 (FP64 and SURROGATE), 1e-12 (FP32_IR).  Takes effect at
+ * the next solve.  Errors: MRCM_E_INVAL unless 0 <= max_steps <= 16 and
+ * 0 < tol < 1. */
+int mrcm_set_interface_refinement(mrcm_ctx* ctx, int32_t max_steps, double tol);
 
 /* Reconstruct fine-scale output from the last solve:
  *  p  : nx*ny composed multiscale cell pressure (basis functions combined
@@ -171,7 +202,11 @@ int mrcm_solve(mrcm_ctx* ctx);
  *  max_cell_imbalance : if not NULL receives max over cells of
  *              |net outflow - q|V|| / max |face flux|.
  * Synchronous: outputs are valid on return.  MRCM_E_STATE before the first
- * successful solve. */
+ * successful solve.  The stitch of a subdomain with no Dirichlet face is a
+ * Neumann problem whose data sum to zero up to the rounding of the composed
+ * solution; that defect is removed evenly from its cells (a uniform source
+ * correction at rounding level), so it appears in max_cell_imbalance
+ * divided by the subdomain's cell count. */
 int mrcm_fine_flux(mrcm_ctx* ctx, double* p, double* ux, double* uy, int32_t on_device,
                    double* max_cell_imbalance);
 

@@ -53,6 +53,20 @@ def fractional_flow(s, mu_w, mu_o):
     return lw / (lw + lo)
 
 
+def cell_injection(prob, hx, hy):
+    """Volume injected per unit time into every cell: q |V| (eq. (Darcy),
+    div u = q; q > 0 is a source such as an injection well)."""
+    if prob.source is None:
+        return np.zeros(prob.nx * prob.ny)
+    return prob.source * hx * hy
+
+
+def neumann_outflow(u_b, flen):
+    """Flux leaving the domain through a Neumann face: the prescribed outward
+    normal velocity u_b times the face length (u . n = u_b, section 2)."""
+    return u_b * flen
+
+
 def harmonic(a, b):
     """Two conductances in series: 1 / (1/a + 1/b)."""
     return 1.0 / (1.0 / a + 1.0 / b)
@@ -152,7 +166,14 @@ def full_space(m):
 
 
 def edge_solution_space(k_lo, k_hi):
-    """Non-polynomial two-function spaces from a 1-D edge problem (§3.1).
+    """Non-polynomial two-function spaces from a 1-D edge problem.
+
+    The paper does not define these spaces: section 3.1 defines the
+    physics-based spaces of eqs. (new_basis1)-(new_basis6), built from the
+    channel structure of the edge.  What follows is the reading taken for a
+    space of "two pressure and two flux functions built from local edge
+    solutions"; its only pins are the reductions below and the exact
+    solution of the edge problem.
 
     t_j is the harmonic mean of the permeabilities across fine face j.
     psi solves the 1-D two-point problem along the edge with conductances

@@ -14,7 +14,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .discretization import DIRICHLET, E, N, S, W, harmonic
+from .discretization import DIRICHLET, E, N, S, W, cell_injection, harmonic, neumann_outflow
 
 
 def _half_trans(kappa, flen, dist):
@@ -37,9 +37,7 @@ def solve_fine(prob, lam=None):
     n = nx * ny
     idx = np.arange(n).reshape(ny, nx)
     rows, cols, vals = [], [], []
-    rhs = np.zeros(n)
-    if prob.source is not None:
-        rhs += prob.source * hx * hy
+    rhs = cell_injection(prob, hx, hy).astype(np.float64, copy=True)
 
     def couple(a, b, T):
         rows.extend([a, b, a, b])
@@ -67,7 +65,7 @@ def solve_fine(prob, lam=None):
             vals.append(t)
             np.add.at(rhs, cells, t * v)
         else:
-            np.add.at(rhs, cells, -v * flen)
+            np.add.at(rhs, cells, -neumann_outflow(v, flen))
     A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(n, n))
     pure_neumann = not prob.has_dirichlet()
@@ -88,16 +86,16 @@ def solve_fine(prob, lam=None):
     for side in (W, E, S, N):
         v = prob.bc_array(side)
         if side == W:
-            out = tx[:, 0] * (P[:, 0] - v) if prob.bc_kind[W] == DIRICHLET else v * hy
+            out = tx[:, 0] * (P[:, 0] - v) if prob.bc_kind[W] == DIRICHLET else neumann_outflow(v, hy)
             Fx[:, 0] = -out
         elif side == E:
-            out = tx[:, -1] * (P[:, -1] - v) if prob.bc_kind[E] == DIRICHLET else v * hy
+            out = tx[:, -1] * (P[:, -1] - v) if prob.bc_kind[E] == DIRICHLET else neumann_outflow(v, hy)
             Fx[:, -1] = out
         elif side == S:
-            out = ty[0, :] * (P[0, :] - v) if prob.bc_kind[S] == DIRICHLET else v * hx
+            out = ty[0, :] * (P[0, :] - v) if prob.bc_kind[S] == DIRICHLET else neumann_outflow(v, hx)
             Fy[0, :] = -out
         else:
-            out = ty[-1, :] * (P[-1, :] - v) if prob.bc_kind[N] == DIRICHLET else v * hx
+            out = ty[-1, :] * (P[-1, :] - v) if prob.bc_kind[N] == DIRICHLET else neumann_outflow(v, hx)
             Fy[-1, :] = out
     return dict(p=p, Fx=Fx.reshape(-1), Fy=Fy.reshape(-1),
                 ux=(Fx / hy).reshape(-1), uy=(Fy / hx).reshape(-1))

@@ -45,8 +45,8 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .discretization import (DIRICHLET, E, N, S, W, Geometry, harmonic,
-                             interface_alpha, interface_spaces)
+from .discretization import (DIRICHLET, E, N, S, W, Geometry, cell_injection, harmonic,
+                             interface_alpha, interface_spaces, neumann_outflow)
 
 
 @dataclasses.dataclass
@@ -66,6 +66,9 @@ class MRCMResult:
     p_stitch: np.ndarray       # pressure of the stitch re-solve
     imbalance_raw: float       # max cell imbalance / max |F| of the raw MRCM flux
     imbalance: float           # same for the stitched flux
+    stitch_defect: float       # largest compatibility defect of a floating
+                               # subdomain's Neumann data / max |F| (removed
+                               # evenly from its cells; rounding level)
     interface_matrix: sp.csr_matrix
     interface_rhs: np.ndarray
     dof_offset: np.ndarray
@@ -116,9 +119,7 @@ def local_operator(geom, prob, kappa, robin_T=None):
     same_y = (np.arange(1, ny) % my) != 0
     couple(idx[:-1, :][same_y, :].ravel(), idx[1:, :][same_y, :].ravel(), Ty[same_y, :].ravel())
 
-    rhs = np.zeros(n)
-    if prob.source is not None:
-        rhs += prob.source * hx * hy
+    rhs = cell_injection(prob, hx, hy).astype(np.float64, copy=True)
     for side, cells, t, flen, v in _bc_faces(geom, prob, kappa):
         if prob.bc_kind[side] == DIRICHLET:
             rows.append(cells)
@@ -126,7 +127,7 @@ def local_operator(geom, prob, kappa, robin_T=None):
             vals.append(t)
             np.add.at(rhs, cells, t * v)
         else:
-            np.add.at(rhs, cells, -v * flen)
+            np.add.at(rhs, cells, -neumann_outflow(v, flen))
     if robin_T is not None:
         for cells, T in robin_T:
             rows.append(cells)
@@ -205,6 +206,16 @@ def _refined(A, solve, b, steps=3):
     return x
 
 
+def _refined_extended(solve, b, residual, steps=3):
+    """x = A^-1 b carried in the x87 extended format: a direct solve, then
+    refinement steps x += A^-1 r with r = residual(x) formed in extended
+    precision and the accumulated solution kept extended."""
+    x = solve(b).astype(np.longdouble)
+    for _ in range(steps):
+        x = x + solve(residual(x).astype(np.float64))
+    return x
+
+
 def _local_solve(A, B, geom, method):
     if method == "superlu":
         lu = spla.splu(A.tocsc())
@@ -258,7 +269,7 @@ def flux_imbalance(geom, prob, Fx, Fy):
     FX = Fx.reshape(ny, nx + 1)
     FY = Fy.reshape(ny + 1, nx)
     net = FX[:, 1:] - FX[:, :-1] + FY[1:, :] - FY[:-1, :]
-    q = np.zeros((ny, nx)) if prob.source is None else (prob.source * geom.hx * geom.hy).reshape(ny, nx)
+    q = cell_injection(prob, geom.hx, geom.hy).reshape(ny, nx)
     scale = max(np.abs(FX).max(), np.abs(FY).max(), 1e-300)
     return float(np.abs(net - q).max() / scale)
 
@@ -270,7 +281,7 @@ def _boundary_fluxes(geom, prob, kappa, p, FX, FY):
         if prob.bc_kind[side] == DIRICHLET:
             out = t * (p[cells] - v)
         else:
-            out = v * flen
+            out = neumann_outflow(v, flen)
         if side == W:
             FX[:, 0] = -out
         elif side == E:
@@ -405,6 +416,9 @@ def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu
             np.add.at(rhsN, per[1]["cells"], avg)    # outflow of hi is -avg
         AN = AN.tolil()
         diag = AN.diagonal()
+        pins = []
+        shift = np.zeros(geom.n_cells, dtype=np.longdouble)
+        defect_max = 0.0
         for sd in range(geom.n_sub):
             I, J = sd % geom.SX, sd // geom.SX
             touches_dirichlet = ((I == 0 and prob.bc_kind[W] == DIRICHLET)
@@ -412,24 +426,67 @@ def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu
                                  or (J == 0 and prob.bc_kind[S] == DIRICHLET)
                                  or (J == geom.SY - 1 and prob.bc_kind[N] == DIRICHLET))
             if not touches_dirichlet:
+                # A Neumann problem has a solution only if its data sum to
+                # zero.  The averaged skeleton fluxes meet this to the
+                # rounding of the composed solution and of the interface
+                # solve; the defect is removed evenly from the subdomain's
+                # cells (a uniform source correction at rounding level)
+                # instead of being left to the pinned cell.
+                li, lj = np.meshgrid(np.arange(mx), np.arange(my))
+                cells = ((J * my + lj) * nx + I * mx + li).reshape(-1)
+                defect = np.sum(rhsN[cells].astype(np.longdouble)) / cells.size
+                rhsN[cells] = (rhsN[cells] - defect).astype(np.float64)
+                shift[cells] = defect
+                defect_max = max(defect_max, float(abs(defect)) * cells.size)
                 c0 = (J * my) * nx + I * mx
                 Tpin = diag[c0]
                 AN[c0, c0] = diag[c0] + Tpin
                 rhsN[c0] += Tpin * p[c0]
+                pins.append((c0, Tpin, p[c0]))
         AN = AN.tocsc()
-        p_st = _refined(AN, spla.splu(AN).solve, rhsN)
-        PS = p_st.reshape(ny, nx)
-        FX = Fx.reshape(ny, nx + 1)
-        FY = Fy.reshape(ny + 1, nx)
-        FX[:, 1:-1] = np.where(same_x[None, :], Tx * (PS[:, :-1] - PS[:, 1:]), FX[:, 1:-1])
-        FY[1:-1, :] = np.where(same_y[:, None], Ty * (PS[:-1, :] - PS[1:, :]), FY[1:-1, :])
-        _boundary_fluxes(geom, prob, kappa, p_st, FX, FY)
-        Fx, Fy = FX.reshape(-1), FY.reshape(-1)
+        ld = np.longdouble
+        inj = (cell_injection(prob, geom.hx, geom.hy).astype(ld) - shift).reshape(ny, nx)
+
+        def stitched_fluxes(x):
+            """Face fluxes of the re-solve from pressure x (extended): the
+            face laws inside subdomains and on the physical boundary, the
+            averaged flux on skeleton faces."""
+            PS = x.reshape(ny, nx)
+            FXl = Fx_raw.reshape(ny, nx + 1).astype(ld)
+            FYl = Fy_raw.reshape(ny + 1, nx).astype(ld)
+            FXl[:, 1:-1] = np.where(same_x[None, :], Tx * (PS[:, :-1] - PS[:, 1:]), FXl[:, 1:-1])
+            FYl[1:-1, :] = np.where(same_y[:, None], Ty * (PS[:-1, :] - PS[1:, :]), FYl[1:-1, :])
+            _boundary_fluxes(geom, prob, kappa, x, FXl, FYl)
+            return FXl, FYl
+
+        def balance_residual(x):
+            """q |V| minus the net outflow of every cell (and the pin), in
+            extended precision: the residual of the re-solve written as the
+            cell balances themselves, so that its solution balances the
+            fluxes formed from it (a residual of the assembled matrix would
+            carry the FP64 rounding of its diagonal sums, eps T |p| per
+            cell)."""
+            FXl, FYl = stitched_fluxes(x)
+            net = FXl[:, 1:] - FXl[:, :-1] + FYl[1:, :] - FYl[:-1, :]
+            r = (inj - net).reshape(-1)
+            for c0, Tpin, pref in pins:
+                r[c0] -= Tpin * (x[c0] - pref)
+            return r
+
+        # the stitched pressure in extended precision; the fluxes are formed
+        # from it and rounded once (section 2: every cell balances)
+        p_ext = _refined_extended(spla.splu(AN).solve, rhsN, balance_residual)
+        p_st = p_ext.astype(np.float64)
+        FXl, FYl = stitched_fluxes(p_ext)
+        Fx, Fy = FXl.astype(np.float64).reshape(-1), FYl.astype(np.float64).reshape(-1)
     imb = flux_imbalance(geom, prob, Fx, Fy)
+    fscale = max(np.abs(Fx).max(), np.abs(Fy).max(), 1e-300)
+    defect = defect_max / fscale if stitch and geom.n_iface else 0.0
     return MRCMResult(p=p, ux=Fx / geom.hy, uy=Fy / geom.hx, Fx=Fx, Fy=Fy,
                       Fx_raw=Fx_raw, Fy_raw=Fy_raw, side_flux=side_flux, coeffs=c,
                       blocks=blocks, sub_dofs=sub_dofs, X=X, p_stitch=p_st,
-                      imbalance_raw=imb_raw, imbalance=imb, interface_matrix=M,
+                      imbalance_raw=imb_raw, imbalance=imb, stitch_defect=defect,
+                      interface_matrix=M,
                       interface_rhs=b, dof_offset=off, n_p=n_p, n_u=n_u)
 
 

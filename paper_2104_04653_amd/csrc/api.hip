@@ -82,6 +82,12 @@ struct mrcm_ctx {
   float* s_pred = nullptr;
   bool s_ready = false;
   double gate_tol = 1e-6;
+  // stopping rules of the iterative refinements (mrcm_set_refinement,
+  // mrcm_set_interface_refinement); defaults set by mrcm_setup
+  int ir_max = 0;
+  double ir_tol = 0.0;
+  int iface_ir_max = 0;
+  double iface_ir_tol = 0.0;
   std::vector<void*> allocs;
 
   // interface plan
@@ -134,16 +140,21 @@ constexpr int STAMP_OFF = 4;
 constexpr int RESULT_N = STAMP_OFF + STAMP_N + 1;
 constexpr size_t REPORT_HEAD = RESULT_N * sizeof(double) + 3 * sizeof(int);
 
-constexpr int IFACE_IR_MAX = 3;         // refinement steps of the interface solve
-// max|r| / max|b| of the interface system that needs no refinement: near the
-// FP64 floor for FP64 local solves; for FP32 + refinement, whose local
-// solutions are converged to about 1e-10 relative, a residual 1e-12 of the
-// right-hand side is already below what its inputs resolve
+constexpr int IFACE_IR_MAX = 3;         // default refinement steps of the interface solve
+// default max|r| / max|b| of the interface system that needs no refinement:
+// near the FP64 floor for FP64 local solves; for FP32 + refinement, whose
+// local solutions are converged to about 1e-10 relative, a residual 1e-12 of
+// the right-hand side is already below what its inputs resolve
 constexpr double IFACE_IR_TOL_FP64 = 1e-14;
 constexpr double IFACE_IR_TOL_FP32 = 1e-12;
+// default stopping rule of the FP32 local refinement: the last correction
+// below 1e-9 of the solution leaves local errors near 1e-11 (the form's
+// target is 1e-8 against FP64), at most 8 steps
+constexpr int LOCAL_IR_MAX = 8;
+constexpr double LOCAL_IR_TOL = 1e-9;
 
 // ---------------------------------------------------------------------------
-// interface spaces (section 3.1), tabulated per interface on its fine faces
+// interface spaces, tabulated per interface on its fine faces
 // ---------------------------------------------------------------------------
 
 double hmean(double a, double b) { return 2.0 * a * b / (a + b); }
@@ -475,6 +486,8 @@ SubArgs sub_args(const mrcm_ctx* c) {
   a.fallback = c->fallback;
   a.ir_iters = c->ir_iters;
   a.gate_tol = c->gate_tol;
+  a.ir_max = c->ir_max;
+  a.ir_tol = c->ir_tol;
   a.scratch = c->scratch;
   a.scratch_stride = c->scratch_stride;
   a.stamps = c->stamps;
@@ -620,6 +633,10 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
     G.generic = (gen && gen[0] == '1') ? 1 : 0;
   }
   c->precision = precision;
+  c->ir_max = LOCAL_IR_MAX;
+  c->ir_tol = LOCAL_IR_TOL;
+  c->iface_ir_max = IFACE_IR_MAX;
+  c->iface_ir_tol = precision == MRCM_PREC_FP32_IR ? IFACE_IR_TOL_FP32 : IFACE_IR_TOL_FP64;
   c->space = space;
   c->mu_w = fluid->mu_w;
   c->mu_o = fluid->mu_o;
@@ -804,9 +821,12 @@ int solve_enqueue(mrcm_ctx* c, const float* pred) {
 // the right-hand side (high contrast with non-polynomial spaces makes the
 // system ill-conditioned) the solve is refined, each step checked at a
 // synchronisation of its own; well-conditioned solves pay nothing.
+bool iface_above_tol(const mrcm_ctx* c) {
+  return c->n_dof > 0 && !(c->h_report[2] <= c->iface_ir_tol * c->h_report[3]);
+}
+
 bool needs_refinement(const mrcm_ctx* c) {
-  const double ir_tol = c->g.prec == 1 ? IFACE_IR_TOL_FP32 : IFACE_IR_TOL_FP64;
-  return c->n_dof > 0 && c->iface_ir < IFACE_IR_MAX && c->h_report[2] > ir_tol * c->h_report[3];
+  return c->iface_ir < c->iface_ir_max && iface_above_tol(c);
 }
 
 // Statistics and status of a solve whose report has been read (and
@@ -843,6 +863,15 @@ int solve_finish(mrcm_ctx* c) {
   if (status & ST_BAD_LAMBDA) return fail(c, MRCM_E_INVAL, "mobility not finite and positive");
   if (status & (ST_LOCAL_PIVOT | ST_IFACE_PIVOT))
     return fail(c, MRCM_E_NOT_SPD, "non-positive or zero pivot in the elimination");
+  if (iface_above_tol(c)) {
+    // the interface elimination does not pivot: a nearly singular pivot
+    // shows as a residual that refinement does not bring down
+    char msg[160];
+    snprintf(msg, sizeof msg, "interface solve: residual %.3e of the right-hand side after %d "
+             "refinement steps (tolerance %.3e)", c->stats.interface_residual, c->iface_ir,
+             c->iface_ir_tol);
+    return fail(c, MRCM_E_NO_CONV, msg);
+  }
   c->solved = true;
   return MRCM_OK;
 }
@@ -1031,6 +1060,26 @@ int mrcm_set_gate_tolerance(mrcm_ctx* c, double tol) {
   if (c->precision != MRCM_PREC_SURROGATE)
     return fail(c, MRCM_E_STATE, "context was not set up with MRCM_PREC_SURROGATE");
   c->gate_tol = tol;
+  return MRCM_OK;
+}
+
+int mrcm_set_refinement(mrcm_ctx* c, int32_t max_steps, double tol) {
+  if (!c) return MRCM_E_INVAL;
+  if (max_steps < 0 || max_steps > 64 || !(tol > 0.0) || !(tol < 1.0))
+    return fail(c, MRCM_E_INVAL, "refinement: 0 <= max_steps <= 64 and 0 < tol < 1 required");
+  if (c->precision != MRCM_PREC_FP32_IR)
+    return fail(c, MRCM_E_STATE, "context was not set up with MRCM_PREC_FP32_IR");
+  c->ir_max = max_steps;
+  c->ir_tol = tol;
+  return MRCM_OK;
+}
+
+int mrcm_set_interface_refinement(mrcm_ctx* c, int32_t max_steps, double tol) {
+  if (!c) return MRCM_E_INVAL;
+  if (max_steps < 0 || max_steps > 16 || !(tol > 0.0) || !(tol < 1.0))
+    return fail(c, MRCM_E_INVAL, "interface refinement: 0 <= max_steps <= 16 and 0 < tol < 1 required");
+  c->iface_ir_max = max_steps;
+  c->iface_ir_tol = tol;
   return MRCM_OK;
 }
 

@@ -346,10 +346,9 @@ __global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
 // symmetrically (Ds A Ds, Ds = diag(A)^-1/2, unit diagonal); the inverse
 // Schur blocks and the solves of the scaled system are FP32, the solution
 // and the residuals FP64.  Refinement stops when the largest correction is
-// below IR_DONE32 of the largest solution value; a subdomain that ends above
+// below a.ir_tol of the largest solution value (at most a.ir_max steps); a
+// subdomain that ends above
 // it, or met a bad FP32 pivot, is listed for the FP64 re-solve.
-constexpr int IR_MAX32 = 8;
-constexpr double IR_DONE32 = 1e-9;
 
 template <int M, int D>
 __global__ void __launch_bounds__(NT) local_basis32_kernel(SubArgs a) {
@@ -394,7 +393,7 @@ __global__ void __launch_bounds__(NT) local_basis32_kernel(SubArgs a) {
 
   int used = 0;
   double rel = 1.0;
-  for (int it = 0; it < IR_MAX32; ++it) {
+  for (int it = 0; it < a.ir_max; ++it) {
     __syncthreads();
     local_residual<M, R>(Bs, Xs, Rg, dg, ex, cy);
     __syncthreads();
@@ -425,11 +424,11 @@ __global__ void __launch_bounds__(NT) local_basis32_kernel(SubArgs a) {
     }
     used = it + 1;
     rel = cmax / fmax(xmax, 1e-300);
-    if (rel <= IR_DONE32) break;
+    if (rel <= a.ir_tol) break;
   }
   if (tid == 0) {
     atomicMax(a.ir_iters, used);
-    if (bad || !(rel <= IR_DONE32)) {
+    if (bad || !(rel <= a.ir_tol)) {
       const int q = atomicAdd(a.fallback, 1);
       a.fallback[1 + q] = sd;
     }
@@ -468,7 +467,6 @@ __global__ void __launch_bounds__(NT) stitch_kernel(SubArgs a) {
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
   __shared__ double pm[MM];          // composed multiscale pressure
   __shared__ double Xs[MM];          // stitch right-hand side / pressure
-  __shared__ double Bs[MM];          // saved right-hand side
   __shared__ double Rs[MM];          // residual / correction
   __shared__ double Sinv_l[LocalStore<M>::big ? 1 : M * MM];
   __shared__ double pivbuf[4 * M];
@@ -522,26 +520,55 @@ __global__ void __launch_bounds__(NT) stitch_kernel(SubArgs a) {
   for (int l = tid; l < MM; l += NT)
     assemble_cell<M, 1>(a, I, J, l, kap, dg, ex, cy, Xs + l, 0, Fout);
   __syncthreads();
-  // a subdomain with no Dirichlet face has a Neumann problem defined up to a
-  // constant: fix it at cell 0 to the composed multiscale pressure
+  // A subdomain with no Dirichlet face has a Neumann problem, solvable only
+  // if its data sum to zero.  The averaged skeleton fluxes meet this to the
+  // rounding of the composed solution; that defect (summed in double-double)
+  // is removed evenly from the cells' data instead of being left to the
+  // pinned cell, and the constant is fixed at cell 0 to the composed
+  // multiscale pressure (its pin then carries no flux).
   const bool dir = (I == 0 && g.kind[0] == 1) || (I == g.SX - 1 && g.kind[1] == 1) ||
                    (J == 0 && g.kind[2] == 1) || (J == g.SY - 1 && g.kind[3] == 1);
-  if (!dir && tid == 0) {
-    const double tp = dg[0];
-    dg[0] += tp;
-    Xs[0] += tp * pm[0];
+  double dfc = 0.0, tp = 0.0;
+  if (!dir) {   // uniform over the work-group
+    double sh = 0.0, sl = 0.0;
+    for (int l = tid; l < MM; l += NT) dd_add(sh, sl, Xs[l]);
+    red[0][tid] = sh;
+    red[1][tid] = sl;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        double h = red[0][tid], lo = red[1][tid];
+        dd_add(h, lo, red[0][tid + w]);
+        red[0][tid] = h;
+        red[1][tid] = lo + red[1][tid + w];
+      }
+      __syncthreads();
+    }
+    dfc = (red[0][0] + red[1][0]) / MM;
+    tp = dg[0];
+    __syncthreads();   // every thread has read the sums and dg[0]
+    for (int l = tid; l < MM; l += NT) Xs[l] -= dfc;
+    __syncthreads();
+    if (tid == 0) {
+      dg[0] += tp;
+      Xs[0] += tp * pm[0];
+    }
   }
   __syncthreads();
-  for (int l = tid; l < MM; l += NT) Bs[l] = Xs[l];
   if (thomas_solve<M, 1, double>(Xs, Sinv, dg, ex, cy, pivbuf) && threadIdx.x == 0)
     atomicOr(a.status, ST_STITCH_PIVOT);
-  // two steps of FP64 iterative refinement with the stored inverse blocks
-  for (int it = 0; it < 2; ++it) {
-    local_residual<M, 1>(Bs, Xs, Rs, dg, ex, cy);
-    thomas_resolve<M, 1, double>(Rs, Sinv, cy);
-    for (int l = tid; l < MM; l += NT) Xs[l] += Rs[l];
-    __syncthreads();
-  }
+  // one step of iterative refinement with the stored inverse blocks; the
+  // residual is the cells' mass balance in double-double (the FP64 diagonal
+  // sums of the assembled matrix would leave eps * T |p| per cell), and the
+  // pressure is kept as the unevaluated sum Xs + Rs (solution + correction)
+  // from which the fluxes are formed: the cell balances then hold to the
+  // rounding of the fluxes themselves
+  __syncthreads();
+  for (int l = tid; l < MM; l += NT)
+    Rs[l] = stitch_balance_residual<M>(a, I, J, l, kap, Xs, Fout, dfc, tp, pm[0]);
+  __syncthreads();
+  thomas_resolve<M, 1, double>(Rs, Sinv, cy);
+  __syncthreads();
 
   // fine fluxes (+x / +y) from the stitched pressure; skeleton faces carry
   // the averaged flux.  Each subdomain writes the W and S faces of its cells
@@ -550,34 +577,10 @@ __global__ void __launch_bounds__(NT) stitch_kernel(SubArgs a) {
   for (int l = tid; l < MM; l += NT) {
     const int li = l % M, lj = l / M;
     const int i = I * M + li, j = J * M + lj;
-    const double kc = kap[l];
-    const double txc = kc * g.hy / (0.5 * g.hx), tyc = kc * g.hx / (0.5 * g.hy);
-    const double ps = Xs[l];
+    double out[4];
+    stitch_out_fluxes<M>(a, I, J, l, kap, Xs, Rs, Fout, out);
     double F[4];  // W, E, S, N in +x / +y direction
-    for (int side = 0; side < 4; ++side) {
-      const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
-      double f;
-      if (inner) {
-        const int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
-        const double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
-        const double T = series2(side < 2 ? txc : tyc, tn);
-        const double out = T * (ps - Xs[nb]);
-        f = (side == 0 || side == 2) ? -out : out;
-      } else {
-        const int e = side_iface(g, I, J, side);
-        const int t = (side < 2) ? lj : li;
-        double out;
-        if (e >= 0) {
-          out = Fout[side][t];
-        } else {
-          const double flen = (side < 2) ? g.hy : g.hx;
-          const double v = a.bcv[side][(side < 2) ? j : i];
-          out = (g.kind[side] == 1) ? ((side < 2) ? txc : tyc) * (ps - v) : v * flen;
-        }
-        f = (side == 0 || side == 2) ? -out : out;
-      }
-      F[side] = f;
-    }
+    for (int side = 0; side < 4; ++side) F[side] = (side == 0 || side == 2) ? -out[side] : out[side];
     a.ux[(size_t)j * (g.nx + 1) + i] = F[0] / g.hy;
     if (li == M - 1 && I == g.SX - 1) a.ux[(size_t)j * (g.nx + 1) + i + 1] = F[1] / g.hy;
     a.uy[(size_t)j * g.nx + i] = F[2] / g.hx;

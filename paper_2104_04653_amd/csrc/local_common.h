@@ -177,6 +177,109 @@ __device__ inline void dd_fma(double& hi, double& lo, double a, double b) {
   lo += pe + se;
 }
 
+// (ah + al) - (bh + bl) rounded once to FP64: the difference of the leading
+// parts is taken with an error-free two-difference, so a face flux
+// T ((p_c - p_d)) formed from pressures carried as unevaluated sums keeps
+// its relative accuracy when the two pressures nearly cancel (the stitched
+// cell balances then hold to rounding of the fluxes themselves, not of the
+// pressures).
+__device__ inline double dd_diff(double ah, double al, double bh, double bl) {
+#pragma clang fp contract(off)
+  const double s = ah - bh;
+  const double v = s - ah;
+  const double e = (ah - (s - v)) + (-bh - v);
+  return s + (e + (al - bl));
+}
+
+// (hi, lo) += b with an error-free two-sum
+__device__ inline void dd_add(double& hi, double& lo, double b) {
+#pragma clang fp contract(off)
+  const double s = hi + b;
+  const double bb = s - hi;
+  lo += (hi - (s - bb)) + (b - bb);
+  hi = s;
+}
+
+// Outward fluxes of cell l through its W, E, S, N faces in the stitch
+// re-solve, from the pressure ph + pl (pl may be NULL): the two-point law
+// inside the subdomain, the prescribed averaged flux Fout on skeleton faces,
+// the physical law on the domain boundary (Dirichlet t_c (p - p_b), Neumann
+// u_b |f|).  The same expressions form the residual of the re-solve and its
+// output fluxes, so the refined pressure balances the fluxes it outputs.
+template <int M>
+__device__ inline void stitch_out_fluxes(const SubArgs& a, int I, int J, int l, const double* kap,
+                                         const double* ph, const double* pl,
+                                         const double (*Fout)[M], double out[4]) {
+  const Geo& g = a.g;
+  const int li = l % M, lj = l / M;
+  const int i = I * M + li, j = J * M + lj;
+  const double kc = kap[l];
+  const double txc = kc * g.hy / (0.5 * g.hx), tyc = kc * g.hx / (0.5 * g.hy);
+  const double pv = ph[l], pvl = pl ? pl[l] : 0.0;
+#pragma unroll
+  for (int side = 0; side < 4; ++side) {
+    const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
+    if (inner) {
+      const int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
+      const double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
+      out[side] = series2(side < 2 ? txc : tyc, tn) * dd_diff(pv, pvl, ph[nb], pl ? pl[nb] : 0.0);
+    } else {
+      const int e = side_iface(g, I, J, side);
+      const int t = (side < 2) ? lj : li;
+      if (e >= 0) {
+        out[side] = Fout[side][t];
+      } else {
+        const double flen = (side < 2) ? g.hy : g.hx;
+        const double v = a.bcv[side][(side < 2) ? j : i];
+        out[side] = (g.kind[side] == 1) ? ((side < 2) ? txc : tyc) * dd_diff(pv, pvl, v, 0.0) : v * flen;
+      }
+    }
+  }
+}
+
+// Residual of cell l of the stitch re-solve written as its mass balance,
+// q |V| - dfc - (net outflow) - (pin flux of a floating subdomain's cell 0),
+// in double-double from the pressure ph (FP64); dfc is the per-cell share
+// of the Neumann data's compatibility defect, tp the pin transmissibility
+// and pref the pinned value (tp = 0: no pin).
+template <int M>
+__device__ inline double stitch_balance_residual(const SubArgs& a, int I, int J, int l,
+                                                 const double* kap, const double* ph,
+                                                 const double (*Fout)[M], double dfc, double tp,
+                                                 double pref) {
+  const Geo& g = a.g;
+  const int li = l % M, lj = l / M;
+  const int i = I * M + li, j = J * M + lj;
+  const double kc = kap[l], pv = ph[l];
+  double hi = a.src ? a.src[(size_t)j * g.nx + i] * g.hx * g.hy : 0.0, lo = 0.0;
+  dd_add(hi, lo, -dfc);
+  // the faces one at a time (the caller keeps its inverse blocks in
+  // registers meanwhile); the same face laws as stitch_out_fluxes
+#pragma unroll 1
+  for (int side = 0; side < 4; ++side) {
+    const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
+    const double th = (side < 2) ? kc * g.hy / (0.5 * g.hx) : kc * g.hx / (0.5 * g.hy);
+    double out;
+    if (inner) {
+      const int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
+      const double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
+      out = series2(th, tn) * dd_diff(pv, 0.0, ph[nb], 0.0);
+    } else {
+      const int e = side_iface(g, I, J, side);
+      if (e >= 0) {
+        out = Fout[side][(side < 2) ? lj : li];
+      } else {
+        const double flen = (side < 2) ? g.hy : g.hx;
+        const double v = a.bcv[side][(side < 2) ? j : i];
+        out = (g.kind[side] == 1) ? th * dd_diff(pv, 0.0, v, 0.0) : v * flen;
+      }
+    }
+    dd_add(hi, lo, -out);
+  }
+  if (l == 0 && tp != 0.0) dd_add(hi, lo, -tp * dd_diff(pv, 0.0, pref, 0.0));
+  return hi + lo;
+}
+
 template <int M>
 __device__ void load_kappa(const SubArgs& a, int I, int J, double* kap) {
   const Geo& g = a.g;

@@ -803,15 +803,13 @@ __device__ inline void solve_column_pair(const d4* Sv, int w, const double* rhs,
 // solution is kept in FP64; every refinement step forms R = B - A X in FP64,
 // solves A^ y = Ds R in FP32 and adds Ds y.  A subdomain whose correction does
 // not fall below IR_DONE of its solution within IR_MAX steps, or whose FP32
-// pivots fail, is appended to a.fallback and re-solved in FP64.  The error
+// pivots fail, is appended to a.fallback and re-solved in FP64 (IR_DONE and
+// IR_MAX are a.ir_tol and a.ir_max, by default 1e-9 and 8 steps).  The error
 // left after a step is about the contraction factor times that step's
 // correction, so IR_DONE = 1e-9 leaves local errors near 1e-11 (the target of
 // this path is 1e-8 against FP64).
 
 typedef float f4 __attribute__((ext_vector_type(4)));
-constexpr int IR_MAX = 8;
-constexpr double IR_DONE = 1e-9;      // relative size of the last correction: converged
-constexpr double IR_ACCEPT = 1e-9;    // ... accepted without the FP64 fallback
 
 __device__ inline float readlane_f(float x, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
@@ -1103,8 +1101,8 @@ __device__ inline f4 residual32_row(int t, const d4* Xv, Lds32& sh, int c, int g
 // symmetrically (Ds A Ds, Ds = diag(A)^-1/2, unit diagonal); the inverse
 // Schur blocks and the correction solves are FP32 (MFMA with FP32
 // accumulation), the solution and the residuals FP64.  Refinement stops when
-// the largest correction is below IR_DONE of the largest solution value; a
-// subdomain that ends above IR_ACCEPT, or met a bad pivot, is listed for the
+// the largest correction is below a.ir_tol of the largest solution value; a
+// subdomain that ends above it, or met a bad pivot, is listed for the
 // FP64 re-solve.
 template <int W>
 __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
@@ -1164,7 +1162,7 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
   int used = 0;
   double rel = 1.0;
 #pragma unroll 1
-  for (int it = 0; it < IR_MAX; ++it) {
+  for (int it = 0; it < a.ir_max; ++it) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) sh.xj[W][4 * gq + v][c] = Xv[C::NR - 1][v];
     __syncthreads();
@@ -1211,11 +1209,11 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
     __syncthreads();
     used = it + 1;
     rel = cmax / fmax(xmax, 1e-300);
-    if (rel <= IR_DONE) break;
+    if (rel <= a.ir_tol) break;
   }
   if (W == 0 && tid == 0) {
     atomicMax(a.ir_iters, used);
-    if (bad || !(rel <= IR_ACCEPT)) {
+    if (bad || !(rel <= a.ir_tol)) {
       const int q = atomicAdd(a.fallback, 1);
       a.fallback[1 + q] = sd;
     }
@@ -1355,10 +1353,48 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
   __syncthreads();
   const bool dir = (I == 0 && g.kind[0] == 1) || (I == g.SX - 1 && g.kind[1] == 1) ||
                    (J == 0 && g.kind[2] == 1) || (J == g.SY - 1 && g.kind[3] == 1);
-  if (!dir && tid == 0) {
-    const double tp = dg[0];
-    dg[0] += tp;
-    bs_[0] += tp * pm[0];
+  // A subdomain with no Dirichlet face has a Neumann problem, solvable only
+  // if its data sum to zero.  The averaged skeleton fluxes meet this to the
+  // rounding of the composed solution; that defect (summed in double-double)
+  // is removed evenly from the cells' data instead of being left to the
+  // pinned cell, and the constant is fixed at cell 0 to the composed
+  // pressure (its pin then carries no flux).
+  // per-cell defect share and pin transmissibility, kept in LDS across the
+  // factorisation (in registers they would push its inverse blocks out)
+  __shared__ double pin_sc[2];
+  if (tid == 0) {
+    pin_sc[0] = 0.0;
+    pin_sc[1] = 0.0;
+  }
+  if (!dir) {   // uniform over the work-group
+    double sh = 0.0, sl = 0.0;
+#pragma unroll
+    for (int q = 0; q < MM / PAIR; ++q) dd_add(sh, sl, bs_[tid + PAIR * q]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double oh = __shfl_xor(sh, off), ol = __shfl_xor(sl, off);
+      dd_add(sh, sl, oh);
+      sl += ol;
+    }
+    if (lane == 0) {
+      red[0][w] = sh;
+      red[1][w] = sl;
+    }
+    __syncthreads();
+    sh = red[0][0];
+    sl = red[1][0];
+    dd_add(sh, sl, red[0][1]);
+    sl += red[1][1];
+    const double dfc = (sh + sl) / MM;
+#pragma unroll
+    for (int q = 0; q < MM / PAIR; ++q) bs_[tid + PAIR * q] -= dfc;
+    if (tid == 0) {    // thread 0 owns cell 0
+      const double tp = dg[0];
+      dg[0] += tp;
+      bs_[0] += tp * pm[0];
+      pin_sc[0] = dfc;
+      pin_sc[1] = tp;
+    }
   }
   __syncthreads();
 
@@ -1367,54 +1403,30 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
   factor_pair(Sv, w, c, gq, dg, ex, cy, xch, pvc);
   if (pvc.bad()) atomicOr(a.status, ST_STITCH_PIVOT);
   solve_column_pair(Sv, w, bs_, ps, c, gq, cy);
-  // iterative refinement with the stored inverse blocks, residual in
-  // double-double: one step brings the per-cell balance to the FP64 floor
-  // (a second left every balance and parity figure unchanged)
-  for (int it = 0; it < 1; ++it) {
-    for (int l = tid; l < MM; l += PAIR) {
-      const int li = l % M, lj = l / M;
-      double hi = bs_[l], lo = 0.0;
-      dd_fma(hi, lo, -dg[l], ps[l]);
-      if (li < M - 1) dd_fma(hi, lo, -ex[l], ps[l + 1]);
-      if (li > 0) dd_fma(hi, lo, -ex[l - 1], ps[l - 1]);
-      if (lj < M - 1) dd_fma(hi, lo, -cy[l], ps[l + M]);
-      if (lj > 0) dd_fma(hi, lo, -cy[l - M], ps[l - M]);
-      rs[l] = hi + lo;
-    }
-    __syncthreads();
-    solve_column_pair(Sv, w, rs, rs, c, gq, cy);   // in place: each row is read before it is written
-    for (int l = tid; l < MM; l += PAIR) ps[l] += rs[l];
-    __syncthreads();
+  // one step of iterative refinement with the stored inverse blocks; the
+  // residual is the cells' mass balance in double-double (the FP64 diagonal
+  // sums of the assembled matrix would leave eps * T |p| per cell), and the
+  // pressure is kept as the unevaluated sum ps + rs (solution + correction)
+  // from which the fluxes are formed: the cell balances then hold to the
+  // rounding of the fluxes themselves
+#pragma unroll 1
+  for (int q = 0; q < MM / PAIR; ++q) {   // one cell at a time: the inverse blocks stay in registers
+    const int l = tid + PAIR * q;
+    rs[l] = stitch_balance_residual<M>(a, I, J, l, kap, ps, Fout, pin_sc[0], pin_sc[1], pm[0]);
   }
+  __syncthreads();
+  solve_column_pair(Sv, w, rs, rs, c, gq, cy);   // in place: each row is read before it is written
 
   double imb = 0.0, fmx = 0.0, psum = 0.0;
+#pragma unroll 1
   for (int l = tid; l < MM; l += PAIR) {
     const int li = l % M, lj = l / M;
     const int i = I * M + li, j = J * M + lj;
-    const double kc = kap[l];
-    const double txc = kc * g.hy / (0.5 * g.hx), tyc = kc * g.hx / (0.5 * g.hy);
-    const double pv = ps[l];
+    double out[4];
+    stitch_out_fluxes<M>(a, I, J, l, kap, ps, rs, Fout, out);
     double F[4];
-    for (int side = 0; side < 4; ++side) {
-      const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
-      double out;
-      if (inner) {
-        const int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
-        const double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
-        out = series2(side < 2 ? txc : tyc, tn) * (pv - ps[nb]);
-      } else {
-        const int e = side_iface(g, I, J, side);
-        const int t = (side < 2) ? lj : li;
-        if (e >= 0) {
-          out = Fout[side][t];
-        } else {
-          const double flen = (side < 2) ? g.hy : g.hx;
-          const double v = a.bcv[side][(side < 2) ? j : i];
-          out = (g.kind[side] == 1) ? ((side < 2) ? txc : tyc) * (pv - v) : v * flen;
-        }
-      }
-      F[side] = (side == 0 || side == 2) ? -out : out;
-    }
+#pragma unroll
+    for (int side = 0; side < 4; ++side) F[side] = (side == 0 || side == 2) ? -out[side] : out[side];
     a.ux[(size_t)j * (g.nx + 1) + i] = F[0] / g.hy;
     if (li == M - 1 && I == g.SX - 1) a.ux[(size_t)j * (g.nx + 1) + i + 1] = F[1] / g.hy;
     a.uy[(size_t)j * g.nx + i] = F[2] / g.hx;

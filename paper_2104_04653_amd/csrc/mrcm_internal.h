@@ -52,6 +52,9 @@ struct SubArgs {
   int* fallback;          // FP32 refinement: [0] = count, [1..] = subdomains to redo in FP64
   int* ir_iters;          // FP32 refinement: [0] = largest refinement count used
   double gate_tol;        // surrogate: accepted if ||b - A x|| <= gate_tol ||b|| per column
+  int ir_max;             // FP32 refinement: at most this many steps
+  double ir_tol;          // FP32 refinement: converged (and accepted without the FP64
+                          // re-solve) once the last correction is <= ir_tol of the solution
   double* scratch;        // generic kernels: per-subdomain work arrays (global memory)
   long long scratch_stride;   // doubles per subdomain in scratch
   unsigned long long* stamps; // phase clock readings (PhaseStamp slots)

@@ -26,7 +26,8 @@ EXPORTED = [
     "mrcm_setup", "mrcm_update_mobility", "mrcm_solve", "mrcm_fine_flux", "mrcm_step", "mrcm_get_stats",
     "mrcm_get_sizes", "mrcm_get_interface_solution", "mrcm_get_local_blocks",
     "mrcm_get_basis", "mrcm_surrogate_inputs", "mrcm_surrogate_targets", "mrcm_set_surrogate",
-    "mrcm_solve_with_predictions", "mrcm_set_gate_tolerance", "mrcm_cnn_create", "mrcm_cnn_num_params",
+    "mrcm_solve_with_predictions", "mrcm_set_gate_tolerance", "mrcm_set_refinement",
+    "mrcm_set_interface_refinement", "mrcm_cnn_create", "mrcm_cnn_num_params",
     "mrcm_cnn_get_params", "mrcm_cnn_set_params", "mrcm_cnn_forward", "mrcm_cnn_loss_grad",
     "mrcm_cnn_train_step", "mrcm_cnn_destroy", "mrcm_last_error", "mrcm_destroy",
 ]
@@ -101,6 +102,8 @@ def load_library(path: str = LIB_PATH):
     lib.mrcm_set_surrogate.argtypes = [P, P]
     lib.mrcm_solve_with_predictions.argtypes = [P, P]
     lib.mrcm_set_gate_tolerance.argtypes = [P, ctypes.c_double]
+    lib.mrcm_set_refinement.argtypes = [P, ctypes.c_int32, ctypes.c_double]
+    lib.mrcm_set_interface_refinement.argtypes = [P, ctypes.c_int32, ctypes.c_double]
     lib.mrcm_cnn_create.argtypes = [ctypes.POINTER(P), i32, ctypes.c_uint64, P]
     lib.mrcm_cnn_num_params.argtypes = [P, ctypes.POINTER(i32)]
     lib.mrcm_cnn_get_params.argtypes = [P, fp]
@@ -171,7 +174,13 @@ class MRCMSolver:
         src = None if prob.source is None else _host(prob.source, nx * ny)
         alpha_arr = None
         if getattr(prob, "alpha_per_interface", None) is not None:
-            alpha_arr = _host(prob.alpha_per_interface)
+            # the library reads one value per interface: vertical interfaces
+            # (SX-1)*SY, then horizontal ones SX*(SY-1)
+            if int(prob.sub_nx) <= 0 or int(prob.sub_ny) <= 0 or nx % int(prob.sub_nx) \
+                    or ny % int(prob.sub_ny):
+                raise ValueError("grid must be divisible by the subdomain size")
+            sx, sy = nx // int(prob.sub_nx), ny // int(prob.sub_ny)
+            alpha_arr = _host(prob.alpha_per_interface, (sx - 1) * sy + sx * (sy - 1))
         fluid = Fluid(float(prob.mu_w), float(prob.mu_o))
         ctx = ctypes.c_void_p()
         st = _current_stream() if stream is None else ctypes.c_void_p(stream)
@@ -349,6 +358,16 @@ class MRCMSolver:
 
     def set_gate_tolerance(self, tol: float):
         self._check(self.lib.mrcm_set_gate_tolerance(self.ctx, float(tol)), "mrcm_set_gate_tolerance")
+
+    def set_refinement(self, max_steps: int, tol: float):
+        """Stopping rule of the FP32 + FP64 local refinement (fp32_ir)."""
+        self._check(self.lib.mrcm_set_refinement(self.ctx, int(max_steps), float(tol)),
+                    "mrcm_set_refinement")
+
+    def set_interface_refinement(self, max_steps: int, tol: float):
+        """Stopping rule of the interface solve's refinement."""
+        self._check(self.lib.mrcm_set_interface_refinement(self.ctx, int(max_steps), float(tol)),
+                    "mrcm_set_interface_refinement")
 
     def set_surrogate(self, net: "SurrogateNet"):
         self._check(self.lib.mrcm_set_surrogate(self.ctx, net.net), "mrcm_set_surrogate")

@@ -95,11 +95,3 @@ def oracle_basis_padded(prob, ref):
         cols = padded_columns(prob, sd)
         out[sd][:, cols] = ref.X[cells][:, :len(cols)]
     return out
-
-
-def flux_floor(prob, lam, p):
-    """Rounding floor of a cell balance computed from FP64 pressures:
-    eps * max transmissibility * max |p| (relative to max |F| by the caller)."""
-    kap = prob.perm * (1.0 if lam is None else lam)
-    t = 2.0 * kap.max() * max(prob.hy / prob.hx, prob.hx / prob.hy)
-    return np.finfo(float).eps * t * np.abs(p).max()

@@ -26,8 +26,10 @@ def check(prob, s, tol=TOL):
     ef = rel(np.r_[g["ux"], g["uy"]], np.r_[ref.ux, ref.uy])
     st = g["stats"]
     say("  rel L2: p %.2e  flux %.2e  refinement steps (max) %d  fp64 fallbacks %d of %d"
-        % (ep, ef, st["ir_iters_max"], st["fallbacks"], st["n_sub"]))
+        "  imbalance %.2e" % (ep, ef, st["ir_iters_max"], st["fallbacks"], st["n_sub"],
+                              g["imbalance"]))
     assert ep < tol and ef < tol
+    assert g["imbalance"] < 1e-12     # every stitched cell balances
     return g
 
 

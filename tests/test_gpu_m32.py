@@ -36,6 +36,7 @@ def check_fp32_ir(prob, lam, ref, label):
         "  ms local %.3f" % (label, ep, ef, st["ir_iters_max"], st["fallbacks"], st["n_sub"],
                              st["ms_local"]))
     assert ep < FP32_TOL and ef < FP32_TOL
+    assert g["imbalance"] < 1e-12     # every stitched cell balances
     return g
 
 

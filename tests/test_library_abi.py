@@ -98,4 +98,19 @@ def test_surrogate_entry_points_reject_null_without_gpu():
     assert lib.mrcm_surrogate_targets(None, None) == binding.E_INVAL
     assert lib.mrcm_solve_with_predictions(None, None) == binding.E_INVAL
     assert lib.mrcm_set_gate_tolerance(None, 1e-6) == binding.E_INVAL
+    assert lib.mrcm_set_refinement(None, 8, 1e-9) == binding.E_INVAL
+    assert lib.mrcm_set_interface_refinement(None, 3, 1e-14) == binding.E_INVAL
     lib.mrcm_cnn_destroy(None)
+
+
+def test_binding_checks_alpha_length_without_gpu():
+    """One Robin parameter per interface: a short array is rejected by the
+    binding before the library could read past its end."""
+    from paper_2104_04653_amd import mrcm as binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libmrcm.so not built")
+    import numpy as np
+    import inputs
+    prob = inputs.make_problem("gauss64", sub=16)           # 4 x 4 subdomains: 24 interfaces
+    with pytest.raises(ValueError):
+        binding.MRCMSolver(prob.replace(alpha_per_interface=np.ones(23)))

@@ -8,10 +8,13 @@ of the chain, not only the parts that happen to be exercised.
 import numpy as np
 import pytest
 
+import oracle.discretization as od
+import oracle.fine as of
 import oracle.mrcm as om
 from inputs import make_problem
 from oracle.fine import solve_fine
 from tests import test_oracle_pins as P
+from tests import test_oracle_pins_data as PD
 from tests.test_oracle_pins import linear_dirichlet
 
 
@@ -22,6 +25,13 @@ PINS = [
     lambda: P.test_full_spaces_pure_neumann(),
     lambda: P.test_conservation(),
     lambda: P.test_alpha_limits(),
+    lambda: PD.test_fine_layered_data_closed_form(3),
+    lambda: PD.test_mrcm_layered_data_closed_form(1, "linear"),
+    lambda: PD.test_mrcm_layered_data_closed_form(3, "linear"),
+    lambda: PD.test_mrcm_layered_data_closed_form(5, "full"),
+    lambda: PD.test_mrcm_layered_data_closed_form_along_y(3),
+    lambda: PD.test_quarter_five_spot_source_sign(),
+    lambda: PD.test_mixed_alpha_limits_per_interface(),
 ]
 
 
@@ -97,3 +107,49 @@ def test_transposed_projection_caught(monkeypatch):
     lin, exact = linear_dirichlet(16, 12, 4, 0.5, 2.0, -1.5, alpha=0.7)
     # a reversed basis spans the same space: still exact (basis independence)
     assert np.abs(om.solve_mrcm(lin).p - exact).max() < 1e-12
+
+
+def _flipped_injection(prob, hx, hy):
+    return -od.cell_injection(prob, hx, hy)
+
+
+def _flipped_outflow(u_b, flen):
+    return -od.neumann_outflow(u_b, flen)
+
+
+def test_source_sign_flip_in_mrcm_caught(monkeypatch):
+    """q enters the local problems and the balance check with the wrong sign
+    (consistently, so the MRCM still conserves its own flipped source)."""
+    monkeypatch.setattr(om, "cell_injection", _flipped_injection)
+    assert not _pins_pass()
+
+
+def test_source_sign_flip_in_fine_caught(monkeypatch):
+    monkeypatch.setattr(of, "cell_injection", _flipped_injection)
+    assert not _pins_pass()
+
+
+def test_source_scale_caught(monkeypatch):
+    """q per cell instead of q per unit area (|V| dropped)."""
+    monkeypatch.setattr(om, "cell_injection",
+                        lambda prob, hx, hy: od.cell_injection(prob, hx, hy) / (hx * hy))
+    assert not _pins_pass()
+
+
+def test_neumann_sign_flip_in_mrcm_caught(monkeypatch):
+    """u_b read as the inward instead of the outward normal velocity, in the
+    local problems and in the boundary fluxes alike."""
+    monkeypatch.setattr(om, "neumann_outflow", _flipped_outflow)
+    assert not _pins_pass()
+
+
+def test_neumann_sign_flip_in_fine_caught(monkeypatch):
+    monkeypatch.setattr(of, "neumann_outflow", _flipped_outflow)
+    assert not _pins_pass()
+
+
+def test_alpha_from_wrong_interface_caught(monkeypatch):
+    """Per-interface alpha read in reverse interface order."""
+    orig = om.interface_alpha
+    monkeypatch.setattr(om, "interface_alpha", lambda geom, prob: orig(geom, prob)[::-1].copy())
+    assert not _pins_pass()
