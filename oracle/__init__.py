@@ -16,6 +16,9 @@ Contents
 * ``mrcm`` - the MRCM itself: local Robin problems (mrc1), basis functions,
   the interface system (mrc2), composition, stitch and the conservation
   check; plus the monolithic form used to pin the static condensation;
-* ``transport`` - the sequential-implicit upwind transport of section 4, used
-  to produce saturation sequences for two-phase workloads.
+* ``transport`` - the sequential-implicit transport of section 4: implicit
+  Euler with first-order upwind fluxes, Newton's method with the
+  inflection-point strategy, and the sequential loop with the Darcy solve;
+* ``cnn`` - the FP64 reference of the learned surrogate (not part of the
+  paper's method).
 """
