@@ -68,7 +68,7 @@ enum { MRCM_SPACE_LINEAR = 0, MRCM_SPACE_EDGE_SOLUTION = 1, MRCM_SPACE_FULL = 2 
 /* Precision of the local (subdomain) factorisations.  The interface system
  * is always solved in FP64.  FP32_IR: FP32 factors and solves of the
  * diagonally scaled local system, FP64 residuals and iterative refinement
- * until the last correction is below 1e-9 of the solution, per-subdomain
+ * until the last correction is below 1e-12 of the solution, per-subdomain
  * FP64 fallback when refinement stalls (16 x 16 subdomains with 2 + 2 dofs,
  * 32 x 32 subdomains with 4 dofs; other sizes MRCM_E_UNSUPPORTED).
  * SURROGATE (16 x 16, 2 + 2 dofs): the basis functions of each
@@ -161,8 +161,9 @@ int mrcm_update_mobility(mrcm_ctx* ctx, const double* values, int32_t values_are
  * FP64 interface system.  Asynchronous except for a final status read.
  * Errors: MRCM_E_INVAL (a mobility not finite and positive), MRCM_E_NOT_SPD
  * (a zero, negative or non-finite pivot), MRCM_E_NO_CONV (the interface
- * residual is still above its tolerance after the allowed refinement steps:
- * the elimination does not pivot, so a nearly singular pivot shows here);
+ * residual is still above its failure bound after the allowed refinement
+ * steps, see mrcm_set_interface_refinement: the elimination does not
+ * pivot, so a nearly singular pivot shows here);
  * after any error the context has no solution (mrcm_fine_flux returns
  * MRCM_E_STATE) until a solve succeeds. */
 int mrcm_solve(mrcm_ctx* ctx);
@@ -172,7 +173,8 @@ int mrcm_solve(mrcm_ctx* ctx);
  * eq. (mrc1)): refinement stops once the largest correction of a subdomain is
  * at most tol of its largest solution value, or after max_steps steps; a
  * subdomain that ends above tol (or met a bad FP32 pivot) is re-solved by the
- * FP64 path and counted in mrcm_stats.fallbacks.  Defaults: 8 steps, 1e-9.
+ * FP64 path and counted in mrcm_stats.fallbacks.  Defaults: 8 steps, 1e-12
+ * (near FP64 accuracy: the stitch's cell balances rest on it).
  * max_steps = 0 sends every subdomain to the FP64 re-solve.  Takes effect at
  * the next solve.  Errors: MRCM_E_INVAL unless 0 <= max_steps <= 64 and
  * 0 < tol < 1; MRCM_E_STATE for another precision. */
@@ -180,12 +182,14 @@ int mrcm_set_refinement(mrcm_ctx* ctx, int32_t max_steps, double tol);
 
 /* Stopping rule of the iterative refinement of the FP64 interface solve
  * (eq. (mrc2)): after the direct solve, refinement steps are taken while
- * max |b - A x| > tol max |b|, at most max_steps; if the residual is still
- * above tol after them the solve fails with MRCM_E_NO_CONV.  Defaults: 3
- * steps; tol 1e-14 (FP64 and SURROGATE), 1e-12 (FP32_IR).  Takes effect at
- * the next solve.  Errors: MRCM_E_INVAL unless 0 <= max_steps <= 16 and
- * 0 < tol < 1. */
-int mrcm_set_interface_refinement(mrcm_ctx* ctx, int32_t max_steps, double tol);
+ * max |b - A x| > tol max |b|, at most max_steps; if the residual is then
+ * above fail_tol max |b| the solve fails with MRCM_E_NO_CONV.  Defaults:
+ * 3 steps; tol 1e-14 (FP64 and SURROGATE), 1e-12 (FP32_IR); fail_tol 1e-10
+ * (the residual of an FP64 solution is about eps |A| |x|, which can exceed
+ * 1e-14 of the right-hand side on ill-conditioned systems whose solution
+ * is still accurate).  Takes effect at the next solve.  Errors: MRCM_E_INVAL
+ * unless 0 <= max_steps <= 16, 0 < tol < 1 and 0 < fail_tol < 1. */
+int mrcm_set_interface_refinement(mrcm_ctx* ctx, int32_t max_steps, double tol, double fail_tol);
 
 /* Reconstruct fine-scale output from the last solve:
  *  p  : nx*ny composed multiscale cell pressure (basis functions combined
@@ -226,6 +230,81 @@ int mrcm_fine_flux(mrcm_ctx* ctx, double* p, double* ux, double* uy, int32_t on_
 int mrcm_step(mrcm_ctx* ctx, const double* values, int32_t values_are_lambda,
               int32_t values_on_device, double* p, double* ux, double* uy,
               int32_t outputs_on_device, double* max_cell_imbalance);
+
+/* ------------------------------------------------------------------------
+ * Implicit transport of the water saturation (section 4): one implicit
+ * Euler step of eq. (BL2D) with first-order upwind fluxes
+ * (eqs. (BL2D_Newton2), (fluxes_impli), (up_fluxes_impli)), solved by
+ * Newton's method (eqs. (BL2D_Newton8), (BL2D_Newton7)) with the
+ * inflection-point strategy: every iterate is kept in [0, 1] and an update
+ * that crosses the inflection point of f is halved.  Each Newton system is
+ * solved by BiCGSTAB on the Jacobi-scaled Jacobian to a relative residual
+ * of 1e-12 (at most 400 iterations).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t newton_iters;    /* Newton iterations taken */
+  int32_t linear_iters;    /* BiCGSTAB iterations, summed over them */
+  int32_t converged;       /* 1 if the last change was <= eta */
+  int32_t linear_failures; /* Newton iterations whose linear solve stopped short */
+  double last_change;      /* L2 norm sqrt(sum V (s^{nu+1} - s^nu)^2) of the last change */
+  double ms;               /* wall time of the call */
+} mrcm_transport_stats;
+
+/* One transport step from s_old to s_new with the face velocities ux, uy of
+ * the last Darcy solve (frozen over the step, eq. (BL2D_Newton)).
+ *  s_old, s_new : device, nx*ny saturations (distinct, non-overlapping);
+ *                 s_new receives the new time level.
+ *  ux, uy       : device, the +x / +y face velocities in the layout of
+ *                 mrcm_fine_flux ((nx+1)*ny and nx*(ny+1)); the face flux is
+ *                 velocity times face length.
+ *  dt           : time step (> 0); porosity is scaled out (time in pore
+ *                 volumes).
+ *  s_inflow     : saturation of the water entering through boundary faces
+ *                 with inflow (eq. (BL2D), inlet condition), in [0, 1].
+ *                 Sources of the context: an injector (q > 0) injects water
+ *                 only; a producer (q < 0) produces the mixture, f(s) q.
+ *  eta          : Newton stops when the L2 norm of the change is <= eta
+ *                 (section 5 uses 1e-6).
+ *  max_newton   : iteration cap (1 .. 1000).
+ *  stats        : may be NULL.
+ * Synchronous.  Errors: MRCM_E_INVAL (bad arguments; nothing is written),
+ * MRCM_E_NO_CONV (no convergence within max_newton: s_new holds the last
+ * iterate), MRCM_E_HIP. */
+int mrcm_transport_step(mrcm_ctx* ctx, const double* s_old, double* s_new, const double* ux,
+                        const double* uy, double dt, double s_inflow, double eta, int32_t max_newton,
+                        mrcm_transport_stats* stats);
+
+/* One step of the sequential implicit scheme (section 4): the transport
+ * step from s_old with the velocities (ux, uy) of the last Darcy solve
+ * (u^n), then the Darcy solve (mrcm_step) with the new saturation, which
+ * writes p, ux, uy (u^{n+1}) in place.  All arrays are device arrays in the
+ * layouts of mrcm_transport_step and mrcm_fine_flux (p may be NULL).  Start
+ * a run with mrcm_step on s^0 to get u^0.  Errors: those of the two calls;
+ * stats (may be NULL) are the transport's. */
+int mrcm_si_step(mrcm_ctx* ctx, const double* s_old, double* s_new, double* p, double* ux,
+                 double* uy, double dt, double s_inflow, double eta, int32_t max_newton,
+                 mrcm_transport_stats* stats);
+
+typedef struct {
+  int32_t outer_iters;   /* Darcy + transport iterations */
+  int32_t newton_iters;  /* Newton iterations, summed over the transport solves */
+  int32_t converged;     /* 1 if the last change was below outer_tol */
+  double last_change;    /* max |s^{k+1} - s^k| of the last outer iteration */
+  double ms;             /* wall time of the call */
+} mrcm_sfi_stats;
+
+/* One step of the sequential fully implicit scheme (section 5.4): from
+ * s^{n+1,0} = s_old, repeat the Darcy solve with the current iterate and the
+ * transport step from s_old with its velocities, until the largest change
+ * of the saturation between successive outer iterations is below outer_tol
+ * (the paper: 1e-4, with eta = 1e-6) or max_outer iterations.  s_new
+ * receives the last iterate; p, ux, uy the Darcy solution of the iterate
+ * before it (device arrays, as in mrcm_si_step; p may be NULL).  Errors:
+ * MRCM_E_INVAL, MRCM_E_NO_CONV (outer loop or a transport solve), and those
+ * of mrcm_step. */
+int mrcm_sfi_step(mrcm_ctx* ctx, const double* s_old, double* s_new, double* p, double* ux,
+                  double* uy, double dt, double s_inflow, double eta, int32_t max_newton,
+                  double outer_tol, int32_t max_outer, mrcm_sfi_stats* stats);
 
 /* Statistics of the last solve / fine_flux. */
 int mrcm_get_stats(const mrcm_ctx* ctx, mrcm_stats* stats);

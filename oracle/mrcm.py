@@ -88,7 +88,7 @@ def _bc_faces(geom, prob, kappa):
     return out
 
 
-def local_operator(geom, prob, kappa, robin_T=None):
+def local_operator(geom, prob, kappa, robin_T=None, extended=False):
     """Block-diagonal matrix of all local problems and their data vector.
 
     Interior faces of a subdomain: harmonic two-point coupling; physical
@@ -133,8 +133,15 @@ def local_operator(geom, prob, kappa, robin_T=None):
             rows.append(cells)
             cols.append(cells)
             vals.append(T)
-    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                      shape=(n, n))
+    rr, cc, vv = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    A = sp.csr_matrix((vv, (rr, cc)), shape=(n, n))
+    if extended:
+        # the same entries with the duplicates (the diagonal's sums of
+        # transmissibilities) summed in the x87 extended format: its products
+        # with a solution are the cells' mass balances (flux form), where the
+        # FP64-summed diagonal leaves eps T |p| per cell
+        A_ext = sp.csr_matrix((vv.astype(np.longdouble), (rr, cc)), shape=(n, n))
+        return A, rhs, (Tx, Ty, tx, ty, same_x, same_y), A_ext
     return A, rhs, (Tx, Ty, tx, ty, same_x, same_y)
 
 
@@ -190,17 +197,19 @@ def _residual(A, x, b):
     """b - A x.  With RESIDUAL == "extended" the products and sums are taken
     in the x87 extended format (64-bit mantissa) and rounded once, so that
     refinement converges to the FP64 solution of the FP64 data instead of
-    stalling at condition-number times FP64 rounding."""
+    stalling at condition-number times FP64 rounding.  A may already hold
+    extended entries (a matrix assembled in extended precision)."""
     if RESIDUAL == "extended":
         ld = np.longdouble
         return (np.asarray(b, dtype=ld) - A.astype(ld) @ np.asarray(x, dtype=ld)).astype(np.float64)
     return b - A @ x
 
 
-def _refined(A, solve, b, steps=3):
-    """x = A^-1 b by a direct solve plus iterative refinement steps."""
+def _refined(A, solve, b, steps=3, A_res=None):
+    """x = A^-1 b by a direct solve plus iterative refinement steps; the
+    residuals use A_res (default A)."""
     x = solve(b)
-    A = A.tocsr()
+    A = (A if A_res is None else A_res).tocsr()
     for _ in range(steps):
         x = x + solve(_residual(A, x, b))
     return x
@@ -216,10 +225,10 @@ def _refined_extended(solve, b, residual, steps=3):
     return x
 
 
-def _local_solve(A, B, geom, method):
+def _local_solve(A, B, geom, method, A_ext=None):
     if method == "superlu":
         lu = spla.splu(A.tocsc())
-        return _refined(A, lu.solve, B)
+        return _refined(A, lu.solve, B, A_res=A_ext)
     if method == "banded":
         # one LAPACK banded Cholesky per subdomain in the local natural
         # ordering, whose half-bandwidth is the subdomain width
@@ -240,7 +249,7 @@ def _local_solve(A, B, geom, method):
         return X
 
     if method == "banded_refined":
-        return _refined(A, lambda r: _local_solve(A, r, geom, "banded"), B)
+        return _refined(A, lambda r: _local_solve(A, r, geom, "banded"), B, A_res=A_ext)
     raise ValueError(method)
 
 
@@ -308,7 +317,8 @@ def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu
 
     # local problems, all subdomains at once (they are uncoupled)
     robin = [(r["cells"], r["TR"]) for per in recs for r in per]
-    A, rhs0, (Tx, Ty, tx, ty, same_x, same_y) = local_operator(geom, prob, kappa, robin)
+    A, rhs0, (Tx, Ty, tx, ty, same_x, same_y), A_ext = local_operator(geom, prob, kappa, robin,
+                                                                    extended=True)
     B = np.zeros((geom.n_cells, R))
     B[:, 0] = rhs0
     for itf, per in zip(geom.interfaces, recs):
@@ -317,7 +327,7 @@ def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu
             c0 = col_off[rec["sub"], rec["side"]]
             G = _interface_data(itf, rec, ps, us, c0)
             B[rec["cells"], c0:c0 + G.shape[1]] += rec["TR"][:, None] * G
-    X = _local_solve(A, B, geom, local_solver)
+    X = _local_solve(A, B, geom, local_solver, A_ext)
 
     # traces and the per-subdomain blocks of the interface system
     blocks = [np.zeros((len(d), R)) for d in sub_dofs]

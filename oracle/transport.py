@@ -33,6 +33,10 @@ f(s) = M s^2 / (M s^2 + (1-s)^2), M = mu_o / mu_w (eq. (fluxos2)).
 
 Each Newton step solves the Jacobian system with a sparse direct solver
 (SuperLU).
+
+The sequential fully implicit variant of section 5.4 (``sfi_step``) repeats
+the Darcy solve and the transport step within a time step until the
+saturation changes by less than 1e-4 between successive outer iterations.
 """
 from __future__ import annotations
 
@@ -211,3 +215,43 @@ def si_run(prob, s0, n_steps, dt, s_inflow=1.0, eta=1e-6, darcy=None):
         traj.append(st.s)
         iters.append(st.iterations)
     return traj, iters
+
+
+@dataclasses.dataclass
+class SFIStep:
+    s: np.ndarray          # saturation at the new time level
+    outer: int             # outer (Darcy + transport) iterations
+    converged: bool
+    changes: list          # max |s^{k+1} - s^k| per outer iteration
+    newton: list           # Newton iterations of each transport solve
+    Fx: np.ndarray         # face fluxes of the last Darcy solve
+    Fy: np.ndarray
+
+
+def sfi_step(prob, s_old, dt, s_inflow=1.0, eta=1e-6, outer_tol=1e-4, max_outer=50, darcy=None):
+    """One time step of the sequential fully implicit scheme (section 5.4):
+    starting from s^{n+1,0} = s^n, repeat a Darcy solve with the current
+    saturation and a transport step from s^n with its fluxes, until the
+    largest change of the saturation between successive outer iterations
+    is below outer_tol (1e-4 in the paper, with eta = 1e-6 for Newton)."""
+    from .discretization import total_mobility
+    from .mrcm import solve_mrcm
+    if darcy is None:
+        def darcy(p, lam):
+            r = solve_mrcm(p, lam=lam)
+            return r.Fx, r.Fy
+    s_old = np.asarray(s_old, dtype=np.float64)
+    s = s_old.copy()
+    changes, newton = [], []
+    converged = False
+    for k in range(1, max_outer + 1):
+        Fx, Fy = darcy(prob, total_mobility(s, prob.mu_w, prob.mu_o))
+        st = transport_step(prob, s_old, Fx, Fy, dt, s_inflow=s_inflow, eta=eta)
+        newton.append(st.iterations)
+        change = float(np.abs(st.s - s).max())
+        changes.append(change)
+        s = st.s
+        if change < outer_tol:
+            converged = True
+            break
+    return SFIStep(s=s, outer=k, converged=converged, changes=changes, newton=newton, Fx=Fx, Fy=Fy)

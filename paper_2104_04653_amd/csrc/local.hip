@@ -189,37 +189,23 @@ __device__ void thomas_resolve(T* Xs, const T* Sinv, const T* cy) {
   }
 }
 
-// r = b - A x for the local five-point matrix (diagonal dg, +x coupling ex,
-// +y coupling cy), NR columns.
+// r <- b - A x in double-double for the local five-point matrix, NR columns
+// (r may be b); dgl: the rounding error of the diagonal sums, so that the
+// residual is the cells' mass balance (flux form) to double-double accuracy
 template <int M, int NR>
-__device__ void local_residual(const double* b, const double* x, double* r, const double* dg,
-                               const double* ex, const double* cy) {
-  for (int o = threadIdx.x; o < M * M * NR; o += NT) {
-    const int l = o / NR, col = o % NR;
-    const int li = l % M, lj = l / M;
-    double ax = dg[l] * x[o];
-    if (li < M - 1) ax += ex[l] * x[(l + 1) * NR + col];
-    if (li > 0) ax += ex[l - 1] * x[(l - 1) * NR + col];
-    if (lj < M - 1) ax += cy[l] * x[(l + M) * NR + col];
-    if (lj > 0) ax += cy[l - M] * x[(l - M) * NR + col];
-    r[o] = b[o] - ax;
-  }
-}
-
-// b <- b - A x in double-double for the local five-point matrix, NR columns
-template <int M, int NR>
-__device__ void local_residual_dd(double* b, const double* x, const double* dg, const double* ex,
-                                  const double* cy) {
+__device__ void local_residual_dd(const double* b, const double* x, double* r, const double* dg,
+                                  const float* dgl, const double* ex, const double* cy) {
   for (int o = threadIdx.x; o < M * M * NR; o += NT) {
     const int l = o / NR, col = o % NR;
     const int li = l % M, lj = l / M;
     double hi = b[o], lo = 0.0;
     dd_fma(hi, lo, -dg[l], x[o]);
+    dd_fma(hi, lo, -(double)dgl[l], x[o]);
     if (li < M - 1) dd_fma(hi, lo, -ex[l], x[(l + 1) * NR + col]);
     if (li > 0) dd_fma(hi, lo, -ex[l - 1], x[(l - 1) * NR + col]);
     if (lj < M - 1) dd_fma(hi, lo, -cy[l], x[(l + M) * NR + col]);
     if (lj > 0) dd_fma(hi, lo, -cy[l - M], x[(l - M) * NR + col]);
-    b[o] = hi + lo;
+    r[o] = hi + lo;
   }
 }
 
@@ -294,6 +280,7 @@ __global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
   constexpr int MM = M * M;
   constexpr bool BIG = LocalStore<M>::big;
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
+  __shared__ float dgl[MM];            // rounding error of the diagonal sums
   __shared__ double Xs_l[BIG ? 1 : MM * R];
   __shared__ double Sinv_l[BIG ? 1 : M * MM];
   __shared__ double pivbuf[4 * M];
@@ -316,20 +303,18 @@ __global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
   load_kappa<M>(a, I, J, kap);
   __syncthreads();
   for (int l = tid; l < MM; l += NT)
-    assemble_cell<M, R>(a, I, J, l, kap, dg, ex, cy, Xs + l * R, 1, nullptr);
+    assemble_cell<M, R>(a, I, J, l, kap, dg, ex, cy, Xs + l * R, 1, nullptr, dgl);
   __syncthreads();
   for (int o = tid; o < MM * R; o += NT) Bs[o] = Xs[o];
 
   if (thomas_solve<M, R, double>(Xs, Sinv, dg, ex, cy, pivbuf) && tid == 0)
     atomicOr(a.status, ST_LOCAL_PIVOT);
-  // iterative refinement, residual in double-double (Bs keeps B; the
-  // correction goes through Rg)
+  // iterative refinement, residual in double-double with the exact diagonal
+  // (Bs keeps B; the correction goes through Rg)
   double* Rg = Rs_l;
   for (int it = 0; it < LOCAL_IR_STEPS; ++it) {
     __syncthreads();
-    for (int o = tid; o < MM * R; o += NT) Rg[o] = Bs[o];
-    __syncthreads();
-    local_residual_dd<M, R>(Rg, Xs, dg, ex, cy);
+    local_residual_dd<M, R>(Bs, Xs, Rg, dg, dgl, ex, cy);
     thomas_resolve<M, R, double>(Rg, Sinv, cy);
     for (int o = tid; o < MM * R; o += NT) Xs[o] += Rg[o];
   }
@@ -340,15 +325,16 @@ __global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
   generic_block<M, D>(a, sd, I, J, kap, Xs);
 }
 
-// FP32 factorisation + FP64 iterative refinement for the generic sizes with
+// FP32 factorisation + double-double-residual refinement for the generic sizes with
 // their work arrays in the per-subdomain scratch (32 x 32 subdomains): the
 // same method as the 16 x 16 FP32 kernel.  The local matrix is scaled
 // symmetrically (Ds A Ds, Ds = diag(A)^-1/2, unit diagonal); the inverse
 // Schur blocks and the solves of the scaled system are FP32, the solution
-// and the residuals FP64.  Refinement stops when the largest correction is
-// below a.ir_tol of the largest solution value (at most a.ir_max steps); a
-// subdomain that ends above
-// it, or met a bad FP32 pivot, is listed for the FP64 re-solve.
+// FP64 and the residuals double-double with the exact diagonal (the cells'
+// mass balances).  Refinement stops when the largest correction is below
+// a.ir_tol of the largest solution value (at most a.ir_max steps); a
+// subdomain that ends above it, or met a bad FP32 pivot, is listed for the
+// FP64 re-solve.
 
 template <int M, int D>
 __global__ void __launch_bounds__(NT) local_basis32_kernel(SubArgs a) {
@@ -356,6 +342,7 @@ __global__ void __launch_bounds__(NT) local_basis32_kernel(SubArgs a) {
   constexpr int MM = M * M;
   static_assert(LocalStore<M>::big && R <= M, "scratch layout of the large subdomains");
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], dsc[MM];
+  __shared__ float dgl[MM];            // rounding error of the diagonal sums
   __shared__ float dgs[MM], exs[MM], cys[MM];
   __shared__ float pivbuf[4 * M];
   __shared__ double red[2][NT / 64];
@@ -375,7 +362,7 @@ __global__ void __launch_bounds__(NT) local_basis32_kernel(SubArgs a) {
   load_kappa<M>(a, I, J, kap);
   __syncthreads();
   for (int l = tid; l < MM; l += NT)
-    assemble_cell<M, R>(a, I, J, l, kap, dg, ex, cy, Bs + l * R, 1, nullptr);
+    assemble_cell<M, R>(a, I, J, l, kap, dg, ex, cy, Bs + l * R, 1, nullptr, dgl);
   __syncthreads();
   for (int l = tid; l < MM; l += NT) dsc[l] = 1.0 / sqrt(dg[l]);
   __syncthreads();
@@ -395,7 +382,7 @@ __global__ void __launch_bounds__(NT) local_basis32_kernel(SubArgs a) {
   double rel = 1.0;
   for (int it = 0; it < a.ir_max; ++it) {
     __syncthreads();
-    local_residual<M, R>(Bs, Xs, Rg, dg, ex, cy);
+    local_residual_dd<M, R>(Bs, Xs, Rg, dg, dgl, ex, cy);
     __syncthreads();
     for (int o = tid; o < MM * R; o += NT) Ws[o] = (float)(dsc[o / R] * Rg[o]);
     thomas_resolve<M, R, float>(Ws, Sinv, cys);

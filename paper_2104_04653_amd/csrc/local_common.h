@@ -13,6 +13,16 @@ namespace local {
 
 __device__ inline double series2(double a, double b) { return 1.0 / (1.0 / a + 1.0 / b); }
 
+// (hi, lo) += b with an error-free two-sum
+__device__ inline void dd_add(double& hi, double& lo, double b) {
+#pragma clang fp contract(off)
+  const double s = hi + b;
+  const double bb = s - hi;
+  lo += (hi - (s - bb)) + (b - bb);
+  hi = s;
+}
+
+
 struct SideGeo {
   double flen, dist, H;
 };
@@ -89,14 +99,19 @@ __device__ inline CellLoads cell_loads(const SubArgs& a, int I, int J, int l, in
 template <int M, int R, bool SIDES = true>
 __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const double* kap,
                               double* dg, double* ex, double* cy, double* xrow, int robin,
-                              const double (*Fout)[M], const CellLoads& cl) {
+                              const double (*Fout)[M], const CellLoads& cl, float* dgl = nullptr) {
   const Geo& g = a.g;
   const int li = l % M, lj = l / M;
   const int i = I * M + li, j = J * M + lj;
   const double kc = kap[l];
   const double txc = kc * g.hy / (0.5 * g.hx);
   const double tyc = kc * g.hx / (0.5 * g.hy);
-  double diag = 0.0, cx = 0.0, cn = 0.0;
+  // the diagonal is a sum of transmissibilities; its FP64 rounding error
+  // (dlo, kept with an error-free two-sum) makes (diag + dlo) x exactly the
+  // flux form sum of T (x_c - x_nb), so that residuals formed with it are the
+  // cells' mass balances (a rounded diagonal leaves eps T |x| per cell, which
+  // sums to a conservation defect of the local solutions)
+  double diag = 0.0, dlo = 0.0, cx = 0.0, cn = 0.0;
   for (int q = 0; q < R; ++q) xrow[q] = 0.0;
   double rhs0 = 0.0;
   if (a.src) rhs0 += cl.sv * g.hx * g.hy;
@@ -108,7 +123,7 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
       int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
       double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
       double T = series2(side < 2 ? txc : tyc, tn);
-      diag += T;
+      dd_add(diag, dlo, T);
       if (side == 1) cx = -T;
       if (side == 3) cn = -T;
       continue;
@@ -120,7 +135,7 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
       const double flen = (side < 2) ? g.hy : g.hx;
       const double v = cl.bv[side];
       if (g.kind[side] == 1) {
-        diag += th;
+        dd_add(diag, dlo, th);
         rhs0 += th * v;
       } else {
         rhs0 -= v * flen;
@@ -133,7 +148,7 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
       const double TR = sg.flen * kc / (sg.dist + al * sg.H);
       const double beta = al * sg.H / kc;
       const double sig = side_sigma(side);
-      diag += TR;
+      dd_add(diag, dlo, TR);
       if (SIDES) {
         const int D = g.D;
         const double* bs = a.basis + (size_t)e * D * M;
@@ -148,6 +163,7 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
     }
   }
   dg[l] = diag;
+  if (dgl) dgl[l] = (float)dlo;
   ex[l] = cx;
   cy[l] = cn;
   xrow[0] += rhs0;
@@ -157,9 +173,9 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
 template <int M, int R, bool SIDES = true>
 __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const double* kap,
                               double* dg, double* ex, double* cy, double* xrow, int robin,
-                              const double (*Fout)[M]) {
+                              const double (*Fout)[M], float* dgl = nullptr) {
   assemble_cell<M, R, SIDES>(a, I, J, l, kap, dg, ex, cy, xrow, robin, Fout,
-                             cell_loads<M>(a, I, J, l, robin));
+                             cell_loads<M>(a, I, J, l, robin), dgl);
 }
 
 // (hi, lo) += a * b in double-double arithmetic: the product is split
@@ -189,15 +205,6 @@ __device__ inline double dd_diff(double ah, double al, double bh, double bl) {
   const double v = s - ah;
   const double e = (ah - (s - v)) + (-bh - v);
   return s + (e + (al - bl));
-}
-
-// (hi, lo) += b with an error-free two-sum
-__device__ inline void dd_add(double& hi, double& lo, double b) {
-#pragma clang fp contract(off)
-  const double s = hi + b;
-  const double bb = s - hi;
-  lo += (hi - (s - bb)) + (b - bb);
-  hi = s;
 }
 
 // Outward fluxes of cell l through its W, E, S, N faces in the stitch

@@ -29,14 +29,15 @@
 //    tiles of a chain stay in that wavefront's registers for the backward
 //    sweep.
 #include "local_common.h"
+#include "mfma_tile.h"
 
 namespace mrcm {
 
 namespace {
 
 using namespace local;
+using namespace tile;
 
-typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4z __attribute__((ext_vector_type(4)));
 
 // the forward sweep of a refinement correction is kept in FP32 registers:
@@ -51,84 +52,6 @@ constexpr int D = 4;
 constexpr int R = 17;
 constexpr int WAVE = 64;
 constexpr int MID = M / 2;   // joining block row of the two-sided elimination
-
-__device__ inline double readlane_d(double x, int lane) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffu), lane);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-__device__ inline d4 mfma(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// 1/p from the hardware reciprocal estimate and two Newton steps (each
-// squares the relative error), in place of the IEEE division sequence
-__device__ inline double recip(double p) {
-  double r = __builtin_amdgcn_rcp(p);
-  r = fma(r, fma(-p, r, 1.0), r);
-  return fma(r, fma(-p, r, 1.0), r);
-}
-
-// value of lane K of each 16-lane row (one 64-bit DPP row_newbcast move)
-template <int K>
-__device__ inline double row_bcast(double x) {
-  return __longlong_as_double(
-      __builtin_amdgcn_update_dpp(0LL, __double_as_longlong(x), 0x150 + K, 0xF, 0xF, false));
-}
-
-// One Gauss-Jordan sweep with pivot K on a tile in the output layout: the
-// pivot column (row 4 v + g, column K) comes from lane K of the lane's own
-// 16-lane row, the pivot row (row K, column c) from lane c of row K % 4.
-// Pivot health is accumulated without branches: pmin = min of the pivots,
-// pnan = sum of pivot * 0 (NaN once a pivot was not finite).
-template <int K>
-__device__ inline void gj_sweep(d4& s, int c, int g, double& pmin, double& pnan) {
-  constexpr int kv = K >> 2, kg = K & 3;
-  const double p = readlane_d(s[kv], K + 16 * kg);
-  const double prow = __shfl(s[kv], c + 16 * kg);
-  double pcol[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) pcol[v] = row_bcast<K>(s[v]);
-  pmin = fmin(pmin, p);
-  pnan = fma(p, 0.0, pnan);
-  const double ip = recip(p);
-  const double b = (c == K) ? ip : prow * ip;      // new row K
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const double nv = fma(-pcol[v], b, (c == K) ? 0.0 : s[v]);
-    s[v] = (v == kv && g == kg) ? b : nv;
-  }
-}
-
-template <int K>
-struct GJ16 {
-  static __device__ inline void run(d4& s, int c, int g, double& pmin, double& pnan) {
-    gj_sweep<K>(s, c, g, pmin, pnan);
-    GJ16<K + 1>::run(s, c, g, pmin, pnan);
-  }
-};
-template <>
-struct GJ16<M> {
-  static __device__ inline void run(d4&, int, int, double&, double&) {}
-};
-
-// Health of all pivots of a kernel's Gauss-Jordan inversions, accumulated
-// without branches (a per-pivot test would keep every pivot live until the
-// kernel's final status write).
-struct PivotCheck {
-  double pmin = 1.0, pnan = 0.0;
-  __device__ bool bad() const { return !(pmin > 0.0) || pnan != 0.0; }
-};
-
-// In-place inverse of the SPD tile s (output layout) by Gauss-Jordan sweeps.
-__device__ inline d4 gauss_jordan16(d4 s, int c, int g, PivotCheck& pc) {
-  GJ16<0>::run(s, c, g, pc.pmin, pc.pnan);
-  // materialise the accumulators here, so that the pivots die with the sweep
-  asm volatile("" : "+v"(pc.pmin), "+v"(pc.pnan));
-  return s;
-}
 
 // D_j - C P C with C = diag(cy of coupling row jc) in output layout (D_j
 // alone for jc < 0): the Schur-complemented diagonal block of row j after
@@ -311,6 +234,7 @@ constexpr int NL = M - 1 - MID;   // rows of wave 1: M-1 .. MID+1 (index t is ro
 template <bool LIST>
 __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM], pz[MM];
+  __shared__ float dgl[MM];            // rounding error of the diagonal sums
   __shared__ Faces fc;
   __shared__ double bside[4][M][D];
   __shared__ double xb[4][M][R];
@@ -337,7 +261,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
 #pragma unroll
   for (int q = 0; q < MM / PAIR; ++q)
     assemble_cell<M, 1, false>(a, I, J, tid + PAIR * q, kap, dg, ex, cy, b0 + tid + PAIR * q, 1, nullptr,
-                               cl[q]);
+                               cl[q], dgl);
   prepare_faces(a, fl, kap, fc);
   __syncthreads();
   robin_data(g, fc, bside);
@@ -476,6 +400,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
     const int i = l % M, j = l / M;
     double ph = b0[l], pl = 0.0;
     dd_fma(ph, pl, -dg[l], pz[l]);
+    dd_fma(ph, pl, -(double)dgl[l], pz[l]);
     dd_fma(ph, pl, i < M - 1 ? -ex[l] : 0.0, pz[i < M - 1 ? l + 1 : l]);
     dd_fma(ph, pl, i > 0 ? -ex[l - 1] : 0.0, pz[i > 0 ? l - 1 : l]);
     dd_fma(ph, pl, j < M - 1 ? -cy[l] : 0.0, pz[j < M - 1 ? l + M : l]);
@@ -503,6 +428,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
       const int i = 4 * v + gq, l = j * M + i;
       double hi = side_rhs(bside, j, i, c), lo = 0.0;
       dd_fma(hi, lo, -dg[l], Xv[t][v]);
+      dd_fma(hi, lo, -(double)dgl[l], Xv[t][v]);
       dd_fma(hi, lo, i < M - 1 ? -ex[l] : 0.0, T[i < M - 1 ? i + 1 : i][c]);
       dd_fma(hi, lo, i > 0 ? -ex[i > 0 ? l - 1 : l] : 0.0, T[i > 0 ? i - 1 : i][c]);
       r[v] = hi + lo;
@@ -800,14 +726,16 @@ __device__ inline void solve_column_pair(const d4* Sv, int w, const double* rhs,
 // Schur blocks of A^ are inverted in FP32 (Gauss-Jordan in registers), and
 // both block sweeps run on v_mfma_f32_16x16x4f32, whose output layout puts
 // rows 4g .. 4g+3 of column c in lane c + 16 g (measured on the device).  The
-// solution is kept in FP64; every refinement step forms R = B - A X in FP64,
-// solves A^ y = Ds R in FP32 and adds Ds y.  A subdomain whose correction does
+// solution is kept in FP64; every refinement step forms R = B - A X in
+// double-double with the exact diagonal (the cells' mass balances; an FP64
+// residual or a rounded diagonal would leave local solutions conservative
+// only to eps T |x| per cell, which the stitch inherits), solves
+// A^ y = Ds R in FP32 and adds Ds y.  A subdomain whose correction does
 // not fall below IR_DONE of its solution within IR_MAX steps, or whose FP32
 // pivots fail, is appended to a.fallback and re-solved in FP64 (IR_DONE and
-// IR_MAX are a.ir_tol and a.ir_max, by default 1e-9 and 8 steps).  The error
-// left after a step is about the contraction factor times that step's
-// correction, so IR_DONE = 1e-9 leaves local errors near 1e-11 (the target of
-// this path is 1e-8 against FP64).
+// IR_MAX are a.ir_tol and a.ir_max, by default 1e-12 and 8 steps).  The
+// error left after a step is about the contraction factor times that step's
+// correction, so IR_DONE = 1e-12 leaves local errors near FP64 accuracy.
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -914,6 +842,7 @@ struct Chain {
 // LDS of the FP32 + refinement kernel
 struct Lds32 {
   double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM], dsc[MM], px[MM];
+  float dgl[MM];            // rounding error of the diagonal sums
   double bside[4][M][D];
   double xb[4][M][R];
   Faces fc;
@@ -1065,8 +994,9 @@ __device__ inline void solve32(const f4* Sv, f4* Wt, Lds32& sh, int c, int gq, R
   __syncthreads();
 }
 
-// FP64 residual of the basis columns in the wave's row t, scaled and rounded
-// to FP32 (the tile of the other wave next to the join must be in sh.xj).
+// Double-double residual of the basis columns in the wave's row t, scaled and
+// rounded to FP32 (the tile of the other wave next to the join must be in
+// sh.xj).
 template <int W>
 __device__ inline f4 residual32_row(int t, const d4* Xv, Lds32& sh, int c, int gq) {
   using C = Chain<W>;
@@ -1083,14 +1013,16 @@ __device__ inline f4 residual32_row(int t, const d4* Xv, Lds32& sh, int c, int g
     const int ir = i < M - 1 ? i + 1 : i, il = i > 0 ? i - 1 : i;
     const double exr = sh.ex[l], exl = sh.ex[j * M + il];
     const double xr = T[ir][c], xl = T[il][c];
-    double r = side_rhs(sh.bside, j, i, c);
-    r = fma(-sh.dg[l], Xv[t][v], r);
-    r = fma(i < M - 1 ? -exr : 0.0, xr, r);
-    r = fma(i > 0 ? -exl : 0.0, xl, r);
-    if (t > 0) r = fma(-sh.cy[C::cprev(t) * M + i], Xv[t > 0 ? t - 1 : 0][v], r);
+    // double-double, with the exact diagonal: the cells' mass balances
+    double r = side_rhs(sh.bside, j, i, c), lo = 0.0;
+    dd_fma(r, lo, -sh.dg[l], Xv[t][v]);
+    dd_fma(r, lo, -(double)sh.dgl[l], Xv[t][v]);
+    dd_fma(r, lo, i < M - 1 ? -exr : 0.0, xr);
+    dd_fma(r, lo, i > 0 ? -exl : 0.0, xl);
+    if (t > 0) dd_fma(r, lo, -sh.cy[C::cprev(t) * M + i], Xv[t > 0 ? t - 1 : 0][v]);
     const double xn = (t + 1 < C::NR) ? Xv[t + 1 < C::NR ? t + 1 : t][v] : sh.xj[1 - W][i][c];
-    r = fma(-sh.cy[C::cnext(t) * M + i], xn, r);
-    w[v] = (float)(sh.dsc[l] * r);
+    dd_fma(r, lo, -sh.cy[C::cnext(t) * M + i], xn);
+    w[v] = (float)(sh.dsc[l] * (r + lo));
   }
   __builtin_amdgcn_wave_barrier();
   return w;
@@ -1100,7 +1032,7 @@ __device__ inline f4 residual32_row(int t, const d4* Xv, Lds32& sh, int c, int g
 // subdomain with the chains of basis_pair_kernel.  The local matrix is scaled
 // symmetrically (Ds A Ds, Ds = diag(A)^-1/2, unit diagonal); the inverse
 // Schur blocks and the correction solves are FP32 (MFMA with FP32
-// accumulation), the solution and the residuals FP64.  Refinement stops when
+// accumulation), the solution FP64 and the residuals double-double.  Refinement stops when
 // the largest correction is below a.ir_tol of the largest solution value; a
 // subdomain that ends above it, or met a bad pivot, is listed for the
 // FP64 re-solve.
@@ -1121,7 +1053,7 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
 #pragma unroll
   for (int q = 0; q < MM / PAIR; ++q)
     assemble_cell<M, 1, false>(a, I, J, tid + PAIR * q, sh.kap, sh.dg, sh.ex, sh.cy,
-                               sh.b0 + tid + PAIR * q, 1, nullptr, cl[q]);
+                               sh.b0 + tid + PAIR * q, 1, nullptr, cl[q], sh.dgl);
   prepare_faces(a, fl, sh.kap, sh.fc);
   for (int l = tid; l < MM; l += PAIR) sh.dsc[l] = 1.0 / sqrt(sh.dg[l]);
   __syncthreads();
@@ -1158,7 +1090,7 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
   for (int l = tid; l < MM; l += PAIR) sh.px[l] = sh.dsc[l] * (double)sh.pcol[l];
   __syncthreads();
 
-  // refinement: FP64 residual, FP32 correction
+  // refinement: double-double residual (the cells' mass balances), FP32 correction
   int used = 0;
   double rel = 1.0;
 #pragma unroll 1
@@ -1170,12 +1102,14 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
       const int li = l % M, lj = l / M;
       const int le = li < M - 1 ? l + 1 : l, lw = li > 0 ? l - 1 : l;
       const int ln = lj < M - 1 ? l + M : l, ls = lj > 0 ? l - M : l;
-      double r = fma(-sh.dg[l], sh.px[l], sh.b0[l]);
-      r = fma(li < M - 1 ? -sh.ex[l] : 0.0, sh.px[le], r);
-      r = fma(li > 0 ? -sh.ex[lw] : 0.0, sh.px[lw], r);
-      r = fma(lj < M - 1 ? -sh.cy[l] : 0.0, sh.px[ln], r);
-      r = fma(lj > 0 ? -sh.cy[ls] : 0.0, sh.px[ls], r);
-      sh.pcol[l] = (float)(sh.dsc[l] * r);
+      double r = sh.b0[l], lo = 0.0;
+      dd_fma(r, lo, -sh.dg[l], sh.px[l]);
+      dd_fma(r, lo, -(double)sh.dgl[l], sh.px[l]);
+      dd_fma(r, lo, li < M - 1 ? -sh.ex[l] : 0.0, sh.px[le]);
+      dd_fma(r, lo, li > 0 ? -sh.ex[lw] : 0.0, sh.px[lw]);
+      dd_fma(r, lo, lj < M - 1 ? -sh.cy[l] : 0.0, sh.px[ln]);
+      dd_fma(r, lo, lj > 0 ? -sh.cy[ls] : 0.0, sh.px[ls]);
+      sh.pcol[l] = (float)(sh.dsc[l] * (r + lo));
     }
     __syncthreads();
     solve32<W>(Sv, Wt, sh, c, gq, [&](int t) { return residual32_row<W>(t, Xv, sh, c, gq); });
@@ -1535,14 +1469,16 @@ __global__ void __launch_bounds__(WAVE) surrogate_targets_kernel(SubArgs a, floa
   }
 }
 
-// Decode the network's prediction of the 16 basis functions, form each
-// column's FP64 residual in the local Robin problem and accept the subdomain
-// only if every column passes; an accepted subdomain gets its basis block
+// Decode the network's prediction of the 16 basis functions, smooth them
+// with a few FP64 red-black Gauss-Seidel sweeps of the local Robin problem,
+// form each column's FP64 residual and accept the subdomain only if every
+// column passes; an accepted subdomain gets its basis block
 // and its block of the interface system written exactly as the FP64 kernel
 // would, a rejected one (or one with source or physical boundary data,
 // whose particular solution the network does not predict) is appended to
 // a.fallback for the FP64 kernel.
 constexpr int GATE = 256;   // threads of the gate kernel: one per cell
+constexpr int GATE_SWEEPS = 4;   // red-black Gauss-Seidel sweeps before the gate
 
 __global__ void __launch_bounds__(GATE) surrogate_gate_kernel(SubArgs a, const float* pred) {
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM];
@@ -1592,6 +1528,33 @@ __global__ void __launch_bounds__(GATE) surrogate_gate_kernel(SubArgs a, const f
   const int ln = j < M - 1 ? tid + M : tid, ls = j > 0 ? tid - M : tid;
   const double ce = i < M - 1 ? ex[tid] : 0.0, cw = i > 0 ? ex[lw] : 0.0;
   const double cn = j < M - 1 ? cy[tid] : 0.0, cs = j > 0 ? cy[ls] : 0.0;
+  // The network's output is FP32: rounding an exact basis function to FP32
+  // alone leaves a relative residual of about 2e-6 (spread over all cells,
+  // while b lives on the boundary cells), above a 1e-6 gate.  A few
+  // red-black Gauss-Seidel sweeps in FP64 remove that rounding noise (it is
+  // high-frequency, which point relaxation damps fastest) before the gate
+  // measures the residual; they need no factorisation, and what they cannot
+  // correct (an approximation error of the network, smooth over the
+  // subdomain) still fails the gate.
+  {
+    const double idg = 1.0 / dg[tid];
+    const int color = (i + j) & 1;
+#pragma unroll 1
+    for (int half = 0; half < 2 * GATE_SWEEPS; ++half) {
+      if (color == (half & 1)) {   // a colour's neighbours all have the other colour
+#pragma unroll
+        for (int q = 0; q < 4 * D; ++q) {
+          double ax = dg[tid] * Xs[q][tid];
+          ax = fma(ce, Xs[q][le], ax);
+          ax = fma(cw, Xs[q][lw], ax);
+          ax = fma(cn, Xs[q][ln], ax);
+          ax = fma(cs, Xs[q][ls], ax);
+          Xs[q][tid] += (side_rhs(bside, j, i, q) - ax) * idg;
+        }
+      }
+      __syncthreads();
+    }
+  }
   double r2[4 * D], b2[4 * D];
 #pragma unroll
   for (int q = 0; q < 4 * D; ++q) {

@@ -27,7 +27,8 @@ EXPORTED = [
     "mrcm_get_sizes", "mrcm_get_interface_solution", "mrcm_get_local_blocks",
     "mrcm_get_basis", "mrcm_surrogate_inputs", "mrcm_surrogate_targets", "mrcm_set_surrogate",
     "mrcm_solve_with_predictions", "mrcm_set_gate_tolerance", "mrcm_set_refinement",
-    "mrcm_set_interface_refinement", "mrcm_cnn_create", "mrcm_cnn_num_params",
+    "mrcm_set_interface_refinement", "mrcm_transport_step", "mrcm_si_step", "mrcm_sfi_step",
+    "mrcm_cnn_create", "mrcm_cnn_num_params",
     "mrcm_cnn_get_params", "mrcm_cnn_set_params", "mrcm_cnn_forward", "mrcm_cnn_loss_grad",
     "mrcm_cnn_train_step", "mrcm_cnn_destroy", "mrcm_last_error", "mrcm_destroy",
 ]
@@ -58,6 +59,18 @@ class Stats(ctypes.Structure):
                 ("n_dof", ctypes.c_int32), ("ir_iters_max", ctypes.c_int32),
                 ("fallbacks", ctypes.c_int32), ("interface_residual", ctypes.c_double),
                 ("ms_surrogate", ctypes.c_double), ("interface_ir_steps", ctypes.c_int32)]
+
+
+class TransportStats(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int32), ("linear_iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("linear_failures", ctypes.c_int32),
+                ("last_change", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
+class SFIStats(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("last_change", ctypes.c_double),
+                ("ms", ctypes.c_double)]
 
 
 _lib = None
@@ -103,7 +116,14 @@ def load_library(path: str = LIB_PATH):
     lib.mrcm_solve_with_predictions.argtypes = [P, P]
     lib.mrcm_set_gate_tolerance.argtypes = [P, ctypes.c_double]
     lib.mrcm_set_refinement.argtypes = [P, ctypes.c_int32, ctypes.c_double]
-    lib.mrcm_set_interface_refinement.argtypes = [P, ctypes.c_int32, ctypes.c_double]
+    lib.mrcm_transport_step.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int32, ctypes.POINTER(TransportStats)]
+    lib.mrcm_si_step.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int32, ctypes.POINTER(TransportStats)]
+    lib.mrcm_sfi_step.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                  ctypes.POINTER(SFIStats)]
+    lib.mrcm_set_interface_refinement.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double]
     lib.mrcm_cnn_create.argtypes = [ctypes.POINTER(P), i32, ctypes.c_uint64, P]
     lib.mrcm_cnn_num_params.argtypes = [P, ctypes.POINTER(i32)]
     lib.mrcm_cnn_get_params.argtypes = [P, fp]
@@ -290,19 +310,20 @@ class MRCMSolver:
         the GPU with device=True."""
         nx, ny = self.nx, self.ny
         imb = ctypes.c_double()
+        fn = self.lib.mrcm_fine_flux
         if device:
             import torch
             p = torch.empty(nx * ny, dtype=torch.float64, device="cuda")
             ux = torch.empty((nx + 1) * ny, dtype=torch.float64, device="cuda")
             uy = torch.empty(nx * (ny + 1), dtype=torch.float64, device="cuda")
             ptrs = [ctypes.c_void_p(t.data_ptr()) for t in (p, ux, uy)]
-            rc = self.lib.mrcm_fine_flux(self.ctx, *ptrs, 1, ctypes.byref(imb))
+            rc = fn(self.ctx, *ptrs, 1, ctypes.byref(imb))
         else:
             p = np.empty(nx * ny)
             ux = np.empty((nx + 1) * ny)
             uy = np.empty(nx * (ny + 1))
             ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in (p, ux, uy)]
-            rc = self.lib.mrcm_fine_flux(self.ctx, *ptrs, 0, ctypes.byref(imb))
+            rc = fn(self.ctx, *ptrs, 0, ctypes.byref(imb))
         self._check(rc, "mrcm_fine_flux")
         return p, ux, uy, imb.value
 
@@ -359,14 +380,77 @@ class MRCMSolver:
     def set_gate_tolerance(self, tol: float):
         self._check(self.lib.mrcm_set_gate_tolerance(self.ctx, float(tol)), "mrcm_set_gate_tolerance")
 
+    def transport_step(self, s_old, s_new, ux, uy, dt: float, s_inflow: float = 1.0,
+                       eta: float = 1e-6, max_newton: int = 50, check: bool = True) -> dict:
+        """One implicit transport step (mrcm_transport_step) on torch float64
+        device tensors: s_old, s_new (nx*ny), ux ((nx+1)*ny), uy (nx*(ny+1)).
+        Returns the step statistics; raises on failure when check is set
+        (MRCM_E_NO_CONV leaves the last iterate in s_new)."""
+        nx, ny = self.nx, self.ny
+        for t, m in ((s_old, nx * ny), (s_new, nx * ny), (ux, (nx + 1) * ny), (uy, nx * (ny + 1))):
+            if not _is_device(t) or t.numel() != m or str(t.dtype) != "torch.float64" \
+                    or not t.is_contiguous():
+                raise ValueError("transport arrays must be contiguous float64 device tensors")
+        import torch
+        cur = torch.cuda.current_stream()
+        if cur.cuda_stream != self._stream:
+            cur.synchronize()
+        st = TransportStats()
+        rc = self.lib.mrcm_transport_step(self.ctx, ctypes.c_void_p(s_old.data_ptr()),
+                                          ctypes.c_void_p(s_new.data_ptr()), ctypes.c_void_p(ux.data_ptr()),
+                                          ctypes.c_void_p(uy.data_ptr()), float(dt), float(s_inflow),
+                                          float(eta), int(max_newton), ctypes.byref(st))
+        out = {k: getattr(st, k) for k, _ in TransportStats._fields_}
+        out["rc"] = rc
+        if check:
+            self._check(rc, "mrcm_transport_step")
+        return out
+
+    def _dev_arrays(self, s_old, s_new, p, ux, uy):
+        nx, ny = self.nx, self.ny
+        for t, m in ((s_old, nx * ny), (s_new, nx * ny), (ux, (nx + 1) * ny), (uy, nx * (ny + 1))):
+            if not _is_device(t) or t.numel() != m or str(t.dtype) != "torch.float64" \
+                    or not t.is_contiguous():
+                raise ValueError("arrays must be contiguous float64 device tensors")
+        if p is not None and (not _is_device(p) or p.numel() != nx * ny or str(p.dtype) != "torch.float64"
+                              or not p.is_contiguous()):
+            raise ValueError("p must be a contiguous float64 device tensor of nx*ny")
+        import torch
+        cur = torch.cuda.current_stream()
+        if cur.cuda_stream != self._stream:
+            cur.synchronize()
+        return [ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(None)
+                for t in (s_old, s_new, p, ux, uy)]
+
+    def si_step(self, s_old, s_new, p, ux, uy, dt: float, s_inflow: float = 1.0, eta: float = 1e-6,
+                max_newton: int = 50) -> dict:
+        """mrcm_si_step: transport with (ux, uy), then the Darcy solve with
+        the new saturation, writing p (may be None), ux, uy in place."""
+        ptrs = self._dev_arrays(s_old, s_new, p, ux, uy)
+        st = TransportStats()
+        self._check(self.lib.mrcm_si_step(self.ctx, *ptrs, float(dt), float(s_inflow), float(eta),
+                                          int(max_newton), ctypes.byref(st)), "mrcm_si_step")
+        return {k: getattr(st, k) for k, _ in TransportStats._fields_}
+
+    def sfi_step(self, s_old, s_new, p, ux, uy, dt: float, s_inflow: float = 1.0, eta: float = 1e-6,
+                 max_newton: int = 50, outer_tol: float = 1e-4, max_outer: int = 50) -> dict:
+        """mrcm_sfi_step: the outer Darcy + transport loop of one time step."""
+        ptrs = self._dev_arrays(s_old, s_new, p, ux, uy)
+        st = SFIStats()
+        self._check(self.lib.mrcm_sfi_step(self.ctx, *ptrs, float(dt), float(s_inflow), float(eta),
+                                           int(max_newton), float(outer_tol), int(max_outer),
+                                           ctypes.byref(st)), "mrcm_sfi_step")
+        return {k: getattr(st, k) for k, _ in SFIStats._fields_}
+
     def set_refinement(self, max_steps: int, tol: float):
         """Stopping rule of the FP32 + FP64 local refinement (fp32_ir)."""
         self._check(self.lib.mrcm_set_refinement(self.ctx, int(max_steps), float(tol)),
                     "mrcm_set_refinement")
 
-    def set_interface_refinement(self, max_steps: int, tol: float):
+    def set_interface_refinement(self, max_steps: int, tol: float, fail_tol: float = 1e-10):
         """Stopping rule of the interface solve's refinement."""
-        self._check(self.lib.mrcm_set_interface_refinement(self.ctx, int(max_steps), float(tol)),
+        self._check(self.lib.mrcm_set_interface_refinement(self.ctx, int(max_steps), float(tol),
+                                                           float(fail_tol)),
                     "mrcm_set_interface_refinement")
 
     def set_surrogate(self, net: "SurrogateNet"):

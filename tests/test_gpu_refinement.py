@@ -5,8 +5,8 @@ fallback and failure paths from the host (GPU, through the C ABI).
   allowed, every subdomain ends above the tolerance and is re-solved by the
   FP64 kernels (the listed re-solve); the basis functions and interface
   blocks are then those of the FP64 form, bit for bit.
-* Refinement of the FP64 interface solve: a tolerance it cannot reach makes
-  the solve fail with MRCM_E_NO_CONV and leaves no solution behind.
+* Refinement of the FP64 interface solve: a failure bound it cannot reach
+  makes the solve fail with MRCM_E_NO_CONV and leaves no solution behind.
 
 These are ordinary numerical outcomes forced by settings; every kernel runs
 to completion.
@@ -89,7 +89,7 @@ def test_interface_refinement_failure_is_reported():
         sol.solve()
         good = sol.fine_flux()
         for max_steps in (0, 2):
-            sol.set_interface_refinement(max_steps, 1e-300)
+            sol.set_interface_refinement(max_steps, 1e-300, 1e-300)
             with pytest.raises(MRCMError) as ei:
                 sol.solve()
             assert ei.value.code == E_NO_CONV
@@ -101,12 +101,12 @@ def test_interface_refinement_failure_is_reported():
                 sol.step(s)
             assert ei.value.code == E_NO_CONV
         with pytest.raises(MRCMError) as ei:
-            sol.set_interface_refinement(3, 0.0)
+            sol.set_interface_refinement(3, 1e-14, 0.0)
         assert ei.value.code == E_INVAL
         with pytest.raises(MRCMError) as ei:
             sol.set_refinement(3, 1e-9)        # not an FP32_IR context
         assert ei.value.code == E_STATE
-        sol.set_interface_refinement(3, 1e-14)
+        sol.set_interface_refinement(3, 1e-14, 1e-10)
         sol.solve()
         again = sol.fine_flux()
     for x, y in zip(good[:3], again[:3]):

@@ -227,36 +227,35 @@ def test_gate_rejects_random_network_and_equals_fp64():
 
 
 def test_gate_accepts_exact_predictions():
-    """FP32 copies of the FP64 basis functions pass a gate above their
-    rounding floor; only subdomains with particular data fall back.  The
-    result then carries the FP32 rounding of the basis functions, and the
-    cell balance holds to the accepted residual, not to FP64 rounding."""
+    """FP32 copies of the FP64 basis functions (the network's output form)
+    pass the default 1e-6 gate once the gate's FP64 relaxation sweeps have
+    removed their rounding noise; only subdomains with particular data fall
+    back.  The result carries the accepted residual (about 1e-7), and the
+    cell balance holds to it, not to FP64 rounding."""
     say("case: gate with exact FP32 predictions (gauss64)")
     torch = _torch()
     prob, s, lam = _prob_and_lam()
     b = _run(prob, s, "fp64")
     pred = b["targets"]
     part = _particular_subdomains(prob)
-    a = _run(prob, s, "surrogate", pred=pred, tol=1e-4)
-    st = a["stats"]
-    ep, ef = rel(a["p"], b["p"]), rel(a["f"], b["f"])
-    say("  tol 1e-4: fallbacks %d (particular data: %d) of %d; vs FP64: p %.2e flux %.2e imbalance %.2e"
-        % (st["fallbacks"], len(part), st["n_sub"], ep, ef, a["imb"]))
-    assert st["fallbacks"] == len(part)
-    assert ep < 1e-5 and ef < 1e-5
-    # an accepted subdomain's local mass balance holds only up to its
-    # residual, so the stitch's cell imbalance sits at the gate level (it
-    # collects in the pinned cell of each floating subdomain)
-    assert a["imb"] < 1e-4
-    # at the default 1e-6 the FP32 rounding floor decides: report the count
-    c = _run(prob, s, "surrogate", pred=pred)
-    say("  tol 1e-6: fallbacks %d of %d" % (c["stats"]["fallbacks"], c["stats"]["n_sub"]))
-    assert c["stats"]["fallbacks"] >= len(part)
-    assert rel(c["p"], b["p"]) < 1e-5
-    # predictions off by 1e-3 relative are rejected everywhere
-    noisy = pred * (1.0 + 1e-3 * torch.randn(pred.shape, device=pred.device,
-                                             generator=torch.Generator(device=pred.device).manual_seed(1)))
-    d = _run(prob, s, "surrogate", pred=noisy.contiguous(), tol=1e-4)
+    for tol in (1e-6, 1e-4):
+        a = _run(prob, s, "surrogate", pred=pred, tol=tol)
+        st = a["stats"]
+        ep, ef = rel(a["p"], b["p"]), rel(a["f"], b["f"])
+        say("  tol %.0e: fallbacks %d (particular data: %d) of %d; vs FP64: p %.2e flux %.2e "
+            "imbalance %.2e" % (tol, st["fallbacks"], len(part), st["n_sub"], ep, ef, a["imb"]))
+        assert st["fallbacks"] == len(part)
+        assert ep < 1e-6 and ef < 1e-6
+        # an accepted subdomain's local mass balance holds only up to its
+        # residual; the stitch spreads that defect over the subdomain's cells
+        assert a["imb"] < 1e-6
+    # predictions with a smooth relative error of 1e-3 (the kind of error a
+    # network makes, which relaxation does not remove) fail everywhere
+    n, cells = pred.shape[0], pred.shape[1]
+    ramp = torch.linspace(-1.0, 1.0, cells, device=pred.device, dtype=pred.dtype)[None, :, None]
+    off = (pred * (1.0 + 1e-3 * ramp)).contiguous()
+    d = _run(prob, s, "surrogate", pred=off, tol=1e-4)
+    say("  smooth 1e-3 error at tol 1e-4: fallbacks %d of %d" % (d["stats"]["fallbacks"], n))
     assert d["stats"]["fallbacks"] == d["stats"]["n_sub"]
     assert np.array_equal(d["p"], b["p"])
 
@@ -285,18 +284,31 @@ def test_training_on_method_patches_and_gain():
     say("  held-out mse %.4e -> %.4e (train batch loss %.4e -> %.4e)"
         % (e0, e1, losses[0], losses[-1]))
     assert e1 < 0.5 * e0
-    # gain on an unseen field
+    # gain on an unseen field, at the 1e-6 gate and at looser gates
     tprob = inputs.make_problem("gauss1024", seed=999, nx=256, ny=256, lx=0.25, ly=0.25)
     ts = inputs.synthetic_saturation(tprob, 1, 4)
     ref = _run(tprob, ts, "fp64")
-    sur = _run(tprob, ts, "surrogate", net=net)
-    st0, st1 = ref["stats"], sur["stats"]
-    t0 = st0["ms_local"] + st0["ms_interface"]
-    t1 = st1["ms_local"] + st1["ms_interface"]
-    say("  gain: FP64 solve %.3f ms, surrogate solve %.3f ms (inference+gate %.3f ms), "
-        "fallbacks %d of %d (%.1f%%), gain %+.3f ms; error vs FP64: p %.2e flux %.2e"
-        % (t0, t1, st1["ms_surrogate"], st1["fallbacks"], st1["n_sub"],
-           100.0 * st1["fallbacks"] / st1["n_sub"], t0 - t1, rel(sur["p"], ref["p"]),
-           rel(sur["f"], ref["f"])))
-    assert rel(sur["p"], ref["p"]) < 1e-5
+    t0 = ref["stats"]["ms_local"] + ref["stats"]["ms_interface"]
+    prev = None
+    for tol in (1e-6, 1e-3, 1e-1):
+        sur = _run(tprob, ts, "surrogate", net=net, tol=tol)
+        st1 = sur["stats"]
+        t1 = st1["ms_local"] + st1["ms_interface"]
+        rate = st1["fallbacks"] / st1["n_sub"]
+        ep, ef = rel(sur["p"], ref["p"]), rel(sur["f"], ref["f"])
+        say("  gate %.0e: FP64 solve %.3f ms, surrogate solve %.3f ms (inference+gate %.3f ms), "
+            "fallbacks %d of %d (%.1f%%), gain %+.3f ms; error vs FP64: p %.2e flux %.2e"
+            % (tol, t0, t1, st1["ms_surrogate"], st1["fallbacks"], st1["n_sub"], 100.0 * rate,
+               t0 - t1, ep, ef))
+        # a looser gate accepts at least what a tighter one did
+        if prev is not None:
+            assert st1["fallbacks"] <= prev
+        prev = st1["fallbacks"]
+        if st1["fallbacks"] == st1["n_sub"]:
+            # nothing accepted: the FP64 result, bit for bit, reached with
+            # strictly more work (inference and gate before the same solve)
+            assert np.array_equal(sur["p"], ref["p"])
+            assert t1 > t0
+        if tol == 1e-6:
+            assert ep < 1e-5
     net.close()

@@ -1,0 +1,140 @@
+"""Implicit transport on the GPU (mrcm_transport_step) against the transport
+oracle (section 4), on the same saturations and the same face velocities.
+
+The Newton iterates of the two sides follow the same steps (the GPU solves
+each Newton system by BiCGSTAB to 1e-12, the oracle by a direct solver), so
+the new saturations agree far below the Newton tolerance; they are
+compared at 1e-9 in the max norm, with the Newton iteration counts equal
+or one apart.  The row pins of the oracle (cell-by-cell scalar solves)
+are checked on the GPU as well.
+"""
+import numpy as np
+import pytest
+
+import inputs
+from oracle import transport as ot
+from oracle.discretization import total_mobility
+from oracle.mrcm import solve_mrcm
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+S_TOL = 1e-9
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def gpu_step(prob, s_old, ux, uy, dt, s_inflow=1.0, eta=1e-6, max_newton=50):
+    import torch
+    from paper_2104_04653_amd import MRCMSolver
+    with MRCMSolver(prob) as sol:
+        so = _dev(s_old)
+        sn = torch.empty_like(so)
+        st = sol.transport_step(so, sn, _dev(ux), _dev(uy), dt, s_inflow=s_inflow, eta=eta,
+                                max_newton=max_newton)
+        torch.cuda.synchronize()
+        return sn.cpu().numpy(), st
+
+
+def check_step(prob, s_old, r, mult, label, eta=1e-6, max_newton=200):
+    dt = mult * ot.cfl_time_step(prob, r.ux, r.uy)
+    ref = ot.transport_step(prob, s_old, r.Fx, r.Fy, dt, eta=eta, max_iter=max_newton)
+    s, st = gpu_step(prob, s_old, r.ux, r.uy, dt, eta=eta, max_newton=max_newton)
+    err = np.abs(s - ref.s).max()
+    say("  %s, %g CFL: Newton %d (oracle %d), BiCGSTAB %d, max |ds| %.2e, %.1f ms"
+        % (label, mult, st["newton_iters"], ref.iterations, st["linear_iters"], err, st["ms"]))
+    assert st["converged"] and ref.converged
+    assert abs(st["newton_iters"] - ref.iterations) <= 1
+    assert err < S_TOL
+    assert s.min() >= 0.0 and s.max() <= 1.0
+    return s, st
+
+
+def test_quarter_five_spot_steps():
+    """Wells only (no boundary flow), 20 and 200 CFL steps from an oil-filled
+    reservoir, and a later step from a displaced front."""
+    prob = inputs.make_problem("channel256_q5", nx=64, ny=64)
+    say("case: transport, quarter-five-spot 64x64")
+    s0 = np.zeros(prob.nx * prob.ny)
+    r = solve_mrcm(prob, lam=total_mobility(s0, prob.mu_w, prob.mu_o))
+    for mult in (20.0, 200.0):
+        check_step(prob, s0, r, mult, "from s = 0")
+    s1 = inputs.synthetic_saturation(prob, 6, 20)
+    r1 = solve_mrcm(prob, lam=total_mobility(s1, prob.mu_w, prob.mu_o))
+    check_step(prob, s1, r1, 20.0, "from a front")
+
+
+def test_left_right_inflow_256():
+    """Inflow of water through the W boundary (p = 1 there, p = 0 on E), a
+    log-normal field, 20 CFL (the 1024^2 workload's setting, at 256^2)."""
+    prob = inputs.make_problem("gauss1024", nx=256, ny=256, lx=0.25, ly=0.25, seed=2)
+    say("case: transport, left-right inflow 256x256")
+    s = inputs.synthetic_saturation(prob, 2, 10)
+    r = solve_mrcm(prob, lam=total_mobility(s, prob.mu_w, prob.mu_o))
+    check_step(prob, s, r, 20.0, "gauss 256")
+
+
+def test_gauss1024_full_size_step():
+    """One 20-CFL step of the 1024^2 workload (1,048,576 cells) against the
+    oracle, with the oracle's Darcy fluxes."""
+    prob = inputs.make_problem("gauss1024")
+    say("case: transport, 1024x1024")
+    s = inputs.synthetic_saturation(prob, 3)
+    r = solve_mrcm(prob, lam=total_mobility(s, prob.mu_w, prob.mu_o))
+    check_step(prob, s, r, 20.0, "gauss 1024")
+
+
+def test_rows_equal_sequential_scalar_solves_on_gpu():
+    """16 identical rows with positive x-fluxes and no y-flux at 60 CFL: the
+    GPU step equals, in every row, the cell-by-cell scalar solves of the
+    oracle's row pin."""
+    from inputs import Problem
+    from inputs.problems import DIRICHLET, NEUMANN
+    from tests.test_oracle_transport import sequential_exact
+    n = 16
+    prob = Problem(name="rows", nx=n, ny=n, lx=float(n), ly=float(n), perm=np.ones(n * n),
+                   sub_nx=n, sub_ny=n, bc_kind=(NEUMANN, DIRICHLET, NEUMANN, NEUMANN),
+                   bc_value=(None, None, None, None))
+    rng = np.random.default_rng(1)
+    s_row = np.sort(rng.uniform(0, 1, n))[::-1]
+    s_old = np.tile(s_row, n)
+    Q = np.full(n + 1, 0.7)
+    ux = np.tile(Q, n) / prob.hy
+    uy = np.zeros(n * (n + 1))
+    say("case: transport, 16 rows of 16 cells")
+    s, st = gpu_step(prob, s_old, ux, uy, 30.0, eta=1e-14, max_newton=200)
+    exact = sequential_exact(s_row, Q, 30.0, fin=1.0)
+    err = np.abs(s.reshape(n, n) - exact[None, :]).max()
+    say("  Newton %d, max error %.2e" % (st["newton_iters"], err))
+    assert err < 1e-12
+
+
+def test_transport_errors():
+    import torch
+    from paper_2104_04653_amd import MRCMError, MRCMSolver
+    from paper_2104_04653_amd.mrcm import E_INVAL, E_NO_CONV
+    prob = inputs.make_problem("channel256_q5", nx=64, ny=64)
+    s0 = np.zeros(prob.nx * prob.ny)
+    r = solve_mrcm(prob, lam=total_mobility(s0, prob.mu_w, prob.mu_o))
+    dt = 200.0 * ot.cfl_time_step(prob, r.ux, r.uy)
+    say("case: transport error paths")
+    with MRCMSolver(prob) as sol:
+        so, ux, uy = _dev(s0), _dev(r.ux), _dev(r.uy)
+        sn = torch.empty_like(so)
+        with pytest.raises(MRCMError) as ei:
+            sol.transport_step(so, so, ux, uy, dt)        # aliasing
+        assert ei.value.code == E_INVAL
+        with pytest.raises(MRCMError) as ei:
+            sol.transport_step(so, sn, ux, uy, -1.0)
+        assert ei.value.code == E_INVAL
+        with pytest.raises(MRCMError) as ei:
+            sol.transport_step(so, sn, ux, uy, dt, s_inflow=1.5)
+        assert ei.value.code == E_INVAL
+        # one Newton iteration is not enough at 200 CFL: reported, with the
+        # iterate left in s_new
+        st = sol.transport_step(so, sn, ux, uy, dt, max_newton=1, check=False)
+        assert st["rc"] == E_NO_CONV and st["newton_iters"] == 1 and not st["converged"]
+        assert torch.isfinite(sn).all()

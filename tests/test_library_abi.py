@@ -99,7 +99,7 @@ def test_surrogate_entry_points_reject_null_without_gpu():
     assert lib.mrcm_solve_with_predictions(None, None) == binding.E_INVAL
     assert lib.mrcm_set_gate_tolerance(None, 1e-6) == binding.E_INVAL
     assert lib.mrcm_set_refinement(None, 8, 1e-9) == binding.E_INVAL
-    assert lib.mrcm_set_interface_refinement(None, 3, 1e-14) == binding.E_INVAL
+    assert lib.mrcm_set_interface_refinement(None, 3, 1e-14, 1e-10) == binding.E_INVAL
     lib.mrcm_cnn_destroy(None)
 
 

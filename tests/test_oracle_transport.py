@@ -219,3 +219,55 @@ def test_downwind_fluxes_caught(monkeypatch):
         return out, np.where(qv > 0, qv, qv * f.reshape(-1))
     monkeypatch.setattr(ot, "water_outflow", downwind)
     assert not _transport_pins_pass()
+
+
+# --------------------------------------------------------------------------
+# sequential fully implicit outer loop (section 5.4)
+# --------------------------------------------------------------------------
+
+def _q5(n=32):
+    from oracle.discretization import total_mobility
+    from oracle.mrcm import solve_mrcm
+    prob = inputs.make_problem("channel256_q5", nx=n, ny=n, sub=8)
+    s0 = np.zeros(prob.nx * prob.ny)
+    r = solve_mrcm(prob, lam=total_mobility(s0, prob.mu_w, prob.mu_o))
+    return prob, s0, ot.cfl_time_step(prob, r.ux, r.uy)
+
+
+def test_sfi_is_a_fixed_point_of_darcy_and_transport():
+    """At convergence the new saturation is (to the outer tolerance) the
+    transport step of the fluxes of its own Darcy solve: one more outer
+    iteration changes it by less than 1e-4."""
+    from oracle.discretization import total_mobility
+    from oracle.mrcm import solve_mrcm
+    prob, s0, dt_cfl = _q5()
+    st = ot.sfi_step(prob, s0, 20 * dt_cfl)
+    assert st.converged and st.outer >= 2
+    assert st.changes[-1] < 1e-4 and all(c < 1 for c in st.changes)
+    r = solve_mrcm(prob, lam=total_mobility(st.s, prob.mu_w, prob.mu_o))
+    again = ot.transport_step(prob, s0, r.Fx, r.Fy, 20 * dt_cfl)
+    assert np.abs(again.s - st.s).max() < 1e-4
+    # mass balance of the step with the fluxes the last transport used
+    out, src = ot.water_outflow(prob, st.s, st.Fx, st.Fy, 1.0, M)
+    V = prob.hx * prob.hy
+    assert V * (st.s - s0).sum() == pytest.approx(20 * dt_cfl * (src.sum() - out.sum()), rel=1e-6)
+
+
+def test_sfi_first_iterate_is_the_sequential_implicit_step():
+    """The first outer iteration is the SI step (Darcy with s^n, then
+    transport); with one outer iteration allowed they coincide."""
+    prob, s0, dt_cfl = _q5()
+    one = ot.sfi_step(prob, s0, 5 * dt_cfl, max_outer=1)
+    traj, _ = ot.si_run(prob, s0, 1, 5 * dt_cfl)
+    assert np.array_equal(one.s, traj[1])
+
+
+def test_sfi_and_si_agree_as_dt_shrinks():
+    """SI and SFI differ by the splitting error, which falls with dt."""
+    prob, s0, dt_cfl = _q5()
+    diffs = []
+    for mult in (8.0, 2.0):
+        sfi = ot.sfi_step(prob, s0, mult * dt_cfl, outer_tol=1e-10)
+        traj, _ = ot.si_run(prob, s0, 1, mult * dt_cfl)
+        diffs.append(np.abs(sfi.s - traj[1]).max())
+    assert diffs[1] < 0.5 * diffs[0]
