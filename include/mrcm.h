@@ -214,6 +214,19 @@ int mrcm_set_interface_refinement(mrcm_ctx* ctx, int32_t max_steps, double tol, 
 int mrcm_fine_flux(mrcm_ctx* ctx, double* p, double* ux, double* uy, int32_t on_device,
                    double* max_cell_imbalance);
 
+/* mrcm_fine_flux for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, outputs, synchronisation and errors, and it allocates
+ * nothing.  Its scratch (the stitch's per-subdomain statistics and their
+ * reduction, 3 doubles per subdomain) is a static device array of the
+ * library, one per GPU, held until the process ends, sized for at most
+ * 65536 subdomains (1.5 MB): larger contexts get MRCM_E_INVAL.  Every call on
+ * one GPU uses that GPU's array, so calls that overlap on one GPU (contexts
+ * on different streams or threads) race; the array keeps the last call's
+ * contents, and every value a call reads from it that call has written. */
+int mrcm_fine_flux_static(mrcm_ctx* ctx, double* p, double* ux, double* uy, int32_t on_device,
+                          double* max_cell_imbalance);
+
 /* One step of the pressure solve in one call: the mobility update, the
  * solve and the fine-scale reconstruction, with one synchronisation where
  * mrcm_update_mobility + mrcm_solve + mrcm_fine_flux take two or three.

@@ -12,12 +12,23 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
 #include <vector>
 
 using namespace mrcm;
+
+// Scratch of mrcm_fine_flux_static: the stitch's per-subdomain statistics
+// (max cell imbalance, max |F|, pressure sum: 3 doubles per subdomain) and
+// the two values they reduce to, in a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends) instead of
+// context memory.  Host code never passes the array's name to a kernel: its
+// device address is taken once per device with hipGetSymbolAddress.
+constexpr int STATIC_MAX_SUB = 65536;
+constexpr size_t STATIC_SCRATCH_DOUBLES = 3 * (size_t)STATIC_MAX_SUB + 2;
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_DOUBLES];
 
 namespace {
 
@@ -95,6 +106,7 @@ struct mrcm_ctx {
   // interface plan
   std::vector<LevelPlan> levels;
   long long leaf_block = 0;  // doubles per subdomain block
+  double* static_scratch = nullptr;       // this device's address of `scratch`
   // implicit transport: work arrays (set up with the context) and the
   // pinned mirror of its scalar block
   TransportArgs tr{};
@@ -138,6 +150,27 @@ int dev_alloc(mrcm_ctx* c, T** p, size_t count) {
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
+// device address of `scratch`, looked up once per device (with that device
+// current) and kept for the process
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+int bind_static_scratch(mrcm_ctx* c) {
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(c, MRCM_E_UNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(c, MRCM_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  c->static_scratch = g_scratch_ptr[dev];
+  return MRCM_OK;
+}
 
 // report block: doubles result[0] = max cell imbalance, [1] = pressure sum
 // (gauge shift), [2] = max |r|, [3] = max |b| of the interface residual,
@@ -784,6 +817,8 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
     HIPCHK(c, hipMemcpy(c->basis, bs.data(), bs.size() * sizeof(double), hipMemcpyHostToDevice));
     int r = build_plan(c);
     if (r != MRCM_OK) return r;
+    r = bind_static_scratch(c);
+    if (r != MRCM_OK) return r;
     HIPCHK(c, hipDeviceSynchronize());
     return MRCM_OK;
   };
@@ -924,10 +959,15 @@ int solve_impl(mrcm_ctx* c, const float* pred) {
 // The fine-scale reconstruction, enqueued: stitch and flux statistics, and
 // the copies of host outputs.  The stitch's pivot flag joins the solve's
 // status word (cleared by the solve).
-int flux_enqueue(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_device) {
+int flux_enqueue(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_device,
+                 double* sub_stats = nullptr, double* result = nullptr) {
   hipStream_t st = c->st;
   const Geo& G = c->g;
   SubArgs a = sub_args(c);
+  // per-subdomain statistics and their reduction: the context's buffers, or
+  // the static scratch (mrcm_fine_flux_static)
+  if (sub_stats) a.sub_stats = sub_stats;
+  if (!result) result = c->result;
   // device outputs are written by the kernels in place; host outputs are
   // copied from the context's buffers
   if (on_device) {
@@ -936,7 +976,7 @@ int flux_enqueue(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_devi
     if (uy) a.uy = uy;
   }
   HIPCHK(c, launch_stitch(a, st));
-  HIPCHK(c, launch_finish_flux(a, c->result, st));
+  HIPCHK(c, launch_finish_flux(a, result, st));
   const size_t ncell = (size_t)G.nx * G.ny;
   if (!on_device) {
     const hipMemcpyKind kind = hipMemcpyDeviceToHost;
@@ -982,6 +1022,28 @@ int mrcm_fine_flux(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_de
   int r = flux_enqueue(c, p, ux, uy, on_device);
   if (r != MRCM_OK) return r;
   HIPCHK(c, read_report(c));
+  return flux_finish(c, max_cell_imbalance);
+}
+
+int mrcm_fine_flux_static(mrcm_ctx* c, double* p, double* ux, double* uy, int32_t on_device,
+                          double* max_cell_imbalance) {
+  if (!c) return MRCM_E_INVAL;
+  if (!c->solved) return fail(c, MRCM_E_STATE, "fine_flux called before a successful solve");
+  if (c->g.n_sub > STATIC_MAX_SUB)
+    return fail(c, MRCM_E_INVAL, "mrcm_fine_flux_static: more than 65536 subdomains (its scratch "
+                                 "holds 3 doubles per subdomain for at most 65536)");
+  if (!c->static_scratch) return fail(c, MRCM_E_STATE, "static scratch not bound to this device");
+  double* sub_stats = c->static_scratch;
+  double* result = c->static_scratch + 3 * (size_t)STATIC_MAX_SUB;
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c->st, c->status);
+  HIPCHK(c, hipGetLastError());
+  int r = flux_enqueue(c, p, ux, uy, on_device, sub_stats, result);
+  if (r != MRCM_OK) return r;
+  // the report head (status word, phase stamps), then the two reduced
+  // values from the scratch over its first two slots
+  HIPCHK(c, hipMemcpyAsync(c->h_report, c->report, REPORT_HEAD, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->h_report, result, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
   return flux_finish(c, max_cell_imbalance);
 }
 

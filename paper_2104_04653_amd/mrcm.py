@@ -23,7 +23,8 @@ SPACES = {"linear": 0, "edge": 1, "full": 2}
 PRECISIONS = {"fp64": 0, "fp32_ir": 1, "surrogate": 2}
 
 EXPORTED = [
-    "mrcm_setup", "mrcm_update_mobility", "mrcm_solve", "mrcm_fine_flux", "mrcm_step", "mrcm_get_stats",
+    "mrcm_setup", "mrcm_update_mobility", "mrcm_solve", "mrcm_fine_flux", "mrcm_fine_flux_static",
+    "mrcm_step", "mrcm_get_stats",
     "mrcm_get_sizes", "mrcm_get_interface_solution", "mrcm_get_local_blocks",
     "mrcm_get_basis", "mrcm_surrogate_inputs", "mrcm_surrogate_targets", "mrcm_set_surrogate",
     "mrcm_solve_with_predictions", "mrcm_set_gate_tolerance", "mrcm_set_refinement",
@@ -101,6 +102,7 @@ def load_library(path: str = LIB_PATH):
     lib.mrcm_update_mobility.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32]
     lib.mrcm_solve.argtypes = [P]
     lib.mrcm_fine_flux.argtypes = [P, P, P, P, ctypes.c_int32, dp]
+    lib.mrcm_fine_flux_static.argtypes = [P, P, P, P, ctypes.c_int32, dp]
     lib.mrcm_step.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int32, dp]
     lib.mrcm_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.mrcm_get_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_int32),
@@ -305,12 +307,13 @@ class MRCMSolver:
         self._check(rc, "mrcm_step")
         return res + (imb.value,)
 
-    def fine_flux(self, device: bool = False):
+    def fine_flux(self, device: bool = False, static: bool = False):
         """Return (p, ux, uy, max_cell_imbalance); numpy, or torch tensors on
-        the GPU with device=True."""
+        the GPU with device=True.  static=True calls mrcm_fine_flux_static
+        (the same result, with the library's static scratch)."""
         nx, ny = self.nx, self.ny
         imb = ctypes.c_double()
-        fn = self.lib.mrcm_fine_flux
+        fn = self.lib.mrcm_fine_flux_static if static else self.lib.mrcm_fine_flux
         if device:
             import torch
             p = torch.empty(nx * ny, dtype=torch.float64, device="cuda")
