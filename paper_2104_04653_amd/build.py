@@ -14,7 +14,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrcm.so")
-SOURCES = ["api.hip", "local.hip", "local_mfma.hip", "interface.hip", "surrogate.hip", "transport.hip"]
+SOURCES = ["api.hip", "local.hip", "local_mfma.hip", "local_mfma32.hip", "interface.hip", "surrogate.hip",
+           "transport.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -216,62 +216,6 @@ struct LocalStore {
   static constexpr bool big = M > 16;
 };
 
-// Traces of every column (Xs: [cell][column], FP64) projected on the
-// interface functions: the subdomain's block of the interface system, rows
-// of flux dofs negated (the form in which the assembled interface matrix
-// is symmetric), last column = right-hand side.
-template <int M, int D>
-__device__ void generic_block(const SubArgs& a, int sd, int I, int J, const double* kap,
-                              const double* Xs) {
-  constexpr int R = 1 + 4 * D;
-  constexpr int NBR = 4 * D, NBC = 4 * D + 1;
-  const Geo& g = a.g;
-  double* blk = a.blocks + (size_t)sd * NBR * NBC;
-  const int nP = g.nP;
-  int e0side = -1;      // side holding global dof 0 (gauge), if any
-  bool e0lo = false;
-  if (g.gauge) {
-    for (int side = 0; side < 4; ++side)
-      if (side_iface(g, I, J, side) == 0) { e0side = side; e0lo = side_sigma(side) > 0; }
-  }
-  for (int o = threadIdx.x; o < NBR * NBC; o += NT) {
-    const int r = o / NBC, qc = o % NBC;
-    const int side = r / D, k = r % D;
-    const int e = side_iface(g, I, J, side);
-    double val = 0.0;
-    if (e >= 0) {
-      const int col = (qc < NBR) ? 1 + qc : 0;
-      const SideGeo sg = side_geo(g, side);
-      const double al = a.alpha[e];
-      const double sig = side_sigma(side);
-      const double* bs = a.basis + (size_t)e * D * M;
-      const bool colside = col >= 1 + side * D && col < 1 + side * D + D;
-      const int kc = col - 1 - side * D;
-      double sum = 0.0;
-      for (int t = 0; t < M; ++t) {
-        const int l = side_cell<M>(side, t);
-        const double kk = kap[l];
-        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
-        const double beta = al * sg.H / kk;
-        double gv = 0.0;
-        if (colside) gv = (kc < nP) ? bs[kc * M + t] : -beta * sig * bs[kc * M + t];
-        const double F = TR * (Xs[l * R + col] - gv);
-        if (k < nP) sum += bs[k * M + t] * F;
-        else sum += bs[k * M + t] * (gv + beta * F / sg.flen);
-      }
-      const double natural = (k < nP) ? sum : sig * sg.flen * sum;
-      const double sgn = (k < nP) ? 1.0 : -1.0;
-      val = (qc < NBR) ? sgn * natural : -sgn * natural;
-      if (e0side >= 0) {
-        const int r0 = e0side * D;   // local position of global dof 0
-        if (r == r0) val = (qc == r0 && e0lo) ? 1.0 : 0.0;
-        else if (qc == r0) val = 0.0;
-      }
-    }
-    blk[o] = val;
-  }
-}
-
 // FP64 local solves (LIST: only the subdomains on the fallback list of the
 // FP32 kernel below)
 template <int M, int D, bool LIST>
@@ -322,7 +266,7 @@ __global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
 
   double* Xg = a.X + (size_t)sd * MM * R;   // column-major per subdomain: [col][cell]
   for (int o = tid; o < MM * R; o += NT) Xg[(o % R) * MM + o / R] = Xs[o];
-  generic_block<M, D>(a, sd, I, J, kap, Xs);
+  generic_block<M, D>(a, sd, I, J, kap, Xs, R, 1);
 }
 
 // FP32 factorisation + double-double-residual refinement for the generic sizes with
@@ -424,7 +368,7 @@ __global__ void __launch_bounds__(NT) local_basis32_kernel(SubArgs a) {
 
   double* Xg = a.X + (size_t)sd * MM * R;   // column-major per subdomain: [col][cell]
   for (int o = tid; o < MM * R; o += NT) Xg[(o % R) * MM + o / R] = Xs[o];
-  generic_block<M, D>(a, sd, I, J, kap, Xs);
+  generic_block<M, D>(a, sd, I, J, kap, Xs, R, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -696,6 +640,16 @@ hipError_t dispatch(const SubArgs& a, hipStream_t st, bool stitch) {
     return launch_basis_m16d4(a, st);
   }
   if (M == 32 && D == 4) {
+    if (stitch && basis32x32_supported(a.g)) return launch_stitch32x32(a, st);
+    if (!stitch && basis32x32_supported(a.g)) {
+      if (a.g.prec == 1) {   // FP32 + refinement, then the FP64 re-solve of the listed ones
+        hipLaunchKernelGGL((local_basis32_kernel<32, 4>), dim3(a.g.n_sub), dim3(NT), 0, st, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_basis32x32(a, st, true);
+      }
+      return launch_basis32x32(a, st, false);
+    }
     if (!stitch && a.g.prec == 1) return launch_fp32<32, 4>(a, st);
     return launch_pair<32, 4>(a, st, stitch);
   }
@@ -721,6 +675,9 @@ bool local_supported(int M, int D) {
 long long local_scratch_doubles(const Geo& g) {
   const bool fast = g.M == 16 && g.D == 4 && g.nP == 2 && !g.generic;
   if (fast) return 0;
+  // the matrix-core kernels of 32 x 32 subdomains; the FP32 form runs the
+  // generic FP32 kernel first and needs its scratch
+  if (basis32x32_supported(g) && g.prec != 1) return basis32x32_scratch();
   const long long MM = (long long)g.M * g.M, R = 1 + 4 * g.D;
   return 2 * MM * R + (g.M > 16 ? MM * R + g.M * MM : 0);
 }

@@ -287,6 +287,63 @@ __device__ inline double stitch_balance_residual(const SubArgs& a, int I, int J,
   return hi + lo;
 }
 
+// Traces of every column projected on the interface functions: the
+// subdomain's block of the interface system, rows of flux dofs negated (the
+// form in which the assembled interface matrix is symmetric), last column =
+// right-hand side.  Column col of the local solutions at cell l is
+// Xs[l * ls + col * cs] (cell-major in LDS or scratch, or the column-major
+// output array); all threads of the work-group take part.
+template <int M, int D>
+__device__ void generic_block(const SubArgs& a, int sd, int I, int J, const double* kap,
+                              const double* Xs, int ls, int cs) {
+  constexpr int NBR = 4 * D, NBC = 4 * D + 1;
+  const Geo& g = a.g;
+  double* blk = a.blocks + (size_t)sd * NBR * NBC;
+  const int nP = g.nP;
+  int e0side = -1;      // side holding global dof 0 (gauge), if any
+  bool e0lo = false;
+  if (g.gauge) {
+    for (int side = 0; side < 4; ++side)
+      if (side_iface(g, I, J, side) == 0) { e0side = side; e0lo = side_sigma(side) > 0; }
+  }
+  for (int o = threadIdx.x; o < NBR * NBC; o += blockDim.x) {
+    const int r = o / NBC, qc = o % NBC;
+    const int side = r / D, k = r % D;
+    const int e = side_iface(g, I, J, side);
+    double val = 0.0;
+    if (e >= 0) {
+      const int col = (qc < NBR) ? 1 + qc : 0;
+      const SideGeo sg = side_geo(g, side);
+      const double al = a.alpha[e];
+      const double sig = side_sigma(side);
+      const double* bs = a.basis + (size_t)e * D * M;
+      const bool colside = col >= 1 + side * D && col < 1 + side * D + D;
+      const int kc = col - 1 - side * D;
+      double sum = 0.0;
+      for (int t = 0; t < M; ++t) {
+        const int l = side_cell<M>(side, t);
+        const double kk = kap[l];
+        const double TR = sg.flen * kk / (sg.dist + al * sg.H);
+        const double beta = al * sg.H / kk;
+        double gv = 0.0;
+        if (colside) gv = (kc < nP) ? bs[kc * M + t] : -beta * sig * bs[kc * M + t];
+        const double F = TR * (Xs[(size_t)l * ls + (size_t)col * cs] - gv);
+        if (k < nP) sum += bs[k * M + t] * F;
+        else sum += bs[k * M + t] * (gv + beta * F / sg.flen);
+      }
+      const double natural = (k < nP) ? sum : sig * sg.flen * sum;
+      const double sgn = (k < nP) ? 1.0 : -1.0;
+      val = (qc < NBR) ? sgn * natural : -sgn * natural;
+      if (e0side >= 0) {
+        const int r0 = e0side * D;   // local position of global dof 0
+        if (r == r0) val = (qc == r0 && e0lo) ? 1.0 : 0.0;
+        else if (qc == r0) val = 0.0;
+      }
+    }
+    blk[o] = val;
+  }
+}
+
 template <int M>
 __device__ void load_kappa(const SubArgs& a, int I, int J, double* kap) {
   const Geo& g = a.g;

@@ -118,6 +118,12 @@ hipError_t launch_basis_m16d4(const SubArgs& a, hipStream_t st);
 hipError_t launch_basis32_m16d4(const SubArgs& a, hipStream_t st);
 hipError_t launch_basis_m16d4_list(const SubArgs& a, hipStream_t st);
 hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st);
+// (local_mfma32.hip) 32 x 32 subdomains, 4 dofs per side (2 + 2): FP64 basis
+// functions on the matrix cores; list = only the FP32 fallback list
+bool basis32x32_supported(const Geo& g);
+long long basis32x32_scratch();   // doubles of per-subdomain scratch it needs
+hipError_t launch_basis32x32(const SubArgs& a, hipStream_t st, bool list);
+hipError_t launch_stitch32x32(const SubArgs& a, hipStream_t st);
 bool local_supported(int M, int D);
 // sizes with an FP32 + refinement kernel (16 x 16 with 2 + 2 dofs, 32 x 32 with 4 dofs)
 bool local_fp32_supported(int M, int D, int nP);

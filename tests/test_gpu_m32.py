@@ -63,3 +63,31 @@ def test_m32_surrogate_is_reported_unsupported():
     with pytest.raises(MRCMError) as e:
         MRCMSolver(prob, precision="surrogate")
     assert e.value.code == 7    # MRCM_E_UNSUPPORTED
+
+
+def test_m32_matrix_core_kernels_match_generic_kernels():
+    """The 32 x 32 matrix-core kernels (basis functions and stitch) against
+    the generic per-subdomain kernels on the same input (MRCM_GENERIC_KERNELS
+    selects the latter): the same method with another elimination order, so
+    the results agree to rounding."""
+    import os
+    prob = inputs.make_problem("channel2048x1024", nx=256, ny=128, lx=0.25, ly=0.125, seed=3)
+    lam = total_mobility(inputs.synthetic_saturation(prob, 3, 5), prob.mu_w, prob.mu_o)
+    say("case: m32 matrix-core vs generic kernels 256x128")
+    os.environ["MRCM_GENERIC_KERNELS"] = "1"
+    try:
+        gen = run_gpu(prob, lam=lam)
+    finally:
+        del os.environ["MRCM_GENERIC_KERNELS"]
+    mc = run_gpu(prob, lam=lam)
+    eb = np.abs(mc["basis"] - gen["basis"]).max() / np.abs(gen["basis"]).max()
+    ebl = np.abs(mc["blocks"] - gen["blocks"]).max() / np.abs(gen["blocks"]).max()
+    ep = rel(mc["p"], gen["p"])
+    ef = rel(np.r_[mc["ux"], mc["uy"]], np.r_[gen["ux"], gen["uy"]])
+    for name, r in (("generic", gen), ("matrix-core", mc)):
+        st = r["stats"]
+        say("  %s: ms local %.3f interface %.3f flux %.3f imbalance %.2e"
+            % (name, st["ms_local"], st["ms_interface"], st["ms_flux"], r["imbalance"]))
+    say("  max rel difference: basis %.2e blocks %.2e; rel L2 p %.2e flux %.2e" % (eb, ebl, ep, ef))
+    assert eb < 1e-11 and ebl < 1e-11 and ep < 1e-11 and ef < 1e-10
+    assert mc["imbalance"] < 1e-12
