@@ -110,6 +110,10 @@ typedef struct {
   int32_t interface_ir_steps; /* refinement steps of the interface solve (taken while
                                  max |b - A x| > tol max |b|, at most max_steps: see
                                  mrcm_set_interface_refinement) */
+  double interface_gflop;      /* algorithmic work of one interface solve (elimination
+                                  of the nested-dissection fronts, back substitution,
+                                  extend-add), GFLOP; fixed by the plan */
+  int32_t interface_launches;  /* kernel launches of one interface solve */
 } mrcm_stats;
 
 /* Set up a solver for one grid, permeability field and decomposition

@@ -106,6 +106,8 @@ struct mrcm_ctx {
   // interface plan
   std::vector<LevelPlan> levels;
   long long leaf_block = 0;  // doubles per subdomain block
+  double iface_flop = 0.0;   // algorithmic FLOP of one interface solve
+  int iface_launches = 0;    // its kernel launches
   double* static_scratch = nullptr;       // this device's address of `scratch`
   // implicit transport: work arrays (set up with the context) and the
   // pinned mirror of its scalar block
@@ -403,6 +405,21 @@ int build_plan(mrcm_ctx* c) {
     node_desc[i] = (int)desc.size();
     desc.push_back(d);
   }
+  // algorithmic work of the elimination: per front of n unknowns with s
+  // eliminated (and one right-hand side), the extend-add, the LU steps
+  // (m multipliers and an m x (m + 1) rank-one update at pivot k, m = n-k-1)
+  // and the back substitution of the s eliminated unknowns
+  c->iface_flop = 0.0;
+  for (const HNode& n : tb.nodes) {
+    if (n.leaf) continue;
+    const double nn = (double)n.dofs.size(), ss = n.s;
+    double f = nn * (nn + 1.0) + 2.0 * ss * (nn - ss) + ss * ss;
+    for (int k = 0; k < n.s; ++k) {
+      const double m = nn - k - 1.0;
+      f += m + 2.0 * m * (m + 1.0);
+    }
+    c->iface_flop += f;
+  }
   for (int lv = 1; lv <= max_level; ++lv) {
     LevelPlan lp{};
     lp.ids_off = (int)ids.size();
@@ -494,6 +511,16 @@ int build_plan(mrcm_ctx* c) {
         ids.insert(ids.end(), panel_ids[q].begin(), panel_ids[q].end());
         ++q;
       }
+  }
+  // launches of one solve (run_interface): a level of small fronts takes
+  // one, a blocked level one per panel with trailing rows; one back
+  // substitution per level; the residual
+  c->iface_launches = 1;
+  for (const LevelPlan& lp : c->levels) {
+    c->iface_launches += 1;
+    if (lp.small) c->iface_launches += 1;
+    else
+      for (const PanelLaunch& pl : lp.panels) c->iface_launches += pl.update_count > 0 ? 1 : 0;
   }
   ALLOC(c, c->tree, total);
   ALLOC(c, c->inv, inv_total);
@@ -1091,6 +1118,8 @@ int mrcm_get_stats(const mrcm_ctx* c, mrcm_stats* s) {
   *s = c->stats;
   s->n_sub = c->g.n_sub;
   s->n_dof = c->n_dof;
+  s->interface_gflop = c->iface_flop * 1e-9;
+  s->interface_launches = c->iface_launches;
   return MRCM_OK;
 }
 

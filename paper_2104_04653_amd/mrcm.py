@@ -59,7 +59,8 @@ class Stats(ctypes.Structure):
                 ("ms_flux", ctypes.c_double), ("n_sub", ctypes.c_int32),
                 ("n_dof", ctypes.c_int32), ("ir_iters_max", ctypes.c_int32),
                 ("fallbacks", ctypes.c_int32), ("interface_residual", ctypes.c_double),
-                ("ms_surrogate", ctypes.c_double), ("interface_ir_steps", ctypes.c_int32)]
+                ("ms_surrogate", ctypes.c_double), ("interface_ir_steps", ctypes.c_int32),
+                ("interface_gflop", ctypes.c_double), ("interface_launches", ctypes.c_int32)]
 
 
 class TransportStats(ctypes.Structure):

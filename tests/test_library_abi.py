@@ -114,3 +114,35 @@ def test_binding_checks_alpha_length_without_gpu():
     prob = inputs.make_problem("gauss64", sub=16)           # 4 x 4 subdomains: 24 interfaces
     with pytest.raises(ValueError):
         binding.MRCMSolver(prob.replace(alpha_per_interface=np.ones(23)))
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    the C compiler gives the header's struct (compiled here with gcc)."""
+    import shutil
+    import subprocess
+    from paper_2104_04653_amd import mrcm as binding
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    pairs = {"mrcm_stats": binding.Stats, "mrcm_transport_stats": binding.TransportStats,
+             "mrcm_sfi_stats": binding.SFIStats}
+    for cname in ("Grid", "BC", "Fluid"):
+        if hasattr(binding, cname):
+            pairs[{"Grid": "mrcm_grid", "BC": "mrcm_bc", "Fluid": "mrcm_fluid"}[cname]] = getattr(binding, cname)
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mrcm.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f[0], cname, f[0]))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
