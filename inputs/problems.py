@@ -55,6 +55,11 @@ class Problem:
     alpha_per_interface: Optional[np.ndarray] = None
     seed: int = 1
     steps: int = 1                        # time steps of the two-phase workload
+    # gravity: the term lambda_g g grad h of Darcy's law with gravity, acting
+    # along y: gravity = g dh/dy (0: no gravity); phase densities
+    gravity: float = 0.0
+    rho_w: float = 0.0
+    rho_o: float = 0.0
 
     @property
     def hx(self) -> float:

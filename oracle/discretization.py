@@ -53,6 +53,48 @@ def fractional_flow(s, mu_w, mu_o):
     return lw / (lw + lo)
 
 
+def gravity_density(s, mu_w, mu_o, rho_w, rho_o):
+    """lambda_g / lambda: the gravitational mobility of eq. (fluxos1_wg),
+    lambda_g = lambda_w rho_w + lambda_o rho_o, over the total mobility
+    (quadratic relative permeabilities of section 5), i.e. the
+    mobility-weighted density of the two phases."""
+    s = np.asarray(s, dtype=np.float64)
+    lw = s * s / mu_w
+    lo = (1.0 - s) * (1.0 - s) / mu_o
+    return (lw * rho_w + lo * rho_o) / (lw + lo)
+
+
+def gravity_face_fluxes(prob, kappa, rho):
+    """The gravity part of the +y face fluxes, shape (ny + 1, nx).
+
+    Darcy's law with gravity (section 5.5, eq. (Darcy_wg)) is
+    u = -kappa (grad p - rho g grad h) with kappa = lambda K and
+    rho = lambda_g / lambda per cell; gravity acts along y with
+    gamma = g dh/dy (``prob.gravity``).  Reading (the paper gives no
+    discretisation of this term): on a half cell the flux is
+    t_c (p_c - p_f) + t_c rho_c gamma d in the +y direction (t_c = kappa_c
+    |f| / d), and the face pressure is eliminated between the two half
+    cells as in the two-point law, which gives
+    F = T (p_below - p_above) + T gamma (h/2) (rho_below + rho_above) on an
+    interior face and t_c gamma (h/2) rho_c on a Dirichlet boundary face.
+    Neumann boundary faces carry the prescribed total flux: zero here."""
+    nx, ny = prob.nx, prob.ny
+    GY = np.zeros((ny + 1, nx))
+    if prob.gravity == 0.0 or rho is None:
+        return GY
+    hx, hy = prob.lx / nx, prob.ly / ny
+    K = np.asarray(kappa, dtype=np.float64).reshape(ny, nx)
+    R = np.asarray(rho, dtype=np.float64).reshape(ny, nx)
+    t = K * hx / (0.5 * hy)
+    g = prob.gravity
+    GY[1:-1, :] = harmonic(t[:-1, :], t[1:, :]) * g * (0.5 * hy) * (R[:-1, :] + R[1:, :])
+    if prob.bc_kind[S] == DIRICHLET:
+        GY[0, :] = t[0, :] * g * (0.5 * hy) * R[0, :]
+    if prob.bc_kind[N] == DIRICHLET:
+        GY[-1, :] = t[-1, :] * g * (0.5 * hy) * R[-1, :]
+    return GY
+
+
 def cell_injection(prob, hx, hy):
     """Volume injected per unit time into every cell: q |V| (eq. (Darcy),
     div u = q; q > 0 is a source such as an injection well)."""

@@ -14,17 +14,20 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .discretization import DIRICHLET, E, N, S, W, cell_injection, harmonic, neumann_outflow
+from .discretization import (DIRICHLET, E, N, S, W, cell_injection, gravity_face_fluxes, harmonic,
+                             neumann_outflow)
 
 
 def _half_trans(kappa, flen, dist):
     return kappa * flen / dist
 
 
-def solve_fine(prob, lam=None):
+def solve_fine(prob, lam=None, rho=None):
     """Return dict(p, ux, uy, Fx, Fy) of the fine two-point solution.
 
     lam: per-cell total mobility (default 1), kappa = lam * K (section 3).
+    rho: per-cell lambda_g / lambda when ``prob.gravity`` is not zero
+    (section 5.5; the face terms of ``gravity_face_fluxes``).
     ux, uy are +x / +y normal velocities on the x- and y-faces; Fx, Fy the
     corresponding face fluxes (velocity times face length).
     For all-Neumann data the pressure is fixed by p_0 = 0 and then shifted
@@ -66,6 +69,9 @@ def solve_fine(prob, lam=None):
             np.add.at(rhs, cells, t * v)
         else:
             np.add.at(rhs, cells, -neumann_outflow(v, flen))
+    # gravity: the constant part of every y-face flux moves to the data
+    GY = gravity_face_fluxes(prob, kappa, rho)
+    rhs -= (GY[1:, :] - GY[:-1, :]).reshape(-1)
     A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(n, n))
     pure_neumann = not prob.has_dirichlet()
@@ -97,5 +103,6 @@ def solve_fine(prob, lam=None):
         else:
             out = ty[-1, :] * (P[-1, :] - v) if prob.bc_kind[N] == DIRICHLET else neumann_outflow(v, hx)
             Fy[-1, :] = out
+    Fy += GY
     return dict(p=p, Fx=Fx.reshape(-1), Fy=Fy.reshape(-1),
                 ux=(Fx / hy).reshape(-1), uy=(Fy / hx).reshape(-1))

@@ -45,8 +45,8 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .discretization import (DIRICHLET, E, N, S, W, Geometry, cell_injection, harmonic,
-                             interface_alpha, interface_spaces, neumann_outflow)
+from .discretization import (DIRICHLET, E, N, S, W, Geometry, cell_injection, gravity_face_fluxes,
+                             harmonic, interface_alpha, interface_spaces, neumann_outflow)
 
 
 @dataclasses.dataclass
@@ -88,7 +88,7 @@ def _bc_faces(geom, prob, kappa):
     return out
 
 
-def local_operator(geom, prob, kappa, robin_T=None, extended=False):
+def local_operator(geom, prob, kappa, robin_T=None, extended=False, GY=None):
     """Block-diagonal matrix of all local problems and their data vector.
 
     Interior faces of a subdomain: harmonic two-point coupling; physical
@@ -96,7 +96,10 @@ def local_operator(geom, prob, kappa, robin_T=None, extended=False):
     -u_b |f|); source q |V|.  Skeleton faces add the Robin diagonal T_R when
     ``robin_T`` (a list of (cells, T_R) pairs) is given; without it they are
     left as zero-flux faces (for the stitch re-solve the prescribed flux is
-    added to the data by the caller).
+    added to the data by the caller).  GY: the gravity part of the +y face
+    fluxes (``gravity_face_fluxes``); it enters the data on the faces inside
+    subdomains and on the physical boundary (the skeleton faces' gravity
+    terms are the callers').
     """
     nx, ny, mx, my = geom.nx, geom.ny, geom.mx, geom.my
     hx, hy = geom.hx, geom.hy
@@ -128,6 +131,10 @@ def local_operator(geom, prob, kappa, robin_T=None, extended=False):
             np.add.at(rhs, cells, t * v)
         else:
             np.add.at(rhs, cells, -neumann_outflow(v, flen))
+    if GY is not None:
+        G = GY.copy()
+        G[1:-1, :][~same_y, :] = 0.0          # skeleton faces
+        rhs -= (G[1:, :] - G[:-1, :]).reshape(-1)
     if robin_T is not None:
         for cells, T in robin_T:
             rows.append(cells)
@@ -145,8 +152,11 @@ def local_operator(geom, prob, kappa, robin_T=None, extended=False):
     return A, rhs, (Tx, Ty, tx, ty, same_x, same_y)
 
 
-def _side_records(geom, prob, kappa, alpha):
-    """Robin data of every skeleton face, per interface and side."""
+def _side_records(geom, prob, kappa, alpha, rho=None):
+    """Robin data of every skeleton face, per interface and side.  G is the
+    gravity part of the Robin flux out of the side's subdomain: the half-cell
+    term t_c rho_c gamma d (n . e_y) through T_R = t_c / (1 + t_c beta / |f|),
+    i.e. T_R rho_c gamma d (n . e_y) (zero on vertical interfaces)."""
     recs = []
     for itf in geom.interfaces:
         a = alpha[itf.index]
@@ -156,7 +166,11 @@ def _side_records(geom, prob, kappa, alpha):
             kc = kappa[cells]
             TR = itf.flen * kc / (itf.dist + a * itf.H)
             beta = a * itf.H / kc
-            per.append(dict(cells=cells, sub=sub, side=side, sigma=sigma, TR=TR, beta=beta))
+            G = np.zeros(cells.size)
+            if rho is not None and prob.gravity != 0.0 and not itf.vertical:
+                ny_out = 1.0 if side == N else -1.0
+                G = TR * rho[cells] * prob.gravity * itf.dist * ny_out
+            per.append(dict(cells=cells, sub=sub, side=side, sigma=sigma, TR=TR, beta=beta, G=G))
         recs.append(per)
     return recs
 
@@ -283,8 +297,9 @@ def flux_imbalance(geom, prob, Fx, Fy):
     return float(np.abs(net - q).max() / scale)
 
 
-def _boundary_fluxes(geom, prob, kappa, p, FX, FY):
-    """Fill the physical boundary faces of +x/+y flux arrays from pressure p."""
+def _boundary_fluxes(geom, prob, kappa, p, FX, FY, GY=None):
+    """Fill the physical boundary faces of +x/+y flux arrays from pressure p
+    (with the gravity part GY of the y-faces)."""
     P = p.reshape(geom.ny, geom.nx)
     for side, cells, t, flen, v in _bc_faces(geom, prob, kappa):
         if prob.bc_kind[side] == DIRICHLET:
@@ -299,12 +314,30 @@ def _boundary_fluxes(geom, prob, kappa, p, FX, FY):
             FY[0, :] = -out
         else:
             FY[-1, :] = out
+    if GY is not None:
+        FY[0, :] += GY[0, :]
+        FY[-1, :] += GY[-1, :]
     del P
 
 
 def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu",
-               ir_steps=3, stitch=True):
-    """Run the MRCM on ``prob`` with total mobility ``lam`` (default 1)."""
+               ir_steps=3, stitch=True, timings=None, rho=None):
+    """Run the MRCM on ``prob`` with total mobility ``lam`` (default 1) and,
+    when ``prob.gravity`` is not zero, the per-cell lambda_g / lambda ``rho``
+    (section 5.5: the same matrices, gravity terms in the data).
+
+    ``timings``: an optional dict that receives the wall time in seconds of
+    each phase (local, interface, compose, stitch); it changes nothing in
+    the computation."""
+    import time
+    clock = [time.perf_counter()]
+
+    def lap(name):
+        if timings is not None:
+            now = time.perf_counter()
+            timings[name] = timings.get(name, 0.0) + now - clock[0]
+            clock[0] = now
+
     geom = Geometry(prob)
     nx, ny, mx, my = geom.nx, geom.ny, geom.mx, geom.my
     lam = np.ones(nx * ny) if lam is None else np.asarray(lam, dtype=np.float64)
@@ -313,14 +346,19 @@ def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu
     alpha = interface_alpha(geom, prob)
     n_p, n_u, off, sub_dofs, col_off, R = _dof_layout(geom, spaces)
     n_dof = int(off[-1])
-    recs = _side_records(geom, prob, kappa, alpha)
+    rho = None if rho is None else np.asarray(rho, dtype=np.float64)
+    GY = gravity_face_fluxes(prob, kappa, rho)
+    recs = _side_records(geom, prob, kappa, alpha, rho)
 
     # local problems, all subdomains at once (they are uncoupled)
     robin = [(r["cells"], r["TR"]) for per in recs for r in per]
     A, rhs0, (Tx, Ty, tx, ty, same_x, same_y), A_ext = local_operator(geom, prob, kappa, robin,
-                                                                    extended=True)
+                                                                    extended=True, GY=GY)
     B = np.zeros((geom.n_cells, R))
     B[:, 0] = rhs0
+    for per in recs:        # gravity through the Robin faces: particular solution's data
+        for rec in per:
+            np.add.at(B[:, 0], rec["cells"], -rec["G"])
     for itf, per in zip(geom.interfaces, recs):
         ps, us = spaces[itf.index]
         for rec in per:
@@ -341,11 +379,13 @@ def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu
             G = _interface_data(itf, rec, ps, us, c0)
             Gfull[:, c0:c0 + G.shape[1]] = G
             F = rec["TR"][:, None] * (X[rec["cells"]] - Gfull)
+            F[:, 0] += rec["G"]
             pf = Gfull + (rec["beta"] / itf.flen)[:, None] * F
             r0 = c0 - 1
             blocks[sd][r0:r0 + nP] += ps @ F
             blocks[sd][r0 + nP:r0 + G.shape[1]] += rec["sigma"] * itf.flen * (us @ pf)
 
+    lap("local")
     # interface system, natural form
     rows, cols, vals = [], [], []
     b = np.zeros(n_dof)
@@ -374,6 +414,7 @@ def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu
         M_solve = M_solve.tocsr()
         b_solve[0] = 0.0
     c = _interface_solve(M_solve, b_solve, interface_solver, ir_steps)
+    lap("interface")
 
     # composition: p = X [1; c] per subdomain
     Cmat = np.zeros((geom.n_sub, R))
@@ -388,8 +429,8 @@ def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu
     FX = np.zeros((ny, nx + 1))
     FY = np.zeros((ny + 1, nx))
     FX[:, 1:-1] = np.where(same_x[None, :], Tx * (P[:, :-1] - P[:, 1:]), 0.0)
-    FY[1:-1, :] = np.where(same_y[:, None], Ty * (P[:-1, :] - P[1:, :]), 0.0)
-    _boundary_fluxes(geom, prob, kappa, p, FX, FY)
+    FY[1:-1, :] = np.where(same_y[:, None], Ty * (P[:-1, :] - P[1:, :]) + GY[1:-1, :], 0.0)
+    _boundary_fluxes(geom, prob, kappa, p, FX, FY, GY)
     side_flux = []
     FXf, FYf = FX.reshape(-1), FY.reshape(-1)
     for itf, per in zip(geom.interfaces, recs):
@@ -401,7 +442,7 @@ def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu
         Fs = []
         for rec in per:
             g = PH - rec["beta"] * rec["sigma"] * UH
-            Fs.append(rec["TR"] * (p[rec["cells"]] - g))
+            Fs.append(rec["TR"] * (p[rec["cells"]] - g) + rec["G"])
         side_flux.append((Fs[0], Fs[1]))
         avg = 0.5 * (Fs[0] - Fs[1])
         if itf.vertical:
@@ -414,11 +455,12 @@ def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu
     if pure_neumann:
         p = p - p.mean()
 
+    lap("compose")
     # stitch: Neumann re-solve per subdomain with the averaged skeleton flux
     p_st = np.full_like(p, np.nan)
     Fx, Fy = Fx_raw.copy(), Fy_raw.copy()
     if stitch and geom.n_iface:
-        AN, rhsN, _ = local_operator(geom, prob, kappa, None)
+        AN, rhsN, _ = local_operator(geom, prob, kappa, None, GY=GY)
         rhsN = rhsN.copy()
         for itf, per in zip(geom.interfaces, recs):
             avg = 0.5 * (side_flux[itf.index][0] - side_flux[itf.index][1])
@@ -465,8 +507,9 @@ def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu
             FXl = Fx_raw.reshape(ny, nx + 1).astype(ld)
             FYl = Fy_raw.reshape(ny + 1, nx).astype(ld)
             FXl[:, 1:-1] = np.where(same_x[None, :], Tx * (PS[:, :-1] - PS[:, 1:]), FXl[:, 1:-1])
-            FYl[1:-1, :] = np.where(same_y[:, None], Ty * (PS[:-1, :] - PS[1:, :]), FYl[1:-1, :])
-            _boundary_fluxes(geom, prob, kappa, x, FXl, FYl)
+            FYl[1:-1, :] = np.where(same_y[:, None], Ty * (PS[:-1, :] - PS[1:, :]) + GY[1:-1, :],
+                                    FYl[1:-1, :])
+            _boundary_fluxes(geom, prob, kappa, x, FXl, FYl, GY)
             return FXl, FYl
 
         def balance_residual(x):
@@ -490,6 +533,7 @@ def solve_mrcm(prob, lam=None, local_solver="superlu", interface_solver="superlu
         FXl, FYl = stitched_fluxes(p_ext)
         Fx, Fy = FXl.astype(np.float64).reshape(-1), FYl.astype(np.float64).reshape(-1)
     imb = flux_imbalance(geom, prob, Fx, Fy)
+    lap("stitch")
     fscale = max(np.abs(Fx).max(), np.abs(Fy).max(), 1e-300)
     defect = defect_max / fscale if stitch and geom.n_iface else 0.0
     return MRCMResult(p=p, ux=Fx / geom.hy, uy=Fy / geom.hx, Fx=Fx, Fy=Fy,

@@ -59,8 +59,8 @@ def test_reversed_normal_is_harmless(monkeypatch):
     of the flux unknowns: the pins must still pass."""
     orig = om._side_records
 
-    def flipped(geom, prob, kappa, alpha):
-        recs = orig(geom, prob, kappa, alpha)
+    def flipped(geom, prob, kappa, alpha, rho=None):
+        recs = orig(geom, prob, kappa, alpha, rho)
         for per in recs:
             per[0]["sigma"], per[1]["sigma"] = -1.0, 1.0
         return recs
@@ -75,8 +75,8 @@ def test_reversed_normal_is_harmless(monkeypatch):
 def test_one_sided_normal_sign_caught(monkeypatch):
     orig = om._side_records
 
-    def flipped(geom, prob, kappa, alpha):
-        recs = orig(geom, prob, kappa, alpha)
+    def flipped(geom, prob, kappa, alpha, rho=None):
+        recs = orig(geom, prob, kappa, alpha, rho)
         for per in recs:
             per[1]["sigma"] = 1.0
         return recs
@@ -153,3 +153,113 @@ def test_alpha_from_wrong_interface_caught(monkeypatch):
     orig = om.interface_alpha
     monkeypatch.setattr(om, "interface_alpha", lambda geom, prob: orig(geom, prob)[::-1].copy())
     assert not _pins_pass()
+
+
+# ---------------------------------------------------------------------------
+# gravity variant (section 5.5)
+# ---------------------------------------------------------------------------
+
+from tests import test_oracle_gravity as PG  # noqa: E402
+
+GRAVITY_PINS = [
+    lambda: PG.test_hydrostatic_closed_box(),
+    lambda: PG.test_hydrostatic_with_dirichlet_top_and_bottom(),
+    lambda: PG.test_layered_column_closed_form(),
+    lambda: PG.test_full_spaces_recover_fine_with_gravity(),
+    lambda: PG.test_one_subdomain_is_fine_with_gravity(),
+    lambda: PG.test_stitched_fluxes_balance_with_gravity(),
+]
+
+
+def _gravity_pins_pass():
+    for pin in GRAVITY_PINS:
+        try:
+            pin()
+        except AssertionError:
+            return False
+    return True
+
+
+def test_unmodified_oracle_passes_gravity_pins():
+    assert _gravity_pins_pass()
+
+
+def _patch_face_fluxes(monkeypatch, fn):
+    monkeypatch.setattr(om, "gravity_face_fluxes", fn)
+    monkeypatch.setattr(of, "gravity_face_fluxes", fn)
+
+
+def test_gravity_face_density_of_one_side_caught(monkeypatch):
+    """The lower cell's density on a whole interior face instead of the two
+    half cells' densities."""
+    orig = od.gravity_face_fluxes
+
+    def lower_only(prob, kappa, rho):
+        GY = orig(prob, kappa, rho)
+        if rho is None or prob.gravity == 0.0:
+            return GY
+        R = np.asarray(rho).reshape(prob.ny, prob.nx)
+        fix = np.where(R[:-1, :] + R[1:, :] != 0, 2.0 * R[:-1, :] / (R[:-1, :] + R[1:, :] + 1e-300), 1.0)
+        GY[1:-1, :] *= fix
+        return GY
+    _patch_face_fluxes(monkeypatch, lower_only)
+    assert not _gravity_pins_pass()
+
+
+def test_gravity_sign_flip_caught(monkeypatch):
+    orig = od.gravity_face_fluxes
+    _patch_face_fluxes(monkeypatch, lambda prob, kappa, rho: -orig(prob, kappa, rho))
+    assert not _gravity_pins_pass()
+
+
+def test_gravity_missing_on_dirichlet_faces_caught(monkeypatch):
+    orig = od.gravity_face_fluxes
+
+    def no_boundary(prob, kappa, rho):
+        GY = orig(prob, kappa, rho)
+        GY[0, :] = 0.0
+        GY[-1, :] = 0.0
+        return GY
+    _patch_face_fluxes(monkeypatch, no_boundary)
+    assert not _gravity_pins_pass()
+
+
+def test_gravity_sign_flip_on_robin_faces_caught(monkeypatch):
+    orig = om._side_records
+
+    def flipped(geom, prob, kappa, alpha, rho=None):
+        recs = orig(geom, prob, kappa, alpha, rho)
+        for per in recs:
+            for r in per:
+                r["G"] = -r["G"]
+        return recs
+    monkeypatch.setattr(om, "_side_records", flipped)
+    assert not _gravity_pins_pass()
+
+
+def test_gravity_dropped_on_robin_faces_caught(monkeypatch):
+    orig = om._side_records
+
+    def dropped(geom, prob, kappa, alpha, rho=None):
+        recs = orig(geom, prob, kappa, alpha, rho)
+        for per in recs:
+            for r in per:
+                r["G"] = 0.0 * r["G"]
+        return recs
+    monkeypatch.setattr(om, "_side_records", dropped)
+    assert not _gravity_pins_pass()
+
+
+def test_gravity_robin_distance_caught(monkeypatch):
+    """The full cell height in place of the centre-to-face distance in the
+    Robin faces' gravity term."""
+    orig = om._side_records
+
+    def doubled(geom, prob, kappa, alpha, rho=None):
+        recs = orig(geom, prob, kappa, alpha, rho)
+        for per in recs:
+            for r in per:
+                r["G"] = 2.0 * r["G"]
+        return recs
+    monkeypatch.setattr(om, "_side_records", doubled)
+    assert not _gravity_pins_pass()
