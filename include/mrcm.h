@@ -195,6 +195,28 @@ int mrcm_set_refinement(mrcm_ctx* ctx, int32_t max_steps, double tol);
  * unless 0 <= max_steps <= 16, 0 < tol < 1 and 0 < fail_tol < 1. */
 int mrcm_set_interface_refinement(mrcm_ctx* ctx, int32_t max_steps, double tol, double fail_tol);
 
+/* Gravity variant of the pressure equation (section 5.5, eqs. (Darcy_wg) and
+ * (fluxos1_wg)): u = -K (lambda grad p - lambda_g g grad h), gravity along
+ * y, with gravity = g dh/dy (a constant; 0 switches the variant off) and
+ * lambda_g = lambda_w rho_w + lambda_o rho_o.  The local matrices are those
+ * without gravity; the term enters the data of the local problems (the
+ * particular solution) and every face flux: on a half cell of
+ * transmissibility t and centre-to-face distance d the flux carries
+ * t d gravity (lambda_g / lambda) (n . e_y), the face pressure is
+ * eliminated between the two half cells as in the two-point law, a Robin
+ * face carries T_R d gravity (lambda_g / lambda) (n . e_y), and Neumann faces
+ * keep their prescribed total flux.  With the variant on, the mobility must
+ * come from a saturation (mrcm_update_mobility / mrcm_step with
+ * values_are_lambda = 0), which also sets lambda_g / lambda per cell.
+ * Allocates one array of nx * ny doubles on the first call that enables
+ * gravity.  Errors: MRCM_E_INVAL for values that are not finite;
+ * MRCM_E_UNSUPPORTED for MRCM_PREC_SURROGATE.  With gravity on, the
+ * transport calls (mrcm_transport_step, mrcm_si_step, mrcm_sfi_step) return
+ * MRCM_E_UNSUPPORTED (their water flux has no gravity segregation term),
+ * mrcm_update_mobility / mrcm_step with lambda values return MRCM_E_INVAL,
+ * and a solve before any saturation was given returns MRCM_E_STATE. */
+int mrcm_set_gravity(mrcm_ctx* ctx, double gravity, double rho_w, double rho_o);
+
 /* Reconstruct fine-scale output from the last solve:
  *  p  : nx*ny composed multiscale cell pressure (basis functions combined
  *       with the interface solution, section 3);

@@ -85,6 +85,7 @@ struct mrcm_ctx {
   double* rvec = nullptr;       // interface refinement: residual (n_dof)
   double* dx = nullptr;         // interface refinement: correction (n_dof)
   int iface_ir = 0;             // refinement steps taken by the last solve
+  bool step_refined = false;    // the last mrcm_step refined its interface solve
   double* scratch = nullptr;    // generic local kernels: per-subdomain work arrays
   long long scratch_stride = 0;
   // surrogate precision: network parameters and per-subdomain activations
@@ -114,6 +115,10 @@ struct mrcm_ctx {
   TransportArgs tr{};
   double* h_tscal = nullptr;
   double* s_prev = nullptr;               // SFI: the previous outer iterate
+  // gravity variant: g dh/dy, phase densities, lambda_g / lambda per cell
+  double grav = 0.0, rho_w = 0.0, rho_o = 0.0;
+  double* rho = nullptr;
+  bool rho_valid = false;                 // rho holds the last saturation's values
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // solve start, local end, gate end
   unsigned long long* stamps = nullptr;   // device, inside the report block
   double clock_khz = 0.0;                 // rate of the clock the kernels read
@@ -554,6 +559,8 @@ SubArgs sub_args(const mrcm_ctx* c) {
   a.K = c->K;
   a.lam = c->lam;
   a.src = c->src;
+  a.rho = c->grav != 0.0 ? c->rho : nullptr;
+  a.g.grav = c->grav;
   for (int s = 0; s < 4; ++s) a.bcv[s] = c->bcv[s];
   a.alpha = c->alpha;
   a.basis = c->basis;
@@ -859,18 +866,63 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
   return MRCM_OK;
 }
 
+namespace {
+
+// total mobility (and, with gravity, lambda_g / lambda) from device values
+int mobility_enqueue(mrcm_ctx* c, const double* src, int32_t values_are_lambda) {
+  const size_t n = (size_t)c->g.nx * c->g.ny;
+  if (c->grav != 0.0) {
+    HIPCHK(c, launch_mobility_gravity(src, c->lam, c->rho, n, c->mu_w, c->mu_o, c->rho_w, c->rho_o, c->st));
+    c->rho_valid = true;
+    return MRCM_OK;
+  }
+  HIPCHK(c, launch_mobility(src, c->lam, n, values_are_lambda ? 0 : 1, c->mu_w, c->mu_o, c->st));
+  return MRCM_OK;
+}
+
+int gravity_check(mrcm_ctx* c, int32_t values_are_lambda) {
+  if (c->grav != 0.0 && values_are_lambda)
+    return fail(c, MRCM_E_INVAL, "the gravity variant takes the saturation (lambda_g / lambda needs it), "
+                                 "not the total mobility");
+  return MRCM_OK;
+}
+
+}  // namespace
+
 int mrcm_update_mobility(mrcm_ctx* c, const double* values, int32_t values_are_lambda,
                          int32_t on_device) {
   if (!c) return MRCM_E_INVAL;
   if (!values) return fail(c, MRCM_E_INVAL, "values is NULL");
+  int r = gravity_check(c, values_are_lambda);
+  if (r != MRCM_OK) return r;
   const size_t n = (size_t)c->g.nx * c->g.ny;
   const double* src = values;
   if (!on_device) {
     HIPCHK(c, hipMemcpyAsync(c->stage, values, n * sizeof(double), hipMemcpyHostToDevice, c->st));
     src = c->stage;
   }
-  HIPCHK(c, launch_mobility(src, c->lam, n, values_are_lambda ? 0 : 1, c->mu_w, c->mu_o, c->st));
+  r = mobility_enqueue(c, src, values_are_lambda);
+  if (r != MRCM_OK) return r;
   if (!on_device) HIPCHK(c, hipStreamSynchronize(c->st));  // host buffer may be reused on return
+  c->solved = false;
+  return MRCM_OK;
+}
+
+int mrcm_set_gravity(mrcm_ctx* c, double gravity, double rho_w, double rho_o) {
+  if (!c) return MRCM_E_INVAL;
+  if (!isfinite(gravity) || !isfinite(rho_w) || !isfinite(rho_o))
+    return fail(c, MRCM_E_INVAL, "mrcm_set_gravity: values must be finite");
+  if (gravity != 0.0 && c->precision == MRCM_PREC_SURROGATE)
+    return fail(c, MRCM_E_UNSUPPORTED, "mrcm_set_gravity: the surrogate precision has no gravity variant");
+  if (gravity != 0.0 && !c->rho) {
+    int r = dev_alloc(c, &c->rho, (size_t)c->g.nx * c->g.ny);
+    if (r != MRCM_OK) return r;
+  }
+  c->grav = gravity;
+  c->rho_w = rho_w;
+  c->rho_o = rho_o;
+  c->g.grav = gravity;
+  c->rho_valid = false;
   c->solved = false;
   return MRCM_OK;
 }
@@ -1029,6 +1081,8 @@ int mrcm_solve(mrcm_ctx* c) {
   if (!c) return MRCM_E_INVAL;
   if (c->precision == MRCM_PREC_SURROGATE && !c->s_ready)
     return fail(c, MRCM_E_STATE, "surrogate precision: mrcm_set_surrogate was not called");
+  if (c->grav != 0.0 && !c->rho_valid)
+    return fail(c, MRCM_E_STATE, "gravity: no saturation given since mrcm_set_gravity");
   return solve_impl(c, nullptr);
 }
 
@@ -1080,23 +1134,43 @@ int mrcm_step(mrcm_ctx* c, const double* values, int32_t values_are_lambda, int3
   if (c->precision == MRCM_PREC_SURROGATE && !c->s_ready)
     return fail(c, MRCM_E_STATE, "surrogate precision: mrcm_set_surrogate was not called");
   if (values) {
+    int r = gravity_check(c, values_are_lambda);
+    if (r != MRCM_OK) return r;
     const size_t n = (size_t)c->g.nx * c->g.ny;
     const double* src = values;
     if (!values_on_device) {   // the host array is read before the call returns
       HIPCHK(c, hipMemcpyAsync(c->stage, values, n * sizeof(double), hipMemcpyHostToDevice, c->st));
       src = c->stage;
     }
-    HIPCHK(c, launch_mobility(src, c->lam, n, values_are_lambda ? 0 : 1, c->mu_w, c->mu_o, c->st));
+    r = mobility_enqueue(c, src, values_are_lambda);
+    if (r != MRCM_OK) return r;
   }
+  if (c->grav != 0.0 && !c->rho_valid)
+    return fail(c, MRCM_E_STATE, "gravity: no saturation given since mrcm_set_gravity");
   c->solved = false;
   int r = solve_enqueue(c, nullptr);
   if (r != MRCM_OK) return r;
+  if (c->step_refined) {
+    // the last step refined its interface solve: this one most likely will
+    // too, so the reconstruction waits for the refined solution instead of
+    // being enqueued (and redone) on the unrefined one
+    HIPCHK(c, read_report(c));
+    c->iface_ir = 0;
+    r = solve_finish(c);
+    if (r != MRCM_OK) return r;
+    c->step_refined = c->iface_ir > 0;
+    r = flux_enqueue(c, p, ux, uy, outputs_on_device);
+    if (r != MRCM_OK) return r;
+    HIPCHK(c, read_report(c));
+    return flux_finish(c, max_cell_imbalance);
+  }
   // the reconstruction is enqueued before the solve's status is known; one
   // synchronisation reads both reports
   r = flux_enqueue(c, p, ux, uy, outputs_on_device);
   if (r != MRCM_OK) return r;
   HIPCHK(c, read_report(c));
   c->iface_ir = 0;
+  c->step_refined = needs_refinement(c);
   if (needs_refinement(c)) {
     // refine (solve_finish synchronises per step), then reconstruct again
     r = solve_finish(c);
@@ -1231,6 +1305,8 @@ namespace {
 
 int transport_check(mrcm_ctx* c, const double* s_old, double* s_new, const double* ux,
                     const double* uy, double dt, double s_inflow, double eta, int32_t max_newton) {
+  if (c->grav != 0.0)
+    return fail(c, MRCM_E_UNSUPPORTED, "transport: no gravity segregation term (set gravity to 0)");
   if (!s_old || !s_new || !ux || !uy) return fail(c, MRCM_E_INVAL, "transport: NULL array");
   if (s_old == s_new) return fail(c, MRCM_E_INVAL, "transport: s_new must not alias s_old");
   if (!(dt > 0.0) || !isfinite(dt)) return fail(c, MRCM_E_INVAL, "transport: dt must be finite and > 0");

@@ -431,8 +431,9 @@ __global__ void __launch_bounds__(NT) stitch_kernel(SubArgs a) {
       const int l = side_cell<M>(side, t);
       const double sig = side_sigma(side);
       const double ko = kap[l];
-      const double Fown = sg.flen * ko / (sg.dist + al * sg.H) *
-                          (pm[l] - (PH - al * sg.H / ko * sig * UH));
+      const double TRo = sg.flen * ko / (sg.dist + al * sg.H);
+      const double Fown = TRo * (pm[l] - (PH - al * sg.H / ko * sig * UH)) +
+                          robin_grav(a, side, (size_t)(J * M + l / M) * g.nx + I * M + l % M, TRo, sg.dist);
       // neighbour across the face
       const int nside = side ^ 1;
       const int nsd = (side == 0) ? sd - 1 : (side == 1) ? sd + 1 : (side == 2) ? sd - g.SX : sd + g.SX;
@@ -441,8 +442,8 @@ __global__ void __launch_bounds__(NT) stitch_kernel(SubArgs a) {
       const size_t nc = (size_t)(nJ * M + nl / M) * g.nx + nI * M + nl % M;
       const double kn = a.K[nc] * a.lam[nc];
       const double pn = compose_at<M, D>(a, nsd, nl);
-      const double Fnb = sg.flen * kn / (sg.dist + al * sg.H) *
-                         (pn - (PH - al * sg.H / kn * (-sig) * UH));
+      const double TRn = sg.flen * kn / (sg.dist + al * sg.H);
+      const double Fnb = TRn * (pn - (PH - al * sg.H / kn * (-sig) * UH)) + robin_grav(a, nside, nc, TRn, sg.dist);
       fo = 0.5 * (Fown - Fnb);
     }
     Fout[side][t] = fo;
@@ -609,6 +610,19 @@ __global__ void mobility_kernel(const double* in, double* lam, size_t n, int fro
   }
 }
 
+// total mobility and rho = lambda_g / lambda (eq. (fluxos1_wg)) from a
+// saturation, for the gravity variant
+__global__ void mobility_gravity_kernel(const double* s_in, double* lam, double* rho, size_t n, double mw,
+                                        double mo, double rw, double ro) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double s = s_in[i];
+    const double lw = s * s / mw, lo = (1.0 - s) * (1.0 - s) / mo;
+    lam[i] = lw + lo;
+    rho[i] = (lw * rw + lo * ro) / (lw + lo);
+  }
+}
+
 template <int M, int D>
 hipError_t launch_pair(const SubArgs& a, hipStream_t st, bool stitch) {
   if (stitch)
@@ -692,6 +706,13 @@ hipError_t launch_finish_flux(const SubArgs& a, double* result, hipStream_t st) 
   if (e != hipSuccess || !a.g.gauge) return e;
   const size_t n = (size_t)a.g.nx * a.g.ny;
   hipLaunchKernelGGL(shift_kernel, dim3(1024), dim3(256), 0, st, a.p_out, n, result + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_mobility_gravity(const double* s, double* lam, double* rho, size_t n, double mu_w,
+                                   double mu_o, double rho_w, double rho_o, hipStream_t st) {
+  hipLaunchKernelGGL(mobility_gravity_kernel, dim3(1024), dim3(256), 0, st, s, lam, rho, n, mu_w, mu_o,
+                     rho_w, rho_o);
   return hipGetLastError();
 }
 

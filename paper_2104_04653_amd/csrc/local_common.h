@@ -65,7 +65,25 @@ __device__ inline int side_cell(int side, int t) {
 // boundary value (domain boundary) and the Robin parameter (skeleton).
 struct CellLoads {
   double sv, bv[4], av[4];
+  double rc, rs, rn;      // gravity: lambda_g / lambda of the cell and its S, N neighbours
 };
+
+// Gravity (section 5.5: u = -kappa (grad p - rho gamma e_y), rho =
+// lambda_g / lambda per cell, gamma = g dh/dy): the constant part of the
+// flux out of a cell through one of its faces, T gamma d rho for a half
+// cell of transmissibility T and centre-to-face distance d (a face between
+// two cells: T their series transmissibility, d h/2 and rho the sum of the
+// two cells' values), signed by the face's outward normal (+1 on N, -1 on
+// S, 0 on the x-faces).
+__device__ inline double grav_out(const Geo& g, int side, double T, double d, double rho) {
+  return side < 2 ? 0.0 : (side == 3 ? 1.0 : -1.0) * T * g.grav * d * rho;
+}
+
+// the gravity part of the one-sided Robin flux out of cell c (global index)
+// through `side`: T_R gamma d rho_c (n . e_y); zero without gravity
+__device__ inline double robin_grav(const SubArgs& a, int side, size_t c, double TR, double d) {
+  return a.rho ? grav_out(a.g, side, TR, d, a.rho[c]) : 0.0;
+}
 
 // Loaded without branches, each from an address selected per side (the
 // cell's own permeability stands in where the value is not needed), so that
@@ -86,6 +104,12 @@ __device__ inline CellLoads cell_loads(const SubArgs& a, int I, int J, int l, in
     const int e = inner ? 0 : side_iface(g, I, J, side);
     cl.bv[side] = *((!inner && e < 0) ? a.bcv[side] + ((side < 2) ? j : i) : stand);
     cl.av[side] = *((!inner && e >= 0 && robin) ? a.alpha + e : stand);
+  }
+  cl.rc = cl.rs = cl.rn = 0.0;
+  if (a.rho) {
+    cl.rc = a.rho[c];
+    cl.rs = a.rho[lj > 0 ? c - g.nx : c];
+    cl.rn = a.rho[lj < M - 1 ? c + g.nx : c];
   }
   return cl;
 }
@@ -126,6 +150,7 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
       dd_add(diag, dlo, T);
       if (side == 1) cx = -T;
       if (side == 3) cn = -T;
+      if (a.rho) rhs0 -= grav_out(g, side, T, 0.5 * g.hy, cl.rc + (side == 2 ? cl.rs : cl.rn));
       continue;
     }
     const int e = side_iface(g, I, J, side);
@@ -137,6 +162,7 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
       if (g.kind[side] == 1) {
         dd_add(diag, dlo, th);
         rhs0 += th * v;
+        if (a.rho) rhs0 -= grav_out(g, side, th, 0.5 * g.hy, cl.rc);
       } else {
         rhs0 -= v * flen;
       }
@@ -149,6 +175,8 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
       const double beta = al * sg.H / kc;
       const double sig = side_sigma(side);
       dd_add(diag, dlo, TR);
+      // gravity through the Robin face: data of the particular solution
+      if (a.rho) rhs0 -= grav_out(g, side, TR, sg.dist, cl.rc);
       if (SIDES) {
         const int D = g.D;
         const double* bs = a.basis + (size_t)e * D * M;
@@ -229,7 +257,12 @@ __device__ inline void stitch_out_fluxes(const SubArgs& a, int I, int J, int l, 
     if (inner) {
       const int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
       const double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
-      out[side] = series2(side < 2 ? txc : tyc, tn) * dd_diff(pv, pvl, ph[nb], pl ? pl[nb] : 0.0);
+      const double T = series2(side < 2 ? txc : tyc, tn);
+      out[side] = T * dd_diff(pv, pvl, ph[nb], pl ? pl[nb] : 0.0);
+      if (a.rho && side >= 2) {
+        const size_t c = (size_t)j * g.nx + i;
+        out[side] += grav_out(g, side, T, 0.5 * g.hy, a.rho[c] + a.rho[side == 2 ? c - g.nx : c + g.nx]);
+      }
     } else {
       const int e = side_iface(g, I, J, side);
       const int t = (side < 2) ? lj : li;
@@ -239,6 +272,7 @@ __device__ inline void stitch_out_fluxes(const SubArgs& a, int I, int J, int l, 
         const double flen = (side < 2) ? g.hy : g.hx;
         const double v = a.bcv[side][(side < 2) ? j : i];
         out[side] = (g.kind[side] == 1) ? ((side < 2) ? txc : tyc) * dd_diff(pv, pvl, v, 0.0) : v * flen;
+        if (a.rho && g.kind[side] == 1) out[side] += grav_out(g, side, tyc, 0.5 * g.hy, a.rho[(size_t)j * g.nx + i]);
       }
     }
   }
@@ -270,7 +304,12 @@ __device__ inline double stitch_balance_residual(const SubArgs& a, int I, int J,
     if (inner) {
       const int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
       const double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
-      out = series2(th, tn) * dd_diff(pv, 0.0, ph[nb], 0.0);
+      const double T = series2(th, tn);
+      out = T * dd_diff(pv, 0.0, ph[nb], 0.0);
+      if (a.rho && side >= 2) {
+        const size_t c = (size_t)j * g.nx + i;
+        out += grav_out(g, side, T, 0.5 * g.hy, a.rho[c] + a.rho[side == 2 ? c - g.nx : c + g.nx]);
+      }
     } else {
       const int e = side_iface(g, I, J, side);
       if (e >= 0) {
@@ -279,6 +318,7 @@ __device__ inline double stitch_balance_residual(const SubArgs& a, int I, int J,
         const double flen = (side < 2) ? g.hy : g.hx;
         const double v = a.bcv[side][(side < 2) ? j : i];
         out = (g.kind[side] == 1) ? th * dd_diff(pv, 0.0, v, 0.0) : v * flen;
+        if (a.rho && g.kind[side] == 1) out += grav_out(g, side, th, 0.5 * g.hy, a.rho[(size_t)j * g.nx + i]);
       }
     }
     dd_add(hi, lo, -out);
@@ -327,7 +367,9 @@ __device__ void generic_block(const SubArgs& a, int sd, int I, int J, const doub
         const double beta = al * sg.H / kk;
         double gv = 0.0;
         if (colside) gv = (kc < nP) ? bs[kc * M + t] : -beta * sig * bs[kc * M + t];
-        const double F = TR * (Xs[(size_t)l * ls + (size_t)col * cs] - gv);
+        double F = TR * (Xs[(size_t)l * ls + (size_t)col * cs] - gv);
+        if (col == 0 && a.rho)
+          F += robin_grav(a, side, (size_t)(J * M + l / M) * g.nx + I * M + l % M, TR, sg.dist);
         if (k < nP) sum += bs[k * M + t] * F;
         else sum += bs[k * M + t] * (gv + beta * F / sg.flen);
       }

@@ -87,6 +87,7 @@ __device__ inline double side_rhs(const double (*bside)[M][D], int lj, int li, i
 struct Faces {
   double tr[4][M], bt[4][M], bl[4][M];
   double phi[4][D][M];
+  double gr[4][M];   // gravity part of the particular solution's Robin flux (0 without gravity)
 };
 
 // The global data of a face (its interface's alpha and functions), loaded
@@ -119,19 +120,25 @@ __device__ inline FaceLoad load_faces(const SubArgs& a, int I, int J) {
   return fl;
 }
 
-__device__ inline void prepare_faces(const SubArgs& a, const FaceLoad& fl, const double* kap, Faces& f) {
+__device__ inline void prepare_faces(const SubArgs& a, const FaceLoad& fl, const double* kap, Faces& f,
+                                     int I, int J) {
   const Geo& g = a.g;
   const int l = threadIdx.x;
   if (l < 4 * M) {
     const int side = l >> 4, t = l & 15;
-    double tr = 0.0, bt = 0.0, bl = 0.0;
+    double tr = 0.0, bt = 0.0, bl = 0.0, gr = 0.0;
     if (fl.e >= 0) {
       const SideGeo sg = side_geo(g, side);
-      const double kk = kap[side_cell<M>(side, t)];
+      const int lc = side_cell<M>(side, t);
+      const double kk = kap[lc];
       tr = sg.flen * kk / (sg.dist + fl.al * sg.H);
       bt = fl.al * sg.H / kk;
       bl = bt / sg.flen;
+      if (a.rho) {
+        gr = robin_grav(a, side, (size_t)(J * M + lc / M) * g.nx + I * M + lc % M, tr, sg.dist);
+      }
     }
+    f.gr[side][t] = gr;
     f.tr[side][t] = tr;
     f.bt[side][t] = bt;
     f.bl[side][t] = bl;
@@ -190,7 +197,7 @@ __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const
       for (int t = 0; t < M; ++t) {
         const double ph = f.phi[side][kc][t];
         const double gv = gscale * (flux_col ? -f.bt[side][t] * sig * ph : ph);
-        const double F = f.tr[side][t] * (xb[side][t][col] - gv);
+        const double F = f.tr[side][t] * (xb[side][t][col] - gv) + (col == 0 ? f.gr[side][t] : 0.0);
         const double wu = fma(f.bl[side][t], F, gv);
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] = fma(f.phi[side][k][t], k < nP ? F : wu, acc[k]);
@@ -262,7 +269,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
   for (int q = 0; q < MM / PAIR; ++q)
     assemble_cell<M, 1, false>(a, I, J, tid + PAIR * q, kap, dg, ex, cy, b0 + tid + PAIR * q, 1, nullptr,
                                cl[q], dgl);
-  prepare_faces(a, fl, kap, fc);
+  prepare_faces(a, fl, kap, fc, I, J);
   __syncthreads();
   robin_data(g, fc, bside);
   __syncthreads();
@@ -1054,7 +1061,7 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
   for (int q = 0; q < MM / PAIR; ++q)
     assemble_cell<M, 1, false>(a, I, J, tid + PAIR * q, sh.kap, sh.dg, sh.ex, sh.cy,
                                sh.b0 + tid + PAIR * q, 1, nullptr, cl[q], sh.dgl);
-  prepare_faces(a, fl, sh.kap, sh.fc);
+  prepare_faces(a, fl, sh.kap, sh.fc, I, J);
   for (int l = tid; l < MM; l += PAIR) sh.dsc[l] = 1.0 / sqrt(sh.dg[l]);
   __syncthreads();
   robin_data(g, sh.fc, sh.bside);
@@ -1236,6 +1243,7 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
   const int side = lane >> 4, t = lane & 15;
   const int e = tid < 4 * M ? side_iface(g, I, J, side) : -1;
   double pn = 0.0, kn = 1.0, al = 0.0, PH = 0.0, UH = 0.0;
+  size_t nc_g = 0;   // the neighbour's cell (global index)
   if (e >= 0) {
     // interface data of the face: alpha and the interface pressure / flux
     // P_H, U_H = sum of coefficient times interface function
@@ -1249,6 +1257,7 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
     const int nI = nsd % g.SX, nJ = nsd / g.SX;
     const int nl = side_cell<M>(nside, t);
     const size_t nc = (size_t)(nJ * M + nl / M) * g.nx + nI * M + nl % M;
+    nc_g = nc;
     kn = a.K[nc] * a.lam[nc];
     double cfn[4 * D];
 #pragma unroll
@@ -1271,10 +1280,13 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
       const int l = side_cell<M>(side, t);
       const double sig = side_sigma(side);
       const double ko = kap[l];
-      const double Fown = sg.flen * ko / (sg.dist + al * sg.H) *
-                          (pm[l] - (PH - al * sg.H / ko * sig * UH));
-      const double Fnb = sg.flen * kn / (sg.dist + al * sg.H) *
-                         (pn - (PH - al * sg.H / kn * (-sig) * UH));
+      const double TRo = sg.flen * ko / (sg.dist + al * sg.H), TRn = sg.flen * kn / (sg.dist + al * sg.H);
+      double Fown = TRo * (pm[l] - (PH - al * sg.H / ko * sig * UH));
+      double Fnb = TRn * (pn - (PH - al * sg.H / kn * (-sig) * UH));
+      if (a.rho) {
+        Fown += robin_grav(a, side, (size_t)(J * M + l / M) * g.nx + I * M + l % M, TRo, sg.dist);
+        Fnb += robin_grav(a, side ^ 1, nc_g, TRn, sg.dist);
+      }
       fo = 0.5 * (Fown - Fnb);
     }
     Fout[side][t] = fo;
@@ -1511,7 +1523,7 @@ __global__ void __launch_bounds__(GATE) surrogate_gate_kernel(SubArgs a, const f
     const double kgeo = exp(mean_log_kappa(kap));
     if (lane < 4 * D) scale[lane] = column_scale(a, I, J, lane, kgeo);
   }
-  prepare_faces(a, fl, kap, fc);
+  prepare_faces(a, fl, kap, fc, I, J);
   __syncthreads();
   robin_data(g, fc, bside);
   {

@@ -620,7 +620,9 @@ __global__ void __launch_bounds__(PAIR, 2) stitch32x32_kernel(SubArgs a) {
       const int l = side_cell<M>(side, t);
       const double sig = side_sigma(side);
       const double ko = sh.kap[l];
-      const double Fown = sg.flen * ko / (sg.dist + al * sg.H) * (sh.pm[l] - (PH - al * sg.H / ko * sig * UH));
+      const double TRo = sg.flen * ko / (sg.dist + al * sg.H);
+      const double Fown = TRo * (sh.pm[l] - (PH - al * sg.H / ko * sig * UH)) +
+                          robin_grav(a, side, (size_t)(J * M + l / M) * g.nx + I * M + l % M, TRo, sg.dist);
       const int nsd = (side == 0) ? sd - 1 : (side == 1) ? sd + 1 : (side == 2) ? sd - g.SX : sd + g.SX;
       const int nI = nsd % g.SX, nJ = nsd / g.SX;
       const int nl = side_cell<M>(side ^ 1, t);
@@ -633,7 +635,8 @@ __global__ void __launch_bounds__(PAIR, 2) stitch32x32_kernel(SubArgs a) {
         cfn[q] = en >= 0 ? a.coef[(size_t)en * D + q % D] : 0.0;
       }
       const double pn = compose32(a, nsd, nl, cfn);
-      const double Fnb = sg.flen * kn / (sg.dist + al * sg.H) * (pn - (PH - al * sg.H / kn * (-sig) * UH));
+      const double TRn = sg.flen * kn / (sg.dist + al * sg.H);
+      const double Fnb = TRn * (pn - (PH - al * sg.H / kn * (-sig) * UH)) + robin_grav(a, side ^ 1, nc, TRn, sg.dist);
       fo = 0.5 * (Fown - Fnb);
     }
     sh.Fout[side][t] = fo;

@@ -30,6 +30,7 @@ struct Geo {
   int prec;         // 0: FP64 local solves, 1: FP32 + FP64 iterative refinement,
                     // 2: surrogate + residual gate + FP64 re-solve
   double hx, hy;
+  double grav;      // gravity along y, g dh/dy (used where SubArgs::rho is set)
 };
 
 // Device data of a context used by the subdomain kernels.
@@ -38,6 +39,7 @@ struct SubArgs {
   const double* K;        // nx*ny absolute permeability
   const double* lam;      // nx*ny total mobility
   const double* src;      // nx*ny source per unit area, or nullptr
+  const double* rho;      // nx*ny lambda_g / lambda (gravity), or nullptr (no gravity)
   const double* bcv[4];   // boundary values per side (ny, ny, nx, nx)
   const double* alpha;    // per interface
   const double* basis;    // [iface][D][M]: rows 0..nP-1 pressure, nP..D-1 flux functions
@@ -110,6 +112,9 @@ hipError_t launch_local_basis(const SubArgs& a, hipStream_t st);
 hipError_t launch_stitch(const SubArgs& a, hipStream_t st);
 hipError_t launch_mobility(const double* in, double* lam, size_t n, int from_saturation,
                            double mu_w, double mu_o, hipStream_t st);
+// total mobility and lambda_g / lambda from a saturation (gravity)
+hipError_t launch_mobility_gravity(const double* s, double* lam, double* rho, size_t n, double mu_w,
+                                   double mu_o, double rho_w, double rho_o, hipStream_t st);
 hipError_t launch_finish_flux(const SubArgs& a, double* result, hipStream_t st);
 // (local_mfma.hip) 16 x 16 subdomains, 2 + 2 interface dofs (FP64: two wavefronts per subdomain)
 hipError_t launch_basis_m16d4(const SubArgs& a, hipStream_t st);

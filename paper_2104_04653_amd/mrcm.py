@@ -27,7 +27,7 @@ EXPORTED = [
     "mrcm_step", "mrcm_get_stats",
     "mrcm_get_sizes", "mrcm_get_interface_solution", "mrcm_get_local_blocks",
     "mrcm_get_basis", "mrcm_surrogate_inputs", "mrcm_surrogate_targets", "mrcm_set_surrogate",
-    "mrcm_solve_with_predictions", "mrcm_set_gate_tolerance", "mrcm_set_refinement",
+    "mrcm_solve_with_predictions", "mrcm_set_gate_tolerance", "mrcm_set_refinement", "mrcm_set_gravity",
     "mrcm_set_interface_refinement", "mrcm_transport_step", "mrcm_si_step", "mrcm_sfi_step",
     "mrcm_cnn_create", "mrcm_cnn_num_params",
     "mrcm_cnn_get_params", "mrcm_cnn_set_params", "mrcm_cnn_forward", "mrcm_cnn_loss_grad",
@@ -119,6 +119,7 @@ def load_library(path: str = LIB_PATH):
     lib.mrcm_solve_with_predictions.argtypes = [P, P]
     lib.mrcm_set_gate_tolerance.argtypes = [P, ctypes.c_double]
     lib.mrcm_set_refinement.argtypes = [P, ctypes.c_int32, ctypes.c_double]
+    lib.mrcm_set_gravity.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.mrcm_transport_step.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_int32, ctypes.POINTER(TransportStats)]
     lib.mrcm_si_step.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -222,6 +223,12 @@ class MRCMSolver:
         n_dof, n_sub, n_cols = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         self.lib.mrcm_get_sizes(self.ctx, ctypes.byref(n_dof), ctypes.byref(n_sub), ctypes.byref(n_cols))
         self.n_dof, self.n_sub, self.n_cols = n_dof.value, n_sub.value, n_cols.value
+        if getattr(prob, "gravity", 0.0) != 0.0:
+            try:
+                self.set_gravity(prob.gravity, prob.rho_w, prob.rho_o)
+            except MRCMError:
+                self.close()
+                raise
 
     # -- helpers ----------------------------------------------------------
     def _check(self, rc, what):
@@ -445,6 +452,12 @@ class MRCMSolver:
                                            int(max_newton), float(outer_tol), int(max_outer),
                                            ctypes.byref(st)), "mrcm_sfi_step")
         return {k: getattr(st, k) for k, _ in SFIStats._fields_}
+
+    def set_gravity(self, gravity: float, rho_w: float, rho_o: float):
+        """mrcm_set_gravity: g dh/dy along y and the phase densities (0 turns
+        the gravity variant off)."""
+        self._check(self.lib.mrcm_set_gravity(self.ctx, float(gravity), float(rho_w), float(rho_o)),
+                    "mrcm_set_gravity")
 
     def set_refinement(self, max_steps: int, tol: float):
         """Stopping rule of the FP32 + FP64 local refinement (fp32_ir)."""
