@@ -30,7 +30,8 @@ DIRICHLET = 1
 SPACE_LINEAR = "linear"
 SPACE_EDGE = "edge"      # edge-solution spaces built from local 1-D problems
 SPACE_FULL = "full"      # all fine-edge indicator functions
-SPACES = (SPACE_LINEAR, SPACE_EDGE, SPACE_FULL)
+SPACE_PHYSICS = "physics"  # channel / barrier spaces of section 3.1 (at most 4 + 4 slots)
+SPACES = (SPACE_LINEAR, SPACE_EDGE, SPACE_FULL, SPACE_PHYSICS)
 
 
 @dataclasses.dataclass
@@ -53,6 +54,9 @@ class Problem:
     u_dofs: int = 2
     alpha: float = 1.0
     alpha_per_interface: Optional[np.ndarray] = None
+    # adaptive Robin parameter: (alpha on interfaces crossed by a
+    # high-permeability channel, alpha elsewhere), or None
+    adaptive_alpha: Optional[tuple] = None
     seed: int = 1
     steps: int = 1                        # time steps of the two-phase workload
     # gravity: the term lambda_g g grad h of Darcy's law with gravity, acting
@@ -158,6 +162,8 @@ def make_problem(workload: str, seed: int = 1, **over) -> Problem:
     sub = spec["sub"]
     if space == SPACE_FULL:
         pd = ud = sub
+    elif space == SPACE_PHYSICS:
+        pd = ud = 4          # slots: up to 2 channels (4 pressure) and 1 barrier (3 flux)
     else:
         pd = ud = 2
     return Problem(name=workload, nx=nx, ny=ny, lx=lx, ly=ly, perm=perm,

@@ -245,6 +245,113 @@ def edge_solution_space(k_lo, k_hi):
     return pspace, uspace
 
 
+# Physics-based spaces (section 3.1, eqs. (new_basis1)-(new_basis6)) and the
+# adaptive Robin parameter.  Readings (the paper gives the functions for
+# given channel and barrier supports, not how the supports are found):
+# * t_j, the harmonic mean of the permeabilities across fine face j, is
+#   compared with the median of t over the interface: faces with
+#   t_j >= 10 median are high-permeability, faces with t_j <= median / 10
+#   low-permeability; maximal runs of such faces are the channels and the
+#   barriers, face j covering [j/m, (j+1)/m] of the normalised interface;
+# * at most NH_MAX channels and NL_MAX barriers are kept (the widest, the
+#   left one first on ties), the others count as background;
+# * a space whose kind of structure is absent is the linear space (the
+#   paper's rule for interfaces without structures, applied per space);
+# * functions with no support (a structure touching the interface end) are
+#   left out, so a space has at most 2 + NH_MAX pressure and 1 + 2 NL_MAX
+#   flux functions;
+# * alpha: alpha_channel on interfaces crossed by a kept channel,
+#   alpha_other elsewhere (section 5.5 uses 1e-2 and 1e2).
+NH_MAX, NL_MAX = 2, 1
+STRUCTURE_RATIO = 10.0
+
+
+def face_conductance(k_lo, k_hi):
+    """t_j: the harmonic mean of the permeabilities on both sides of face j."""
+    return harmonic_mean(np.asarray(k_lo, float), np.asarray(k_hi, float))
+
+
+def _runs(mask):
+    """Maximal runs of True in mask as (first, last) face indices."""
+    runs, j, m = [], 0, mask.size
+    while j < m:
+        if mask[j]:
+            k = j
+            while k + 1 < m and mask[k + 1]:
+                k += 1
+            runs.append((j, k))
+            j = k + 1
+        else:
+            j += 1
+    return runs
+
+
+def _keep_widest(runs, n):
+    order = sorted(range(len(runs)), key=lambda r: (-(runs[r][1] - runs[r][0]), runs[r][0]))
+    return sorted(runs[r] for r in order[:n])
+
+
+def classify_interface(t):
+    """(channels, barriers): kept runs of high and low faces of one interface."""
+    t = np.asarray(t, float)
+    med = float(np.median(t))
+    high = _runs(t >= STRUCTURE_RATIO * med)
+    low = _runs(t <= med / STRUCTURE_RATIO)
+    return _keep_widest(high, NH_MAX), _keep_widest(low, NL_MAX)
+
+
+def physics_pressure_space(channels, m):
+    """Eqs. (new_basis1)-(new_basis3) at the face midpoints, for channels
+    given as face runs; the functions with no support are left out."""
+    x = (np.arange(m) + 0.5) / m
+    a = [j0 / m for j0, _ in channels]
+    b = [(j1 + 1) / m for _, j1 in channels]
+    n = len(channels)
+    funcs = []
+    # psi_0: falls from 1 at the interface start to 0 where channel 1 begins
+    if a[0] > 0.0:
+        funcs.append(np.where(x < a[0], (a[0] - x) / a[0], 0.0))
+    for k in range(n):
+        lo = 0.0 if k == 0 else b[k - 1]          # b_0 = a
+        hi = 1.0 if k == n - 1 else a[k + 1]      # a_{N+1} = b
+        f = np.zeros(m)
+        up = (x > lo) & (x < a[k])
+        f[up] = (x[up] - lo) / (a[k] - lo)
+        f[(x >= a[k]) & (x <= b[k])] = 1.0
+        down = (x > b[k]) & (x < hi)
+        f[down] = (hi - x[down]) / (hi - b[k])
+        funcs.append(f)
+    # psi_{N+1}: rises from 0 where the last channel ends to 1 at the end
+    if b[-1] < 1.0:
+        funcs.append(np.where(x > b[-1], (x - b[-1]) / (1.0 - b[-1]), 0.0))
+    return np.stack(funcs)
+
+
+def physics_flux_space(barriers, m):
+    """Eqs. (new_basis4)-(new_basis6): indicators of the segments before,
+    on and after each barrier; the empty ones are left out."""
+    x = (np.arange(m) + 0.5) / m
+    edges = [0.0]
+    for j0, j1 in barriers:
+        edges += [j0 / m, (j1 + 1) / m]
+    edges.append(1.0)
+    funcs = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        if hi > lo:
+            funcs.append(((x > lo) & (x < hi)).astype(np.float64))
+    return np.stack(funcs)
+
+
+def physics_space(t):
+    """(pressure functions, flux functions) of one interface from t."""
+    m = np.asarray(t).size
+    channels, barriers = classify_interface(t)
+    xi = (np.arange(m) + 0.5) / m
+    ps = physics_pressure_space(channels, m) if channels else linear_space(xi)
+    us = physics_flux_space(barriers, m) if barriers else linear_space(xi)
+    return ps, us
+
+
 def interface_spaces(geom, prob):
     """Per interface: (psi [nP, m], phi [nU, m]) evaluated on its fine faces."""
     out = []
@@ -265,6 +372,8 @@ def interface_spaces(geom, prob):
             if prob.p_dofs != 2 or prob.u_dofs != 2:
                 raise ValueError("edge-solution spaces have 2 + 2 functions")
             ps, us = edge_solution_space(perm[itf.lo_cells], perm[itf.hi_cells])
+        elif prob.space == "physics":
+            ps, us = physics_space(face_conductance(perm[itf.lo_cells], perm[itf.hi_cells]))
         elif prob.space == "custom":
             ps, us = prob.custom_space(itf)
         else:
@@ -274,6 +383,14 @@ def interface_spaces(geom, prob):
 
 
 def interface_alpha(geom, prob):
+    if prob.adaptive_alpha is not None:
+        a_ch, a_other = prob.adaptive_alpha
+        out = np.empty(geom.n_iface)
+        for itf in geom.interfaces:
+            channels, _ = classify_interface(face_conductance(prob.perm[itf.lo_cells],
+                                                              prob.perm[itf.hi_cells]))
+            out[itf.index] = a_ch if channels else a_other
+        return out
     if prob.alpha_per_interface is not None:
         a = np.asarray(prob.alpha_per_interface, dtype=np.float64)
         if a.shape != (geom.n_iface,):

@@ -263,3 +263,69 @@ def test_gravity_robin_distance_caught(monkeypatch):
         return recs
     monkeypatch.setattr(om, "_side_records", doubled)
     assert not _gravity_pins_pass()
+
+
+# ---------------------------------------------------------------------------
+# physics-based interface spaces (section 3.1)
+# ---------------------------------------------------------------------------
+
+from tests import test_oracle_physics_spaces as PS  # noqa: E402
+
+PHYSICS_PINS = [lambda seed=seed: PS.test_pressure_functions(seed) for seed in range(12)] + \
+    [lambda seed=seed: PS.test_flux_functions(seed) for seed in range(8)] + [
+    lambda: PS.test_no_structure_gives_the_linear_space(),
+    lambda: PS.test_classification(),
+    lambda: PS.test_barrier_flux_space_is_exact_where_linear_is_not(),
+]
+
+
+def _physics_pins_pass():
+    for pin in PHYSICS_PINS:
+        try:
+            pin()
+        except AssertionError:
+            return False
+    return True
+
+
+def test_unmodified_oracle_passes_physics_pins():
+    assert _physics_pins_pass()
+
+
+def test_ramp_towards_the_wrong_end_caught(monkeypatch):
+    """psi_0 rising instead of falling across the first segment."""
+    orig = od.physics_pressure_space
+
+    def flipped(channels, m):
+        ps = orig(channels, m)
+        if channels[0][0] > 0:
+            x = (np.arange(m) + 0.5) / m
+            a1 = channels[0][0] / m
+            ps = ps.copy()
+            ps[0] = np.where(x < a1, x / a1, 0.0)
+        return ps
+    monkeypatch.setattr(od, "physics_pressure_space", flipped)
+    monkeypatch.setattr(PS, "physics_pressure_space", flipped)
+    assert not _physics_pins_pass()
+
+
+def test_barrier_segment_off_by_one_caught(monkeypatch):
+    """The barrier indicator one face short at its end."""
+    orig = od.physics_flux_space
+
+    def short(barriers, m):
+        return orig([(j0, max(j0, j1 - 1)) for j0, j1 in barriers], m)
+    monkeypatch.setattr(od, "physics_flux_space", short)
+    monkeypatch.setattr(PS, "physics_flux_space", short)
+    assert not _physics_pins_pass()
+
+
+def test_classification_against_the_mean_caught(monkeypatch):
+    """Structures judged against the mean conductance instead of the median
+    (a channel then raises the reference and is no longer found)."""
+    orig_median = np.median
+    monkeypatch.setattr(od.np, "median", lambda t: float(np.mean(t)))
+    try:
+        assert not _physics_pins_pass()
+    finally:
+        monkeypatch.setattr(od.np, "median", orig_median)
