@@ -63,7 +63,7 @@ enum { MRCM_BC_NEUMANN = 0, MRCM_BC_DIRICHLET = 1 };
  * does not define this space (its own physics-based spaces are those of
  * eqs. (new_basis1)-(new_basis6)), so it is a reading of "spaces built from
  * local edge solutions".  FULL: every fine-edge indicator (m + m dofs). */
-enum { MRCM_SPACE_LINEAR = 0, MRCM_SPACE_EDGE_SOLUTION = 1, MRCM_SPACE_FULL = 2 };
+enum { MRCM_SPACE_LINEAR = 0, MRCM_SPACE_EDGE_SOLUTION = 1, MRCM_SPACE_FULL = 2, MRCM_SPACE_PHYSICS = 3 };
 
 /* Precision of the local (subdomain) factorisations.  The interface system
  * is always solved in FP64.  FP32_IR: FP32 factors and solves of the
@@ -124,7 +124,17 @@ typedef struct {
  *  sub_nx/ny  : subdomain size in cells; this build requires
  *               sub_nx == sub_ny in {4, 8, 16, 32}.
  *  space      : MRCM_SPACE_*; p_dofs/u_dofs must match the space (2, 2 for
- *               LINEAR and EDGE_SOLUTION, sub_nx each for FULL).
+ *               LINEAR and EDGE_SOLUTION, sub_nx each for FULL, 4, 4 for
+ *               PHYSICS).  PHYSICS: the channel and barrier spaces of section
+ *               3.1, eqs. (new_basis1)-(new_basis6), built per interface from
+ *               K: faces whose conductance (harmonic mean of K across the
+ *               face) is at least 10 times the interface's median form
+ *               channels, at most a tenth of it barriers; at most 2 channels
+ *               and 1 barrier are kept (the widest); a space with no
+ *               structure of its kind is linear.  The 4 + 4 dofs per
+ *               interface are slots: the interface's pressure functions
+ *               first, then its flux functions; unused slots are fixed to 0.
+ *               FP64 only (the generic kernels).
  *  alpha_per_interface : host, one alpha > 0 per interface (eq. (beta)), or
  *               NULL to use alpha_scalar everywhere.
  *  bc, source : boundary data (deep-copied) and q per unit area (host,
@@ -194,6 +204,14 @@ int mrcm_set_refinement(mrcm_ctx* ctx, int32_t max_steps, double tol);
  * is still accurate).  Takes effect at the next solve.  Errors: MRCM_E_INVAL
  * unless 0 <= max_steps <= 16, 0 < tol < 1 and 0 < fail_tol < 1. */
 int mrcm_set_interface_refinement(mrcm_ctx* ctx, int32_t max_steps, double tol, double fail_tol);
+
+/* Adaptive Robin parameter (section 3.1, last paragraph; section 5.5):
+ * alpha_channel on every interface crossed by a high-permeability channel
+ * (the classification of MRCM_SPACE_PHYSICS, made for every space) and
+ * alpha_other elsewhere; replaces the alpha given to mrcm_setup.  Takes
+ * effect at the next solve.  Errors: MRCM_E_INVAL unless both are finite
+ * and > 0. */
+int mrcm_set_adaptive_alpha(mrcm_ctx* ctx, double alpha_channel, double alpha_other);
 
 /* Gravity variant of the pressure equation (section 5.5, eqs. (Darcy_wg) and
  * (fluxos1_wg)): u = -K (lambda grad p - lambda_g g grad h), gravity along

@@ -4,6 +4,7 @@
 // of every entry point are in include/mrcm.h.
 #include "../../include/mrcm.h"
 #include "mrcm_internal.h"
+#include "physics_space.h"
 
 #include <math.h>
 #include <stdio.h>
@@ -19,6 +20,7 @@
 #include <vector>
 
 using namespace mrcm;
+using namespace mrcm::phys;
 
 // Scratch of mrcm_fine_flux_static: the stitch's per-subdomain statistics
 // (max cell imbalance, max |F|, pressure sum: 3 doubles per subdomain) and
@@ -119,6 +121,10 @@ struct mrcm_ctx {
   double grav = 0.0, rho_w = 0.0, rho_o = 0.0;
   double* rho = nullptr;
   bool rho_valid = false;                 // rho holds the last saturation's values
+  // per interface: crossed by a high-permeability channel (adaptive alpha);
+  // physics spaces: numbers of active pressure and flux functions
+  std::vector<char> has_channel;
+  int2* nact = nullptr;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // solve start, local end, gate end
   unsigned long long* stamps = nullptr;   // device, inside the report block
   double clock_khz = 0.0;                 // rate of the clock the kernels read
@@ -560,6 +566,7 @@ SubArgs sub_args(const mrcm_ctx* c) {
   a.lam = c->lam;
   a.src = c->src;
   a.rho = c->grav != 0.0 ? c->rho : nullptr;
+  a.nact = c->nact;
   a.g.grav = c->grav;
   for (int s = 0; s < 4; ++s) a.bcv[s] = c->bcv[s];
   a.alpha = c->alpha;
@@ -671,6 +678,8 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
     if (p_dofs != 2 || u_dofs != 2) return MRCM_E_INVAL;
   } else if (space == MRCM_SPACE_FULL) {
     if (p_dofs != M || u_dofs != M) return MRCM_E_INVAL;
+  } else if (space == MRCM_SPACE_PHYSICS) {
+    if (p_dofs != PHYS_P || u_dofs != PHYS_U) return MRCM_E_INVAL;
   } else {
     return MRCM_E_INVAL;
   }
@@ -810,12 +819,39 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
     std::vector<double> al(std::max(n_iface, 1), alpha_scalar);
     if (alpha_per_interface) std::copy(alpha_per_interface, alpha_per_interface + n_iface, al.begin());
     HIPCHK(c, hipMemcpy(c->alpha, al.data(), al.size() * sizeof(double), hipMemcpyHostToDevice));
-    // interface functions, rows [psi_0.., phi_0..] per interface
+    // interface functions, rows [psi_0.., phi_0..] per interface; the
+    // channels of every interface (adaptive alpha)
     std::vector<double> bs((size_t)std::max(n_iface, 1) * G.D * M, 0.0);
-    std::vector<double> klo(M), khi(M);
+    std::vector<double> klo(M), khi(M), tf(M);
+    std::vector<int2> nact(std::max(n_iface, 1), make_int2(0, 0));
+    c->has_channel.assign(std::max(n_iface, 1), 0);
     for (int e = 0; e < n_iface; ++e) {
       double* b = bs.data() + (size_t)e * G.D * M;
-      if (space == MRCM_SPACE_LINEAR) {
+      for (int t = 0; t < M; ++t) {
+        size_t cl, ch;
+        if (e < G.nV) {
+          const int J = e / (SX - 1), I = e % (SX - 1);
+          const int i = (I + 1) * M, j = J * M + t;
+          cl = (size_t)j * G.nx + i - 1;
+          ch = (size_t)j * G.nx + i;
+        } else {
+          const int h = e - G.nV, J = h / SX, I = h % SX;
+          const int j = (J + 1) * M, i = I * M + t;
+          cl = (size_t)(j - 1) * G.nx + i;
+          ch = (size_t)j * G.nx + i;
+        }
+        klo[t] = perm[cl];
+        khi[t] = perm[ch];
+        tf[t] = hmean(klo[t], khi[t]);
+      }
+      {
+        std::vector<Run> chn, bar;
+        classify_faces(tf, chn, bar);
+        c->has_channel[e] = !chn.empty();
+      }
+      if (space == MRCM_SPACE_PHYSICS) {
+        physics_space(tf, b, M, nact[e].x, nact[e].y);
+      } else if (space == MRCM_SPACE_LINEAR) {
         for (int t = 0; t < M; ++t) {
           const double xi = (t + 0.5) / M;
           b[0 * M + t] = 1.0 - xi;
@@ -829,26 +865,14 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
           b[(M + k) * M + k] = 1.0;
         }
       } else {
-        for (int t = 0; t < M; ++t) {
-          size_t cl, ch;
-          if (e < G.nV) {
-            const int J = e / (SX - 1), I = e % (SX - 1);
-            const int i = (I + 1) * M, j = J * M + t;
-            cl = (size_t)j * G.nx + i - 1;
-            ch = (size_t)j * G.nx + i;
-          } else {
-            const int h = e - G.nV, J = h / SX, I = h % SX;
-            const int j = (J + 1) * M, i = I * M + t;
-            cl = (size_t)(j - 1) * G.nx + i;
-            ch = (size_t)j * G.nx + i;
-          }
-          klo[t] = perm[cl];
-          khi[t] = perm[ch];
-        }
         edge_solution(klo, khi, b, M);
       }
     }
     HIPCHK(c, hipMemcpy(c->basis, bs.data(), bs.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (space == MRCM_SPACE_PHYSICS) {
+      ALLOC(c, c->nact, nact.size());
+      HIPCHK(c, hipMemcpy(c->nact, nact.data(), nact.size() * sizeof(int2), hipMemcpyHostToDevice));
+    }
     int r = build_plan(c);
     if (r != MRCM_OK) return r;
     r = bind_static_scratch(c);
@@ -904,6 +928,20 @@ int mrcm_update_mobility(mrcm_ctx* c, const double* values, int32_t values_are_l
   r = mobility_enqueue(c, src, values_are_lambda);
   if (r != MRCM_OK) return r;
   if (!on_device) HIPCHK(c, hipStreamSynchronize(c->st));  // host buffer may be reused on return
+  c->solved = false;
+  return MRCM_OK;
+}
+
+int mrcm_set_adaptive_alpha(mrcm_ctx* c, double alpha_channel, double alpha_other) {
+  if (!c) return MRCM_E_INVAL;
+  if (!finite_pos(alpha_channel) || !finite_pos(alpha_other))
+    return fail(c, MRCM_E_INVAL, "mrcm_set_adaptive_alpha: values must be finite and > 0");
+  const int n_iface = (c->g.SX - 1) * c->g.SY + c->g.SX * (c->g.SY - 1);
+  if (n_iface == 0) return MRCM_OK;
+  std::vector<double> al(n_iface);
+  for (int e = 0; e < n_iface; ++e) al[e] = c->has_channel[e] ? alpha_channel : alpha_other;
+  HIPCHK(c, hipStreamSynchronize(c->st));   // no kernel of the context still reads alpha
+  HIPCHK(c, hipMemcpy(c->alpha, al.data(), n_iface * sizeof(double), hipMemcpyHostToDevice));
   c->solved = false;
   return MRCM_OK;
 }

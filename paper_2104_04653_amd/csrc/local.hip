@@ -670,6 +670,9 @@ hipError_t dispatch(const SubArgs& a, hipStream_t st, bool stitch) {
   if (M == 16 && D == 4) return launch_pair<16, 4>(a, st, stitch);
   if (M == 8 && D == 4) return launch_pair<8, 4>(a, st, stitch);
   if (M == 4 && D == 4) return launch_pair<4, 4>(a, st, stitch);
+  if (M == 16 && D == 8) return launch_pair<16, 8>(a, st, stitch);
+  if (M == 8 && D == 8) return launch_pair<8, 8>(a, st, stitch);
+  if (M == 32 && D == 8) return launch_pair<32, 8>(a, st, stitch);
   if (M == 8 && D == 16) return launch_pair<8, 16>(a, st, stitch);
   if (M == 4 && D == 8) return launch_pair<4, 8>(a, st, stitch);
   return hipErrorInvalidValue;
@@ -683,7 +686,7 @@ bool local_fp32_supported(int M, int D, int nP) {
 
 bool local_supported(int M, int D) {
   return (M == 32 && D == 4) || (M == 16 && D == 4) || (M == 8 && D == 4) || (M == 4 && D == 4) || (M == 8 && D == 16) ||
-         (M == 4 && D == 8);
+         (M == 4 && D == 8) || (M == 8 && D == 8) || (M == 16 && D == 8) || (M == 32 && D == 8);
 }
 
 long long local_scratch_doubles(const Geo& g) {

@@ -79,6 +79,13 @@ __device__ inline double grav_out(const Geo& g, int side, double T, double d, do
   return side < 2 ? 0.0 : (side == 3 ? 1.0 : -1.0) * T * g.grav * d * rho;
 }
 
+// physics spaces: slot k of interface e holds a function (pressure slots
+// 0 .. nP-1, flux slots nP .. D-1, the first nact[e] of each in use)
+__device__ inline bool slot_active(const SubArgs& a, int e, int k) {
+  const int2 n = a.nact[e];
+  return k < a.g.nP ? k < n.x : k - a.g.nP < n.y;
+}
+
 // the gravity part of the one-sided Robin flux out of cell c (global index)
 // through `side`: T_R gamma d rho_c (n . e_y); zero without gravity
 __device__ inline double robin_grav(const SubArgs& a, int side, size_t c, double TR, double d) {
@@ -380,6 +387,16 @@ __device__ void generic_block(const SubArgs& a, int sd, int I, int J, const doub
         const int r0 = e0side * D;   // local position of global dof 0
         if (r == r0) val = (qc == r0 && e0lo) ? 1.0 : 0.0;
         else if (qc == r0) val = 0.0;
+      }
+      if (a.nact) {
+        // slots beyond the interface's functions: their row and column are
+        // zero, and the lower-index side puts 1 on the diagonal (the dof
+        // is then 0)
+        if (!slot_active(a, e, k)) val = (qc == r && side_sigma(side) > 0) ? 1.0 : 0.0;
+        else if (qc < NBR) {
+          const int es = side_iface(g, I, J, qc / D);
+          if (es >= 0 && !slot_active(a, es, qc % D)) val = 0.0;
+        }
       }
     }
     blk[o] = val;

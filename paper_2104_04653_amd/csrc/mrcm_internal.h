@@ -40,6 +40,8 @@ struct SubArgs {
   const double* lam;      // nx*ny total mobility
   const double* src;      // nx*ny source per unit area, or nullptr
   const double* rho;      // nx*ny lambda_g / lambda (gravity), or nullptr (no gravity)
+  const int2* nact;       // per interface: active pressure / flux functions (physics
+                          // spaces; the other slots are zero), or nullptr (all active)
   const double* bcv[4];   // boundary values per side (ny, ny, nx, nx)
   const double* alpha;    // per interface
   const double* basis;    // [iface][D][M]: rows 0..nP-1 pressure, nP..D-1 flux functions

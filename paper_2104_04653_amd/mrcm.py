@@ -19,7 +19,7 @@ OK, E_INVAL, E_NOMEM, E_HIP, E_NOT_SPD, E_NO_CONV, E_STATE, E_UNSUPPORTED = rang
 ERROR_NAMES = {0: "MRCM_OK", 1: "MRCM_E_INVAL", 2: "MRCM_E_NOMEM", 3: "MRCM_E_HIP",
                4: "MRCM_E_NOT_SPD", 5: "MRCM_E_NO_CONV", 6: "MRCM_E_STATE",
                7: "MRCM_E_UNSUPPORTED"}
-SPACES = {"linear": 0, "edge": 1, "full": 2}
+SPACES = {"linear": 0, "edge": 1, "full": 2, "physics": 3}
 PRECISIONS = {"fp64": 0, "fp32_ir": 1, "surrogate": 2}
 
 EXPORTED = [
@@ -28,6 +28,7 @@ EXPORTED = [
     "mrcm_get_sizes", "mrcm_get_interface_solution", "mrcm_get_local_blocks",
     "mrcm_get_basis", "mrcm_surrogate_inputs", "mrcm_surrogate_targets", "mrcm_set_surrogate",
     "mrcm_solve_with_predictions", "mrcm_set_gate_tolerance", "mrcm_set_refinement", "mrcm_set_gravity",
+    "mrcm_set_adaptive_alpha",
     "mrcm_set_interface_refinement", "mrcm_transport_step", "mrcm_si_step", "mrcm_sfi_step",
     "mrcm_cnn_create", "mrcm_cnn_num_params",
     "mrcm_cnn_get_params", "mrcm_cnn_set_params", "mrcm_cnn_forward", "mrcm_cnn_loss_grad",
@@ -120,6 +121,7 @@ def load_library(path: str = LIB_PATH):
     lib.mrcm_set_gate_tolerance.argtypes = [P, ctypes.c_double]
     lib.mrcm_set_refinement.argtypes = [P, ctypes.c_int32, ctypes.c_double]
     lib.mrcm_set_gravity.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.mrcm_set_adaptive_alpha.argtypes = [P, ctypes.c_double, ctypes.c_double]
     lib.mrcm_transport_step.argtypes = [P, P, P, P, P, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_int32, ctypes.POINTER(TransportStats)]
     lib.mrcm_si_step.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -223,12 +225,14 @@ class MRCMSolver:
         n_dof, n_sub, n_cols = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         self.lib.mrcm_get_sizes(self.ctx, ctypes.byref(n_dof), ctypes.byref(n_sub), ctypes.byref(n_cols))
         self.n_dof, self.n_sub, self.n_cols = n_dof.value, n_sub.value, n_cols.value
-        if getattr(prob, "gravity", 0.0) != 0.0:
-            try:
+        try:
+            if getattr(prob, "gravity", 0.0) != 0.0:
                 self.set_gravity(prob.gravity, prob.rho_w, prob.rho_o)
-            except MRCMError:
-                self.close()
-                raise
+            if getattr(prob, "adaptive_alpha", None) is not None:
+                self.set_adaptive_alpha(*prob.adaptive_alpha)
+        except MRCMError:
+            self.close()
+            raise
 
     # -- helpers ----------------------------------------------------------
     def _check(self, rc, what):
@@ -452,6 +456,11 @@ class MRCMSolver:
                                            int(max_newton), float(outer_tol), int(max_outer),
                                            ctypes.byref(st)), "mrcm_sfi_step")
         return {k: getattr(st, k) for k, _ in SFIStats._fields_}
+
+    def set_adaptive_alpha(self, alpha_channel: float, alpha_other: float):
+        """mrcm_set_adaptive_alpha: alpha per interface from its channels."""
+        self._check(self.lib.mrcm_set_adaptive_alpha(self.ctx, float(alpha_channel), float(alpha_other)),
+                    "mrcm_set_adaptive_alpha")
 
     def set_gravity(self, gravity: float, rho_w: float, rho_o: float):
         """mrcm_set_gravity: g dh/dy along y and the phase densities (0 turns
