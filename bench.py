@@ -73,6 +73,8 @@ def parse():
                          "(default fp64,fp32_ir,surrogate; fp64,fp32_ir for 32 x 32 subdomains)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-transport", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the gravity and physics-space variants of the step")
     ap.add_argument("--cpu-workers", type=int, default=0,
                     help="oracle process pool size (default: the usable cores, at most 16)")
     ap.add_argument("--seed", type=int, default=1)
@@ -250,8 +252,10 @@ def main():
 
     last_p = {}
 
-    def run_form(precision):
-        sol = MRCMSolver(prob, precision=precision)
+    def run_form(precision, variant=None):
+        """Time the steps of one form; variant: (label, problem) of the same
+        workload with another interface space or with gravity."""
+        sol = MRCMSolver(variant[1] if variant else prob, precision=precision)
         net = None
         if precision == "surrogate":
             net = trained_surrogate()
@@ -458,6 +462,18 @@ def main():
                 fp_, ff = last_p[f]
                 out["forms"][f]["rel_l2_vs_fp64_last_step"] = {
                     "p": float((fp_ - rp).norm() / rp.norm()), "flux": float((ff - rf).norm() / rf.norm())}
+    if not args.no_variants:
+        # the rows beyond the plain step, on the same workload and inputs:
+        # gravity (g dh/dy = -1, water 1, oil 0.8) and the physics-based
+        # spaces with the adaptive alpha (generic kernels, 4 + 4 dof slots)
+        out["variants"] = {}
+        for label, vp in (("gravity", prob.replace(gravity=-1.0, rho_w=1.0, rho_o=0.8)),
+                          ("physics_spaces_adaptive_alpha",
+                           prob.replace(space="physics", p_dofs=4, u_dofs=4, adaptive_alpha=(1e-2, 1e2)))):
+            r = run_form("fp64", (label, vp))
+            out["variants"][label] = {k: r[k] for k in ("ms_per_step", "subdomain_solves_per_s", "phases_ms",
+                                                        "max_cell_imbalance", "n_dof")}
+            log("variant %s: %.3f ms/step" % (label, r["ms_per_step"]))
     if not args.no_transport:
         out["transport"] = run_transport()
         log("transport: %.2f ms/step" % out["transport"]["ms_per_step"])

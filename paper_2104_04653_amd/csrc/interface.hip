@@ -758,21 +758,45 @@ __global__ void __launch_bounds__(NT) front_rhs_kernel(const NodeDesc* nodes, co
       for (int a = k + 1 + t; a < n; a += NT) rl[a] -= F[(long long)a * ld + k] * rk;
     }
   } else {
+    // per panel: z = A11^-1 y_panel, then y_a -= A_a,panel z for the rows
+    // below; 8 lanes per row, 4 consecutive columns each (a row's 32 panel
+    // entries are one 256-byte segment), reduced across the 8 lanes
+    const int l8 = t & 7, row = t >> 3;   // 32 rows per pass
     for (int k0 = 0; k0 < s; k0 += PANEL_NB) {
       const int nb = min(PANEL_NB, s - k0);
       const double* Di = inv + nd.inv_off + (long long)(k0 / PANEL_NB) * PANEL_NB * PANEL_NB;
       __syncthreads();
-      if (t < nb) {
+      {
         double v = 0.0;
-        for (int m = 0; m < nb; ++m) v += Di[t * PANEL_NB + m] * rl[k0 + m];
-        z[t] = v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int m = 4 * l8 + q;
+          const bool in = row < nb && m < nb;
+          const double d = Di[in ? row * PANEL_NB + m : 0];
+          const double y = rl[in ? k0 + m : k0];
+          v += in ? d * y : 0.0;
+        }
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        if (row < nb && l8 == 0) z[row] = v;
       }
       __syncthreads();
-      for (int a = k0 + nb + t; a < n; a += NT) {
-        const double* fr = F + (long long)a * ld + k0;
+      for (int a0 = k0 + nb; a0 < n; a0 += NT / 8) {
+        const int a = a0 + row;
+        const double* fr = F + (long long)(a < n ? a : k0 + nb) * ld + k0;
         double v = 0.0;
-        for (int c = 0; c < nb; ++c) v += fr[c] * z[c];
-        rl[a] -= v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int m = 4 * l8 + q;
+          const double f = fr[m < nb ? m : 0];
+          const double zm = z[m < nb ? m : 0];
+          v += (a < n && m < nb) ? f * zm : 0.0;
+        }
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        if (a < n && l8 == 0) rl[a] -= v;
       }
     }
   }
