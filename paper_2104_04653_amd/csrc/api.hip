@@ -1383,11 +1383,13 @@ int transport_impl(mrcm_ctx* c, const double* s_old, double* s_new, const double
   HIPCHK(c, launch_copy(s_new, s_old, n, st));
   mrcm_transport_stats out{};
   double change = 0.0;
+  int last_iters = 20;   // BiCGSTAB iterations of the previous Newton system
   for (int it = 1; it <= max_newton; ++it) {
     HIPCHK(c, launch_transport_assemble(a, st));
-    // most solves converge within the first batch; later launches of a
-    // batch return at once after convergence
-    int k = 0, batch = 24;
+    // the first batch covers the previous system's iteration count and a
+    // margin (successive Newton systems need similar counts); the launches
+    // of a batch after convergence return at once (about 3 us each)
+    int k = 0, batch = last_iters + 4;
     for (;;) {
       HIPCHK(c, launch_transport_bicg(a, k, batch, st));
       k += batch;
@@ -1396,6 +1398,7 @@ int transport_impl(mrcm_ctx* c, const double* s_old, double* s_new, const double
       if (c->h_tscal[TS_DONE] != 0.0 || k > a.max_iter) break;
       batch = 8;
     }
+    last_iters = std::max(4, (int)c->h_tscal[TS_ITERS]);
     out.linear_iters += (int)c->h_tscal[TS_ITERS];
     if (c->h_tscal[TS_DONE] != 1.0) out.linear_failures += 1;
     HIPCHK(c, launch_transport_update(a, st));
