@@ -214,6 +214,10 @@ __device__ void local_residual_dd(const double* b, const double* x, double* r, c
 template <int M>
 struct LocalStore {
   static constexpr bool big = M > 16;
+  // the inverse Schur blocks in the scratch too: large subdomains, and 16 x 16
+  // ones whose basis block (R columns) leaves no LDS for them at two
+  // work-groups per CU
+  static constexpr bool sinv_global(int R) { return big || M * M * R * 8 > 48 * 1024; }
 };
 
 // FP64 local solves (LIST: only the subdomains on the fallback list of the
@@ -223,10 +227,13 @@ __global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
   constexpr int R = 1 + 4 * D;
   constexpr int MM = M * M;
   constexpr bool BIG = LocalStore<M>::big;
+  // with many columns (8 dofs per interface) the inverse blocks go to the
+  // scratch as well, so that two work-groups share a CU
+  constexpr bool SG = LocalStore<M>::sinv_global(R);
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
   __shared__ float dgl[MM];            // rounding error of the diagonal sums
   __shared__ double Xs_l[BIG ? 1 : MM * R];
-  __shared__ double Sinv_l[BIG ? 1 : M * MM];
+  __shared__ double Sinv_l[SG ? 1 : M * MM];
   __shared__ double pivbuf[4 * M];
   const Geo& g = a.g;
   const int tid = threadIdx.x;
@@ -242,7 +249,7 @@ __global__ void __launch_bounds__(NT) local_basis_kernel(SubArgs a) {
   double* Rs_l = scr + MM * R;
   double* Bs = scr;
   double* Xs = BIG ? scr + 2 * MM * R : Xs_l;
-  double* Sinv = BIG ? scr + 3 * MM * R : Sinv_l;
+  double* Sinv = BIG ? scr + 3 * MM * R : SG ? scr + 2 * MM * R : Sinv_l;
 
   load_kappa<M>(a, I, J, kap);
   __syncthreads();
@@ -696,7 +703,8 @@ long long local_scratch_doubles(const Geo& g) {
   // generic FP32 kernel first and needs its scratch
   if (basis32x32_supported(g) && g.prec != 1) return basis32x32_scratch();
   const long long MM = (long long)g.M * g.M, R = 1 + 4 * g.D;
-  return 2 * MM * R + (g.M > 16 ? MM * R + g.M * MM : 0);
+  if (g.M > 16) return 3 * MM * R + g.M * MM;
+  return 2 * MM * R + (MM * R * 8 > 48 * 1024 ? g.M * MM : 0);
 }
 
 hipError_t launch_local_basis(const SubArgs& a, hipStream_t st) { return dispatch(a, st, false); }
