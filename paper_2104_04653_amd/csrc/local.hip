@@ -660,6 +660,9 @@ hipError_t dispatch(const SubArgs& a, hipStream_t st, bool stitch) {
     }
     return launch_basis_m16d4(a, st);
   }
+  if (M == 16 && D == 8 && !a.g.generic && a.g.prec == 0) {
+    return stitch ? launch_stitch_m16d8(a, st) : launch_basis_m16d8(a, st);
+  }
   if (M == 32 && D == 4) {
     if (stitch && basis32x32_supported(a.g)) return launch_stitch32x32(a, st);
     if (!stitch && basis32x32_supported(a.g)) {
@@ -697,7 +700,7 @@ bool local_supported(int M, int D) {
 }
 
 long long local_scratch_doubles(const Geo& g) {
-  const bool fast = g.M == 16 && g.D == 4 && g.nP == 2 && !g.generic;
+  const bool fast = g.M == 16 && ((g.D == 4 && g.nP == 2) || (g.D == 8 && g.prec == 0)) && !g.generic;
   if (fast) return 0;
   // the matrix-core kernels of 32 x 32 subdomains; the FP32 form runs the
   // generic FP32 kernel first and needs its scratch

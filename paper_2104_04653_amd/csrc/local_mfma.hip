@@ -82,26 +82,30 @@ __device__ inline double side_rhs(const double (*bside)[M][D], int lj, int li, i
 
 // Per skeleton face (side, t) of a subdomain: Robin transmissibility T_R,
 // beta = alpha H / kappa and beta / |f| (all 0 on the domain boundary), and
-// the interface functions of the side.  Computed once per kernel by the first
-// 4 M threads; used by the Robin right-hand sides and by write_block.
-struct Faces {
+// the DD interface functions of the side.  Computed once per kernel by the
+// first 4 M threads; used by the Robin right-hand sides and by write_block.
+template <int DD>
+struct FacesT {
   double tr[4][M], bt[4][M], bl[4][M];
-  double phi[4][D][M];
+  double phi[4][DD][M];
   double gr[4][M];   // gravity part of the particular solution's Robin flux (0 without gravity)
 };
+using Faces = FacesT<D>;
 
 // The global data of a face (its interface's alpha and functions), loaded
 // by the first 4 M threads at the start of a kernel so that the loads are in
 // flight with the mobility loads; prepare_faces completes the face data once
 // the cell mobilities are in LDS.
-struct FaceLoad {
+template <int DD>
+struct FaceLoadT {
   int e = -1;
   double al = 0.0;
-  double phi[D] = {0.0, 0.0, 0.0, 0.0};
+  double phi[DD] = {};
 };
 
-__device__ inline FaceLoad load_faces(const SubArgs& a, int I, int J) {
-  FaceLoad fl;
+template <int DD = D>
+__device__ inline FaceLoadT<DD> load_faces(const SubArgs& a, int I, int J) {
+  FaceLoadT<DD> fl;
   const int l = threadIdx.x;
   if (l < 4 * M) {
     const int side = l >> 4, t = l & 15;
@@ -110,18 +114,19 @@ __device__ inline FaceLoad load_faces(const SubArgs& a, int I, int J) {
     // the domain boundary), so that the loads are not behind a branch
     const bool has = fl.e >= 0;
     const double al = *(has ? a.alpha + fl.e : a.K);
-    double ph[D];
+    double ph[DD];
 #pragma unroll
-    for (int k = 0; k < D; ++k) ph[k] = *(has ? a.basis + ((size_t)fl.e * D + k) * M + t : a.K);
+    for (int k = 0; k < DD; ++k) ph[k] = *(has ? a.basis + ((size_t)fl.e * DD + k) * M + t : a.K);
     fl.al = has ? al : 0.0;
 #pragma unroll
-    for (int k = 0; k < D; ++k) fl.phi[k] = has ? ph[k] : 0.0;
+    for (int k = 0; k < DD; ++k) fl.phi[k] = has ? ph[k] : 0.0;
   }
   return fl;
 }
 
-__device__ inline void prepare_faces(const SubArgs& a, const FaceLoad& fl, const double* kap, Faces& f,
-                                     int I, int J) {
+template <int DD>
+__device__ inline void prepare_faces(const SubArgs& a, const FaceLoadT<DD>& fl, const double* kap,
+                                     FacesT<DD>& f, int I, int J) {
   const Geo& g = a.g;
   const int l = threadIdx.x;
   if (l < 4 * M) {
@@ -143,35 +148,45 @@ __device__ inline void prepare_faces(const SubArgs& a, const FaceLoad& fl, const
     f.bt[side][t] = bt;
     f.bl[side][t] = bl;
 #pragma unroll
-    for (int k = 0; k < D; ++k) f.phi[side][k][t] = fl.phi[k];
+    for (int k = 0; k < DD; ++k) f.phi[side][k][t] = fl.phi[k];
   }
 }
 
-// Robin data of the basis columns, bside[side][t][k] = T_R g_k(t) (flux
+// Robin data of the basis columns of one window of 4 dofs per side (dofs
+// 4 win .. 4 win + 3), bside[side][t][k] = T_R g_{4 win + k}(t) (flux
 // functions scaled by -beta sigma), from the face data (first 4 M threads).
-__device__ inline void robin_data(const Geo& g, const Faces& f, double (*bside)[M][D]) {
+template <int DD>
+__device__ inline void robin_data(const Geo& g, const FacesT<DD>& f, double (*bside)[M][4], int win = 0) {
   const int l = threadIdx.x;
   if (l < 4 * M) {
     const int side = l >> 4, t = l & 15;
     const double sig = side_sigma(side);
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const double ph = f.phi[side][k][t];
-      bside[side][t][k] = f.tr[side][t] * (k < g.nP ? ph : -f.bt[side][t] * sig * ph);
+    for (int k = 0; k < 4; ++k) {
+      const int kg = 4 * win + k;
+      const double ph = f.phi[side][kg][t];
+      bside[side][t][k] = f.tr[side][t] * (kg < g.nP ? ph : -f.bt[side][t] * sig * ph);
     }
   }
 }
 
-// Traces of every column on the skeleton faces (xb: solution in the cells
-// next to each side's faces) projected on the interface functions: the
-// subdomain's block of the interface system, rows of flux dofs negated
-// (the form in which the assembled interface matrix is symmetric), last
-// column = right-hand side.  One (side, column) pair
-// per thread, the D rows of that side accumulated together.
-__device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const Faces& f,
-                                   const double (*xb)[M][R]) {
+// Traces of the columns of one window on the skeleton faces (xb: solution in
+// the cells next to each side's faces; column 0 the particular solution,
+// column 1 + c the window's basis column c, which is dof 4 win + (c & 3) of
+// side c >> 2) projected on all DD interface functions of each side: the
+// window's columns of the subdomain's block of the interface system, rows
+// of flux dofs negated (the form in which the assembled interface matrix is
+// symmetric), last column = right-hand side (written by window 0).  One
+// (side, column) pair per thread, the DD rows of that side accumulated
+// together.  Slots beyond an interface's functions (nact) get a zero row and
+// column, and 1 on the diagonal from the lower-index side (the dof is then
+// 0), as in the per-subdomain kernels.
+template <int DD>
+__device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const FacesT<DD>& f,
+                                   const double (*xb)[M][R], int win = 0) {
   const Geo& g = a.g;
-  constexpr int NBR = 4 * D, NBC = 4 * D + 1;
+  constexpr int NBR = 4 * DD, NBC = 4 * DD + 1;
+  constexpr int NQ = 17;                       // window columns + right-hand side
   double* blk = a.blocks + (size_t)sd * NBR * NBC;
   const int nP = g.nP;
   int e0side = -1;
@@ -180,42 +195,52 @@ __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const
     for (int side = 0; side < 4; ++side)
       if (side_iface(g, I, J, side) == 0) { e0side = side; e0lo = side_sigma(side) > 0; }
   }
-  for (int pr = threadIdx.x; pr < 4 * NBC; pr += blockDim.x) {
-    const int side = pr / NBC, qc = pr % NBC;
+  const int npair = win == 0 ? 4 * NQ : 4 * (NQ - 1);
+  for (int pr = threadIdx.x; pr < npair; pr += blockDim.x) {
+    const int side = pr / (npair / 4), ql = pr % (npair / 4);
+    const bool rhs = ql == NQ - 1;
+    const int col = rhs ? 0 : 1 + ql;                             // column of xb
+    const int csd = ql >> 2, kc = 4 * win + (ql & 3);             // the column's side and dof
+    const int qc = rhs ? NBR : csd * DD + kc;                     // its column of the block
     const int e = side_iface(g, I, J, side);
-    double acc[D];
+    double acc[DD];
 #pragma unroll
-    for (int k = 0; k < D; ++k) acc[k] = 0.0;
+    for (int k = 0; k < DD; ++k) acc[k] = 0.0;
     const double sig = side_sigma(side);
     if (e >= 0) {
-      const int col = (qc < NBR) ? 1 + qc : 0;
-      const bool colside = col >= 1 + side * D && col < 1 + side * D + D;
-      const int kc = colside ? col - 1 - side * D : 0;
+      const bool colside = !rhs && csd == side;
       const bool flux_col = colside && kc >= nP;
       const double gscale = colside ? 1.0 : 0.0;
+      const int kp = colside ? kc : 0;
 #pragma unroll 4
       for (int t = 0; t < M; ++t) {
-        const double ph = f.phi[side][kc][t];
+        const double ph = f.phi[side][kp][t];
         const double gv = gscale * (flux_col ? -f.bt[side][t] * sig * ph : ph);
-        const double F = f.tr[side][t] * (xb[side][t][col] - gv) + (col == 0 ? f.gr[side][t] : 0.0);
+        const double F = f.tr[side][t] * (xb[side][t][col] - gv) + (rhs ? f.gr[side][t] : 0.0);
         const double wu = fma(f.bl[side][t], F, gv);
 #pragma unroll
-        for (int k = 0; k < D; ++k) acc[k] = fma(f.phi[side][k][t], k < nP ? F : wu, acc[k]);
+        for (int k = 0; k < DD; ++k) acc[k] = fma(f.phi[side][k][t], k < nP ? F : wu, acc[k]);
       }
     }
     const double flen = side_geo(g, side).flen;
+    const int es = rhs ? -1 : side_iface(g, I, J, csd);
+    const bool col_dead = a.nact && es >= 0 && !slot_active(a, es, kc);
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const int r = side * D + k;
+    for (int k = 0; k < DD; ++k) {
+      const int r = side * DD + k;
       double val = 0.0;
       if (e >= 0) {
         const double natural = (k < nP) ? acc[k] : sig * flen * acc[k];
         const double sgn = (k < nP) ? 1.0 : -1.0;
-        val = (qc < NBR) ? sgn * natural : -sgn * natural;
+        val = !rhs ? sgn * natural : -sgn * natural;
         if (e0side >= 0) {
-          const int r0 = e0side * D;
+          const int r0 = e0side * DD;
           if (r == r0) val = (qc == r0 && e0lo) ? 1.0 : 0.0;
           else if (qc == r0) val = 0.0;
+        }
+        if (a.nact) {
+          if (!slot_active(a, e, k)) val = (qc == r && sig > 0) ? 1.0 : 0.0;
+          else if (col_dead) val = 0.0;
         }
       }
       blk[r * NBC + qc] = val;
@@ -238,11 +263,18 @@ static_assert(MM % PAIR == 0, "whole cells per thread");
 constexpr int NU = MID + 1;       // rows of wave 0: 0 .. MID
 constexpr int NL = M - 1 - MID;   // rows of wave 1: M-1 .. MID+1 (index t is row M-1-t)
 
-template <bool LIST>
+// DD dofs per interface side: DD / 4 windows of 4 dofs per side, one
+// work-group each (work-group b: subdomain b / (DD / 4), window b % (DD / 4)).
+// Every window factorises the subdomain's matrix, solves its 16 basis columns
+// and the particular solution (stored by window 0), and writes its columns
+// of the interface block.
+template <bool LIST, int DD>
 __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
+  static_assert(DD % 4 == 0 && (!LIST || DD == 4), "windows of 4 dofs per side");
+  constexpr int NW = DD / 4, RX = 4 * DD + 1;
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM], b0[MM], pz[MM];
   __shared__ float dgl[MM];            // rounding error of the diagonal sums
-  __shared__ Faces fc;
+  __shared__ FacesT<DD> fc;
   __shared__ double bside[4][M][D];
   __shared__ double xb[4][M][R];
   __shared__ double xs[2][M][M + 1];   // exchange tiles; per-wave staging
@@ -252,14 +284,15 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
   // so that row offsets that depend on it are scalar too
   const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63, c = lane & 15, gq = lane >> 4;
-  int sd = blockIdx.x;
+  int sd = NW == 1 ? (int)blockIdx.x : (int)blockIdx.x / NW;
+  const int win = NW == 1 ? 0 : (int)blockIdx.x % NW;
   if (LIST) {   // re-solve only the subdomains on the fallback list
     if ((int)blockIdx.x >= a.fallback[0]) return;
     sd = a.fallback[1 + blockIdx.x];
   }
   const int I = sd % g.SX, J = sd / g.SX;
 
-  const FaceLoad fl = load_faces(a, I, J);
+  const FaceLoadT<DD> fl = load_faces<DD>(a, I, J);
   CellLoads cl[MM / PAIR];   // issued with the permeability loads
 #pragma unroll
   for (int q = 0; q < MM / PAIR; ++q) cl[q] = cell_loads<M>(a, I, J, tid + PAIR * q, 1);
@@ -271,7 +304,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
                                cl[q], dgl);
   prepare_faces(a, fl, kap, fc, I, J);
   __syncthreads();
-  robin_data(g, fc, bside);
+  robin_data(g, fc, bside, win);
   __syncthreads();
 
   const d4 zero = {0.0, 0.0, 0.0, 0.0};
@@ -578,8 +611,9 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
 
   // basis functions to global memory, column-major per subdomain: each
   // row tile is transposed through the wave's LDS tile so that every store
-  // instruction writes four whole 128-byte column segments
-  double* Xg = a.X + (size_t)sd * R * MM;
+  // instruction writes four whole 128-byte column segments (tile column
+  // q0 + 4 s4 is dof 4 win + q0 of side s4)
+  double* Xg = a.X + (size_t)sd * RX * MM;
   {
     double (*Tt)[M + 1] = xs[w];
     const int ci = lane & 15, q0 = lane >> 4;
@@ -593,7 +627,9 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
           const int q = q0 + 4 * s4;
-          Xg[(size_t)(1 + q) * MM + j * M + ci] = Tt[ci][q];
+          const int qg = NW == 1 ? q : s4 * DD + 4 * win + q0;   // (the same index for NW = 1,
+                                                                  // in the form that keeps spills down)
+          Xg[(size_t)(1 + qg) * MM + j * M + ci] = Tt[ci][q];
         }
         __builtin_amdgcn_wave_barrier();
         if (gq == 0) xb[0][j][1 + c] = Xv[t][0];
@@ -606,7 +642,8 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
     if (w == 0) xb[2][4 * v + gq][1 + c] = Xv[0][v];
     else xb[3][4 * v + gq][1 + c] = Xv[0][v];
   }
-  for (int l = tid; l < MM; l += PAIR) Xg[l] = pz[l];
+  if (win == 0)
+    for (int l = tid; l < MM; l += PAIR) Xg[l] = pz[l];
   if (tid < M) {
     xb[0][tid][0] = pz[tid * M];
     xb[1][tid][0] = pz[tid * M + M - 1];
@@ -614,12 +651,15 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
     xb[3][tid][0] = pz[(M - 1) * M + tid];
   }
   __syncthreads();
-  write_block(a, sd, I, J, fc, xb);
+  write_block(a, sd, I, J, fc, xb, win);
 }
 
 // Two-wavefront elimination of the 16 Schur blocks (wave 0: rows 0..MID-1
 // and the joining row MID, wave 1: rows M-1..MID+1, index t = row M-1-t);
 // xch is an LDS tile for the hand-over at the join.  Both waves must call.
+// TAG (the caller's dofs per side) gives each stitch kernel a copy of its
+// own: a helper with one caller compiles to fewer spills in that caller.
+template <int TAG>
 __device__ inline void factor_pair(d4* Sv, int w, int c, int g, const double* dg, const double* ex,
                                    const double* cy, double (*xch)[M + 1], PivotCheck& pvc) {
   const d4 zero = {0.0, 0.0, 0.0, 0.0};
@@ -651,6 +691,7 @@ __device__ inline void factor_pair(d4* Sv, int w, int c, int g, const double* dg
 // One column solve with the blocks of factor_pair (rhs and result in LDS,
 // cell-major; the column is replicated over the 16 MFMA columns and lanes
 // with c == 0 write the result).  Both waves must call.
+template <int TAG>
 __device__ inline void solve_column_pair(const d4* Sv, int w, const double* rhs, double* out, int c,
                                          int g, const double* cy) {
   const d4 zero = {0.0, 0.0, 0.0, 0.0};
@@ -1051,7 +1092,7 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
   const int sd = blockIdx.x;
   const int I = sd % g.SX, J = sd / g.SX;
 
-  const FaceLoad fl = load_faces(a, I, J);
+  const FaceLoadT<D> fl = load_faces(a, I, J);
   CellLoads cl[MM / PAIR];   // issued with the permeability loads
 #pragma unroll
   for (int q = 0; q < MM / PAIR; ++q) cl[q] = cell_loads<M>(a, I, J, tid + PAIR * q, 1);
@@ -1195,25 +1236,31 @@ __global__ void __launch_bounds__(PAIR, 2) basis32_pair_kernel(SubArgs a) {
 
 // interface coefficient of basis column q of subdomain (I, J) (0 for a side
 // on the domain boundary, whose basis columns are zero)
+template <int DD = D>
 __device__ inline double column_coef(const SubArgs& a, int I, int J, int q) {
-  const int e = side_iface(a.g, I, J, q / D);
-  return e >= 0 ? a.coef[(size_t)e * D + q % D] : 0.0;
+  const int e = side_iface(a.g, I, J, q / DD);
+  return e >= 0 ? a.coef[(size_t)e * DD + q % DD] : 0.0;
 }
 
 // composed pressure p = X [1; c] at cell l of subdomain sd, coefficients cf
-// of its 4 D basis columns; all loads are issued unconditionally
-__device__ inline double compose16(const SubArgs& a, int sd, int l, const double* cf) {
-  const double* xr = a.X + (size_t)sd * R * MM + l;
-  double x[4 * D];
-#pragma unroll
-  for (int q = 0; q < 4 * D; ++q) x[q] = xr[(size_t)(1 + q) * MM];
+// of its 4 DD basis columns; the loads are issued 16 at a time, unconditionally
+template <int DD>
+__device__ inline double compose(const SubArgs& a, int sd, int l, const double* cf) {
+  const double* xr = a.X + (size_t)sd * (4 * DD + 1) * MM + l;
   double p = xr[0];
 #pragma unroll
-  for (int q = 0; q < 4 * D; ++q) p = fma(x[q], cf[q], p);
+  for (int q0 = 0; q0 < 4 * DD; q0 += 16) {
+    double x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) x[q] = xr[(size_t)(1 + q0 + q) * MM];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) p = fma(x[q], cf[q0 + q], p);
+  }
   return p;
 }
 
 // four wavefronts per SIMD: 128 registers per lane and 19 KB of LDS per pair
+template <int DD>
 __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) stamp_now(a.stamps + STAMP_FLUX);
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
@@ -1235,8 +1282,8 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
   const int I = sd % g.SX, J = sd / g.SX;
   const int nP = g.nP;
 
-  __shared__ double cfs[4 * D];
-  if (tid < 4 * D) cfs[tid] = column_coef(a, I, J, tid);
+  __shared__ double cfs[4 * DD];
+  if (tid < 4 * DD) cfs[tid] = column_coef<DD>(a, I, J, tid);
   // the neighbour's side of each skeleton face (first 4 M threads): its
   // composed pressure and mobility next to the face, loaded before this
   // subdomain's own pressure so that both sets of loads are in flight together
@@ -1248,10 +1295,10 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
     // interface data of the face: alpha and the interface pressure / flux
     // P_H, U_H = sum of coefficient times interface function
     al = a.alpha[e];
-    const double* bsf = a.basis + (size_t)e * D * M;
-    const double* ce = a.coef + (size_t)e * D;
+    const double* bsf = a.basis + (size_t)e * DD * M;
+    const double* ce = a.coef + (size_t)e * DD;
     for (int k = 0; k < nP; ++k) PH += ce[k] * bsf[k * M + t];
-    for (int k = nP; k < D; ++k) UH += ce[k] * bsf[k * M + t];
+    for (int k = nP; k < DD; ++k) UH += ce[k] * bsf[k * M + t];
     const int nside = side ^ 1;
     const int nsd = (side == 0) ? sd - 1 : (side == 1) ? sd + 1 : (side == 2) ? sd - g.SX : sd + g.SX;
     const int nI = nsd % g.SX, nJ = nsd / g.SX;
@@ -1259,17 +1306,17 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
     const size_t nc = (size_t)(nJ * M + nl / M) * g.nx + nI * M + nl % M;
     nc_g = nc;
     kn = a.K[nc] * a.lam[nc];
-    double cfn[4 * D];
+    double cfn[4 * DD];
 #pragma unroll
-    for (int q = 0; q < 4 * D; ++q) cfn[q] = column_coef(a, nI, nJ, q);
-    pn = compose16(a, nsd, nl, cfn);
+    for (int q = 0; q < 4 * DD; ++q) cfn[q] = column_coef<DD>(a, nI, nJ, q);
+    pn = compose<DD>(a, nsd, nl, cfn);
   }
   CellLoads cl[MM / PAIR];   // issued with the permeability loads
 #pragma unroll
   for (int q = 0; q < MM / PAIR; ++q) cl[q] = cell_loads<M>(a, I, J, tid + PAIR * q, 0);
   load_kappa<M>(a, I, J, kap);
   __syncthreads();
-  for (int l = tid; l < MM; l += PAIR) pm[l] = compose16(a, sd, l, cfs);
+  for (int l = tid; l < MM; l += PAIR) pm[l] = compose<DD>(a, sd, l, cfs);
   __syncthreads();
   if (tid < 4 * M) {
     // one-sided Robin fluxes on both sides of each skeleton face; outflow
@@ -1346,9 +1393,9 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
 
   d4 Sv[NU];
   PivotCheck pvc;
-  factor_pair(Sv, w, c, gq, dg, ex, cy, xch, pvc);
+  factor_pair<DD>(Sv, w, c, gq, dg, ex, cy, xch, pvc);
   if (pvc.bad()) atomicOr(a.status, ST_STITCH_PIVOT);
-  solve_column_pair(Sv, w, bs_, ps, c, gq, cy);
+  solve_column_pair<DD>(Sv, w, bs_, ps, c, gq, cy);
   // one step of iterative refinement with the stored inverse blocks; the
   // residual is the cells' mass balance in double-double (the FP64 diagonal
   // sums of the assembled matrix would leave eps * T |p| per cell), and the
@@ -1361,7 +1408,7 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
     rs[l] = stitch_balance_residual<M>(a, I, J, l, kap, ps, Fout, pin_sc[0], pin_sc[1], pm[0]);
   }
   __syncthreads();
-  solve_column_pair(Sv, w, rs, rs, c, gq, cy);   // in place: each row is read before it is written
+  solve_column_pair<DD>(Sv, w, rs, rs, c, gq, cy);   // in place: each row is read before it is written
 
   double imb = 0.0, fmx = 0.0, psum = 0.0;
 #pragma unroll 1
@@ -1506,7 +1553,7 @@ __global__ void __launch_bounds__(GATE) surrogate_gate_kernel(SubArgs a, const f
   const int sd = blockIdx.x, I = sd % g.SX, J = sd / g.SX;
   static_assert(GATE == MM, "one thread per cell");
 
-  const FaceLoad fl = load_faces(a, I, J);
+  const FaceLoadT<D> fl = load_faces(a, I, J);
   const float* pr = pred + (size_t)sd * MM * 4 * D;
   // raw predictions, cell-major in memory: 16 per thread, coalesced (entry
   // tid + k GATE is column tid % 16 of cell tid / 16 + 16 k)
@@ -1631,12 +1678,17 @@ __global__ void __launch_bounds__(GATE) surrogate_gate_kernel(SubArgs a, const f
 }  // namespace
 
 hipError_t launch_basis_m16d4(const SubArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(basis_pair_kernel<false>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
+  hipLaunchKernelGGL((basis_pair_kernel<false, 4>), dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_basis_m16d4_list(const SubArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(basis_pair_kernel<true>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
+  hipLaunchKernelGGL((basis_pair_kernel<true, 4>), dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_basis_m16d8(const SubArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((basis_pair_kernel<false, 8>), dim3(2 * a.g.n_sub), dim3(PAIR), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1646,7 +1698,12 @@ hipError_t launch_basis32_m16d4(const SubArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(stitch_pair_kernel, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
+  hipLaunchKernelGGL(stitch_pair_kernel<4>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stitch_m16d8(const SubArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(stitch_pair_kernel<8>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
   return hipGetLastError();
 }
 

@@ -125,6 +125,10 @@ hipError_t launch_basis_m16d4(const SubArgs& a, hipStream_t st);
 hipError_t launch_basis32_m16d4(const SubArgs& a, hipStream_t st);
 hipError_t launch_basis_m16d4_list(const SubArgs& a, hipStream_t st);
 hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st);
+// 16 x 16 subdomains with 8 dofs per side (physics-based spaces, 4 + 4 slots):
+// two work-groups per subdomain, one per window of 4 dofs per side
+hipError_t launch_basis_m16d8(const SubArgs& a, hipStream_t st);
+hipError_t launch_stitch_m16d8(const SubArgs& a, hipStream_t st);
 // (local_mfma32.hip) 32 x 32 subdomains, 4 dofs per side (2 + 2): FP64 basis
 // functions on the matrix cores; list = only the FP32 fallback list
 bool basis32x32_supported(const Geo& g);

@@ -1,14 +1,17 @@
 """Physics-based interface spaces and the adaptive Robin parameter on the GPU
 (MRCM_SPACE_PHYSICS, mrcm_set_adaptive_alpha; section 3.1) against the
-oracle's spaces, on the generic kernels (4 + 4 dof slots per interface, the
-unused ones fixed to zero).
+oracle's spaces (4 + 4 dof slots per interface, the unused ones fixed to
+zero): 16 x 16 subdomains on the matrix-core kernels (two windows of 4 dofs
+per side), 32 x 32 on the generic kernels.
 
 * the local solutions X, column by column, in the slots of each
   interface's functions (which also checks the library's construction of
   the functions and of the Robin data from them);
 * p and the stitched fluxes at 1e-10, per-cell balance 1e-12, at 16x16 and
   32x32 subdomains, with and without the adaptive alpha;
-* the barrier case on which these spaces are exact (the fine solution).
+* the barrier case on which these spaces are exact (the fine solution);
+* the 16 x 16 matrix-core kernels against the generic kernels on the same
+  input (another elimination order: equal to rounding), blocks included.
 """
 import numpy as np
 import pytest
@@ -145,3 +148,34 @@ def test_physics_spaces_errors():
         with pytest.raises(MRCMError) as ei:
             sol.set_adaptive_alpha(0.0, 1.0)
         assert ei.value.code == E_INVAL
+
+
+def test_physics_matrix_core_kernels_match_generic_kernels():
+    """16 x 16 subdomains with 8 dofs per side: the matrix-core kernels
+    (each window of 4 dofs per side solved by a work-group of its own, the
+    blocks' columns written by their window) against the generic kernels
+    (MRCM_GENERIC_KERNELS selects them) on the same input."""
+    import os
+    prob = physics_problem("channel256_q5", adaptive=(1e-2, 1e2), nx=128, ny=96, lx=0.5, ly=0.375, seed=4)
+    s = inputs.synthetic_saturation(prob, 5, 20)
+    say("case: physics spaces, matrix-core vs generic kernels 128x96")
+    os.environ["MRCM_GENERIC_KERNELS"] = "1"
+    try:
+        gen = run_gpu(prob, s=s)
+    finally:
+        del os.environ["MRCM_GENERIC_KERNELS"]
+    mc = run_gpu(prob, s=s)
+    eb = np.abs(mc["basis"] - gen["basis"]).max() / np.abs(gen["basis"]).max()
+    ebl = np.abs(mc["blocks"] - gen["blocks"]).max() / np.abs(gen["blocks"]).max()
+    ep = rel(mc["p"], gen["p"])
+    ef = rel(np.r_[mc["ux"], mc["uy"]], np.r_[gen["ux"], gen["uy"]])
+    for name, r in (("generic", gen), ("matrix-core", mc)):
+        st = r["stats"]
+        say("  %s: ms local %.3f interface %.3f flux %.3f imbalance %.2e"
+            % (name, st["ms_local"], st["ms_interface"], st["ms_flux"], r["imbalance"]))
+    say("  max rel difference: basis %.2e blocks %.2e; rel L2 p %.2e flux %.2e" % (eb, ebl, ep, ef))
+    # the unused slots hold exact zeros on both paths
+    assert np.array_equal(mc["basis"] == 0.0, gen["basis"] == 0.0)
+    assert np.array_equal(mc["blocks"] == 0.0, gen["blocks"] == 0.0)
+    assert eb < 1e-11 and ebl < 1e-11 and ep < 1e-11 and ef < 1e-10
+    assert mc["imbalance"] < 1e-12
