@@ -125,6 +125,7 @@ struct mrcm_ctx {
   // physics spaces: numbers of active pressure and flux functions
   std::vector<char> has_channel;
   int2* nact = nullptr;
+  std::vector<int2> h_nact;               // host copy (the interface plan leaves inactive slots out)
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // solve start, local end, gate end
   unsigned long long* stamps = nullptr;   // device, inside the report block
   double clock_khz = 0.0;                 // rate of the clock the kernels read
@@ -278,10 +279,21 @@ struct HNode {
 struct TreeBuilder {
   int SX, SY, nV, D;
   std::vector<HNode> nodes;
+  // physics spaces: slots of inactive functions (nP = pressure slots) are
+  // not unknowns of the elimination: their coefficient is 0, their row and
+  // column of the interface system are empty apart from a unit diagonal
+  const std::vector<int2>* nact = nullptr;
+  int nP = 0;
   int viface(int I, int J) const { return J * (SX - 1) + I; }
   int hiface(int I, int J) const { return nV + J * SX + I; }
+  bool active(int e, int k) const {
+    if (!nact) return true;
+    const int2 n = (*nact)[e];
+    return k < nP ? k < n.x : k - nP < n.y;
+  }
   void add_dofs(std::vector<int>& out, int e) const {
-    for (int k = 0; k < D; ++k) out.push_back(e * D + k);
+    for (int k = 0; k < D; ++k)
+      if (active(e, k)) out.push_back(e * D + k);
   }
   int rec(int I0, int I1, int J0, int J1) {
     if ((I1 - I0) * (J1 - J0) == 1) {
@@ -345,6 +357,10 @@ int build_plan(mrcm_ctx* c) {
     return MRCM_OK;
   }
   TreeBuilder tb{g.SX, g.SY, g.nV, g.D, {}};
+  if (!c->h_nact.empty()) {
+    tb.nact = &c->h_nact;
+    tb.nP = g.nP;
+  }
   tb.nodes.reserve(2 * g.n_sub);
   const int root = tb.rec(0, g.SX, 0, g.SY);
   (void)root;
@@ -538,6 +554,9 @@ int build_plan(mrcm_ctx* c) {
   ALLOC(c, c->rtree, r_total);
   ALLOC(c, c->rvec, c->n_dof);
   ALLOC(c, c->dx, c->n_dof);
+  // the coefficients and corrections of unknowns the plan leaves out stay 0
+  HIPCHK(c, hipMemset(c->coef, 0, std::max(c->n_dof, 1) * sizeof(double)));
+  HIPCHK(c, hipMemset(c->dx, 0, std::max(c->n_dof, 1) * sizeof(double)));
   ALLOC(c, c->partials, 2 * RESID_WG);
   ALLOC(c, c->d_nodes, desc.size());
   ALLOC(c, c->d_maps, maps.size());
@@ -872,6 +891,7 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
     if (space == MRCM_SPACE_PHYSICS) {
       ALLOC(c, c->nact, nact.size());
       HIPCHK(c, hipMemcpy(c->nact, nact.data(), nact.size() * sizeof(int2), hipMemcpyHostToDevice));
+      c->h_nact = nact;
     }
     int r = build_plan(c);
     if (r != MRCM_OK) return r;
