@@ -195,6 +195,15 @@ __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const
     for (int side = 0; side < 4; ++side)
       if (side_iface(g, I, J, side) == 0) { e0side = side; e0lo = side_sigma(side) > 0; }
   }
+  // the window's face values, [side][column][t], for the neighbours' stitch
+  {
+    double* xf = a.xface + (size_t)sd * 4 * (NBR + 1) * M;
+    for (int o = threadIdx.x; o < 4 * NQ * M; o += blockDim.x) {
+      const int side = o / (NQ * M), ql = (o / M) % NQ, t = o % M;
+      const int colg = ql == 0 ? 0 : 1 + ((ql - 1) >> 2) * DD + 4 * win + ((ql - 1) & 3);
+      if (ql > 0 || win == 0) __builtin_nontemporal_store(xb[side][t][ql], &xf[(side * (NBR + 1) + colg) * M + t]);
+    }
+  }
   const int npair = win == 0 ? 4 * NQ : 4 * (NQ - 1);
   for (int pr = threadIdx.x; pr < npair; pr += blockDim.x) {
     const int side = pr / (npair / 4), ql = pr % (npair / 4);
@@ -629,7 +638,9 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
           const int q = q0 + 4 * s4;
           const int qg = NW == 1 ? q : s4 * DD + 4 * win + q0;   // (the same index for NW = 1,
                                                                   // in the form that keeps spills down)
-          Xg[(size_t)(1 + qg) * MM + j * M + ci] = Tt[ci][q];
+          // streaming stores: the stitch reads X back in another launch, and
+          // lines kept in L2 would only push out the spilled registers
+          __builtin_nontemporal_store(Tt[ci][q], &Xg[(size_t)(1 + qg) * MM + j * M + ci]);
         }
         __builtin_amdgcn_wave_barrier();
         if (gq == 0) xb[0][j][1 + c] = Xv[t][0];
@@ -643,7 +654,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
     else xb[3][4 * v + gq][1 + c] = Xv[0][v];
   }
   if (win == 0)
-    for (int l = tid; l < MM; l += PAIR) Xg[l] = pz[l];
+    for (int l = tid; l < MM; l += PAIR) __builtin_nontemporal_store(pz[l], &Xg[l]);
   if (tid < M) {
     xb[0][tid][0] = pz[tid * M];
     xb[1][tid][0] = pz[tid * M + M - 1];
@@ -1259,6 +1270,21 @@ __device__ inline double compose(const SubArgs& a, int sd, int l, const double* 
   return p;
 }
 
+// the same sum from a face array (column q at xf[q M])
+template <int DD>
+__device__ inline double compose_face(const double* xf, const double* cf) {
+  double p = xf[0];
+#pragma unroll
+  for (int q0 = 0; q0 < 4 * DD; q0 += 16) {
+    double x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) x[q] = xf[(size_t)(1 + q0 + q) * M];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) p = fma(x[q], cf[q0 + q], p);
+  }
+  return p;
+}
+
 // four wavefronts per SIMD: 128 registers per lane and 19 KB of LDS per pair
 template <int DD>
 __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
@@ -1309,7 +1335,9 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
     double cfn[4 * DD];
 #pragma unroll
     for (int q = 0; q < 4 * DD; ++q) cfn[q] = column_coef<DD>(a, nI, nJ, q);
-    pn = compose<DD>(a, nsd, nl, cfn);
+    // the neighbour's face values, one 128-byte line per column (the same
+    // numbers as its cells of X, so p is the same sum)
+    pn = compose_face<DD>(a.xface + ((size_t)nsd * 4 + nside) * (4 * DD + 1) * M + t, cfn);
   }
   CellLoads cl[MM / PAIR];   // issued with the permeability loads
 #pragma unroll
