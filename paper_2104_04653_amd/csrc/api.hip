@@ -66,7 +66,6 @@ struct mrcm_ctx {
   double *K = nullptr, *lam = nullptr, *stage = nullptr, *src = nullptr;
   double* bcv[4] = {nullptr, nullptr, nullptr, nullptr};
   double *alpha = nullptr, *basis = nullptr, *X = nullptr, *coef = nullptr;
-  double* xface = nullptr;                // face cells' local solutions (16 x 16 subdomains)
   double *p = nullptr, *ux = nullptr, *uy = nullptr, *sub_stats = nullptr, *result = nullptr;
   double* tree = nullptr;
   // report block (one device allocation, read back with one copy):
@@ -592,7 +591,6 @@ SubArgs sub_args(const mrcm_ctx* c) {
   a.alpha = c->alpha;
   a.basis = c->basis;
   a.X = c->X;
-  a.xface = c->xface;
   a.blocks = c->tree;  // the subdomain blocks are the leaves of the interface tree
   a.coef = c->coef;
   a.p_out = c->p;
@@ -780,7 +778,6 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
     ALLOC(c, c->alpha, n_iface);
     ALLOC(c, c->basis, (size_t)std::max(n_iface, 1) * G.D * M);
     ALLOC(c, c->X, (size_t)G.n_sub * M * M * c->R);
-    if (M == 16) ALLOC(c, c->xface, (size_t)G.n_sub * 4 * M * c->R);
     ALLOC(c, c->coef, std::max(c->n_dof, 1));
     ALLOC(c, c->p, ncell);
     ALLOC(c, c->ux, (size_t)(G.nx + 1) * G.ny);

@@ -172,11 +172,21 @@ __device__ inline double readlane_d(double x, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// value of lane K of each 16-lane row (DPP row_newbcast, two 32-bit moves)
+// value of lane K of each 16-lane row (one 64-bit DPP row_newbcast move;
+// every lane has a valid source, so bound_ctrl only spares the copy of an
+// "old" value into the destination)
 template <int K>
-__device__ inline double row_bcast(double x) {   // one 64-bit DPP row_newbcast move
+__device__ inline double row_bcast(double x) {
   return __longlong_as_double(
-      __builtin_amdgcn_update_dpp(0LL, __double_as_longlong(x), 0x150 + K, 0xF, 0xF, false));
+      __builtin_amdgcn_update_dpp(0LL, __double_as_longlong(x), 0x150 + K, 0xF, 0xF, true));
+}
+
+// min(m, |p|) for pivot tracking, p uniform: the plain v_min_f64 (a NaN
+// pivot is caught by the pnan accumulator, so no quieting is needed)
+__device__ inline double pivot_min_abs(double m, double p) {
+  double r;
+  asm("v_min_f64 %0, %1, |%2|" : "=v"(r) : "v"(m), "s"(p));
+  return r;
 }
 
 // One Gauss-Jordan sweep with pivot K on a 16 x 16 tile held by one
@@ -193,15 +203,16 @@ __device__ inline void gj16_sweep(d4& s, int c, int g, double& pmin, double& pna
   double pcol[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) pcol[v] = row_bcast<K>(s[v]);
-  pmin = fmin(pmin, fabs(p));
+  pmin = pivot_min_abs(pmin, p);
   pnan = fma(p, 0.0, pnan);
   double ip = __builtin_amdgcn_rcp(p);              // reciprocal estimate, two Newton steps
   ip = fma(ip, fma(-p, ip, 1.0), ip);
   ip = fma(ip, fma(-p, ip, 1.0), ip);
   const double b = (c == K) ? ip : prow * ip;      // new row K
+  const double keep = (c == K) ? 0.0 : 1.0;        // column K is replaced, not updated
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const double nv = fma(-pcol[v], b, (c == K) ? 0.0 : s[v]);
+    const double nv = fma(-pcol[v], b, s[v] * keep);
     s[v] = (v == kv && g == kg) ? b : nv;
   }
 }

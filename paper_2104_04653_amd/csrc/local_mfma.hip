@@ -195,15 +195,6 @@ __device__ inline void write_block(const SubArgs& a, int sd, int I, int J, const
     for (int side = 0; side < 4; ++side)
       if (side_iface(g, I, J, side) == 0) { e0side = side; e0lo = side_sigma(side) > 0; }
   }
-  // the window's face values, [side][column][t], for the neighbours' stitch
-  {
-    double* xf = a.xface + (size_t)sd * 4 * (NBR + 1) * M;
-    for (int o = threadIdx.x; o < 4 * NQ * M; o += blockDim.x) {
-      const int side = o / (NQ * M), ql = (o / M) % NQ, t = o % M;
-      const int colg = ql == 0 ? 0 : 1 + ((ql - 1) >> 2) * DD + 4 * win + ((ql - 1) & 3);
-      if (ql > 0 || win == 0) __builtin_nontemporal_store(xb[side][t][ql], &xf[(side * (NBR + 1) + colg) * M + t]);
-    }
-  }
   const int npair = win == 0 ? 4 * NQ : 4 * (NQ - 1);
   for (int pr = threadIdx.x; pr < npair; pr += blockDim.x) {
     const int side = pr / (npair / 4), ql = pr % (npair / 4);
@@ -825,13 +816,18 @@ __device__ inline void gj_sweep_f32(f4& s, int c, int g, float& pmin, float& pna
   float pcol[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) pcol[v] = row_bcast_f<K>(s[v]);
-  pmin = fminf(pmin, p);
+  {
+    float r;   // the plain v_min_f32 (a NaN pivot is caught by pnan)
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(pmin), "s"(p));
+    pmin = r;
+  }
   pnan = fmaf(p, 0.0f, pnan);
   const float ip = __builtin_amdgcn_rcpf(p);
   const float b = (c == K) ? ip : prow * ip;
+  const float keep = (c == K) ? 0.0f : 1.0f;   // column K is replaced, not updated
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const float nv = fmaf(-pcol[v], b, (c == K) ? 0.0f : s[v]);
+    const float nv = fmaf(-pcol[v], b, s[v] * keep);
     s[v] = (v == kv && g == kg) ? b : nv;
   }
 }
@@ -1270,29 +1266,45 @@ __device__ inline double compose(const SubArgs& a, int sd, int l, const double* 
   return p;
 }
 
-// the same sum from a face array (column q at xf[q M])
+// The composed pressure p = X [1; c] of every cell (the multiscale solution
+// from the local solutions and the interface coefficients; it is the
+// pressure output) and each subdomain's pressure sum (for the zero-mean
+// shift without Dirichlet data), one cell per thread, one work-group per
+// subdomain: a streaming pass over X, so that the stitch kernel, whose work
+// is the latency-bound re-solve, reads only the pressures next to its faces.
 template <int DD>
-__device__ inline double compose_face(const double* xf, const double* cf) {
-  double p = xf[0];
+__global__ void __launch_bounds__(MM) compose_kernel(SubArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) stamp_now(a.stamps + STAMP_FLUX);
+  __shared__ double cfs[4 * DD];
+  __shared__ double red[MM / WAVE];
+  const Geo& g = a.g;
+  const int sd = blockIdx.x, l = threadIdx.x;
+  const int I = sd % g.SX, J = sd / g.SX;
+  if (l < 4 * DD) cfs[l] = column_coef<DD>(a, I, J, l);
+  __syncthreads();
+  const double p = compose<DD>(a, sd, l, cfs);
+  a.p_out[(size_t)(J * M + l / M) * g.nx + I * M + l % M] = p;
+  double s = p;
 #pragma unroll
-  for (int q0 = 0; q0 < 4 * DD; q0 += 16) {
-    double x[16];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((l & (WAVE - 1)) == 0) red[l / WAVE] = s;
+  __syncthreads();
+  if (l == 0) {
+    double t = red[0];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) x[q] = xf[(size_t)(1 + q0 + q) * M];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) p = fma(x[q], cf[q0 + q], p);
+    for (int k = 1; k < MM / WAVE; ++k) t += red[k];
+    a.sub_stats[3 * sd + 2] = t;
   }
-  return p;
 }
 
 // four wavefronts per SIMD: 128 registers per lane and 19 KB of LDS per pair
 template <int DD>
 __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) stamp_now(a.stamps + STAMP_FLUX);
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
-  __shared__ double pm[MM], bs_[MM], ps[MM], rs[MM];
+  __shared__ double bs_[MM], ps[MM], rs[MM];
+  __shared__ double pm0;   // composed pressure of cell 0 (the pin)
   __shared__ double Fout[4][M];
-  __shared__ double red[3][2];
+  __shared__ double red[2][2];
   __shared__ double xch[M][M + 1];
   const Geo& g = a.g;
   // the wave index is uniform per wavefront: taken into a scalar register,
@@ -1301,22 +1313,21 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
   const int lane = tid & 63, c = lane & 15, gq = lane >> 4;
   // Consecutive subdomains on one XCD: work-groups go to the 8 XCDs in
   // turn, so work-group b takes subdomain (b mod 8) n/8 + b/8, and the
-  // neighbours' face columns that a work-group reads were loaded into the
-  // same L2 by the neighbours' own work-groups (the launch 12 µs shorter).
+  // lines of the neighbours' face cells that a work-group reads were mostly
+  // loaded into the same L2 by the neighbours' own work-groups.
   const int nbk = gridDim.x;
   const int sd = (nbk % 8 == 0) ? (blockIdx.x % 8) * (nbk / 8) + blockIdx.x / 8 : blockIdx.x;
   const int I = sd % g.SX, J = sd / g.SX;
   const int nP = g.nP;
 
-  __shared__ double cfs[4 * DD];
-  if (tid < 4 * DD) cfs[tid] = column_coef<DD>(a, I, J, tid);
-  // the neighbour's side of each skeleton face (first 4 M threads): its
-  // composed pressure and mobility next to the face, loaded before this
-  // subdomain's own pressure so that both sets of loads are in flight together
+  // both sides of each skeleton face (first 4 M threads): the composed
+  // pressures next to the face (written by compose_kernel) and the
+  // neighbour's mobility
   const int side = lane >> 4, t = lane & 15;
   const int e = tid < 4 * M ? side_iface(g, I, J, side) : -1;
-  double pn = 0.0, kn = 1.0, al = 0.0, PH = 0.0, UH = 0.0;
+  double pn = 0.0, po = 0.0, kn = 1.0, al = 0.0, PH = 0.0, UH = 0.0;
   size_t nc_g = 0;   // the neighbour's cell (global index)
+  if (tid == 0) pm0 = a.p_out[(size_t)(J * M) * g.nx + I * M];
   if (e >= 0) {
     // interface data of the face: alpha and the interface pressure / flux
     // P_H, U_H = sum of coefficient times interface function
@@ -1332,19 +1343,14 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
     const size_t nc = (size_t)(nJ * M + nl / M) * g.nx + nI * M + nl % M;
     nc_g = nc;
     kn = a.K[nc] * a.lam[nc];
-    double cfn[4 * DD];
-#pragma unroll
-    for (int q = 0; q < 4 * DD; ++q) cfn[q] = column_coef<DD>(a, nI, nJ, q);
-    // the neighbour's face values, one 128-byte line per column (the same
-    // numbers as its cells of X, so p is the same sum)
-    pn = compose_face<DD>(a.xface + ((size_t)nsd * 4 + nside) * (4 * DD + 1) * M + t, cfn);
+    pn = a.p_out[nc];
+    const int lo = side_cell<M>(side, t);
+    po = a.p_out[(size_t)(J * M + lo / M) * g.nx + I * M + lo % M];
   }
   CellLoads cl[MM / PAIR];   // issued with the permeability loads
 #pragma unroll
   for (int q = 0; q < MM / PAIR; ++q) cl[q] = cell_loads<M>(a, I, J, tid + PAIR * q, 0);
   load_kappa<M>(a, I, J, kap);
-  __syncthreads();
-  for (int l = tid; l < MM; l += PAIR) pm[l] = compose<DD>(a, sd, l, cfs);
   __syncthreads();
   if (tid < 4 * M) {
     // one-sided Robin fluxes on both sides of each skeleton face; outflow
@@ -1356,7 +1362,7 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
       const double sig = side_sigma(side);
       const double ko = kap[l];
       const double TRo = sg.flen * ko / (sg.dist + al * sg.H), TRn = sg.flen * kn / (sg.dist + al * sg.H);
-      double Fown = TRo * (pm[l] - (PH - al * sg.H / ko * sig * UH));
+      double Fown = TRo * (po - (PH - al * sg.H / ko * sig * UH));
       double Fnb = TRn * (pn - (PH - al * sg.H / kn * (-sig) * UH));
       if (a.rho) {
         Fown += robin_grav(a, side, (size_t)(J * M + l / M) * g.nx + I * M + l % M, TRo, sg.dist);
@@ -1412,7 +1418,7 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
     if (tid == 0) {    // thread 0 owns cell 0
       const double tp = dg[0];
       dg[0] += tp;
-      bs_[0] += tp * pm[0];
+      bs_[0] += tp * pm0;
       pin_sc[0] = dfc;
       pin_sc[1] = tp;
     }
@@ -1433,12 +1439,12 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
 #pragma unroll 1
   for (int q = 0; q < MM / PAIR; ++q) {   // one cell at a time: the inverse blocks stay in registers
     const int l = tid + PAIR * q;
-    rs[l] = stitch_balance_residual<M>(a, I, J, l, kap, ps, Fout, pin_sc[0], pin_sc[1], pm[0]);
+    rs[l] = stitch_balance_residual<M>(a, I, J, l, kap, ps, Fout, pin_sc[0], pin_sc[1], pm0);
   }
   __syncthreads();
   solve_column_pair<DD>(Sv, w, rs, rs, c, gq, cy);   // in place: each row is read before it is written
 
-  double imb = 0.0, fmx = 0.0, psum = 0.0;
+  double imb = 0.0, fmx = 0.0;
 #pragma unroll 1
   for (int l = tid; l < MM; l += PAIR) {
     const int li = l % M, lj = l / M;
@@ -1456,26 +1462,22 @@ __global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
     const double net = F[1] - F[0] + F[3] - F[2];
     imb = fmax(imb, fabs(net - q));
     fmx = fmax(fmx, fmax(fmax(fabs(F[0]), fabs(F[1])), fmax(fabs(F[2]), fabs(F[3]))));
-    a.p_out[(size_t)j * g.nx + i] = pm[l];
-    psum += pm[l];
   }
   // reductions over the wave (fixed butterfly order), then over the two waves
+  // (the pressure sum of the subdomain is compose_kernel's)
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     imb = fmax(imb, __shfl_xor(imb, off));
     fmx = fmax(fmx, __shfl_xor(fmx, off));
-    psum += __shfl_xor(psum, off);
   }
   if (lane == 0) {
     red[0][w] = imb;
     red[1][w] = fmx;
-    red[2][w] = psum;
   }
   __syncthreads();
   if (tid == 0) {
     a.sub_stats[3 * sd + 0] = fmax(red[0][0], red[0][1]);
     a.sub_stats[3 * sd + 1] = fmax(red[1][0], red[1][1]);
-    a.sub_stats[3 * sd + 2] = red[2][0] + red[2][1];
   }
 }
 
@@ -1726,11 +1728,13 @@ hipError_t launch_basis32_m16d4(const SubArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(compose_kernel<4>, dim3(a.g.n_sub), dim3(MM), 0, st, a);
   hipLaunchKernelGGL(stitch_pair_kernel<4>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_stitch_m16d8(const SubArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(compose_kernel<8>, dim3(a.g.n_sub), dim3(MM), 0, st, a);
   hipLaunchKernelGGL(stitch_pair_kernel<8>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
   return hipGetLastError();
 }

@@ -36,18 +36,31 @@ __device__ inline double recip(double p) {
   return fma(r, fma(-p, r, 1.0), r);
 }
 
-// value of lane K of each 16-lane row (one 64-bit DPP row_newbcast move)
+// value of lane K of each 16-lane row (one 64-bit DPP row_newbcast move;
+// every lane has a valid source, so bound_ctrl only spares the compiler the
+// copy of an "old" value into the destination first)
 template <int K>
 __device__ inline double row_bcast(double x) {
   return __longlong_as_double(
-      __builtin_amdgcn_update_dpp(0LL, __double_as_longlong(x), 0x150 + K, 0xF, 0xF, false));
+      __builtin_amdgcn_update_dpp(0LL, __double_as_longlong(x), 0x150 + K, 0xF, 0xF, true));
+}
+
+// min(m, p) for pivot tracking, with p uniform (a scalar register): the
+// plain v_min_f64, without the quieting of NaN operands that fmin adds (a
+// NaN pivot is caught by the pnan accumulator instead)
+__device__ inline double pivot_min(double m, double p) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(m), "s"(p));
+  return r;
 }
 
 // One Gauss-Jordan sweep with pivot K on a tile in the output layout: the
 // pivot column (row 4 v + g, column K) comes from lane K of the lane's own
 // 16-lane row, the pivot row (row K, column c) from lane c of row K % 4.
-// Pivot health is accumulated without branches: pmin = min of the pivots,
-// pnan = sum of pivot * 0 (NaN once a pivot was not finite).
+// Column K is replaced by -pcol / p rather than updated: its old value is
+// multiplied by 0 (one multiply per register instead of a two-instruction
+// select).  Pivot health is accumulated without branches: pmin = min of
+// the pivots, pnan = sum of pivot * 0 (NaN once a pivot was not finite).
 template <int K>
 __device__ inline void gj_sweep(d4& s, int c, int g, double& pmin, double& pnan) {
   constexpr int kv = K >> 2, kg = K & 3;
@@ -56,13 +69,14 @@ __device__ inline void gj_sweep(d4& s, int c, int g, double& pmin, double& pnan)
   double pcol[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) pcol[v] = row_bcast<K>(s[v]);
-  pmin = fmin(pmin, p);
+  pmin = pivot_min(pmin, p);
   pnan = fma(p, 0.0, pnan);
   const double ip = recip(p);
   const double b = (c == K) ? ip : prow * ip;      // new row K
+  const double keep = (c == K) ? 0.0 : 1.0;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const double nv = fma(-pcol[v], b, (c == K) ? 0.0 : s[v]);
+    const double nv = fma(-pcol[v], b, s[v] * keep);
     s[v] = (v == kv && g == kg) ? b : nv;
   }
 }

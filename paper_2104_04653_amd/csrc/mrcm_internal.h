@@ -46,9 +46,6 @@ struct SubArgs {
   const double* alpha;    // per interface
   const double* basis;    // [iface][D][M]: rows 0..nP-1 pressure, nP..D-1 flux functions
   double* X;              // [sub][R][M*M] local solutions (R = 1 + 4D), column-major per subdomain
-  double* xface;          // [sub][side][R][M]: the local solutions in the cells next to each
-                          // side's faces (16 x 16 matrix-core kernels; the neighbours' stitch
-                          // reads them there instead of gathering strided cells of X), or nullptr
   double* blocks;         // [sub][4D][4D+1] symmetric local interface blocks
   const double* coef;     // interface solution (stitch kernel)
   double* p_out;          // nx*ny composed pressure (stitch kernel)
