@@ -200,7 +200,7 @@ __device__ void local_residual_dd(const double* b, const double* x, double* r, c
     const int li = l % M, lj = l / M;
     double hi = b[o], lo = 0.0;
     dd_fma(hi, lo, -dg[l], x[o]);
-    dd_fma(hi, lo, -(double)dgl[l], x[o]);
+    dd_fma_low(lo, -(double)dgl[l], x[o]);
     if (li < M - 1) dd_fma(hi, lo, -ex[l], x[(l + 1) * NR + col]);
     if (li > 0) dd_fma(hi, lo, -ex[l - 1], x[(l - 1) * NR + col]);
     if (lj < M - 1) dd_fma(hi, lo, -cy[l], x[(l + M) * NR + col]);

@@ -228,6 +228,11 @@ __device__ inline void dd_fma(double& hi, double& lo, double a, double b) {
   lo += pe + se;
 }
 
+// (hi, lo) += a b for a product at most eps |hi| (the rounding error of a
+// diagonal sum times the solution): it goes into the low part alone, whose
+// own rounding error is then of order eps^2 |hi|, as dd_fma's
+__device__ inline void dd_fma_low(double& lo, double a, double b) { lo = fma(a, b, lo); }
+
 // (ah + al) - (bh + bl) rounded once to FP64: the difference of the leading
 // parts is taken with an error-free two-difference, so a face flux
 // T ((p_c - p_d)) formed from pressures carried as unevaluated sums keeps

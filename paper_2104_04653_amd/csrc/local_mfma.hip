@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
     const int i = l % M, j = l / M;
     double ph = b0[l], pl = 0.0;
     dd_fma(ph, pl, -dg[l], pz[l]);
-    dd_fma(ph, pl, -(double)dgl[l], pz[l]);
+    dd_fma_low(pl, -(double)dgl[l], pz[l]);
     dd_fma(ph, pl, i < M - 1 ? -ex[l] : 0.0, pz[i < M - 1 ? l + 1 : l]);
     dd_fma(ph, pl, i > 0 ? -ex[l - 1] : 0.0, pz[i > 0 ? l - 1 : l]);
     dd_fma(ph, pl, j < M - 1 ? -cy[l] : 0.0, pz[j < M - 1 ? l + M : l]);
@@ -468,7 +468,7 @@ __global__ void __launch_bounds__(PAIR, 2) basis_pair_kernel(SubArgs a) {
       const int i = 4 * v + gq, l = j * M + i;
       double hi = side_rhs(bside, j, i, c), lo = 0.0;
       dd_fma(hi, lo, -dg[l], Xv[t][v]);
-      dd_fma(hi, lo, -(double)dgl[l], Xv[t][v]);
+      dd_fma_low(lo, -(double)dgl[l], Xv[t][v]);
       dd_fma(hi, lo, i < M - 1 ? -ex[l] : 0.0, T[i < M - 1 ? i + 1 : i][c]);
       dd_fma(hi, lo, i > 0 ? -ex[i > 0 ? l - 1 : l] : 0.0, T[i > 0 ? i - 1 : i][c]);
       r[v] = hi + lo;
@@ -1071,7 +1071,7 @@ __device__ inline f4 residual32_row(int t, const d4* Xv, Lds32& sh, int c, int g
     // double-double, with the exact diagonal: the cells' mass balances
     double r = side_rhs(sh.bside, j, i, c), lo = 0.0;
     dd_fma(r, lo, -sh.dg[l], Xv[t][v]);
-    dd_fma(r, lo, -(double)sh.dgl[l], Xv[t][v]);
+    dd_fma_low(lo, -(double)sh.dgl[l], Xv[t][v]);
     dd_fma(r, lo, i < M - 1 ? -exr : 0.0, xr);
     dd_fma(r, lo, i > 0 ? -exl : 0.0, xl);
     if (t > 0) dd_fma(r, lo, -sh.cy[C::cprev(t) * M + i], Xv[t > 0 ? t - 1 : 0][v]);
@@ -1159,7 +1159,7 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
       const int ln = lj < M - 1 ? l + M : l, ls = lj > 0 ? l - M : l;
       double r = sh.b0[l], lo = 0.0;
       dd_fma(r, lo, -sh.dg[l], sh.px[l]);
-      dd_fma(r, lo, -(double)sh.dgl[l], sh.px[l]);
+      dd_fma_low(lo, -(double)sh.dgl[l], sh.px[l]);
       dd_fma(r, lo, li < M - 1 ? -sh.ex[l] : 0.0, sh.px[le]);
       dd_fma(r, lo, li > 0 ? -sh.ex[lw] : 0.0, sh.px[lw]);
       dd_fma(r, lo, lj < M - 1 ? -sh.cy[l] : 0.0, sh.px[ln]);

@@ -206,7 +206,7 @@ __device__ __forceinline__ void residual_row(const Lds32b& sh, const double* Xg,
     double hi = k == 0 ? side_rhs32(sh.bside, j, i, c) : sh.b0[l], lo = 0.0;
     const double xc = x[l];
     dd_fma(hi, lo, -sh.dg[l], xc);
-    dd_fma(hi, lo, -(double)sh.dgl[l], xc);
+    dd_fma_low(lo, -(double)sh.dgl[l], xc);
     dd_fma(hi, lo, -ce, x[le]);
     dd_fma(hi, lo, -cw, x[lw]);
     dd_fma(hi, lo, -cn, x[ln]);
