@@ -741,6 +741,7 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
   G.nV = (SX - 1) * SY; G.n_sub = SX * SY;
   G.nP = p_dofs; G.nU = u_dofs; G.D = p_dofs + u_dofs;
   G.hx = g->lx / g->nx; G.hy = g->ly / g->ny;
+  G.tfx = G.hy / (0.5 * G.hx); G.tfy = G.hx / (0.5 * G.hy);
   bool any_dir = false;
   for (int s = 0; s < 4; ++s) { G.kind[s] = bc->kind[s]; any_dir |= bc->kind[s] == MRCM_BC_DIRICHLET; }
   G.gauge = any_dir ? 0 : 1;

@@ -11,7 +11,10 @@
 namespace mrcm {
 namespace local {
 
-__device__ inline double series2(double a, double b) { return 1.0 / (1.0 / a + 1.0 / b); }
+// transmissibility of a face from the half-cell transmissibilities of its
+// two cells (in series): one division, and symmetric in a and b, so both
+// cells of a face compute the same value
+__device__ inline double series2(double a, double b) { return a * b / (a + b); }
 
 // (hi, lo) += b with an error-free two-sum
 __device__ inline void dd_add(double& hi, double& lo, double b) {
@@ -135,8 +138,8 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
   const int li = l % M, lj = l / M;
   const int i = I * M + li, j = J * M + lj;
   const double kc = kap[l];
-  const double txc = kc * g.hy / (0.5 * g.hx);
-  const double tyc = kc * g.hx / (0.5 * g.hy);
+  const double txc = kc * g.tfx;
+  const double tyc = kc * g.tfy;
   // the diagonal is a sum of transmissibilities; its FP64 rounding error
   // (dlo, kept with an error-free two-sum) makes (diag + dlo) x exactly the
   // flux form sum of T (x_c - x_nb), so that residuals formed with it are the
@@ -152,7 +155,7 @@ __device__ void assemble_cell(const SubArgs& a, int I, int J, int l, const doubl
     const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
     if (inner) {
       int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
-      double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
+      double tn = kap[nb] * ((side < 2) ? g.tfx : g.tfy);
       double T = series2(side < 2 ? txc : tyc, tn);
       dd_add(diag, dlo, T);
       if (side == 1) cx = -T;
@@ -261,14 +264,14 @@ __device__ inline void stitch_out_fluxes(const SubArgs& a, int I, int J, int l, 
   const int li = l % M, lj = l / M;
   const int i = I * M + li, j = J * M + lj;
   const double kc = kap[l];
-  const double txc = kc * g.hy / (0.5 * g.hx), tyc = kc * g.hx / (0.5 * g.hy);
+  const double txc = kc * g.tfx, tyc = kc * g.tfy;
   const double pv = ph[l], pvl = pl ? pl[l] : 0.0;
 #pragma unroll
   for (int side = 0; side < 4; ++side) {
     const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
     if (inner) {
       const int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
-      const double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
+      const double tn = kap[nb] * ((side < 2) ? g.tfx : g.tfy);
       const double T = series2(side < 2 ? txc : tyc, tn);
       out[side] = T * dd_diff(pv, pvl, ph[nb], pl ? pl[nb] : 0.0);
       if (a.rho && side >= 2) {
@@ -311,11 +314,11 @@ __device__ inline double stitch_balance_residual(const SubArgs& a, int I, int J,
 #pragma unroll 1
   for (int side = 0; side < 4; ++side) {
     const bool inner = (side == 0) ? li > 0 : (side == 1) ? li < M - 1 : (side == 2) ? lj > 0 : lj < M - 1;
-    const double th = (side < 2) ? kc * g.hy / (0.5 * g.hx) : kc * g.hx / (0.5 * g.hy);
+    const double th = kc * ((side < 2) ? g.tfx : g.tfy);
     double out;
     if (inner) {
       const int nb = (side == 0) ? l - 1 : (side == 1) ? l + 1 : (side == 2) ? l - M : l + M;
-      const double tn = (side < 2) ? kap[nb] * g.hy / (0.5 * g.hx) : kap[nb] * g.hx / (0.5 * g.hy);
+      const double tn = kap[nb] * ((side < 2) ? g.tfx : g.tfy);
       const double T = series2(th, tn);
       out = T * dd_diff(pv, 0.0, ph[nb], 0.0);
       if (a.rho && side >= 2) {

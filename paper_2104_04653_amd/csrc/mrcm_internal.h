@@ -30,6 +30,7 @@ struct Geo {
   int prec;         // 0: FP64 local solves, 1: FP32 + FP64 iterative refinement,
                     // 2: surrogate + residual gate + FP64 re-solve
   double hx, hy;
+  double tfx, tfy;  // half-cell transmissibility per unit kappa: hy / (hx / 2), hx / (hy / 2)
   double grav;      // gravity along y, g dh/dy (used where SubArgs::rho is set)
 };
 
