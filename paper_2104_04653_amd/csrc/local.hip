@@ -663,6 +663,8 @@ hipError_t dispatch(const SubArgs& a, hipStream_t st, bool stitch) {
   if (M == 16 && D == 8 && !a.g.generic && a.g.prec == 0) {
     return stitch ? launch_stitch_m16d8(a, st) : launch_basis_m16d8(a, st);
   }
+  if (M == 32 && D == 8 && basis32x32_supported(a.g))
+    return stitch ? launch_stitch32x32(a, st) : launch_basis32x32(a, st, false);
   if (M == 32 && D == 4) {
     if (stitch && basis32x32_supported(a.g)) return launch_stitch32x32(a, st);
     if (!stitch && basis32x32_supported(a.g)) {
@@ -704,7 +706,7 @@ long long local_scratch_doubles(const Geo& g) {
   if (fast) return 0;
   // the matrix-core kernels of 32 x 32 subdomains; the FP32 form runs the
   // generic FP32 kernel first and needs its scratch
-  if (basis32x32_supported(g) && g.prec != 1) return basis32x32_scratch();
+  if (basis32x32_supported(g) && g.prec != 1) return basis32x32_scratch(g);
   const long long MM = (long long)g.M * g.M, R = 1 + 4 * g.D;
   if (g.M > 16) return 3 * MM * R + g.M * MM;
   return 2 * MM * R + (MM * R * 8 > 48 * 1024 ? g.M * MM : 0);

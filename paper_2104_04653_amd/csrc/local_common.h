@@ -347,10 +347,12 @@ __device__ inline double stitch_balance_residual(const SubArgs& a, int I, int J,
 // form in which the assembled interface matrix is symmetric), last column =
 // right-hand side.  Column col of the local solutions at cell l is
 // Xs[l * ls + col * cs] (cell-major in LDS or scratch, or the column-major
-// output array); all threads of the work-group take part.
+// output array); all threads of the work-group take part.  win >= 0: only
+// the columns of dofs 4 win .. 4 win + 3 of each side (and the right-hand
+// side for window 0), the ones that window's work-group solved.
 template <int M, int D>
 __device__ void generic_block(const SubArgs& a, int sd, int I, int J, const double* kap,
-                              const double* Xs, int ls, int cs) {
+                              const double* Xs, int ls, int cs, int win = -1) {
   constexpr int NBR = 4 * D, NBC = 4 * D + 1;
   const Geo& g = a.g;
   double* blk = a.blocks + (size_t)sd * NBR * NBC;
@@ -363,6 +365,7 @@ __device__ void generic_block(const SubArgs& a, int sd, int I, int J, const doub
   }
   for (int o = threadIdx.x; o < NBR * NBC; o += blockDim.x) {
     const int r = o / NBC, qc = o % NBC;
+    if (win >= 0 && (qc < NBR ? ((qc % D) >> 2) != win : win != 0)) continue;
     const int side = r / D, k = r % D;
     const int e = side_iface(g, I, J, side);
     double val = 0.0;

@@ -45,6 +45,10 @@ constexpr long long SC_ZC = SC_SINV + (long long)M * 1024;   // [row][4 tiles][4
 constexpr long long SC_XCH = SC_ZC + (long long)M * 1024;    // block + 4 tiles
 constexpr long long SC_RES = SC_XCH + 2048;                  // per wave: 4 tiles
 constexpr long long SC_TOTAL = SC_RES + 2048;
+// with windows of dofs (8 per side): each window's scratch, followed by its
+// copy of the particular solution (SC_PART)
+constexpr long long SC_PART = SC_TOTAL;
+constexpr long long SC_WINDOW = SC_TOTAL + MM;
 
 struct Blk {
   d4 t[2][2];   // tile (row block, column block)
@@ -154,27 +158,47 @@ __device__ __forceinline__ double side_rhs32(const double (*bside)[M][D], int lj
   return on ? v : 0.0;
 }
 
-// Solution tiles of row j in the output array: basis column c of the lane,
-// the particular column (col 0) replicated over the 16 MFMA columns, only
-// the lanes of column 0 storing it.
-__device__ __forceinline__ void store_x(double* Xg, int j, const d4* zb, const d4* zp, int c, int g) {
+// Where a lane's columns live: colp(c), the basis column of lane column c;
+// partp(), the particular solution.  XPlain: 4 dofs per side, the columns of
+// X itself.  XWindow: one window of 4 dofs per side out of more (col, the
+// lane's column of X); the particular solution is X's column 0 for the first
+// window, and the other windows keep their own copy in their scratch, as
+// only the first writes X's.
+struct XPlain {
+  double* x;
+  __device__ double* colp(int c) const { return x + (size_t)(1 + c) * MM; }
+  __device__ double* partp() const { return x; }
+};
+struct XWindow {
+  double* x;
+  int col;
+  double* part;
+  __device__ double* colp(int) const { return x + (size_t)col * MM; }
+  __device__ double* partp() const { return part; }
+};
+
+// Solution tiles of row j: basis column c of the lane, the particular column
+// replicated over the 16 MFMA columns, only the lanes of column 0 storing it.
+template <class XV>
+__device__ __forceinline__ void store_x(const XV& xv, int j, const d4* zb, const d4* zp, int c, int g) {
 #pragma unroll
   for (int Rr = 0; Rr < 2; ++Rr)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int l = j * M + 16 * Rr + 4 * v + g;
-      Xg[(size_t)(1 + c) * MM + l] = zb[Rr][v];
-      if (c == 0) Xg[l] = zp[Rr][v];
+      xv.colp(c)[l] = zb[Rr][v];
+      if (c == 0) xv.partp()[l] = zp[Rr][v];
     }
 }
-__device__ __forceinline__ void load_x(const double* Xg, int j, d4* zb, d4* zp, int c, int g) {
+template <class XV>
+__device__ __forceinline__ void load_x(const XV& xv, int j, d4* zb, d4* zp, int c, int g) {
 #pragma unroll
   for (int Rr = 0; Rr < 2; ++Rr)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int l = j * M + 16 * Rr + 4 * v + g;
-      zb[Rr][v] = Xg[(size_t)(1 + c) * MM + l];
-      zp[Rr][v] = Xg[l];
+      zb[Rr][v] = xv.colp(c)[l];
+      zp[Rr][v] = xv.partp()[l];
     }
 }
 
@@ -191,7 +215,8 @@ struct Lds32b {
 // elements are formed one at a time into the lane's own slots of buf (the
 // tile layout of store_t4) and read back as tiles: formed all together, their
 // 96 operand loads would be in flight at once beside the inverse block.
-__device__ __forceinline__ void residual_row(const Lds32b& sh, const double* Xg, int j, int c, int g,
+template <class XV>
+__device__ __forceinline__ void residual_row(const Lds32b& sh, const XV& xv, int j, int c, int g,
                                              int lane, double* buf, d4* rb, d4* rp) {
 #pragma unroll 1
   for (int e = 0; e < 16; ++e) {
@@ -202,7 +227,7 @@ __device__ __forceinline__ void residual_row(const Lds32b& sh, const double* Xg,
     const int ln = j < M - 1 ? l + M : l, ls = j > 0 ? l - M : l;
     const double ce = i < M - 1 ? sh.ex[l] : 0.0, cw = i > 0 ? sh.ex[lw] : 0.0;
     const double cn = j < M - 1 ? sh.cy[l] : 0.0, cs = j > 0 ? sh.cy[ls] : 0.0;
-    const double* x = Xg + (k == 0 ? (size_t)(1 + c) * MM : 0);
+    const double* x = k == 0 ? xv.colp(c) : xv.partp();
     double hi = k == 0 ? side_rhs32(sh.bside, j, i, c) : sh.b0[l], lo = 0.0;
     const double xc = x[l];
     dd_fma(hi, lo, -sh.dg[l], xc);
@@ -330,10 +355,12 @@ __device__ __forceinline__ void backward32(const double* cy, const double* scr, 
   }
 }
 
-// Robin data of the basis columns per skeleton face: T_R g_k(t), with the
-// flux functions scaled by -beta sigma (zero on the domain boundary)
+// Robin data of the basis columns of one window of 4 dofs per side (dofs
+// 4 win .. 4 win + 3 of DD) per skeleton face: T_R g_k(t), with the flux
+// functions scaled by -beta sigma (zero on the domain boundary)
+template <int DD>
 __device__ __forceinline__ void robin_data32(const SubArgs& a, int I, int J, const double* kap,
-                                    double (*bside)[M][D]) {
+                                    double (*bside)[M][D], int win) {
   const Geo& g = a.g;
   for (int o = threadIdx.x; o < 4 * M; o += blockDim.x) {
     const int side = o / M, t = o % M;
@@ -346,11 +373,12 @@ __device__ __forceinline__ void robin_data32(const SubArgs& a, int I, int J, con
       const double TR = sg.flen * kk / (sg.dist + al * sg.H);
       const double beta = al * sg.H / kk;
       const double sig = side_sigma(side);
-      const double* bs = a.basis + (size_t)e * D * M;
+      const double* bs = a.basis + (size_t)e * DD * M;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        const double ph = bs[k * M + t];
-        v[k] = TR * (k < g.nP ? ph : -beta * sig * ph);
+        const int kg = 4 * win + k;
+        const double ph = bs[kg * M + t];
+        v[k] = TR * (kg < g.nP ? ph : -beta * sig * ph);
       }
     }
 #pragma unroll
@@ -358,8 +386,8 @@ __device__ __forceinline__ void robin_data32(const SubArgs& a, int I, int J, con
   }
 }
 
-template <int W>
-__device__ __forceinline__ void basis32_wave(const SubArgs& a, Lds32b& sh, int sd, double* scr, double* Xg) {
+template <int W, class XV>
+__device__ __forceinline__ void basis32_wave(const SubArgs& a, Lds32b& sh, int sd, double* scr, const XV& xv) {
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
   PivotCheck pc;
   Blk P;
@@ -374,7 +402,7 @@ __device__ __forceinline__ void basis32_wave(const SubArgs& a, Lds32b& sh, int s
         rp[Rr][v] = sh.b0[j * M + i];
       }
   };
-  auto out_x = [&](int j, const d4* b, const d4* p) { store_x(Xg, j, b, p, c, g); };
+  auto out_x = [&](int j, const d4* b, const d4* p) { store_x(xv, j, b, p, c, g); };
   // factorisation and forward solve; the join; backward solve
   forward32<W, true, true>(sh.dg, sh.ex, sh.cy, sh.tr[W], scr, c, g, lane, pc, P, zb, zp, rhs_b, out_x);
   double* xch = scr + SC_XCH;
@@ -391,13 +419,13 @@ __device__ __forceinline__ void basis32_wave(const SubArgs& a, Lds32b& sh, int s
     load_t4(xch + 1024, zbn, zpn, lane);
     join32<true, true>(sh.dg, sh.ex, sh.cy, sh.tr[0], scr, c, g, lane, pc, P, zb, zp, Pn, zbn, zpn, xb, xp,
                        rhs_b);
-    store_x(Xg, JN, xb, xp, c, g);
+    store_x(xv, JN, xb, xp, c, g);
   }
   __syncthreads();
   if (W == 0) store_t4(xch + 1024, xb, xp, lane);   // the join's solution for wave 1
   __syncthreads();
   if (W == 1) load_t4(xch + 1024, xb, xp, lane);
-  auto z_x = [&](int j, d4* b, d4* p) { load_x(Xg, j, b, p, c, g); };
+  auto z_x = [&](int j, d4* b, d4* p) { load_x(xv, j, b, p, c, g); };
   backward32<W, true>(sh.cy, scr, c, g, lane, xb, xp, z_x, out_x);
   if (pc.bad()) atomicOr(a.status, ST_LOCAL_PIVOT);
   __syncthreads();
@@ -408,7 +436,7 @@ __device__ __forceinline__ void basis32_wave(const SubArgs& a, Lds32b& sh, int s
   // the correction to X
   double* zc = scr + SC_ZC;
   double* rbuf = scr + SC_RES + (long long)W * 1024;   // the wave's residual slots
-  auto rhs_r = [&](int j, d4* rb, d4* rp) { residual_row(sh, Xg, j, c, g, lane, rbuf, rb, rp); };
+  auto rhs_r = [&](int j, d4* rb, d4* rp) { residual_row(sh, xv, j, c, g, lane, rbuf, rb, rp); };
   auto out_zc = [&](int j, const d4* b, const d4* p) { store_t4(zc + (long long)j * 1024, b, p, lane); };
   forward32<W, false, true>(sh.dg, sh.ex, sh.cy, sh.tr[W], scr, c, g, lane, pc, P, zb, zp, rhs_r, out_zc);
   __syncthreads();   // every residual is formed before any correction is added
@@ -427,9 +455,9 @@ __device__ __forceinline__ void basis32_wave(const SubArgs& a, Lds32b& sh, int s
   if (W == 1) load_t4(xch + 1024, xb, xp, lane);
   auto add_x = [&](int j, const d4* b, const d4* p) {
     d4 ob[2], op[2];
-    load_x(Xg, j, ob, op, c, g);
+    load_x(xv, j, ob, op, c, g);
     d4 nb[2] = {ob[0] + b[0], ob[1] + b[1]}, np[2] = {op[0] + p[0], op[1] + p[1]};
-    store_x(Xg, j, nb, np, c, g);
+    store_x(xv, j, nb, np, c, g);
   };
   if (W == 0) add_x(JN, xb, xp);
   auto z_c = [&](int j, d4* b, d4* p) { load_t4(zc + (long long)j * 1024, b, p, lane); };
@@ -437,30 +465,43 @@ __device__ __forceinline__ void basis32_wave(const SubArgs& a, Lds32b& sh, int s
 }
 
 // FP64 basis functions of 32 x 32 subdomains (LIST: only the subdomains on
-// the fallback list of the FP32 kernel).  Two wavefronts per subdomain.
-template <bool LIST>
+// the fallback list of the FP32 kernel).  Two wavefronts per subdomain; with
+// DD = 8 dofs per side, DD / 4 windows of 4 dofs per side, one work-group
+// each (work-group b: subdomain b / (DD / 4), window b % (DD / 4), its own
+// scratch), every window factorising the subdomain's matrix.
+template <bool LIST, int DD>
 __global__ void __launch_bounds__(PAIR, 2) basis32x32_kernel(SubArgs a) {
+  static_assert(DD % 4 == 0 && (!LIST || DD == 4), "windows of 4 dofs per side");
+  constexpr int NW = DD / 4, RX = 4 * DD + 1;
   __shared__ Lds32b sh;
   const Geo& g = a.g;
-  int sd = blockIdx.x;
+  int sd = NW == 1 ? (int)blockIdx.x : (int)blockIdx.x / NW;
+  const int win = NW == 1 ? 0 : (int)blockIdx.x % NW;
   if (LIST) {
     if ((int)blockIdx.x >= a.fallback[0]) return;
     sd = a.fallback[1 + blockIdx.x];
   }
   const int I = sd % g.SX, J = sd / g.SX;
-  const int tid = threadIdx.x;
-  double* scr = a.scratch + (size_t)sd * a.scratch_stride;
-  double* Xg = a.X + (size_t)sd * R * MM;
+  const int tid = threadIdx.x, c = tid & 15;
+  double* scr = a.scratch + (size_t)sd * a.scratch_stride + (size_t)win * SC_WINDOW;
+  double* Xg = a.X + (size_t)sd * RX * MM;
   load_kappa<M>(a, I, J, sh.kap);
   __syncthreads();
   for (int l = tid; l < MM; l += PAIR)
     assemble_cell<M, 1, false>(a, I, J, l, sh.kap, sh.dg, sh.ex, sh.cy, sh.b0 + l, 1, nullptr, sh.dgl);
-  robin_data32(a, I, J, sh.kap, sh.bside);
+  robin_data32<DD>(a, I, J, sh.kap, sh.bside, win);
   __syncthreads();
-  if (__builtin_amdgcn_readfirstlane(tid >> 6) == 0) basis32_wave<0>(a, sh, sd, scr, Xg);
-  else basis32_wave<1>(a, sh, sd, scr, Xg);
+  if constexpr (NW == 1) {
+    const XPlain xv{Xg};
+    if (__builtin_amdgcn_readfirstlane(tid >> 6) == 0) basis32_wave<0>(a, sh, sd, scr, xv);
+    else basis32_wave<1>(a, sh, sd, scr, xv);
+  } else {
+    const XWindow xv{Xg, 1 + (c >> 2) * DD + 4 * win + (c & 3), win == 0 ? Xg : scr + SC_PART};
+    if (__builtin_amdgcn_readfirstlane(tid >> 6) == 0) basis32_wave<0>(a, sh, sd, scr, xv);
+    else basis32_wave<1>(a, sh, sd, scr, xv);
+  }
   __syncthreads();
-  generic_block<M, D>(a, sd, I, J, sh.kap, Xg, 1, MM);
+  generic_block<M, DD>(a, sd, I, J, sh.kap, Xg, 1, MM, NW == 1 ? -1 : win);
 }
 
 // ---------------------------------------------------------------------------
@@ -477,11 +518,12 @@ constexpr long long SS_PL = SS_RS + MM;
 constexpr long long SS_XCH = SS_PL + MM;
 constexpr long long SS_TOTAL = SS_XCH + 2048;
 
+template <int DD>
 struct Lds32s {
   double kap[MM], dg[MM], ex[MM], cy[MM], pm[MM], bs[MM];
   double Fout[4][M];          // outflow of this subdomain on its skeleton faces
   double tr[2][16][16];       // per-wave transpose tiles
-  double cfs[4 * D];          // interface coefficients of the basis columns
+  double cfs[4 * DD];         // interface coefficients of the basis columns
   double red[2][2];
   double pin[2];              // per-cell defect share, pin transmissibility
 };
@@ -501,23 +543,38 @@ __device__ __forceinline__ void load_t2(const double* src, d4* zp, int lane) {
   }
 }
 
-// composed pressure p = X [1; coefficients] at cell l of subdomain sd
+// composed pressure p = X [1; coefficients] at cell l of subdomain sd (4 DD
+// basis columns; the loads issued 16 at a time)
+template <int DD>
 __device__ __forceinline__ double compose32(const SubArgs& a, int sd, int l, const double* cf) {
-  const double* xr = a.X + (size_t)sd * R * MM + l;
-  double x[4 * D];
+  const double* xr = a.X + (size_t)sd * (4 * DD + 1) * MM + l;
+  if constexpr (DD == 4) {
+    double x[4 * DD];
 #pragma unroll
-  for (int q = 0; q < 4 * D; ++q) x[q] = xr[(size_t)(1 + q) * MM];
-  double p = xr[0];
+    for (int q = 0; q < 4 * DD; ++q) x[q] = xr[(size_t)(1 + q) * MM];
+    double p = xr[0];
 #pragma unroll
-  for (int q = 0; q < 4 * D; ++q) p = fma(x[q], cf[q], p);
-  return p;
+    for (int q = 0; q < 4 * DD; ++q) p = fma(x[q], cf[q], p);
+    return p;
+  } else {
+    double p = xr[0];
+#pragma unroll
+    for (int q0 = 0; q0 < 4 * DD; q0 += 16) {
+      double x[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) x[q] = xr[(size_t)(1 + q0 + q) * MM];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) p = fma(x[q], cf[q0 + q], p);
+    }
+    return p;
+  }
 }
 
 // One wavefront's solve of the stitch system for one column (rhs(j, rp)
 // fills the tiles of row j, replicated over the 16 MFMA columns) into the
 // cell array dst; FACTOR: form and store the inverse blocks first.
-template <int W, bool FACTOR, class Rhs>
-__device__ __forceinline__ void stitch_solve32(Lds32s& sh, double* scr, int c, int g, int lane,
+template <int W, bool FACTOR, class Rhs, class Sh>
+__device__ __forceinline__ void stitch_solve32(Sh& sh, double* scr, int c, int g, int lane,
                                                PivotCheck& pc, double* dst, Rhs rhs) {
   Blk P;
   d4 zb[2], zp[2];
@@ -557,8 +614,8 @@ __device__ __forceinline__ void stitch_solve32(Lds32s& sh, double* scr, int c, i
   backward32<W, false>(sh.cy, scr, c, g, lane, xb, xp, z, put);
 }
 
-template <int W>
-__device__ __forceinline__ void stitch32_wave(const SubArgs& a, Lds32s& sh, double* scr, int I, int J) {
+template <int W, class Sh>
+__device__ __forceinline__ void stitch32_wave(const SubArgs& a, Sh& sh, double* scr, int I, int J) {
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
   PivotCheck pc;
   double* ps = scr + SS_PS;
@@ -588,20 +645,21 @@ __device__ __forceinline__ void stitch32_wave(const SubArgs& a, Lds32s& sh, doub
   stitch_solve32<W, false>(sh, scr, c, g, lane, pc, pl, rhs_r);
 }
 
+template <int DD>
 __global__ void __launch_bounds__(PAIR, 2) stitch32x32_kernel(SubArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) stamp_now(a.stamps + STAMP_FLUX);
-  __shared__ Lds32s sh;
+  __shared__ Lds32s<DD> sh;
   const Geo& g = a.g;
   const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int sd = blockIdx.x, I = sd % g.SX, J = sd / g.SX;
   double* scr = a.scratch + (size_t)sd * a.scratch_stride;
-  if (tid < 4 * D) {
-    const int e = side_iface(g, I, J, tid / D);
-    sh.cfs[tid] = e >= 0 ? a.coef[(size_t)e * D + tid % D] : 0.0;
+  if (tid < 4 * DD) {
+    const int e = side_iface(g, I, J, tid / DD);
+    sh.cfs[tid] = e >= 0 ? a.coef[(size_t)e * DD + tid % DD] : 0.0;
   }
   load_kappa<M>(a, I, J, sh.kap);
   __syncthreads();
-  for (int l = tid; l < MM; l += PAIR) sh.pm[l] = compose32(a, sd, l, sh.cfs);
+  for (int l = tid; l < MM; l += PAIR) sh.pm[l] = compose32<DD>(a, sd, l, sh.cfs);
   __syncthreads();
   // one-sided Robin fluxes on both sides of each skeleton face, and their
   // average (the outflow of this subdomain)
@@ -612,11 +670,11 @@ __global__ void __launch_bounds__(PAIR, 2) stitch32x32_kernel(SubArgs a) {
     if (e >= 0) {
       const SideGeo sg = side_geo(g, side);
       const double al = a.alpha[e];
-      const double* bsf = a.basis + (size_t)e * D * M;
-      const double* ce = a.coef + (size_t)e * D;
+      const double* bsf = a.basis + (size_t)e * DD * M;
+      const double* ce = a.coef + (size_t)e * DD;
       double PH = 0.0, UH = 0.0;
       for (int k = 0; k < g.nP; ++k) PH += ce[k] * bsf[k * M + t];
-      for (int k = g.nP; k < D; ++k) UH += ce[k] * bsf[k * M + t];
+      for (int k = g.nP; k < DD; ++k) UH += ce[k] * bsf[k * M + t];
       const int l = side_cell<M>(side, t);
       const double sig = side_sigma(side);
       const double ko = sh.kap[l];
@@ -628,13 +686,13 @@ __global__ void __launch_bounds__(PAIR, 2) stitch32x32_kernel(SubArgs a) {
       const int nl = side_cell<M>(side ^ 1, t);
       const size_t nc = (size_t)(nJ * M + nl / M) * g.nx + nI * M + nl % M;
       const double kn = a.K[nc] * a.lam[nc];
-      double cfn[4 * D];
+      double cfn[4 * DD];
 #pragma unroll
-      for (int q = 0; q < 4 * D; ++q) {
-        const int en = side_iface(g, nI, nJ, q / D);
-        cfn[q] = en >= 0 ? a.coef[(size_t)en * D + q % D] : 0.0;
+      for (int q = 0; q < 4 * DD; ++q) {
+        const int en = side_iface(g, nI, nJ, q / DD);
+        cfn[q] = en >= 0 ? a.coef[(size_t)en * DD + q % DD] : 0.0;
       }
-      const double pn = compose32(a, nsd, nl, cfn);
+      const double pn = compose32<DD>(a, nsd, nl, cfn);
       const double TRn = sg.flen * kn / (sg.dist + al * sg.H);
       const double Fnb = TRn * (pn - (PH - al * sg.H / kn * (-sig) * UH)) + robin_grav(a, side ^ 1, nc, TRn, sg.dist);
       fo = 0.5 * (Fown - Fnb);
@@ -732,23 +790,33 @@ __global__ void __launch_bounds__(PAIR, 2) stitch32x32_kernel(SubArgs a) {
 }  // namespace
 
 bool basis32x32_supported(const Geo& g) {
-  return g.M == M && g.D == D && g.nP == 2 && !g.generic;
+  return g.M == M && !g.generic && ((g.D == 4 && g.nP == 2) || (g.D == 8 && g.prec == 0));
 }
 
-long long basis32x32_scratch() { return SC_TOTAL > SS_TOTAL ? SC_TOTAL : SS_TOTAL; }
+long long basis32x32_scratch(const Geo& g) {
+  const long long basis = g.D == 4 ? SC_TOTAL : (g.D / 4) * SC_WINDOW;   // one scratch per window
+  return basis > SS_TOTAL ? basis : SS_TOTAL;
+}
 
 hipError_t launch_stitch32x32(const SubArgs& a, hipStream_t st) {
   if (a.scratch_stride < SS_TOTAL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(stitch32x32_kernel, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
+  if (a.g.D == 8)
+    hipLaunchKernelGGL(stitch32x32_kernel<8>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
+  else
+    hipLaunchKernelGGL(stitch32x32_kernel<4>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_basis32x32(const SubArgs& a, hipStream_t st, bool list) {
-  if (a.scratch_stride < SC_TOTAL) return hipErrorInvalidValue;
-  if (list)
-    hipLaunchKernelGGL(basis32x32_kernel<true>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
-  else
-    hipLaunchKernelGGL(basis32x32_kernel<false>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
+  if (a.scratch_stride < basis32x32_scratch(a.g)) return hipErrorInvalidValue;
+  if (a.g.D == 8) {
+    if (list) return hipErrorInvalidValue;   // no FP32 form with 8 dofs per side
+    hipLaunchKernelGGL((basis32x32_kernel<false, 8>), dim3(2 * a.g.n_sub), dim3(PAIR), 0, st, a);
+  } else if (list) {
+    hipLaunchKernelGGL((basis32x32_kernel<true, 4>), dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((basis32x32_kernel<false, 4>), dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -130,10 +130,11 @@ hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st);
 // two work-groups per subdomain, one per window of 4 dofs per side
 hipError_t launch_basis_m16d8(const SubArgs& a, hipStream_t st);
 hipError_t launch_stitch_m16d8(const SubArgs& a, hipStream_t st);
-// (local_mfma32.hip) 32 x 32 subdomains, 4 dofs per side (2 + 2): FP64 basis
-// functions on the matrix cores; list = only the FP32 fallback list
+// (local_mfma32.hip) 32 x 32 subdomains, 4 dofs per side (2 + 2) or 8 (FP64
+// only, two windows of 4): FP64 basis functions on the matrix cores; list =
+// only the FP32 fallback list
 bool basis32x32_supported(const Geo& g);
-long long basis32x32_scratch();   // doubles of per-subdomain scratch it needs
+long long basis32x32_scratch(const Geo& g);   // doubles of per-subdomain scratch they need
 hipError_t launch_basis32x32(const SubArgs& a, hipStream_t st, bool list);
 hipError_t launch_stitch32x32(const SubArgs& a, hipStream_t st);
 bool local_supported(int M, int D);

@@ -1,8 +1,8 @@
 """Physics-based interface spaces and the adaptive Robin parameter on the GPU
 (MRCM_SPACE_PHYSICS, mrcm_set_adaptive_alpha; section 3.1) against the
 oracle's spaces (4 + 4 dof slots per interface, the unused ones fixed to
-zero): 16 x 16 subdomains on the matrix-core kernels (two windows of 4 dofs
-per side), 32 x 32 on the generic kernels.
+zero), on the matrix-core kernels (two windows of 4 dofs per side) at
+16 x 16 and 32 x 32 subdomains.
 
 * the local solutions X, column by column, in the slots of each
   interface's functions (which also checks the library's construction of
@@ -10,8 +10,8 @@ per side), 32 x 32 on the generic kernels.
 * p and the stitched fluxes at 1e-10, per-cell balance 1e-12, at 16x16 and
   32x32 subdomains, with and without the adaptive alpha;
 * the barrier case on which these spaces are exact (the fine solution);
-* the 16 x 16 matrix-core kernels against the generic kernels on the same
-  input (another elimination order: equal to rounding), blocks included.
+* the matrix-core kernels against the generic kernels on the same input
+  (another elimination order: equal to rounding), blocks included.
 """
 import numpy as np
 import pytest
@@ -150,15 +150,21 @@ def test_physics_spaces_errors():
         assert ei.value.code == E_INVAL
 
 
-def test_physics_matrix_core_kernels_match_generic_kernels():
-    """16 x 16 subdomains with 8 dofs per side: the matrix-core kernels
-    (each window of 4 dofs per side solved by a work-group of its own, the
-    blocks' columns written by their window) against the generic kernels
-    (MRCM_GENERIC_KERNELS selects them) on the same input."""
+@pytest.mark.parametrize("m", [16, 32])
+def test_physics_matrix_core_kernels_match_generic_kernels(m):
+    """8 dofs per side on the matrix-core kernels (each window of 4 dofs per
+    side solved by a work-group of its own, the blocks' columns written by
+    their window) against the generic kernels (MRCM_GENERIC_KERNELS selects
+    them) on the same input, with 16 x 16 and 32 x 32 subdomains."""
     import os
-    prob = physics_problem("channel256_q5", adaptive=(1e-2, 1e2), nx=128, ny=96, lx=0.5, ly=0.375, seed=4)
+    if m == 16:
+        prob = physics_problem("channel256_q5", adaptive=(1e-2, 1e2), nx=128, ny=96, lx=0.5, ly=0.375, seed=4)
+    else:
+        prob = physics_problem("channel2048x1024", adaptive=(1e-2, 1e2), nx=192, ny=128, lx=0.1875,
+                               ly=0.125, seed=4)
+    assert prob.sub_nx == m
     s = inputs.synthetic_saturation(prob, 5, 20)
-    say("case: physics spaces, matrix-core vs generic kernels 128x96")
+    say("case: physics spaces, matrix-core vs generic kernels %dx%d sub %d" % (prob.nx, prob.ny, m))
     os.environ["MRCM_GENERIC_KERNELS"] = "1"
     try:
         gen = run_gpu(prob, s=s)
