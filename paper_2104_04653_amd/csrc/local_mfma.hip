@@ -1269,31 +1269,49 @@ __device__ inline double compose(const SubArgs& a, int sd, int l, const double* 
 // The composed pressure p = X [1; c] of every cell (the multiscale solution
 // from the local solutions and the interface coefficients; it is the
 // pressure output) and each subdomain's pressure sum (for the zero-mean
-// shift without Dirichlet data), one cell per thread, one work-group per
-// subdomain: a streaming pass over X, so that the stitch kernel, whose work
-// is the latency-bound re-solve, reads only the pressures next to its faces.
+// shift without Dirichlet data), one work-group per subdomain, two
+// neighbouring cells per thread (16-byte loads, each cell's sum in the
+// order of compose): a streaming pass over X, so that the stitch kernel,
+// whose work is the latency-bound re-solve, reads only the pressures next
+// to its faces.
+constexpr int COMPOSE_NT = MM / 2;
 template <int DD>
-__global__ void __launch_bounds__(MM) compose_kernel(SubArgs a) {
+__global__ void __launch_bounds__(COMPOSE_NT) compose_kernel(SubArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) stamp_now(a.stamps + STAMP_FLUX);
   __shared__ double cfs[4 * DD];
-  __shared__ double red[MM / WAVE];
+  __shared__ double red[COMPOSE_NT / WAVE];
   const Geo& g = a.g;
-  const int sd = blockIdx.x, l = threadIdx.x;
+  const int sd = blockIdx.x, t = threadIdx.x, l = 2 * t;
   const int I = sd % g.SX, J = sd / g.SX;
-  if (l < 4 * DD) cfs[l] = column_coef<DD>(a, I, J, l);
+  if (t < 4 * DD) cfs[t] = column_coef<DD>(a, I, J, t);
   __syncthreads();
-  const double p = compose<DD>(a, sd, l, cfs);
-  a.p_out[(size_t)(J * M + l / M) * g.nx + I * M + l % M] = p;
-  double s = p;
+  typedef double dbl2 __attribute__((ext_vector_type(2)));
+  const dbl2* xr = reinterpret_cast<const dbl2*>(a.X + (size_t)sd * (4 * DD + 1) * MM + l);
+  dbl2 p = __builtin_nontemporal_load(xr);
+#pragma unroll
+  for (int q0 = 0; q0 < 4 * DD; q0 += 16) {
+    dbl2 x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) x[q] = __builtin_nontemporal_load(xr + (size_t)(1 + q0 + q) * (MM / 2));
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      p.x = fma(x[q].x, cfs[q0 + q], p.x);
+      p.y = fma(x[q].y, cfs[q0 + q], p.y);
+    }
+  }
+  double* po = a.p_out + (size_t)(J * M + l / M) * g.nx + I * M + l % M;
+  po[0] = p.x;
+  po[1] = p.y;
+  double s = p.x + p.y;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if ((l & (WAVE - 1)) == 0) red[l / WAVE] = s;
+  if ((t & (WAVE - 1)) == 0) red[t / WAVE] = s;
   __syncthreads();
-  if (l == 0) {
-    double t = red[0];
+  if (t == 0) {
+    double u = red[0];
 #pragma unroll
-    for (int k = 1; k < MM / WAVE; ++k) t += red[k];
-    a.sub_stats[3 * sd + 2] = t;
+    for (int k = 1; k < COMPOSE_NT / WAVE; ++k) u += red[k];
+    a.sub_stats[3 * sd + 2] = u;
   }
 }
 
@@ -1728,13 +1746,13 @@ hipError_t launch_basis32_m16d4(const SubArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_stitch_m16d4(const SubArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(compose_kernel<4>, dim3(a.g.n_sub), dim3(MM), 0, st, a);
+  hipLaunchKernelGGL(compose_kernel<4>, dim3(a.g.n_sub), dim3(COMPOSE_NT), 0, st, a);
   hipLaunchKernelGGL(stitch_pair_kernel<4>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_stitch_m16d8(const SubArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(compose_kernel<8>, dim3(a.g.n_sub), dim3(MM), 0, st, a);
+  hipLaunchKernelGGL(compose_kernel<8>, dim3(a.g.n_sub), dim3(COMPOSE_NT), 0, st, a);
   hipLaunchKernelGGL(stitch_pair_kernel<8>, dim3(a.g.n_sub), dim3(PAIR), 0, st, a);
   return hipGetLastError();
 }
