@@ -53,7 +53,7 @@ TRANSPORT_BYTES_NEWTON = 15 * 8
 # summary was taken on
 KERNELS = {
     16: ("basis_pair_kernel<false, 4>", ("local_mfma.hip", "local_common.h", "mrcm_internal.h", "mfma_tile.h")),
-    32: ("basis32x32_kernel<false>", ("local_mfma32.hip", "local_common.h", "mrcm_internal.h", "mfma_tile.h")),
+    32: ("basis32x32_kernel<false, 4>", ("local_mfma32.hip", "local_common.h", "mrcm_internal.h", "mfma_tile.h")),
 }
 
 

@@ -1016,6 +1016,9 @@ hipError_t launch_iface_residual(const Geo& g, const double* blocks, const doubl
   if (g.D == 4)
     hipLaunchKernelGGL(iface_residual_kernel<4>, dim3(RESID_WG), dim3(NT), 0, st, g, blocks, x, r,
                        partials);
+  else if (g.D == 8)
+    hipLaunchKernelGGL(iface_residual_kernel<8>, dim3(RESID_WG), dim3(NT), 0, st, g, blocks, x, r,
+                       partials);
   else
     hipLaunchKernelGGL(iface_residual_kernel<0>, dim3(RESID_WG), dim3(NT), 0, st, g, blocks, x, r,
                        partials);
