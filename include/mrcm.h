@@ -105,7 +105,8 @@ typedef struct {
   int32_t n_dof;         /* interface unknowns */
   int32_t ir_iters_max;  /* FP32_IR: largest refinement count over subdomains */
   int32_t fallbacks;     /* FP32_IR / SURROGATE: subdomains re-solved in FP64 */
-  double interface_residual; /* max |b - A x| / max |b| of the interface solve */
+  double interface_residual; /* max_i |b - A x|_i / max_i (|b_i| + sum_j |A_ij x_j|)
+                                of the interface solve (a normwise backward error) */
   double ms_surrogate;   /* SURROGATE: network inference + residual gate */
   int32_t interface_ir_steps; /* refinement steps of the interface solve (taken while
                                  max |b - A x| > tol max |b|, at most max_steps: see
@@ -196,13 +197,14 @@ int mrcm_set_refinement(mrcm_ctx* ctx, int32_t max_steps, double tol);
 
 /* Stopping rule of the iterative refinement of the FP64 interface solve
  * (eq. (mrc2)): after the direct solve, refinement steps are taken while
- * max |b - A x| > tol max |b|, at most max_steps; if the residual is then
- * above fail_tol max |b| the solve fails with MRCM_E_NO_CONV.  Defaults:
- * 3 steps; tol 1e-14 (FP64 and SURROGATE), 1e-12 (FP32_IR); fail_tol 1e-10
- * (the residual of an FP64 solution is about eps |A| |x|, which can exceed
- * 1e-14 of the right-hand side on ill-conditioned systems whose solution
- * is still accurate).  Takes effect at the next solve.  Errors: MRCM_E_INVAL
- * unless 0 <= max_steps <= 16, 0 < tol < 1 and 0 < fail_tol < 1. */
+ * max |b - A x| > tol S, S = max_i (|b_i| + sum_j |A_ij x_j|), at most
+ * max_steps; if the residual is then above fail_tol S the solve fails with
+ * MRCM_E_NO_CONV.  Measured against S (a normwise backward error), the
+ * residual that FP64 rounding leaves is about eps wherever the solution
+ * is accurate, also where |A| |x| is far above |b|.  Defaults: 3 steps;
+ * tol 1e-14 (FP64 and SURROGATE), 1e-12 (FP32_IR); fail_tol 1e-10.  Takes
+ * effect at the next solve.  Errors: MRCM_E_INVAL unless
+ * 0 <= max_steps <= 16, 0 < tol < 1 and 0 < fail_tol < 1. */
 int mrcm_set_interface_refinement(mrcm_ctx* ctx, int32_t max_steps, double tol, double fail_tol);
 
 /* Adaptive Robin parameter (section 3.1, last paragraph; section 5.5):

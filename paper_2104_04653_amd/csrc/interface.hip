@@ -822,7 +822,10 @@ __global__ void add_kernel(double* x, const double* dx, int n) {
 
 // r = b - A x gathered from the subdomain blocks (each interface row has
 // two owners: its lower- and higher-index subdomain).  Stage 1: per
-// work-group maxima of |r| and |b|; stage 2: one work-group reduces them.
+// work-group maxima of |r_i| and of the row's scale |b_i| + sum_j |A_ij x_j|
+// (so that max |r| / max scale is a normwise backward error, which the
+// rounding of an FP64 solve leaves near eps even where |A| |x| is far above
+// |b|); stage 2: one work-group reduces them.
 // interface edge on side (W, E, S, N) of subdomain (I, J), -1 on the
 // domain boundary
 __device__ inline int side_edge(const Geo& g, int I, int J, int side) {
@@ -859,6 +862,7 @@ __global__ void __launch_bounds__(NT) iface_residual_kernel(Geo g, const double*
       sub[1] = sub[0] + g.SX; side[1] = 2;
     }
     double hi = 0.0, lo = 0.0, b = 0.0;   // residual b - A x in double-double
+    double sabs = 0.0;                    // sum of |A_ij x_j| of the row
     if constexpr (DT > 0) {
       // all of the row's loads first, from clamped addresses (a side on the
       // domain boundary contributes the exact no-op 0 * 0), then the
@@ -889,7 +893,10 @@ __global__ void __launch_bounds__(NT) iface_residual_kernel(Geo g, const double*
 #pragma unroll
         for (int sd_side = 0; sd_side < 4; ++sd_side)
 #pragma unroll
-          for (int kk = 0; kk < DT; ++kk) two_prod_sub(hi, lo, av[o][sd_side][kk], xv[o][sd_side][kk]);
+          for (int kk = 0; kk < DT; ++kk) {
+            two_prod_sub(hi, lo, av[o][sd_side][kk], xv[o][sd_side][kk]);
+            sabs += fabs(av[o][sd_side][kk] * xv[o][sd_side][kk]);
+          }
       }
     } else {
       for (int o = 0; o < 2; ++o) {
@@ -901,14 +908,18 @@ __global__ void __launch_bounds__(NT) iface_residual_kernel(Geo g, const double*
         for (int sd_side = 0; sd_side < 4; ++sd_side) {
           const int ee = side_edge(g, I, J, sd_side);
           if (ee < 0) continue;
-          for (int kk = 0; kk < D; ++kk) two_prod_sub(hi, lo, blk[sd_side * D + kk], x[(size_t)ee * D + kk]);
+          for (int kk = 0; kk < D; ++kk) {
+            const double av = blk[sd_side * D + kk], xv = x[(size_t)ee * D + kk];
+            two_prod_sub(hi, lo, av, xv);
+            sabs += fabs(av * xv);
+          }
         }
       }
     }
     const double res = hi + lo;
     if (rvec) rvec[row] = res;
     rmax = fmax(rmax, fabs(res));
-    bmax = fmax(bmax, fabs(b));
+    bmax = fmax(bmax, fabs(b) + sabs);
   }
   red[0][threadIdx.x] = rmax;
   red[1][threadIdx.x] = bmax;

@@ -1,7 +1,8 @@
 """mrcm_step (mobility update, solve and fine-scale reconstruction in one
 call with one synchronisation) against the three separate calls: the same
 kernels on the same inputs, so the outputs are bitwise equal, also where the
-interface solve needs refinement (the reconstruction is then redone)."""
+interface solve is refined (the reconstruction is then redone; the
+refinement is forced by a stopping tolerance below the FP64 floor)."""
 import numpy as np
 import pytest
 
@@ -12,32 +13,36 @@ from tests.gpu_util import rel, run_oracle, say
 pytestmark = pytest.mark.gpu
 
 
-def separate_calls(prob, s, precision="fp64"):
+def separate_calls(prob, s, precision="fp64", refine=False):
     from paper_2104_04653_amd import MRCMSolver
     with MRCMSolver(prob, precision=precision) as sol:
+        if refine:
+            sol.set_interface_refinement(2, 1e-17, 1e-10)
         sol.update_mobility(s)
         sol.solve()
         p, ux, uy, imb = sol.fine_flux()
         return p, ux, uy, imb, sol.stats()
 
 
-def one_step(prob, s, precision="fp64"):
+def one_step(prob, s, precision="fp64", refine=False):
     from paper_2104_04653_amd import MRCMSolver
     with MRCMSolver(prob, precision=precision) as sol:
+        if refine:
+            sol.set_interface_refinement(2, 1e-17, 1e-10)
         p, ux, uy, imb = sol.step(s)
         return p, ux, uy, imb, sol.stats()
 
 
-@pytest.mark.parametrize("workload,kw,step", [
-    ("gauss64", {"seed": 2}, (3, 10)),
-    ("channel256_q5", {}, (7, 20)),   # needs interface refinement
+@pytest.mark.parametrize("workload,kw,step,refine", [
+    ("gauss64", {"seed": 2}, (3, 10), False),
+    ("channel256_q5", {}, (7, 20), True),   # with interface refinement
 ])
-def test_step_equals_separate_calls(workload, kw, step):
+def test_step_equals_separate_calls(workload, kw, step, refine):
     prob = inputs.make_problem(workload, **kw)
     s = inputs.synthetic_saturation(prob, *step)
     say("case: step vs separate calls,", workload)
-    a = separate_calls(prob, s)
-    b = one_step(prob, s)
+    a = separate_calls(prob, s, refine=refine)
+    b = one_step(prob, s, refine=refine)
     for x, y in zip(a[:3], b[:3]):
         assert np.array_equal(x, y)
     assert a[3] == b[3]
@@ -52,7 +57,7 @@ def test_step_equals_separate_calls(workload, kw, step):
             st["ms_local"], st["ms_interface"], st["ms_flux"]))
         for k in ("ms_local", "ms_interface", "ms_flux"):
             assert 0.0 < st[k] < 1e3
-    if workload == "channel256_q5":
+    if refine:
         assert sb["interface_ir_steps"] > 0
     # and against the oracle, as the separate calls are
     ref = run_oracle(prob, s=s)
