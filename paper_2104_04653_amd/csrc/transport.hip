@@ -63,12 +63,42 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-// sum of component comp of the np partials (stride 2), the same order in
-// every work-group
-__device__ inline double sum_partials(const double* part, int np, int comp, double* red) {
-  double v = 0.0;
-  for (int k = threadIdx.x; k < np; k += TB) v += part[2 * (size_t)k + comp];
-  return block_sum(v, red);
+// two sums over the work-group at once (one pair of barriers; each sum in
+// the order of block_sum); red holds 2 TB / 64 doubles
+__device__ inline double2 block_sum2(double u, double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    u += __shfl_xor(u, off);
+    v += __shfl_xor(v, off);
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = u;
+    red[TB / 64 + (threadIdx.x >> 6)] = v;
+  }
+  __syncthreads();
+  double su = 0.0, sv = 0.0;
+#pragma unroll
+  for (int k = 0; k < TB / 64; ++k) {
+    su += red[k];
+    sv += red[TB / 64 + k];
+  }
+  return make_double2(su, sv);
+}
+
+// both components of the np partials (pairs), the same order in every
+// work-group: thread t adds partials t, t + TB, ... (16-byte loads, issued
+// together), then block_sum2
+__device__ inline double2 sum_partials(const double* part, int np, double* red) {
+  const double2* p2 = reinterpret_cast<const double2*>(part);
+  double u = 0.0, v = 0.0;
+#pragma unroll 4
+  for (int k = threadIdx.x; k < np; k += TB) {
+    const double2 x = p2[k];
+    u += x.x;
+    v += x.y;
+  }
+  return block_sum2(u, v, red);
 }
 
 
@@ -159,12 +189,15 @@ __global__ void __launch_bounds__(TB) assemble_kernel(TransportArgs a) {
 // kernel C's partials; convergence check; p_k = r + beta (p_{k-1} - omega
 // v_{k-1}) and v_k = A p_k (neighbours' p formed on the fly); partials of
 // (r^, v_k).
+// FIRST: iteration 0, whose p is r (the previous p and v hold nothing and
+// are not read)
+template <bool FIRST>
 __global__ void __launch_bounds__(TB) bicg_a_kernel(TransportArgs a, int k, int np) {
-  __shared__ double red[TB / 64];
+  __shared__ double red[2 * TB / 64];
   if (a.scal[TS_DONE] != 0.0) return;
   const int par = k & 1, prv = par ^ 1;
-  const double rho = sum_partials(a.part[2], np, 0, red);
-  const double rr = sum_partials(a.part[2], np, 1, red);
+  const double2 sr = sum_partials(a.part[2], np, red);
+  const double rho = sr.x, rr = sr.y;
   const double bb = a.scal[TS_BB];
   const bool conv = rr <= a.tol2 * bb;
   const bool brk = !(rho != 0.0) || !isfinite(rho);
@@ -176,30 +209,50 @@ __global__ void __launch_bounds__(TB) bicg_a_kernel(TransportArgs a, int k, int 
     }
     return;
   }
-  const double beta = k == 0 ? 0.0 : (rho / a.scal[TS_RHO + prv]) * (a.scal[TS_ALPHA + prv] / a.scal[TS_OMEGA + prv]);
-  const double om = k == 0 ? 0.0 : a.scal[TS_OMEGA + prv];
+  const double beta = FIRST ? 0.0 : (rho / a.scal[TS_RHO + prv]) * (a.scal[TS_ALPHA + prv] / a.scal[TS_OMEGA + prv]);
+  const double om = FIRST ? 0.0 : a.scal[TS_OMEGA + prv];
   if (blockIdx.x == 0 && threadIdx.x == 0) a.scal[TS_RHO + par] = rho;
   const double* po = a.p[prv];
   const double* vo = a.v[prv];
   double* pn = a.p[par];
   double* vn = a.v[par];
   const int n = a.nx * a.ny;
+  // the loads of all CPT cells are issued together: indices are clamped
+  // rather than branched on, the terms of missing neighbours are dropped by
+  // selects (in the stencil's order of addition), and the stores wait until
+  // every value is formed
+  double pcs[CPT], vvs[CPT];
   double rv = 0.0;
+#pragma unroll
   for (int kk = 0; kk < CPT; ++kk) {
     const int cell = (blockIdx.x * CPT + kk) * TB + threadIdx.x;
-    if (cell >= n) break;
-    const int i = cell % a.nx, j = cell / a.nx;
-    // the first iteration's p is r (the previous buffers hold nothing)
-    auto pnew = [&](int c2) { return k == 0 ? a.r[c2] : a.r[c2] + beta * (po[c2] - om * vo[c2]); };
-    const double pc = pnew(cell);
+    const int cc = min(cell, n - 1);
+    const int i = cc % a.nx, j = cc / a.nx;
+    const int cw = i > 0 ? cc - 1 : cc, ce = i < a.nx - 1 ? cc + 1 : cc;
+    const int cs = j > 0 ? cc - a.nx : cc, cn = j < a.ny - 1 ? cc + a.nx : cc;
+    auto pnew = [&](int c2) {
+      if (FIRST) return a.r[c2];
+      const double r = a.r[c2], pv = po[c2], v = vo[c2];
+      return r + beta * (pv - om * v);
+    };
+    const double w = a.aw[cc], e = a.ae[cc], so = a.as[cc], no = a.an[cc], rh = a.rh[cc];
+    const double pc = pnew(cc), pw = pnew(cw), pe = pnew(ce), ps = pnew(cs), pnb = pnew(cn);
     double vv = pc;
-    if (i > 0) vv += a.aw[cell] * pnew(cell - 1);
-    if (i < a.nx - 1) vv += a.ae[cell] * pnew(cell + 1);
-    if (j > 0) vv += a.as[cell] * pnew(cell - a.nx);
-    if (j < a.ny - 1) vv += a.an[cell] * pnew(cell + a.nx);
-    pn[cell] = pc;
-    vn[cell] = vv;
-    rv += a.rh[cell] * vv;
+    vv += i > 0 ? w * pw : 0.0;
+    vv += i < a.nx - 1 ? e * pe : 0.0;
+    vv += j > 0 ? so * ps : 0.0;
+    vv += j < a.ny - 1 ? no * pnb : 0.0;
+    pcs[kk] = pc;
+    vvs[kk] = vv;
+    if (cell < n) rv += rh * vv;
+  }
+#pragma unroll
+  for (int kk = 0; kk < CPT; ++kk) {
+    const int cell = (blockIdx.x * CPT + kk) * TB + threadIdx.x;
+    if (cell < n) {
+      pn[cell] = pcs[kk];
+      vn[cell] = vvs[kk];
+    }
   }
   const double s = block_sum(rv, red);
   if (threadIdx.x == 0) {
@@ -211,10 +264,10 @@ __global__ void __launch_bounds__(TB) bicg_a_kernel(TransportArgs a, int k, int 
 // Kernel B: alpha = rho / (r^, v); q = r - alpha v (the "s" of BiCGSTAB)
 // and t = A q (neighbours' q on the fly); partials of (t, q), (t, t).
 __global__ void __launch_bounds__(TB) bicg_b_kernel(TransportArgs a, int k, int np) {
-  __shared__ double red[TB / 64];
+  __shared__ double red[2 * TB / 64];
   if (a.scal[TS_DONE] != 0.0) return;
   const int par = k & 1;
-  const double rv = sum_partials(a.part[0], np, 0, red);
+  const double rv = sum_partials(a.part[0], np, red).x;
   const double alpha = a.scal[TS_RHO + par] / rv;
   if (!(rv != 0.0) || !isfinite(alpha)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -226,61 +279,91 @@ __global__ void __launch_bounds__(TB) bicg_b_kernel(TransportArgs a, int k, int 
   if (blockIdx.x == 0 && threadIdx.x == 0) a.scal[TS_ALPHA + par] = alpha;
   const double* vn = a.v[par];
   const int n = a.nx * a.ny;
+  // loads of all CPT cells issued together, as in kernel A
+  double qcs[CPT], tvs[CPT];
   double ts = 0.0, tt = 0.0;
+#pragma unroll
   for (int kk = 0; kk < CPT; ++kk) {
     const int cell = (blockIdx.x * CPT + kk) * TB + threadIdx.x;
-    if (cell >= n) break;
-    const int i = cell % a.nx, j = cell / a.nx;
-    auto qnew = [&](int c2) { return a.r[c2] - alpha * vn[c2]; };
-    const double qc = qnew(cell);
+    const int cc = min(cell, n - 1);
+    const int i = cc % a.nx, j = cc / a.nx;
+    const int cw = i > 0 ? cc - 1 : cc, ce = i < a.nx - 1 ? cc + 1 : cc;
+    const int cs = j > 0 ? cc - a.nx : cc, cn = j < a.ny - 1 ? cc + a.nx : cc;
+    auto qnew = [&](int c2) {
+      const double r = a.r[c2], v = vn[c2];
+      return r - alpha * v;
+    };
+    const double w = a.aw[cc], e = a.ae[cc], so = a.as[cc], no = a.an[cc];
+    const double qc = qnew(cc), qw = qnew(cw), qe = qnew(ce), qs = qnew(cs), qn = qnew(cn);
     double tv = qc;
-    if (i > 0) tv += a.aw[cell] * qnew(cell - 1);
-    if (i < a.nx - 1) tv += a.ae[cell] * qnew(cell + 1);
-    if (j > 0) tv += a.as[cell] * qnew(cell - a.nx);
-    if (j < a.ny - 1) tv += a.an[cell] * qnew(cell + a.nx);
-    a.q[cell] = qc;
-    a.t[cell] = tv;
-    ts += tv * qc;
-    tt += tv * tv;
+    tv += i > 0 ? w * qw : 0.0;
+    tv += i < a.nx - 1 ? e * qe : 0.0;
+    tv += j > 0 ? so * qs : 0.0;
+    tv += j < a.ny - 1 ? no * qn : 0.0;
+    qcs[kk] = qc;
+    tvs[kk] = tv;
+    if (cell < n) {
+      ts += tv * qc;
+      tt += tv * tv;
+    }
   }
-  const double s1 = block_sum(ts, red);
-  const double s2 = block_sum(tt, red);
+#pragma unroll
+  for (int kk = 0; kk < CPT; ++kk) {
+    const int cell = (blockIdx.x * CPT + kk) * TB + threadIdx.x;
+    if (cell < n) {
+      a.q[cell] = qcs[kk];
+      a.t[cell] = tvs[kk];
+    }
+  }
+  const double2 s = block_sum2(ts, tt, red);
   if (threadIdx.x == 0) {
-    a.part[1][2 * (size_t)blockIdx.x + 0] = s1;
-    a.part[1][2 * (size_t)blockIdx.x + 1] = s2;
+    a.part[1][2 * (size_t)blockIdx.x + 0] = s.x;
+    a.part[1][2 * (size_t)blockIdx.x + 1] = s.y;
   }
 }
 
 // Kernel C: omega = (t, q) / (t, t); x += alpha p + omega q; r = q - omega t;
 // partials of (r^, r), (r, r) for the next kernel A.
 __global__ void __launch_bounds__(TB) bicg_c_kernel(TransportArgs a, int k, int np) {
-  __shared__ double red[TB / 64];
+  __shared__ double red[2 * TB / 64];
   if (a.scal[TS_DONE] != 0.0) return;
   const int par = k & 1;
-  const double ts = sum_partials(a.part[1], np, 0, red);
-  const double tt = sum_partials(a.part[1], np, 1, red);
+  const double2 st = sum_partials(a.part[1], np, red);
+  const double ts = st.x, tt = st.y;
   const double alpha = a.scal[TS_ALPHA + par];
   // t = 0 means q = 0: the half step already solved the system
   const double omega = tt > 0.0 ? ts / tt : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) a.scal[TS_OMEGA + par] = omega;
   const double* pn = a.p[par];
   const int n = a.nx * a.ny;
+  // loads of all CPT cells issued together, as in kernel A
+  double xs[CPT], rcs[CPT];
   double rhr = 0.0, rr = 0.0;
+#pragma unroll
   for (int kk = 0; kk < CPT; ++kk) {
     const int cell = (blockIdx.x * CPT + kk) * TB + threadIdx.x;
-    if (cell >= n) break;
-    const double qc = a.q[cell];
-    a.x[cell] += alpha * pn[cell] + omega * qc;
-    const double rc = qc - omega * a.t[cell];
-    a.r[cell] = rc;
-    rhr += a.rh[cell] * rc;
-    rr += rc * rc;
+    const int cc = min(cell, n - 1);
+    const double qc = a.q[cc], xo = a.x[cc], pc = pn[cc], tc = a.t[cc], rh = a.rh[cc];
+    xs[kk] = xo + (alpha * pc + omega * qc);
+    const double rc = qc - omega * tc;
+    rcs[kk] = rc;
+    if (cell < n) {
+      rhr += rh * rc;
+      rr += rc * rc;
+    }
   }
-  const double s1 = block_sum(rhr, red);
-  const double s2 = block_sum(rr, red);
+#pragma unroll
+  for (int kk = 0; kk < CPT; ++kk) {
+    const int cell = (blockIdx.x * CPT + kk) * TB + threadIdx.x;
+    if (cell < n) {
+      a.x[cell] = xs[kk];
+      a.r[cell] = rcs[kk];
+    }
+  }
+  const double2 s = block_sum2(rhr, rr, red);
   if (threadIdx.x == 0) {
-    a.part[2][2 * (size_t)blockIdx.x + 0] = s1;
-    a.part[2][2 * (size_t)blockIdx.x + 1] = s2;
+    a.part[2][2 * (size_t)blockIdx.x + 0] = s.x;
+    a.part[2][2 * (size_t)blockIdx.x + 1] = s.y;
   }
   // omega = 0 with t != 0 stalls BiCGSTAB: stop (breakdown)
   if (!(omega != 0.0) && tt > 0.0 && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -291,8 +374,8 @@ __global__ void __launch_bounds__(TB) bicg_c_kernel(TransportArgs a, int k, int 
 
 // |b|^2 from the assembly's partials, and the solve's start state
 __global__ void __launch_bounds__(TB) bicg_start_kernel(TransportArgs a, int np) {
-  __shared__ double red[TB / 64];
-  const double bb = sum_partials(a.part[2], np, 0, red);
+  __shared__ double red[2 * TB / 64];
+  const double bb = sum_partials(a.part[2], np, red).x;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     a.scal[TS_BB] = bb;
     a.scal[TS_DONE] = bb > 0.0 ? 0.0 : 1.0;   // H = 0: nothing to solve
@@ -324,8 +407,8 @@ __global__ void __launch_bounds__(TB) update_kernel(TransportArgs a) {
 }
 
 __global__ void __launch_bounds__(TB) change_kernel(TransportArgs a, int np) {
-  __shared__ double red[TB / 64];
-  const double ch = sum_partials(a.part[0], np, 0, red);
+  __shared__ double red[2 * TB / 64];
+  const double ch = sum_partials(a.part[0], np, red).x;
   if (threadIdx.x == 0) a.scal[TS_CHANGE] = ch * a.V;
 }
 
@@ -390,7 +473,10 @@ hipError_t launch_transport_assemble(const TransportArgs& a, hipStream_t st) {
 hipError_t launch_transport_bicg(const TransportArgs& a, int k0, int count, hipStream_t st) {
   const int nb = transport_blocks(a.nx, a.ny);
   for (int k = k0; k < k0 + count; ++k) {
-    hipLaunchKernelGGL(bicg_a_kernel, dim3(nb), dim3(TB), 0, st, a, k, nb);
+    if (k == 0)
+      hipLaunchKernelGGL(bicg_a_kernel<true>, dim3(nb), dim3(TB), 0, st, a, k, nb);
+    else
+      hipLaunchKernelGGL(bicg_a_kernel<false>, dim3(nb), dim3(TB), 0, st, a, k, nb);
     hipLaunchKernelGGL(bicg_b_kernel, dim3(nb), dim3(TB), 0, st, a, k, nb);
     hipLaunchKernelGGL(bicg_c_kernel, dim3(nb), dim3(TB), 0, st, a, k, nb);
   }
