@@ -808,7 +808,7 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
                          &c->tr.p[0], &c->tr.p[1], &c->tr.v[0], &c->tr.v[1], &c->tr.q, &c->tr.t};
       for (double** v : vecs) ALLOC(c, *v, ncell);
       const int nb = transport_blocks(G.nx, G.ny);
-      for (int k = 0; k < 3; ++k) ALLOC(c, c->tr.part[k], 2 * (size_t)nb);
+      for (int k = 0; k < 3; ++k) ALLOC(c, c->tr.part[k], 4 * (size_t)nb);
       ALLOC(c, c->tr.scal, TS_N);
       ALLOC(c, c->s_prev, ncell);
       void* h = nullptr;

@@ -205,7 +205,7 @@ struct TransportArgs {
   double* aw; double* ae; double* as; double* an;   // scaled couplings
   double* x;             // Newton direction (BiCGSTAB solution)
   double* r; double* rh; double* p[2]; double* v[2]; double* q; double* t;
-  double* part[3];       // partial sums of kernels A, B, C (2 per work-group)
+  double* part[3];       // per-work-group partial sums (up to 4 per work-group)
   double* scal;          // TS_* slots
 };
 

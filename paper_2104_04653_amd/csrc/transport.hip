@@ -9,14 +9,17 @@
 //    a cell's row couples it to the neighbours its water comes from.  Rows
 //    are scaled by their diagonal (Jacobi), which leaves a unit diagonal,
 //    four coupling coefficients and the right-hand side -H / diag.
-//  * BiCGSTAB on the scaled system, three fused kernels per iteration (p and
-//    v = A p; s and t = A s; x, r), each forming the neighbours' values it
-//    needs from the previous vectors instead of a separate pass.  Inner
-//    products are reduced per work-group into partial sums that the next
-//    kernel's work-groups all sum in the same fixed order (deterministic, no
-//    atomics), so every work-group forms the iteration's scalars itself.
-//    Convergence or breakdown sets a flag in device memory that makes the
-//    remaining launches of a batch return at once.
+//  * BiCGSTAB on the scaled system, two fused kernels per iteration (B: s
+//    and t = A s; AC: x and r, then the next p and v = A p), each forming
+//    the neighbours' values it needs from the previous vectors instead of a
+//    separate pass.  The textbook's third reduction, (r^, r) after the r
+//    update, is replaced by (r^, s) - omega (r^, t), which kernel B reduces
+//    with (t, s) and (t, t).  Inner products are reduced per work-group into
+//    partial sums that the next kernel's work-groups all sum in the same
+//    fixed order (deterministic, no atomics), so every work-group forms the
+//    iteration's scalars itself.  Convergence or breakdown sets a flag in
+//    device memory that makes the remaining launches of a batch return at
+//    once.
 //  * update_kernel: s <- clamp(s + d) to [0, 1], then the inflection-point
 //    rule (an update whose ends lie on different sides of the inflection
 //    point of f is halved), and the partial sums of the change's squared
@@ -63,45 +66,50 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-// two sums over the work-group at once (one pair of barriers; each sum in
-// the order of block_sum); red holds 2 TB / 64 doubles
-__device__ inline double2 block_sum2(double u, double v, double* red) {
+// NV sums over the work-group at once (one pair of barriers; each sum in
+// the order of block_sum); red holds NV TB / 64 doubles
+template <int NV>
+__device__ inline void block_sum_n(double (&v)[NV], double* red) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    u += __shfl_xor(u, off);
-    v += __shfl_xor(v, off);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] += __shfl_xor(v[c], off);
   }
   __syncthreads();
   if ((threadIdx.x & 63) == 0) {
-    red[threadIdx.x >> 6] = u;
-    red[TB / 64 + (threadIdx.x >> 6)] = v;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) red[c * (TB / 64) + (threadIdx.x >> 6)] = v[c];
   }
   __syncthreads();
-  double su = 0.0, sv = 0.0;
 #pragma unroll
-  for (int k = 0; k < TB / 64; ++k) {
-    su += red[k];
-    sv += red[TB / 64 + k];
+  for (int c = 0; c < NV; ++c) {
+    double sc = 0.0;
+#pragma unroll
+    for (int k = 0; k < TB / 64; ++k) sc += red[c * (TB / 64) + k];
+    v[c] = sc;
   }
-  return make_double2(su, sv);
 }
 
-// both components of the np partials (pairs), the same order in every
-// work-group: thread t adds partials t, t + TB, ... (16-byte loads, issued
-// together), then block_sum2
-__device__ inline double2 sum_partials(const double* part, int np, double* red) {
+// the NV components of the np partials (NV consecutive values per
+// work-group), the same order in every work-group: thread t adds partials
+// t, t + TB, ... (16-byte loads, issued together), then block_sum_n
+template <int NV>
+__device__ inline void sum_partials(const double* part, int np, double* red, double (&out)[NV]) {
+  static_assert(NV % 2 == 0, "partials are read in pairs");
   const double2* p2 = reinterpret_cast<const double2*>(part);
-  double u = 0.0, v = 0.0;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) out[c] = 0.0;
 #pragma unroll 4
   for (int k = threadIdx.x; k < np; k += TB) {
-    const double2 x = p2[k];
-    u += x.x;
-    v += x.y;
+#pragma unroll
+    for (int c = 0; c < NV / 2; ++c) {
+      const double2 x = p2[(size_t)k * (NV / 2) + c];
+      out[2 * c] += x.x;
+      out[2 * c + 1] += x.y;
+    }
   }
-  return block_sum2(u, v, red);
+  block_sum_n<NV>(out, red);
 }
-
-
 
 // Residual and scaled Jacobian of every cell; BiCGSTAB start (x = 0,
 // r = r^ = b, p = v = 0); partials of |b|^2 into part[2] (read as the
@@ -185,44 +193,33 @@ __global__ void __launch_bounds__(TB) assemble_kernel(TransportArgs a) {
   }
 }
 
-// Kernel A of iteration k (par = k & 1): rho_k = (r^, r_k) and |r_k|^2 from
-// kernel C's partials; convergence check; p_k = r + beta (p_{k-1} - omega
-// v_{k-1}) and v_k = A p_k (neighbours' p formed on the fly); partials of
-// (r^, v_k).
-// FIRST: iteration 0, whose p is r (the previous p and v hold nothing and
-// are not read)
-template <bool FIRST>
-__global__ void __launch_bounds__(TB) bicg_a_kernel(TransportArgs a, int k, int np) {
+// BiCGSTAB with two kernels (and two global reductions) per iteration.
+// Kernel C of the textbook order (x += alpha p + omega q, r = q - omega t)
+// is merged into the next iteration's kernel A (p = r + beta (p - omega v),
+// v = A p): since r_{k+1} = q - omega t, the next rho = (r^, r_{k+1}) equals
+// (r^, q) - omega (r^, t), which kernel B reduces with (t, q) and (t, t).
+// |r|^2 for the convergence test is reduced from the r that is formed.
+//
+// Partials: part[0] (kernel A / AC -> B): (r^, v), (r, r); part[1]
+// (B -> AC): (t, q), (t, t), (r^, q), (r^, t); part[2] (assembly): |b|^2.
+
+// Iteration 0's kernel A: rho_0 = (r^, r_0) = |b|^2 from the assembly's
+// partials, p_0 = r_0, v_0 = A p_0; partials (r^, v_0), (r_0, r_0).
+__global__ void __launch_bounds__(TB) bicg_first_kernel(TransportArgs a, int np) {
   __shared__ double red[2 * TB / 64];
   if (a.scal[TS_DONE] != 0.0) return;
-  const int par = k & 1, prv = par ^ 1;
-  const double2 sr = sum_partials(a.part[2], np, red);
-  const double rho = sr.x, rr = sr.y;
-  const double bb = a.scal[TS_BB];
-  const bool conv = rr <= a.tol2 * bb;
-  const bool brk = !(rho != 0.0) || !isfinite(rho);
-  if (conv || brk || k >= a.max_iter) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      a.scal[TS_DONE] = conv ? 1.0 : 2.0;
-      a.scal[TS_ITERS] = k;
-      a.scal[TS_RR] = rr;
-    }
-    return;
-  }
-  const double beta = FIRST ? 0.0 : (rho / a.scal[TS_RHO + prv]) * (a.scal[TS_ALPHA + prv] / a.scal[TS_OMEGA + prv]);
-  const double om = FIRST ? 0.0 : a.scal[TS_OMEGA + prv];
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.scal[TS_RHO + par] = rho;
-  const double* po = a.p[prv];
-  const double* vo = a.v[prv];
-  double* pn = a.p[par];
-  double* vn = a.v[par];
+  double sb[2];
+  sum_partials<2>(a.part[2], np, red, sb);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.scal[TS_RHO + 0] = sb[0];
+  double* pn = a.p[0];
+  double* vn = a.v[0];
   const int n = a.nx * a.ny;
   // the loads of all CPT cells are issued together: indices are clamped
   // rather than branched on, the terms of missing neighbours are dropped by
   // selects (in the stencil's order of addition), and the stores wait until
   // every value is formed
   double pcs[CPT], vvs[CPT];
-  double rv = 0.0;
+  double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int kk = 0; kk < CPT; ++kk) {
     const int cell = (blockIdx.x * CPT + kk) * TB + threadIdx.x;
@@ -230,13 +227,8 @@ __global__ void __launch_bounds__(TB) bicg_a_kernel(TransportArgs a, int k, int 
     const int i = cc % a.nx, j = cc / a.nx;
     const int cw = i > 0 ? cc - 1 : cc, ce = i < a.nx - 1 ? cc + 1 : cc;
     const int cs = j > 0 ? cc - a.nx : cc, cn = j < a.ny - 1 ? cc + a.nx : cc;
-    auto pnew = [&](int c2) {
-      if (FIRST) return a.r[c2];
-      const double r = a.r[c2], pv = po[c2], v = vo[c2];
-      return r + beta * (pv - om * v);
-    };
     const double w = a.aw[cc], e = a.ae[cc], so = a.as[cc], no = a.an[cc], rh = a.rh[cc];
-    const double pc = pnew(cc), pw = pnew(cw), pe = pnew(ce), ps = pnew(cs), pnb = pnew(cn);
+    const double pc = a.r[cc], pw = a.r[cw], pe = a.r[ce], ps = a.r[cs], pnb = a.r[cn];
     double vv = pc;
     vv += i > 0 ? w * pw : 0.0;
     vv += i < a.nx - 1 ? e * pe : 0.0;
@@ -244,7 +236,10 @@ __global__ void __launch_bounds__(TB) bicg_a_kernel(TransportArgs a, int k, int 
     vv += j < a.ny - 1 ? no * pnb : 0.0;
     pcs[kk] = pc;
     vvs[kk] = vv;
-    if (cell < n) rv += rh * vv;
+    if (cell < n) {
+      acc[0] += rh * vv;
+      acc[1] += pc * pc;
+    }
   }
 #pragma unroll
   for (int kk = 0; kk < CPT; ++kk) {
@@ -254,34 +249,52 @@ __global__ void __launch_bounds__(TB) bicg_a_kernel(TransportArgs a, int k, int 
       vn[cell] = vvs[kk];
     }
   }
-  const double s = block_sum(rv, red);
+  block_sum_n<2>(acc, red);
   if (threadIdx.x == 0) {
-    a.part[0][2 * (size_t)blockIdx.x + 0] = s;
-    a.part[0][2 * (size_t)blockIdx.x + 1] = 0.0;
+    a.part[0][2 * (size_t)blockIdx.x + 0] = acc[0];
+    a.part[0][2 * (size_t)blockIdx.x + 1] = acc[1];
   }
 }
 
-// Kernel B: alpha = rho / (r^, v); q = r - alpha v (the "s" of BiCGSTAB)
-// and t = A q (neighbours' q on the fly); partials of (t, q), (t, t).
+// Kernel B of iteration k (par = k & 1): the stopping tests on r_k
+// (converged; breakdown: omega_{k-1} = 0, rho_k = 0 or not finite, (r^, v_k)
+// = 0; iteration limit); alpha = rho_k / (r^, v_k); q = r - alpha v (the "s"
+// of BiCGSTAB) and t = A q (neighbours' q on the fly); partials (t, q),
+// (t, t), (r^, q), (r^, t).
 __global__ void __launch_bounds__(TB) bicg_b_kernel(TransportArgs a, int k, int np) {
-  __shared__ double red[2 * TB / 64];
+  __shared__ double red[4 * TB / 64];
   if (a.scal[TS_DONE] != 0.0) return;
-  const int par = k & 1;
-  const double rv = sum_partials(a.part[0], np, red).x;
-  const double alpha = a.scal[TS_RHO + par] / rv;
+  const int par = k & 1, prv = par ^ 1;
+  double sv[2];
+  sum_partials<2>(a.part[0], np, red, sv);
+  const double rv = sv[0], rr = sv[1];
+  const double rho = a.scal[TS_RHO + par];
+  const bool conv = rr <= a.tol2 * a.scal[TS_BB];
+  // omega_{k-1} = 0 with r_k != 0 stalls BiCGSTAB
+  const bool brk = (k > 0 && !(a.scal[TS_OMEGA + prv] != 0.0)) || !(rho != 0.0) || !isfinite(rho);
+  if (conv || brk || k >= a.max_iter) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.scal[TS_DONE] = conv ? 1.0 : 2.0;
+      a.scal[TS_ITERS] = k;
+      a.scal[TS_RR] = rr;
+    }
+    return;
+  }
+  const double alpha = rho / rv;
   if (!(rv != 0.0) || !isfinite(alpha)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       a.scal[TS_DONE] = 2.0;
       a.scal[TS_ITERS] = k;
+      a.scal[TS_RR] = rr;
     }
     return;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) a.scal[TS_ALPHA + par] = alpha;
   const double* vn = a.v[par];
   const int n = a.nx * a.ny;
-  // loads of all CPT cells issued together, as in kernel A
+  // loads of all CPT cells issued together, as in bicg_first_kernel
   double qcs[CPT], tvs[CPT];
-  double ts = 0.0, tt = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int kk = 0; kk < CPT; ++kk) {
     const int cell = (blockIdx.x * CPT + kk) * TB + threadIdx.x;
@@ -293,7 +306,7 @@ __global__ void __launch_bounds__(TB) bicg_b_kernel(TransportArgs a, int k, int 
       const double r = a.r[c2], v = vn[c2];
       return r - alpha * v;
     };
-    const double w = a.aw[cc], e = a.ae[cc], so = a.as[cc], no = a.an[cc];
+    const double w = a.aw[cc], e = a.ae[cc], so = a.as[cc], no = a.an[cc], rh = a.rh[cc];
     const double qc = qnew(cc), qw = qnew(cw), qe = qnew(ce), qs = qnew(cs), qn = qnew(cn);
     double tv = qc;
     tv += i > 0 ? w * qw : 0.0;
@@ -303,8 +316,10 @@ __global__ void __launch_bounds__(TB) bicg_b_kernel(TransportArgs a, int k, int 
     qcs[kk] = qc;
     tvs[kk] = tv;
     if (cell < n) {
-      ts += tv * qc;
-      tt += tv * tv;
+      acc[0] += tv * qc;
+      acc[1] += tv * tv;
+      acc[2] += rh * qc;
+      acc[3] += rh * tv;
     }
   }
 #pragma unroll
@@ -315,41 +330,76 @@ __global__ void __launch_bounds__(TB) bicg_b_kernel(TransportArgs a, int k, int 
       a.t[cell] = tvs[kk];
     }
   }
-  const double2 s = block_sum2(ts, tt, red);
+  block_sum_n<4>(acc, red);
   if (threadIdx.x == 0) {
-    a.part[1][2 * (size_t)blockIdx.x + 0] = s.x;
-    a.part[1][2 * (size_t)blockIdx.x + 1] = s.y;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a.part[1][4 * (size_t)blockIdx.x + c] = acc[c];
   }
 }
 
-// Kernel C: omega = (t, q) / (t, t); x += alpha p + omega q; r = q - omega t;
-// partials of (r^, r), (r, r) for the next kernel A.
-__global__ void __launch_bounds__(TB) bicg_c_kernel(TransportArgs a, int k, int np) {
-  __shared__ double red[2 * TB / 64];
+// Kernel AC of iteration k (par = k & 1, nxt = par ^ 1): omega_k =
+// (t, q) / (t, t); x += alpha p_k + omega q; r_{k+1} = q - omega t;
+// rho_{k+1} = (r^, q) - omega (r^, t), beta = (rho_{k+1} / rho_k)
+// (alpha / omega); p_{k+1} = r_{k+1} + beta (p_k - omega v_k) and
+// v_{k+1} = A p_{k+1} (the neighbours' r and p formed on the fly);
+// partials (r^, v_{k+1}), (r_{k+1}, r_{k+1}).  A breakdown here (omega = 0,
+// rho_{k+1} = 0) leaves p and v meaningless; the next kernel B stops on it.
+__global__ void __launch_bounds__(TB) bicg_ac_kernel(TransportArgs a, int k, int np) {
+  __shared__ double red[4 * TB / 64];
   if (a.scal[TS_DONE] != 0.0) return;
-  const int par = k & 1;
-  const double2 st = sum_partials(a.part[1], np, red);
-  const double ts = st.x, tt = st.y;
+  const int par = k & 1, nxt = par ^ 1;
+  double sb[4];
+  sum_partials<4>(a.part[1], np, red, sb);
+  const double tq = sb[0], tt = sb[1], rq = sb[2], rt = sb[3];
   const double alpha = a.scal[TS_ALPHA + par];
   // t = 0 means q = 0: the half step already solved the system
-  const double omega = tt > 0.0 ? ts / tt : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.scal[TS_OMEGA + par] = omega;
-  const double* pn = a.p[par];
+  const double omega = tt > 0.0 ? tq / tt : 0.0;
+  const double rho1 = rq - omega * rt;
+  const double beta = (rho1 / a.scal[TS_RHO + par]) * (alpha / omega);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.scal[TS_OMEGA + par] = omega;
+    a.scal[TS_RHO + nxt] = rho1;
+  }
+  const double* po = a.p[par];
+  const double* vo = a.v[par];
+  double* pn = a.p[nxt];
+  double* vn = a.v[nxt];
   const int n = a.nx * a.ny;
-  // loads of all CPT cells issued together, as in kernel A
-  double xs[CPT], rcs[CPT];
-  double rhr = 0.0, rr = 0.0;
+  // loads of all CPT cells issued together, as in bicg_first_kernel
+  double xs[CPT], rcs[CPT], pcs[CPT], vvs[CPT];
+  double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int kk = 0; kk < CPT; ++kk) {
     const int cell = (blockIdx.x * CPT + kk) * TB + threadIdx.x;
     const int cc = min(cell, n - 1);
-    const double qc = a.q[cc], xo = a.x[cc], pc = pn[cc], tc = a.t[cc], rh = a.rh[cc];
-    xs[kk] = xo + (alpha * pc + omega * qc);
-    const double rc = qc - omega * tc;
+    const int i = cc % a.nx, j = cc / a.nx;
+    const int cw = i > 0 ? cc - 1 : cc, ce = i < a.nx - 1 ? cc + 1 : cc;
+    const int cs = j > 0 ? cc - a.nx : cc, cn = j < a.ny - 1 ? cc + a.nx : cc;
+    auto rnew = [&](int c2) {
+      const double q = a.q[c2], t = a.t[c2];
+      return q - omega * t;
+    };
+    auto pnew = [&](int c2, double r) {
+      const double pv = po[c2], v = vo[c2];
+      return r + beta * (pv - omega * v);
+    };
+    const double w = a.aw[cc], e = a.ae[cc], so = a.as[cc], no = a.an[cc], rh = a.rh[cc];
+    const double xo = a.x[cc], qo = a.q[cc], pk = po[cc];
+    const double rc = rnew(cc);
+    const double pc = pnew(cc, rc), pw = pnew(cw, rnew(cw)), pe = pnew(ce, rnew(ce));
+    const double ps = pnew(cs, rnew(cs)), pnb = pnew(cn, rnew(cn));
+    double vv = pc;
+    vv += i > 0 ? w * pw : 0.0;
+    vv += i < a.nx - 1 ? e * pe : 0.0;
+    vv += j > 0 ? so * ps : 0.0;
+    vv += j < a.ny - 1 ? no * pnb : 0.0;
+    xs[kk] = xo + (alpha * pk + omega * qo);
     rcs[kk] = rc;
+    pcs[kk] = pc;
+    vvs[kk] = vv;
     if (cell < n) {
-      rhr += rh * rc;
-      rr += rc * rc;
+      acc[0] += rh * vv;
+      acc[1] += rc * rc;
     }
   }
 #pragma unroll
@@ -358,24 +408,23 @@ __global__ void __launch_bounds__(TB) bicg_c_kernel(TransportArgs a, int k, int 
     if (cell < n) {
       a.x[cell] = xs[kk];
       a.r[cell] = rcs[kk];
+      pn[cell] = pcs[kk];
+      vn[cell] = vvs[kk];
     }
   }
-  const double2 s = block_sum2(rhr, rr, red);
+  block_sum_n<2>(acc, red);
   if (threadIdx.x == 0) {
-    a.part[2][2 * (size_t)blockIdx.x + 0] = s.x;
-    a.part[2][2 * (size_t)blockIdx.x + 1] = s.y;
-  }
-  // omega = 0 with t != 0 stalls BiCGSTAB: stop (breakdown)
-  if (!(omega != 0.0) && tt > 0.0 && blockIdx.x == 0 && threadIdx.x == 0) {
-    a.scal[TS_DONE] = 2.0;
-    a.scal[TS_ITERS] = k + 1;
+    a.part[0][2 * (size_t)blockIdx.x + 0] = acc[0];
+    a.part[0][2 * (size_t)blockIdx.x + 1] = acc[1];
   }
 }
 
 // |b|^2 from the assembly's partials, and the solve's start state
 __global__ void __launch_bounds__(TB) bicg_start_kernel(TransportArgs a, int np) {
   __shared__ double red[2 * TB / 64];
-  const double bb = sum_partials(a.part[2], np, red).x;
+  double sb[2];
+  sum_partials<2>(a.part[2], np, red, sb);
+  const double bb = sb[0];
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     a.scal[TS_BB] = bb;
     a.scal[TS_DONE] = bb > 0.0 ? 0.0 : 1.0;   // H = 0: nothing to solve
@@ -408,7 +457,9 @@ __global__ void __launch_bounds__(TB) update_kernel(TransportArgs a) {
 
 __global__ void __launch_bounds__(TB) change_kernel(TransportArgs a, int np) {
   __shared__ double red[2 * TB / 64];
-  const double ch = sum_partials(a.part[0], np, red).x;
+  double sc[2];
+  sum_partials<2>(a.part[0], np, red, sc);
+  const double ch = sc[0];
   if (threadIdx.x == 0) a.scal[TS_CHANGE] = ch * a.V;
 }
 
@@ -473,12 +524,9 @@ hipError_t launch_transport_assemble(const TransportArgs& a, hipStream_t st) {
 hipError_t launch_transport_bicg(const TransportArgs& a, int k0, int count, hipStream_t st) {
   const int nb = transport_blocks(a.nx, a.ny);
   for (int k = k0; k < k0 + count; ++k) {
-    if (k == 0)
-      hipLaunchKernelGGL(bicg_a_kernel<true>, dim3(nb), dim3(TB), 0, st, a, k, nb);
-    else
-      hipLaunchKernelGGL(bicg_a_kernel<false>, dim3(nb), dim3(TB), 0, st, a, k, nb);
+    if (k == 0) hipLaunchKernelGGL(bicg_first_kernel, dim3(nb), dim3(TB), 0, st, a, nb);
     hipLaunchKernelGGL(bicg_b_kernel, dim3(nb), dim3(TB), 0, st, a, k, nb);
-    hipLaunchKernelGGL(bicg_c_kernel, dim3(nb), dim3(TB), 0, st, a, k, nb);
+    hipLaunchKernelGGL(bicg_ac_kernel, dim3(nb), dim3(TB), 0, st, a, k, nb);
   }
   return hipGetLastError();
 }
