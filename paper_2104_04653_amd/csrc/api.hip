@@ -1409,22 +1409,24 @@ int transport_impl(mrcm_ctx* c, const double* s_old, double* s_new, const double
     HIPCHK(c, launch_transport_assemble(a, st));
     // the first batch covers the previous system's iteration count and a
     // margin (successive Newton systems need similar counts); the launches
-    // of a batch after convergence return at once (about 3 us each)
-    int k = 0, batch = last_iters + 4;
+    // of a batch after convergence return at once (about 3 us each).  The
+    // Newton update is queued behind every batch and applies itself only
+    // once the solve has stopped, so one host read per batch sees both.
+    int k = 0, batch = last_iters + 2;
     for (;;) {
       HIPCHK(c, launch_transport_bicg(a, k, batch, st));
       k += batch;
+      HIPCHK(c, launch_transport_update(a, st));
       HIPCHK(c, hipMemcpyAsync(c->h_tscal, a.scal, TS_N * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(c, hipStreamSynchronize(st));
       if (c->h_tscal[TS_DONE] != 0.0 || k > a.max_iter) break;
       batch = 8;
     }
+    // kernel B stops the solve at the iteration limit at the latest
+    if (c->h_tscal[TS_DONE] == 0.0) return fail(c, MRCM_E_NO_CONV, "transport: BiCGSTAB did not stop");
     last_iters = std::max(4, (int)c->h_tscal[TS_ITERS]);
     out.linear_iters += (int)c->h_tscal[TS_ITERS];
     if (c->h_tscal[TS_DONE] != 1.0) out.linear_failures += 1;
-    HIPCHK(c, launch_transport_update(a, st));
-    HIPCHK(c, hipMemcpyAsync(c->h_tscal, a.scal, TS_N * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
     change = sqrt(c->h_tscal[TS_CHANGE]);
     out.newton_iters = it;
     if (!isfinite(change)) break;

@@ -214,7 +214,8 @@ int transport_blocks(int nx, int ny);   // work-groups of a cell-wise launch (pa
 hipError_t launch_transport_assemble(const TransportArgs& a, hipStream_t st);
 // BiCGSTAB iterations k0 .. k0+count-1 (launches after convergence return at once)
 hipError_t launch_transport_bicg(const TransportArgs& a, int k0, int count, hipStream_t st);
-// Newton update (bound, inflection-point rule) and the squared norm of the change
+// Newton update (bound, inflection-point rule) and the squared norm of the
+// change; does nothing while scal[TS_DONE] is 0 (the solve has not stopped)
 hipError_t launch_transport_update(const TransportArgs& a, hipStream_t st);
 // max |a - b| over the cells into scal[TS_OUTER]
 hipError_t launch_transport_maxdiff(const TransportArgs& t, const double* a, const double* b,

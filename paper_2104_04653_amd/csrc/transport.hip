@@ -20,10 +20,11 @@
 //    iteration's scalars itself.  Convergence or breakdown sets a flag in
 //    device memory that makes the remaining launches of a batch return at
 //    once.
-//  * update_kernel: s <- clamp(s + d) to [0, 1], then the inflection-point
-//    rule (an update whose ends lie on different sides of the inflection
-//    point of f is halved), and the partial sums of the change's squared
-//    L2 norm.
+//  * update_kernel (queued after every batch of BiCGSTAB launches, a no-op
+//    until the solve has stopped): s <- clamp(s + d) to [0, 1], then the
+//    inflection-point rule (an update whose ends lie on different sides of
+//    the inflection point of f is halved), and the partial sums of the
+//    change's squared L2 norm.
 //
 // Layout: cell (i, j) at j*nx + i; face velocities as the Darcy step
 // returns them (ux on (nx+1)*ny x-faces, uy on nx*(ny+1) y-faces).
@@ -437,6 +438,9 @@ __global__ void __launch_bounds__(TB) bicg_start_kernel(TransportArgs a, int np)
 // V (s_new - s)^2 into part[0]
 __global__ void __launch_bounds__(TB) update_kernel(TransportArgs a) {
   __shared__ double red[TB / 64];
+  // queued after every BiCGSTAB batch: applies the direction only once the
+  // solve has stopped
+  if (a.scal[TS_DONE] == 0.0) return;
   const int n = a.nx * a.ny;
   double ch = 0.0;
   for (int k = 0; k < CPT; ++k) {
@@ -457,6 +461,7 @@ __global__ void __launch_bounds__(TB) update_kernel(TransportArgs a) {
 
 __global__ void __launch_bounds__(TB) change_kernel(TransportArgs a, int np) {
   __shared__ double red[2 * TB / 64];
+  if (a.scal[TS_DONE] == 0.0) return;
   double sc[2];
   sum_partials<2>(a.part[0], np, red, sc);
   const double ch = sc[0];
