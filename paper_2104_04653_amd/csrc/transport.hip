@@ -206,12 +206,20 @@ __global__ void __launch_bounds__(TB) assemble_kernel(TransportArgs a) {
 
 // Iteration 0's kernel A: rho_0 = (r^, r_0) = |b|^2 from the assembly's
 // partials, p_0 = r_0, v_0 = A p_0; partials (r^, v_0), (r_0, r_0).
+// It also sets the solve's start state (the flag of the previous solve is
+// not read).
 __global__ void __launch_bounds__(TB) bicg_first_kernel(TransportArgs a, int np) {
   __shared__ double red[2 * TB / 64];
-  if (a.scal[TS_DONE] != 0.0) return;
   double sb[2];
   sum_partials<2>(a.part[2], np, red, sb);
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.scal[TS_RHO + 0] = sb[0];
+  const double bb = sb[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.scal[TS_BB] = bb;
+    a.scal[TS_DONE] = bb > 0.0 ? 0.0 : 1.0;   // H = 0: nothing to solve
+    a.scal[TS_ITERS] = 0.0;
+    a.scal[TS_RR] = bb;
+    a.scal[TS_RHO + 0] = bb;
+  }
   double* pn = a.p[0];
   double* vn = a.v[0];
   const int n = a.nx * a.ny;
@@ -420,20 +428,6 @@ __global__ void __launch_bounds__(TB) bicg_ac_kernel(TransportArgs a, int k, int
   }
 }
 
-// |b|^2 from the assembly's partials, and the solve's start state
-__global__ void __launch_bounds__(TB) bicg_start_kernel(TransportArgs a, int np) {
-  __shared__ double red[2 * TB / 64];
-  double sb[2];
-  sum_partials<2>(a.part[2], np, red, sb);
-  const double bb = sb[0];
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    a.scal[TS_BB] = bb;
-    a.scal[TS_DONE] = bb > 0.0 ? 0.0 : 1.0;   // H = 0: nothing to solve
-    a.scal[TS_ITERS] = 0.0;
-    a.scal[TS_RR] = bb;
-  }
-}
-
 // Newton update with the bound and the inflection-point rule; partials of
 // V (s_new - s)^2 into part[0]
 __global__ void __launch_bounds__(TB) update_kernel(TransportArgs a) {
@@ -520,9 +514,6 @@ int transport_blocks(int nx, int ny) {
 hipError_t launch_transport_assemble(const TransportArgs& a, hipStream_t st) {
   const int nb = transport_blocks(a.nx, a.ny);
   hipLaunchKernelGGL(assemble_kernel, dim3(nb), dim3(TB), 0, st, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(bicg_start_kernel, dim3(1), dim3(TB), 0, st, a, nb);
   return hipGetLastError();
 }
 

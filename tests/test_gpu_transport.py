@@ -77,6 +77,19 @@ def test_left_right_inflow_256():
     check_step(prob, s, r, 20.0, "gauss 256")
 
 
+def test_ragged_grid_steps():
+    """80 x 48 cells (3840, not a multiple of the 1024 cells a transport
+    work-group covers): the last work-group's spare lanes load from clamped
+    indices and neither store nor add to the inner products."""
+    prob = inputs.make_problem("channel256_q5", nx=80, ny=48, seed=4)
+    say("case: transport, quarter-five-spot 80x48")
+    s0 = np.zeros(prob.nx * prob.ny)
+    r = solve_mrcm(prob, lam=total_mobility(s0, prob.mu_w, prob.mu_o))
+    s1, _ = check_step(prob, s0, r, 20.0, "80x48 from s = 0")
+    r1 = solve_mrcm(prob, lam=total_mobility(s1, prob.mu_w, prob.mu_o))
+    check_step(prob, s1, r1, 50.0, "80x48 second step")
+
+
 def test_gauss1024_full_size_step():
     """One 20-CFL step of the 1024^2 workload (1,048,576 cells) against the
     oracle, with the oracle's Darcy fluxes."""
