@@ -43,12 +43,13 @@ PEAK_HBM_GBS = 8000.0
 # multiply-add over the real (unpadded) channels
 CNN_FLOP_PATCH = 2 * 256 * 9 * (5 * 32 + 32 * 32 + 32 * 32 + 32 * 16)
 PEAK_BF16_TFLOPS = 2500.0
-# transport, algorithmic HBM bytes per cell: one BiCGSTAB iteration (two
-# fused kernels: 9 + 14 doubles read or written per cell) and one Newton
-# iteration outside the iterations (assembly 12 doubles, the solve's first
-# p and v = A p 8, update 3)
-TRANSPORT_BYTES_ITER = 23 * 8
-TRANSPORT_BYTES_NEWTON = 23 * 8
+# transport, algorithmic HBM bytes per cell (the couplings one per face,
+# about two per cell): one BiCGSTAB iteration (two fused kernels: 7 + 12
+# doubles read or written per cell) and one Newton iteration outside the
+# iterations (assembly 10 doubles, the solve's first p and v = A p 6,
+# update 3)
+TRANSPORT_BYTES_ITER = 19 * 8
+TRANSPORT_BYTES_NEWTON = 19 * 8
 
 # the roofline kernel of each subdomain size, and the sources its counter
 # summary was taken on

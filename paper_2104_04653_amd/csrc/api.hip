@@ -803,9 +803,11 @@ int mrcm_setup(mrcm_ctx** out, const mrcm_grid* g, const double* perm, int32_t s
       c->h_report = static_cast<double*>(h);
     }
     {
-      // transport work arrays: 4 couplings, x, r, r^, 2 p, 2 v, q, t
-      double** vecs[] = {&c->tr.aw, &c->tr.ae, &c->tr.as, &c->tr.an, &c->tr.x, &c->tr.r, &c->tr.rh,
-                         &c->tr.p[0], &c->tr.p[1], &c->tr.v[0], &c->tr.v[1], &c->tr.q, &c->tr.t};
+      // transport work arrays: face couplings, x, r, r^, 2 p, 2 v, q, t
+      ALLOC(c, c->tr.cfx, (size_t)(G.nx + 1) * G.ny);
+      ALLOC(c, c->tr.cfy, (size_t)G.nx * (G.ny + 1));
+      double** vecs[] = {&c->tr.x, &c->tr.r, &c->tr.rh, &c->tr.p[0], &c->tr.p[1], &c->tr.v[0],
+                         &c->tr.v[1], &c->tr.q, &c->tr.t};
       for (double** v : vecs) ALLOC(c, *v, ncell);
       const int nb = transport_blocks(G.nx, G.ny);
       for (int k = 0; k < 3; ++k) ALLOC(c, c->tr.part[k], 4 * (size_t)nb);

@@ -202,7 +202,16 @@ struct TransportArgs {
   const double* src;     // nx*ny source per unit area, or nullptr
   const double* s_old;   // saturation at the last time level
   double* s;             // current Newton iterate
-  double* aw; double* ae; double* as; double* an;   // scaled couplings
+  // scaled couplings, one per face: the upwind Jacobian couples a cell only
+  // to the neighbours its water comes from, so a face holds at most one
+  // nonzero coupling, in the row of its downstream cell; all couplings are
+  // <= 0.  cfx ((nx+1)*ny x-faces, face (i, j) west of cell (i, j)) holds
+  // the east cell's coupling to the west cell when the flow is +x, minus
+  // the west cell's coupling to the east cell when it is -x; cfy
+  // (nx*(ny+1) y-faces) likewise with south and north.  A cell's couplings
+  // are min(west face, 0), -max(east face, 0), min(south face, 0) and
+  // -max(north face, 0).
+  double* cfx; double* cfy;
   double* x;             // Newton direction (BiCGSTAB solution)
   double* r; double* rh; double* p[2]; double* v[2]; double* q; double* t;
   double* part[3];       // per-work-group partial sums (up to 4 per work-group)

@@ -1,14 +1,16 @@
 // Implicit transport of the water saturation (paper, section 4) on the GPU:
 // implicit Euler with first-order upwind fluxes (eqs. (BL2D_Newton2),
 // (fluxes_impli), (up_fluxes_impli)), Newton's method (eqs. (BL2D_Newton8),
-// (BL2D_Newton7)) with the inflection-point strategy, one cell per thread.
+// (BL2D_Newton7)) with the inflection-point strategy, 4 cells per thread.
 //
 // Per Newton iteration:
 //  * assemble_kernel: the residual H and the Jacobian H' of every cell.  A
 //    face's water flux depends on the saturation of its upwind cell only, so
 //    a cell's row couples it to the neighbours its water comes from.  Rows
 //    are scaled by their diagonal (Jacobi), which leaves a unit diagonal,
-//    four coupling coefficients and the right-hand side -H / diag.
+//    up to four coupling coefficients and the right-hand side -H / diag.
+//    A face carries at most one nonzero coupling (in its downstream cell's
+//    row), so the couplings are stored one per face.
 //  * BiCGSTAB on the scaled system, two fused kernels per iteration (B: s
 //    and t = A s; AC: x and r, then the next p and v = A p), each forming
 //    the neighbours' values it needs from the previous vectors instead of a
@@ -177,10 +179,15 @@ __global__ void __launch_bounds__(TB) assemble_kernel(TransportArgs a) {
     }
     const double H = si - a.s_old[cell] + a.c * (out - wsrc);
     const double inv = 1.0 / (1.0 + a.c * dg);
-    a.aw[cell] = a.c * cw * inv;
-    a.ae[cell] = a.c * ce * inv;
-    a.as[cell] = a.c * cs * inv;
-    a.an[cell] = a.c * cn * inv;
+    // the couplings, one per face (see TransportArgs::cfx): every face is
+    // written by exactly one cell, the one whose row holds its coupling
+    // (the downstream cell; for a face without flow, the cell on its +
+    // side; a boundary face by its only cell, as 0)
+    const size_t fx = (size_t)j * (a.nx + 1) + i, fy = (size_t)j * a.nx + i;
+    if (Fw >= 0.0 || i == 0) a.cfx[fx] = i > 0 ? a.c * cw * inv : 0.0;
+    if (Fe < 0.0 || i == a.nx - 1) a.cfx[fx + 1] = i < a.nx - 1 ? -(a.c * ce * inv) : 0.0;
+    if (Fs >= 0.0 || j == 0) a.cfy[fy] = j > 0 ? a.c * cs * inv : 0.0;
+    if (Fn < 0.0 || j == a.ny - 1) a.cfy[fy + a.nx] = j < a.ny - 1 ? -(a.c * cn * inv) : 0.0;
     const double bi = -H * inv;
     a.x[cell] = 0.0;
     a.r[cell] = bi;
@@ -236,7 +243,10 @@ __global__ void __launch_bounds__(TB) bicg_first_kernel(TransportArgs a, int np)
     const int i = cc % a.nx, j = cc / a.nx;
     const int cw = i > 0 ? cc - 1 : cc, ce = i < a.nx - 1 ? cc + 1 : cc;
     const int cs = j > 0 ? cc - a.nx : cc, cn = j < a.ny - 1 ? cc + a.nx : cc;
-    const double w = a.aw[cc], e = a.ae[cc], so = a.as[cc], no = a.an[cc], rh = a.rh[cc];
+    const size_t fx = (size_t)j * (a.nx + 1) + i, fy = (size_t)j * a.nx + i;
+    const double w = fmin(a.cfx[fx], 0.0), e = -fmax(a.cfx[fx + 1], 0.0);
+    const double so = fmin(a.cfy[fy], 0.0), no = -fmax(a.cfy[fy + a.nx], 0.0);
+    const double rh = a.rh[cc];
     const double pc = a.r[cc], pw = a.r[cw], pe = a.r[ce], ps = a.r[cs], pnb = a.r[cn];
     double vv = pc;
     vv += i > 0 ? w * pw : 0.0;
@@ -315,7 +325,10 @@ __global__ void __launch_bounds__(TB) bicg_b_kernel(TransportArgs a, int k, int 
       const double r = a.r[c2], v = vn[c2];
       return r - alpha * v;
     };
-    const double w = a.aw[cc], e = a.ae[cc], so = a.as[cc], no = a.an[cc], rh = a.rh[cc];
+    const size_t fx = (size_t)j * (a.nx + 1) + i, fy = (size_t)j * a.nx + i;
+    const double w = fmin(a.cfx[fx], 0.0), e = -fmax(a.cfx[fx + 1], 0.0);
+    const double so = fmin(a.cfy[fy], 0.0), no = -fmax(a.cfy[fy + a.nx], 0.0);
+    const double rh = a.rh[cc];
     const double qc = qnew(cc), qw = qnew(cw), qe = qnew(ce), qs = qnew(cs), qn = qnew(cn);
     double tv = qc;
     tv += i > 0 ? w * qw : 0.0;
@@ -392,7 +405,10 @@ __global__ void __launch_bounds__(TB) bicg_ac_kernel(TransportArgs a, int k, int
       const double pv = po[c2], v = vo[c2];
       return r + beta * (pv - omega * v);
     };
-    const double w = a.aw[cc], e = a.ae[cc], so = a.as[cc], no = a.an[cc], rh = a.rh[cc];
+    const size_t fx = (size_t)j * (a.nx + 1) + i, fy = (size_t)j * a.nx + i;
+    const double w = fmin(a.cfx[fx], 0.0), e = -fmax(a.cfx[fx + 1], 0.0);
+    const double so = fmin(a.cfy[fy], 0.0), no = -fmax(a.cfy[fy + a.nx], 0.0);
+    const double rh = a.rh[cc];
     const double xo = a.x[cc], qo = a.q[cc], pk = po[cc];
     const double rc = rnew(cc);
     const double pc = pnew(cc, rc), pw = pnew(cw, rnew(cw)), pe = pnew(ce, rnew(ce));
