@@ -5,6 +5,7 @@
 #include "../../include/mrcm.h"
 #include "mrcm_internal.h"
 #include "physics_space.h"
+#include "transport.h"
 
 #include <math.h>
 #include <stdio.h>

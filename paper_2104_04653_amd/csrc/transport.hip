@@ -30,7 +30,7 @@
 //
 // Layout: cell (i, j) at j*nx + i; face velocities as the Darcy step
 // returns them (ux on (nx+1)*ny x-faces, uy on nx*(ny+1) y-faces).
-#include "mrcm_internal.h"
+#include "transport.h"
 
 #include <math.h>
 
