@@ -114,9 +114,9 @@ __device__ inline void sum_partials(const double* part, int np, double* red, dou
   block_sum_n<NV>(out, red);
 }
 
-// Residual and scaled Jacobian of every cell; BiCGSTAB start (x = 0,
-// r = r^ = b, p = v = 0); partials of |b|^2 into part[2] (read as the
-// "previous kernel C" by the first iteration).
+// Residual and scaled Jacobian of every cell; BiCGSTAB start vectors (x = 0,
+// r = r^ = b); partials of |b|^2 into part[2], which bicg_first_kernel
+// sums.
 __global__ void __launch_bounds__(TB) assemble_kernel(TransportArgs a) {
   __shared__ double red[TB / 64];
   const int n = a.nx * a.ny;
