@@ -90,6 +90,23 @@ def test_ragged_grid_steps():
     check_step(prob, s1, r1, 50.0, "80x48 second step")
 
 
+def test_no_flow_leaves_the_saturation_unchanged():
+    """Zero face velocities and no wells: the residual is zero from the
+    start, so the linear solve stops before its first iteration and one
+    Newton iteration returns s_old exactly (a degenerate case of eq.
+    (BL2D_Newton2): no flux, no change)."""
+    prob = inputs.make_problem("gauss1024", nx=64, ny=48, seed=3)
+    say("case: transport without flow, 64x48")
+    s_old = inputs.synthetic_saturation(prob, 2, 10)
+    ux = np.zeros((prob.nx + 1) * prob.ny)
+    uy = np.zeros(prob.nx * (prob.ny + 1))
+    s, st = gpu_step(prob, s_old, ux, uy, 0.5)
+    say("  Newton %d, BiCGSTAB %d, last change %.1e" % (st["newton_iters"], st["linear_iters"],
+                                                        st["last_change"]))
+    assert st["converged"] and st["newton_iters"] == 1 and st["linear_iters"] == 0
+    assert np.array_equal(s, s_old)
+
+
 def test_gauss1024_full_size_step():
     """One 20-CFL step of the 1024^2 workload (1,048,576 cells) against the
     oracle, with the oracle's Darcy fluxes."""
