@@ -1231,7 +1231,12 @@ __device__ inline void basis32_body(const SubArgs& a, Lds32& sh) {
   write_block(a, sd, I, J, sh.fc, sh.xb);
 }
 
-__global__ void __launch_bounds__(PAIR, 2) basis32_pair_kernel(SubArgs a) {
+// One wavefront per SIMD: the FP32 inverse blocks live beside the FP64
+// solution, residual and correction tiles, which at two wavefronts per SIMD
+// (256 registers) spilled 103 dwords per lane to scratch; at one the
+// compiler keeps them in the accumulation registers instead (local phase
+// 0.72 -> 0.58 ms at 1024^2).
+__global__ void __launch_bounds__(PAIR, 1) basis32_pair_kernel(SubArgs a) {
   __shared__ Lds32 sh;
   if (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0) basis32_body<0>(a, sh);
   else basis32_body<1>(a, sh);
