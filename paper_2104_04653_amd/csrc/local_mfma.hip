@@ -1320,9 +1320,12 @@ __global__ void __launch_bounds__(COMPOSE_NT) compose_kernel(SubArgs a) {
   }
 }
 
-// four wavefronts per SIMD: 128 registers per lane and 19 KB of LDS per pair
+// a register budget of two wavefronts per SIMD: 155 registers per lane, no
+// spills, so three wavefronts fit (19 KB of LDS per pair); the flux phase is
+// about 8 us shorter at 1024^2 than at four wavefronts per SIMD with 128
+// registers and 84 bytes of spills per lane
 template <int DD>
-__global__ void __launch_bounds__(PAIR, 4) stitch_pair_kernel(SubArgs a) {
+__global__ void __launch_bounds__(PAIR, 2) stitch_pair_kernel(SubArgs a) {
   __shared__ double kap[MM], dg[MM], ex[MM], cy[MM];
   __shared__ double bs_[MM], ps[MM], rs[MM];
   __shared__ double pm0;   // composed pressure of cell 0 (the pin)
