@@ -501,9 +501,12 @@ __device__ __forceinline__ void basis32_wave(const SubArgs& a, Lds32b& sh, int s
 // the fallback list of the FP32 kernel).  Two wavefronts per subdomain; with
 // DD = 8 dofs per side, DD / 4 windows of 4 dofs per side, one work-group
 // each (work-group b: subdomain b / (DD / 4), window b % (DD / 4), its own
-// scratch), every window factorising the subdomain's matrix.
+// scratch), every window factorising the subdomain's matrix.  With 4 dofs
+// per side, one wavefront per SIMD: the 25 dwords per lane that spilled to
+// scratch at two stay in accumulation registers (the launch about 3% shorter
+// at 2048 x 1024); with 8, two wavefronts per SIMD measured faster.
 template <bool LIST, int DD>
-__global__ void __launch_bounds__(PAIR, 2) basis32x32_kernel(SubArgs a) {
+__global__ void __launch_bounds__(PAIR, DD == 4 ? 1 : 2) basis32x32_kernel(SubArgs a) {
   static_assert(DD % 4 == 0 && (!LIST || DD == 4), "windows of 4 dofs per side");
   constexpr int NW = DD / 4, RX = 4 * DD + 1;
   __shared__ Lds32b sh;
